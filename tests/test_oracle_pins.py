@@ -1,0 +1,434 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics.
+
+Each test checks the oracle against something other than itself: a closed
+form, an invariant of the discretisation, a textbook routine, or a
+convergence rate of a manufactured solution.  The mistakes each one is meant
+to catch are named in its docstring.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_2510_12011_amd import inputs
+
+
+# ---------------------------------------------------------------------------
+# element matrices
+# ---------------------------------------------------------------------------
+def test_reference_tet_stiffness_and_mass():
+    """Unit right tetrahedron, sigma = I: K_e = (1/6)[[3,-1,-1,-1],[-1,1,0,0],
+    [-1,0,1,0],[-1,0,0,1]] and M_e = (1/120)(1 + delta_ij) (textbook values).
+    Catches a wrong gradient (transposed J^-1), a wrong volume factor or a
+    wrong mass weighting."""
+    pts = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]]
+    Me, Ke, det = orc.element(pts, None, 1.0, 1.0)
+    assert det == pytest.approx(1.0)
+    K_ref = np.array([[3, -1, -1, -1], [-1, 1, 0, 0], [-1, 0, 1, 0], [-1, 0, 0, 1]]) / 6.0
+    M_ref = (np.ones((4, 4)) + np.eye(4)) / 120.0
+    np.testing.assert_allclose(Ke, K_ref, atol=1e-15)
+    np.testing.assert_allclose(Me, M_ref, atol=1e-16)
+
+
+def test_reference_tet_anisotropic():
+    """Fibre along x with (sl, st): sigma = diag(sl, st, st), so on the unit
+    right tet K_e[1][1] = sl/6, K_e[2][2] = st/6, K_e[0][0] = (sl + 2 st)/6.
+    A fibre given with non-unit length must be normalised."""
+    sl, st = 0.17, 0.019
+    pts = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]]
+    _, Ke, _ = orc.element(pts, [3.0, 0.0, 0.0], sl, st)
+    assert Ke[1, 1] == pytest.approx(sl / 6, rel=1e-14)
+    assert Ke[2, 2] == pytest.approx(st / 6, rel=1e-14)
+    assert Ke[3, 3] == pytest.approx(st / 6, rel=1e-14)
+    assert Ke[0, 0] == pytest.approx((sl + 2 * st) / 6, rel=1e-14)
+    assert Ke[1, 2] == pytest.approx(0.0, abs=1e-16)
+
+
+def test_element_invariants_random_tets():
+    """Any tet, any fibre: K_e symmetric with zero row sums; K_e = vol G^T S G
+    gives u^T K_e u = vol a^T S a for the linear field u = a.x; sum M_e = vol."""
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        pts = rng.normal(size=(4, 3))
+        f = rng.normal(size=3)
+        sl, st = rng.uniform(0.05, 1.0, 2)
+        Me, Ke, det = orc.element(pts, f, sl, st)
+        vol = abs(det) / 6
+        vol_ref = abs(np.linalg.det(pts[1:] - pts[0])) / 6
+        assert vol == pytest.approx(vol_ref, rel=1e-12)
+        assert Me.sum() == pytest.approx(vol, rel=1e-14)
+        np.testing.assert_allclose(Ke, Ke.T, rtol=0, atol=1e-12 * abs(Ke).max())
+        np.testing.assert_allclose(Ke.sum(axis=1), 0, atol=1e-12 * abs(Ke).max())
+        fh = f / np.linalg.norm(f)
+        S = st * np.eye(3) + (sl - st) * np.outer(fh, fh)
+        a = rng.normal(size=3)
+        u = pts @ a
+        assert u @ Ke @ u == pytest.approx(vol * a @ S @ a, rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# global matrices
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cube_jit():
+    sp = inputs.tiny_cube(n=12)           # jittered unit cube
+    return sp, orc.assemble_spec(sp)
+
+
+def test_mass_sums_to_volume(cube_jit):
+    """sum_ij M_ij = |Omega| = 1 mm^3 even on the jittered cube (the
+    boundary is not jittered)."""
+    _, m = cube_jit
+    assert m.M.sum() == pytest.approx(1.0, rel=1e-13)
+
+
+def test_mass_second_moment(cube_jit):
+    """x^T M x = int x^2 dV = 1/3 on the unit cube: P1 interpolates the
+    linear field x exactly, so this holds on any mesh of the cube."""
+    sp, m = cube_jit
+    x = sp.mesh.xyz[:, 0]
+    assert x @ orc.spmv(m, m.M, x) == pytest.approx(1.0 / 3.0, rel=1e-13)
+
+
+def test_symmetry_and_row_sums(cube_jit):
+    _, m = cube_jit
+    Md, Kd = m.dense("M"), m.dense("K")
+    np.testing.assert_allclose(Md, Md.T, atol=1e-18)
+    np.testing.assert_allclose(Kd, Kd.T, atol=1e-15)
+    assert abs(Kd.sum(axis=1)).max() <= 1e-13 * abs(Kd).max()
+
+
+def _interior_nodes(mesh):
+    g = mesh.grid
+    lo, hi = g.min(axis=0), g.max(axis=0)
+    return np.nonzero(np.all((g > lo + 1e-9) & (g < hi - 1e-9), axis=1))[0]
+
+
+def test_patch_test_anisotropic():
+    """Interior rows of K annihilate every linear field, for any constant
+    sigma tensor, on a jittered mesh; and u^T K u = a^T S a |Omega|."""
+    sp = inputs.small_box(nx=6, ny=5, nz=4, jitter=0.2, fibre=(0.6, 0.8, 0.0))
+    m = orc.assemble_spec(sp)
+    a = np.array([0.3, -1.1, 0.7])
+    u = sp.mesh.xyz @ a
+    Ku = orc.spmv(m, m.K, u)
+    inner = _interior_nodes(sp.mesh)
+    assert abs(Ku[inner]).max() <= 1e-12 * abs(m.K).max()
+    f = np.array([0.6, 0.8, 0.0])
+    S = sp.sigma_t * np.eye(3) + (sp.sigma_l - sp.sigma_t) * np.outer(f, f)
+    vol = 1.2 * 1.0 * 0.8
+    assert u @ Ku == pytest.approx(a @ S @ a * vol, rel=1e-12)
+
+
+def test_kuhn_grid_is_seven_point_laplacian():
+    """Unjittered Kuhn grid, isotropic sigma: an interior row is sigma*h times
+    the 7-point stencil (6 on the diagonal, -1 on the six axis neighbours and
+    exactly 0 on the eight diagonal neighbours)."""
+    n, h, sig = 6, 1.0 / 6, 0.3
+    mesh = inputs.kuhn_box(n, n, n, 1.0, 1.0, 1.0)
+    m = orc.assemble(mesh.xyz, mesh.tets, None, sig, sig)
+    Kd = m.dense("K")
+    i, j, k = 3, 2, 4
+    idx = (i * (n + 1) + j) * (n + 1) + k
+    row = Kd[idx]
+    assert row[idx] == pytest.approx(6 * sig * h, rel=1e-14)
+    for d in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]:
+        jdx = ((i + d[0]) * (n + 1) + j + d[1]) * (n + 1) + k + d[2]
+        assert row[jdx] == pytest.approx(-sig * h, rel=1e-14)
+    others = np.delete(row, [idx] + [((i + d[0]) * (n + 1) + j + d[1]) * (n + 1) + k + d[2]
+                                     for d in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0),
+                                               (0, 0, 1), (0, 0, -1)]])
+    assert abs(others).max() <= 1e-15
+    # pattern: 15 nonzeros per interior row of the Kuhn split
+    assert np.diff(m.row_ptr)[idx] == 15
+
+
+def test_slab_counts_and_volume():
+    """Coarse 20x7x3 mm slab: node/element counts of the Kuhn split and
+    sum M = 420 mm^3."""
+    sp = inputs.slab(h=0.5)
+    assert sp.mesh.n_nodes == 41 * 15 * 7
+    assert sp.mesh.n_tets == 6 * 40 * 14 * 6
+    m = orc.assemble_spec(sp)
+    assert m.M.sum() == pytest.approx(420.0, rel=1e-13)
+    # nnz = N + 2 * #edges; the Kuhn split has 7 edge directions
+    nx, ny, nz = 40, 14, 6
+    edges = (nx * (ny + 1) * (nz + 1) + (nx + 1) * ny * (nz + 1) + (nx + 1) * (ny + 1) * nz
+             + nx * ny * (nz + 1) + nx * (ny + 1) * nz + (nx + 1) * ny * nz + nx * ny * nz)
+    assert m.col.shape[0] == sp.mesh.n_nodes + 2 * edges
+
+
+# ---------------------------------------------------------------------------
+# PCG
+# ---------------------------------------------------------------------------
+def _system(sp, dt=0.01):
+    m = orc.assemble_spec(sp)
+    A = sp.chi * sp.cm * m.M + sp.theta * dt * m.K
+    return m, A
+
+
+def test_pcg_matches_dense_solve():
+    """Jacobi-PCG on A = chi Cm M + theta dt K equals numpy.linalg.solve."""
+    sp = inputs.small_box(nx=6, ny=5, nz=4)
+    m, A = _system(sp)
+    Ad = m.dense("M") * sp.chi * sp.cm + m.dense("K") * sp.theta * 0.01
+    np.linalg.cholesky(Ad)                      # SPD
+    rng = np.random.default_rng(1)
+    b = rng.normal(size=m.n)
+    x_ref = np.linalg.solve(Ad, b)
+    x, it, _ = orc.pcg(m, A, b, np.zeros(m.n), rtol=1e-14)
+    assert it > 0
+    np.testing.assert_allclose(x, x_ref, rtol=0, atol=1e-12 * abs(x_ref).max())
+
+
+def test_pcg_exact_start_takes_no_iterations():
+    sp = inputs.small_box(nx=4, ny=4, nz=4)
+    m, A = _system(sp)
+    Ad = m.dense("M") * sp.chi * sp.cm + m.dense("K") * sp.theta * 0.01
+    b = np.random.default_rng(2).normal(size=m.n)
+    x_ref = np.linalg.solve(Ad, b)
+    x, it, _ = orc.pcg(m, A, b, x_ref, rtol=1e-10)
+    assert it == 0
+    x, it, _ = orc.pcg(m, A, np.zeros(m.n), np.zeros(m.n), rtol=1e-10)
+    assert it == 0 and not x.any()
+
+
+def test_pcg_iteration_bound():
+    """kappa(D^-1/2 A D^-1/2) <= 5 on Kuhn meshes, so CG needs at most
+    ln(2/eps)/ln((sqrt5+1)/(sqrt5-1)) ~ 25 iterations for eps = 1e-10
+    (Jacobi-scaled energy-norm bound; the 2-norm of z tracks it closely)."""
+    sp = inputs.tiny_cube(n=10)
+    m, A = _system(sp)
+    b = np.random.default_rng(3).normal(size=m.n)
+    _, it, _ = orc.pcg(m, A, b, np.zeros(m.n), rtol=1e-10)
+    assert 5 < it <= 30
+
+
+# ---------------------------------------------------------------------------
+# time stepping
+# ---------------------------------------------------------------------------
+def test_charge_balance_invariant():
+    """Summing the theta-scheme rows removes K (K 1 = 0, K symmetric) and chi:
+    1^T M (V^{k+1} - V^k) = (dt / Cm) 1^T M I_stim when I_ion = 0.
+    Catches a wrong dt or Cm factor on the source, or a K term that does not
+    cancel."""
+    sp = inputs.small_box(nx=6, ny=5, nz=4, ionic="ms")
+    sp.ionic = "none"
+    sp.rtol = 1e-14
+    o = orc.Oracle(sp)
+    o.state.V[:] = 1.0
+    o.state.Vprev[:] = 1.0
+    m = o.mats
+    ones = np.ones(m.n)
+    Istim = np.zeros(m.n)
+    Istim[sp.stimuli[0].nodes] = sp.stimuli[0].intensity
+    rhs = sp.dt / sp.cm * (ones @ orc.spmv(m, m.M, Istim))
+    for _ in range(5):
+        V0 = o.state.V.copy()
+        o.steps(1)
+        lhs = ones @ orc.spmv(m, m.M, o.state.V - V0)
+        assert lhs == pytest.approx(rhs, rel=1e-10)
+
+
+def test_uniform_stimulus_reduces_to_single_cell():
+    """Uniform stimulus on the whole mesh from a uniform rest state: V stays
+    uniform (K V = 0) and each step is the single-cell operator split
+    V <- V + dt (I_stim/Cm - I_ion(V, u^{k+1})/Cm)."""
+    sp = inputs.small_box(nx=4, ny=3, nz=3, ionic="ms", n_steps=300)
+    sp.stimuli = [inputs.Stimulus(np.arange(sp.mesh.n_nodes, dtype=np.int32), 0.0, 1.0, 0.5)]
+    sp.rtol = 1e-13
+    o = orc.Oracle(sp)
+    V, u = orc.ionic_init("ms", 1)
+    out, _ = o.steps(300, out_every=1)
+    for k in range(300):
+        iion = orc.ionic_step("ms", V, u, sp.dt)
+        ist = 0.5 if k < 100 else 0.0
+        V = V + sp.dt * (ist / sp.cm - iion)
+        row = out[k]
+        assert abs(row - row.mean()).max() <= 1e-9
+        assert row.mean() == pytest.approx(V[0], abs=1e-9)
+    assert out.max() > 0.0                          # the pulse excites the cell
+
+
+def test_ms_rest_is_fixed_point():
+    """No stimulus: (u, h) = (0, 1) is a fixed point, V stays at V_rest."""
+    sp = inputs.small_box(nx=4, ny=3, nz=3, ionic="ms")
+    sp.stimuli = []
+    o = orc.Oracle(sp)
+    o.steps(50)
+    assert abs(o.state.V + 80.0).max() <= 1e-10
+    assert (o.state.u == 1.0).all()
+    assert np.isinf(o.state.lat).all()
+
+
+def test_ms_rush_larsen_exact_for_frozen_u():
+    """With u held fixed, RL gives h(t) = h_inf + (h0 - h_inf) e^{-t/tau}
+    exactly, for any dt."""
+    p = orc.ionic_defaults("ms")
+    for V, hinf, tau in [(-80.0, 1.0, p[2]), (-10.0, 0.0, p[3])]:
+        u = np.array([[0.3]])
+        t = 0.0
+        for dt in [0.01, 0.5, 3.0, 0.2]:
+            orc.ionic_step("ms", np.array([V]), u, dt)
+            t += dt
+            h_ref = hinf + (0.3 - hinf) * np.exp(-t / tau)
+            assert u[0, 0] == pytest.approx(h_ref, rel=1e-13, abs=1e-15)
+
+
+def test_ms_current_closed_form():
+    """I_ion/Cm = -v_amp (h u^2 (1-u)/tau_in - u/tau_out) at u=(V+80)/100."""
+    p = orc.ionic_defaults("ms")
+    V = np.array([-80.0, -60.0, -20.0, 15.0])
+    u = np.full((1, 4), 0.7)
+    iion = orc.ionic_step("ms", V, u, 1e-300)       # dt -> 0: h unchanged
+    uu = (V + 80.0) / 100.0
+    ref = -100.0 * (0.7 * uu ** 2 * (1 - uu) / p[0] - uu / p[1])
+    np.testing.assert_allclose(iion, ref, rtol=1e-13, atol=1e-14)
+
+
+def _single_cell(kind, t_end, dt=0.01, stim=50.0, dur=2.0):
+    V, u = orc.ionic_init(kind, 1)
+    Vs = np.empty(int(round(t_end / dt)))
+    for k in range(Vs.shape[0]):
+        iion = orc.ionic_step(kind, V, u, dt)
+        V = V + dt * ((stim if k * dt < dur else 0.0) - iion)
+        Vs[k] = V[0]
+    return Vs, u
+
+
+def test_ms_action_potential_duration():
+    """Mitchell & Schaeffer (2003): the longest APD is about
+    tau_close ln(tau_out / (4 tau_in)) = 150 ln 5 = 241 ms at the defaults."""
+    Vs, _ = _single_cell("ms", 400.0)
+    t = np.arange(Vs.shape[0]) * 0.01
+    mid = -80.0 + 50.0
+    up = np.argmax(Vs > mid)
+    down = up + np.argmax(Vs[up:] < mid)
+    apd = t[down] - t[up]
+    assert apd == pytest.approx(150.0 * np.log(5.0), rel=0.10)
+
+
+def test_tt_qualitative_action_potential():
+    """ten Tusscher-Panfilov (parity unpinned against the literature): rest
+    near -85 mV, an action potential that overshoots 0 mV under a 2 ms
+    pulse, an endocardial APD90 of a few hundred ms, all states finite."""
+    Vs, u = _single_cell("tt", 500.0, stim=50.0, dur=1.0)
+    assert -88.0 < Vs[-1] < -83.0
+    assert Vs.max() > 20.0
+    t = np.arange(Vs.shape[0]) * 0.01
+    up = np.argmax(Vs > -40.0)
+    lo = Vs[-1]
+    rep = up + np.argmax(Vs[up + 500:] < lo + 0.1 * (Vs.max() - lo)) + 500
+    assert 200.0 < t[rep] - t[up] < 400.0
+    assert np.isfinite(u).all()
+
+
+def test_symmetry_under_axis_permutations():
+    """Unjittered cube, isotropic sigma, corner stimulus: the Kuhn split is
+    invariant under permutations of the axes, so V(i,j,k) = V(pi(i,j,k))."""
+    n = 8
+    sp = inputs.tiny_cube(n=n, jitter=0.0, n_steps=150)
+    o = orc.Oracle(sp)
+    o.steps(150)
+    V = o.state.V.reshape(n + 1, n + 1, n + 1)
+    assert V.max() - V.min() > 1.0
+    for perm in itertools.permutations(range(3)):
+        np.testing.assert_allclose(V.transpose(perm), V, rtol=0, atol=1e-9)
+
+
+def test_activation_propagates_from_corner():
+    """The corner node activates during the pulse, every stimulated node
+    activates, and LAT grows with distance from the corner along the x-axis
+    edge once the wave has left the stimulated block."""
+    sp = inputs.tiny_cube(n=10, n_steps=600)
+    o = orc.Oracle(sp)
+    o.steps(600)
+    lat = o.state.lat
+    stim = sp.stimuli[0].nodes
+    assert np.isfinite(lat[stim]).all() and lat[0] <= 2.0 + 1e-12
+    n = 10
+    edge = [(i * (n + 1) + 0) * (n + 1) + 0 for i in range(n + 1)]
+    le = lat[edge]
+    assert np.isfinite(le).all()
+    assert np.all(np.diff(le[5:]) > 0)
+
+
+# ---------------------------------------------------------------------------
+# manufactured solution (Neumann-compatible 3D form of the paper's test)
+# ---------------------------------------------------------------------------
+K_DECAY = 0.1
+
+
+def _w(x, t):
+    return np.exp(-K_DECAY * t) * np.cos(np.pi * x[:, 0]) * np.cos(np.pi * x[:, 1]) \
+        * np.cos(np.pi * x[:, 2])
+
+
+def _mms_run(n, dt, T, theta):
+    """chi = Cm = 1, sigma = I, I_ion = 0, source r = w_t - lap w =
+    (-k + 3 pi^2) w entered at t^{k+theta}; returns (error L2, V)."""
+    sp = inputs.tiny_cube(n=n, jitter=0.0, n_steps=0)
+    sp.stimuli, sp.ionic = [], "none"
+    sp.chi, sp.cm, sp.sigma_l, sp.sigma_t, sp.theta, sp.dt = 1.0, 1.0, 1.0, 1.0, theta, dt
+    sp.rtol = 1e-13
+    o = orc.Oracle(sp)
+    x = sp.mesh.xyz
+    w0 = _w(x, 0.0)
+    o.state.V[:] = w0
+    o.state.Vprev[:] = w0
+    ns = int(round(T / dt))
+    c = -K_DECAY + 3 * np.pi ** 2
+    src = np.stack([c * (theta * _w(x, (k + 1) * dt) + (1 - theta) * _w(x, k * dt))
+                    for k in range(ns)])
+    o.steps(ns, extra_src=src)
+    e = o.state.V - _w(x, ns * dt)
+    return np.sqrt(e @ orc.spmv(o.mats, o.mats.M, e)), o.state.V
+
+
+def test_mms_space_order_two():
+    errs = [_mms_run(n, 0.002, 0.2, 0.5)[0] for n in (8, 16, 32)]
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] >= 1.9, (errs, rates)
+
+
+def _semi_discrete_run(dt, T, theta, lam=1.0):
+    """Manufactured solution of the space-discrete system itself:
+    M V' + K V = M s(t) with V(t) = a(t) phi, a(t) = e^{-kt} cos(lam t), holds
+    exactly for s(t) = a'(t) phi + a(t) M^{-1} K phi (M^{-1} K phi from a dense
+    solve).  The fully discrete error is then pure time-stepping error."""
+    n = 6
+    sp = inputs.tiny_cube(n=n, jitter=0.05, n_steps=0)
+    sp.stimuli, sp.ionic = [], "none"
+    sp.chi, sp.cm, sp.sigma_l, sp.sigma_t, sp.theta, sp.dt = 1.0, 1.0, 1.0, 1.0, theta, dt
+    sp.rtol = 1e-14
+    o = orc.Oracle(sp)
+    x = sp.mesh.xyz
+    phi = _w(x, 0.0) + 0.3 * np.random.default_rng(5).uniform(-1, 1, x.shape[0])
+    g = np.linalg.solve(o.mats.dense("M"), o.mats.dense("K") @ phi)
+
+    def a(t):
+        return np.exp(-K_DECAY * t) * np.cos(lam * t)
+
+    def da(t):
+        return -np.exp(-K_DECAY * t) * (K_DECAY * np.cos(lam * t) + lam * np.sin(lam * t))
+
+    def s(t):
+        return da(t) * phi + a(t) * g
+
+    o.state.V[:] = phi
+    o.state.Vprev[:] = phi
+    ns = int(round(T / dt))
+    src = np.stack([theta * s((k + 1) * dt) + (1 - theta) * s(k * dt) for k in range(ns)])
+    o.steps(ns, extra_src=src)
+    return abs(o.state.V - a(ns * dt) * phi).max()
+
+
+@pytest.mark.parametrize("theta,order", [(0.5, 2.0), (1.0, 1.0)])
+def test_time_order(theta, order):
+    """Second order in dt for Crank-Nicolson, first for backward Euler,
+    against the exact solution of the semi-discrete system.  A wrong sign or
+    weight on the (1-theta) dt K V^k term makes the scheme inconsistent."""
+    errs = [_semi_discrete_run(dt, 2.0, theta) for dt in (0.2, 0.1, 0.05, 0.025)]
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] == pytest.approx(order, abs=0.1), (errs, rates)
