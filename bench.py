@@ -1,0 +1,133 @@
+"""Benchmark of the monodomain hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload slab]
+
+A step is one time step of the whole hot path (ionic update, fused RHS and
+initial residual, Jacobi-PCG to tolerance, activation times) on the
+workload's synthetic mesh.  W untimed steps run first, the state is reset to
+rest, then exactly K steps are timed between device synchronisations.  The
+value is DOF*steps/s = n_nodes * K / seconds.
+
+Also reported, as one JSON line:
+  roofline      the dominant kernel (PCG SpMV): algorithmic bytes per launch
+                (12 B per structural nonzero + 16 B per row) over its mean
+                duration, measured with HIP events attached to every SpMV
+                dispatch of the timed region, against 8 TB/s
+  cpu_baseline  the CPU oracle (plain FP64 C, OpenMP) timed on this host on a
+                bounded prefix of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("DOF·steps/s at equal accuracy, learned+FP32 vs plain FP64 PCG; "
+          "SpMV HBM GB/s")
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    from paper_2510_12011_amd import inputs
+    if name == "slab":
+        return inputs.slab(h=0.1), "slab 20x7x3 mm, h=0.1 mm Kuhn tets, ten Tusscher-Panfilov, plain FP64"
+    if name == "slab_h0.05":
+        return (inputs.slab(h=0.05),
+                "slab 20x7x3 mm, h=0.05 mm Kuhn tets, ten Tusscher-Panfilov, plain FP64")
+    if name == "tiny":
+        return inputs.tiny_cube(), "unit cube 20^3 hexes, Mitchell-Schaeffer, plain FP64"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(spec, steps, threads=None):
+    from oracle import orc
+    if threads:
+        orc.lib().orc_set_threads(threads)
+    o = orc.Oracle(spec)
+    t0 = time.perf_counter()
+    _, it = o.steps(steps)
+    dt = time.perf_counter() - t0
+    return {"value": spec.mesh.n_nodes * steps / dt, "unit": "DOF*steps/s",
+            "cores": orc.threads(), "kind": "oracle",
+            "sample": f"first {steps} steps from rest of the same workload "
+                      f"(mean {float(np.mean(it)):.1f} CG iterations/step), setup excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="slab")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the method runs one simulation per GPU and "
+              "this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_12011_amd import sim
+
+    spec, desc = workload(args.workload)
+    n = spec.mesh.n_nodes
+    print(f"[bench] workload {args.workload}: {n} nodes, {spec.mesh.n_tets} tets", flush=True)
+    s = sim.from_spec(spec)
+    st = s.stats()
+    if args.warmup:
+        s.run(args.warmup)
+        s.prepare(spec.dt)          # back to rest; timing starts from t = 0
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, status = s.run(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = s.stats()
+    iters = s.iterations(args.steps)
+    print(f"[bench] {args.steps} steps in {elapsed:.3f} s, mean CG iterations "
+          f"{iters.mean():.2f}, status {status}", flush=True)
+
+    value = n * args.steps / elapsed
+    nnz = st["nnz"]
+    bytes_per_launch = 12 * nnz + 16 * n
+    spmv_avg = st["spmv_seconds"] / max(1, st["spmv_timed"])
+    achieved = bytes_per_launch / spmv_avg / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_nodes": n, "nnz": nnz, "n_tets": spec.mesh.n_tets,
+                   "dt_ms": spec.dt, "rtol": spec.rtol, "stopping": "relative to ||z0||",
+                   "warm_start": "2V^k - V^(k-1)", "mean_cg_iters": float(iters.mean()),
+                   "max_cg_iters": int(iters.max())},
+        "roofline": {"bound": "hbm", "kernel": "k_spmv_dot", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": 1e6 * spmv_avg, "launches_timed": st["spmv_timed"]},
+    }
+    if not args.no_cpu:
+        print(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps", flush=True)
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

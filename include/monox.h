@@ -1,0 +1,198 @@
+/*
+ * monox.h -- C ABI of the MI355X monodomain finite-element hot path.
+ *
+ * The library advances the monodomain model of TorchCor (arXiv 2510.12011):
+ * Eq. (1) discretised with P1 finite elements in space and the theta-method
+ * in time (Eq. 2 and the definitions of A and b after Eq. 3), one step being
+ *   1. ionic update at every node (states by forward Euler, gating variables
+ *      by Rush-Larsen), I_ion = I_ion(V^k, u^{k+1});
+ *   2. b = chi M (Cm V^k - dt I_ion + dt I_stim) - (1-theta) dt K V^k;
+ *   3. A V^{k+1} = b, A = chi Cm M + theta dt K, solved by Jacobi-PCG
+ *      (Algorithm 1) from a warm start (2V^k - V^{k-1} by default);
+ *   4. activation (LAT) and repolarisation (LRT) times.
+ * The problem statement follows the "Software functionality" section: a mesh
+ * with fibres and element regions, per-region longitudinal/transverse
+ * conductivities, an ionic model with editable parameters, any number of
+ * timed stimuli on node sets, solver tolerances, V saved at a fixed interval.
+ *
+ * Units (Table 1): mm, ms, mV, uA/mm^2, uF/mm^2, 1/mm, S/m.
+ * Node and element ids are 0-based int32.  Every array crossing this
+ * interface is in the caller's ORIGINAL node order; the library reorders
+ * nodes internally (reverse Cuthill-McKee) and undoes it on output.
+ *
+ * Ownership: the caller owns every host array; the library copies inputs
+ * before returning and keeps no pointer to them.  Device memory comes from
+ * the caller: a persistent workspace bound with mdx_bind_workspace (it must
+ * outlive the context) and a setup scratch passed to mdx_prepare (free to
+ * reuse once mdx_prepare has returned).  The library itself allocates only
+ * pinned host staging buffers (flags and one snapshot of V).
+ *
+ * Errors: every call returns an mdx_status.  Negative: the call had no
+ * effect; mdx_last_error() describes it.  Positive: a warning, results are
+ * valid (e.g. some PCG solves reached max_iter).  No C++ exception crosses
+ * this interface.  A context is bound to one device and one HIP stream and
+ * is not thread-safe.
+ */
+#ifndef MONOX_H
+#define MONOX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef MDX_API
+#define MDX_API __attribute__((visibility("default")))
+#endif
+
+typedef enum {
+    MDX_OK = 0,
+    MDX_WARN_NOT_CONVERGED = 1,   /* some solves hit max_iter; see mdx_stats */
+    MDX_ERR_INVALID_ARG = -1,     /* bad pointer, size, range or value       */
+    MDX_ERR_BAD_MESH = -2,        /* out-of-range id, degenerate element     */
+    MDX_ERR_DEVICE = -3,          /* a HIP call failed                       */
+    MDX_ERR_NO_WORKSPACE = -4,    /* workspace missing or too small          */
+    MDX_ERR_NONFINITE = -5,       /* NaN/Inf appeared in V                   */
+    MDX_ERR_STATE = -6,           /* call out of order (e.g. run before prepare) */
+    MDX_ERR_UNSUPPORTED = -7
+} mdx_status;
+
+typedef struct mdx_ctx mdx_ctx;
+
+/* ionic models: none (diffusion only), Mitchell-Schaeffer two-variable,
+ * ten Tusscher-Panfilov 2006 (endocardial) */
+enum { MDX_IONIC_NONE = 0, MDX_IONIC_MS = 1, MDX_IONIC_TT = 2 };
+/* PCG warm start: previous step V^k, extrapolation 2V^k - V^{k-1} (paper) */
+enum { MDX_WS_PREV = 0, MDX_WS_EXTRAP = 1 };
+/* relative stopping test: ||z|| / ||z_0|| (paper) or ||z|| / ||D^-1 b|| */
+enum { MDX_REL_INITIAL = 0, MDX_REL_RHS = 1 };
+/* which assembled matrix mdx_get_matrix returns */
+enum { MDX_MAT_M = 0, MDX_MAT_K = 1, MDX_MAT_A = 2 };
+
+typedef struct {
+    double atol;          /* absolute tolerance on ||z|| (0: off)           */
+    double rtol;          /* relative tolerance, see rel_mode               */
+    int32_t rel_mode;     /* MDX_REL_*                                      */
+    int32_t max_iter;     /* iteration cap per solve (>= 1)                 */
+    int32_t warm_start;   /* MDX_WS_*                                       */
+    int32_t reserved;     /* must be 0                                      */
+} mdx_solver_opts;
+
+typedef struct {
+    int64_t steps;            /* steps advanced since prepare / reset        */
+    int64_t cg_iters_total;
+    int64_t cg_iters_max;
+    int64_t not_converged;    /* solves that reached max_iter                */
+    int64_t n_nodes, nnz, n_sell_slots, bandwidth;
+    double step_loop_seconds; /* host wall time inside mdx_run               */
+    int64_t spmv_timed;       /* SpMV launches timed (profiling on, real work) */
+    double spmv_seconds;      /* their summed device duration (HIP events)   */
+} mdx_stats;
+
+/* ---- context -------------------------------------------------------- */
+/* device: HIP device ordinal; stream: a hipStream_t (NULL = null stream).
+ * device -1 creates a host-only context that accepts the problem statement
+ * (validation, reordering, workspace sizing) but no device work. */
+MDX_API mdx_status mdx_create(mdx_ctx **out, int device, void *stream);
+MDX_API void mdx_destroy(mdx_ctx *ctx);
+/* message of the last failing call on ctx (never NULL) */
+MDX_API const char *mdx_last_error(const mdx_ctx *ctx);
+/* library version, for the binding's sanity check */
+MDX_API int mdx_version(void);
+
+/* ---- problem statement ------------------------------------------------ */
+/* Mesh (P1 tetrahedra).  xyz: n_nodes*3 doubles, divided by unit_conversion
+ * to give mm (1000 for micrometre input).  tets: n_tets*4 ids.  region:
+ * n_tets region tags or NULL (all 0).  fibre: n_tets*3 directions (any
+ * length, normalised inside) or NULL (isotropic: transverse value used).
+ * Rejects non-finite coordinates, ids out of range and elements with
+ * |det J| <= 1e-14 h^3 (h: the element's longest edge). */
+MDX_API mdx_status mdx_set_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz,
+                        double unit_conversion, int64_t n_tets, const int32_t *tets,
+                        const int32_t *region, const double *fibre);
+/* Conductivities (S/m) along (il) and across (it) the fibre for every
+ * element whose region tag is in region_ids[0..n_ids).  Later calls override
+ * earlier ones for the same tag.  Every tag present must be covered before
+ * mdx_prepare. */
+MDX_API mdx_status mdx_add_conductivity(mdx_ctx *ctx, int32_t n_ids, const int32_t *region_ids,
+                                double il, double it);
+/* chi (1/mm) > 0, Cm (uF/mm^2) > 0, theta in [0, 1] (0.5: Crank-Nicolson) */
+MDX_API mdx_status mdx_set_tissue(mdx_ctx *ctx, double chi, double cm, double theta);
+/* Ionic model and its editable parameters (NULL: defaults).
+ * MDX_IONIC_MS, 7 params: tau_in, tau_out, tau_open, tau_close, u_gate,
+ *   v_rest, v_amp (defaults 0.3, 6, 120, 150, 0.13, -80, 100).
+ * MDX_IONIC_TT, 12 params: maximal conductances GNa, GK1, Gto, GKr, GKs,
+ *   GCaL, GbNa, GbCa, GpCa, GpK and pump/exchanger scales PNaK, kNaCa. */
+MDX_API mdx_status mdx_set_ionic(mdx_ctx *ctx, int32_t kind, int32_t n_params, const double *params);
+/* number of ionic states per node (excluding V) and of parameters */
+MDX_API int32_t mdx_ionic_nstates(int32_t kind);
+MDX_API int32_t mdx_ionic_nparams(int32_t kind);
+/* Stimulus: intensity (uA/mm^2) on node_idx[0..n_idx) for steps k with
+ * round(start/dt) <= k < round((start+duration)/dt).  Stimuli add. */
+MDX_API mdx_status mdx_add_stimulus(mdx_ctx *ctx, int64_t n_idx, const int32_t *node_idx,
+                            double start, double duration, double intensity);
+MDX_API mdx_status mdx_set_solver(mdx_ctx *ctx, const mdx_solver_opts *opts);
+
+/* ---- device memory ---------------------------------------------------- */
+/* Bytes of persistent workspace and of one-off setup scratch that
+ * mdx_prepare needs for the current mesh and model (256-byte aligned). */
+MDX_API mdx_status mdx_workspace_size(mdx_ctx *ctx, size_t *persistent_bytes, size_t *scratch_bytes);
+/* device_ptr: device memory on ctx's device, at least persistent_bytes. */
+MDX_API mdx_status mdx_bind_workspace(mdx_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* ---- setup and time stepping ------------------------------------------ */
+/* Assemble M, K and A = chi Cm M + theta dt K on the device, build the
+ * Jacobi preconditioner and set V, states to the ionic model's rest values
+ * (V^{-1} := V^0), LAT/LRT to +inf, step counter to 0.  scratch: device
+ * memory of at least scratch_bytes.  Blocks until the device is done. */
+MDX_API mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_bytes);
+/* Advance n_steps.  Every out_every steps (0: never) the current V is
+ * written to v_out (host, [n_steps/out_every][n_nodes] doubles, may be
+ * NULL).  Returns MDX_WARN_NOT_CONVERGED if a solve hit max_iter,
+ * MDX_ERR_NONFINITE (state left as is, step counter at the failing step)
+ * if V stopped being finite. */
+MDX_API mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_out);
+/* LAT and LRT (ms; +inf where not reached), host arrays of n_nodes or NULL */
+MDX_API mdx_status mdx_get_times(mdx_ctx *ctx, double *lat, double *lrt);
+/* PCG iteration count of each of the last n steps (n <= steps run so far
+ * in the last mdx_run call), -1 where max_iter was hit. */
+MDX_API mdx_status mdx_get_iterations(mdx_ctx *ctx, int64_t n, int32_t *iters);
+MDX_API mdx_status mdx_get_stats(mdx_ctx *ctx, mdx_stats *out);
+/* Profiling: when enabled, every PCG SpMV launch in mdx_run carries HIP
+ * start/stop events on the context's stream; the durations of the launches
+ * that did work (not those queued after convergence) are summed into
+ * mdx_stats.spmv_seconds / spmv_timed.  Off by default. */
+MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t enable);
+
+/* ---- state (checkpoint / resume, parity checks) ----------------------- */
+/* V^k, V^{k-1}, states u (SoA, [nstates][n_nodes]), LAT, LRT and the step
+ * index, all host arrays in original node order; any pointer may be NULL
+ * on get.  set requires all of V, Vprev, u (if nstates > 0). */
+MDX_API mdx_status mdx_get_state(mdx_ctx *ctx, double *V, double *Vprev, double *u,
+                         double *lat, double *lrt, int64_t *step);
+MDX_API mdx_status mdx_set_state(mdx_ctx *ctx, const double *V, const double *Vprev,
+                         const double *u, const double *lat, const double *lrt,
+                         int64_t step);
+
+/* ---- inspection -------------------------------------------------------- */
+/* Assembled matrix `which` (MDX_MAT_*) as COO triplets in original node
+ * numbering, structural zeros of the padded layout omitted.  Call with
+ * rows == NULL to get *nnz; then with arrays of *nnz entries. */
+MDX_API mdx_status mdx_get_matrix(mdx_ctx *ctx, int32_t which, int64_t *nnz, int32_t *rows,
+                          int32_t *cols, double *vals);
+/* y = which * x with the library's SpMV kernel; host x, y in original order */
+MDX_API mdx_status mdx_spmv(mdx_ctx *ctx, int32_t which, const double *x, double *y);
+/* One ionic update of the model set by mdx_set_ionic on n independent cells,
+ * DEVICE arrays on ctx's device and stream: V[n]; u[nstates][n] (SoA)
+ * advanced in place; iion[n] receives I_ion(V, u^{k+1}) / Cm in mV/ms.
+ * Needs no mesh and no workspace; does not touch the simulation state.
+ * Blocks until the device is done. */
+MDX_API mdx_status mdx_ionic_step(mdx_ctx *ctx, double dt, int64_t n, const double *V,
+                          double *u, double *iion);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MONOX_H */

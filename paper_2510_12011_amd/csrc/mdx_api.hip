@@ -1,0 +1,1086 @@
+// Host side of the monodomain library: the C ABI of include/monox.h.
+//
+// Setup (host, once per mesh): validation, node adjacency, reverse
+// Cuthill-McKee ordering (the paper reorders with RCM to shrink the matrix
+// bandwidth, "Software implementation" section), the sliced-ELL pattern shared
+// by M, K and A, and the slot map that lists, for every matrix slot, the
+// (element, a, b) contributions in ascending element order.  Device setup
+// (mdx_prepare): element matrices, deterministic gather into M and K,
+// A = chi Cm M + theta dt K, the Jacobi diagonal, rest state.
+//
+// Time loop (mdx_run): per step the kernels of mdx_ionic.hip / mdx_solver.hip
+// are queued on the context's stream; PCG iterations are queued in chunks
+// (first chunk = last step's count + 1) and the host reads the device-side
+// `done` flag once per chunk.  Iterations queued after convergence return at
+// their first instruction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/monox.h"
+#include "mdx_internal.h"
+
+using namespace mdx;
+
+namespace {
+
+constexpr int kMaxGroups = 1024;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Stim {
+    std::vector<int32_t> nodes;   // original ids, sorted, unique
+    double start, duration, amp;
+};
+
+// byte offsets of every array inside the persistent workspace / setup scratch
+struct Layout {
+    size_t slice_ptr, col, Mv, Kv, Av, dinv, vec[3], r, p, q, b, s, istim, u, lat, lrt, stim_idx,
+        partial, scalars, total;
+    size_t x_xyz, x_tets, x_fibre, x_sig, x_vol, x_ek, x_cptr, x_contrib, x_total;
+};
+
+}  // namespace
+
+struct mdx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // problem statement (host copies, original numbering)
+    int64_t n = 0, m = 0;
+    std::vector<double> xyz;       // mm
+    std::vector<int32_t> tets, region;
+    std::vector<double> fibre;     // empty: isotropic
+    std::map<int32_t, std::pair<double, double>> cond;
+    double chi = 140.0, cm = 0.01, theta = 0.5;
+    int ionic_kind = 0;
+    std::vector<double> ionic_params;
+    std::vector<Stim> stims;
+    mdx_solver_opts opts{1e-5, 1e-5, MDX_REL_INITIAL, 100, MDX_WS_EXTRAP, 0};
+
+    // ordering and layout (host)
+    std::vector<int32_t> perm, iperm;   // perm[new] = old, iperm[old] = new
+    int64_t npad = 0, nslices = 0, nslots = 0, nnz = 0, bandwidth = 0;
+    std::vector<int64_t> slice_ptr;
+    std::vector<int32_t> col_sell, rowlen;
+    std::vector<int64_t> stim_off;      // offsets of each stimulus in the device list
+
+    // device memory
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L{};
+    Tiling tiling{};
+    bool prepared = false;
+    double dt = 0.0;
+    int64_t step = 0;
+    int vb[3] = {0, 1, 2};   // which vec[] holds V^k, V^{k-1}, x
+    std::vector<char> active;  // stimuli currently summed into istim
+
+    Scalars *sc_host = nullptr;   // pinned
+    double *stage = nullptr;      // pinned, npad doubles
+
+    // profiling: event pairs around the SpMV launches of one step
+    bool profiling = false;
+    std::vector<hipEvent_t> ev;
+
+    // statistics
+    int last_iters = 0;
+    std::vector<int32_t> iters_hist;
+    mdx_stats stats{};
+
+    template <class T>
+    T *dev(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    double *vec(int role) const { return dev<double>(L.vec[vb[role]]); }
+};
+
+namespace {
+
+mdx_status fail(mdx_ctx *c, mdx_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, MDX_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                              \
+    }                                                                          \
+    catch (const std::bad_alloc &) {                                           \
+        return fail(ctx, MDX_ERR_INVALID_ARG, "host allocation failed");       \
+    }                                                                          \
+    catch (...) {                                                              \
+        return fail(ctx, MDX_ERR_INVALID_ARG, "unexpected host exception");    \
+    }
+
+// ---------------------------------------------------------------------------
+// graph of the mesh: node -> neighbouring nodes (sharing a tet), no self
+// ---------------------------------------------------------------------------
+void node_graph(int64_t n, int64_t m, const int32_t *tets, std::vector<int64_t> &ptr,
+                std::vector<int32_t> &adj)
+{
+    std::vector<int64_t> tptr(n + 1, 0);
+    for (int64_t q = 0; q < 4 * m; ++q) tptr[tets[q] + 1]++;
+    for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+    std::vector<int32_t> tlist(tptr[n]);
+    {
+        std::vector<int64_t> pos(tptr.begin(), tptr.end() - 1);
+        for (int64_t e = 0; e < m; ++e)
+            for (int a = 0; a < 4; ++a) tlist[pos[tets[4 * e + a]]++] = (int32_t)e;
+    }
+    std::vector<int32_t> mark(n, -1);
+    ptr.assign(n + 1, 0);
+    adj.clear();
+    adj.reserve((size_t)(14 * n));
+    for (int64_t i = 0; i < n; ++i) {
+        size_t row0 = adj.size();
+        mark[i] = (int32_t)i;
+        for (int64_t q = tptr[i]; q < tptr[i + 1]; ++q) {
+            const int32_t *t = tets + 4 * (int64_t)tlist[q];
+            for (int a = 0; a < 4; ++a)
+                if (mark[t[a]] != (int32_t)i) {
+                    mark[t[a]] = (int32_t)i;
+                    adj.push_back(t[a]);
+                }
+        }
+        std::sort(adj.begin() + row0, adj.end());
+        ptr[i + 1] = (int64_t)adj.size();
+    }
+}
+
+// Reverse Cuthill-McKee: per connected component, BFS from a pseudo-peripheral
+// node (George-Liu search) visiting neighbours by increasing degree (ties by
+// index); the concatenated order is reversed.  Returns perm[new] = old.
+std::vector<int32_t> rcm(int64_t n, const std::vector<int64_t> &ptr, const std::vector<int32_t> &adj)
+{
+    auto deg = [&](int32_t v) { return ptr[v + 1] - ptr[v]; };
+    std::vector<int32_t> order;
+    order.reserve(n);
+    std::vector<char> placed(n, 0);
+    std::vector<int32_t> level(n, -1), queue;
+    queue.reserve(n);
+    std::vector<int32_t> touched;
+
+    // BFS levels from root; returns eccentricity and the last level's nodes
+    auto bfs_levels = [&](int32_t root, std::vector<int32_t> &last) {
+        for (int32_t v : touched) level[v] = -1;
+        touched.clear();
+        queue.clear();
+        queue.push_back(root);
+        level[root] = 0;
+        touched.push_back(root);
+        size_t head = 0;
+        int ecc = 0;
+        while (head < queue.size()) {
+            int32_t v = queue[head++];
+            ecc = std::max(ecc, level[v]);
+            for (int64_t q = ptr[v]; q < ptr[v + 1]; ++q) {
+                int32_t w = adj[q];
+                if (level[w] < 0) {
+                    level[w] = level[v] + 1;
+                    touched.push_back(w);
+                    queue.push_back(w);
+                }
+            }
+        }
+        last.clear();
+        for (int32_t v : queue)
+            if (level[v] == ecc) last.push_back(v);
+        return ecc;
+    };
+
+    std::vector<int32_t> last, nbr;
+    for (int64_t s = 0; s < n; ++s) {
+        if (placed[s]) continue;
+        int32_t root = (int32_t)s;
+        int ecc = bfs_levels(root, last);
+        for (int guard = 0; guard < 64; ++guard) {
+            int32_t cand = last[0];
+            for (int32_t v : last)
+                if (deg(v) < deg(cand) || (deg(v) == deg(cand) && v < cand)) cand = v;
+            std::vector<int32_t> last2;
+            int e2 = bfs_levels(cand, last2);
+            if (e2 > ecc) {
+                root = cand;
+                ecc = e2;
+                last.swap(last2);
+            } else {
+                break;
+            }
+        }
+        // Cuthill-McKee BFS from root
+        size_t head = order.size();
+        order.push_back(root);
+        placed[root] = 1;
+        while (head < order.size()) {
+            int32_t v = order[head++];
+            nbr.clear();
+            for (int64_t q = ptr[v]; q < ptr[v + 1]; ++q)
+                if (!placed[adj[q]]) nbr.push_back(adj[q]);
+            std::sort(nbr.begin(), nbr.end(), [&](int32_t a, int32_t b) {
+                return deg(a) < deg(b) || (deg(a) == deg(b) && a < b);
+            });
+            for (int32_t w : nbr) {
+                placed[w] = 1;
+                order.push_back(w);
+            }
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
+// position of column c in new-row r of the sliced-ELL pattern, or -1
+int64_t sell_slot(const mdx_ctx *c, int64_t r, int32_t colv)
+{
+    int64_t base = c->slice_ptr[r / SLICE] + (r % SLICE);
+    int lo = 0, hi = c->rowlen[r] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) / 2;
+        int32_t v = c->col_sell[base + (int64_t)mid * SLICE];
+        if (v == colv) return base + (int64_t)mid * SLICE;
+        if (v < colv) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+void compute_layout(mdx_ctx *c)
+{
+    Layout &L = c->L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    const size_t np = (size_t)c->npad, ns = (size_t)c->nslots;
+    L.slice_ptr = take(sizeof(int64_t) * (c->nslices + 1));
+    L.col = take(sizeof(int32_t) * ns);
+    L.Mv = take(sizeof(double) * ns);
+    L.Kv = take(sizeof(double) * ns);
+    L.Av = take(sizeof(double) * ns);
+    L.dinv = take(sizeof(double) * np);
+    for (int i = 0; i < 3; ++i) L.vec[i] = take(sizeof(double) * np);
+    L.r = take(sizeof(double) * np);
+    L.p = take(sizeof(double) * np);
+    L.q = take(sizeof(double) * np);
+    L.b = take(sizeof(double) * np);
+    L.s = take(sizeof(double) * np);
+    L.istim = take(sizeof(double) * np);
+    L.u = take(sizeof(double) * np * std::max(1, ionic_nstates(c->ionic_kind)));
+    L.lat = take(sizeof(double) * np);
+    L.lrt = take(sizeof(double) * np);
+    size_t nst = 0;
+    for (auto &s : c->stims) nst += s.nodes.size();
+    L.stim_idx = take(sizeof(int32_t) * std::max<size_t>(nst, 1));
+    L.partial = take(sizeof(double) * 3 * 3 * kMaxGroups);
+    L.scalars = take(sizeof(Scalars));
+    L.total = o;
+
+    o = 0;
+    const size_t m = (size_t)c->m, n = (size_t)c->n;
+    L.x_xyz = take(sizeof(double) * 3 * n);
+    L.x_tets = take(sizeof(int32_t) * 4 * m);
+    L.x_fibre = take(sizeof(double) * 3 * (c->fibre.empty() ? 1 : m));
+    L.x_sig = take(sizeof(double) * 2 * m);
+    L.x_vol = take(sizeof(double) * m);
+    L.x_ek = take(sizeof(double) * 16 * m);
+    L.x_cptr = take(sizeof(int64_t) * (ns + 1));
+    L.x_contrib = take(sizeof(int32_t) * 16 * m);
+    L.x_total = o;
+}
+
+mdx_status require_mesh(mdx_ctx *ctx)
+{
+    if (ctx->n <= 0) return fail(ctx, MDX_ERR_STATE, "no mesh set");
+    return MDX_OK;
+}
+
+mdx_status copy_vec_out(mdx_ctx *ctx, const double *dsrc, double *host)
+{
+    HIPCHK(hipMemcpyAsync(ctx->stage, dsrc, sizeof(double) * ctx->npad, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int64_t i = 0; i < ctx->n; ++i) host[i] = ctx->stage[ctx->iperm[i]];
+    return MDX_OK;
+}
+
+mdx_status copy_vec_in(mdx_ctx *ctx, const double *host, double *ddst)
+{
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int64_t r = 0; r < ctx->npad; ++r) ctx->stage[r] = r < ctx->n ? host[ctx->perm[r]] : 0.0;
+    HIPCHK(hipMemcpyAsync(ddst, ctx->stage, sizeof(double) * ctx->npad, hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MDX_OK;
+}
+
+StepParams step_params(const mdx_ctx *c)
+{
+    StepParams sp;
+    sp.chi = c->chi;
+    sp.cm = c->cm;
+    sp.theta = c->theta;
+    sp.dt = c->dt;
+    sp.warm_start = c->opts.warm_start;
+    sp.rel_mode = c->opts.rel_mode;
+    return sp;
+}
+
+// Rebuild istim if the set of stimuli active at step k changed.
+mdx_status update_stimulus(mdx_ctx *ctx, int64_t k, bool &any)
+{
+    std::vector<char> want(ctx->stims.size(), 0);
+    any = false;
+    for (size_t s = 0; s < ctx->stims.size(); ++s) {
+        const Stim &st = ctx->stims[s];
+        int64_t ks = std::llround(st.start / ctx->dt);
+        int64_t ke = std::llround((st.start + st.duration) / ctx->dt);
+        want[s] = (k >= ks && k < ke) ? 1 : 0;
+        any = any || want[s];
+    }
+    if (want == ctx->active) return MDX_OK;
+    double *istim = ctx->dev<double>(ctx->L.istim);
+    launch_fill(ctx->stream, ctx->npad, 0.0, istim);
+    for (size_t s = 0; s < ctx->stims.size(); ++s)
+        if (want[s])
+            launch_stim_add(ctx->stream, (int64_t)ctx->stims[s].nodes.size(),
+                            ctx->dev<int32_t>(ctx->L.stim_idx) + ctx->stim_off[s],
+                            ctx->stims[s].amp, istim);
+    HIPCHK(hipGetLastError());
+    ctx->active = want;
+    return MDX_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int mdx_version(void) { return 1; }
+
+int32_t mdx_ionic_nstates(int32_t kind) { return ionic_nstates(kind); }
+int32_t mdx_ionic_nparams(int32_t kind) { return ionic_nparams(kind); }
+
+mdx_status mdx_create(mdx_ctx **out, int device, void *stream)
+{
+    if (!out) return MDX_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (device == -1) {   // host-only context: problem statement and validation only
+        mdx_ctx *ctx = new (std::nothrow) mdx_ctx();
+        if (!ctx) return MDX_ERR_INVALID_ARG;
+        ctx->device = -1;
+        *out = ctx;
+        return MDX_OK;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return MDX_ERR_DEVICE;
+    mdx_ctx *ctx = new (std::nothrow) mdx_ctx();
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)stream;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return MDX_ERR_DEVICE;
+    }
+    *out = ctx;
+    return MDX_OK;
+}
+
+void mdx_destroy(mdx_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->device < 0) {
+        delete ctx;
+        return;
+    }
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream); else (void)hipDeviceSynchronize();
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    if (ctx->sc_host) (void)hipHostFree(ctx->sc_host);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    delete ctx;
+}
+
+const char *mdx_last_error(const mdx_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mdx_status mdx_set_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz, double unit_conversion,
+                        int64_t n_tets, const int32_t *tets, const int32_t *region,
+                        const double *fibre)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    GUARD_BEGIN
+    if (n_nodes <= 0 || n_tets <= 0 || !xyz || !tets)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "empty mesh or null array");
+    if (n_nodes >= (int64_t)1 << 31 || n_tets >= (int64_t)1 << 27)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "mesh too large (n < 2^31, tets < 2^27)");
+    if (!(unit_conversion > 0.0) || !std::isfinite(unit_conversion))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "unit_conversion must be finite and > 0");
+    for (int64_t i = 0; i < 3 * n_nodes; ++i)
+        if (!std::isfinite(xyz[i]))
+            return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite coordinate at node %lld",
+                        (long long)(i / 3));
+    for (int64_t q = 0; q < 4 * n_tets; ++q)
+        if (tets[q] < 0 || tets[q] >= n_nodes)
+            return fail(ctx, MDX_ERR_BAD_MESH, "element %lld references node %d out of range",
+                        (long long)(q / 4), tets[q]);
+    if (fibre)
+        for (int64_t q = 0; q < 3 * n_tets; ++q)
+            if (!std::isfinite(fibre[q]))
+                return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite fibre at element %lld",
+                            (long long)(q / 3));
+    std::vector<double> X(xyz, xyz + 3 * n_nodes);
+    for (double &v : X) v /= unit_conversion;
+    // element quality: |det J| > 1e-14 h^3
+    for (int64_t e = 0; e < n_tets; ++e) {
+        const int32_t *t = tets + 4 * e;
+        double d[3][3], h2 = 0.0;
+        for (int a = 1; a < 4; ++a)
+            for (int k = 0; k < 3; ++k) d[a - 1][k] = X[3 * t[a] + k] - X[3 * t[0] + k];
+        for (int a = 0; a < 4; ++a)
+            for (int b = a + 1; b < 4; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    double w = X[3 * t[a] + k] - X[3 * t[b] + k];
+                    s += w * w;
+                }
+                h2 = std::max(h2, s);
+            }
+        double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                     d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                     d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+        double h3 = h2 * std::sqrt(h2);
+        if (!(std::fabs(det) > 1e-14 * h3))
+            return fail(ctx, MDX_ERR_BAD_MESH, "degenerate element %lld (|det J| = %g)",
+                        (long long)e, std::fabs(det));
+    }
+
+    // adjacency, RCM, sliced-ELL pattern
+    std::vector<int64_t> gptr;
+    std::vector<int32_t> gadj;
+    node_graph(n_nodes, n_tets, tets, gptr, gadj);
+    std::vector<int32_t> perm = rcm(n_nodes, gptr, gadj);
+    std::vector<int32_t> iperm(n_nodes);
+    for (int64_t r = 0; r < n_nodes; ++r) iperm[perm[r]] = (int32_t)r;
+
+    const int64_t npad = (n_nodes + TILE - 1) / TILE * TILE;
+    const int64_t nslices = npad / SLICE;
+    std::vector<int32_t> rowlen(npad, 0);
+    int64_t nnz = 0, bw = 0;
+    for (int64_t r = 0; r < n_nodes; ++r) {
+        int32_t o = perm[r];
+        rowlen[r] = (int32_t)(gptr[o + 1] - gptr[o] + 1);
+        nnz += rowlen[r];
+    }
+    std::vector<int64_t> sptr(nslices + 1, 0);
+    for (int64_t s = 0; s < nslices; ++s) {
+        int w = 0;
+        for (int l = 0; l < SLICE; ++l) w = std::max(w, rowlen[s * SLICE + l]);
+        sptr[s + 1] = sptr[s] + (int64_t)w * SLICE;
+    }
+    std::vector<int32_t> colv(sptr[nslices]);
+    std::vector<int32_t> cols;
+    for (int64_t r = 0; r < npad; ++r) {
+        int64_t base = sptr[r / SLICE] + (r % SLICE);
+        int64_t w = (sptr[r / SLICE + 1] - sptr[r / SLICE]) / SLICE;
+        cols.clear();
+        if (r < n_nodes) {
+            int32_t o = perm[r];
+            cols.push_back((int32_t)r);
+            for (int64_t q = gptr[o]; q < gptr[o + 1]; ++q) cols.push_back(iperm[gadj[q]]);
+            std::sort(cols.begin(), cols.end());
+            for (int32_t c : cols) bw = std::max<int64_t>(bw, std::llabs((long long)c - r));
+        }
+        for (int64_t j = 0; j < w; ++j)
+            colv[base + j * SLICE] = j < (int64_t)cols.size() ? cols[j] : (int32_t)r;
+    }
+
+    ctx->n = n_nodes;
+    ctx->m = n_tets;
+    ctx->xyz.swap(X);
+    ctx->tets.assign(tets, tets + 4 * n_tets);
+    ctx->region.assign(n_tets, 0);
+    if (region) ctx->region.assign(region, region + n_tets);
+    ctx->fibre.clear();
+    if (fibre) ctx->fibre.assign(fibre, fibre + 3 * n_tets);
+    ctx->perm.swap(perm);
+    ctx->iperm.swap(iperm);
+    ctx->npad = npad;
+    ctx->nslices = nslices;
+    ctx->nslots = sptr[nslices];
+    ctx->nnz = nnz;
+    ctx->bandwidth = bw;
+    ctx->slice_ptr.swap(sptr);
+    ctx->col_sell.swap(colv);
+    ctx->rowlen.swap(rowlen);
+    ctx->stims.clear();
+    ctx->prepared = false;
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    return MDX_OK;
+    GUARD_END
+}
+
+mdx_status mdx_add_conductivity(mdx_ctx *ctx, int32_t n_ids, const int32_t *region_ids, double il,
+                                double it)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (n_ids <= 0 || !region_ids)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "no region ids given");
+    if (!(il >= 0.0) || !(it >= 0.0) || !std::isfinite(il) || !std::isfinite(it) || il + it <= 0.0)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "conductivities must be finite and >= 0 (not both 0)");
+    GUARD_BEGIN
+    for (int32_t i = 0; i < n_ids; ++i) ctx->cond[region_ids[i]] = {il, it};
+    ctx->prepared = false;
+    return MDX_OK;
+    GUARD_END
+}
+
+mdx_status mdx_set_tissue(mdx_ctx *ctx, double chi, double cm, double theta)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (!(chi > 0.0) || !(cm > 0.0) || !std::isfinite(chi) || !std::isfinite(cm))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "chi and Cm must be finite and > 0");
+    if (!(theta >= 0.0 && theta <= 1.0))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "theta must lie in [0, 1]");
+    ctx->chi = chi;
+    ctx->cm = cm;
+    ctx->theta = theta;
+    ctx->prepared = false;
+    return MDX_OK;
+}
+
+mdx_status mdx_set_ionic(mdx_ctx *ctx, int32_t kind, int32_t n_params, const double *params)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (kind < MDX_IONIC_NONE || kind > MDX_IONIC_TT)
+        return fail(ctx, MDX_ERR_UNSUPPORTED, "unknown ionic model %d", kind);
+    int np = ionic_nparams(kind);
+    if (params && n_params != np)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "model %d takes %d parameters, got %d", kind, np,
+                    n_params);
+    std::vector<double> p(np);
+    ionic_defaults(kind, p.data());
+    if (params)
+        for (int i = 0; i < np; ++i) {
+            if (!std::isfinite(params[i]))
+                return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite ionic parameter %d", i);
+            p[i] = params[i];
+        }
+    if (kind == MDX_IONIC_MS && (!(p[0] > 0) || !(p[1] > 0) || !(p[2] > 0) || !(p[3] > 0) ||
+                                 p[6] == 0.0))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "Mitchell-Schaeffer time constants must be > 0");
+    if (ctx->ionic_kind != kind) ctx->prepared = false;
+    ctx->ionic_kind = kind;
+    ctx->ionic_params = p;
+    return MDX_OK;
+}
+
+mdx_status mdx_add_stimulus(mdx_ctx *ctx, int64_t n_idx, const int32_t *node_idx, double start,
+                            double duration, double intensity)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (mdx_status s = require_mesh(ctx)) return s;
+    if (n_idx <= 0 || !node_idx) return fail(ctx, MDX_ERR_INVALID_ARG, "empty stimulus");
+    if (!std::isfinite(start) || !(duration >= 0.0) || !std::isfinite(duration) ||
+        !std::isfinite(intensity))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "stimulus start/duration/intensity invalid");
+    GUARD_BEGIN
+    Stim st;
+    st.nodes.assign(node_idx, node_idx + n_idx);
+    for (int32_t v : st.nodes)
+        if (v < 0 || v >= ctx->n)
+            return fail(ctx, MDX_ERR_INVALID_ARG, "stimulus node %d out of range", v);
+    std::sort(st.nodes.begin(), st.nodes.end());
+    st.nodes.erase(std::unique(st.nodes.begin(), st.nodes.end()), st.nodes.end());
+    st.start = start;
+    st.duration = duration;
+    st.amp = intensity;
+    ctx->stims.push_back(std::move(st));
+    ctx->prepared = false;
+    return MDX_OK;
+    GUARD_END
+}
+
+mdx_status mdx_set_solver(mdx_ctx *ctx, const mdx_solver_opts *o)
+{
+    if (!ctx || !o) return MDX_ERR_INVALID_ARG;
+    if (!(o->atol >= 0.0) || !(o->rtol >= 0.0) || o->max_iter < 1 || o->reserved != 0 ||
+        (o->rel_mode != MDX_REL_INITIAL && o->rel_mode != MDX_REL_RHS) ||
+        (o->warm_start != MDX_WS_PREV && o->warm_start != MDX_WS_EXTRAP))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "invalid solver options");
+    ctx->opts = *o;
+    if (ctx->prepared) {
+        Scalars *sc = ctx->dev<Scalars>(ctx->L.scalars);
+        HIPCHK(hipMemcpyAsync(&sc->atol, &o->atol, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(&sc->rtol, &o->rtol, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return MDX_OK;
+}
+
+mdx_status mdx_workspace_size(mdx_ctx *ctx, size_t *persistent_bytes, size_t *scratch_bytes)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (mdx_status s = require_mesh(ctx)) return s;
+    compute_layout(ctx);
+    if (persistent_bytes) *persistent_bytes = ctx->L.total;
+    if (scratch_bytes) *scratch_bytes = ctx->L.x_total;
+    return MDX_OK;
+}
+
+mdx_status mdx_bind_workspace(mdx_ctx *ctx, void *device_ptr, size_t bytes)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
+    if (mdx_status s = require_mesh(ctx)) return s;
+    compute_layout(ctx);
+    if (!device_ptr || ((uintptr_t)device_ptr % kAlign) != 0)
+        return fail(ctx, MDX_ERR_NO_WORKSPACE, "workspace must be non-null and 256-byte aligned");
+    if (bytes < ctx->L.total)
+        return fail(ctx, MDX_ERR_NO_WORKSPACE, "workspace of %zu bytes < required %zu", bytes,
+                    ctx->L.total);
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, device_ptr) != hipSuccess ||
+        attr.type != hipMemoryTypeDevice || attr.device != ctx->device)
+        return fail(ctx, MDX_ERR_NO_WORKSPACE, "workspace is not device memory of device %d",
+                    ctx->device);
+    ctx->ws = (char *)device_ptr;
+    ctx->ws_bytes = bytes;
+    ctx->prepared = false;
+    return MDX_OK;
+}
+
+mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_bytes)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
+    if (mdx_status s = require_mesh(ctx)) return s;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, MDX_ERR_INVALID_ARG, "dt must be > 0");
+    compute_layout(ctx);
+    if (!ctx->ws || ctx->ws_bytes < ctx->L.total)
+        return fail(ctx, MDX_ERR_NO_WORKSPACE, "no (large enough) workspace bound");
+    if (!scratch || ((uintptr_t)scratch % kAlign) != 0 || scratch_bytes < ctx->L.x_total)
+        return fail(ctx, MDX_ERR_NO_WORKSPACE, "setup scratch missing, unaligned or < %zu bytes",
+                    ctx->L.x_total);
+    GUARD_BEGIN
+    // per-element conductivities
+    std::vector<double> sig(2 * ctx->m);
+    for (int64_t e = 0; e < ctx->m; ++e) {
+        auto it = ctx->cond.find(ctx->region[e]);
+        if (it == ctx->cond.end())
+            return fail(ctx, MDX_ERR_STATE, "no conductivity for region %d", ctx->region[e]);
+        sig[2 * e] = it->second.first;
+        sig[2 * e + 1] = it->second.second;
+    }
+    // slot map: contributions (tet*16 + a*4 + b) per slot, ascending tet order
+    std::vector<int64_t> cptr(ctx->nslots + 1, 0);
+    std::vector<int64_t> slot_of(16 * ctx->m);
+    for (int64_t e = 0; e < ctx->m; ++e) {
+        const int32_t *t = &ctx->tets[4 * e];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                int64_t s = sell_slot(ctx, ctx->iperm[t[a]], ctx->iperm[t[b]]);
+                if (s < 0) return fail(ctx, MDX_ERR_BAD_MESH, "pattern lookup failed");
+                slot_of[16 * e + 4 * a + b] = s;
+                cptr[s + 1]++;
+            }
+    }
+    for (int64_t s = 0; s < ctx->nslots; ++s) cptr[s + 1] += cptr[s];
+    std::vector<int32_t> contrib(16 * ctx->m);
+    {
+        std::vector<int64_t> pos(cptr.begin(), cptr.end() - 1);
+        for (int64_t q = 0; q < 16 * ctx->m; ++q) contrib[pos[slot_of[q]]++] = (int32_t)q;
+    }
+    slot_of.clear();
+    slot_of.shrink_to_fit();
+
+    // host-side check of everything the kernels index with, before any launch
+    if (ctx->slice_ptr.size() != (size_t)ctx->nslices + 1 || ctx->slice_ptr[0] != 0 ||
+        ctx->slice_ptr[ctx->nslices] != ctx->nslots || (int64_t)ctx->col_sell.size() != ctx->nslots ||
+        cptr[ctx->nslots] != 16 * ctx->m || ctx->npad % TILE != 0 || ctx->npad < ctx->n)
+        return fail(ctx, MDX_ERR_BAD_MESH, "internal layout inconsistent");
+    for (int64_t sl = 0; sl < ctx->nslices; ++sl)
+        if (ctx->slice_ptr[sl + 1] < ctx->slice_ptr[sl] ||
+            (ctx->slice_ptr[sl + 1] - ctx->slice_ptr[sl]) % SLICE != 0)
+            return fail(ctx, MDX_ERR_BAD_MESH, "internal layout inconsistent (slice %lld)",
+                        (long long)sl);
+    for (int32_t c : ctx->col_sell)
+        if (c < 0 || c >= ctx->npad) return fail(ctx, MDX_ERR_BAD_MESH, "column out of range");
+    for (int32_t code : contrib)
+        if (code < 0 || code >= 16 * ctx->m)
+            return fail(ctx, MDX_ERR_BAD_MESH, "contribution out of range");
+
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!ctx->stage) HIPCHK(hipHostMalloc((void **)&ctx->stage, sizeof(double) * ctx->npad,
+                                          hipHostMallocDefault));
+    const Layout &L = ctx->L;
+    char *x = (char *)scratch;
+    hipStream_t st = ctx->stream;
+    HIPCHK(hipMemcpyAsync(x + L.x_xyz, ctx->xyz.data(), sizeof(double) * 3 * ctx->n,
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(x + L.x_tets, ctx->tets.data(), sizeof(int32_t) * 4 * ctx->m,
+                          hipMemcpyHostToDevice, st));
+    if (!ctx->fibre.empty())
+        HIPCHK(hipMemcpyAsync(x + L.x_fibre, ctx->fibre.data(), sizeof(double) * 3 * ctx->m,
+                              hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(x + L.x_sig, sig.data(), sizeof(double) * 2 * ctx->m,
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(x + L.x_cptr, cptr.data(), sizeof(int64_t) * (ctx->nslots + 1),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(x + L.x_contrib, contrib.data(), sizeof(int32_t) * 16 * ctx->m,
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->dev<int64_t>(L.slice_ptr), ctx->slice_ptr.data(),
+                          sizeof(int64_t) * (ctx->nslices + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->dev<int32_t>(L.col), ctx->col_sell.data(),
+                          sizeof(int32_t) * ctx->nslots, hipMemcpyHostToDevice, st));
+    // stimulus node lists in the new numbering
+    std::vector<int32_t> sidx;
+    ctx->stim_off.assign(1, 0);
+    for (auto &s : ctx->stims) {
+        for (int32_t v : s.nodes) sidx.push_back(ctx->iperm[v]);
+        ctx->stim_off.push_back((int64_t)sidx.size());
+    }
+    if (!sidx.empty())
+        HIPCHK(hipMemcpyAsync(ctx->dev<int32_t>(L.stim_idx), sidx.data(),
+                              sizeof(int32_t) * sidx.size(), hipMemcpyHostToDevice, st));
+
+    double *Mv = ctx->dev<double>(L.Mv), *Kv = ctx->dev<double>(L.Kv), *Av = ctx->dev<double>(L.Av);
+    launch_element(st, ctx->m, (double *)(x + L.x_xyz), (int32_t *)(x + L.x_tets),
+                   ctx->fibre.empty() ? nullptr : (double *)(x + L.x_fibre),
+                   (double *)(x + L.x_sig), (double *)(x + L.x_vol), (double *)(x + L.x_ek));
+    launch_gather(st, ctx->nslots, (int64_t *)(x + L.x_cptr), (int32_t *)(x + L.x_contrib),
+                  (double *)(x + L.x_vol), (double *)(x + L.x_ek), Mv, Kv);
+    launch_system(st, ctx->nslots, Mv, Kv, ctx->chi * ctx->cm, ctx->theta * dt, Av);
+    SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
+    launch_dinv(st, ctx->npad, ctx->n, P, Av, ctx->dev<double>(L.dinv));
+    HIPCHK(hipGetLastError());
+
+    // state: rest values, zeroed work vectors, LAT/LRT = +inf
+    ctx->vb[0] = 0;
+    ctx->vb[1] = 1;
+    ctx->vb[2] = 2;
+    launch_ionic_init(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad, ctx->vec(0),
+                      ctx->vec(1),
+                      ionic_nstates(ctx->ionic_kind) ? ctx->dev<double>(L.u) : nullptr);
+    for (size_t off : {L.vec[2], L.r, L.p, L.q, L.b, L.s, L.istim})
+        launch_fill(st, ctx->npad, 0.0, ctx->dev<double>(off));
+    const double inf = std::numeric_limits<double>::infinity();
+    launch_fill(st, ctx->npad, inf, ctx->dev<double>(L.lat));
+    launch_fill(st, ctx->npad, inf, ctx->dev<double>(L.lrt));
+    HIPCHK(hipGetLastError());
+    Scalars init{};
+    init.atol = ctx->opts.atol;
+    init.rtol = ctx->opts.rtol;
+    HIPCHK(hipMemcpyAsync(ctx->dev<Scalars>(L.scalars), &init, sizeof(Scalars),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+
+    ctx->tiling = make_tiling(ctx->npad, kMaxGroups);
+    ctx->dt = dt;
+    ctx->step = 0;
+    ctx->active.assign(ctx->stims.size(), 0);
+    ctx->last_iters = 0;
+    ctx->iters_hist.clear();
+    ctx->stats = mdx_stats{};
+    ctx->prepared = true;
+    return MDX_OK;
+    GUARD_END
+}
+
+mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_out)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "mdx_prepare has not been called");
+    if (n_steps < 0 || out_every < 0) return fail(ctx, MDX_ERR_INVALID_ARG, "negative count");
+    GUARD_BEGIN
+    HIPCHK(hipSetDevice(ctx->device));
+    const Layout &L = ctx->L;
+    hipStream_t st = ctx->stream;
+    const Tiling &T = ctx->tiling;
+    SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
+    double *Mv = ctx->dev<double>(L.Mv), *Kv = ctx->dev<double>(L.Kv), *Av = ctx->dev<double>(L.Av);
+    double *dinv = ctx->dev<double>(L.dinv);
+    double *r = ctx->dev<double>(L.r), *p = ctx->dev<double>(L.p), *q = ctx->dev<double>(L.q);
+    double *b = ctx->dev<double>(L.b), *s = ctx->dev<double>(L.s);
+    double *u = ionic_nstates(ctx->ionic_kind) ? ctx->dev<double>(L.u) : nullptr;
+    double *part0 = ctx->dev<double>(L.partial);
+    double *part_pq = part0 + 3 * kMaxGroups, *part_rz = part0 + 6 * kMaxGroups;
+    Scalars *sc = ctx->dev<Scalars>(L.scalars);
+    const StepParams sp = step_params(ctx);
+    const int max_iter = ctx->opts.max_iter;
+    mdx_status result = MDX_OK;
+    ctx->iters_hist.clear();
+    int64_t n_out = 0;
+    auto t_start = std::chrono::steady_clock::now();
+
+    for (int64_t j = 0; j < n_steps; ++j) {
+        const int64_t k = ctx->step;
+        bool any_stim = false;
+        if (mdx_status e = update_stimulus(ctx, k, any_stim)) return e;
+        double *V = ctx->vec(0), *Vprev = ctx->vec(1), *X = ctx->vec(2);
+        launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad, ctx->dt,
+                          ctx->cm, V, u, any_stim ? ctx->dev<double>(L.istim) : nullptr, s, 0);
+        launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, p, b, part0);
+        launch_init_finalize(st, T, part0, sp.rel_mode, sc);
+        int launched = 0;
+        bool done = false;
+        // first chunk: the previous step's count; then one at a time
+        int chunk = std::max(1, ctx->last_iters);
+        while (!done && launched < max_iter) {
+            int c = std::min(chunk, max_iter - launched);
+            for (int i = 0; i < c; ++i) {
+                const int it = launched + i;
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (ctx->profiling && 2 * it + 1 < (int)ctx->ev.size()) {
+                    e0 = ctx->ev[2 * it];
+                    e1 = ctx->ev[2 * it + 1];
+                }
+                launch_spmv_dot(st, T, P, Av, p, q, part_pq, &sc->done, e0, e1);
+                launch_cg_update(st, T, it, part_pq, dinv, p, q, X, r, part_rz, sc);
+                launch_cg_direction(st, T, it, part_rz, dinv, r, p, sc);
+            }
+            launched += c;
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            done = ctx->sc_host->done != 0;
+            chunk = 1;
+        }
+        if (ctx->sc_host->nonfinite)
+            return fail(ctx, MDX_ERR_NONFINITE, "non-finite value in the solve of step %lld",
+                        (long long)k);
+        const int iters = done ? ctx->sc_host->iters : -1;
+        ctx->last_iters = done ? iters : max_iter;
+        if (ctx->profiling) {
+            const int real = std::min(done ? iters : max_iter, (int)ctx->ev.size() / 2);
+            for (int it = 0; it < real; ++it) {
+                float ms = 0.0f;
+                HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2 * it], ctx->ev[2 * it + 1]));
+                ctx->stats.spmv_seconds += 1e-3 * ms;
+                ctx->stats.spmv_timed++;
+            }
+        }
+        launch_epilogue(st, ctx->n, (double)(k + 1) * ctx->dt, V, X, ctx->dev<double>(L.lat),
+                        ctx->dev<double>(L.lrt), sc);
+        // rotate: V^{k+1} <- x, V^k -> V^{k-1}
+        int old_prev = ctx->vb[1];
+        ctx->vb[1] = ctx->vb[0];
+        ctx->vb[0] = ctx->vb[2];
+        ctx->vb[2] = old_prev;
+        ctx->step++;
+        ctx->iters_hist.push_back(iters);
+        ctx->stats.steps++;
+        if (iters < 0) {
+            ctx->stats.not_converged++;
+            ctx->stats.cg_iters_total += max_iter;
+            result = MDX_WARN_NOT_CONVERGED;
+        } else {
+            ctx->stats.cg_iters_total += iters;
+            ctx->stats.cg_iters_max = std::max<int64_t>(ctx->stats.cg_iters_max, iters);
+        }
+        if (out_every > 0 && (j + 1) % out_every == 0 && v_out) {
+            if (mdx_status e = copy_vec_out(ctx, ctx->vec(0), v_out + n_out * ctx->n)) return e;
+            ++n_out;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->stats.step_loop_seconds +=
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (ctx->sc_host->nonfinite)
+        return fail(ctx, MDX_ERR_NONFINITE, "non-finite V after step %lld", (long long)ctx->step);
+    return result;
+    GUARD_END
+}
+
+mdx_status mdx_get_times(mdx_ctx *ctx, double *lat, double *lrt)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
+    if (lat)
+        if (mdx_status e = copy_vec_out(ctx, ctx->dev<double>(ctx->L.lat), lat)) return e;
+    if (lrt)
+        if (mdx_status e = copy_vec_out(ctx, ctx->dev<double>(ctx->L.lrt), lrt)) return e;
+    return MDX_OK;
+}
+
+mdx_status mdx_get_iterations(mdx_ctx *ctx, int64_t n, int32_t *iters)
+{
+    if (!ctx || (n > 0 && !iters)) return MDX_ERR_INVALID_ARG;
+    if (n < 0 || n > (int64_t)ctx->iters_hist.size())
+        return fail(ctx, MDX_ERR_INVALID_ARG, "only %zu step counts recorded",
+                    ctx->iters_hist.size());
+    std::copy(ctx->iters_hist.end() - n, ctx->iters_hist.end(), iters);
+    return MDX_OK;
+}
+
+mdx_status mdx_get_stats(mdx_ctx *ctx, mdx_stats *out)
+{
+    if (!ctx || !out) return MDX_ERR_INVALID_ARG;
+    *out = ctx->stats;
+    out->n_nodes = ctx->n;
+    out->nnz = ctx->nnz;
+    out->n_sell_slots = ctx->nslots;
+    out->bandwidth = ctx->bandwidth;
+    return MDX_OK;
+}
+
+mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (enable && ctx->ev.empty()) {
+        const int pairs = std::min(ctx->opts.max_iter, 4096);
+        for (int i = 0; i < 2 * pairs; ++i) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ctx->ev.push_back(e);
+        }
+    }
+    ctx->profiling = enable != 0;
+    return MDX_OK;
+}
+
+mdx_status mdx_get_state(mdx_ctx *ctx, double *V, double *Vprev, double *u, double *lat,
+                         double *lrt, int64_t *step)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
+    GUARD_BEGIN
+    if (V) if (mdx_status e = copy_vec_out(ctx, ctx->vec(0), V)) return e;
+    if (Vprev) if (mdx_status e = copy_vec_out(ctx, ctx->vec(1), Vprev)) return e;
+    int ns = ionic_nstates(ctx->ionic_kind);
+    if (u)
+        for (int s = 0; s < ns; ++s)
+            if (mdx_status e = copy_vec_out(ctx, ctx->dev<double>(ctx->L.u) + s * ctx->npad,
+                                            u + s * ctx->n))
+                return e;
+    if (lat) if (mdx_status e = copy_vec_out(ctx, ctx->dev<double>(ctx->L.lat), lat)) return e;
+    if (lrt) if (mdx_status e = copy_vec_out(ctx, ctx->dev<double>(ctx->L.lrt), lrt)) return e;
+    if (step) *step = ctx->step;
+    return MDX_OK;
+    GUARD_END
+}
+
+mdx_status mdx_set_state(mdx_ctx *ctx, const double *V, const double *Vprev, const double *u,
+                         const double *lat, const double *lrt, int64_t step)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
+    int ns = ionic_nstates(ctx->ionic_kind);
+    if (!V || !Vprev || (ns > 0 && !u) || step < 0)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "V, Vprev (and u) are required, step >= 0");
+    for (int64_t i = 0; i < ctx->n; ++i)
+        if (!std::isfinite(V[i]) || !std::isfinite(Vprev[i]))
+            return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite V at node %lld", (long long)i);
+    GUARD_BEGIN
+    if (mdx_status e = copy_vec_in(ctx, V, ctx->vec(0))) return e;
+    if (mdx_status e = copy_vec_in(ctx, Vprev, ctx->vec(1))) return e;
+    for (int s = 0; s < ns; ++s)
+        if (mdx_status e = copy_vec_in(ctx, u + s * ctx->n, ctx->dev<double>(ctx->L.u) + s * ctx->npad))
+            return e;
+    if (lat) {
+        if (mdx_status e = copy_vec_in(ctx, lat, ctx->dev<double>(ctx->L.lat))) return e;
+    }
+    if (lrt) {
+        if (mdx_status e = copy_vec_in(ctx, lrt, ctx->dev<double>(ctx->L.lrt))) return e;
+    }
+    // padding rows of lat/lrt were zeroed by copy_vec_in; they are never read
+    ctx->step = step;
+    return MDX_OK;
+    GUARD_END
+}
+
+mdx_status mdx_get_matrix(mdx_ctx *ctx, int32_t which, int64_t *nnz, int32_t *rows, int32_t *cols,
+                          double *vals)
+{
+    if (!ctx || !nnz) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
+    if (which < MDX_MAT_M || which > MDX_MAT_A) return fail(ctx, MDX_ERR_INVALID_ARG, "bad matrix");
+    if (!rows) {
+        *nnz = ctx->nnz;
+        return MDX_OK;
+    }
+    if (!cols || !vals || *nnz < ctx->nnz)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "arrays of %lld entries required", (long long)ctx->nnz);
+    GUARD_BEGIN
+    size_t off = which == MDX_MAT_M ? ctx->L.Mv : which == MDX_MAT_K ? ctx->L.Kv : ctx->L.Av;
+    std::vector<double> v(ctx->nslots);
+    HIPCHK(hipMemcpyAsync(v.data(), ctx->dev<double>(off), sizeof(double) * ctx->nslots,
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    int64_t o = 0;
+    for (int64_t r = 0; r < ctx->n; ++r) {
+        int64_t base = ctx->slice_ptr[r / SLICE] + (r % SLICE);
+        for (int j = 0; j < ctx->rowlen[r]; ++j) {
+            rows[o] = ctx->perm[r];
+            cols[o] = ctx->perm[ctx->col_sell[base + (int64_t)j * SLICE]];
+            vals[o] = v[base + (int64_t)j * SLICE];
+            ++o;
+        }
+    }
+    *nnz = o;
+    return MDX_OK;
+    GUARD_END
+}
+
+mdx_status mdx_spmv(mdx_ctx *ctx, int32_t which, const double *x, double *y)
+{
+    if (!ctx || !x || !y) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
+    if (which < MDX_MAT_M || which > MDX_MAT_A) return fail(ctx, MDX_ERR_INVALID_ARG, "bad matrix");
+    GUARD_BEGIN
+    const Layout &L = ctx->L;
+    size_t off = which == MDX_MAT_M ? L.Mv : which == MDX_MAT_K ? L.Kv : L.Av;
+    double *p = ctx->dev<double>(L.p), *q = ctx->dev<double>(L.q);
+    if (mdx_status e = copy_vec_in(ctx, x, p)) return e;
+    SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
+    Scalars *sc = ctx->dev<Scalars>(L.scalars);
+    launch_spmv_dot(ctx->stream, ctx->tiling, P, ctx->dev<double>(off), p, q,
+                    ctx->dev<double>(L.partial) + 3 * kMaxGroups, &sc->zero);
+    HIPCHK(hipGetLastError());
+    return copy_vec_out(ctx, q, y);
+    GUARD_END
+}
+
+mdx_status mdx_ionic_step(mdx_ctx *ctx, double dt, int64_t n, const double *V, double *u,
+                          double *iion)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
+    if (n < 0 || (n > 0 && (!V || !iion || (ionic_nstates(ctx->ionic_kind) > 0 && !u))))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "null device array");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(ctx, MDX_ERR_INVALID_ARG, "dt must be >= 0");
+    if (ctx->ionic_params.empty() && ctx->ionic_kind != 0)
+        return fail(ctx, MDX_ERR_STATE, "ionic model not set");
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_ionic_step(ctx->stream, ctx->ionic_kind, ctx->ionic_params.data(), n, n, dt, 1.0, V, u,
+                      nullptr, iion, 1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MDX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,369 @@
+// Per-step solver kernels of the plain FP64 path.
+//
+// One time step (the paper's Eq. 2 and the definitions of A and b after
+// Eq. 3, Jacobi-PCG of Algorithm 1):
+//   rhs_init      b = chi M (Cm V^k + dt s) - (1-theta) dt K V^k,  s = I_stim - I_ion,
+//                 x0 = 2V^k - V^{k-1} (or V^k), r0 = b - A x0 with
+//                 A x0 = chi Cm (M x0) + theta dt (K x0), p0 = z0 = D^-1 r0,
+//                 per-workgroup partials of r.z, z.z, |D^-1 b|^2
+//   init_finalize rho_0, ||z_0||, the stopping reference, done if z_0 is at the
+//                 rounding floor
+//   per iteration k:
+//   spmv_dot      q = A p, partial p.q
+//   cg_update     alpha = rho_k / p.q; x += alpha p; r -= alpha q; z = D^-1 r;
+//                 partials r.z, z.z
+//   cg_direction  ||z||; stop if ||z|| < atol, ||z|| < rtol * ref or at the
+//                 floor; else beta = r.z / rho_k, p = z + beta p
+//   epilogue      activation / repolarisation times, non-finite check
+//
+// Matrix traversal: sliced ELL (see mdx_internal.h); one lane per row, so the
+// j-th column/value loads of a wavefront are contiguous.  Each workgroup owns
+// a contiguous run of 256-row tiles, and workgroups are remapped so that each
+// of the 8 XCDs owns a contiguous eighth of the rows: the x-gathers of
+// neighbouring rows (RCM keeps them within the bandwidth) then hit that XCD's
+// own L2.
+//
+// Reductions: wavefront butterfly (shfl_xor) -> LDS across the 4 wavefronts
+// -> one partial per workgroup.  Consumers re-reduce all partials in a fixed
+// order in every workgroup, so scalars are bitwise identical everywhere and
+// runs are deterministic; no atomics, no grid-wide synchronisation.
+#include "mdx_internal.h"
+
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+
+namespace mdx {
+
+Tiling make_tiling(int64_t n_rows_padded, int max_groups)
+{
+    Tiling t;
+    t.n_rows = n_rows_padded;
+    t.n_tiles = (int)(n_rows_padded / TILE);
+    int g = std::max(1, std::min(t.n_tiles, max_groups));
+    t.tpb = (t.n_tiles + g - 1) / g;
+    t.groups = (t.n_tiles + t.tpb - 1) / t.tpb;
+    return t;
+}
+
+namespace {
+
+// Hardware dispatches workgroup i to XCD i % 8; return the logical workgroup
+// so that XCD x owns the contiguous logical range of its share.
+__device__ __forceinline__ int logical_group(int nb)
+{
+    int i = blockIdx.x;
+    int x = i % NXCD, j = i / NXCD;
+    int q = nb / NXCD, rem = nb % NXCD;
+    return x * q + min(x, rem) + j;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the 256 threads of the workgroup; the totals are
+// returned to every thread.
+template <int NV>
+__device__ __forceinline__ void group_sum(double (&v)[NV])
+{
+    __shared__ double lds[4][NV];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) lds[w][k] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
+    __syncthreads();
+}
+
+// Every workgroup reduces the `groups` partials of a producer kernel, laid
+// out partial[k * groups + g], in the same order.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ partial, int groups,
+                                                double (&v)[NV])
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int g = threadIdx.x; g < groups; g += TILE)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += partial[k * groups + g];
+    group_sum<NV>(v);
+}
+
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *__restrict__ partial,
+                                               int groups, int g)
+{
+    group_sum<NV>(v);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) partial[k * groups + g] = v[k];
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill(int64_t n, double v, double *__restrict__ x)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_stim_add(int64_t n_idx, const int32_t *__restrict__ idx,
+                                                  double amp, double *__restrict__ istim)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n_idx) istim[idx[j]] += amp;   // node lists are duplicate-free
+}
+
+__global__ __launch_bounds__(256) void k_rhs_init(
+    Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
+    StepParams sp, const double *__restrict__ V, const double *__restrict__ Vprev,
+    const double *__restrict__ src, double *__restrict__ x, double *__restrict__ r,
+    double *__restrict__ p, double *__restrict__ b, double *__restrict__ partial)
+{
+    const int g = logical_group(t.groups);
+    const int lane = threadIdx.x & (SLICE - 1);
+    const double cK_old = (1.0 - sp.theta) * sp.dt;   // weight of K V^k in b
+    const double cM_new = sp.chi * sp.cm;             // A = cM_new M + cK_new K
+    const double cK_new = sp.theta * sp.dt;
+    const bool extrap = sp.warm_start == 1;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
+    for (int tile = g * t.tpb; tile < t_end; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        double mv = 0.0, kv = 0.0, mx = 0.0, kx = 0.0;
+        for (int64_t e = beg; e < end; e += SLICE) {
+            const int32_t c = col[e];
+            const double m = Mv[e], kk = Kv[e];
+            const double vj = V[c];
+            const double x0j = extrap ? 2.0 * vj - Vprev[c] : vj;
+            mv += m * (sp.cm * vj + sp.dt * src[c]);
+            kv += kk * vj;
+            mx += m * x0j;
+            kx += kk * x0j;
+        }
+        const double bi = sp.chi * mv - cK_old * kv;
+        const double ax = cM_new * mx + cK_new * kx;
+        const double vi = V[row];
+        const double x0i = extrap ? 2.0 * vi - Vprev[row] : vi;
+        const double di = dinv[row];
+        const double ri = bi - ax;
+        const double zi = di * ri;
+        x[row] = x0i;
+        r[row] = ri;
+        p[row] = zi;
+        b[row] = bi;
+        acc[0] += ri * zi;
+        acc[1] += zi * zi;
+        acc[2] += (di * bi) * (di * bi);
+    }
+    write_partials<3>(acc, partial, t.groups, g);
+}
+
+__global__ __launch_bounds__(256) void k_init_finalize(int groups, const double *__restrict__ partial,
+                                                       int rel_mode, Scalars *__restrict__ sc)
+{
+    double v[3];
+    reduce_partials<3>(partial, groups, v);
+    if (threadIdx.x == 0) {
+        const double z0 = sqrt(v[1]);
+        const double db = sqrt(v[2]);
+        sc->rho[0] = v[0];
+        sc->z0 = z0;
+        sc->znorm = z0;
+        sc->ref = rel_mode == 1 ? db : z0;
+        sc->floor_ = 1e-15 * db;
+        sc->done = (z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
+        sc->iters = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__restrict__ slice_ptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const double *__restrict__ Av,
+                                                  const double *__restrict__ p,
+                                                  double *__restrict__ q,
+                                                  double *__restrict__ partial,
+                                                  const int32_t *__restrict__ done)
+{
+    if (*done) return;
+    const int g = logical_group(t.groups);
+    const int lane = threadIdx.x & (SLICE - 1);
+    double acc[1] = {0.0};
+    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
+    for (int tile = g * t.tpb; tile < t_end; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        double sum = 0.0;
+#pragma unroll 4
+        for (int64_t e = beg; e < end; e += SLICE) sum += Av[e] * p[col[e]];
+        q[row] = sum;
+        acc[0] += p[row] * sum;
+    }
+    write_partials<1>(acc, partial, t.groups, g);
+}
+
+__global__ __launch_bounds__(256) void k_cg_update(Tiling t, int k,
+                                                   const double *__restrict__ partial_pq,
+                                                   const double *__restrict__ dinv,
+                                                   const double *__restrict__ p,
+                                                   const double *__restrict__ q,
+                                                   double *__restrict__ x, double *__restrict__ r,
+                                                   double *__restrict__ partial_rz,
+                                                   Scalars *__restrict__ sc)
+{
+    if (sc->done) return;
+    double pq[1];
+    reduce_partials<1>(partial_pq, t.groups, pq);
+    const double alpha = sc->rho[k & 1] / pq[0];
+    const int g = logical_group(t.groups);
+    double acc[2] = {0.0, 0.0};
+    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
+    for (int tile = g * t.tpb; tile < t_end; ++tile) {
+        const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        const double zi = dinv[i] * ri;
+        acc[0] += ri * zi;
+        acc[1] += zi * zi;
+    }
+    write_partials<2>(acc, partial_rz, t.groups, g);
+}
+
+__global__ __launch_bounds__(256) void k_cg_direction(Tiling t, int k,
+                                                      const double *__restrict__ partial_rz,
+                                                      const double *__restrict__ dinv,
+                                                      const double *__restrict__ r,
+                                                      double *__restrict__ p,
+                                                      Scalars *__restrict__ sc)
+{
+    if (sc->done) return;
+    double v[2];
+    reduce_partials<2>(partial_rz, t.groups, v);
+    const double zn = sqrt(v[1]);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!(zn == zn)) {   // NaN: stop the solve, flag it
+        if (lead) {
+            sc->nonfinite = 2;
+            sc->done = 1;
+            sc->iters = k + 1;
+            sc->znorm = zn;
+        }
+        return;
+    }
+    if (zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_) {
+        if (lead) {
+            sc->done = 1;
+            sc->iters = k + 1;
+            sc->znorm = zn;
+        }
+        return;
+    }
+    const double beta = v[0] / sc->rho[k & 1];
+    if (lead) {
+        sc->rho[(k + 1) & 1] = v[0];
+        sc->znorm = zn;
+    }
+    const int g = logical_group(t.groups);
+    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
+    for (int tile = g * t.tpb; tile < t_end; ++tile) {
+        const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+        p[i] = dinv[i] * r[i] + beta * p[i];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_epilogue(int64_t n, double t1, const double *__restrict__ Vold,
+                                                  const double *__restrict__ Vnew,
+                                                  double *__restrict__ lat, double *__restrict__ lrt,
+                                                  Scalars *__restrict__ sc)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double vn = Vnew[i];
+    if (!isfinite(vn)) sc->nonfinite = 1;
+    double l = lat[i];
+    if (isinf(l) && vn > 0.0) {
+        l = t1;
+        lat[i] = t1;
+    }
+    if (!isinf(l) && l < t1 && isinf(lrt[i]) && vn < -70.0 && vn < Vold[i]) lrt[i] = t1;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+void launch_fill(hipStream_t s, int64_t n, double v, double *x)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, s, n, v, x);
+}
+
+void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double amp, double *istim)
+{
+    if (n_idx > 0)
+        hipLaunchKernelGGL(k_stim_add, dim3(blocks_for(n_idx)), dim3(256), 0, s, n_idx, idx, amp,
+                           istim);
+}
+
+void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
+                     const double *Kv, const double *dinv, const StepParams &sp, const double *V,
+                     const double *Vprev, const double *src, double *x, double *r, double *p,
+                     double *b, double *partial)
+{
+    hipLaunchKernelGGL(k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
+                       dinv, sp, V, Vprev, src, x, r, p, b, partial);
+}
+
+void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
+                          Scalars *sc)
+{
+    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(TILE), 0, s, t.groups, partial, rel_mode, sc);
+}
+
+void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *Av, const double *p,
+                     double *q, double *partial, const int32_t *done, hipEvent_t ev_start,
+                     hipEvent_t ev_stop)
+{
+    if (ev_start)
+        hipExtLaunchKernelGGL(k_spmv_dot, dim3(t.groups), dim3(TILE), 0, s, ev_start, ev_stop, 0, t,
+                              P.slice_ptr, P.col, Av, p, q, partial, done);
+    else
+        hipLaunchKernelGGL(k_spmv_dot, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av,
+                           p, q, partial, done);
+}
+
+void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
+                      const double *dinv, const double *p, const double *q, double *x, double *r,
+                      double *partial_rz, Scalars *sc)
+{
+    hipLaunchKernelGGL(k_cg_update, dim3(t.groups), dim3(TILE), 0, s, t, k, partial_pq, dinv, p, q,
+                       x, r, partial_rz, sc);
+}
+
+void launch_cg_direction(hipStream_t s, const Tiling &t, int k, const double *partial_rz,
+                         const double *dinv, const double *r, double *p, Scalars *sc)
+{
+    hipLaunchKernelGGL(k_cg_direction, dim3(t.groups), dim3(TILE), 0, s, t, k, partial_rz, dinv, r,
+                       p, sc);
+}
+
+void launch_epilogue(hipStream_t s, int64_t n, double t1, const double *Vold, const double *Vnew,
+                     double *lat, double *lrt, Scalars *sc)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_epilogue, dim3(blocks_for(n)), dim3(256), 0, s, n, t1, Vold, Vnew, lat,
+                           lrt, sc);
+}
+
+}  // namespace mdx

@@ -1,0 +1,210 @@
+"""Python front end of the monodomain library (thin: marshalling only).
+
+PyTorch provides the device memory (the persistent workspace and the setup
+scratch are ``torch.uint8`` tensors on the device) and the HIP stream (the
+current torch stream of that device).  Every step of the method runs in the
+HIP kernels of ``libmonox.so``.
+
+The call sequence mirrors the paper's API ("Best Practices" section):
+device, ionic model with editable parameters, mesh with unit conversion,
+per-region conductivities, stimuli, then solve with tolerances and a save
+interval.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+IONIC = {"none": L.MDX_IONIC_NONE, "ms": L.MDX_IONIC_MS, "tt": L.MDX_IONIC_TT}
+
+
+class Simulation:
+    """One monodomain simulation on one GPU (one mdx_ctx)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.device = device
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        self._check(L.lib().mdx_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream)),
+                    ctx=None)
+        self._h = h
+        self._ws = None
+        self.n = 0
+        self.nstates = 0
+        self.kind = "none"
+
+    # -- plumbing -------------------------------------------------------
+    def _check(self, status, ctx="self"):
+        if status < 0:
+            msg = (L.lib().mdx_last_error(self._h).decode() if ctx is not None else
+                   "context creation failed")
+            raise L.MdxError(status, msg)
+        return status
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().mdx_destroy(self._h)
+            self._h = C.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- problem statement ----------------------------------------------
+    def set_mesh(self, xyz, tets, region=None, fibre=None, unit_conversion=1.0):
+        xyz = np.ascontiguousarray(xyz, np.float64)
+        tets = np.ascontiguousarray(tets, np.int32)
+        region = None if region is None else np.ascontiguousarray(region, np.int32)
+        fibre = None if fibre is None else np.ascontiguousarray(fibre, np.float64)
+        self._check(L.lib().mdx_set_mesh(self._h, xyz.shape[0], _ptr(xyz), unit_conversion,
+                                         tets.shape[0], _ptr(tets), _ptr(region), _ptr(fibre)))
+        self.n = xyz.shape[0]
+
+    def add_conductivity(self, region_ids, il, it):
+        ids = np.ascontiguousarray(np.atleast_1d(region_ids), np.int32)
+        self._check(L.lib().mdx_add_conductivity(self._h, ids.shape[0], _ptr(ids), il, it))
+
+    def set_tissue(self, chi, cm, theta=0.5):
+        self._check(L.lib().mdx_set_tissue(self._h, chi, cm, theta))
+
+    def set_ionic(self, kind: str, params=None):
+        k = IONIC[kind]
+        p = None if params is None else np.ascontiguousarray(params, np.float64)
+        self._check(L.lib().mdx_set_ionic(self._h, k, 0 if p is None else p.shape[0], _ptr(p)))
+        self.kind = kind
+        self.nstates = L.lib().mdx_ionic_nstates(k)
+
+    def add_stimulus(self, nodes, start, duration, intensity):
+        idx = np.ascontiguousarray(nodes, np.int32)
+        self._check(L.lib().mdx_add_stimulus(self._h, idx.shape[0], _ptr(idx), start, duration,
+                                             intensity))
+
+    def set_solver(self, atol=0.0, rtol=1e-10, rel_mode=0, max_iter=1000, warm_start=1):
+        o = L.SolverOpts(atol, rtol, rel_mode, max_iter, warm_start, 0)
+        self._check(L.lib().mdx_set_solver(self._h, C.byref(o)))
+
+    # -- device memory and setup ----------------------------------------
+    def workspace_size(self):
+        a, b = C.c_size_t(), C.c_size_t()
+        self._check(L.lib().mdx_workspace_size(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def _alloc(self, nbytes):
+        t = self._torch.empty(nbytes + 256, dtype=self._torch.uint8, device=f"cuda:{self.device}")
+        off = (-t.data_ptr()) % 256
+        return t, off
+
+    def prepare(self, dt):
+        pb, sb = self.workspace_size()
+        ws, off = self._alloc(pb)
+        self._check(L.lib().mdx_bind_workspace(self._h, C.c_void_p(ws.data_ptr() + off), pb))
+        self._ws = ws
+        scratch, soff = self._alloc(sb)
+        self._check(L.lib().mdx_prepare(self._h, dt, C.c_void_p(scratch.data_ptr() + soff), sb))
+        del scratch
+        self.dt = dt
+
+    # -- stepping and results --------------------------------------------
+    def run(self, n_steps, out_every=0):
+        """Advance n_steps; returns snapshots [n_steps // out_every, n] and the status."""
+        n_out = n_steps // out_every if out_every > 0 else 0
+        v_out = np.zeros((max(n_out, 1), self.n)) if n_out else None
+        st = self._check(L.lib().mdx_run(self._h, n_steps, out_every, _ptr(v_out)))
+        return (v_out[:n_out] if n_out else np.zeros((0, self.n))), st
+
+    def times(self):
+        lat, lrt = np.zeros(self.n), np.zeros(self.n)
+        self._check(L.lib().mdx_get_times(self._h, _ptr(lat), _ptr(lrt)))
+        return lat, lrt
+
+    def iterations(self, n):
+        it = np.zeros(n, np.int32)
+        self._check(L.lib().mdx_get_iterations(self._h, n, _ptr(it)))
+        return it
+
+    def stats(self):
+        s = L.Stats()
+        self._check(L.lib().mdx_get_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in L.Stats._fields_}
+
+    def set_profiling(self, enable=True):
+        self._check(L.lib().mdx_set_profiling(self._h, 1 if enable else 0))
+
+    def get_state(self):
+        V, Vp = np.zeros(self.n), np.zeros(self.n)
+        u = np.zeros((self.nstates, self.n))
+        lat, lrt = np.zeros(self.n), np.zeros(self.n)
+        k = C.c_int64()
+        self._check(L.lib().mdx_get_state(self._h, _ptr(V), _ptr(Vp),
+                                          _ptr(u) if self.nstates else None, _ptr(lat),
+                                          _ptr(lrt), C.byref(k)))
+        return dict(V=V, Vprev=Vp, u=u, lat=lat, lrt=lrt, step=k.value)
+
+    def set_state(self, V, Vprev, u=None, lat=None, lrt=None, step=0):
+        f = lambda a: None if a is None else np.ascontiguousarray(a, np.float64)
+        V, Vprev, u, lat, lrt = f(V), f(Vprev), f(u), f(lat), f(lrt)
+        self._check(L.lib().mdx_set_state(self._h, _ptr(V), _ptr(Vprev), _ptr(u), _ptr(lat),
+                                          _ptr(lrt), step))
+
+    def matrix(self, which):
+        """(rows, cols, vals) in original numbering; which in 'M', 'K', 'A'."""
+        w = {"M": L.MDX_MAT_M, "K": L.MDX_MAT_K, "A": L.MDX_MAT_A}[which]
+        nnz = C.c_int64()
+        self._check(L.lib().mdx_get_matrix(self._h, w, C.byref(nnz), None, None, None))
+        rows = np.zeros(nnz.value, np.int32)
+        cols = np.zeros(nnz.value, np.int32)
+        vals = np.zeros(nnz.value)
+        self._check(L.lib().mdx_get_matrix(self._h, w, C.byref(nnz), _ptr(rows), _ptr(cols),
+                                           _ptr(vals)))
+        return rows, cols, vals
+
+    def spmv(self, which, x):
+        w = {"M": L.MDX_MAT_M, "K": L.MDX_MAT_K, "A": L.MDX_MAT_A}[which]
+        x = np.ascontiguousarray(x, np.float64)
+        y = np.zeros(self.n)
+        self._check(L.lib().mdx_spmv(self._h, w, _ptr(x), _ptr(y)))
+        return y
+
+    def ionic_step(self, dt, V, u):
+        """One ionic update of independent cells on device tensors (float64):
+        V [n], u [nstates, n] updated in place; returns I_ion/Cm [n]."""
+        torch = self._torch
+        n = V.shape[0]
+        iion = torch.empty(n, dtype=torch.float64, device=V.device)
+        self._check(L.lib().mdx_ionic_step(self._h, dt, n, _dptr(V),
+                                           _dptr(u) if self.nstates else None, _dptr(iion)))
+        return iion
+
+
+def from_spec(spec, device: int = 0, ionic_params=None, prepare=True) -> Simulation:
+    """Build a Simulation from an inputs.RunSpec."""
+    sim = Simulation(device)
+    m = spec.mesh
+    sim.set_mesh(m.xyz, m.tets, m.region, m.fibre)
+    sim.add_conductivity(np.unique(m.region), spec.sigma_l, spec.sigma_t)
+    sim.set_tissue(spec.chi, spec.cm, spec.theta)
+    sim.set_ionic(spec.ionic, ionic_params)
+    for s in spec.stimuli:
+        sim.add_stimulus(s.nodes, s.start, s.duration, s.intensity)
+    sim.set_solver(spec.atol, spec.rtol, spec.rel_mode, spec.max_iter, spec.warm_start)
+    if prepare:
+        sim.prepare(spec.dt)
+    return sim

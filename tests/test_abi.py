@@ -1,0 +1,138 @@
+"""The C-ABI library loads, exports every declared symbol, and validates its
+inputs on the host (host-only context, no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2510_12011_amd import _lib as L
+from paper_2510_12011_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "monox.h")).read()
+    return sorted(set(re.findall(r"MDX_API\s+[\w\s\*]+?\b(mdx_\w+)\s*\(", src)))
+
+
+def test_header_matches_binding():
+    assert _declared() == L.exported_symbols()
+
+
+def test_library_exports_every_symbol():
+    lib = L.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.mdx_version() == 1
+
+
+def test_only_the_abi_is_exported():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    funcs = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert funcs == set(_declared())
+
+
+def test_ionic_model_sizes():
+    lib = L.lib()
+    assert lib.mdx_ionic_nstates(L.MDX_IONIC_NONE) == 0
+    assert lib.mdx_ionic_nstates(L.MDX_IONIC_MS) == 1
+    assert lib.mdx_ionic_nstates(L.MDX_IONIC_TT) == 18
+    assert lib.mdx_ionic_nparams(L.MDX_IONIC_MS) == 7
+    assert lib.mdx_ionic_nparams(L.MDX_IONIC_TT) == 12
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+@pytest.fixture
+def host_ctx():
+    h = C.c_void_p()
+    assert L.lib().mdx_create(C.byref(h), -1, None) == L.MDX_OK
+    yield h
+    L.lib().mdx_destroy(h)
+
+
+def _err(h):
+    return L.lib().mdx_last_error(h).decode()
+
+
+def test_validation_rejects_bad_meshes(host_ctx):
+    lib = L.lib()
+    m = inputs.kuhn_box(2, 2, 2, 1.0, 1.0, 1.0)
+    xyz, tets = np.ascontiguousarray(m.xyz), np.ascontiguousarray(m.tets)
+    n, ne = xyz.shape[0], tets.shape[0]
+    assert lib.mdx_set_mesh(host_ctx, n, _p(xyz), 1.0, ne, _p(tets), None, None) == L.MDX_OK
+    bad = tets.copy()
+    bad[3, 2] = n
+    assert lib.mdx_set_mesh(host_ctx, n, _p(xyz), 1.0, ne, _p(bad), None, None) == L.MDX_ERR_BAD_MESH
+    assert "out of range" in _err(host_ctx)
+    deg = tets.copy()
+    deg[5, 3] = deg[5, 2]                       # two equal vertices: zero volume
+    assert lib.mdx_set_mesh(host_ctx, n, _p(xyz), 1.0, ne, _p(deg), None, None) == L.MDX_ERR_BAD_MESH
+    assert "degenerate" in _err(host_ctx)
+    nanx = xyz.copy()
+    nanx[4, 1] = np.nan
+    assert lib.mdx_set_mesh(host_ctx, n, _p(nanx), 1.0, ne, _p(tets), None, None) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_set_mesh(host_ctx, n, _p(xyz), 0.0, ne, _p(tets), None, None) == L.MDX_ERR_INVALID_ARG
+
+
+def test_validation_rejects_bad_parameters(host_ctx):
+    lib = L.lib()
+    m = inputs.kuhn_box(2, 2, 2, 1.0, 1.0, 1.0)
+    xyz, tets = np.ascontiguousarray(m.xyz), np.ascontiguousarray(m.tets)
+    assert lib.mdx_set_mesh(host_ctx, xyz.shape[0], _p(xyz), 1.0, tets.shape[0], _p(tets),
+                            None, None) == L.MDX_OK
+    assert lib.mdx_set_tissue(host_ctx, 140.0, 0.01, 1.5) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_set_tissue(host_ctx, -1.0, 0.01, 0.5) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_set_tissue(host_ctx, 140.0, 0.0, 0.5) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_set_tissue(host_ctx, 140.0, 0.01, 0.5) == L.MDX_OK
+    ids = np.array([0], np.int32)
+    assert lib.mdx_add_conductivity(host_ctx, 1, _p(ids), -0.1, 0.1) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_set_ionic(host_ctx, 7, 0, None) == L.MDX_ERR_UNSUPPORTED
+    p3 = np.ones(3)
+    assert lib.mdx_set_ionic(host_ctx, L.MDX_IONIC_MS, 3, _p(p3)) == L.MDX_ERR_INVALID_ARG
+    idx = np.array([0, 999], np.int32)
+    assert lib.mdx_add_stimulus(host_ctx, 2, _p(idx), 0.0, 1.0, 0.5) == L.MDX_ERR_INVALID_ARG
+    o = L.SolverOpts(0.0, 1e-8, 0, 0, 1, 0)
+    assert lib.mdx_set_solver(host_ctx, C.byref(o)) == L.MDX_ERR_INVALID_ARG
+    o = L.SolverOpts(0.0, 1e-8, 3, 10, 1, 0)
+    assert lib.mdx_set_solver(host_ctx, C.byref(o)) == L.MDX_ERR_INVALID_ARG
+    # a host-only context cannot bind device memory or prepare
+    assert lib.mdx_prepare(host_ctx, 0.01, None, 0) == L.MDX_ERR_DEVICE
+    assert lib.mdx_run(host_ctx, 1, 0, None) == L.MDX_ERR_STATE
+
+
+def test_workspace_sizing_and_pattern_stats(host_ctx):
+    """nnz of the Kuhn pattern = N + 2 #edges; the sliced layout pads each
+    64-row slice to its longest row; workspace grows with the ionic state."""
+    lib = L.lib()
+    sp = inputs.slab(h=0.5)
+    m = sp.mesh
+    xyz, tets = np.ascontiguousarray(m.xyz), np.ascontiguousarray(m.tets)
+    fib = np.ascontiguousarray(m.fibre)
+    assert lib.mdx_set_mesh(host_ctx, xyz.shape[0], _p(xyz), 1.0, tets.shape[0], _p(tets),
+                            None, _p(fib)) == L.MDX_OK
+    st = L.Stats()
+    assert lib.mdx_get_stats(host_ctx, C.byref(st)) == L.MDX_OK
+    nx, ny, nz = 40, 14, 6
+    edges = (nx * (ny + 1) * (nz + 1) + (nx + 1) * ny * (nz + 1) + (nx + 1) * (ny + 1) * nz
+             + nx * ny * (nz + 1) + nx * (ny + 1) * nz + (nx + 1) * ny * nz + nx * ny * nz)
+    assert st.nnz == m.n_nodes + 2 * edges
+    assert st.n_sell_slots >= st.nnz
+    assert st.n_sell_slots <= 1.25 * st.nnz
+    # RCM keeps the band narrow: within a few grid planes (7 x 15 nodes)
+    assert st.bandwidth <= 4 * 7 * 15
+    a, b = C.c_size_t(), C.c_size_t()
+    assert lib.mdx_set_ionic(host_ctx, L.MDX_IONIC_MS, 0, None) == L.MDX_OK
+    assert lib.mdx_workspace_size(host_ctx, C.byref(a), C.byref(b)) == L.MDX_OK
+    ms_bytes = a.value
+    assert lib.mdx_set_ionic(host_ctx, L.MDX_IONIC_TT, 0, None) == L.MDX_OK
+    assert lib.mdx_workspace_size(host_ctx, C.byref(a), C.byref(b)) == L.MDX_OK
+    assert a.value - ms_bytes >= 17 * 8 * m.n_nodes
+    assert a.value % 256 == 0 and b.value % 256 == 0

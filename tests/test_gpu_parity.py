@@ -1,0 +1,199 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars (plain FP64 path): assembled matrices and SpMV to rounding (1e-13
+relative to the largest entry); one ionic step to 1e-11 relative; whole
+trajectories to relative L2 <= 1e-9 on V at every snapshot, with activation
+times equal to within one time step and the same nodes activated.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_2510_12011_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+V_REL_L2 = 1e-9
+
+
+def _sim(spec, **kw):
+    from paper_2510_12011_amd import sim
+    print(f"[case] {spec.name} n={spec.mesh.n_nodes} ionic={spec.ionic}", flush=True)
+    return sim.from_spec(spec, **kw)
+
+
+def _coo_to_dense_map(rows, cols, vals):
+    return {(int(r), int(c)): v for r, c, v in zip(rows, cols, vals)}
+
+
+def _rel_l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("spec_fn", [
+    lambda: inputs.small_box(nx=6, ny=5, nz=4, jitter=0.2),
+    lambda: inputs.tiny_cube(n=8),
+])
+def test_assembly_parity(spec_fn):
+    spec = spec_fn()
+    s = _sim(spec)
+    m = orc.assemble_spec(spec)
+    A_or = spec.chi * spec.cm * m.M + spec.theta * spec.dt * m.K
+    orows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+    for which, ref in (("M", m.M), ("K", m.K), ("A", A_or)):
+        rows, cols, vals = s.matrix(which)
+        assert rows.shape[0] == ref.shape[0]
+        order = np.lexsort((cols, rows))
+        rows, cols, vals = rows[order], cols[order], vals[order]
+        np.testing.assert_array_equal(rows, orows)
+        np.testing.assert_array_equal(cols, m.col)
+        scale = abs(ref).max()
+        np.testing.assert_allclose(vals, ref, rtol=0, atol=1e-13 * scale)
+
+
+def test_spmv_parity():
+    spec = inputs.tiny_cube(n=10)
+    s = _sim(spec)
+    m = orc.assemble_spec(spec)
+    x = np.random.default_rng(4).normal(size=m.n)
+    for which, val in (("M", m.M), ("K", m.K)):
+        y = s.spmv(which, x)
+        y_ref = orc.spmv(m, val, x)
+        np.testing.assert_allclose(y, y_ref, rtol=0, atol=1e-13 * abs(y_ref).max())
+
+
+def _tt_states(n_samples=256):
+    """Physiological TT states along a single-cell action potential (oracle)."""
+    V, u = orc.ionic_init("tt", 1)
+    Vs, us = [], []
+    dt = 0.01
+    for k in range(40000):
+        iion = orc.ionic_step("tt", V, u, dt)
+        V = V + dt * ((50.0 if k < 100 else 0.0) - iion)
+        if k % (40000 // n_samples) == 0:
+            Vs.append(V[0])
+            us.append(u[:, 0].copy())
+    return np.array(Vs), np.stack(us, axis=1)
+
+
+@pytest.mark.parametrize("kind", ["ms", "tt"])
+def test_ionic_step_parity(kind):
+    import torch
+    from paper_2510_12011_amd import sim
+    s = sim.Simulation(0)
+    s.set_ionic(kind)
+    rng = np.random.default_rng(11)
+    if kind == "ms":
+        n = 1000
+        V = rng.uniform(-95.0, 30.0, n)
+        u = rng.uniform(0.0, 1.0, (1, n))
+    else:
+        V, u = _tt_states()
+        V = np.concatenate([V, V + rng.normal(0, 2.0, V.shape[0]), [15.0, -40.0]])
+        u = np.concatenate([u, u, u[:, :2]], axis=1)
+        u = np.ascontiguousarray(u)
+    n = V.shape[0]
+    for dt in (0.01, 0.02):
+        u_or = u.copy()
+        i_or = orc.ionic_step(kind, V, u_or, dt)
+        Vd = torch.tensor(V, dtype=torch.float64, device="cuda:0")
+        ud = torch.tensor(u, dtype=torch.float64, device="cuda:0").contiguous()
+        i_gpu = s.ionic_step(dt, Vd, ud).cpu().numpy()
+        u_gpu = ud.cpu().numpy()
+        np.testing.assert_allclose(u_gpu, u_or, rtol=1e-11, atol=1e-300)
+        np.testing.assert_allclose(i_gpu, i_or, rtol=1e-11, atol=1e-11 * abs(i_or).max())
+    assert n > 0
+
+
+def _compare_run(spec, n_steps, out_every, lat_bar=None):
+    s = _sim(spec)
+    o = orc.Oracle(spec)
+    v_or, it_or = o.steps(n_steps, out_every=out_every)
+    v_gpu, status = s.run(n_steps, out_every=out_every)
+    assert status == 0
+    it_gpu = s.iterations(n_steps)
+    errs = [_rel_l2(a, b) for a, b in zip(v_gpu, v_or)]
+    print(f"  V rel L2 per snapshot: max {max(errs):.2e}", flush=True)
+    assert max(errs) <= V_REL_L2, errs
+    assert abs(it_gpu.astype(int) - it_or).max() <= 1
+    lat_g, lrt_g = s.times()
+    lat_o = o.state.lat
+    assert np.array_equal(np.isfinite(lat_g), np.isfinite(lat_o))
+    fin = np.isfinite(lat_o)
+    if fin.any():
+        assert abs(lat_g[fin] - lat_o[fin]).max() <= spec.dt * (1 + 1e-9)
+    return s, o
+
+
+def test_trajectory_parity_tiny_cube():
+    """Unit cube, Mitchell-Schaeffer, 500 steps of 0.01 ms, rtol 1e-10."""
+    spec = inputs.tiny_cube()
+    s, o = _compare_run(spec, 500, 100)
+    assert np.isfinite(o.state.lat).sum() > 0.9 * spec.mesh.n_nodes
+
+
+def test_trajectory_parity_box_tt():
+    """Anisotropic jittered box, ten Tusscher-Panfilov, 400 steps."""
+    spec = inputs.small_box(nx=10, ny=8, nz=6, ionic="tt", n_steps=400, stim_extent=0.5)
+    _compare_run(spec, 400, 50)
+
+
+@pytest.mark.parametrize("theta,ws,rel", [(1.0, 0, 0), (0.5, 0, 1), (0.0, 1, 0)])
+def test_trajectory_parity_variants(theta, ws, rel):
+    """Backward Euler / forward Euler theta, previous-step warm start,
+    RHS-relative stopping."""
+    spec = inputs.small_box(nx=8, ny=6, nz=5, ionic="ms", theta=theta, n_steps=200)
+    spec.warm_start, spec.rel_mode = ws, rel
+    if theta == 0.0:
+        spec.dt = 0.002            # explicit diffusion needs a small step
+    _compare_run(spec, 200, 50)
+
+
+def test_coarse_slab_tt_full_length():
+    """20 x 7 x 3 mm slab at h = 0.5 mm, ten Tusscher-Panfilov, 50 ms."""
+    spec = inputs.slab(h=0.5, n_steps=5000)
+    _compare_run(spec, 5000, 500)
+
+
+def test_deterministic_and_checkpoint():
+    """Two runs are bitwise equal; n steps, save, restore into a fresh
+    context, n more steps equals 2n steps bitwise."""
+    spec = inputs.tiny_cube(n=10, n_steps=200)
+    a = _sim(spec)
+    va, _ = a.run(200, 100)
+    b = _sim(spec)
+    vb1, _ = b.run(100, 100)
+    st = b.get_state()
+    c = _sim(spec)
+    c.set_state(st["V"], st["Vprev"], st["u"], st["lat"], st["lrt"], st["step"])
+    vc, _ = c.run(100, 100)
+    assert np.array_equal(va[0], vb1[0])
+    assert np.array_equal(va[1], vc[0])
+    la, _ = a.times()
+    lc, _ = c.times()
+    assert np.array_equal(la, lc)
+
+
+def test_slab_full_size_prefix_and_front():
+    """The bench workload (slab, h = 0.1 mm, 442,401 nodes): the first 10
+    steps from rest match the oracle, and 2 steps taken from the GPU state at
+    t = 8 ms (wavefront inside the slab) match the oracle's 2 steps from that
+    same state."""
+    spec = inputs.slab(h=0.1, n_steps=10)
+    s = _sim(spec)
+    o = orc.Oracle(spec)
+    v_or, it_or = o.steps(10, out_every=10)
+    v_gpu, _ = s.run(10, 10)
+    assert _rel_l2(v_gpu[0], v_or[0]) <= V_REL_L2
+    s.run(790)
+    st = s.get_state()
+    o.state = orc.State(st["V"], st["Vprev"], np.ascontiguousarray(st["u"]), st["lat"], st["lrt"],
+                        st["step"])
+    v_or, _ = o.steps(2, out_every=1)
+    v_gpu, _ = s.run(2, 1)
+    for a, b in zip(v_gpu, v_or):
+        assert _rel_l2(a, b) <= V_REL_L2
+    assert ((st["V"] > 0).sum() > 1000)       # a wave is in flight
+    sys.stdout.flush()
