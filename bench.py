@@ -9,10 +9,11 @@ rest, then exactly K steps are timed between device synchronisations.  The
 value is DOF*steps/s = n_nodes * K / seconds.
 
 Also reported, as one JSON line:
-  roofline      the dominant kernel (PCG SpMV): algorithmic bytes per launch
-                (12 B per structural nonzero + 16 B per row) over its mean
-                duration, measured with HIP events attached to every SpMV
-                dispatch of the timed region, against 8 TB/s
+  roofline      the dominant kernel (PCG SpMV with fused p.q): algorithmic
+                bytes per launch (12 B per structural nonzero + 16 B per row)
+                over its mean duration, measured with HIP events attached to
+                every dispatch of that kernel in the timed region, against
+                8 TB/s
   cpu_baseline  the CPU oracle (plain FP64 C, OpenMP) timed on this host on a
                 bounded prefix of the same workload
 """
@@ -35,14 +36,20 @@ HBM_PEAK_GBS = 8000.0
 
 
 def workload(name):
+    """(spec, description, precision) of a named workload."""
     from paper_2510_12011_amd import inputs
     if name == "slab":
-        return inputs.slab(h=0.1), "slab 20x7x3 mm, h=0.1 mm Kuhn tets, ten Tusscher-Panfilov, plain FP64"
-    if name == "slab_h0.05":
-        return (inputs.slab(h=0.05),
-                "slab 20x7x3 mm, h=0.05 mm Kuhn tets, ten Tusscher-Panfilov, plain FP64")
+        return (inputs.slab(h=0.1),
+                "slab 20x7x3 mm, h=0.1 mm Kuhn tets (442,401 nodes), ten Tusscher-Panfilov, "
+                "plain FP64, rtol 1e-10 of ||z0||", "fp64")
+    if name in ("precision", "precision_fp64"):
+        prec = "mixed" if name == "precision" else "fp64"
+        return (inputs.slab_precision(h=0.05, precision=prec),
+                f"slab 20x7x3 mm, h=0.05 mm Kuhn tets (3,449,001 nodes), ten Tusscher-Panfilov, "
+                f"{'mixed FP32/FP64' if prec == 'mixed' else 'plain FP64'}, rtol 1e-8 of ||D^-1 b||",
+                prec)
     if name == "tiny":
-        return inputs.tiny_cube(), "unit cube 20^3 hexes, Mitchell-Schaeffer, plain FP64"
+        return (inputs.tiny_cube(), "unit cube 20^3 hexes, Mitchell-Schaeffer, plain FP64", "fp64")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -68,6 +75,7 @@ def main():
     ap.add_argument("--workload", default="slab")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-every", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method runs one simulation per GPU and "
@@ -77,15 +85,18 @@ def main():
     import torch
     from paper_2510_12011_amd import sim
 
-    spec, desc = workload(args.workload)
+    spec, desc, prec = workload(args.workload)
     n = spec.mesh.n_nodes
-    print(f"[bench] workload {args.workload}: {n} nodes, {spec.mesh.n_tets} tets", flush=True)
-    s = sim.from_spec(spec)
+    print(f"[bench] workload {args.workload}: {n} nodes, {spec.mesh.n_tets} tets, {prec}",
+          flush=True)
+    s = sim.from_spec(spec, precision=prec)
     st = s.stats()
     if args.warmup:
         s.run(args.warmup)
         s.prepare(spec.dt)          # back to rest; timing starts from t = 0
-    s.set_profiling(True)
+    # HIP events on the SpMV launches of every 10th step of the timed region
+    # (events on every launch would slow the step loop by ~15%)
+    s.set_profiling(args.profile_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, status = s.run(args.steps)
@@ -98,9 +109,14 @@ def main():
 
     value = n * args.steps / elapsed
     nnz = st["nnz"]
-    bytes_per_launch = 12 * nnz + 16 * n
-    spmv_avg = st["spmv_seconds"] / max(1, st["spmv_timed"])
-    achieved = bytes_per_launch / spmv_avg / 1e9
+    # dominant kernel: the PCG launch carrying q = A p.  Its algorithmic bytes
+    # (summed by the library over the launches that did the product): per
+    # structural nonzero the value and column (12 B FP64, 8 B FP32), per row p
+    # read once and q written once (16 B FP64, 8 B FP32)
+    launches = max(1, st["spmv_timed"])
+    spmv_avg = st["spmv_seconds"] / launches
+    bytes_avg = st["spmv_bytes"] / launches
+    achieved = bytes_avg / spmv_avg / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -112,16 +128,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": desc, "n_nodes": n, "nnz": nnz, "n_tets": spec.mesh.n_tets,
-                   "dt_ms": spec.dt, "rtol": spec.rtol, "stopping": "relative to ||z0||",
+                   "dt_ms": spec.dt, "rtol": spec.rtol,
+                   "stopping": "relative to ||z0||" if spec.rel_mode == 0 else "relative to ||D^-1 b||",
                    "warm_start": "2V^k - V^(k-1)", "mean_cg_iters": float(iters.mean()),
                    "max_cg_iters": int(iters.max())},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv_dot", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_spmv_dot" if prec == "fp64" else "k_spmv32_dot",
+                     "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": 1e6 * spmv_avg, "launches_timed": st["spmv_timed"]},
+                     "traffic": None, "bytes_per_launch": bytes_avg,
+                     "avg_launch_us": 1e6 * spmv_avg, "launches_timed": st["spmv_timed"],
+                     "sampled_every_n_steps": args.profile_every,
+                     "launches_with_product": st["spmv_work"],
+                     "cache_resident": bool((12 if prec == "fp64" else 8) * nnz < 256e6)},
     }
     if not args.no_cpu:
         print(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps", flush=True)

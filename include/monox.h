@@ -71,12 +71,27 @@ enum { MDX_REL_INITIAL = 0, MDX_REL_RHS = 1 };
 /* which assembled matrix mdx_get_matrix returns */
 enum { MDX_MAT_M = 0, MDX_MAT_K = 1, MDX_MAT_A = 2 };
 
+/* arithmetic of the step:
+ *   MDX_PREC_FP64          plain FP64 throughout;
+ *   MDX_PREC_MIXED         PCG iterations in FP32 (matrix values and vectors
+ *                          of the SpMV and vector updates) with FP64 dot
+ *                          products, FP64 right-hand side, solution and
+ *                          residual replacement; ionic model in FP64;
+ *   MDX_PREC_MIXED_GATES32 as MIXED, and the ionic gating variables stored
+ *                          and advanced in FP32 (concentrations FP64).  On the
+ *                          ten Tusscher-Panfilov slab this alone moves V by
+ *                          ~1e-5 relative L2 over 50 ms. */
+enum { MDX_PREC_FP64 = 0, MDX_PREC_MIXED = 1, MDX_PREC_MIXED_GATES32 = 2 };
+
 typedef struct {
     double atol;          /* absolute tolerance on ||z|| (0: off)           */
     double rtol;          /* relative tolerance, see rel_mode               */
     int32_t rel_mode;     /* MDX_REL_*                                      */
     int32_t max_iter;     /* iteration cap per solve (>= 1)                 */
     int32_t warm_start;   /* MDX_WS_*                                       */
+    int32_t precision;    /* MDX_PREC_*                                     */
+    int32_t rr_interval;  /* mixed: FP64 residual replacement every this   */
+                          /* many iterations (0: only at convergence / cap) */
     int32_t reserved;     /* must be 0                                      */
 } mdx_solver_opts;
 
@@ -87,8 +102,12 @@ typedef struct {
     int64_t not_converged;    /* solves that reached max_iter                */
     int64_t n_nodes, nnz, n_sell_slots, bandwidth;
     double step_loop_seconds; /* host wall time inside mdx_run               */
-    int64_t spmv_timed;       /* SpMV launches timed (profiling on, real work) */
+    int64_t spmv_timed;       /* PCG SpMV-kernel launches timed (profiling on) */
     double spmv_seconds;      /* their summed device duration (HIP events)   */
+    int64_t spmv_work;        /* of those, launches that did the SpMV (the   */
+                              /* others only applied the stopping test)      */
+    double spmv_bytes;        /* algorithmic bytes moved by those launches   */
+    double host_wait_seconds; /* host time blocked on the stream in mdx_run  */
 } mdx_stats;
 
 /* ---- context -------------------------------------------------------- */
@@ -160,11 +179,25 @@ MDX_API mdx_status mdx_get_times(mdx_ctx *ctx, double *lat, double *lrt);
  * in the last mdx_run call), -1 where max_iter was hit. */
 MDX_API mdx_status mdx_get_iterations(mdx_ctx *ctx, int64_t n, int32_t *iters);
 MDX_API mdx_status mdx_get_stats(mdx_ctx *ctx, mdx_stats *out);
-/* Profiling: when enabled, every PCG SpMV launch in mdx_run carries HIP
- * start/stop events on the context's stream; the durations of the launches
- * that did work (not those queued after convergence) are summed into
- * mdx_stats.spmv_seconds / spmv_timed.  Off by default. */
-MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t enable);
+/* Profiling: every_n > 0 attaches HIP start/stop events (on the context's
+ * stream) to every launch of the PCG kernel that computes q = A p during
+ * every every_n-th step of mdx_run; their durations are summed into
+ * mdx_stats.spmv_seconds (count spmv_timed, of which spmv_work did the
+ * product, moving spmv_bytes algorithmic bytes).  0 (default) turns it off.
+ * Events cost time: sample (e.g. every 10th step) to keep the step loop's
+ * timing representative. */
+MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
+
+/* Launch-shape tuning (no effect on results beyond rounding order):
+ *   MDX_TUNE_MAX_GROUPS  cap on workgroups of the row-tiled kernels
+ *                        (16..65536, default 4096);
+ *   MDX_TUNE_ITER_SCHEME PCG iteration as three kernels (0: SpMV, update,
+ *                        direction; default) or two kernels (1: the
+ *                        direction is formed per gathered column inside
+ *                        the SpMV).
+ * Takes effect at the next mdx_prepare / mdx_run. */
+enum { MDX_TUNE_MAX_GROUPS = 1, MDX_TUNE_ITER_SCHEME = 2 };
+MDX_API mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value);
 
 /* ---- state (checkpoint / resume, parity checks) ----------------------- */
 /* V^k, V^{k-1}, states u (SoA, [nstates][n_nodes]), LAT, LRT and the step

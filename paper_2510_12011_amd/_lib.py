@@ -26,12 +26,15 @@ MDX_ERR_UNSUPPORTED = -7
 MDX_IONIC_NONE, MDX_IONIC_MS, MDX_IONIC_TT = 0, 1, 2
 MDX_WS_PREV, MDX_WS_EXTRAP = 0, 1
 MDX_REL_INITIAL, MDX_REL_RHS = 0, 1
+MDX_PREC_FP64, MDX_PREC_MIXED, MDX_PREC_MIXED_GATES32 = 0, 1, 2
 MDX_MAT_M, MDX_MAT_K, MDX_MAT_A = 0, 1, 2
+MDX_TUNE_MAX_GROUPS, MDX_TUNE_ITER_SCHEME = 1, 2
 
 
 class SolverOpts(C.Structure):
     _fields_ = [("atol", C.c_double), ("rtol", C.c_double), ("rel_mode", C.c_int32),
-                ("max_iter", C.c_int32), ("warm_start", C.c_int32), ("reserved", C.c_int32)]
+                ("max_iter", C.c_int32), ("warm_start", C.c_int32), ("precision", C.c_int32),
+                ("rr_interval", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -39,7 +42,9 @@ class Stats(C.Structure):
                 ("cg_iters_max", C.c_int64), ("not_converged", C.c_int64),
                 ("n_nodes", C.c_int64), ("nnz", C.c_int64), ("n_sell_slots", C.c_int64),
                 ("bandwidth", C.c_int64), ("step_loop_seconds", C.c_double),
-                ("spmv_timed", C.c_int64), ("spmv_seconds", C.c_double)]
+                ("spmv_timed", C.c_int64), ("spmv_seconds", C.c_double),
+                ("spmv_work", C.c_int64), ("spmv_bytes", C.c_double),
+                ("host_wait_seconds", C.c_double)]
 
 
 class MdxError(RuntimeError):
@@ -70,6 +75,7 @@ _SIGS = {
     "mdx_get_iterations": (C.c_int, [P, C.c_int64, P]),
     "mdx_get_stats": (C.c_int, [P, C.POINTER(Stats)]),
     "mdx_set_profiling": (C.c_int, [P, C.c_int32]),
+    "mdx_set_tuning": (C.c_int, [P, C.c_int32, C.c_int64]),
     "mdx_get_state": (C.c_int, [P, P, P, P, P, P, C.POINTER(C.c_int64)]),
     "mdx_set_state": (C.c_int, [P, P, P, P, P, P, C.c_int64]),
     "mdx_get_matrix": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int64), P, P, P]),

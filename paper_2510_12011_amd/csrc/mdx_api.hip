@@ -10,8 +10,8 @@
 //
 // Time loop (mdx_run): per step the kernels of mdx_ionic.hip / mdx_solver.hip
 // are queued on the context's stream; PCG iterations are queued in chunks
-// (first chunk = last step's count + 1) and the host reads the device-side
-// `done` flag once per chunk.  Iterations queued after convergence return at
+// (first chunk = last step's count) and the host reads the device-side
+// `done` flag once per chunk.  Kernels queued after convergence return at
 // their first instruction.
 #include <hip/hip_runtime.h>
 
@@ -34,7 +34,8 @@ using namespace mdx;
 
 namespace {
 
-constexpr int kMaxGroups = 1024;
+constexpr int kMaxGroups = 4096;      // default cap on row-tiled workgroups
+constexpr int kPartialCap = 65536;    // partial slots per reduction (>= any cap)
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -46,8 +47,10 @@ struct Stim {
 
 // byte offsets of every array inside the persistent workspace / setup scratch
 struct Layout {
-    size_t slice_ptr, col, Mv, Kv, Av, dinv, vec[3], r, p, q, b, s, istim, u, lat, lrt, stim_idx,
-        partial, scalars, total;
+    size_t slice_ptr, col, Mv, Kv, Av, dinv, vec[3], r, p, p2, q, b, s, istim, u, lat, lrt, stim_idx,
+        partial, scalars;
+    size_t A32, dinv32, r32, p32, q32, delta, g32;   // mixed-precision form
+    size_t total;
     size_t x_xyz, x_tets, x_fibre, x_sig, x_vol, x_ek, x_cptr, x_contrib, x_total;
 };
 
@@ -68,7 +71,7 @@ struct mdx_ctx {
     int ionic_kind = 0;
     std::vector<double> ionic_params;
     std::vector<Stim> stims;
-    mdx_solver_opts opts{1e-5, 1e-5, MDX_REL_INITIAL, 100, MDX_WS_EXTRAP, 0};
+    mdx_solver_opts opts{1e-5, 1e-5, MDX_REL_INITIAL, 100, MDX_WS_EXTRAP, MDX_PREC_FP64, 50, 0};
 
     // ordering and layout (host)
     std::vector<int32_t> perm, iperm;   // perm[new] = old, iperm[old] = new
@@ -91,8 +94,14 @@ struct mdx_ctx {
     Scalars *sc_host = nullptr;   // pinned
     double *stage = nullptr;      // pinned, npad doubles
 
-    // profiling: event pairs around the SpMV launches of one step
-    bool profiling = false;
+    // launch-shape tuning
+    int max_groups = kMaxGroups;
+    int iter_scheme = 0;
+
+    // profiling: event pairs around the SpMV launches of every
+    // `profile_every`-th step (0: off)
+    int profile_every = 0;
+    bool profiling = false;   // this step carries events
     std::vector<hipEvent_t> ev;
 
     // statistics
@@ -281,6 +290,7 @@ void compute_layout(mdx_ctx *c)
     for (int i = 0; i < 3; ++i) L.vec[i] = take(sizeof(double) * np);
     L.r = take(sizeof(double) * np);
     L.p = take(sizeof(double) * np);
+    L.p2 = take(sizeof(double) * np);
     L.q = take(sizeof(double) * np);
     L.b = take(sizeof(double) * np);
     L.s = take(sizeof(double) * np);
@@ -291,8 +301,15 @@ void compute_layout(mdx_ctx *c)
     size_t nst = 0;
     for (auto &s : c->stims) nst += s.nodes.size();
     L.stim_idx = take(sizeof(int32_t) * std::max<size_t>(nst, 1));
-    L.partial = take(sizeof(double) * 3 * 3 * kMaxGroups);
+    L.partial = take(sizeof(double) * 3 * 3 * kPartialCap);
     L.scalars = take(sizeof(Scalars));
+    L.A32 = take(sizeof(float) * ns);
+    L.dinv32 = take(sizeof(float) * np);
+    L.r32 = take(sizeof(float) * np);
+    L.p32 = take(sizeof(float) * np);
+    L.q32 = take(sizeof(float) * np);
+    L.delta = take(sizeof(float) * np);
+    L.g32 = take(sizeof(float) * np * std::max(1, ionic_gate_rows(c->ionic_kind)));
     L.total = o;
 
     o = 0;
@@ -626,6 +643,7 @@ mdx_status mdx_set_solver(mdx_ctx *ctx, const mdx_solver_opts *o)
 {
     if (!ctx || !o) return MDX_ERR_INVALID_ARG;
     if (!(o->atol >= 0.0) || !(o->rtol >= 0.0) || o->max_iter < 1 || o->reserved != 0 ||
+        o->precision < MDX_PREC_FP64 || o->precision > MDX_PREC_MIXED_GATES32 || o->rr_interval < 0 ||
         (o->rel_mode != MDX_REL_INITIAL && o->rel_mode != MDX_REL_RHS) ||
         (o->warm_start != MDX_WS_PREV && o->warm_start != MDX_WS_EXTRAP))
         return fail(ctx, MDX_ERR_INVALID_ARG, "invalid solver options");
@@ -774,6 +792,9 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     launch_system(st, ctx->nslots, Mv, Kv, ctx->chi * ctx->cm, ctx->theta * dt, Av);
     SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
     launch_dinv(st, ctx->npad, ctx->n, P, Av, ctx->dev<double>(L.dinv));
+    // FP32 copies for the mixed-precision form
+    launch_to_f32(st, ctx->nslots, Av, ctx->dev<float>(L.A32));
+    launch_to_f32(st, ctx->npad, ctx->dev<double>(L.dinv), ctx->dev<float>(L.dinv32));
     HIPCHK(hipGetLastError());
 
     // state: rest values, zeroed work vectors, LAT/LRT = +inf
@@ -783,8 +804,12 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     launch_ionic_init(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad, ctx->vec(0),
                       ctx->vec(1),
                       ionic_nstates(ctx->ionic_kind) ? ctx->dev<double>(L.u) : nullptr);
-    for (size_t off : {L.vec[2], L.r, L.p, L.q, L.b, L.s, L.istim})
+    for (size_t off : {L.vec[2], L.r, L.p, L.p2, L.q, L.b, L.s, L.istim})
         launch_fill(st, ctx->npad, 0.0, ctx->dev<double>(off));
+    // FP32 vectors: zero bits (float zero) via the double fill over half the count
+    for (size_t off : {L.r32, L.p32, L.q32, L.delta})
+        launch_fill(st, ctx->npad / 2, 0.0, ctx->dev<double>(off));
+    launch_gates_to_f32(st, ctx->ionic_kind, ctx->npad, ctx->dev<double>(L.u), ctx->dev<float>(L.g32));
     const double inf = std::numeric_limits<double>::infinity();
     launch_fill(st, ctx->npad, inf, ctx->dev<double>(L.lat));
     launch_fill(st, ctx->npad, inf, ctx->dev<double>(L.lrt));
@@ -796,7 +821,7 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
                           hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
 
-    ctx->tiling = make_tiling(ctx->npad, kMaxGroups);
+    ctx->tiling = make_tiling(ctx->npad, ctx->max_groups);
     ctx->dt = dt;
     ctx->step = 0;
     ctx->active.assign(ctx->stims.size(), 0);
@@ -821,14 +846,21 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
     double *Mv = ctx->dev<double>(L.Mv), *Kv = ctx->dev<double>(L.Kv), *Av = ctx->dev<double>(L.Av);
     double *dinv = ctx->dev<double>(L.dinv);
-    double *r = ctx->dev<double>(L.r), *p = ctx->dev<double>(L.p), *q = ctx->dev<double>(L.q);
+    double *r = ctx->dev<double>(L.r), *q = ctx->dev<double>(L.q);
+    double *pbuf[2] = {ctx->dev<double>(L.p), ctx->dev<double>(L.p2)};
     double *b = ctx->dev<double>(L.b), *s = ctx->dev<double>(L.s);
     double *u = ionic_nstates(ctx->ionic_kind) ? ctx->dev<double>(L.u) : nullptr;
     double *part0 = ctx->dev<double>(L.partial);
-    double *part_pq = part0 + 3 * kMaxGroups, *part_rz = part0 + 6 * kMaxGroups;
+    double *part_pq = part0 + 3 * kPartialCap, *part_rz = part0 + 6 * kPartialCap;
     Scalars *sc = ctx->dev<Scalars>(L.scalars);
     const StepParams sp = step_params(ctx);
     const int max_iter = ctx->opts.max_iter;
+    const bool mixed = ctx->opts.precision != MDX_PREC_FP64;
+    const bool gates32 = ctx->opts.precision == MDX_PREC_MIXED_GATES32;
+    float *A32 = ctx->dev<float>(L.A32);
+    float *dinv32 = ctx->dev<float>(L.dinv32), *r32 = ctx->dev<float>(L.r32);
+    float *p32 = ctx->dev<float>(L.p32), *q32 = ctx->dev<float>(L.q32);
+    float *delta = ctx->dev<float>(L.delta), *g32 = ctx->dev<float>(L.g32);
     mdx_status result = MDX_OK;
     ctx->iters_hist.clear();
     int64_t n_out = 0;
@@ -839,47 +871,144 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         bool any_stim = false;
         if (mdx_status e = update_stimulus(ctx, k, any_stim)) return e;
         double *V = ctx->vec(0), *Vprev = ctx->vec(1), *X = ctx->vec(2);
-        launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad, ctx->dt,
-                          ctx->cm, V, u, any_stim ? ctx->dev<double>(L.istim) : nullptr, s, 0);
-        launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, p, b, part0);
-        launch_init_finalize(st, T, part0, sp.rel_mode, sc);
-        int launched = 0;
+        ctx->profiling = ctx->profile_every > 0 && k % ctx->profile_every == 0;
+        const double *istim = any_stim ? ctx->dev<double>(L.istim) : nullptr;
+        int units = 0;   // kernels carrying the SpMV launched so far
         bool done = false;
-        // first chunk: the previous step's count; then one at a time
-        int chunk = std::max(1, ctx->last_iters);
-        while (!done && launched < max_iter) {
-            int c = std::min(chunk, max_iter - launched);
-            for (int i = 0; i < c; ++i) {
-                const int it = launched + i;
-                hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (ctx->profiling && 2 * it + 1 < (int)ctx->ev.size()) {
-                    e0 = ctx->ev[2 * it];
-                    e1 = ctx->ev[2 * it + 1];
+        if (mixed) {
+            // ---- mixed-precision form ----
+            if (gates32)
+                launch_ionic_step_mixed(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n,
+                                        ctx->npad, ctx->dt, ctx->cm, V, u, g32, istim, s);
+            else
+                launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
+                                  ctx->dt, ctx->cm, V, u, istim, s, 0);
+            launch_rhs_init_mixed(st, T, P, Mv, Kv, dinv, dinv32, sp, V, Vprev, s, X, b, r32,
+                                  delta, part0);
+            launch_init_finalize(st, T, part0, sp.rel_mode, sc);
+            launch_set_direction32(st, ctx->npad, dinv32, r32, p32, sc);
+            int it = 0;
+            int chunk = std::max(1, ctx->last_iters);
+            for (int guard = 0; !done && it < max_iter && guard < 2 * max_iter + 8; ++guard) {
+                const int c = std::min(chunk, max_iter - it);
+                for (int i = 0; i < c; ++i) {
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (ctx->profiling && 2 * units + 1 < (int)ctx->ev.size()) {
+                        e0 = ctx->ev[2 * units];
+                        e1 = ctx->ev[2 * units + 1];
+                    }
+                    launch_spmv32_dot(st, T, P, A32, p32, q32, part_pq, sc, e0, e1);
+                    launch_cg_update32(st, T, it + i, part_pq, dinv32, p32, q32, delta, r32, part_rz,
+                                       sc);
+                    launch_cg_direction32(st, T, it + i, ctx->opts.rr_interval, max_iter, part_rz,
+                                          dinv32, r32, p32, sc);
+                    ++units;
                 }
-                launch_spmv_dot(st, T, P, Av, p, q, part_pq, &sc->done, e0, e1);
-                launch_cg_update(st, T, it, part_pq, dinv, p, q, X, r, part_rz, sc);
-                launch_cg_direction(st, T, it, part_rz, dinv, r, p, sc);
+                launch_replacement(st, T, P, max_iter, Av, X, delta, b, dinv, dinv32, r32, p32,
+                                   part0, sc);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+                auto w0 = std::chrono::steady_clock::now();
+                HIPCHK(hipStreamSynchronize(st));
+                ctx->stats.host_wait_seconds +=
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+                done = ctx->sc_host->done != 0;
+                it = ctx->sc_host->it_next;
+                chunk = 1;
             }
-            launched += c;
-            HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            done = ctx->sc_host->done != 0;
-            chunk = 1;
+        } else {
+        launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad, ctx->dt,
+                          ctx->cm, V, u, istim, s, 0);
+        launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0);
+        launch_init_finalize(st, T, part0, sp.rel_mode, sc);
+        if (ctx->iter_scheme == 1) {
+            // Unit 0 is the first half of iteration 0; unit u >= 1 is the
+            // second half of iteration u-1 followed by the first half of
+            // iteration u, which tests ||z_u||.  Units 0..c detect convergence
+            // in <= c iterations with no idle launch.  First chunk: the
+            // previous step's count; then one unit at a time.
+            int chunk = std::max(1, ctx->last_iters) + 1;
+            while (!done && units <= max_iter) {
+                const int c = std::min(chunk, max_iter + 1 - units);
+                for (int i = 0; i < c; ++i) {
+                    const int u_ = units + i;
+                    if (u_ >= 1)
+                        launch_cg_update(st, T, u_ - 1, part_pq, dinv, pbuf[(u_ - 1) & 1], q, X, r,
+                                         part_rz, sc);
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (ctx->profiling && 2 * u_ + 1 < (int)ctx->ev.size()) {
+                        e0 = ctx->ev[2 * u_];
+                        e1 = ctx->ev[2 * u_ + 1];
+                    }
+                    launch_cg_direction_spmv(st, T, u_, max_iter, P, Av, dinv, r,
+                                             pbuf[(u_ + 1) & 1], pbuf[u_ & 1], q, part_rz,
+                                             part_pq, sc, e0, e1);
+                }
+                units += c;
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+                auto w0 = std::chrono::steady_clock::now();
+                HIPCHK(hipStreamSynchronize(st));
+                ctx->stats.host_wait_seconds +=
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+                done = ctx->sc_host->done != 0;
+                chunk = 1;
+            }
+        } else {
+            // Three kernels per iteration: q = A p (+ p.q), update (+ r.z,
+            // z.z), direction (test, beta, p = z + beta p).  Iteration it's
+            // direction kernel tests ||z_{it+1}||.  First chunk: the previous
+            // step's count; then one iteration at a time.
+            double *p = pbuf[0];
+            launch_set_direction(st, ctx->npad, dinv, r, p, sc);
+            int chunk = std::max(1, ctx->last_iters);
+            while (!done && units < max_iter) {
+                const int c = std::min(chunk, max_iter - units);
+                for (int i = 0; i < c; ++i) {
+                    const int it = units + i;
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (ctx->profiling && 2 * it + 1 < (int)ctx->ev.size()) {
+                        e0 = ctx->ev[2 * it];
+                        e1 = ctx->ev[2 * it + 1];
+                    }
+                    launch_spmv_dot(st, T, P, Av, p, q, part_pq, &sc->done, e0, e1);
+                    launch_cg_update(st, T, it, part_pq, dinv, p, q, X, r, part_rz, sc);
+                    launch_cg_direction(st, T, it, part_rz, dinv, r, p, sc);
+                }
+                units += c;
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+                auto w0 = std::chrono::steady_clock::now();
+                HIPCHK(hipStreamSynchronize(st));
+                ctx->stats.host_wait_seconds +=
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+                done = ctx->sc_host->done != 0;
+                chunk = 1;
+            }
         }
+        }   // FP64 path
         if (ctx->sc_host->nonfinite)
             return fail(ctx, MDX_ERR_NONFINITE, "non-finite value in the solve of step %lld",
                         (long long)k);
         const int iters = done ? ctx->sc_host->iters : -1;
         ctx->last_iters = done ? iters : max_iter;
         if (ctx->profiling) {
-            const int real = std::min(done ? iters : max_iter, (int)ctx->ev.size() / 2);
-            for (int it = 0; it < real; ++it) {
+            const int timed = std::min(units, (int)ctx->ev.size() / 2);
+            for (int u_ = 0; u_ < timed; ++u_) {
                 float ms = 0.0f;
-                HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2 * it], ctx->ev[2 * it + 1]));
+                HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2 * u_], ctx->ev[2 * u_ + 1]));
                 ctx->stats.spmv_seconds += 1e-3 * ms;
                 ctx->stats.spmv_timed++;
             }
+            const int64_t work = std::min<int64_t>(
+                mixed ? ctx->sc_host->it_next : (done ? iters : max_iter), timed);
+            ctx->stats.spmv_work += work;
+            // per nonzero: value + column; per row: p read once, q written once
+            // (the two-kernel FP64 scheme also reads r, D^-1, p_{k-1}, writes p_k)
+            const double per_nnz = mixed ? 8.0 : 12.0;
+            const double per_row = mixed ? 8.0 : ctx->iter_scheme == 1 ? 40.0 : 16.0;
+            ctx->stats.spmv_bytes +=
+                (double)work * (per_nnz * (double)ctx->nnz + per_row * (double)ctx->n);
         }
         launch_epilogue(st, ctx->n, (double)(k + 1) * ctx->dt, V, X, ctx->dev<double>(L.lat),
                         ctx->dev<double>(L.lrt), sc);
@@ -951,16 +1080,36 @@ mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t enable)
     if (!ctx) return MDX_ERR_INVALID_ARG;
     if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
     HIPCHK(hipSetDevice(ctx->device));
+    if (enable < 0) return fail(ctx, MDX_ERR_INVALID_ARG, "sampling period must be >= 0");
     if (enable && ctx->ev.empty()) {
-        const int pairs = std::min(ctx->opts.max_iter, 4096);
+        const int pairs = std::min(ctx->opts.max_iter + 1, 4097);
         for (int i = 0; i < 2 * pairs; ++i) {
             hipEvent_t e;
             HIPCHK(hipEventCreate(&e));
             ctx->ev.push_back(e);
         }
     }
-    ctx->profiling = enable != 0;
+    ctx->profile_every = enable;
     return MDX_OK;
+}
+
+mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    switch (key) {
+    case MDX_TUNE_MAX_GROUPS:
+        if (value < 16 || value > kPartialCap)
+            return fail(ctx, MDX_ERR_INVALID_ARG, "max_groups must lie in [16, %d]", kPartialCap);
+        ctx->max_groups = (int)value;
+        if (ctx->npad > 0) ctx->tiling = make_tiling(ctx->npad, ctx->max_groups);
+        return MDX_OK;
+    case MDX_TUNE_ITER_SCHEME:
+        if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "scheme is 0 or 1");
+        ctx->iter_scheme = (int)value;
+        return MDX_OK;
+    default:
+        return fail(ctx, MDX_ERR_INVALID_ARG, "unknown tuning key %d", key);
+    }
 }
 
 mdx_status mdx_get_state(mdx_ctx *ctx, double *V, double *Vprev, double *u, double *lat,
@@ -972,6 +1121,9 @@ mdx_status mdx_get_state(mdx_ctx *ctx, double *V, double *Vprev, double *u, doub
     if (V) if (mdx_status e = copy_vec_out(ctx, ctx->vec(0), V)) return e;
     if (Vprev) if (mdx_status e = copy_vec_out(ctx, ctx->vec(1), Vprev)) return e;
     int ns = ionic_nstates(ctx->ionic_kind);
+    if (u && ctx->opts.precision == MDX_PREC_MIXED_GATES32)   // gates live in FP32
+        launch_gates_to_f64(ctx->stream, ctx->ionic_kind, ctx->npad, ctx->dev<float>(ctx->L.g32),
+                            ctx->dev<double>(ctx->L.u));
     if (u)
         for (int s = 0; s < ns; ++s)
             if (mdx_status e = copy_vec_out(ctx, ctx->dev<double>(ctx->L.u) + s * ctx->npad,
@@ -1001,6 +1153,10 @@ mdx_status mdx_set_state(mdx_ctx *ctx, const double *V, const double *Vprev, con
     for (int s = 0; s < ns; ++s)
         if (mdx_status e = copy_vec_in(ctx, u + s * ctx->n, ctx->dev<double>(ctx->L.u) + s * ctx->npad))
             return e;
+    launch_gates_to_f32(ctx->stream, ctx->ionic_kind, ctx->npad, ctx->dev<double>(ctx->L.u),
+                        ctx->dev<float>(ctx->L.g32));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     if (lat) {
         if (mdx_status e = copy_vec_in(ctx, lat, ctx->dev<double>(ctx->L.lat))) return e;
     }
@@ -1059,7 +1215,7 @@ mdx_status mdx_spmv(mdx_ctx *ctx, int32_t which, const double *x, double *y)
     SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
     Scalars *sc = ctx->dev<Scalars>(L.scalars);
     launch_spmv_dot(ctx->stream, ctx->tiling, P, ctx->dev<double>(off), p, q,
-                    ctx->dev<double>(L.partial) + 3 * kMaxGroups, &sc->zero);
+                    ctx->dev<double>(L.partial) + 3 * kPartialCap, &sc->zero);
     HIPCHK(hipGetLastError());
     return copy_vec_out(ctx, q, y);
     GUARD_END

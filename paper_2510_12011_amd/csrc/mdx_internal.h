@@ -45,6 +45,12 @@ struct alignas(256) Scalars {
     int32_t iters;      // iterations taken by the finished solve
     int32_t nonfinite;  // a non-finite V was produced
     int32_t zero;       // always 0 (for launches that must not early-exit)
+    // mixed-precision form: residual replacement protocol
+    int32_t replace;    // a replacement is pending (iteration kernels idle)
+    int32_t redirect;   // a replacement did not stop: p = z + beta p pending
+    int32_t it_next;    // iterations completed (index of the next one)
+    int32_t pad_;
+    double beta;        // beta after a replacement
 };
 
 struct SellView {
@@ -75,30 +81,77 @@ void launch_ionic_step(hipStream_t s, int kind, const double *params, int64_t n,
                        double dt, double cm, const double *V, double *u, const double *istim,
                        double *out, int raw);
 
-// ---- solver (mdx_solver.hip) ---------------------------------------------
+// Mixed-precision form: gates in FP32 (g32, ionic_gate_rows(kind) rows of ld
+// floats), concentrations and the current in FP64 (u).  The FP64 array u
+// keeps the full state layout; launch_gates_to_f32 / _to_f64 move the gate
+// rows between u and g32.
+int ionic_gate_rows(int kind);
+int ionic_gate_row0(int kind);
+void launch_ionic_step_mixed(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
+                             double dt, double cm, const double *V, double *u, float *g32,
+                             const double *istim, double *out);
+void launch_gates_to_f32(hipStream_t s, int kind, int64_t ld, const double *u, float *g32);
+void launch_gates_to_f64(hipStream_t s, int kind, int64_t ld, const float *g32, double *u);
+
 struct StepParams {
     double chi, cm, theta, dt;
     int warm_start;    // 0: x0 = V^k, 1: x0 = 2V^k - V^{k-1}
     int rel_mode;      // 0: relative to ||z_0||, 1: relative to ||D^-1 b||
 };
+
+// ---- mixed-precision solver (mdx_mixed.hip) -----------------------------
+void launch_to_f32(hipStream_t s, int64_t n, const double *a, float *b);
+void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
+                           const double *Kv, const double *dinv, const float *dinv32,
+                           const StepParams &sp, const double *V, const double *Vprev,
+                           const double *src, double *x, double *b, float *r32, float *delta,
+                           double *partial);
+void launch_set_direction32(hipStream_t s, int64_t n, const float *dinv32, const float *r32,
+                            float *p32, const Scalars *sc);
+void launch_spmv32_dot(hipStream_t s, const Tiling &t, SellView P, const float *A32,
+                       const float *p, float *q, double *partial, Scalars *sc,
+                       hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+void launch_cg_update32(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
+                        const float *dinv32, const float *p, const float *q, float *delta,
+                        float *r, double *partial_rz, Scalars *sc);
+void launch_cg_direction32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter,
+                           const double *partial_rz, const float *dinv32, const float *r, float *p,
+                           Scalars *sc);
+// flush, true residual, finalize, redirect (all no-ops unless a replacement is pending)
+void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const double *Av,
+                        double *x, float *delta, const double *b, const double *dinv,
+                        const float *dinv32, float *r32, float *p32, double *partial, Scalars *sc);
+
+// ---- solver (mdx_solver.hip) ---------------------------------------------
 void launch_fill(hipStream_t s, int64_t n, double v, double *x);
 void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double amp, double *istim);
-// b, x0, r0 = b - A x0, p0 = z0 = D^-1 r0 and the partials (r.z, z.z, |D^-1 b|^2)
+// b, x0, r0 = b - A x0 and the partials (r.z, z.z, |D^-1 b|^2), z = D^-1 r
 void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                      const double *Kv, const double *dinv, const StepParams &sp,
                      const double *V, const double *Vprev, const double *src, double *x,
-                     double *r, double *p, double *b, double *partial);
+                     double *r, double *b, double *partial);
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
                           Scalars *sc);
+// q = A p with partial p.q (no convergence logic; `done` non-zero skips it).
 // ev_start/ev_stop: optional events recorded around the dispatch
 void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *Av,
                      const double *p, double *q, double *partial, const int32_t *done,
                      hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// PCG iteration k, first half (test of ||z_k||, beta_k, q = A p_k, partial p_k.q)
+void launch_cg_direction_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
+                              const double *Av, const double *dinv, const double *r,
+                              const double *p_prev, double *p_cur, double *q,
+                              const double *partial_rz, double *partial_pq, Scalars *sc,
+                              hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// three-kernel scheme: direction update (test, beta, p = z + beta p) and p_0 = z_0
+void launch_cg_direction(hipStream_t s, const Tiling &t, int k, const double *partial_rz,
+                         const double *dinv, const double *r, double *p, Scalars *sc);
+void launch_set_direction(hipStream_t s, int64_t n, const double *dinv, const double *r, double *p,
+                          const Scalars *sc);
+// PCG iteration k, second half (alpha_k, x and r update, partials r.z, z.z)
 void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
                       const double *dinv, const double *p, const double *q, double *x, double *r,
                       double *partial_rz, Scalars *sc);
-void launch_cg_direction(hipStream_t s, const Tiling &t, int k, const double *partial_rz,
-                         const double *dinv, const double *r, double *p, Scalars *sc);
 void launch_epilogue(hipStream_t s, int64_t n, double t1, const double *Vold, const double *Vnew,
                      double *lat, double *lrt, Scalars *sc);
 

@@ -29,21 +29,41 @@ struct IonicParams {
     double v[16];
 };
 
+// exponential in the gate precision
+__device__ __forceinline__ double ex(double x) { return exp(x); }
+__device__ __forceinline__ float ex(float x) { return expf(x); }
+__device__ __forceinline__ double sqr_root(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqr_root(float x) { return sqrtf(x); }
+
+// Rush-Larsen step y <- y_inf + (y - y_inf) exp(-dt/tau).  In FP32 it is
+// evaluated as y + (y_inf - y) (1 - exp(-dt/tau)) with expm1: exp(-dt/tau)
+// is within 1e-4 of 1, and rounding it to FP32 would misstate the decay
+// rate by ~1e-3, an error that accumulates step after step.
+__device__ __forceinline__ double rush_larsen(double y, double y_inf, double tau, double dt)
+{
+    return y_inf - (y_inf - y) * exp(-dt / tau);
+}
+__device__ __forceinline__ float rush_larsen(float y, float y_inf, float tau, float dt)
+{
+    return y - (y_inf - y) * expm1f(-dt / tau);
+}
+
 // ---------------------------------------------------------------------------
 // Mitchell-Schaeffer: params tau_in, tau_out, tau_open, tau_close, u_gate,
 // v_rest, v_amp.  dh/dt = (1-h)/tau_open below u_gate, -h/tau_close above;
 // I_ion/Cm = -v_amp (h u^2 (1-u)/tau_in - u/tau_out).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double ms_point(const IonicParams &P, double dt, double V, double &h)
+template <typename G>
+__device__ __forceinline__ double ms_point(const IonicParams &P, double dt, double V, G &h)
 {
     const double tau_in = P.v[0], tau_out = P.v[1], tau_open = P.v[2], tau_close = P.v[3];
     const double u_gate = P.v[4], v_rest = P.v[5], v_amp = P.v[6];
     double u = (V - v_rest) / v_amp;
     bool recovering = u < u_gate;
-    double h_inf = recovering ? 1.0 : 0.0;
-    double tau = recovering ? tau_open : tau_close;
-    h = h_inf + (h - h_inf) * exp(-dt / tau);
-    return -v_amp * (h * u * u * (1.0 - u) / tau_in - u / tau_out);
+    G h_inf = recovering ? G(1) : G(0);
+    G tau = (G)(recovering ? tau_open : tau_close);
+    h = rush_larsen(h, h_inf, tau, (G)dt);
+    return -v_amp * ((double)h * u * u * (1.0 - u) / tau_in - u / tau_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -141,17 +161,89 @@ __device__ __forceinline__ Currents tt_currents(const IonicParams &P, double V, 
     return c;
 }
 
-__device__ __forceinline__ double rush_larsen(double y, double y_inf, double tau, double dt)
-{
-    return y_inf - (y_inf - y) * exp(-dt / tau);
-}
-
 __device__ __forceinline__ double sq(double x) { return x * x; }
 
-__device__ double tt_point(const IonicParams &P, double dt, double V, double *y)
+
+
+// Gating variables of the model advanced by Rush-Larsen at V^k, in precision
+// T.  g[0..11] = xr1 xr2 xs m h j d f f2 fCass s r; cass is CaSS^k.
+template <typename T>
+__device__ __forceinline__ void tt_gates(T V, T dt, T cass, T *g)
 {
+    const T one = T(1);
+    auto sqt = [](T x) { return x * x; };
+    // fast sodium m, h, j
+    T m_inf = one / sqt(one + ex((T(-56.86) - V) / T(9.03)));
+    T tau_m = (one / (one + ex((T(-60.0) - V) / T(5.0))))
+            * (T(0.1) / (one + ex((V + T(35.0)) / T(5.0))) + T(0.1) / (one + ex((V - T(50.0)) / T(200.0))));
+    T h_inf = one / sqt(one + ex((V + T(71.55)) / T(7.43)));
+    T alpha_h, beta_h, alpha_j, beta_j;
+    if (V < T(-40.0)) {
+        alpha_h = T(0.057) * ex(-(V + T(80.0)) / T(6.8));
+        beta_h = T(2.7) * ex(T(0.079) * V) + T(3.1e5) * ex(T(0.3485) * V);
+        alpha_j = (T(-25428.0) * ex(T(0.2444) * V) - T(6.948e-6) * ex(T(-0.04391) * V)) * (V + T(37.78))
+                / (one + ex(T(0.311) * (V + T(79.23))));
+        beta_j = T(0.02424) * ex(T(-0.01052) * V) / (one + ex(T(-0.1378) * (V + T(40.14))));
+    } else {
+        alpha_h = T(0.0);
+        beta_h = T(0.77) / (T(0.13) * (one + ex(-(V + T(10.66)) / T(11.1))));
+        alpha_j = T(0.0);
+        beta_j = T(0.6) * ex(T(0.057) * V) / (one + ex(T(-0.1) * (V + T(32.0))));
+    }
+    // rapid and slow delayed rectifiers
+    T xr1_inf = one / (one + ex((T(-26.0) - V) / T(7.0)));
+    T tau_xr1 = (T(450.0) / (one + ex((T(-45.0) - V) / T(10.0)))) * (T(6.0) / (one + ex((V + T(30.0)) / T(11.5))));
+    T xr2_inf = one / (one + ex((V + T(88.0)) / T(24.0)));
+    T tau_xr2 = (T(3.0) / (one + ex((T(-60.0) - V) / T(20.0)))) * (T(1.12) / (one + ex((V - T(60.0)) / T(20.0))));
+    T xs_inf = one / (one + ex((T(-5.0) - V) / T(14.0)));
+    T tau_xs = (T(1400.0) / sqr_root(one + ex((T(5.0) - V) / T(6.0)))) * (one / (one + ex((V - T(35.0)) / T(15.0))))
+             + T(80.0);
+    // transient outward r, s (endocardial s)
+    T r_inf = one / (one + ex((T(20.0) - V) / T(6.0)));
+    T tau_r = T(9.5) * ex(-sqt(V + T(40.0)) / T(1800.0)) + T(0.8);
+    T s_inf = one / (one + ex((V + T(28.0)) / T(5.0)));
+    T tau_s = T(1000.0) * ex(-sqt(V + T(67.0)) / T(1000.0)) + T(8.0);
+    // L-type calcium d, f, f2, fCass
+    T d_inf = one / (one + ex((T(-8.0) - V) / T(7.5)));
+    T tau_d = (T(1.4) / (one + ex((T(-35.0) - V) / T(13.0))) + T(0.25)) * (T(1.4) / (one + ex((V + T(5.0)) / T(5.0))))
+            + one / (one + ex((T(50.0) - V) / T(20.0)));
+    T f_inf = one / (one + ex((V + T(20.0)) / T(7.0)));
+    T tau_f = T(1102.5) * ex(-sqt(V + T(27.0)) / T(225.0)) + T(200.0) / (one + ex((T(13.0) - V) / T(10.0)))
+            + T(180.0) / (one + ex((V + T(30.0)) / T(10.0))) + T(20.0);
+    T f2_inf = T(0.67) / (one + ex((V + T(35.0)) / T(7.0))) + T(0.33);
+    T tau_f2 = T(562.0) * ex(-sqt(V + T(27.0)) / T(240.0)) + T(31.0) / (one + ex((T(25.0) - V) / T(10.0)))
+             + T(80.0) / (one + ex((V + T(30.0)) / T(10.0)));
+    T cass_ratio2 = sqt(cass / T(0.05));
+    T fcass_inf = T(0.6) / (one + cass_ratio2) + T(0.4);
+    T tau_fcass = T(80.0) / (one + cass_ratio2) + T(2.0);
+
+    g[0] = rush_larsen(g[0], xr1_inf, tau_xr1, dt);
+    g[1] = rush_larsen(g[1], xr2_inf, tau_xr2, dt);
+    g[2] = rush_larsen(g[2], xs_inf, tau_xs, dt);
+    g[3] = rush_larsen(g[3], m_inf, tau_m, dt);
+    g[4] = rush_larsen(g[4], h_inf, one / (alpha_h + beta_h), dt);
+    g[5] = rush_larsen(g[5], h_inf, one / (alpha_j + beta_j), dt);
+    g[6] = rush_larsen(g[6], d_inf, tau_d, dt);
+    g[7] = rush_larsen(g[7], f_inf, tau_f, dt);
+    g[8] = rush_larsen(g[8], f2_inf, tau_f2, dt);
+    g[9] = rush_larsen(g[9], fcass_inf, tau_fcass, dt);
+    g[10] = rush_larsen(g[10], s_inf, tau_s, dt);
+    g[11] = rush_larsen(g[11], r_inf, tau_r, dt);
+}
+
+// One step of the model at one node: concentration-type states c[0..5]
+// (Ki Nai Cai CaSR CaSS Rbar) by forward Euler in FP64, gates g[0..11] by
+// Rush-Larsen in precision G; returns I_ion(V^k, u^{k+1}) / Cm in FP64.
+template <typename G>
+__device__ double tt_point(const IonicParams &P, double dt, double V, double *c, G *g)
+{
+    double y[TT_NS];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) y[s] = c[s];
+#pragma unroll
+    for (int s = 0; s < 12; ++s) y[6 + s] = (double)g[s];
     const VOnly vo = v_only(V);
-    const Currents c = tt_currents(P, V, vo, y);
+    const Currents cur = tt_currents(P, V, vo, y);
 
     // ---- calcium subsystem and ion concentrations: rates at (V^k, u^k) ----
     const double cai = y[CAI], casr = y[CASR], cass = y[CASS], rbar = y[RBAR];
@@ -168,80 +260,29 @@ __device__ double tt_point(const IonicParams &P, double dt, double V, double *y)
     double buf_ss = 1.0 / (1.0 + BUF_SS * KBUF_SS / sq(cass + KBUF_SS));
     double d_rbar = -k2 * cass * rbar + K4 * (1.0 - rbar);
     double d_cai = buf_c * ((i_leak - i_up) * VOLSR / VOLC + i_xfer
-                            - (c.ibCa + c.ipCa - 2.0 * c.iNaCa) * CAPAC / (2.0 * VOLC * Far));
+                            - (cur.ibCa + cur.ipCa - 2.0 * cur.iNaCa) * CAPAC / (2.0 * VOLC * Far));
     double d_casr = buf_sr * (i_up - i_rel - i_leak);
-    double d_cass = buf_ss * (-c.iCaL * CAPAC / (2.0 * VOLSS * Far) + i_rel * VOLSR / VOLSS
+    double d_cass = buf_ss * (-cur.iCaL * CAPAC / (2.0 * VOLSS * Far) + i_rel * VOLSR / VOLSS
                               - i_xfer * VOLC / VOLSS);
-    double d_nai = -(c.iNa + c.ibNa + 3.0 * c.iNaK + 3.0 * c.iNaCa) * CAPAC / (VOLC * Far);
-    double d_ki = -(c.iK1 + c.ito + c.iKr + c.iKs - 2.0 * c.iNaK + c.ipK) * CAPAC / (VOLC * Far);
+    double d_nai = -(cur.iNa + cur.ibNa + 3.0 * cur.iNaK + 3.0 * cur.iNaCa) * CAPAC / (VOLC * Far);
+    double d_ki = -(cur.iK1 + cur.ito + cur.iKr + cur.iKs - 2.0 * cur.iNaK + cur.ipK) * CAPAC / (VOLC * Far);
 
     // ---- gating variables at V^k ----
-    // fast sodium m, h, j
-    double m_inf = 1.0 / sq(1.0 + exp((-56.86 - V) / 9.03));
-    double tau_m = (1.0 / (1.0 + exp((-60.0 - V) / 5.0)))
-                 * (0.1 / (1.0 + exp((V + 35.0) / 5.0)) + 0.1 / (1.0 + exp((V - 50.0) / 200.0)));
-    double h_inf = 1.0 / sq(1.0 + exp((V + 71.55) / 7.43));
-    double alpha_h, beta_h, alpha_j, beta_j;
-    if (V < -40.0) {
-        alpha_h = 0.057 * exp(-(V + 80.0) / 6.8);
-        beta_h = 2.7 * exp(0.079 * V) + 3.1e5 * exp(0.3485 * V);
-        alpha_j = (-25428.0 * exp(0.2444 * V) - 6.948e-6 * exp(-0.04391 * V)) * (V + 37.78)
-                / (1.0 + exp(0.311 * (V + 79.23)));
-        beta_j = 0.02424 * exp(-0.01052 * V) / (1.0 + exp(-0.1378 * (V + 40.14)));
-    } else {
-        alpha_h = 0.0;
-        beta_h = 0.77 / (0.13 * (1.0 + exp(-(V + 10.66) / 11.1)));
-        alpha_j = 0.0;
-        beta_j = 0.6 * exp(0.057 * V) / (1.0 + exp(-0.1 * (V + 32.0)));
-    }
-    // rapid and slow delayed rectifiers
-    double xr1_inf = 1.0 / (1.0 + exp((-26.0 - V) / 7.0));
-    double tau_xr1 = (450.0 / (1.0 + exp((-45.0 - V) / 10.0))) * (6.0 / (1.0 + exp((V + 30.0) / 11.5)));
-    double xr2_inf = 1.0 / (1.0 + exp((V + 88.0) / 24.0));
-    double tau_xr2 = (3.0 / (1.0 + exp((-60.0 - V) / 20.0))) * (1.12 / (1.0 + exp((V - 60.0) / 20.0)));
-    double xs_inf = 1.0 / (1.0 + exp((-5.0 - V) / 14.0));
-    double tau_xs = (1400.0 / sqrt(1.0 + exp((5.0 - V) / 6.0))) * (1.0 / (1.0 + exp((V - 35.0) / 15.0)))
-                  + 80.0;
-    // transient outward r, s (endocardial s)
-    double r_inf = 1.0 / (1.0 + exp((20.0 - V) / 6.0));
-    double tau_r = 9.5 * exp(-sq(V + 40.0) / 1800.0) + 0.8;
-    double s_inf = 1.0 / (1.0 + exp((V + 28.0) / 5.0));
-    double tau_s = 1000.0 * exp(-sq(V + 67.0) / 1000.0) + 8.0;
-    // L-type calcium d, f, f2, fCass
-    double d_inf = 1.0 / (1.0 + exp((-8.0 - V) / 7.5));
-    double tau_d = (1.4 / (1.0 + exp((-35.0 - V) / 13.0)) + 0.25) * (1.4 / (1.0 + exp((V + 5.0) / 5.0)))
-                 + 1.0 / (1.0 + exp((50.0 - V) / 20.0));
-    double f_inf = 1.0 / (1.0 + exp((V + 20.0) / 7.0));
-    double tau_f = 1102.5 * exp(-sq(V + 27.0) / 225.0) + 200.0 / (1.0 + exp((13.0 - V) / 10.0))
-                 + 180.0 / (1.0 + exp((V + 30.0) / 10.0)) + 20.0;
-    double f2_inf = 0.67 / (1.0 + exp((V + 35.0) / 7.0)) + 0.33;
-    double tau_f2 = 562.0 * exp(-sq(V + 27.0) / 240.0) + 31.0 / (1.0 + exp((25.0 - V) / 10.0))
-                  + 80.0 / (1.0 + exp((V + 30.0) / 10.0));
-    double cass_ratio2 = sq(cass / 0.05);
-    double fcass_inf = 0.6 / (1.0 + cass_ratio2) + 0.4;
-    double tau_fcass = 80.0 / (1.0 + cass_ratio2) + 2.0;
+    tt_gates<G>((G)V, (G)dt, (G)cass, g);
 
-    // ---- advance ----
-    y[KI] = y[KI] + dt * d_ki;
-    y[NAI] = y[NAI] + dt * d_nai;
-    y[CAI] = cai + dt * d_cai;
-    y[CASR] = casr + dt * d_casr;
-    y[CASS] = cass + dt * d_cass;
-    y[RBAR] = rbar + dt * d_rbar;
-    y[XR1] = rush_larsen(y[XR1], xr1_inf, tau_xr1, dt);
-    y[XR2] = rush_larsen(y[XR2], xr2_inf, tau_xr2, dt);
-    y[XS] = rush_larsen(y[XS], xs_inf, tau_xs, dt);
-    y[MG] = rush_larsen(y[MG], m_inf, tau_m, dt);
-    y[HG] = rush_larsen(y[HG], h_inf, 1.0 / (alpha_h + beta_h), dt);
-    y[JG] = rush_larsen(y[JG], h_inf, 1.0 / (alpha_j + beta_j), dt);
-    y[DG] = rush_larsen(y[DG], d_inf, tau_d, dt);
-    y[FG] = rush_larsen(y[FG], f_inf, tau_f, dt);
-    y[F2G] = rush_larsen(y[F2G], f2_inf, tau_f2, dt);
-    y[FCASS] = rush_larsen(y[FCASS], fcass_inf, tau_fcass, dt);
-    y[SG] = rush_larsen(y[SG], s_inf, tau_s, dt);
-    y[RG] = rush_larsen(y[RG], r_inf, tau_r, dt);
+    // ---- forward Euler for the concentration-type states ----
+    c[KI] = c[KI] + dt * d_ki;
+    c[NAI] = c[NAI] + dt * d_nai;
+    c[CAI] = cai + dt * d_cai;
+    c[CASR] = casr + dt * d_casr;
+    c[CASS] = cass + dt * d_cass;
+    c[RBAR] = rbar + dt * d_rbar;
 
     // ---- I_ion(V^k, u^{k+1}) ----
+#pragma unroll
+    for (int s = 0; s < 6; ++s) y[s] = c[s];
+#pragma unroll
+    for (int s = 0; s < 12; ++s) y[6 + s] = (double)g[s];
     return tt_currents(P, V, vo, y).total();
 }
 
@@ -259,15 +300,19 @@ __global__ __launch_bounds__(256) void k_ionic_step(IonicParams P, int64_t n, in
     double iion = 0.0;
     if constexpr (KIND == MDX_KIND_MS) {
         double h = u[i];
-        iion = ms_point(P, dt, v, h);
+        iion = ms_point<double>(P, dt, v, h);
         u[i] = h;
     } else if constexpr (KIND == MDX_KIND_TT) {
-        double y[TT_NS];
+        double c[6], g[12];
 #pragma unroll
-        for (int s = 0; s < TT_NS; ++s) y[s] = u[s * ld + i];
-        iion = tt_point(P, dt, v, y);
+        for (int s = 0; s < 6; ++s) c[s] = u[s * ld + i];
 #pragma unroll
-        for (int s = 0; s < TT_NS; ++s) u[s * ld + i] = y[s];
+        for (int s = 0; s < 12; ++s) g[s] = u[(6 + s) * ld + i];
+        iion = tt_point<double>(P, dt, v, c, g);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) u[s * ld + i] = c[s];
+#pragma unroll
+        for (int s = 0; s < 12; ++s) u[(6 + s) * ld + i] = g[s];
     }
     if (raw)
         out[i] = iion;
@@ -295,6 +340,60 @@ __global__ __launch_bounds__(256) void k_ionic_init(IonicParams P, int64_t n, in
     }
     V[i] = real ? v0 : 0.0;
     Vprev[i] = real ? v0 : 0.0;
+}
+
+// Mixed-precision form: gating variables stored and advanced in FP32
+// (g32[s * ld + i], s over the model's gates), concentration-type states and
+// the current in FP64 (u[s * ld + i], rows 0..5 for the ten Tusscher-Panfilov
+// model; Mitchell-Schaeffer has only its gate h).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_ionic_step_mixed(IonicParams P, int64_t n, int64_t ld,
+                                                          double dt, double cm,
+                                                          const double *__restrict__ V,
+                                                          double *__restrict__ u,
+                                                          float *__restrict__ g32,
+                                                          const double *__restrict__ istim,
+                                                          double *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = V[i];
+    double iion = 0.0;
+    if constexpr (KIND == MDX_KIND_MS) {
+        float h = g32[i];
+        iion = ms_point<float>(P, dt, v, h);
+        g32[i] = h;
+    } else if constexpr (KIND == MDX_KIND_TT) {
+        double c[6];
+        float g[12];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) c[s] = u[s * ld + i];
+#pragma unroll
+        for (int s = 0; s < 12; ++s) g[s] = g32[s * ld + i];
+        iion = tt_point<float>(P, dt, v, c, g);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) u[s * ld + i] = c[s];
+#pragma unroll
+        for (int s = 0; s < 12; ++s) g32[s * ld + i] = g[s];
+    }
+    out[i] = (istim ? istim[i] : 0.0) - cm * iion;
+}
+
+// copy rows [row0, row0 + rows) of an FP64 SoA state block to FP32 or back
+__global__ __launch_bounds__(256) void k_rows_to_f32(int64_t ld, int rows, const double *__restrict__ src,
+                                                     float *__restrict__ dst)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ld * rows) return;
+    dst[i] = (float)src[i];
+}
+
+__global__ __launch_bounds__(256) void k_rows_to_f64(int64_t ld, int rows, const float *__restrict__ src,
+                                                     double *__restrict__ dst)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ld * rows) return;
+    dst[i] = (double)src[i];
 }
 
 IonicParams pack(int kind, const double *params)
@@ -350,6 +449,45 @@ void launch_ionic_step(hipStream_t s, int kind, const double *params, int64_t n,
     else
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
                            istim, out, raw);
+}
+
+int ionic_gate_rows(int kind) { return kind == 1 ? 1 : kind == 2 ? 12 : 0; }
+int ionic_gate_row0(int kind) { return kind == 1 ? 0 : kind == 2 ? 6 : 0; }
+
+void launch_ionic_step_mixed(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
+                             double dt, double cm, const double *V, double *u, float *g32,
+                             const double *istim, double *out)
+{
+    if (n <= 0) return;
+    IonicParams P = pack(kind, params);
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (kind == 1)
+        hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, dt, cm, V,
+                           u, g32, istim, out);
+    else if (kind == 2)
+        hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, dt, cm, V,
+                           u, g32, istim, out);
+    else
+        hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, dt, cm,
+                           V, u, g32, istim, out);
+}
+
+void launch_gates_to_f32(hipStream_t s, int kind, int64_t ld, const double *u, float *g32)
+{
+    const int rows = ionic_gate_rows(kind);
+    if (rows == 0) return;
+    const int64_t cnt = ld * rows;
+    hipLaunchKernelGGL(k_rows_to_f32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ld, rows,
+                       u + (int64_t)ionic_gate_row0(kind) * ld, g32);
+}
+
+void launch_gates_to_f64(hipStream_t s, int kind, int64_t ld, const float *g32, double *u)
+{
+    const int rows = ionic_gate_rows(kind);
+    if (rows == 0) return;
+    const int64_t cnt = ld * rows;
+    hipLaunchKernelGGL(k_rows_to_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ld, rows,
+                       g32, u + (int64_t)ionic_gate_row0(kind) * ld);
 }
 
 }  // namespace mdx

@@ -8,12 +8,14 @@
 //                 per-workgroup partials of r.z, z.z, |D^-1 b|^2
 //   init_finalize rho_0, ||z_0||, the stopping reference, done if z_0 is at the
 //                 rounding floor
-//   per iteration k:
-//   spmv_dot      q = A p, partial p.q
-//   cg_update     alpha = rho_k / p.q; x += alpha p; r -= alpha q; z = D^-1 r;
-//                 partials r.z, z.z
-//   cg_direction  ||z||; stop if ||z|| < atol, ||z|| < rtol * ref or at the
-//                 floor; else beta = r.z / rho_k, p = z + beta p
+//   per iteration k (two kernels):
+//   cg_direction_spmv  (k >= 1) ||z_k||; stop if ||z_k|| < atol, < rtol * ref
+//                 or at the floor; beta_k = rho_k / rho_{k-1};
+//                 q = A p_k with p_k = z_k + beta_k p_{k-1} formed per gathered
+//                 column; partial p_k . q
+//   cg_update     alpha = rho_k / p_k.q; x += alpha p_k; r -= alpha q;
+//                 z = D^-1 r; partials r.z, z.z
+//   spmv_dot      plain q = A p with partial p.q (inspection entry point)
 //   epilogue      activation / repolarisation times, non-finite check
 //
 // Matrix traversal: sliced ELL (see mdx_internal.h); one lane per row, so the
@@ -27,6 +29,7 @@
 // -> one partial per workgroup.  Consumers re-reduce all partials in a fixed
 // order in every workgroup, so scalars are bitwise identical everywhere and
 // runs are deterministic; no atomics, no grid-wide synchronisation.
+#include "mdx_device.h"
 #include "mdx_internal.h"
 
 #include <hip/hip_ext.h>
@@ -48,65 +51,6 @@ Tiling make_tiling(int64_t n_rows_padded, int max_groups)
 
 namespace {
 
-// Hardware dispatches workgroup i to XCD i % 8; return the logical workgroup
-// so that XCD x owns the contiguous logical range of its share.
-__device__ __forceinline__ int logical_group(int nb)
-{
-    int i = blockIdx.x;
-    int x = i % NXCD, j = i / NXCD;
-    int q = nb / NXCD, rem = nb % NXCD;
-    return x * q + min(x, rem) + j;
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Sum NV values over the 256 threads of the workgroup; the totals are
-// returned to every thread.
-template <int NV>
-__device__ __forceinline__ void group_sum(double (&v)[NV])
-{
-    __shared__ double lds[4][NV];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = wave_sum(v[k]);
-        if (lane == 0) lds[w][k] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
-    __syncthreads();
-}
-
-// Every workgroup reduces the `groups` partials of a producer kernel, laid
-// out partial[k * groups + g], in the same order.
-template <int NV>
-__device__ __forceinline__ void reduce_partials(const double *__restrict__ partial, int groups,
-                                                double (&v)[NV])
-{
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = threadIdx.x; g < groups; g += TILE)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += partial[k * groups + g];
-    group_sum<NV>(v);
-}
-
-template <int NV>
-__device__ __forceinline__ void write_partials(double (&v)[NV], double *__restrict__ partial,
-                                               int groups, int g)
-{
-    group_sum<NV>(v);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) partial[k * groups + g] = v[k];
-}
-
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fill(int64_t n, double v, double *__restrict__ x)
 {
@@ -126,7 +70,7 @@ __global__ __launch_bounds__(256) void k_rhs_init(
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
     StepParams sp, const double *__restrict__ V, const double *__restrict__ Vprev,
     const double *__restrict__ src, double *__restrict__ x, double *__restrict__ r,
-    double *__restrict__ p, double *__restrict__ b, double *__restrict__ partial)
+    double *__restrict__ b, double *__restrict__ partial)
 {
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
@@ -160,7 +104,6 @@ __global__ __launch_bounds__(256) void k_rhs_init(
         const double zi = di * ri;
         x[row] = x0i;
         r[row] = ri;
-        p[row] = zi;
         b[row] = bi;
         acc[0] += ri * zi;
         acc[1] += zi * zi;
@@ -184,6 +127,9 @@ __global__ __launch_bounds__(256) void k_init_finalize(int groups, const double 
         sc->floor_ = 1e-15 * db;
         sc->done = (z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
         sc->iters = 0;
+        sc->replace = 0;
+        sc->redirect = 0;
+        sc->it_next = 0;
     }
 }
 
@@ -213,6 +159,83 @@ __global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__res
     write_partials<1>(acc, partial, t.groups, g);
 }
 
+// Iteration k, first half.  For k >= 1 every workgroup reduces the r.z and
+// z.z partials of the previous update, applies the stopping test to
+// ||z_k|| (Algorithm 1, with z formed before the test), and forms
+// beta_k = rho_k / rho_{k-1}.  Then q = A p_k, where the direction
+// p_k = D^-1 r_k + beta_k p_{k-1} (p_0 = z_0) is formed on the fly for every
+// gathered column, so no separate direction pass is needed; own rows store
+// p_k (double-buffered against p_{k-1}) and a partial of p_k . q.
+// k == max_iter only tests.
+__global__ __launch_bounds__(256) void k_cg_direction_spmv(
+    Tiling t, int k, int max_iter, const int64_t *__restrict__ slice_ptr,
+    const int32_t *__restrict__ col, const double *__restrict__ Av,
+    const double *__restrict__ dinv, const double *__restrict__ r,
+    const double *__restrict__ p_prev, double *__restrict__ p_cur, double *__restrict__ q,
+    const double *__restrict__ partial_rz, double *__restrict__ partial_pq,
+    Scalars *__restrict__ sc)
+{
+    if (sc->done) return;
+    double beta = 0.0;
+    if (k > 0) {
+        double v[2];
+        reduce_partials<2>(partial_rz, t.groups, v);
+        const double zn = sqrt(v[1]);
+        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+        if (!(zn == zn)) {   // NaN: stop the solve and flag it
+            if (lead) {
+                sc->nonfinite = 2;
+                sc->done = 1;
+                sc->iters = k;
+                sc->znorm = zn;
+            }
+            return;
+        }
+        if (zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_) {
+            if (lead) {
+                sc->done = 1;
+                sc->iters = k;
+                sc->znorm = zn;
+            }
+            return;
+        }
+        if (lead) sc->znorm = zn;
+        if (k >= max_iter) return;   // cap reached: the host reports no convergence
+        beta = v[0] / sc->rho[(k - 1) & 1];
+        if (lead) sc->rho[k & 1] = v[0];
+    }
+    const int g = logical_group(t.groups);
+    const int lane = threadIdx.x & (SLICE - 1);
+    double acc[1] = {0.0};
+    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
+    for (int tile = g * t.tpb; tile < t_end; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        double sum = 0.0;
+        if (k == 0) {
+#pragma unroll 4
+            for (int64_t e = beg; e < end; e += SLICE) {
+                const int32_t c = col[e];
+                sum += Av[e] * (dinv[c] * r[c]);
+            }
+        } else {
+#pragma unroll 4
+            for (int64_t e = beg; e < end; e += SLICE) {
+                const int32_t c = col[e];
+                sum += Av[e] * (dinv[c] * r[c] + beta * p_prev[c]);
+            }
+        }
+        const double pi = k == 0 ? dinv[row] * r[row] : dinv[row] * r[row] + beta * p_prev[row];
+        p_cur[row] = pi;
+        q[row] = sum;
+        acc[0] += pi * sum;
+    }
+    write_partials<1>(acc, partial_pq, t.groups, g);
+}
+
+// Iteration k, second half: alpha_k = rho_k / (p_k . q); x += alpha p_k;
+// r -= alpha q; z = D^-1 r; partials r.z and z.z for the next test.
 __global__ __launch_bounds__(256) void k_cg_update(Tiling t, int k,
                                                    const double *__restrict__ partial_pq,
                                                    const double *__restrict__ dinv,
@@ -241,6 +264,9 @@ __global__ __launch_bounds__(256) void k_cg_update(Tiling t, int k,
     write_partials<2>(acc, partial_rz, t.groups, g);
 }
 
+// Three-kernel scheme, last kernel of iteration k: stopping test on
+// ||z_{k+1}||, beta = rho_{k+1} / rho_k, p = z + beta p in place (p and the
+// SpMV input are the same buffer).  Used with k_spmv_dot + k_cg_update.
 __global__ __launch_bounds__(256) void k_cg_direction(Tiling t, int k,
                                                       const double *__restrict__ partial_rz,
                                                       const double *__restrict__ dinv,
@@ -253,7 +279,7 @@ __global__ __launch_bounds__(256) void k_cg_direction(Tiling t, int k,
     reduce_partials<2>(partial_rz, t.groups, v);
     const double zn = sqrt(v[1]);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (!(zn == zn)) {   // NaN: stop the solve, flag it
+    if (!(zn == zn)) {
         if (lead) {
             sc->nonfinite = 2;
             sc->done = 1;
@@ -281,6 +307,17 @@ __global__ __launch_bounds__(256) void k_cg_direction(Tiling t, int k,
         const int64_t i = (int64_t)tile * TILE + threadIdx.x;
         p[i] = dinv[i] * r[i] + beta * p[i];
     }
+}
+
+// z_0 -> p (three-kernel scheme starts from p_0 = z_0)
+__global__ __launch_bounds__(256) void k_set_direction(int64_t n, const double *__restrict__ dinv,
+                                                       const double *__restrict__ r,
+                                                       double *__restrict__ p,
+                                                       const Scalars *__restrict__ sc)
+{
+    if (sc->done) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = dinv[i] * r[i];
 }
 
 __global__ __launch_bounds__(256) void k_epilogue(int64_t n, double t1, const double *__restrict__ Vold,
@@ -318,11 +355,11 @@ void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double am
 
 void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                      const double *Kv, const double *dinv, const StepParams &sp, const double *V,
-                     const double *Vprev, const double *src, double *x, double *r, double *p,
-                     double *b, double *partial)
+                     const double *Vprev, const double *src, double *x, double *r, double *b,
+                     double *partial)
 {
     hipLaunchKernelGGL(k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
-                       dinv, sp, V, Vprev, src, x, r, p, b, partial);
+                       dinv, sp, V, Vprev, src, x, r, b, partial);
 }
 
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
@@ -343,6 +380,22 @@ void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *A
                            p, q, partial, done);
 }
 
+void launch_cg_direction_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
+                              const double *Av, const double *dinv, const double *r,
+                              const double *p_prev, double *p_cur, double *q,
+                              const double *partial_rz, double *partial_pq, Scalars *sc,
+                              hipEvent_t ev_start, hipEvent_t ev_stop)
+{
+    if (ev_start)
+        hipExtLaunchKernelGGL(k_cg_direction_spmv, dim3(t.groups), dim3(TILE), 0, s, ev_start,
+                              ev_stop, 0, t, k, max_iter, P.slice_ptr, P.col, Av, dinv, r, p_prev,
+                              p_cur, q, partial_rz, partial_pq, sc);
+    else
+        hipLaunchKernelGGL(k_cg_direction_spmv, dim3(t.groups), dim3(TILE), 0, s, t, k, max_iter,
+                           P.slice_ptr, P.col, Av, dinv, r, p_prev, p_cur, q, partial_rz,
+                           partial_pq, sc);
+}
+
 void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
                       const double *dinv, const double *p, const double *q, double *x, double *r,
                       double *partial_rz, Scalars *sc)
@@ -356,6 +409,12 @@ void launch_cg_direction(hipStream_t s, const Tiling &t, int k, const double *pa
 {
     hipLaunchKernelGGL(k_cg_direction, dim3(t.groups), dim3(TILE), 0, s, t, k, partial_rz, dinv, r,
                        p, sc);
+}
+
+void launch_set_direction(hipStream_t s, int64_t n, const double *dinv, const double *r, double *p,
+                          const Scalars *sc)
+{
+    hipLaunchKernelGGL(k_set_direction, dim3(blocks_for(n)), dim3(256), 0, s, n, dinv, r, p, sc);
 }
 
 void launch_epilogue(hipStream_t s, int64_t n, double t1, const double *Vold, const double *Vnew,

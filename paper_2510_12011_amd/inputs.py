@@ -152,6 +152,8 @@ class RunSpec:
     max_iter: int = 1000
     warm_start: int = 1        # 0: previous step; 1: 2V^k - V^{k-1}
     out_every: int = 100       # snapshot interval in steps
+    precision: str = "fp64"    # "fp64" | "mixed"
+    rr_interval: int = 50      # mixed: residual replacement interval
 
     def sigma_per_tet(self):
         m = self.mesh.n_tets
@@ -199,3 +201,13 @@ def small_box(nx=6, ny=5, nz=4, lx=1.2, ly=1.0, lz=0.8, jitter=0.05, seed=3,
     return RunSpec(name=f"box_{nx}x{ny}x{nz}", mesh=mesh, sigma_l=sigma_l,
                    sigma_t=sigma_t, chi=140.0, cm=0.01, theta=theta, ionic=ionic,
                    dt=dt, n_steps=n_steps, stimuli=[stim], rtol=rtol)
+
+
+def slab_precision(h: float = 0.05, n_steps: int = 10000, precision: str = "mixed") -> RunSpec:
+    """The slab at h (default 0.05 mm: 401 x 141 x 61 = 3,449,001 nodes) for the
+    mixed-precision form: relative tolerance 1e-8 against ||D^-1 b||, FP64
+    residual replacement every 50 iterations and at convergence."""
+    sp = slab(h=h, n_steps=n_steps, rtol=1e-8, rel_mode=1)
+    sp.precision = precision
+    sp.name = f"slab_h{h:g}_{precision}"
+    return sp

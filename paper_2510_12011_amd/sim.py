@@ -28,6 +28,8 @@ def _dptr(t):
 
 
 IONIC = {"none": L.MDX_IONIC_NONE, "ms": L.MDX_IONIC_MS, "tt": L.MDX_IONIC_TT}
+PRECISION = {"fp64": L.MDX_PREC_FP64, "mixed": L.MDX_PREC_MIXED,
+             "mixed_gates32": L.MDX_PREC_MIXED_GATES32}
 
 
 class Simulation:
@@ -97,8 +99,9 @@ class Simulation:
         self._check(L.lib().mdx_add_stimulus(self._h, idx.shape[0], _ptr(idx), start, duration,
                                              intensity))
 
-    def set_solver(self, atol=0.0, rtol=1e-10, rel_mode=0, max_iter=1000, warm_start=1):
-        o = L.SolverOpts(atol, rtol, rel_mode, max_iter, warm_start, 0)
+    def set_solver(self, atol=0.0, rtol=1e-10, rel_mode=0, max_iter=1000, warm_start=1,
+                   precision=0, rr_interval=50):
+        o = L.SolverOpts(atol, rtol, rel_mode, max_iter, warm_start, precision, rr_interval, 0)
         self._check(L.lib().mdx_set_solver(self._h, C.byref(o)))
 
     # -- device memory and setup ----------------------------------------
@@ -145,8 +148,15 @@ class Simulation:
         self._check(L.lib().mdx_get_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in L.Stats._fields_}
 
-    def set_profiling(self, enable=True):
-        self._check(L.lib().mdx_set_profiling(self._h, 1 if enable else 0))
+    def set_tuning(self, max_groups=None, iter_scheme=None):
+        if max_groups is not None:
+            self._check(L.lib().mdx_set_tuning(self._h, L.MDX_TUNE_MAX_GROUPS, int(max_groups)))
+        if iter_scheme is not None:
+            self._check(L.lib().mdx_set_tuning(self._h, L.MDX_TUNE_ITER_SCHEME, int(iter_scheme)))
+
+    def set_profiling(self, every_n=1):
+        """Time the SpMV launches of every every_n-th step (0: off)."""
+        self._check(L.lib().mdx_set_profiling(self._h, int(every_n)))
 
     def get_state(self):
         V, Vp = np.zeros(self.n), np.zeros(self.n)
@@ -194,8 +204,10 @@ class Simulation:
         return iion
 
 
-def from_spec(spec, device: int = 0, ionic_params=None, prepare=True) -> Simulation:
-    """Build a Simulation from an inputs.RunSpec."""
+def from_spec(spec, device: int = 0, ionic_params=None, prepare=True,
+              precision: str | None = None) -> Simulation:
+    """Build a Simulation from an inputs.RunSpec (precision: 'fp64' or
+    'mixed'; default: the spec's)."""
     sim = Simulation(device)
     m = spec.mesh
     sim.set_mesh(m.xyz, m.tets, m.region, m.fibre)
@@ -204,7 +216,9 @@ def from_spec(spec, device: int = 0, ionic_params=None, prepare=True) -> Simulat
     sim.set_ionic(spec.ionic, ionic_params)
     for s in spec.stimuli:
         sim.add_stimulus(s.nodes, s.start, s.duration, s.intensity)
-    sim.set_solver(spec.atol, spec.rtol, spec.rel_mode, spec.max_iter, spec.warm_start)
+    prec = precision if precision is not None else getattr(spec, "precision", "fp64")
+    sim.set_solver(spec.atol, spec.rtol, spec.rel_mode, spec.max_iter, spec.warm_start,
+                   PRECISION[prec], getattr(spec, "rr_interval", 50))
     if prepare:
         sim.prepare(spec.dt)
     return sim

@@ -1,0 +1,136 @@
+"""Mixed-precision form (FP32 SpMV and vectors, FP64 dots, FP64 residual
+replacement, FP32 gates / FP64 concentrations) against the FP64 oracle and
+the FP64 GPU path.  Bar: V relative L2 <= 1e-5 at every snapshot, activation
+times within one time step."""
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_2510_12011_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+V_REL_L2 = 1e-5
+
+
+def _sim(spec, precision):
+    from paper_2510_12011_amd import sim
+    print(f"[case] {spec.name} n={spec.mesh.n_nodes} ionic={spec.ionic} {precision}", flush=True)
+    return sim.from_spec(spec, precision=precision)
+
+
+def _rel_l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _lat_check(lat_a, lat_b, dt):
+    fa, fb = np.isfinite(lat_a), np.isfinite(lat_b)
+    # a node at the threshold may flip by one step; never a missing activation
+    # far from the threshold
+    both = fa & fb
+    assert (fa != fb).sum() <= max(2, 1e-4 * lat_a.size)
+    if both.any():
+        assert abs(lat_a[both] - lat_b[both]).max() <= dt * (1 + 1e-9)
+
+
+def _rhs_relative(spec, rtol=1e-8):
+    spec.rtol, spec.rel_mode = rtol, 1
+    return spec
+
+
+@pytest.mark.parametrize("spec_fn,steps,every", [
+    (lambda: inputs.tiny_cube(), 500, 100),
+    (lambda: inputs.small_box(nx=10, ny=8, nz=6, ionic="tt", n_steps=400, stim_extent=0.5), 400, 50),
+    (lambda: inputs.slab(h=0.5, n_steps=5000), 5000, 500),
+])
+def test_mixed_vs_oracle(spec_fn, steps, every):
+    spec = _rhs_relative(spec_fn())
+    s = _sim(spec, "mixed")
+    o = orc.Oracle(spec)
+    v_or, it_or = o.steps(steps, out_every=every)
+    v_gpu, status = s.run(steps, every)
+    assert status == 0
+    errs = [_rel_l2(a, b) for a, b in zip(v_gpu, v_or)]
+    print(f"  mixed vs oracle: V rel L2 max {max(errs):.2e}", flush=True)
+    assert max(errs) <= V_REL_L2, errs
+    lat, _ = s.times()
+    _lat_check(lat, o.state.lat, spec.dt)
+    it_gpu = s.iterations(steps)
+    assert (it_gpu >= 0).all()
+
+
+def test_mixed_replacement_interval():
+    """A replacement interval shorter than the iteration count exercises the
+    continue-after-replacement branch; results stay within the bar."""
+    spec = _rhs_relative(inputs.small_box(nx=8, ny=6, nz=5, ionic="ms", n_steps=200))
+    spec.rtol = 1e-12
+    spec.rr_interval = 3
+    s = _sim(spec, "mixed")
+    o = orc.Oracle(spec)
+    v_or, _ = o.steps(200, out_every=50)
+    v_gpu, status = s.run(200, 50)
+    assert status == 0
+    assert max(_rel_l2(a, b) for a, b in zip(v_gpu, v_or)) <= V_REL_L2
+
+
+def test_mixed_vs_fp64_slab_full_length():
+    """Slab h = 0.1 mm (442,401 nodes), 100 ms: mixed vs the FP64 GPU path
+    (itself checked against the oracle), same tolerance (1e-8 of ||D^-1 b||)."""
+    spec = _rhs_relative(inputs.slab(h=0.1))
+    a = _sim(spec, "fp64")
+    va, _ = a.run(10000, 1000)
+    lat_a, _ = a.times()
+    del a
+    b = _sim(spec, "mixed")
+    vb, _ = b.run(10000, 1000)
+    lat_b, _ = b.times()
+    errs = [_rel_l2(x, y) for x, y in zip(vb, va)]
+    print(f"  mixed vs fp64: V rel L2 max {max(errs):.2e}", flush=True)
+    assert max(errs) <= V_REL_L2, errs
+    _lat_check(lat_b, lat_a, spec.dt)
+    assert np.isfinite(lat_a).mean() > 0.99
+
+
+def test_precision_workload_full_size():
+    """The precision workload (slab h = 0.05 mm, 3,449,001 nodes): 1,000 steps
+    mixed vs FP64 on the GPU, then one step from the FP64 GPU state at 10 ms
+    against the oracle's step from that state."""
+    spec = inputs.slab_precision(h=0.05)
+    a = _sim(spec, "fp64")
+    va, _ = a.run(1000, 500)
+    st = a.get_state()
+    lat_a, _ = a.times()
+    o = orc.Oracle(spec)
+    # the oracle advances its state arrays in place: give it copies
+    o.state = orc.State(st["V"].copy(), st["Vprev"].copy(), np.array(st["u"], order="C"),
+                        st["lat"].copy(), st["lrt"].copy(), st["step"])
+    v_or, _ = o.steps(1, out_every=1)
+    v_a1, _ = a.run(1, 1)
+    assert _rel_l2(v_a1[0], v_or[0]) <= 1e-9
+    del a
+    b = _sim(spec, "mixed")
+    vb, _ = b.run(1000, 500)
+    errs = [_rel_l2(x, y) for x, y in zip(vb, va)]
+    print(f"  h=0.05 mixed vs fp64: V rel L2 {errs}", flush=True)
+    assert max(errs) <= V_REL_L2
+    lat_b, _ = b.times()
+    _lat_check(lat_b, lat_a, spec.dt)
+    # one mixed step from the same FP64 state vs the oracle's step
+    b.set_state(st["V"], st["Vprev"], st["u"], st["lat"], st["lrt"], st["step"])
+    v_b1, _ = b.run(1, 1)
+    assert _rel_l2(v_b1[0], v_or[0]) <= V_REL_L2
+
+
+def test_fp32_gates_option_error_is_reported():
+    """The FP32-gate variant runs and stays finite; its deviation from the
+    oracle on the coarse TT slab is of order 1e-5 (measured, stated in the
+    design notes), so it is not the default precision form."""
+    spec = _rhs_relative(inputs.slab(h=0.5, n_steps=2000))
+    s = _sim(spec, "mixed_gates32")
+    o = orc.Oracle(spec)
+    v_or, _ = o.steps(2000, out_every=500)
+    v_gpu, status = s.run(2000, 500)
+    assert status == 0 and np.isfinite(v_gpu).all()
+    err = max(_rel_l2(a, b) for a, b in zip(v_gpu, v_or))
+    print(f"  fp32 gates vs oracle: V rel L2 max {err:.2e}", flush=True)
+    assert err <= 1e-4

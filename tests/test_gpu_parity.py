@@ -189,8 +189,9 @@ def test_slab_full_size_prefix_and_front():
     assert _rel_l2(v_gpu[0], v_or[0]) <= V_REL_L2
     s.run(790)
     st = s.get_state()
-    o.state = orc.State(st["V"], st["Vprev"], np.ascontiguousarray(st["u"]), st["lat"], st["lrt"],
-                        st["step"])
+    # the oracle advances its state arrays in place: give it copies
+    o.state = orc.State(st["V"].copy(), st["Vprev"].copy(), np.array(st["u"], order="C"),
+                        st["lat"].copy(), st["lrt"].copy(), st["step"])
     v_or, _ = o.steps(2, out_every=1)
     v_gpu, _ = s.run(2, 1)
     for a, b in zip(v_gpu, v_or):
