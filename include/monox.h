@@ -225,6 +225,32 @@ MDX_API mdx_status mdx_spmv(mdx_ctx *ctx, int32_t which, const double *x, double
 MDX_API mdx_status mdx_ionic_step(mdx_ctx *ctx, double dt, int64_t n, const double *V,
                           double *u, double *iion);
 
+/* ---- learned warm start: the network ---------------------------------- */
+/* A per-node MLP 4 -> 64 -> 64 -> 64 -> 1 (ReLU) predicts the normalised
+ * increment V^{n+1} - V^n from node-local features; not part of the paper,
+ * whose warm start is the extrapolation 2V^k - V^{k-1} (after Algorithm 1).
+ * Parameters: FP32, MDX_MLP_NPARAM values laid out
+ *   W1[64][4] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[64] b4
+ * (W[out][in]).  Kernels use BF16 weights and activations with FP32
+ * accumulation (BF16 MFMA).  All arrays below are DEVICE arrays on ctx's
+ * device; calls are queued on ctx's stream and return without waiting. */
+#define MDX_MLP_NPARAM 8705
+MDX_API int32_t mdx_mlp_nparams(void);
+/* y[i] = net(X[i]) for i < n; X is [n][4] FP32 (16-byte aligned), y [n]. */
+MDX_API mdx_status mdx_mlp_forward(mdx_ctx *ctx, const float *params, int64_t n, const float *X,
+                                   float *y);
+/* bytes of scratch mdx_mlp_grad needs for n samples */
+MDX_API size_t mdx_mlp_grad_scratch(int64_t n);
+/* grad = d/dparams of L = (1/n) sum_i (net(X[i]) - T[i])^2 and loss = L
+ * (loss may be NULL).  Deterministic: per-workgroup partials in scratch are
+ * summed in a fixed order. */
+MDX_API mdx_status mdx_mlp_grad(mdx_ctx *ctx, const float *params, int64_t n, const float *X,
+                                const float *T, float *grad, float *loss, void *scratch,
+                                size_t scratch_bytes);
+/* one Adam step (Kingma & Ba) on params with moments m, v; t >= 1 */
+MDX_API mdx_status mdx_mlp_adam(mdx_ctx *ctx, float *params, float *m, float *v, const float *grad,
+                                int32_t t, double lr, double beta1, double beta2, double eps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,12 @@ _SIGS = {
     "mdx_get_matrix": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int64), P, P, P]),
     "mdx_spmv": (C.c_int, [P, C.c_int32, P, P]),
     "mdx_ionic_step": (C.c_int, [P, C.c_double, C.c_int64, P, P, P]),
+    "mdx_mlp_nparams": (C.c_int32, []),
+    "mdx_mlp_forward": (C.c_int, [P, P, C.c_int64, P, P]),
+    "mdx_mlp_grad_scratch": (C.c_size_t, [C.c_int64]),
+    "mdx_mlp_grad": (C.c_int, [P, P, C.c_int64, P, P, P, P, P, C.c_size_t]),
+    "mdx_mlp_adam": (C.c_int, [P, P, P, P, P, C.c_int32, C.c_double, C.c_double, C.c_double,
+                               C.c_double]),
 }
 
 _lib = None

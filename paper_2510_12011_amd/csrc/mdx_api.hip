@@ -1239,4 +1239,50 @@ mdx_status mdx_ionic_step(mdx_ctx *ctx, double dt, int64_t n, const double *V, d
     return MDX_OK;
 }
 
+int32_t mdx_mlp_nparams(void) { return mlp_nparams(); }
+
+size_t mdx_mlp_grad_scratch(int64_t n) { return n > 0 ? mlp_grad_scratch_bytes(n) : 0; }
+
+mdx_status mdx_mlp_forward(mdx_ctx *ctx, const float *params, int64_t n, const float *X, float *y)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
+    if (n < 0 || (n > 0 && (!params || !X || !y)) || ((uintptr_t)X % 16) != 0)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "null or misaligned device array");
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_mlp_forward(ctx->stream, params, n, X, y);
+    HIPCHK(hipGetLastError());
+    return MDX_OK;
+}
+
+mdx_status mdx_mlp_grad(mdx_ctx *ctx, const float *params, int64_t n, const float *X, const float *T,
+                        float *grad, float *loss, void *scratch, size_t scratch_bytes)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
+    if (n <= 0 || !params || !X || !T || !grad || ((uintptr_t)X % 16) != 0)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "null or misaligned device array, or n <= 0");
+    if (!scratch || scratch_bytes < mlp_grad_scratch_bytes(n))
+        return fail(ctx, MDX_ERR_NO_WORKSPACE, "scratch of %zu bytes required",
+                    mlp_grad_scratch_bytes(n));
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_mlp_grad(ctx->stream, params, n, X, T, grad, loss, (float *)scratch);
+    HIPCHK(hipGetLastError());
+    return MDX_OK;
+}
+
+mdx_status mdx_mlp_adam(mdx_ctx *ctx, float *params, float *m, float *v, const float *grad, int32_t t,
+                        double lr, double beta1, double beta2, double eps)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
+    if (!params || !m || !v || !grad || t < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) ||
+        !(beta2 >= 0.0 && beta2 < 1.0) || !(eps >= 0.0))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "invalid Adam arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_adam(ctx->stream, params, m, v, grad, t, lr, beta1, beta2, eps);
+    HIPCHK(hipGetLastError());
+    return MDX_OK;
+}
+
 }  // extern "C"

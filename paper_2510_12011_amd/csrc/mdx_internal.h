@@ -122,6 +122,16 @@ void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter
                         double *x, float *delta, const double *b, const double *dinv,
                         const float *dinv32, float *r32, float *p32, double *partial, Scalars *sc);
 
+// ---- learned warm start network (mdx_mlp.hip) ------------------------------
+int mlp_nparams();
+int mlp_grad_groups(int64_t n);
+size_t mlp_grad_scratch_bytes(int64_t n);
+void launch_mlp_forward(hipStream_t s, const float *P, int64_t n, const float *X, float *y);
+void launch_mlp_grad(hipStream_t s, const float *P, int64_t n, const float *X, const float *T,
+                     float *grad, float *loss, float *partials);
+void launch_adam(hipStream_t s, float *P, float *m, float *v, const float *g, int t, double lr,
+                 double b1, double b2, double eps);
+
 // ---- solver (mdx_solver.hip) ---------------------------------------------
 void launch_fill(hipStream_t s, int64_t n, double v, double *x);
 void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double amp, double *istim);

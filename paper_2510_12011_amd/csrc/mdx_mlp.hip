@@ -1,0 +1,432 @@
+// Per-node MLP of the learned warm start: 4 -> 64 -> 64 -> 64 -> 1, ReLU,
+// BF16 weights and activations, FP32 accumulation, on the 32x32x8 BF16 MFMA
+// of gfx950.  Forward (inference), gradient of the mean-squared error
+// (training) and Adam.
+//
+// Parameter vector (FP32 master copy, 8,705 values):
+//   W1[64][4] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[64] b4
+//
+// Arithmetic: layer 1 in FP32 VALU with BF16-rounded W1 on FP32 features;
+// h1 = bf16(relu(z1)); layers 2 and 3 on MFMA (BF16 operands, FP32
+// accumulators) plus FP32 bias; h2 = bf16(relu(z2)); h3 = relu(z3) in FP32;
+// y = sum bf16(W4) h3 + b4 in FP32.
+//
+// One wavefront handles a tile of 32 nodes.  Hidden layers are computed as
+// transposed products Z^T = W H^T (M = output unit, N = node, K = input
+// unit).  With v_mfma_f32_32x32x8_bf16 the accumulator element held in
+// register v of lane l is Z^T[8(v/4) + 4(l/32) + v%4][l%32]; the B operand
+// of the next layer's K-step s in lane l is H^T[8s + 4(l/32) + i][l%32],
+// i = 0..3.  These coincide (s = v/4 within a 32-row output tile), so each
+// layer's output feeds the next MFMA from registers with no data exchange.
+#include "mdx_device.h"
+#include "mdx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace mdx {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int NH = 64;
+constexpr int OFF_W1 = 0, OFF_B1 = 256, OFF_W2 = 320, OFF_B2 = 4416, OFF_W3 = 4480,
+              OFF_B3 = 8576, OFF_W4 = 8640, OFF_B4 = 8704;
+constexpr int NPARAM = 8705;
+constexpr int WSTRIDE = 68;   // LDS row stride (bf16) of W2/W3: 8-byte aligned, fewer conflicts
+
+__device__ __forceinline__ unsigned short f2bf(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ __forceinline__ float round_bf(float f) { return bf2f(f2bf(f)); }
+
+__device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// weights staged in LDS once per workgroup
+struct MlpLds {
+    float w1[NH][4];       // BF16-rounded
+    float b1[NH];
+    unsigned short w2[NH * WSTRIDE];
+    float b2[NH];
+    unsigned short w3[NH * WSTRIDE];
+    float b3[NH];
+    float w4[NH];          // BF16-rounded
+    float b4;
+};
+
+__device__ void load_weights(const float *__restrict__ P, MlpLds &w)
+{
+    for (int i = threadIdx.x; i < NH * 4; i += blockDim.x) w.w1[i / 4][i % 4] = round_bf(P[OFF_W1 + i]);
+    for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {
+        const int o = i / NH, k = i % NH;
+        w.w2[o * WSTRIDE + k] = f2bf(P[OFF_W2 + i]);
+        w.w3[o * WSTRIDE + k] = f2bf(P[OFF_W3 + i]);
+    }
+    for (int i = threadIdx.x; i < NH; i += blockDim.x) {
+        w.b1[i] = P[OFF_B1 + i];
+        w.b2[i] = P[OFF_B2 + i];
+        w.b3[i] = P[OFF_B3 + i];
+        w.w4[i] = round_bf(P[OFF_W4 + i]);
+    }
+    if (threadIdx.x == 0) w.b4 = P[OFF_B4];
+}
+
+// A fragment of W (rows = output units): lane holds W[32 ot + l%32][8 ks + 4 half + 0..3]
+__device__ __forceinline__ bf16x4 frag_w(const unsigned short *w, int ot, int ks, int lane)
+{
+    const int o = 32 * ot + (lane & 31), k = 8 * ks + 4 * (lane >> 5);
+    return *reinterpret_cast<const bf16x4 *>(w + o * WSTRIDE + k);
+}
+
+// A fragment of W^T (rows = input units): lane holds W[8 s + 4 half + i][32 kt + l%32]
+__device__ __forceinline__ bf16x4 frag_wt(const unsigned short *w, int kt, int s, int lane)
+{
+    const int k = 32 * kt + (lane & 31), o = 8 * s + 4 * (lane >> 5);
+    bf16x4 a;
+    a[0] = (short)w[(o + 0) * WSTRIDE + k];
+    a[1] = (short)w[(o + 1) * WSTRIDE + k];
+    a[2] = (short)w[(o + 2) * WSTRIDE + k];
+    a[3] = (short)w[(o + 3) * WSTRIDE + k];
+    return a;
+}
+
+// unit index held in accumulator register v of output tile ot by this lane
+__device__ __forceinline__ int unit_of(int ot, int v, int half) { return 32 * ot + 8 * (v / 4) + 4 * half + (v % 4); }
+
+struct Tile {
+    bf16x4 h1[8];      // B fragments: h1 for units 8t + 4 half + i
+    bf16x4 h2[8];      // B fragments: h2 for units 8t + 4 half + i
+    float z1[32];      // layer-1 pre-activations (same units as h1, t*4 + i)
+    float z2[32];      // layer-2 pre-activations, index 16 ot + v
+    float z3[32];      // layer-3 pre-activations, index 16 ot + v
+    float y;
+};
+
+__device__ __forceinline__ void forward_tile(const MlpLds &w, float4 x, Tile &T, bool keep)
+{
+    const int lane = threadIdx.x & 63, half = lane >> 5;
+    // layer 1 (VALU)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = 8 * t + 4 * half + i;
+            float z = w.b1[o] + w.w1[o][0] * x.x + w.w1[o][1] * x.y + w.w1[o][2] * x.z + w.w1[o][3] * x.w;
+            if (keep) T.z1[4 * t + i] = z;
+            T.h1[t][i] = (short)f2bf(fmaxf(z, 0.0f));
+        }
+    }
+    // layer 2 (MFMA)
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot) {
+        f32x16 acc = {0};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) acc = mfma(frag_w(w.w2, ot, ks, lane), T.h1[ks], acc);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const float z = acc[v] + w.b2[unit_of(ot, v, half)];
+            if (keep) T.z2[16 * ot + v] = z;
+            T.h2[4 * ot + v / 4][v % 4] = (short)f2bf(fmaxf(z, 0.0f));
+        }
+    }
+    // layer 3 (MFMA) and output layer (VALU)
+    float s = 0.0f;
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot) {
+        f32x16 acc = {0};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) acc = mfma(frag_w(w.w3, ot, ks, lane), T.h2[ks], acc);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int o = unit_of(ot, v, half);
+            const float z = acc[v] + w.b3[o];
+            T.z3[16 * ot + v] = z;
+            s += w.w4[o] * fmaxf(z, 0.0f);
+        }
+    }
+    s += __shfl_xor(s, 32, 64);
+    T.y = s + w.b4;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P, int64_t n,
+                                                     const float *__restrict__ X,
+                                                     float *__restrict__ y)
+{
+    __shared__ MlpLds w;
+    load_weights(P, w);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t n_tiles = (n + 31) / 32;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    Tile T;
+    for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; tile < n_tiles;
+         tile += waves) {
+        const int64_t node = tile * 32 + (lane & 31);
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (node < n) x = reinterpret_cast<const float4 *>(X)[node];
+        forward_tile(w, x, T, false);
+        if (lane < 32 && node < n) y[node] = T.y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training: gradient of L = (1/n) sum_i (y_i - t_i)^2.  One wavefront per
+// workgroup; each workgroup accumulates its samples' gradient into its own
+// slice of `partial` (NPARAM values + its loss sum), reduced afterwards in a
+// fixed order by k_mlp_reduce -- no atomics, deterministic.
+// Weight gradients dW = dZ H^T are MFMA products over the tile's 32 nodes:
+// activations and deltas are staged in LDS as [unit][node] BF16 so that the
+// A fragments (lane = output unit) and B fragments (lane = input unit) are
+// 8-byte reads.  An extra row of ones in each staged input gives the bias
+// gradients as one more column of the same products.
+// ---------------------------------------------------------------------------
+constexpr int SSTRIDE = 36;   // staged row stride (bf16): 32 nodes + pad
+
+struct TrainLds {
+    MlpLds w;
+    unsigned short xs[32 * SSTRIDE];    // rows 0..3 features, 4 ones, rest 0
+    unsigned short h1s[96 * SSTRIDE];   // rows 0..63 h1, 64 ones, rest 0
+    unsigned short h2s[96 * SSTRIDE];
+    unsigned short h3s[96 * SSTRIDE];
+    unsigned short d1s[64 * SSTRIDE];   // dz1 [unit][node]
+    unsigned short d2s[64 * SSTRIDE];
+    unsigned short d3s[64 * SSTRIDE];
+    unsigned short dys[32 * SSTRIDE];   // row 0: dL/dy, rest 0
+};
+
+__device__ __forceinline__ bf16x4 frag_rows(const unsigned short *s, int row, int ks, int lane)
+{
+    return *reinterpret_cast<const bf16x4 *>(s + row * SSTRIDE + 8 * ks + 4 * (lane >> 5));
+}
+
+// acc[v] -> partial for output tile (mt, nt) of dW = D S^T where D rows are
+// output units m and S rows are inputs n; map(m, n) gives the parameter
+// index or -1.
+template <class Map>
+__device__ __forceinline__ void product_to_partial(const unsigned short *D, int mt,
+                                                   const unsigned short *S, int nt, float *part,
+                                                   Map map)
+{
+    const int lane = threadIdx.x & 63, half = lane >> 5;
+    f32x16 acc = {0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+        acc = mfma(frag_rows(D, 32 * mt + (lane & 31), ks, lane),
+                   frag_rows(S, 32 * nt + (lane & 31), ks, lane), acc);
+    const int n = 32 * nt + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int m = 32 * mt + 8 * (v / 4) + 4 * half + (v % 4);
+        const int idx = map(m, n);
+        if (idx >= 0) part[idx] += acc[v];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ P, int64_t n,
+                                                 const float *__restrict__ X,
+                                                 const float *__restrict__ Tgt,
+                                                 int tiles_per_group, float *__restrict__ partials)
+{
+    __shared__ TrainLds L;
+    load_weights(P, L.w);
+    const int lane = threadIdx.x;
+    const int half = lane >> 5;
+    const int j = lane & 31;
+    // constant rows: ones and zero padding
+    for (int i = lane; i < 32 * SSTRIDE; i += 64) {
+        const int row = i / SSTRIDE;
+        L.xs[i] = row == 4 ? (unsigned short)0x3f80 : 0;
+        L.dys[i] = 0;
+    }
+    for (int i = lane; i < 96 * SSTRIDE; i += 64) {
+        const int row = i / SSTRIDE;
+        const unsigned short v = row == 64 ? (unsigned short)0x3f80 : 0;
+        L.h1s[i] = v;
+        L.h2s[i] = v;
+        L.h3s[i] = v;
+    }
+    float *part = partials + (int64_t)blockIdx.x * (NPARAM + 1);
+    for (int i = lane; i < NPARAM + 1; i += 64) part[i] = 0.0f;
+    __syncthreads();
+
+    const double inv_n = 1.0 / (double)n;
+    float loss = 0.0f;
+    Tile T;
+    const int64_t t0 = (int64_t)blockIdx.x * tiles_per_group;
+    const int64_t n_tiles = (n + 31) / 32;
+    for (int64_t tile = t0; tile < min(t0 + tiles_per_group, n_tiles); ++tile) {
+        const int64_t node = tile * 32 + j;
+        const bool valid = node < n;
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+        float tg = 0.0f;
+        if (valid) {
+            x = reinterpret_cast<const float4 *>(X)[node];
+            tg = Tgt[node];
+        }
+        forward_tile(L.w, x, T, true);
+        const float r = valid ? T.y - tg : 0.0f;
+        if (half == 0) loss += r * r;
+        const float dy = (float)(2.0 * inv_n) * r;
+
+        // output layer: dz3 = dy W4 (z3 > 0); stage h3 and dz3
+        bf16x4 d3f[8];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int o = unit_of(ot, v, half);
+                const float z = T.z3[16 * ot + v];
+                const float dz = z > 0.0f ? dy * L.w.w4[o] : 0.0f;
+                d3f[4 * ot + v / 4][v % 4] = (short)f2bf(dz);
+                L.d3s[o * SSTRIDE + j] = f2bf(dz);
+                L.h3s[o * SSTRIDE + j] = f2bf(fmaxf(z, 0.0f));
+            }
+        if (half == 0) L.dys[j] = f2bf(dy);
+        // dh2 = W3^T dz3 -> dz2 = dh2 (z2 > 0); stage h2 and dz2
+        bf16x4 d2f[8];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            f32x16 acc = {0};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) acc = mfma(frag_wt(L.w.w3, kt, s, lane), d3f[s], acc);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int k = unit_of(kt, v, half);
+                const float z = T.z2[16 * kt + v];
+                const float dz = z > 0.0f ? acc[v] : 0.0f;
+                d2f[4 * kt + v / 4][v % 4] = (short)f2bf(dz);
+                L.d2s[k * SSTRIDE + j] = f2bf(dz);
+                L.h2s[k * SSTRIDE + j] = (unsigned short)T.h2[4 * kt + v / 4][v % 4];
+            }
+        }
+        // dh1 = W2^T dz2 -> dz1 = dh1 (z1 > 0); stage h1, dz1, x
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            f32x16 acc = {0};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) acc = mfma(frag_wt(L.w.w2, kt, s, lane), d2f[s], acc);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int k = unit_of(kt, v, half);   // = 8 t + 4 half + i, t = 4 kt + v / 4
+                const int t = 4 * kt + v / 4, i = v % 4;
+                const float z = T.z1[4 * t + i];
+                L.d1s[k * SSTRIDE + j] = f2bf(z > 0.0f ? acc[v] : 0.0f);
+                L.h1s[k * SSTRIDE + j] = (unsigned short)T.h1[t][i];
+            }
+        }
+        if (half == 0) {
+            L.xs[0 * SSTRIDE + j] = f2bf(x.x);
+            L.xs[1 * SSTRIDE + j] = f2bf(x.y);
+            L.xs[2 * SSTRIDE + j] = f2bf(x.z);
+            L.xs[3 * SSTRIDE + j] = f2bf(x.w);
+        }
+        __syncthreads();
+        // weight and bias gradients: MFMA over the tile's 32 nodes
+#pragma unroll
+        for (int nt = 0; nt < 3; ++nt) {
+            product_to_partial(L.dys, 0, L.h3s, nt, part, [](int m, int c) {
+                return m == 0 ? (c < NH ? OFF_W4 + c : c == NH ? OFF_B4 : -1) : -1;
+            });
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                product_to_partial(L.d3s, mt, L.h2s, nt, part, [](int m, int c) {
+                    return c < NH ? OFF_W3 + m * NH + c : c == NH ? OFF_B3 + m : -1;
+                });
+                product_to_partial(L.d2s, mt, L.h1s, nt, part, [](int m, int c) {
+                    return c < NH ? OFF_W2 + m * NH + c : c == NH ? OFF_B2 + m : -1;
+                });
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+            product_to_partial(L.d1s, mt, L.xs, 0, part, [](int m, int c) {
+                return c < 4 ? OFF_W1 + m * 4 + c : c == 4 ? OFF_B1 + m : -1;
+            });
+        __syncthreads();
+    }
+    loss = wave_sum((double)loss);
+    if (lane == 0) part[NPARAM] = loss;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_reduce(int groups, const float *__restrict__ partials,
+                                                    int64_t n, float *__restrict__ grad,
+                                                    float *__restrict__ loss)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > NPARAM) return;
+    float s = 0.0f;
+    for (int g = 0; g < groups; ++g) s += partials[(int64_t)g * (NPARAM + 1) + p];
+    if (p < NPARAM)
+        grad[p] = s;
+    else if (loss)
+        loss[0] = (float)((double)s / (double)n);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ P, float *__restrict__ m,
+                                              float *__restrict__ v, const float *__restrict__ g,
+                                              float lr, float b1, float b2, float eps, float c1,
+                                              float c2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NPARAM) return;
+    const float gi = g[p];
+    const float mi = b1 * m[p] + (1.0f - b1) * gi;
+    const float vi = b2 * v[p] + (1.0f - b2) * gi * gi;
+    m[p] = mi;
+    v[p] = vi;
+    P[p] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+
+int mlp_nparams() { return NPARAM; }
+
+int mlp_grad_groups(int64_t n)
+{
+    const int64_t tiles = (n + 31) / 32;
+    const int64_t tpg = std::max<int64_t>(1, (tiles + 2047) / 2048);
+    return (int)((tiles + tpg - 1) / tpg);
+}
+
+size_t mlp_grad_scratch_bytes(int64_t n)
+{
+    return sizeof(float) * (size_t)(NPARAM + 1) * (size_t)mlp_grad_groups(n);
+}
+
+void launch_mlp_forward(hipStream_t s, const float *P, int64_t n, const float *X, float *y)
+{
+    if (n <= 0) return;
+    const int64_t tiles = (n + 31) / 32;
+    const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 2048);
+    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, s, P, n, X, y);
+}
+
+void launch_mlp_grad(hipStream_t s, const float *P, int64_t n, const float *X, const float *T,
+                     float *grad, float *loss, float *partials)
+{
+    const int64_t tiles = (n + 31) / 32;
+    const int groups = mlp_grad_groups(n);
+    const int tpg = (int)((tiles + groups - 1) / groups);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(groups), dim3(64), 0, s, P, n, X, T, tpg, partials);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, s, groups,
+                       partials, n, grad, loss);
+}
+
+void launch_adam(hipStream_t s, float *P, float *m, float *v, const float *g, int t, double lr,
+                 double b1, double b2, double eps)
+{
+    const double c1 = 1.0 - std::pow(b1, (double)t), c2 = 1.0 - std::pow(b2, (double)t);
+    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, P, m, v, g, (float)lr,
+                       (float)b1, (float)b2, (float)eps, (float)c1, (float)c2);
+}
+
+}  // namespace mdx
