@@ -64,8 +64,10 @@ typedef struct mdx_ctx mdx_ctx;
 /* ionic models: none (diffusion only), Mitchell-Schaeffer two-variable,
  * ten Tusscher-Panfilov 2006 (endocardial) */
 enum { MDX_IONIC_NONE = 0, MDX_IONIC_MS = 1, MDX_IONIC_TT = 2 };
-/* PCG warm start: previous step V^k, extrapolation 2V^k - V^{k-1} (paper) */
-enum { MDX_WS_PREV = 0, MDX_WS_EXTRAP = 1 };
+/* PCG warm start: previous step V^k, extrapolation 2V^k - V^{k-1} (paper),
+ * or the learned per-node network (see mdx_set_mlp), which falls back to
+ * V^k whenever its initial residual is not the smaller of the two */
+enum { MDX_WS_PREV = 0, MDX_WS_EXTRAP = 1, MDX_WS_MLP = 2 };
 /* relative stopping test: ||z|| / ||z_0|| (paper) or ||z|| / ||D^-1 b|| */
 enum { MDX_REL_INITIAL = 0, MDX_REL_RHS = 1 };
 /* which assembled matrix mdx_get_matrix returns */
@@ -108,6 +110,7 @@ typedef struct {
                               /* others only applied the stopping test)      */
     double spmv_bytes;        /* algorithmic bytes moved by those launches   */
     double host_wait_seconds; /* host time blocked on the stream in mdx_run  */
+    int64_t fallbacks;        /* learned warm start: steps that used V^k     */
 } mdx_stats;
 
 /* ---- context -------------------------------------------------------- */
@@ -250,6 +253,23 @@ MDX_API mdx_status mdx_mlp_grad(mdx_ctx *ctx, const float *params, int64_t n, co
 /* one Adam step (Kingma & Ba) on params with moments m, v; t >= 1 */
 MDX_API mdx_status mdx_mlp_adam(mdx_ctx *ctx, float *params, float *m, float *v, const float *grad,
                                 int32_t t, double lr, double beta1, double beta2, double eps);
+
+/* ---- learned warm start: use in the time step ------------------------- */
+/* Install the network for MDX_WS_MLP.  params: HOST FP32 [MDX_MLP_NPARAM];
+ * norm: HOST [9] = feature means (4), feature standard deviations (4),
+ * output scale.  Features of node i at step n: V^n, V^n - V^{n-1},
+ * (I_stim - I_ion)/Cm (mV/ms), (K V^n)_i / K_ii; guess x0 = V^n + scale y.
+ * Requires a prepared context; the network lives in the workspace. */
+MDX_API mdx_status mdx_set_mlp(mdx_ctx *ctx, const float *params, const double *norm);
+/* Training-data recorder: when non-NULL, every step of mdx_run writes the
+ * raw features of node i (internal node order, i < n_nodes) to X[i][0..3]
+ * and, after the solve, V^{n+1}_i - V^n_i to dV[i] (DEVICE arrays of
+ * n_nodes float4 / float, overwritten each step).  The permutation from
+ * internal to original order is node_order[i] (mdx_get_node_order).  Pass
+ * NULLs to stop recording. */
+MDX_API mdx_status mdx_set_recorder(mdx_ctx *ctx, float *X, float *dV);
+/* original node id of internal row i, i < n_nodes (host array) */
+MDX_API mdx_status mdx_get_node_order(mdx_ctx *ctx, int32_t *order);
 
 #ifdef __cplusplus
 }

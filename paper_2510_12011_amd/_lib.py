@@ -24,7 +24,7 @@ MDX_ERR_STATE = -6
 MDX_ERR_UNSUPPORTED = -7
 
 MDX_IONIC_NONE, MDX_IONIC_MS, MDX_IONIC_TT = 0, 1, 2
-MDX_WS_PREV, MDX_WS_EXTRAP = 0, 1
+MDX_WS_PREV, MDX_WS_EXTRAP, MDX_WS_MLP = 0, 1, 2
 MDX_REL_INITIAL, MDX_REL_RHS = 0, 1
 MDX_PREC_FP64, MDX_PREC_MIXED, MDX_PREC_MIXED_GATES32 = 0, 1, 2
 MDX_MAT_M, MDX_MAT_K, MDX_MAT_A = 0, 1, 2
@@ -44,7 +44,7 @@ class Stats(C.Structure):
                 ("bandwidth", C.c_int64), ("step_loop_seconds", C.c_double),
                 ("spmv_timed", C.c_int64), ("spmv_seconds", C.c_double),
                 ("spmv_work", C.c_int64), ("spmv_bytes", C.c_double),
-                ("host_wait_seconds", C.c_double)]
+                ("host_wait_seconds", C.c_double), ("fallbacks", C.c_int64)]
 
 
 class MdxError(RuntimeError):
@@ -82,6 +82,9 @@ _SIGS = {
     "mdx_spmv": (C.c_int, [P, C.c_int32, P, P]),
     "mdx_ionic_step": (C.c_int, [P, C.c_double, C.c_int64, P, P, P]),
     "mdx_mlp_nparams": (C.c_int32, []),
+    "mdx_set_mlp": (C.c_int, [P, P, P]),
+    "mdx_set_recorder": (C.c_int, [P, P, P]),
+    "mdx_get_node_order": (C.c_int, [P, P]),
     "mdx_mlp_forward": (C.c_int, [P, P, C.c_int64, P, P]),
     "mdx_mlp_grad_scratch": (C.c_size_t, [C.c_int64]),
     "mdx_mlp_grad": (C.c_int, [P, P, C.c_int64, P, P, P, P, P, C.c_size_t]),

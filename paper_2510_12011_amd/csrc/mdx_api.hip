@@ -50,6 +50,7 @@ struct Layout {
     size_t slice_ptr, col, Mv, Kv, Av, dinv, vec[3], r, p, p2, q, b, s, istim, u, lat, lrt, stim_idx,
         partial, scalars;
     size_t A32, dinv32, r32, p32, q32, delta, g32;   // mixed-precision form
+    size_t kdiag, feat, mlp_y, mlp_params;            // learned warm start
     size_t total;
     size_t x_xyz, x_tets, x_fibre, x_sig, x_vol, x_ek, x_cptr, x_contrib, x_total;
 };
@@ -93,6 +94,11 @@ struct mdx_ctx {
 
     Scalars *sc_host = nullptr;   // pinned
     double *stage = nullptr;      // pinned, npad doubles
+
+    // learned warm start
+    bool mlp_set = false;
+    MlpNorm mlp_norm{{0.f, 0.f, 0.f, 0.f}, {1.f, 1.f, 1.f, 1.f}, 0.f};
+    float *rec_X = nullptr, *rec_dV = nullptr;   // training-data recorder
 
     // launch-shape tuning
     int max_groups = kMaxGroups;
@@ -310,6 +316,10 @@ void compute_layout(mdx_ctx *c)
     L.q32 = take(sizeof(float) * np);
     L.delta = take(sizeof(float) * np);
     L.g32 = take(sizeof(float) * np * std::max(1, ionic_gate_rows(c->ionic_kind)));
+    L.kdiag = take(sizeof(double) * np);
+    L.feat = take(sizeof(float) * 4 * np);
+    L.mlp_y = take(sizeof(float) * np);
+    L.mlp_params = take(sizeof(float) * mlp_nparams());
     L.total = o;
 
     o = 0;
@@ -645,7 +655,8 @@ mdx_status mdx_set_solver(mdx_ctx *ctx, const mdx_solver_opts *o)
     if (!(o->atol >= 0.0) || !(o->rtol >= 0.0) || o->max_iter < 1 || o->reserved != 0 ||
         o->precision < MDX_PREC_FP64 || o->precision > MDX_PREC_MIXED_GATES32 || o->rr_interval < 0 ||
         (o->rel_mode != MDX_REL_INITIAL && o->rel_mode != MDX_REL_RHS) ||
-        (o->warm_start != MDX_WS_PREV && o->warm_start != MDX_WS_EXTRAP))
+        (o->warm_start != MDX_WS_PREV && o->warm_start != MDX_WS_EXTRAP &&
+         o->warm_start != MDX_WS_MLP))
         return fail(ctx, MDX_ERR_INVALID_ARG, "invalid solver options");
     ctx->opts = *o;
     if (ctx->prepared) {
@@ -792,6 +803,7 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     launch_system(st, ctx->nslots, Mv, Kv, ctx->chi * ctx->cm, ctx->theta * dt, Av);
     SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
     launch_dinv(st, ctx->npad, ctx->n, P, Av, ctx->dev<double>(L.dinv));
+    launch_kdiag(st, ctx->npad, ctx->n, P, Kv, ctx->dev<double>(L.kdiag));
     // FP32 copies for the mixed-precision form
     launch_to_f32(st, ctx->nslots, Av, ctx->dev<float>(L.A32));
     launch_to_f32(st, ctx->npad, ctx->dev<double>(L.dinv), ctx->dev<float>(L.dinv32));
@@ -806,6 +818,8 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
                       ionic_nstates(ctx->ionic_kind) ? ctx->dev<double>(L.u) : nullptr);
     for (size_t off : {L.vec[2], L.r, L.p, L.p2, L.q, L.b, L.s, L.istim})
         launch_fill(st, ctx->npad, 0.0, ctx->dev<double>(off));
+    launch_fill(st, ctx->npad * 2, 0.0, ctx->dev<double>(L.feat));   // 4 floats per row
+    launch_fill(st, ctx->npad / 2, 0.0, ctx->dev<double>(L.mlp_y));
     // FP32 vectors: zero bits (float zero) via the double fill over half the count
     for (size_t off : {L.r32, L.p32, L.q32, L.delta})
         launch_fill(st, ctx->npad / 2, 0.0, ctx->dev<double>(off));
@@ -829,6 +843,8 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     ctx->iters_hist.clear();
     ctx->stats = mdx_stats{};
     ctx->prepared = true;
+    ctx->mlp_set = false;
+    ctx->rec_X = ctx->rec_dV = nullptr;
     return MDX_OK;
     GUARD_END
 }
@@ -857,6 +873,12 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     const int max_iter = ctx->opts.max_iter;
     const bool mixed = ctx->opts.precision != MDX_PREC_FP64;
     const bool gates32 = ctx->opts.precision == MDX_PREC_MIXED_GATES32;
+    const bool learned = ctx->opts.warm_start == MDX_WS_MLP;
+    if (learned && !ctx->mlp_set)
+        return fail(ctx, MDX_ERR_STATE, "warm start MDX_WS_MLP needs mdx_set_mlp first");
+    double *kdiag = ctx->dev<double>(L.kdiag);
+    float *feat = ctx->dev<float>(L.feat), *mlp_y = ctx->dev<float>(L.mlp_y);
+    const float *mlp_params = ctx->dev<float>(L.mlp_params);
     float *A32 = ctx->dev<float>(L.A32);
     float *dinv32 = ctx->dev<float>(L.dinv32), *r32 = ctx->dev<float>(L.r32);
     float *p32 = ctx->dev<float>(L.p32), *q32 = ctx->dev<float>(L.q32);
@@ -873,19 +895,40 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         double *V = ctx->vec(0), *Vprev = ctx->vec(1), *X = ctx->vec(2);
         ctx->profiling = ctx->profile_every > 0 && k % ctx->profile_every == 0;
         const double *istim = any_stim ? ctx->dev<double>(L.istim) : nullptr;
+
+        // ---- ionic update: s = I_stim - I_ion ----
+        if (gates32)
+            launch_ionic_step_mixed(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
+                                    ctx->dt, ctx->cm, V, u, g32, istim, s);
+        else
+            launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
+                              ctx->dt, ctx->cm, V, u, istim, s, 0);
+
+        // ---- right-hand side, warm start, initial residual ----
+        if (learned) {
+            launch_rhs_features(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm, ctx->n, V, Vprev,
+                                s, b, feat, ctx->rec_X, part0);
+            launch_mlp_forward(st, mlp_params, ctx->n, feat, mlp_y);   // padding rows keep y = 0
+            launch_two_residuals(st, T, P, Av, dinv, ctx->mlp_norm.out_scale, V, mlp_y, b, X, r, q,
+                                 mixed ? 1 : 0, part_pq);
+            launch_init_finalize_ws(st, T, part_pq, part0, sp.rel_mode, sc);
+            launch_select(st, ctx->npad, V, q, X, r, mixed ? r32 : nullptr, delta, sc);
+        } else {
+            if (ctx->rec_X)   // training-data recorder: raw features
+                launch_rhs_features(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm, ctx->n, V,
+                                    Vprev, s, b, nullptr, ctx->rec_X, part_rz);
+            if (mixed)
+                launch_rhs_init_mixed(st, T, P, Mv, Kv, dinv, dinv32, sp, V, Vprev, s, X, b, r32,
+                                      delta, part0);
+            else
+                launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0);
+            launch_init_finalize(st, T, part0, sp.rel_mode, sc);
+        }
+
+        // ---- PCG ----
         int units = 0;   // kernels carrying the SpMV launched so far
         bool done = false;
         if (mixed) {
-            // ---- mixed-precision form ----
-            if (gates32)
-                launch_ionic_step_mixed(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n,
-                                        ctx->npad, ctx->dt, ctx->cm, V, u, g32, istim, s);
-            else
-                launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
-                                  ctx->dt, ctx->cm, V, u, istim, s, 0);
-            launch_rhs_init_mixed(st, T, P, Mv, Kv, dinv, dinv32, sp, V, Vprev, s, X, b, r32,
-                                  delta, part0);
-            launch_init_finalize(st, T, part0, sp.rel_mode, sc);
             launch_set_direction32(st, ctx->npad, dinv32, r32, p32, sc);
             int it = 0;
             int chunk = std::max(1, ctx->last_iters);
@@ -916,12 +959,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                 it = ctx->sc_host->it_next;
                 chunk = 1;
             }
-        } else {
-        launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad, ctx->dt,
-                          ctx->cm, V, u, istim, s, 0);
-        launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0);
-        launch_init_finalize(st, T, part0, sp.rel_mode, sc);
-        if (ctx->iter_scheme == 1) {
+        } else if (ctx->iter_scheme == 1) {
             // Unit 0 is the first half of iteration 0; unit u >= 1 is the
             // second half of iteration u-1 followed by the first half of
             // iteration u, which tests ||z_u||.  Units 0..c detect convergence
@@ -986,7 +1024,8 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                 chunk = 1;
             }
         }
-        }   // FP64 path
+        if (learned && !ctx->sc_host->use_mlp) ctx->stats.fallbacks++;
+        if (ctx->rec_dV) launch_record_dv(st, ctx->n, V, X, ctx->rec_dV);
         if (ctx->sc_host->nonfinite)
             return fail(ctx, MDX_ERR_NONFINITE, "non-finite value in the solve of step %lld",
                         (long long)k);
@@ -1282,6 +1321,50 @@ mdx_status mdx_mlp_adam(mdx_ctx *ctx, float *params, float *m, float *v, const f
     HIPCHK(hipSetDevice(ctx->device));
     launch_adam(ctx->stream, params, m, v, grad, t, lr, beta1, beta2, eps);
     HIPCHK(hipGetLastError());
+    return MDX_OK;
+}
+
+mdx_status mdx_set_mlp(mdx_ctx *ctx, const float *params, const double *norm)
+{
+    if (!ctx || !params || !norm) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
+    const int np = mlp_nparams();
+    for (int i = 0; i < np; ++i)
+        if (!std::isfinite(params[i])) return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite parameter %d", i);
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(norm[i])) return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite norm %d", i);
+    for (int c = 0; c < 4; ++c)
+        if (!(norm[4 + c] > 0.0)) return fail(ctx, MDX_ERR_INVALID_ARG, "std must be > 0");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipMemcpyAsync(ctx->dev<float>(ctx->L.mlp_params), params, sizeof(float) * np,
+                          hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int c = 0; c < 4; ++c) {
+        ctx->mlp_norm.mean[c] = (float)norm[c];
+        ctx->mlp_norm.inv_std[c] = (float)(1.0 / norm[4 + c]);
+    }
+    ctx->mlp_norm.out_scale = (float)norm[8];
+    ctx->mlp_set = true;
+    return MDX_OK;
+}
+
+mdx_status mdx_set_recorder(mdx_ctx *ctx, float *X, float *dV)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
+    if ((X == nullptr) != (dV == nullptr))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "set both recorder arrays or neither");
+    if (X && ((uintptr_t)X % 16) != 0) return fail(ctx, MDX_ERR_INVALID_ARG, "X must be 16-byte aligned");
+    ctx->rec_X = X;
+    ctx->rec_dV = dV;
+    return MDX_OK;
+}
+
+mdx_status mdx_get_node_order(mdx_ctx *ctx, int32_t *order)
+{
+    if (!ctx || !order) return MDX_ERR_INVALID_ARG;
+    if (mdx_status s = require_mesh(ctx)) return s;
+    std::copy(ctx->perm.begin(), ctx->perm.end(), order);
     return MDX_OK;
 }
 

@@ -49,8 +49,15 @@ struct alignas(256) Scalars {
     int32_t replace;    // a replacement is pending (iteration kernels idle)
     int32_t redirect;   // a replacement did not stop: p = z + beta p pending
     int32_t it_next;    // iterations completed (index of the next one)
-    int32_t pad_;
+    int32_t use_mlp;    // learned warm start: the MLP guess was chosen this step
     double beta;        // beta after a replacement
+};
+
+// standardisation of the learned warm start's features and output scale
+struct MlpNorm {
+    float mean[4];
+    float inv_std[4];
+    float out_scale;
 };
 
 struct SellView {
@@ -131,6 +138,26 @@ void launch_mlp_grad(hipStream_t s, const float *P, int64_t n, const float *X, c
                      float *grad, float *loss, float *partials);
 void launch_adam(hipStream_t s, float *P, float *m, float *v, const float *g, int t, double lr,
                  double b1, double b2, double eps);
+
+// ---- learned warm start in the step (mdx_learned.hip) ----------------------
+void launch_kdiag(hipStream_t s, int64_t n_rows, int64_t n_real, SellView K, const double *Kv,
+                  double *kdiag);
+// b and the features (standardised into feat, raw into raw; either may be
+// null); partial |D^-1 b|^2
+void launch_rhs_features(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
+                         const double *Kv, const double *kdiag, const double *dinv,
+                         const StepParams &sp, const MlpNorm &nm, int64_t n_real, const double *V,
+                         const double *Vprev, const double *src, double *b, float *feat,
+                         float *raw, double *partial);
+void launch_two_residuals(hipStream_t s, const Tiling &t, SellView P, const double *Av,
+                          const double *dinv, float out_scale, const double *V, const float *y,
+                          const double *b, double *x, double *r_mlp, double *r_prev, int fp32_iter,
+                          double *partial);
+void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
+                             int rel_mode, Scalars *sc);
+void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
+                   double *r, float *r32, float *delta, const Scalars *sc);
+void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv);
 
 // ---- solver (mdx_solver.hip) ---------------------------------------------
 void launch_fill(hipStream_t s, int64_t n, double v, double *x);

@@ -1,0 +1,242 @@
+// Learned warm start for the PCG solve of each step.
+//
+// Per-node features at step n (after the ionic update):
+//   f0 = V^n,  f1 = V^n - V^{n-1},  f2 = s / Cm = (I_stim - I_ion) / Cm,
+//   f3 = (K V^n)_i / K_ii  (one neighbour aggregate from the stiffness SpMV)
+// are standardised and fed to the per-node MLP (mdx_mlp.hip), whose output
+// y predicts the increment: x_mlp = V^n + out_scale * y.  One pass over A
+// forms the initial residuals of both x_mlp and the previous-step guess V^n;
+// the MLP guess is used only if its ||D^-1 r0|| is smaller (and finite),
+// otherwise the previous step is (the fallback).
+//
+// k_rhs_features also serves as the recorder of training data: raw features
+// of every node, and after the solve the increment V^{n+1} - V^n.
+#include "mdx_device.h"
+#include "mdx_internal.h"
+
+namespace mdx {
+
+namespace {
+
+// b (FP64) and the features; partial |D^-1 b|^2
+__global__ __launch_bounds__(256) void k_rhs_features(
+    Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ kdiag,
+    const double *__restrict__ dinv, StepParams sp, MlpNorm nm, int64_t n_real,
+    const double *__restrict__ V, const double *__restrict__ Vprev, const double *__restrict__ src,
+    double *__restrict__ b, float4 *__restrict__ feat, float4 *__restrict__ raw,
+    double *__restrict__ partial)
+{
+    const int g = logical_group(t.groups);
+    const int lane = threadIdx.x & (SLICE - 1);
+    const double cK_old = (1.0 - sp.theta) * sp.dt;
+    double acc[1] = {0.0};
+    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
+    for (int tile = g * t.tpb; tile < t_end; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        double mv = 0.0, kv = 0.0;
+        for (int64_t e = beg; e < end; e += SLICE) {
+            const int32_t c = col[e];
+            const double vj = V[c];
+            mv += Mv[e] * (sp.cm * vj + sp.dt * src[c]);
+            kv += Kv[e] * vj;
+        }
+        const double bi = sp.chi * mv - cK_old * kv;
+        b[row] = bi;
+        const double db = dinv[row] * bi;
+        acc[0] += db * db;
+        const double vi = V[row];
+        const double kd = kdiag[row];
+        float4 f;
+        f.x = (float)vi;
+        f.y = (float)(vi - Vprev[row]);
+        f.z = (float)(src[row] / sp.cm);
+        f.w = (float)(kd != 0.0 ? kv / kd : 0.0);
+        if (raw && row < n_real) raw[row] = f;
+        if (feat) {
+            float4 h;
+            h.x = (f.x - nm.mean[0]) * nm.inv_std[0];
+            h.y = (f.y - nm.mean[1]) * nm.inv_std[1];
+            h.z = (f.z - nm.mean[2]) * nm.inv_std[2];
+            h.w = (f.w - nm.mean[3]) * nm.inv_std[3];
+            feat[row] = h;
+        }
+    }
+    write_partials<1>(acc, partial, t.groups, g);
+}
+
+// r_mlp = b - A x_mlp with x_mlp = V + s y formed per gathered column, and
+// r_prev = b - A V, in one pass over A; partials of r.z and z.z for both
+// (rounded to FP32 first when the iteration runs in FP32).
+__global__ __launch_bounds__(256) void k_two_residuals(
+    Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ Av, const double *__restrict__ dinv, float out_scale,
+    const double *__restrict__ V, const float *__restrict__ y, const double *__restrict__ b,
+    double *__restrict__ x, double *__restrict__ r_mlp, double *__restrict__ r_prev, int fp32_iter,
+    double *__restrict__ partial)
+{
+    const int g = logical_group(t.groups);
+    const int lane = threadIdx.x & (SLICE - 1);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
+    for (int tile = g * t.tpb; tile < t_end; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        double am = 0.0, ap = 0.0;
+        for (int64_t e = beg; e < end; e += SLICE) {
+            const int32_t c = col[e];
+            const double a = Av[e], vj = V[c];
+            am += a * (vj + (double)out_scale * (double)y[c]);
+            ap += a * vj;
+        }
+        const double vi = V[row];
+        const double xi = vi + (double)out_scale * (double)y[row];
+        x[row] = xi;
+        const double rm = b[row] - am, rp = b[row] - ap, di = dinv[row];
+        r_mlp[row] = rm;
+        r_prev[row] = rp;
+        if (fp32_iter) {
+            const float rmf = (float)rm, rpf = (float)rp, df = (float)di;
+            const float zmf = df * rmf, zpf = df * rpf;
+            acc[0] += (double)rmf * (double)zmf;
+            acc[1] += (double)zmf * (double)zmf;
+            acc[2] += (double)rpf * (double)zpf;
+            acc[3] += (double)zpf * (double)zpf;
+        } else {
+            const double zm = di * rm, zp = di * rp;
+            acc[0] += rm * zm;
+            acc[1] += zm * zm;
+            acc[2] += rp * zp;
+            acc[3] += zp * zp;
+        }
+    }
+    write_partials<4>(acc, partial, t.groups, g);
+}
+
+// choose the guess; scalars of the PCG initialisation
+__global__ __launch_bounds__(256) void k_init_finalize_ws(int groups, const double *__restrict__ p4,
+                                                          const double *__restrict__ p1,
+                                                          int rel_mode, Scalars *__restrict__ sc)
+{
+    double v[4], w[1];
+    reduce_partials<4>(p4, groups, v);
+    reduce_partials<1>(p1, groups, w);
+    if (threadIdx.x != 0) return;
+    const bool finite = v[1] == v[1] && v[1] < 1e300;
+    const bool use = finite && v[1] < v[3];
+    const double rz = use ? v[0] : v[2];
+    const double z0 = sqrt(use ? v[1] : v[3]);
+    const double db = sqrt(w[0]);
+    sc->use_mlp = use ? 1 : 0;
+    sc->rho[0] = rz;
+    sc->z0 = z0;
+    sc->znorm = z0;
+    sc->ref = rel_mode == 1 ? db : z0;
+    sc->floor_ = 1e-15 * db;
+    sc->done = (z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
+    sc->iters = 0;
+    sc->replace = 0;
+    sc->redirect = 0;
+    sc->it_next = 0;
+}
+
+// fallback: r = r_prev, x = V; then the FP32 residual / correction if the
+// iteration runs in FP32
+__global__ __launch_bounds__(256) void k_select(int64_t n, const double *__restrict__ V,
+                                                const double *__restrict__ r_prev,
+                                                double *__restrict__ x, double *__restrict__ r,
+                                                float *__restrict__ r32, float *__restrict__ delta,
+                                                const Scalars *__restrict__ sc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!sc->use_mlp) {
+        x[i] = V[i];
+        r[i] = r_prev[i];
+    }
+    if (r32) {
+        r32[i] = (float)r[i];
+        delta[i] = 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_record_dv(int64_t n, const double *__restrict__ Vold,
+                                                   const double *__restrict__ Vnew,
+                                                   float *__restrict__ dv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dv[i] = (float)(Vnew[i] - Vold[i]);
+}
+
+__global__ __launch_bounds__(256) void k_kdiag(int64_t n_rows, int64_t n_real,
+                                               const int64_t *__restrict__ slice_ptr,
+                                               const int32_t *__restrict__ col,
+                                               const double *__restrict__ Kv,
+                                               double *__restrict__ kdiag)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    double d = 0.0;
+    if (r < n_real) {
+        const int64_t sl = r / SLICE;
+        const int lane = (int)(r % SLICE);
+        for (int64_t e = slice_ptr[sl] + lane; e < slice_ptr[sl + 1]; e += SLICE)
+            if (col[e] == r) d += Kv[e];
+    }
+    kdiag[r] = d;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+void launch_kdiag(hipStream_t s, int64_t n_rows, int64_t n_real, SellView K, const double *Kv,
+                  double *kdiag)
+{
+    hipLaunchKernelGGL(k_kdiag, dim3(blocks_for(n_rows)), dim3(256), 0, s, n_rows, n_real,
+                       K.slice_ptr, K.col, Kv, kdiag);
+}
+
+void launch_rhs_features(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
+                         const double *Kv, const double *kdiag, const double *dinv,
+                         const StepParams &sp, const MlpNorm &nm, int64_t n_real, const double *V,
+                         const double *Vprev, const double *src, double *b, float *feat,
+                         float *raw, double *partial)
+{
+    hipLaunchKernelGGL(k_rhs_features, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv,
+                       Kv, kdiag, dinv, sp, nm, n_real, V, Vprev, src, b, (float4 *)feat,
+                       (float4 *)raw, partial);
+}
+
+void launch_two_residuals(hipStream_t s, const Tiling &t, SellView P, const double *Av,
+                          const double *dinv, float out_scale, const double *V, const float *y,
+                          const double *b, double *x, double *r_mlp, double *r_prev, int fp32_iter,
+                          double *partial)
+{
+    hipLaunchKernelGGL(k_two_residuals, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av,
+                       dinv, out_scale, V, y, b, x, r_mlp, r_prev, fp32_iter, partial);
+}
+
+void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
+                             int rel_mode, Scalars *sc)
+{
+    hipLaunchKernelGGL(k_init_finalize_ws, dim3(1), dim3(TILE), 0, s, t.groups, p4, p1, rel_mode, sc);
+}
+
+void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
+                   double *r, float *r32, float *delta, const Scalars *sc)
+{
+    hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(256), 0, s, n, V, r_prev, x, r, r32,
+                       delta, sc);
+}
+
+void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_record_dv, dim3(blocks_for(n)), dim3(256), 0, s, n, Vold, Vnew, dv);
+}
+
+}  // namespace mdx

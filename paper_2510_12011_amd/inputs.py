@@ -211,3 +211,115 @@ def slab_precision(h: float = 0.05, n_steps: int = 10000, precision: str = "mixe
     sp.precision = precision
     sp.name = f"slab_h{h:g}_{precision}"
     return sp
+
+
+# ---------------------------------------------------------------------------
+# ellipsoidal shells (ventricle-like)
+# ---------------------------------------------------------------------------
+def ellipsoid_shell(a: float = 35.0, b: float = 30.0, c: float = 45.0, wall: float = 9.0,
+                    n_nodes: int = 200_000, theta0_deg: float = 12.0,
+                    fibre_endo_deg: float = 60.0, fibre_epi_deg: float = -60.0,
+                    seed: int = 0, jitter: float = 0.1) -> Mesh:
+    """Truncated ellipsoidal shell: epicardial semi-axes (a, b, c) in mm
+    (c along z, the long axis), wall thickness `wall`, cut at the equatorial
+    plane z = 0 and open at the apex (polar angle < theta0).
+
+    Built as a curvilinear hexahedral grid in (depth, polar angle, azimuth)
+    -- azimuth periodic -- split into Kuhn tets, with a seeded interior jitter
+    of `jitter` of the local spacing in the polar and azimuthal directions.
+    Grid counts are chosen for about `n_nodes` nodes with cells of similar
+    size in all three directions.  Fibres: helical angle varying linearly
+    through the wall from `fibre_endo_deg` (endocardium) to `fibre_epi_deg`
+    (epicardium), measured from the circumferential direction towards the
+    long axis.  Region tag 0 everywhere; grid holds the unjittered
+    coordinates."""
+    th0, th1 = np.deg2rad(theta0_deg), np.pi / 2
+    rm = (a + b + c) / 3.0                         # mean epicardial radius
+    r_in = 1.0 - wall / rm                         # inner surface as a radial fraction
+    # cell counts: depth n_r, polar n_t, azimuth n_p (periodic)
+    len_t = (th1 - th0) * (rm - 0.5 * wall)
+    len_p = 2 * np.pi * (rm - 0.5 * wall) * np.sin(0.5 * (th0 + th1))
+    h = (wall * len_t * len_p / n_nodes) ** (1.0 / 3.0)
+    n_r = max(2, int(round(wall / h)))
+    n_t = max(4, int(round(len_t / h)))
+    n_p = max(8, int(round(len_p / h)))
+    rr = np.linspace(r_in, 1.0, n_r + 1)
+    tt = np.linspace(th0, th1, n_t + 1)
+    pp = np.arange(n_p) * (2 * np.pi / n_p)
+    R, TT, PP = np.meshgrid(rr, tt, pp, indexing="ij")
+    rng = np.random.default_rng(seed)
+    if jitter > 0:
+        inner = (np.arange(n_t + 1) > 0) & (np.arange(n_t + 1) < n_t)
+        dt_, dp_ = (th1 - th0) / n_t, 2 * np.pi / n_p
+        jt = rng.uniform(-1, 1, TT.shape) * jitter * dt_
+        jp = rng.uniform(-1, 1, PP.shape) * jitter * dp_
+        TT = TT + jt * inner[None, :, None]
+        PP = PP + jp
+    def to_xyz(R, TT, PP):
+        return np.stack([a * R * np.sin(TT) * np.cos(PP), b * R * np.sin(TT) * np.sin(PP),
+                         c * R * np.cos(TT)], axis=-1)
+    xyz = to_xyz(R, TT, PP).reshape(-1, 3)
+    Rg, Tg, Pg = np.meshgrid(rr, tt, pp, indexing="ij")
+    grid = to_xyz(Rg, Tg, Pg).reshape(-1, 3)
+
+    def nid(i, j, k):
+        return (i * (n_t + 1) + j) * n_p + (k % n_p)
+
+    ci, cj, ck = np.meshgrid(np.arange(n_r), np.arange(n_t), np.arange(n_p), indexing="ij")
+    ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
+    unit = np.eye(3, dtype=np.int64)
+    tets = []
+    for perm in itertools.permutations(range(3)):
+        offs = [np.zeros(3, np.int64)]
+        for ax in perm:
+            offs.append(offs[-1] + unit[ax])
+        cols = [nid(ci + o[0], cj + o[1], ck + o[2]) for o in offs]
+        tets.append(np.stack(cols, axis=1))
+    tets = np.stack(tets, axis=1).reshape(-1, 4).astype(np.int64)
+    # orient positively
+    p = xyz[tets]
+    det = np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]))
+    flip = det < 0
+    tets[flip, 2], tets[flip, 3] = tets[flip, 3].copy(), tets[flip, 2].copy()
+    tets = tets.astype(np.int32)
+    # helical fibres at element centroids (in the unjittered parametrisation)
+    cen_r = rr[ci][:, None].repeat(6, axis=1).ravel() + 0.5 * (rr[1] - rr[0])
+    cen_t = tt[cj][:, None].repeat(6, axis=1).ravel() + 0.5 * (tt[1] - tt[0])
+    cen_p = pp[ck][:, None].repeat(6, axis=1).ravel() + np.pi / n_p
+    depth = (cen_r - r_in) / (1.0 - r_in)                 # 0 endo .. 1 epi
+    alpha = np.deg2rad(fibre_endo_deg + (fibre_epi_deg - fibre_endo_deg) * depth)
+    e_p = np.stack([-a * np.sin(cen_p), b * np.cos(cen_p), np.zeros_like(cen_p)], axis=1)
+    e_t = np.stack([a * np.cos(cen_t) * np.cos(cen_p), b * np.cos(cen_t) * np.sin(cen_p),
+                    -c * np.sin(cen_t)], axis=1)
+    e_p /= np.linalg.norm(e_p, axis=1, keepdims=True)
+    e_t /= np.linalg.norm(e_t, axis=1, keepdims=True)
+    fib = np.cos(alpha)[:, None] * e_p + np.sin(alpha)[:, None] * e_t
+    mesh = Mesh(xyz=xyz, tets=tets, grid=grid, fibre=fib, region=np.zeros(tets.shape[0], np.int32),
+                shape=(n_r, n_t, n_p))
+    mesh.r_frac = np.repeat(rr, (n_t + 1) * n_p)        # per-node radial fraction
+    mesh.r_in = r_in
+    return mesh
+
+
+def endocardial_site(mesh: Mesh, seed: int, radius: float = 1.5) -> np.ndarray:
+    """Nodes within `radius` mm of a random endocardial node (seeded)."""
+    endo = np.nonzero(np.isclose(mesh.r_frac, mesh.r_in))[0]
+    rng = np.random.default_rng(seed)
+    centre = mesh.grid[endo[rng.integers(endo.shape[0])]]
+    d = np.linalg.norm(mesh.grid - centre, axis=1)
+    return np.nonzero(d <= radius)[0].astype(np.int32)
+
+
+def shell_run(n_nodes: int = 1_200_000, ionic: str = "tt", dt: float = 0.02, n_steps: int = 20000,
+              site_seed: int = 1, mesh_seed: int = 1000, sigma_scale: float = 1.0,
+              rtol: float = 1e-8, rel_mode: int = 1, mesh: Mesh | None = None) -> RunSpec:
+    """Ventricle-like shell run: sigma (0.17, 0.019) S/m times sigma_scale,
+    chi 140/mm, Cm 0.01 uF/mm^2, 0.5 uA/mm^2 for 2 ms at a random endocardial
+    site; relative tolerance 1e-8 of ||D^-1 b||."""
+    if mesh is None:
+        mesh = ellipsoid_shell(n_nodes=n_nodes, seed=mesh_seed)
+    stim = Stimulus(endocardial_site(mesh, site_seed), 0.0, 2.0, 50.0 * UA_PER_CM2_TO_PER_MM2)
+    return RunSpec(name=f"shell_{mesh.n_nodes}_site{site_seed}", mesh=mesh,
+                   sigma_l=0.17 * sigma_scale, sigma_t=0.019 * sigma_scale, chi=140.0, cm=0.01,
+                   theta=0.5, ionic=ionic, dt=dt, n_steps=n_steps, stimuli=[stim], rtol=rtol,
+                   rel_mode=rel_mode)

@@ -1,0 +1,137 @@
+"""Learned warm start: record training data from the plain solver, train the
+per-node network on the GPU with the library's own kernels (mdx_mlp_grad,
+mdx_mlp_adam), install it (mdx_set_mlp) and measure what it saves.
+
+Torch is used here only as device memory and for data plumbing (selecting,
+standardising and batching recorded samples); the network's forward pass,
+gradient and optimiser step are the library's BF16-MFMA kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+
+import numpy as np
+
+from . import _lib as L
+
+N_PARAM = 8705
+_SHAPES = [((64, 4), 4), ((64,), 0), ((64, 64), 64), ((64,), 0), ((64, 64), 64), ((64,), 0),
+           ((64,), 64), ((1,), 0)]
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-uniform weights (bound sqrt(6 / fan_in)), zero biases, FP32, in the
+    library's parameter layout."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape, fan_in in _SHAPES:
+        if fan_in:
+            lim = np.sqrt(6.0 / fan_in)
+            parts.append(rng.uniform(-lim, lim, shape).ravel())
+        else:
+            parts.append(np.zeros(int(np.prod(shape))))
+    theta = np.concatenate(parts).astype(np.float32)
+    assert theta.shape[0] == N_PARAM
+    return theta
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def record(sim, n_steps: int, every: int = 10, front: float = 0.02, frac: float = 0.05,
+           seed: int = 0):
+    """Advance `sim` by n_steps; on every `every`-th step record (raw
+    features, V^{n+1} - V^n) of all nodes whose increment exceeds `front` mV
+    plus a random `frac` of the others.  Returns device tensors X [N, 4],
+    dV [N]."""
+    import torch
+    dev = f"cuda:{sim.device}"
+    n = sim.n
+    Xr = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    dVr = torch.empty(n, dtype=torch.float32, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    xs, ds = [], []
+    done = 0
+    while done < n_steps:
+        skip = min(every - 1, n_steps - done - 1)
+        if skip > 0:
+            sim.run(skip)
+        sim._check(L.lib().mdx_set_recorder(sim._h, _p(Xr), _p(dVr)))
+        sim.run(1)
+        sim._check(L.lib().mdx_set_recorder(sim._h, None, None))
+        keep = (dVr.abs() > front) | (torch.rand(n, generator=g, device=dev) < frac)
+        idx = keep.nonzero().squeeze(1)
+        xs.append(Xr[idx].clone())
+        ds.append(dVr[idx].clone())
+        done += skip + 1
+    return torch.cat(xs), torch.cat(ds)
+
+
+def fit(sim, X, dV, epochs: int = 10, batch: int = 8192, lr: float = 2e-3, seed: int = 0,
+        theta0: np.ndarray | None = None, log=None):
+    """Train on (X, dV).  Returns (params float32 [8705], norm float64 [9],
+    per-epoch mean loss)."""
+    import torch
+    dev = X.device
+    mean = X.mean(0)
+    std = X.std(0).clamp_min(1e-6)
+    out_scale = dV.std().clamp_min(1e-6)
+    Xn = ((X - mean) / std).contiguous()
+    T = (dV / out_scale).contiguous()
+    n = Xn.shape[0]
+    P = torch.tensor(init_params(seed) if theta0 is None else theta0, dtype=torch.float32,
+                     device=dev)
+    M = torch.zeros_like(P)
+    Vm = torch.zeros_like(P)
+    G = torch.empty_like(P)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    nb = L.lib().mdx_mlp_grad_scratch(batch)
+    scratch = torch.empty(nb // 4 + 64, dtype=torch.float32, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    t = 0
+    history = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g, device=dev)
+        tot, cnt = 0.0, 0
+        for s in range(0, n - batch + 1, batch):
+            idx = perm[s:s + batch]
+            xb, tb = Xn[idx].contiguous(), T[idx].contiguous()
+            t += 1
+            sim._check(L.lib().mdx_mlp_grad(sim._h, _p(P), batch, _p(xb), _p(tb), _p(G),
+                                            _p(loss), _p(scratch), nb))
+            sim._check(L.lib().mdx_mlp_adam(sim._h, _p(P), _p(M), _p(Vm), _p(G), t, lr, 0.9,
+                                            0.999, 1e-8))
+            if cnt % 16 == 0:
+                tot += float(loss.item())
+                cnt += 1
+            else:
+                cnt += 1
+        history.append(tot / max(1, (cnt + 15) // 16))
+        if log:
+            log(f"epoch {ep}: loss {history[-1]:.4f}")
+    norm = np.concatenate([mean.double().cpu().numpy(), std.double().cpu().numpy(),
+                           [float(out_scale)]])
+    return P.cpu().numpy(), norm, history
+
+
+def install(sim, params: np.ndarray, norm: np.ndarray):
+    p = np.ascontiguousarray(params, np.float32)
+    nm = np.ascontiguousarray(norm, np.float64)
+    sim._check(L.lib().mdx_set_mlp(sim._h, p.ctypes.data_as(C.c_void_p),
+                                   nm.ctypes.data_as(C.c_void_p)))
+
+
+def timed_run(sim, n_steps: int):
+    """Run n_steps; returns (seconds, iterations per step, fallbacks)."""
+    import torch
+    f0 = sim.stats()["fallbacks"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(n_steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return el, sim.iterations(n_steps), sim.stats()["fallbacks"] - f0
