@@ -197,10 +197,78 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
  *   MDX_TUNE_ITER_SCHEME PCG iteration as three kernels (0: SpMV, update,
  *                        direction; default) or two kernels (1: the
  *                        direction is formed per gathered column inside
- *                        the SpMV).
- * Takes effect at the next mdx_prepare / mdx_run. */
-enum { MDX_TUNE_MAX_GROUPS = 1, MDX_TUNE_ITER_SCHEME = 2 };
+ *                        the SpMV);
+ *   MDX_TUNE_FORMAT      batched context: storage the iteration's FP32 SpMV
+ *                        reads, 0 sliced ELL (default; 1 lane per row) or
+ *                        1 CSR (no padding; 8 lanes per row);
+ *   MDX_TUNE_LANES_PER_ROW   batched context: lanes of a wavefront per row in
+ *                        that SpMV: 1, 2 or 4 for sliced ELL (64, 32 or 16
+ *                        rows per wavefront), 4, 8 or 16 for CSR;
+ *   MDX_TUNE_TILES_PER_GROUP batched context: 256-row tiles per workgroup
+ *                        (default: about 4096 workgroups);
+ *   MDX_TUNE_GRAPH       batched context: 1 to replay each time step's work
+ *                        up to the convergence check as a captured HIP graph
+ *                        (one per iteration count and buffer rotation), 0 to
+ *                        launch it kernel by kernel (default 0).
+ * MAX_GROUPS and ITER_SCHEME take effect at the next mdx_prepare / mdx_run;
+ * the batched keys need a prepared batched context and act at once. */
+enum {
+    MDX_TUNE_MAX_GROUPS = 1,
+    MDX_TUNE_ITER_SCHEME = 2,
+    MDX_TUNE_LANES_PER_ROW = 3,
+    MDX_TUNE_TILES_PER_GROUP = 4,
+    MDX_TUNE_GRAPH = 5,
+    MDX_TUNE_FORMAT = 6
+};
 MDX_API mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value);
+
+/* ---- batched form ------------------------------------------------------- */
+/* Many independent meshes ("instances") in one context, each its own
+ * monodomain problem (Eq. 1, discretised as Eq. 2-3, its own conductivities
+ * through region tags and its own stimuli), advanced together as one
+ * block-diagonal system.  node_ptr: HOST [n_inst + 1], instance i owns the
+ * nodes [node_ptr[i], node_ptr[i+1]) of the concatenated xyz (node_ptr[0] =
+ * 0, strictly increasing, node_ptr[n_inst] = n_nodes); every element's nodes
+ * must lie in one instance (else MDX_ERR_BAD_MESH).  The remaining arguments
+ * and checks are those of mdx_set_mesh over the concatenation.  Inside, each
+ * instance is ordered by reverse Cuthill-McKee and starts on a 256-row
+ * boundary.  A batched context solves with the mixed-precision form
+ * (MDX_PREC_MIXED or MDX_PREC_MIXED_GATES32; MDX_PREC_FP64 and MDX_WS_MLP
+ * return MDX_ERR_UNSUPPORTED from mdx_run), with its own CG scalars,
+ * stopping test and iteration count per instance: finished instances stop
+ * iterating while the others continue.  All other calls work on the
+ * concatenated node numbering. */
+MDX_API mdx_status mdx_set_mesh_batch(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr,
+                                      int64_t n_nodes, const double *xyz,
+                                      double unit_conversion, int64_t n_tets,
+                                      const int32_t *tets, const int32_t *region,
+                                      const double *fibre);
+/* PCG iterations of the last n steps of a batched context, per instance:
+ * iters[s * n_inst + i] (HOST, n * n_inst; -1: the solve hit max_iter). */
+MDX_API mdx_status mdx_get_instance_iterations(mdx_ctx *ctx, int64_t n, int32_t *iters);
+
+#define MDX_TUNE_MAX_CANDIDATES 32
+typedef struct {
+    int32_t format;             /* installed choice: MDX_TUNE_FORMAT value    */
+    int32_t lanes_per_row;
+    int32_t tiles_per_group;
+    int32_t n_candidates;
+    double seconds;             /* its mean SpMV time                        */
+    double bytes;               /* algorithmic bytes per SpMV: 8 nnz + 8 n    */
+    int32_t cand_format[MDX_TUNE_MAX_CANDIDATES];
+    int32_t cand_lanes_per_row[MDX_TUNE_MAX_CANDIDATES];
+    int32_t cand_tiles_per_group[MDX_TUNE_MAX_CANDIDATES];
+    double cand_seconds[MDX_TUNE_MAX_CANDIDATES];
+} mdx_tune_report;
+/* Autotuner of a prepared batched context: times reps launches (1..1000) of
+ * the iteration's FP32 SpMV on the context's own matrix for sliced ELL with
+ * 1, 2, 4 lanes per row (64, 32, 16 rows per wavefront) and CSR with 4, 8,
+ * 16 lanes per row (16, 8, 4 rows per wavefront), each with 1, 2, 4, 8 tiles
+ * per workgroup, and installs the fastest (as the MDX_TUNE_FORMAT,
+ * MDX_TUNE_LANES_PER_ROW and MDX_TUNE_TILES_PER_GROUP keys would).  Results
+ * of later steps change only by the FP32 summation order of the SpMV.
+ * report (HOST, may be NULL) receives every candidate's time. */
+MDX_API mdx_status mdx_autotune(mdx_ctx *ctx, int32_t reps, mdx_tune_report *report);
 
 /* ---- state (checkpoint / resume, parity checks) ----------------------- */
 /* V^k, V^{k-1}, states u (SoA, [nstates][n_nodes]), LAT, LRT and the step

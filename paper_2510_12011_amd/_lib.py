@@ -29,6 +29,8 @@ MDX_REL_INITIAL, MDX_REL_RHS = 0, 1
 MDX_PREC_FP64, MDX_PREC_MIXED, MDX_PREC_MIXED_GATES32 = 0, 1, 2
 MDX_MAT_M, MDX_MAT_K, MDX_MAT_A = 0, 1, 2
 MDX_TUNE_MAX_GROUPS, MDX_TUNE_ITER_SCHEME = 1, 2
+MDX_TUNE_LANES_PER_ROW, MDX_TUNE_TILES_PER_GROUP, MDX_TUNE_GRAPH, MDX_TUNE_FORMAT = 3, 4, 5, 6
+MDX_TUNE_MAX_CANDIDATES = 32
 
 
 class SolverOpts(C.Structure):
@@ -47,6 +49,16 @@ class Stats(C.Structure):
                 ("host_wait_seconds", C.c_double), ("fallbacks", C.c_int64)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("format", C.c_int32), ("lanes_per_row", C.c_int32),
+                ("tiles_per_group", C.c_int32), ("n_candidates", C.c_int32),
+                ("seconds", C.c_double), ("bytes", C.c_double),
+                ("cand_format", C.c_int32 * MDX_TUNE_MAX_CANDIDATES),
+                ("cand_lanes_per_row", C.c_int32 * MDX_TUNE_MAX_CANDIDATES),
+                ("cand_tiles_per_group", C.c_int32 * MDX_TUNE_MAX_CANDIDATES),
+                ("cand_seconds", C.c_double * MDX_TUNE_MAX_CANDIDATES)]
+
+
 class MdxError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"mdx status {status}: {message}")
@@ -62,6 +74,10 @@ _SIGS = {
     "mdx_destroy": (None, [P]),
     "mdx_last_error": (C.c_char_p, [P]),
     "mdx_set_mesh": (C.c_int, [P, C.c_int64, P, C.c_double, C.c_int64, P, P, P]),
+    "mdx_set_mesh_batch": (C.c_int, [P, C.c_int32, P, C.c_int64, P, C.c_double, C.c_int64, P, P,
+                                     P]),
+    "mdx_get_instance_iterations": (C.c_int, [P, C.c_int64, P]),
+    "mdx_autotune": (C.c_int, [P, C.c_int32, C.POINTER(TuneReport)]),
     "mdx_add_conductivity": (C.c_int, [P, C.c_int32, P, C.c_double, C.c_double]),
     "mdx_set_tissue": (C.c_int, [P, C.c_double, C.c_double, C.c_double]),
     "mdx_set_ionic": (C.c_int, [P, C.c_int32, C.c_int32, P]),

@@ -51,6 +51,8 @@ struct Layout {
         partial, scalars;
     size_t A32, dinv32, r32, p32, q32, delta, g32;   // mixed-precision form
     size_t kdiag, feat, mlp_y, mlp_params;            // learned warm start
+    size_t tile_real, grp, inst_grp, bsc, sptr_t, col_t, A32_t;   // batched form
+    size_t csr_ptr, csr_col, csr_val;
     size_t total;
     size_t x_xyz, x_tets, x_fibre, x_sig, x_vol, x_ek, x_cptr, x_contrib, x_total;
 };
@@ -103,6 +105,27 @@ struct mdx_ctx {
     // launch-shape tuning
     int max_groups = kMaxGroups;
     int iter_scheme = 0;
+
+    // batched form: instances, each a contiguous row range starting on a
+    // TILE boundary (a single-mesh context has one instance, rows [0, n))
+    bool batched = false;
+    int n_inst = 1;
+    std::vector<int64_t> inst_node_ptr;   // original numbering, n_inst + 1
+    std::vector<int64_t> inst_row0;       // internal rows, n_inst + 1 (last: npad)
+    std::vector<int64_t> inst_nnz;
+    std::vector<int32_t> tile_real;       // real rows of each tile
+    int64_t nslots_lpr[3] = {0, 0, 0};    // slots of the lanes-per-row layouts 1, 2, 4
+    int fmt = 0;                          // iteration SpMV format: 0 sliced ELL, 1 CSR
+    bool csr_built = false;
+    int lpr = 1;                          // lanes per row of the iteration SpMV
+    int lpr_built = 0;                    // layout held in sptr_t / col_t / A32_t (0: none)
+    int tpb_b = 1;                        // tiles per workgroup
+    SegTiling seg{};
+    BScalars *bsc_host = nullptr;         // pinned, n_inst
+    std::vector<int32_t> inst_iters_hist; // per step, n_inst each
+    bool use_graph = false;
+    hipStream_t own_stream = nullptr;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (iterations, rotation)
 
     // profiling: event pairs around the SpMV launches of every
     // `profile_every`-th step (0: off)
@@ -320,6 +343,21 @@ void compute_layout(mdx_ctx *c)
     L.feat = take(sizeof(float) * 4 * np);
     L.mlp_y = take(sizeof(float) * np);
     L.mlp_params = take(sizeof(float) * mlp_nparams());
+    {
+        const size_t n_tiles = np / TILE, ni = (size_t)c->n_inst;
+        L.tile_real = take(sizeof(int32_t) * n_tiles);
+        L.grp = take(sizeof(int4) * (n_tiles + ni));
+        L.inst_grp = take(sizeof(int32_t) * (ni + 1));
+        L.bsc = take(sizeof(BScalars) * ni);
+        const size_t alt = c->batched ? (size_t)std::max(c->nslots_lpr[1], c->nslots_lpr[2]) : 1;
+        L.sptr_t = take(sizeof(int64_t) * (c->batched ? np / (SLICE / 4) + 1 : 1));
+        L.col_t = take(sizeof(int32_t) * alt);
+        L.A32_t = take(sizeof(float) * alt);
+        const size_t cnz = c->batched ? (size_t)c->nnz : 1;
+        L.csr_ptr = take(sizeof(int32_t) * (c->batched ? np + 1 : 1));
+        L.csr_col = take(sizeof(int32_t) * cnz);
+        L.csr_val = take(sizeof(float) * cnz);
+    }
     L.total = o;
 
     o = 0;
@@ -353,7 +391,8 @@ mdx_status copy_vec_out(mdx_ctx *ctx, const double *dsrc, double *host)
 mdx_status copy_vec_in(mdx_ctx *ctx, const double *host, double *ddst)
 {
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    for (int64_t r = 0; r < ctx->npad; ++r) ctx->stage[r] = r < ctx->n ? host[ctx->perm[r]] : 0.0;
+    for (int64_t r = 0; r < ctx->npad; ++r)
+        ctx->stage[r] = ctx->perm[r] >= 0 ? host[ctx->perm[r]] : 0.0;
     HIPCHK(hipMemcpyAsync(ddst, ctx->stage, sizeof(double) * ctx->npad, hipMemcpyHostToDevice,
                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -373,7 +412,7 @@ StepParams step_params(const mdx_ctx *c)
 }
 
 // Rebuild istim if the set of stimuli active at step k changed.
-mdx_status update_stimulus(mdx_ctx *ctx, int64_t k, bool &any)
+mdx_status update_stimulus(mdx_ctx *ctx, hipStream_t st, int64_t k, bool &any)
 {
     std::vector<char> want(ctx->stims.size(), 0);
     any = false;
@@ -386,15 +425,572 @@ mdx_status update_stimulus(mdx_ctx *ctx, int64_t k, bool &any)
     }
     if (want == ctx->active) return MDX_OK;
     double *istim = ctx->dev<double>(ctx->L.istim);
-    launch_fill(ctx->stream, ctx->npad, 0.0, istim);
+    launch_fill(st, ctx->npad, 0.0, istim);
     for (size_t s = 0; s < ctx->stims.size(); ++s)
         if (want[s])
-            launch_stim_add(ctx->stream, (int64_t)ctx->stims[s].nodes.size(),
+            launch_stim_add(st, (int64_t)ctx->stims[s].nodes.size(),
                             ctx->dev<int32_t>(ctx->L.stim_idx) + ctx->stim_off[s],
                             ctx->stims[s].amp, istim);
     HIPCHK(hipGetLastError());
     ctx->active = want;
     return MDX_OK;
+}
+
+void release_graphs(mdx_ctx *ctx)
+{
+    for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+}
+
+// rows covered by the pointwise kernels and their padding mask: the real
+// rows are a prefix in a single-mesh context and interleaved with padding
+// (masked per tile) in a batched one
+int64_t span_rows(const mdx_ctx *c) { return c->batched ? c->npad : c->n; }
+const int32_t *row_mask(const mdx_ctx *c)
+{
+    return c->batched ? c->dev<int32_t>(c->L.tile_real) : nullptr;
+}
+
+// group table of the segmented kernels: instance i's tiles in runs of tpb
+mdx_status build_groups(mdx_ctx *c, int tpb, std::vector<int4> &grp, std::vector<int32_t> &ig)
+{
+    grp.clear();
+    ig.assign(c->n_inst + 1, 0);
+    for (int i = 0; i < c->n_inst; ++i) {
+        ig[i] = (int32_t)grp.size();
+        const int t0 = (int)(c->inst_row0[i] / TILE), t1 = (int)(c->inst_row0[i + 1] / TILE);
+        for (int t = t0; t < t1; t += tpb) grp.push_back(make_int4(i, t, std::min(t + tpb, t1), 0));
+    }
+    ig[c->n_inst] = (int32_t)grp.size();
+    if ((int64_t)grp.size() > kPartialCap)
+        return fail(c, MDX_ERR_INVALID_ARG, "%zu workgroups exceed %d: use more tiles per group",
+                    grp.size(), kPartialCap);
+    return MDX_OK;
+}
+
+mdx_status install_groups(mdx_ctx *c, int tpb)
+{
+    mdx_ctx *ctx = c;   // for HIPCHK
+    std::vector<int4> grp;
+    std::vector<int32_t> ig;
+    if (mdx_status e = build_groups(c, tpb, grp, ig)) return e;
+    HIPCHK(hipMemcpyAsync(c->dev<int4>(c->L.grp), grp.data(), sizeof(int4) * grp.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->dev<int32_t>(c->L.inst_grp), ig.data(), sizeof(int32_t) * ig.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->seg.groups = (int)grp.size();
+    c->seg.n_inst = c->n_inst;
+    c->seg.grp = c->dev<int4>(c->L.grp);
+    c->seg.inst_grp = c->dev<int32_t>(c->L.inst_grp);
+    c->tpb_b = tpb;
+    release_graphs(c);
+    return MDX_OK;
+}
+
+// slice pointers of the lanes-per-row layout lpr (2 or 4)
+std::vector<int64_t> lpr_slices(const mdx_ctx *c, int lpr)
+{
+    const int H = SLICE / lpr;
+    const int64_t ns = c->npad / H;
+    std::vector<int64_t> sp(ns + 1, 0);
+    for (int64_t sl = 0; sl < ns; ++sl) {
+        int w = 0;
+        for (int l = 0; l < H; ++l) w = std::max(w, (c->rowlen[sl * H + l] + lpr - 1) / lpr);
+        sp[sl + 1] = sp[sl] + (int64_t)w * SLICE;
+    }
+    return sp;
+}
+
+// build the iteration matrix in layout lpr (2 or 4) into the alternative
+// arrays; lpr = 1 is the base layout and needs nothing
+mdx_status build_lpr_layout(mdx_ctx *c, int lpr)
+{
+    mdx_ctx *ctx = c;   // for HIPCHK
+    if (lpr == 1 || c->lpr_built == lpr) return MDX_OK;
+    std::vector<int64_t> sp = lpr_slices(c, lpr);
+    const int li = lpr == 2 ? 1 : 2;
+    if (sp.back() != c->nslots_lpr[li] || (int64_t)sp.size() - 1 != c->npad / (SLICE / lpr))
+        return fail(c, MDX_ERR_STATE, "internal layout inconsistent (lanes per row %d)", lpr);
+    HIPCHK(hipMemcpyAsync(c->dev<int64_t>(c->L.sptr_t), sp.data(), sizeof(int64_t) * sp.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    SellView base{c->dev<int64_t>(c->L.slice_ptr), c->dev<int32_t>(c->L.col)};
+    launch_relayout(c->stream, lpr, (int64_t)sp.size() - 1, c->dev<int64_t>(c->L.sptr_t), base,
+                    c->dev<float>(c->L.A32), c->dev<int32_t>(c->L.col_t), c->dev<float>(c->L.A32_t));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->lpr_built = lpr;
+    return MDX_OK;
+}
+
+// CSR copy of the FP32 iteration matrix (real entries only)
+mdx_status build_csr(mdx_ctx *c)
+{
+    mdx_ctx *ctx = c;   // for HIPCHK
+    if (c->csr_built) return MDX_OK;
+    if (c->nnz >= ((int64_t)1 << 31)) return fail(c, MDX_ERR_UNSUPPORTED, "CSR needs nnz < 2^31");
+    std::vector<int32_t> rp(c->npad + 1, 0);
+    for (int64_t r = 0; r < c->npad; ++r) rp[r + 1] = rp[r] + c->rowlen[r];
+    if (rp[c->npad] != c->nnz) return fail(c, MDX_ERR_STATE, "internal layout inconsistent (CSR)");
+    HIPCHK(hipMemcpyAsync(c->dev<int32_t>(c->L.csr_ptr), rp.data(), sizeof(int32_t) * rp.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    SellView base{c->dev<int64_t>(c->L.slice_ptr), c->dev<int32_t>(c->L.col)};
+    launch_build_csr(c->stream, c->npad, base, c->dev<float>(c->L.A32), c->dev<int32_t>(c->L.csr_ptr),
+                     c->dev<int32_t>(c->L.csr_col), c->dev<float>(c->L.csr_val));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->csr_built = true;
+    return MDX_OK;
+}
+
+// install format / lanes per row for the iteration SpMV (building its arrays)
+mdx_status set_iter_layout(mdx_ctx *c, int fmt, int lpr)
+{
+    if (fmt == 0 && lpr != 1 && lpr != 2 && lpr != 4)
+        return fail(c, MDX_ERR_INVALID_ARG, "sliced ELL takes 1, 2 or 4 lanes per row");
+    if (fmt == 1 && lpr != 4 && lpr != 8 && lpr != 16)
+        return fail(c, MDX_ERR_INVALID_ARG, "CSR takes 4, 8 or 16 lanes per row");
+    if (fmt == 0) {
+        if (mdx_status e = build_lpr_layout(c, lpr)) return e;
+    } else {
+        if (mdx_status e = build_csr(c)) return e;
+    }
+    c->fmt = fmt;
+    c->lpr = lpr;
+    release_graphs(c);
+    return MDX_OK;
+}
+
+IterMatrix iter_matrix(const mdx_ctx *c)
+{
+    const Layout &L = c->L;
+    IterMatrix A{};
+    A.format = c->fmt;
+    A.lpr = c->lpr;
+    if (c->fmt == 1) {
+        A.rptr = c->dev<int32_t>(L.csr_ptr);
+        A.col = c->dev<int32_t>(L.csr_col);
+        A.val = c->dev<float>(L.csr_val);
+    } else if (c->lpr == 1) {
+        A.sptr = c->dev<int64_t>(L.slice_ptr);
+        A.col = c->dev<int32_t>(L.col);
+        A.val = c->dev<float>(L.A32);
+    } else {
+        A.sptr = c->dev<int64_t>(L.sptr_t);
+        A.col = c->dev<int32_t>(L.col_t);
+        A.val = c->dev<float>(L.A32_t);
+    }
+    return A;
+}
+
+mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, bool batched,
+                         int64_t n_nodes, const double *xyz, double unit_conversion,
+                         int64_t n_tets, const int32_t *tets, const int32_t *region,
+                         const double *fibre)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    GUARD_BEGIN
+    if (n_nodes <= 0 || n_tets <= 0 || !xyz || !tets)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "empty mesh or null array");
+    if (n_nodes >= (int64_t)1 << 31 || n_tets >= (int64_t)1 << 27)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "mesh too large (n < 2^31, tets < 2^27)");
+    if (!(unit_conversion > 0.0) || !std::isfinite(unit_conversion))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "unit_conversion must be finite and > 0");
+    for (int64_t i = 0; i < 3 * n_nodes; ++i)
+        if (!std::isfinite(xyz[i]))
+            return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite coordinate at node %lld",
+                        (long long)(i / 3));
+    for (int64_t q = 0; q < 4 * n_tets; ++q)
+        if (tets[q] < 0 || tets[q] >= n_nodes)
+            return fail(ctx, MDX_ERR_BAD_MESH, "element %lld references node %d out of range",
+                        (long long)(q / 4), tets[q]);
+    if (node_ptr[0] != 0 || node_ptr[n_inst] != n_nodes)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "node_ptr must run from 0 to n_nodes");
+    for (int32_t i = 0; i < n_inst; ++i)
+        if (node_ptr[i + 1] <= node_ptr[i])
+            return fail(ctx, MDX_ERR_INVALID_ARG, "instance %d has no nodes", i);
+    std::vector<int32_t> inst_of(n_nodes);
+    for (int32_t i = 0; i < n_inst; ++i)
+        std::fill(inst_of.begin() + node_ptr[i], inst_of.begin() + node_ptr[i + 1], i);
+    for (int64_t e = 0; e < n_tets; ++e)
+        for (int a = 1; a < 4; ++a)
+            if (inst_of[tets[4 * e + a]] != inst_of[tets[4 * e]])
+                return fail(ctx, MDX_ERR_BAD_MESH, "element %lld joins two instances",
+                            (long long)e);
+    if (fibre)
+        for (int64_t q = 0; q < 3 * n_tets; ++q)
+            if (!std::isfinite(fibre[q]))
+                return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite fibre at element %lld",
+                            (long long)(q / 3));
+    std::vector<double> X(xyz, xyz + 3 * n_nodes);
+    for (double &v : X) v /= unit_conversion;
+    // element quality: |det J| > 1e-14 h^3
+    for (int64_t e = 0; e < n_tets; ++e) {
+        const int32_t *t = tets + 4 * e;
+        double d[3][3], h2 = 0.0;
+        for (int a = 1; a < 4; ++a)
+            for (int k = 0; k < 3; ++k) d[a - 1][k] = X[3 * t[a] + k] - X[3 * t[0] + k];
+        for (int a = 0; a < 4; ++a)
+            for (int b = a + 1; b < 4; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    double w = X[3 * t[a] + k] - X[3 * t[b] + k];
+                    s += w * w;
+                }
+                h2 = std::max(h2, s);
+            }
+        double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                     d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                     d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+        double h3 = h2 * std::sqrt(h2);
+        if (!(std::fabs(det) > 1e-14 * h3))
+            return fail(ctx, MDX_ERR_BAD_MESH, "degenerate element %lld (|det J| = %g)",
+                        (long long)e, std::fabs(det));
+    }
+
+    // adjacency, RCM (per connected component), instances one after another
+    std::vector<int64_t> gptr;
+    std::vector<int32_t> gadj;
+    node_graph(n_nodes, n_tets, tets, gptr, gadj);
+    std::vector<int32_t> order = rcm(n_nodes, gptr, gadj);
+    if (n_inst > 1)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return inst_of[a] < inst_of[b]; });
+    std::vector<int64_t> row0(n_inst + 1, 0);
+    for (int32_t i = 0; i < n_inst; ++i)
+        row0[i + 1] = row0[i] + (node_ptr[i + 1] - node_ptr[i] + TILE - 1) / TILE * TILE;
+    const int64_t npad = row0[n_inst];
+    if (npad >= ((int64_t)1 << 31))
+        return fail(ctx, MDX_ERR_INVALID_ARG, "padded row count exceeds 2^31");
+    std::vector<int32_t> perm(npad, -1), iperm(n_nodes);
+    {
+        int64_t q = 0;
+        for (int32_t i = 0; i < n_inst; ++i)
+            for (int64_t k = 0; k < node_ptr[i + 1] - node_ptr[i]; ++k) perm[row0[i] + k] = order[q++];
+    }
+    order.clear();
+    order.shrink_to_fit();
+    for (int64_t r = 0; r < npad; ++r)
+        if (perm[r] >= 0) iperm[perm[r]] = (int32_t)r;
+    std::vector<int32_t> tile_real(npad / TILE, 0);
+    for (int64_t r = 0; r < npad; ++r)
+        if (perm[r] >= 0) tile_real[r / TILE]++;
+
+    // sliced-ELL pattern over the padded rows (padding rows are empty)
+    const int64_t nslices = npad / SLICE;
+    std::vector<int32_t> rowlen(npad, 0);
+    std::vector<int64_t> inst_nnz(n_inst, 0);
+    int64_t nnz = 0, bw = 0;
+    for (int32_t i = 0; i < n_inst; ++i)
+        for (int64_t r = row0[i]; r < row0[i + 1]; ++r)
+            if (perm[r] >= 0) {
+                const int32_t o = perm[r];
+                rowlen[r] = (int32_t)(gptr[o + 1] - gptr[o] + 1);
+                nnz += rowlen[r];
+                inst_nnz[i] += rowlen[r];
+            }
+    std::vector<int64_t> sptr(nslices + 1, 0);
+    for (int64_t sl = 0; sl < nslices; ++sl) {
+        int w = 0;
+        for (int l = 0; l < SLICE; ++l) w = std::max(w, rowlen[sl * SLICE + l]);
+        sptr[sl + 1] = sptr[sl] + (int64_t)w * SLICE;
+    }
+    std::vector<int32_t> colv(sptr[nslices]);
+    std::vector<int32_t> cols;
+    for (int64_t r = 0; r < npad; ++r) {
+        int64_t base = sptr[r / SLICE] + (r % SLICE);
+        int64_t w = (sptr[r / SLICE + 1] - sptr[r / SLICE]) / SLICE;
+        cols.clear();
+        if (perm[r] >= 0) {
+            int32_t o = perm[r];
+            cols.push_back((int32_t)r);
+            for (int64_t q = gptr[o]; q < gptr[o + 1]; ++q) cols.push_back(iperm[gadj[q]]);
+            std::sort(cols.begin(), cols.end());
+            for (int32_t c : cols) bw = std::max<int64_t>(bw, std::llabs((long long)c - r));
+        }
+        for (int64_t j = 0; j < w; ++j)
+            colv[base + j * SLICE] = j < (int64_t)cols.size() ? cols[j] : (int32_t)r;
+    }
+    // slot counts of the 2- and 4-lanes-per-row layouts (autotuner candidates)
+    int64_t nsl[3] = {sptr[nslices], 0, 0};
+    if (batched)
+        for (int li = 1; li < 3; ++li) {
+            const int lpr = 1 << li, H = SLICE / lpr;
+            int64_t tot = 0;
+            for (int64_t sl = 0; sl < npad / H; ++sl) {
+                int w = 0;
+                for (int l = 0; l < H; ++l) w = std::max(w, (rowlen[sl * H + l] + lpr - 1) / lpr);
+                tot += (int64_t)w * SLICE;
+            }
+            nsl[li] = tot;
+        }
+
+    ctx->n = n_nodes;
+    ctx->m = n_tets;
+    ctx->xyz.swap(X);
+    ctx->tets.assign(tets, tets + 4 * n_tets);
+    ctx->region.assign(n_tets, 0);
+    if (region) ctx->region.assign(region, region + n_tets);
+    ctx->fibre.clear();
+    if (fibre) ctx->fibre.assign(fibre, fibre + 3 * n_tets);
+    ctx->perm.swap(perm);
+    ctx->iperm.swap(iperm);
+    ctx->npad = npad;
+    ctx->nslices = nslices;
+    ctx->nslots = sptr[nslices];
+    ctx->nnz = nnz;
+    ctx->bandwidth = bw;
+    ctx->slice_ptr.swap(sptr);
+    ctx->col_sell.swap(colv);
+    ctx->rowlen.swap(rowlen);
+    ctx->batched = batched;
+    ctx->n_inst = n_inst;
+    ctx->inst_node_ptr.assign(node_ptr, node_ptr + n_inst + 1);
+    ctx->inst_row0.swap(row0);
+    ctx->inst_nnz.swap(inst_nnz);
+    ctx->tile_real.swap(tile_real);
+    for (int li = 0; li < 3; ++li) ctx->nslots_lpr[li] = nsl[li];
+    ctx->fmt = 0;
+    ctx->lpr = 1;
+    ctx->lpr_built = 0;
+    ctx->csr_built = false;
+    release_graphs(ctx);
+    ctx->stims.clear();
+    ctx->prepared = false;
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    return MDX_OK;
+    GUARD_END
+}
+
+
+// ---------------------------------------------------------------------------
+// batched form: one time step's work up to the host check
+// ---------------------------------------------------------------------------
+struct BatchPtrs {
+    SellView P;
+    IterMatrix IM;
+    const double *Mv, *Kv, *Av, *dinv;
+    const float *dinv32;
+    double *b, *s, *u, *part0, *part_pq, *part_rz;
+    float *r32, *p32, *q32, *delta, *g32;
+    BScalars *bsc;
+};
+
+BatchPtrs batch_ptrs(mdx_ctx *c)
+{
+    const Layout &L = c->L;
+    BatchPtrs q;
+    q.P = SellView{c->dev<int64_t>(L.slice_ptr), c->dev<int32_t>(L.col)};
+    q.IM = iter_matrix(c);
+    q.Mv = c->dev<double>(L.Mv);
+    q.Kv = c->dev<double>(L.Kv);
+    q.Av = c->dev<double>(L.Av);
+    q.dinv = c->dev<double>(L.dinv);
+    q.dinv32 = c->dev<float>(L.dinv32);
+    q.b = c->dev<double>(L.b);
+    q.s = c->dev<double>(L.s);
+    q.u = ionic_nstates(c->ionic_kind) ? c->dev<double>(L.u) : nullptr;
+    q.part0 = c->dev<double>(L.partial);
+    q.part_pq = q.part0 + 3 * kPartialCap;
+    q.part_rz = q.part0 + 6 * kPartialCap;
+    q.r32 = c->dev<float>(L.r32);
+    q.p32 = c->dev<float>(L.p32);
+    q.q32 = c->dev<float>(L.q32);
+    q.delta = c->dev<float>(L.delta);
+    q.g32 = c->dev<float>(L.g32);
+    q.bsc = c->dev<BScalars>(L.bsc);
+    return q;
+}
+
+BParams batch_params(const mdx_ctx *c)
+{
+    return BParams{c->opts.atol, c->opts.rtol, c->opts.max_iter, c->opts.rr_interval,
+                   c->opts.rel_mode};
+}
+
+// ionic update, right-hand side and initial residual, `iters` PCG iterations
+// of every running instance, one residual-replacement pass.  With `timed`,
+// event pairs bracket the SpMV launches.
+void enqueue_batched_step(mdx_ctx *c, hipStream_t st, int iters, const double *istim, bool timed)
+{
+    const BatchPtrs q = batch_ptrs(c);
+    const BParams bp = batch_params(c);
+    const StepParams sp = step_params(c);
+    double *V = c->vec(0), *Vprev = c->vec(1), *X = c->vec(2);
+    if (c->opts.precision == MDX_PREC_MIXED_GATES32)
+        launch_ionic_step_mixed(st, c->ionic_kind, c->ionic_params.data(), c->npad, c->npad, c->dt,
+                                c->cm, V, q.u, q.g32, istim, q.s, row_mask(c));
+    else
+        launch_ionic_step(st, c->ionic_kind, c->ionic_params.data(), c->npad, c->npad, c->dt, c->cm,
+                          V, q.u, istim, q.s, 0, row_mask(c));
+    launch_b_rhs_init(st, c->seg, q.P, q.Mv, q.Kv, q.dinv, q.dinv32, sp, V, Vprev, q.s, X, q.b, q.r32,
+                      q.delta, q.part0);
+    launch_b_init_finalize(st, c->seg, q.part0, bp, q.bsc);
+    launch_b_set_direction(st, c->seg, q.dinv32, q.r32, q.p32, q.bsc);
+    for (int i = 0; i < iters; ++i) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed && 2 * i + 1 < (int)c->ev.size()) {
+            e0 = c->ev[2 * i];
+            e1 = c->ev[2 * i + 1];
+        }
+        launch_b_iteration(st, c->seg, q.IM, bp, q.dinv32, q.p32, q.q32, q.delta, q.r32, q.part_pq,
+                           q.part_rz, q.bsc, e0, e1);
+    }
+    launch_b_replacement(st, c->seg, q.P, bp, q.Av, X, q.delta, q.b, q.dinv, q.dinv32, q.r32, q.p32,
+                         q.part0, q.bsc);
+}
+
+mdx_status fetch_bscalars(mdx_ctx *c, hipStream_t st)
+{
+    mdx_ctx *ctx = c;   // for HIPCHK
+    HIPCHK(hipMemcpyAsync(c->bsc_host, c->dev<BScalars>(c->L.bsc), sizeof(BScalars) * c->n_inst,
+                          hipMemcpyDeviceToHost, st));
+    auto w0 = std::chrono::steady_clock::now();
+    HIPCHK(hipStreamSynchronize(st));
+    c->stats.host_wait_seconds +=
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+    return MDX_OK;
+}
+
+bool all_done(const mdx_ctx *c)
+{
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!c->bsc_host[i].done) return false;
+    return true;
+}
+
+mdx_status run_batched(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_out)
+{
+    if (ctx->opts.precision == MDX_PREC_FP64)
+        return fail(ctx, MDX_ERR_UNSUPPORTED,
+                    "a batched context runs the mixed-precision solver (MDX_PREC_MIXED)");
+    if (ctx->opts.warm_start == MDX_WS_MLP || ctx->rec_X)
+        return fail(ctx, MDX_ERR_UNSUPPORTED, "no learned warm start or recorder in a batched context");
+    // graphs cannot be captured on the legacy default stream: use an own one
+    hipStream_t st = ctx->stream;
+    if (!st) {
+        if (!ctx->own_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        st = ctx->own_stream;
+    }
+    const Layout &L = ctx->L;
+    const BatchPtrs q = batch_ptrs(ctx);
+    const BParams bp = batch_params(ctx);
+    const int max_iter = ctx->opts.max_iter;
+    double *istim_dev = ctx->dev<double>(L.istim);
+    Scalars *sc = ctx->dev<Scalars>(L.scalars);
+    mdx_status result = MDX_OK;
+    ctx->iters_hist.clear();
+    ctx->inst_iters_hist.clear();
+    int64_t n_out = 0;
+    auto t_start = std::chrono::steady_clock::now();
+
+    for (int64_t j = 0; j < n_steps; ++j) {
+        const int64_t k = ctx->step;
+        bool any_stim = false;
+        if (mdx_status e = update_stimulus(ctx, st, k, any_stim)) return e;
+        double *V = ctx->vec(0), *X = ctx->vec(2);
+        const bool profiling = ctx->profile_every > 0 && k % ctx->profile_every == 0;
+        const int C = std::max(1, std::min(ctx->last_iters, max_iter));
+        if (ctx->use_graph && !profiling) {
+            const std::pair<int, int> key{C, ctx->vb[0]};
+            auto it = ctx->graphs.find(key);
+            if (it == ctx->graphs.end()) {
+                hipGraph_t g = nullptr;
+                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                enqueue_batched_step(ctx, st, C, istim_dev, false);
+                HIPCHK(hipStreamEndCapture(st, &g));
+                hipGraphExec_t ex = nullptr;
+                hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                HIPCHK(ie);
+                it = ctx->graphs.emplace(key, ex).first;
+            }
+            HIPCHK(hipGraphLaunch(it->second, st));
+        } else {
+            enqueue_batched_step(ctx, st, C, any_stim ? istim_dev : nullptr, profiling);
+        }
+        HIPCHK(hipGetLastError());
+        int units = C;
+        if (mdx_status e = fetch_bscalars(ctx, st)) return e;
+        while (!all_done(ctx) && units < max_iter + 1) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (profiling && 2 * units + 1 < (int)ctx->ev.size()) {
+                e0 = ctx->ev[2 * units];
+                e1 = ctx->ev[2 * units + 1];
+            }
+            launch_b_iteration(st, ctx->seg, q.IM, bp, q.dinv32, q.p32, q.q32, q.delta, q.r32,
+                               q.part_pq, q.part_rz, q.bsc, e0, e1);
+            launch_b_replacement(st, ctx->seg, q.P, bp, q.Av, X, q.delta, q.b, q.dinv, q.dinv32, q.r32,
+                                 q.p32, q.part0, q.bsc);
+            HIPCHK(hipGetLastError());
+            ++units;
+            if (mdx_status e = fetch_bscalars(ctx, st)) return e;
+        }
+        if (!all_done(ctx))
+            return fail(ctx, MDX_ERR_STATE, "batched solve of step %lld did not finish",
+                        (long long)k);
+        int max_it = 0, step_iters = 0;
+        bool failed = false;
+        double bytes = 0.0;
+        for (int i = 0; i < ctx->n_inst; ++i) {
+            const BScalars &b = ctx->bsc_host[i];
+            if (b.nonfinite)
+                return fail(ctx, MDX_ERR_NONFINITE,
+                            "non-finite value in the solve of instance %d, step %lld", i,
+                            (long long)k);
+            const int itv = b.failed ? -1 : b.iters;
+            ctx->inst_iters_hist.push_back(itv);
+            max_it = std::max(max_it, b.it);
+            if (itv < 0) {
+                failed = true;
+                ctx->stats.not_converged++;
+            } else {
+                step_iters = std::max(step_iters, itv);
+            }
+            ctx->stats.cg_iters_total += b.it;
+            const int64_t ni = ctx->inst_node_ptr[i + 1] - ctx->inst_node_ptr[i];
+            bytes += (double)b.it * (8.0 * (double)ctx->inst_nnz[i] + 8.0 * (double)ni);
+        }
+        ctx->stats.cg_iters_max = std::max<int64_t>(ctx->stats.cg_iters_max, max_it);
+        ctx->last_iters = max_it;
+        if (failed) result = MDX_WARN_NOT_CONVERGED;
+        if (profiling) {
+            const int timed = std::min(units, (int)ctx->ev.size() / 2);
+            for (int u_ = 0; u_ < timed; ++u_) {
+                float ms = 0.0f;
+                HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2 * u_], ctx->ev[2 * u_ + 1]));
+                ctx->stats.spmv_seconds += 1e-3 * ms;
+                ctx->stats.spmv_timed++;
+            }
+            if (timed == units) {
+                ctx->stats.spmv_work += units;
+                ctx->stats.spmv_bytes += bytes;
+            }
+        }
+        launch_epilogue(st, ctx->npad, (double)(k + 1) * ctx->dt, V, X, ctx->dev<double>(L.lat),
+                        ctx->dev<double>(L.lrt), sc);
+        int old_prev = ctx->vb[1];
+        ctx->vb[1] = ctx->vb[0];
+        ctx->vb[0] = ctx->vb[2];
+        ctx->vb[2] = old_prev;
+        ctx->step++;
+        ctx->iters_hist.push_back(failed ? -1 : step_iters);
+        ctx->stats.steps++;
+        if (out_every > 0 && (j + 1) % out_every == 0 && v_out) {
+            HIPCHK(hipStreamSynchronize(st));
+            if (mdx_status e = copy_vec_out(ctx, ctx->vec(0), v_out + n_out * ctx->n)) return e;
+            ++n_out;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->stats.step_loop_seconds +=
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (ctx->sc_host->nonfinite)
+        return fail(ctx, MDX_ERR_NONFINITE, "non-finite V after step %lld", (long long)ctx->step);
+    return result;
 }
 
 }  // namespace
@@ -444,6 +1040,12 @@ void mdx_destroy(mdx_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream); else (void)hipDeviceSynchronize();
     for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    release_graphs(ctx);
+    if (ctx->own_stream) {
+        (void)hipStreamSynchronize(ctx->own_stream);
+        (void)hipStreamDestroy(ctx->own_stream);
+    }
+    if (ctx->bsc_host) (void)hipHostFree(ctx->bsc_host);
     if (ctx->sc_host) (void)hipHostFree(ctx->sc_host);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     delete ctx;
@@ -455,117 +1057,20 @@ mdx_status mdx_set_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz, double
                         int64_t n_tets, const int32_t *tets, const int32_t *region,
                         const double *fibre)
 {
+    const int64_t ptr[2] = {0, n_nodes};
+    return set_mesh_impl(ctx, 1, ptr, false, n_nodes, xyz, unit_conversion, n_tets, tets, region,
+                         fibre);
+}
+
+mdx_status mdx_set_mesh_batch(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, int64_t n_nodes,
+                              const double *xyz, double unit_conversion, int64_t n_tets,
+                              const int32_t *tets, const int32_t *region, const double *fibre)
+{
     if (!ctx) return MDX_ERR_INVALID_ARG;
-    GUARD_BEGIN
-    if (n_nodes <= 0 || n_tets <= 0 || !xyz || !tets)
-        return fail(ctx, MDX_ERR_INVALID_ARG, "empty mesh or null array");
-    if (n_nodes >= (int64_t)1 << 31 || n_tets >= (int64_t)1 << 27)
-        return fail(ctx, MDX_ERR_INVALID_ARG, "mesh too large (n < 2^31, tets < 2^27)");
-    if (!(unit_conversion > 0.0) || !std::isfinite(unit_conversion))
-        return fail(ctx, MDX_ERR_INVALID_ARG, "unit_conversion must be finite and > 0");
-    for (int64_t i = 0; i < 3 * n_nodes; ++i)
-        if (!std::isfinite(xyz[i]))
-            return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite coordinate at node %lld",
-                        (long long)(i / 3));
-    for (int64_t q = 0; q < 4 * n_tets; ++q)
-        if (tets[q] < 0 || tets[q] >= n_nodes)
-            return fail(ctx, MDX_ERR_BAD_MESH, "element %lld references node %d out of range",
-                        (long long)(q / 4), tets[q]);
-    if (fibre)
-        for (int64_t q = 0; q < 3 * n_tets; ++q)
-            if (!std::isfinite(fibre[q]))
-                return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite fibre at element %lld",
-                            (long long)(q / 3));
-    std::vector<double> X(xyz, xyz + 3 * n_nodes);
-    for (double &v : X) v /= unit_conversion;
-    // element quality: |det J| > 1e-14 h^3
-    for (int64_t e = 0; e < n_tets; ++e) {
-        const int32_t *t = tets + 4 * e;
-        double d[3][3], h2 = 0.0;
-        for (int a = 1; a < 4; ++a)
-            for (int k = 0; k < 3; ++k) d[a - 1][k] = X[3 * t[a] + k] - X[3 * t[0] + k];
-        for (int a = 0; a < 4; ++a)
-            for (int b = a + 1; b < 4; ++b) {
-                double s = 0.0;
-                for (int k = 0; k < 3; ++k) {
-                    double w = X[3 * t[a] + k] - X[3 * t[b] + k];
-                    s += w * w;
-                }
-                h2 = std::max(h2, s);
-            }
-        double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
-                     d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
-                     d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
-        double h3 = h2 * std::sqrt(h2);
-        if (!(std::fabs(det) > 1e-14 * h3))
-            return fail(ctx, MDX_ERR_BAD_MESH, "degenerate element %lld (|det J| = %g)",
-                        (long long)e, std::fabs(det));
-    }
-
-    // adjacency, RCM, sliced-ELL pattern
-    std::vector<int64_t> gptr;
-    std::vector<int32_t> gadj;
-    node_graph(n_nodes, n_tets, tets, gptr, gadj);
-    std::vector<int32_t> perm = rcm(n_nodes, gptr, gadj);
-    std::vector<int32_t> iperm(n_nodes);
-    for (int64_t r = 0; r < n_nodes; ++r) iperm[perm[r]] = (int32_t)r;
-
-    const int64_t npad = (n_nodes + TILE - 1) / TILE * TILE;
-    const int64_t nslices = npad / SLICE;
-    std::vector<int32_t> rowlen(npad, 0);
-    int64_t nnz = 0, bw = 0;
-    for (int64_t r = 0; r < n_nodes; ++r) {
-        int32_t o = perm[r];
-        rowlen[r] = (int32_t)(gptr[o + 1] - gptr[o] + 1);
-        nnz += rowlen[r];
-    }
-    std::vector<int64_t> sptr(nslices + 1, 0);
-    for (int64_t s = 0; s < nslices; ++s) {
-        int w = 0;
-        for (int l = 0; l < SLICE; ++l) w = std::max(w, rowlen[s * SLICE + l]);
-        sptr[s + 1] = sptr[s] + (int64_t)w * SLICE;
-    }
-    std::vector<int32_t> colv(sptr[nslices]);
-    std::vector<int32_t> cols;
-    for (int64_t r = 0; r < npad; ++r) {
-        int64_t base = sptr[r / SLICE] + (r % SLICE);
-        int64_t w = (sptr[r / SLICE + 1] - sptr[r / SLICE]) / SLICE;
-        cols.clear();
-        if (r < n_nodes) {
-            int32_t o = perm[r];
-            cols.push_back((int32_t)r);
-            for (int64_t q = gptr[o]; q < gptr[o + 1]; ++q) cols.push_back(iperm[gadj[q]]);
-            std::sort(cols.begin(), cols.end());
-            for (int32_t c : cols) bw = std::max<int64_t>(bw, std::llabs((long long)c - r));
-        }
-        for (int64_t j = 0; j < w; ++j)
-            colv[base + j * SLICE] = j < (int64_t)cols.size() ? cols[j] : (int32_t)r;
-    }
-
-    ctx->n = n_nodes;
-    ctx->m = n_tets;
-    ctx->xyz.swap(X);
-    ctx->tets.assign(tets, tets + 4 * n_tets);
-    ctx->region.assign(n_tets, 0);
-    if (region) ctx->region.assign(region, region + n_tets);
-    ctx->fibre.clear();
-    if (fibre) ctx->fibre.assign(fibre, fibre + 3 * n_tets);
-    ctx->perm.swap(perm);
-    ctx->iperm.swap(iperm);
-    ctx->npad = npad;
-    ctx->nslices = nslices;
-    ctx->nslots = sptr[nslices];
-    ctx->nnz = nnz;
-    ctx->bandwidth = bw;
-    ctx->slice_ptr.swap(sptr);
-    ctx->col_sell.swap(colv);
-    ctx->rowlen.swap(rowlen);
-    ctx->stims.clear();
-    ctx->prepared = false;
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
-    return MDX_OK;
-    GUARD_END
+    if (n_inst < 1 || n_inst > (1 << 20) || !node_ptr)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "n_inst must lie in [1, 2^20] with node_ptr given");
+    return set_mesh_impl(ctx, n_inst, node_ptr, true, n_nodes, xyz, unit_conversion, n_tets, tets,
+                         region, fibre);
 }
 
 mdx_status mdx_add_conductivity(mdx_ctx *ctx, int32_t n_ids, const int32_t *region_ids, double il,
@@ -659,6 +1164,7 @@ mdx_status mdx_set_solver(mdx_ctx *ctx, const mdx_solver_opts *o)
          o->warm_start != MDX_WS_MLP))
         return fail(ctx, MDX_ERR_INVALID_ARG, "invalid solver options");
     ctx->opts = *o;
+    release_graphs(ctx);   // captured steps hold the solver options
     if (ctx->prepared) {
         Scalars *sc = ctx->dev<Scalars>(ctx->L.scalars);
         HIPCHK(hipMemcpyAsync(&sc->atol, &o->atol, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
@@ -802,8 +1308,8 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
                   (double *)(x + L.x_vol), (double *)(x + L.x_ek), Mv, Kv);
     launch_system(st, ctx->nslots, Mv, Kv, ctx->chi * ctx->cm, ctx->theta * dt, Av);
     SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
-    launch_dinv(st, ctx->npad, ctx->n, P, Av, ctx->dev<double>(L.dinv));
-    launch_kdiag(st, ctx->npad, ctx->n, P, Kv, ctx->dev<double>(L.kdiag));
+    launch_dinv(st, ctx->npad, span_rows(ctx), P, Av, ctx->dev<double>(L.dinv));
+    launch_kdiag(st, ctx->npad, span_rows(ctx), P, Kv, ctx->dev<double>(L.kdiag));
     // FP32 copies for the mixed-precision form
     launch_to_f32(st, ctx->nslots, Av, ctx->dev<float>(L.A32));
     launch_to_f32(st, ctx->npad, ctx->dev<double>(L.dinv), ctx->dev<float>(L.dinv32));
@@ -813,9 +1319,12 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     ctx->vb[0] = 0;
     ctx->vb[1] = 1;
     ctx->vb[2] = 2;
+    if (ctx->batched)
+        HIPCHK(hipMemcpyAsync(ctx->dev<int32_t>(L.tile_real), ctx->tile_real.data(),
+                              sizeof(int32_t) * ctx->tile_real.size(), hipMemcpyHostToDevice, st));
     launch_ionic_init(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad, ctx->vec(0),
-                      ctx->vec(1),
-                      ionic_nstates(ctx->ionic_kind) ? ctx->dev<double>(L.u) : nullptr);
+                      ctx->vec(1), ionic_nstates(ctx->ionic_kind) ? ctx->dev<double>(L.u) : nullptr,
+                      row_mask(ctx));
     for (size_t off : {L.vec[2], L.r, L.p, L.p2, L.q, L.b, L.s, L.istim})
         launch_fill(st, ctx->npad, 0.0, ctx->dev<double>(off));
     launch_fill(st, ctx->npad * 2, 0.0, ctx->dev<double>(L.feat));   // 4 floats per row
@@ -836,6 +1345,25 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     HIPCHK(hipStreamSynchronize(st));
 
     ctx->tiling = make_tiling(ctx->npad, ctx->max_groups);
+    release_graphs(ctx);
+    ctx->fmt = 0;
+    ctx->lpr = 1;
+    ctx->lpr_built = 0;
+    ctx->csr_built = false;
+    ctx->inst_iters_hist.clear();
+    if (ctx->batched) {
+        if (ctx->bsc_host) (void)hipHostFree(ctx->bsc_host);
+        ctx->bsc_host = nullptr;
+        HIPCHK(hipHostMalloc((void **)&ctx->bsc_host, sizeof(BScalars) * ctx->n_inst,
+                             hipHostMallocDefault));
+        std::memset((void *)ctx->bsc_host, 0, sizeof(BScalars) * ctx->n_inst);
+        HIPCHK(hipMemcpyAsync(ctx->dev<BScalars>(L.bsc), ctx->bsc_host,
+                              sizeof(BScalars) * ctx->n_inst, hipMemcpyHostToDevice, st));
+        // default: about 4096 workgroups
+        const int64_t n_tiles = ctx->npad / TILE;
+        const int tpb = (int)std::max<int64_t>(1, (n_tiles + kMaxGroups - 1) / kMaxGroups);
+        if (mdx_status e = install_groups(ctx, tpb)) return e;
+    }
     ctx->dt = dt;
     ctx->step = 0;
     ctx->active.assign(ctx->stims.size(), 0);
@@ -856,6 +1384,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     if (n_steps < 0 || out_every < 0) return fail(ctx, MDX_ERR_INVALID_ARG, "negative count");
     GUARD_BEGIN
     HIPCHK(hipSetDevice(ctx->device));
+    if (ctx->batched) return run_batched(ctx, n_steps, out_every, v_out);
     const Layout &L = ctx->L;
     hipStream_t st = ctx->stream;
     const Tiling &T = ctx->tiling;
@@ -891,7 +1420,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     for (int64_t j = 0; j < n_steps; ++j) {
         const int64_t k = ctx->step;
         bool any_stim = false;
-        if (mdx_status e = update_stimulus(ctx, k, any_stim)) return e;
+        if (mdx_status e = update_stimulus(ctx, st, k, any_stim)) return e;
         double *V = ctx->vec(0), *Vprev = ctx->vec(1), *X = ctx->vec(2);
         ctx->profiling = ctx->profile_every > 0 && k % ctx->profile_every == 0;
         const double *istim = any_stim ? ctx->dev<double>(L.istim) : nullptr;
@@ -1103,6 +1632,88 @@ mdx_status mdx_get_iterations(mdx_ctx *ctx, int64_t n, int32_t *iters)
     return MDX_OK;
 }
 
+mdx_status mdx_get_instance_iterations(mdx_ctx *ctx, int64_t n, int32_t *iters)
+{
+    if (!ctx || (n > 0 && !iters)) return MDX_ERR_INVALID_ARG;
+    const int64_t steps = (int64_t)ctx->inst_iters_hist.size() / std::max(1, ctx->n_inst);
+    if (!ctx->batched) return fail(ctx, MDX_ERR_UNSUPPORTED, "not a batched context");
+    if (n < 0 || n > steps)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "only %lld steps recorded", (long long)steps);
+    std::copy(ctx->inst_iters_hist.end() - n * ctx->n_inst, ctx->inst_iters_hist.end(), iters);
+    return MDX_OK;
+}
+
+mdx_status mdx_autotune(mdx_ctx *ctx, int32_t reps, mdx_tune_report *rep)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared || !ctx->batched)
+        return fail(ctx, MDX_ERR_STATE, "needs a prepared batched context");
+    if (reps < 1 || reps > 1000) return fail(ctx, MDX_ERR_INVALID_ARG, "reps must lie in [1, 1000]");
+    GUARD_BEGIN
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    // every instance running: the scalars are re-initialised by the next step
+    std::memset((void *)ctx->bsc_host, 0, sizeof(BScalars) * ctx->n_inst);
+    HIPCHK(hipMemcpyAsync(ctx->dev<BScalars>(ctx->L.bsc), ctx->bsc_host,
+                          sizeof(BScalars) * ctx->n_inst, hipMemcpyHostToDevice, st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    mdx_tune_report r{};
+    double best = std::numeric_limits<double>::infinity();
+    int best_fmt = 0, best_lpr = 1, best_tpb = ctx->tpb_b;
+    const int layouts[6][2] = {{0, 1}, {0, 2}, {0, 4}, {1, 4}, {1, 8}, {1, 16}};
+    const int tpbs[4] = {1, 2, 4, 8};
+    mdx_status st_ = MDX_OK;
+    for (const auto &lay : layouts) {
+        if ((st_ = set_iter_layout(ctx, lay[0], lay[1]))) break;
+        const BatchPtrs q = batch_ptrs(ctx);
+        for (int tpb : tpbs) {
+            std::vector<int4> grp;
+            std::vector<int32_t> ig;
+            if (build_groups(ctx, tpb, grp, ig) != MDX_OK) continue;   // too many groups
+            if ((st_ = install_groups(ctx, tpb))) break;
+            for (int w = 0; w < 2; ++w)
+                launch_b_spmv(st, ctx->seg, q.IM, q.dinv32, q.q32, q.part_pq, q.bsc);
+            HIPCHK(hipEventRecord(e0, st));
+            for (int i = 0; i < reps; ++i)
+                launch_b_spmv(st, ctx->seg, q.IM, q.dinv32, q.q32, q.part_pq, q.bsc);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            const double sec = 1e-3 * ms / reps;
+            if (r.n_candidates < MDX_TUNE_MAX_CANDIDATES) {
+                r.cand_format[r.n_candidates] = lay[0];
+                r.cand_lanes_per_row[r.n_candidates] = lay[1];
+                r.cand_tiles_per_group[r.n_candidates] = tpb;
+                r.cand_seconds[r.n_candidates] = sec;
+                r.n_candidates++;
+            }
+            if (sec < best) {
+                best = sec;
+                best_fmt = lay[0];
+                best_lpr = lay[1];
+                best_tpb = tpb;
+            }
+        }
+        if (st_) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st_) return st_;
+    if (mdx_status e = set_iter_layout(ctx, best_fmt, best_lpr)) return e;
+    if (mdx_status e = install_groups(ctx, best_tpb)) return e;
+    r.format = best_fmt;
+    r.lanes_per_row = best_lpr;
+    r.tiles_per_group = best_tpb;
+    r.seconds = best;
+    r.bytes = 8.0 * (double)ctx->nnz + 8.0 * (double)ctx->n;
+    if (rep) *rep = r;
+    return MDX_OK;
+    GUARD_END
+}
+
 mdx_status mdx_get_stats(mdx_ctx *ctx, mdx_stats *out)
 {
     if (!ctx || !out) return MDX_ERR_INVALID_ARG;
@@ -1145,6 +1756,33 @@ mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value)
     case MDX_TUNE_ITER_SCHEME:
         if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "scheme is 0 or 1");
         ctx->iter_scheme = (int)value;
+        return MDX_OK;
+    case MDX_TUNE_FORMAT:
+        if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "format is 0 or 1");
+        if (!ctx->batched || !ctx->prepared)
+            return fail(ctx, MDX_ERR_STATE, "needs a prepared batched context");
+        GUARD_BEGIN
+        HIPCHK(hipSetDevice(ctx->device));
+        return set_iter_layout(ctx, (int)value, value == 1 ? 8 : 1);
+        GUARD_END
+    case MDX_TUNE_LANES_PER_ROW:
+    case MDX_TUNE_TILES_PER_GROUP:
+        if (!ctx->batched || !ctx->prepared)
+            return fail(ctx, MDX_ERR_STATE, "needs a prepared batched context");
+        GUARD_BEGIN
+        HIPCHK(hipSetDevice(ctx->device));
+        if (key == MDX_TUNE_LANES_PER_ROW) {
+            if (value < 1 || value > 16) return fail(ctx, MDX_ERR_INVALID_ARG, "bad lanes per row");
+            return set_iter_layout(ctx, ctx->fmt, (int)value);
+        }
+        if (value < 1 || value > (1 << 20))
+            return fail(ctx, MDX_ERR_INVALID_ARG, "tiles per group must lie in [1, 2^20]");
+        return install_groups(ctx, (int)value);
+        GUARD_END
+    case MDX_TUNE_GRAPH:
+        if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "graph is 0 or 1");
+        ctx->use_graph = value != 0;
+        release_graphs(ctx);
         return MDX_OK;
     default:
         return fail(ctx, MDX_ERR_INVALID_ARG, "unknown tuning key %d", key);
@@ -1227,7 +1865,8 @@ mdx_status mdx_get_matrix(mdx_ctx *ctx, int32_t which, int64_t *nnz, int32_t *ro
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     int64_t o = 0;
-    for (int64_t r = 0; r < ctx->n; ++r) {
+    for (int64_t r = 0; r < ctx->npad; ++r) {
+        if (ctx->perm[r] < 0) continue;
         int64_t base = ctx->slice_ptr[r / SLICE] + (r % SLICE);
         for (int j = 0; j < ctx->rowlen[r]; ++j) {
             rows[o] = ctx->perm[r];
@@ -1364,7 +2003,9 @@ mdx_status mdx_get_node_order(mdx_ctx *ctx, int32_t *order)
 {
     if (!ctx || !order) return MDX_ERR_INVALID_ARG;
     if (mdx_status s = require_mesh(ctx)) return s;
-    std::copy(ctx->perm.begin(), ctx->perm.end(), order);
+    if (ctx->batched)
+        return fail(ctx, MDX_ERR_UNSUPPORTED, "internal rows of a batched context include padding");
+    std::copy(ctx->perm.begin(), ctx->perm.begin() + ctx->n, order);
     return MDX_OK;
 }
 

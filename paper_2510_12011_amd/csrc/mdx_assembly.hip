@@ -114,7 +114,8 @@ __global__ __launch_bounds__(256) void k_dinv(int64_t n_rows, int64_t n_real,
     double d = 0.0;
     for (int64_t e = slice_ptr[sl] + lane; e < slice_ptr[sl + 1]; e += SLICE)
         if (col[e] == r) d += Av[e];
-    dinv[r] = 1.0 / d;
+    // a padding row of the batched layout has only zero-valued self entries
+    dinv[r] = d != 0.0 ? 1.0 / d : 0.0;
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }

@@ -1,0 +1,552 @@
+// Batched form: many independent monodomain systems in one block-diagonal
+// matrix, solved together by the mixed-precision PCG (FP32 matrix values and
+// vectors in the iteration, FP64 right-hand side, solution, dot products and
+// residual replacement), with one set of CG scalars per instance.
+//
+// Per time step (after the pointwise ionic update over all rows):
+//   b_rhs_init        b, x0, r0 = b - A x0 (FP64 M and K), r32, delta = 0;
+//                     per-group partials r.z, |D^-1 r0|^2, |D^-1 b|^2
+//   b_init_finalize   one workgroup per instance: rho_0, ||z_0||, stopping
+//                     reference and rounding floor
+//   b_set_direction   p_0 = z_0
+//   per iteration:    spmv (q = A p, p.q), alpha (per instance), update
+//                     (x, r, z; r.z, z.z), beta (per instance: test, replacement
+//                     trigger, beta), direction (p = z + beta p)
+//   replacement       flush (x64 += delta), true residual in FP64, finalize
+//                     (stop or continue), redirect
+// Every kernel returns at once for the workgroups of an instance that has
+// finished (or, for the iteration kernels, waits for a replacement), so
+// converged instances cost no memory traffic while the others iterate; the
+// host stops when every instance is done.
+//
+// The iteration's SpMV takes the matrix in the layout chosen by the
+// autotuner: lpr lanes per row (64/lpr rows per wavefront), the lanes of a
+// row summed by a butterfly over adjacent lanes.
+#include "mdx_device.h"
+#include "mdx_internal.h"
+
+#include <hip/hip_ext.h>
+
+namespace mdx {
+
+namespace {
+
+__device__ __forceinline__ bool stopped(const BScalars &s) { return s.done != 0; }
+__device__ __forceinline__ bool idle(const BScalars &s) { return s.done != 0 || s.replace != 0; }
+
+// Sum NV per-group partials of groups [g0, g1) (layout partial[k * groups + g]).
+template <int NV>
+__device__ __forceinline__ void reduce_range(const double *__restrict__ partial, int groups, int g0,
+                                             int g1, double (&v)[NV])
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int g = g0 + (int)threadIdx.x; g < g1; g += TILE)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += partial[k * groups + g];
+    group_sum<NV>(v);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_relayout(int lpr, int64_t n_slices,
+                                                  const int64_t *__restrict__ sptr_new,
+                                                  const int64_t *__restrict__ sptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const float *__restrict__ A32,
+                                                  int32_t *__restrict__ col_new,
+                                                  float *__restrict__ A32_new)
+{
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sl = tid / SLICE;
+    if (sl >= n_slices) return;
+    const int lane = (int)(tid % SLICE);
+    const int H = SLICE / lpr;
+    const int64_t row = sl * H + lane / lpr;
+    const int sub = lane % lpr;
+    const int64_t bsl = row / SLICE;
+    const int64_t bbase = sptr[bsl] + (row % SLICE);
+    const int64_t bw = (sptr[bsl + 1] - sptr[bsl]) / SLICE;   // base width of the row's slice
+    const int64_t w = (sptr_new[sl + 1] - sptr_new[sl]) / SLICE;
+    for (int64_t j = 0; j < w; ++j) {
+        const int64_t k = j * lpr + sub;   // entry of the row
+        const int64_t e = sptr_new[sl] + j * SLICE + lane;
+        if (k < bw) {
+            col_new[e] = col[bbase + k * SLICE];
+            A32_new[e] = A32[bbase + k * SLICE];
+        } else {
+            col_new[e] = (int32_t)row;
+            A32_new[e] = 0.0f;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_build_csr(int64_t n_rows, const int64_t *__restrict__ sptr,
+                                                   const int32_t *__restrict__ col,
+                                                   const float *__restrict__ A32,
+                                                   const int32_t *__restrict__ rptr,
+                                                   int32_t *__restrict__ col_csr,
+                                                   float *__restrict__ val_csr)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int64_t base = sptr[r / SLICE] + (r % SLICE);
+    const int32_t b = rptr[r], len = rptr[r + 1] - b;
+    for (int k = 0; k < len; ++k) {
+        col_csr[b + k] = col[base + (int64_t)k * SLICE];
+        val_csr[b + k] = A32[base + (int64_t)k * SLICE];
+    }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_b_rhs_init(
+    SegTiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
+    const float *__restrict__ dinv32, StepParams sp, const double *__restrict__ V,
+    const double *__restrict__ Vprev, const double *__restrict__ src, double *__restrict__ x,
+    double *__restrict__ b, float *__restrict__ r32, float *__restrict__ delta,
+    double *__restrict__ partial)
+{
+    const int g = logical_group(t.groups);
+    const int4 gr = t.grp[g];
+    const int lane = threadIdx.x & (SLICE - 1);
+    const double cK_old = (1.0 - sp.theta) * sp.dt;
+    const double cM_new = sp.chi * sp.cm;
+    const double cK_new = sp.theta * sp.dt;
+    const bool extrap = sp.warm_start == 1;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        double mv = 0.0, kv = 0.0, mx = 0.0, kx = 0.0;
+        for (int64_t e = beg; e < end; e += SLICE) {
+            const int32_t c = col[e];
+            const double m = Mv[e], kk = Kv[e];
+            const double vj = V[c];
+            const double x0j = extrap ? 2.0 * vj - Vprev[c] : vj;
+            mv += m * (sp.cm * vj + sp.dt * src[c]);
+            kv += kk * vj;
+            mx += m * x0j;
+            kx += kk * x0j;
+        }
+        const double bi = sp.chi * mv - cK_old * kv;
+        const double ri = bi - (cM_new * mx + cK_new * kx);
+        const double vi = V[row];
+        x[row] = extrap ? 2.0 * vi - Vprev[row] : vi;
+        b[row] = bi;
+        const float rf = (float)ri;
+        r32[row] = rf;
+        delta[row] = 0.0f;
+        const float zf = dinv32[row] * rf;
+        const double zi = dinv[row] * ri, di = dinv[row] * bi;
+        acc[0] += (double)rf * (double)zf;
+        acc[1] += zi * zi;
+        acc[2] += di * di;
+    }
+    write_partials<3>(acc, partial, t.groups, g);
+}
+
+__global__ __launch_bounds__(256) void k_b_init_finalize(int groups,
+                                                         const int32_t *__restrict__ inst_grp,
+                                                         const double *__restrict__ partial,
+                                                         BParams bp, BScalars *__restrict__ sc)
+{
+    const int i = blockIdx.x;
+    double v[3];
+    reduce_range<3>(partial, groups, inst_grp[i], inst_grp[i + 1], v);
+    if (threadIdx.x != 0) return;
+    BScalars &s = sc[i];
+    const double z0 = sqrt(v[1]), db = sqrt(v[2]);
+    s.rho = v[0];
+    s.alpha = 0.0;
+    s.beta = 0.0;
+    s.z0 = z0;
+    s.znorm = z0;
+    s.ref = bp.rel_mode == 1 ? db : z0;
+    s.floor_ = 1e-15 * db;
+    s.iters = 0;
+    s.it = 0;
+    s.replace = 0;
+    s.redirect = 0;
+    s.failed = 0;
+    const bool finite = z0 == z0 && db == db && v[0] == v[0];
+    s.nonfinite = finite ? 0 : 1;
+    s.done = (!finite || z0 <= s.floor_ || z0 < bp.atol) ? 1 : 0;
+}
+
+// p = D^-1 r for the groups of running instances
+__global__ __launch_bounds__(256) void k_b_set_direction(SegTiling t,
+                                                         const float *__restrict__ dinv32,
+                                                         const float *__restrict__ r32,
+                                                         float *__restrict__ p32,
+                                                         const BScalars *__restrict__ sc)
+{
+    const int4 gr = t.grp[logical_group(t.groups)];
+    if (stopped(sc[gr.x])) return;
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+        const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+        p32[i] = dinv32[i] * r32[i];
+    }
+}
+
+// q = A p (FP32, lpr lanes per row), partial p.q (FP64 accumulation)
+template <int LPR>
+__global__ __launch_bounds__(256) void k_b_spmv(SegTiling t, const int64_t *__restrict__ sptr,
+                                                const int32_t *__restrict__ col,
+                                                const float *__restrict__ A,
+                                                const float *__restrict__ p,
+                                                float *__restrict__ q, double *__restrict__ partial,
+                                                const BScalars *__restrict__ sc)
+{
+    const int g = logical_group(t.groups);
+    const int4 gr = t.grp[g];
+    if (idle(sc[gr.x])) return;
+    constexpr int H = SLICE / LPR;   // rows per wavefront
+    const int lane = threadIdx.x & (SLICE - 1);
+    const int w = threadIdx.x >> 6;
+    double acc[1] = {0.0};
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+#pragma unroll
+        for (int pass = 0; pass < LPR; ++pass) {
+            const int64_t row = (int64_t)tile * TILE + pass * (TILE / LPR) + w * H + lane / LPR;
+            const int64_t sl = row / H;
+            const int64_t beg = sptr[sl] + lane, end = sptr[sl + 1];
+            float sum = 0.0f;
+#pragma unroll 4
+            for (int64_t e = beg; e < end; e += SLICE) sum += A[e] * p[col[e]];
+            if constexpr (LPR >= 4) sum += __shfl_xor(sum, 2, 64);
+            if constexpr (LPR >= 2) sum += __shfl_xor(sum, 1, 64);
+            if ((lane & (LPR - 1)) == 0) {
+                q[row] = sum;
+                acc[0] += (double)p[row] * (double)sum;
+            }
+        }
+    }
+    write_partials<1>(acc, partial, t.groups, g);
+}
+
+// q = A p with A in CSR: LPR lanes per row stride through the row's
+// contiguous entries, then a butterfly over the row's lanes
+template <int LPR>
+__global__ __launch_bounds__(256) void k_b_spmv_csr(SegTiling t, const int32_t *__restrict__ rptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const float *__restrict__ A,
+                                                    const float *__restrict__ p,
+                                                    float *__restrict__ q,
+                                                    double *__restrict__ partial,
+                                                    const BScalars *__restrict__ sc)
+{
+    const int g = logical_group(t.groups);
+    const int4 gr = t.grp[g];
+    if (idle(sc[gr.x])) return;
+    constexpr int H = SLICE / LPR;   // rows per wavefront
+    const int lane = threadIdx.x & (SLICE - 1);
+    const int w = threadIdx.x >> 6;
+    const int sub = lane & (LPR - 1);
+    double acc[1] = {0.0};
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+        for (int pass = 0; pass < LPR; ++pass) {
+            const int64_t row = (int64_t)tile * TILE + pass * (TILE / LPR) + w * H + lane / LPR;
+            const int32_t end = rptr[row + 1];
+            float sum = 0.0f;
+            for (int32_t e = rptr[row] + sub; e < end; e += LPR) sum += A[e] * p[col[e]];
+#pragma unroll
+            for (int off = LPR / 2; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+            if (sub == 0) {
+                q[row] = sum;
+                acc[0] += (double)p[row] * (double)sum;
+            }
+        }
+    }
+    write_partials<1>(acc, partial, t.groups, g);
+}
+
+__global__ __launch_bounds__(256) void k_b_alpha(int groups, const int32_t *__restrict__ inst_grp,
+                                                 const double *__restrict__ partial,
+                                                 BScalars *__restrict__ sc)
+{
+    const int i = blockIdx.x;
+    BScalars &s = sc[i];
+    if (idle(s)) return;
+    double v[1];
+    reduce_range<1>(partial, groups, inst_grp[i], inst_grp[i + 1], v);
+    if (threadIdx.x != 0) return;
+    s.alpha = s.rho / v[0];
+    s.redirect = 0;
+}
+
+// delta += alpha p; r -= alpha q; z = D^-1 r; partials r.z, z.z
+__global__ __launch_bounds__(256) void k_b_update(SegTiling t, const float *__restrict__ dinv32,
+                                                  const float *__restrict__ p,
+                                                  const float *__restrict__ q,
+                                                  float *__restrict__ delta, float *__restrict__ r,
+                                                  double *__restrict__ partial,
+                                                  const BScalars *__restrict__ sc)
+{
+    const int g = logical_group(t.groups);
+    const int4 gr = t.grp[g];
+    const BScalars &s = sc[gr.x];
+    if (idle(s)) return;
+    const float alpha = (float)s.alpha;
+    double acc[2] = {0.0, 0.0};
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+        const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+        delta[i] += alpha * p[i];
+        const float ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        const float zi = dinv32[i] * ri;
+        acc[0] += (double)ri * (double)zi;
+        acc[1] += (double)zi * (double)zi;
+    }
+    write_partials<2>(acc, partial, t.groups, g);
+}
+
+// stopping test of the recursive residual; a replacement is requested when it
+// passes, every rr iterations and at the cap; otherwise beta
+__global__ __launch_bounds__(256) void k_b_beta(int groups, const int32_t *__restrict__ inst_grp,
+                                                const double *__restrict__ partial, BParams bp,
+                                                BScalars *__restrict__ sc)
+{
+    const int i = blockIdx.x;
+    BScalars &s = sc[i];
+    if (idle(s)) return;
+    double v[2];
+    reduce_range<2>(partial, groups, inst_grp[i], inst_grp[i + 1], v);
+    if (threadIdx.x != 0) return;
+    const double zn = sqrt(v[1]);
+    const int it = s.it + 1;
+    s.it = it;
+    s.znorm = zn;
+    if (!(zn == zn) || !(v[0] == v[0])) {
+        s.nonfinite = 1;
+        s.done = 1;
+        s.iters = it;
+        return;
+    }
+    const bool pass = zn < bp.atol || zn < bp.rtol * s.ref || zn <= s.floor_;
+    if (pass || (bp.rr > 0 && it % bp.rr == 0) || it >= bp.max_iter) {
+        s.replace = 1;
+        return;
+    }
+    s.beta = v[0] / s.rho;
+    s.rho = v[0];
+}
+
+// p = D^-1 r + beta p
+__global__ __launch_bounds__(256) void k_b_direction(SegTiling t, const float *__restrict__ dinv32,
+                                                     const float *__restrict__ r,
+                                                     float *__restrict__ p,
+                                                     const BScalars *__restrict__ sc)
+{
+    const int4 gr = t.grp[logical_group(t.groups)];
+    const BScalars &s = sc[gr.x];
+    if (idle(s)) return;
+    const float bf = (float)s.beta;
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+        const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+        p[i] = dinv32[i] * r[i] + bf * p[i];
+    }
+}
+
+// ---- residual replacement --------------------------------------------------
+__device__ __forceinline__ bool replacing(const BScalars &s) { return s.replace && !s.done; }
+
+__global__ __launch_bounds__(256) void k_b_flush(SegTiling t, double *__restrict__ x,
+                                                 float *__restrict__ delta,
+                                                 const BScalars *__restrict__ sc)
+{
+    const int4 gr = t.grp[logical_group(t.groups)];
+    if (!replacing(sc[gr.x])) return;
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+        const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+        x[i] += (double)delta[i];
+        delta[i] = 0.0f;
+    }
+}
+
+// r64 = b - A x64 (FP64 values), r32 = r64; partials r32.z32, |D^-1 r64|^2
+__global__ __launch_bounds__(256) void k_b_true_residual(
+    SegTiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ Av, const double *__restrict__ x, const double *__restrict__ b,
+    const double *__restrict__ dinv, const float *__restrict__ dinv32, float *__restrict__ r32,
+    double *__restrict__ partial, const BScalars *__restrict__ sc)
+{
+    const int g = logical_group(t.groups);
+    const int4 gr = t.grp[g];
+    if (!replacing(sc[gr.x])) return;
+    const int lane = threadIdx.x & (SLICE - 1);
+    double acc[2] = {0.0, 0.0};
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        double ax = 0.0;
+#pragma unroll 4
+        for (int64_t e = beg; e < end; e += SLICE) ax += Av[e] * x[col[e]];
+        const double ri = b[row] - ax;
+        const float rf = (float)ri;
+        r32[row] = rf;
+        const float zf = dinv32[row] * rf;
+        const double zi = dinv[row] * ri;
+        acc[0] += (double)rf * (double)zf;
+        acc[1] += zi * zi;
+    }
+    write_partials<2>(acc, partial, t.groups, g);
+}
+
+__global__ __launch_bounds__(256) void k_b_replace_finalize(int groups,
+                                                            const int32_t *__restrict__ inst_grp,
+                                                            const double *__restrict__ partial,
+                                                            BParams bp, BScalars *__restrict__ sc)
+{
+    const int i = blockIdx.x;
+    BScalars &s = sc[i];
+    if (!replacing(s)) return;
+    double v[2];
+    reduce_range<2>(partial, groups, inst_grp[i], inst_grp[i + 1], v);
+    if (threadIdx.x != 0) return;
+    const double zn = sqrt(v[1]);
+    const int it = s.it;
+    s.znorm = zn;
+    s.replace = 0;
+    if (!(zn == zn) || !(v[0] == v[0])) {
+        s.nonfinite = 1;
+        s.done = 1;
+        s.iters = it;
+        return;
+    }
+    if (zn < bp.atol || zn < bp.rtol * s.ref || zn <= s.floor_) {
+        s.done = 1;
+        s.iters = it;
+        return;
+    }
+    if (it >= bp.max_iter) {
+        s.failed = 1;
+        s.done = 1;
+        s.iters = it;
+        return;
+    }
+    s.beta = v[0] / s.rho;
+    s.rho = v[0];
+    s.redirect = 1;
+}
+
+__global__ __launch_bounds__(256) void k_b_redirect(SegTiling t, const float *__restrict__ dinv32,
+                                                    const float *__restrict__ r,
+                                                    float *__restrict__ p,
+                                                    const BScalars *__restrict__ sc)
+{
+    const int4 gr = t.grp[logical_group(t.groups)];
+    const BScalars &s = sc[gr.x];
+    if (!s.redirect || s.done) return;
+    const float bf = (float)s.beta;
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+        const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+        p[i] = dinv32[i] * r[i] + bf * p[i];
+    }
+}
+
+template <class Ptr, class Kernel>
+void spmv_launch(Kernel k, hipStream_t s, const SegTiling &t, const Ptr *ptr, const IterMatrix &A,
+                 const float *p32, float *q32, double *part_pq, const BScalars *sc, hipEvent_t e0,
+                 hipEvent_t e1)
+{
+    if (e0)
+        hipExtLaunchKernelGGL(k, dim3(t.groups), dim3(TILE), 0, s, e0, e1, 0, t, ptr, A.col, A.val,
+                              p32, q32, part_pq, sc);
+    else
+        hipLaunchKernelGGL(k, dim3(t.groups), dim3(TILE), 0, s, t, ptr, A.col, A.val, p32, q32,
+                           part_pq, sc);
+}
+
+}  // namespace
+
+void launch_relayout(hipStream_t s, int lpr, int64_t n_slices, const int64_t *sptr_new,
+                     SellView base, const float *A32, int32_t *col_new, float *A32_new)
+{
+    const int64_t threads = n_slices * SLICE;
+    if (threads > 0)
+        hipLaunchKernelGGL(k_relayout, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, lpr,
+                           n_slices, sptr_new, base.slice_ptr, base.col, A32, col_new, A32_new);
+}
+
+void launch_b_rhs_init(hipStream_t s, const SegTiling &t, SellView P, const double *Mv,
+                       const double *Kv, const double *dinv, const float *dinv32,
+                       const StepParams &sp, const double *V, const double *Vprev,
+                       const double *src, double *x, double *b, float *r32, float *delta,
+                       double *partial)
+{
+    hipLaunchKernelGGL(k_b_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
+                       dinv, dinv32, sp, V, Vprev, src, x, b, r32, delta, partial);
+}
+
+void launch_b_init_finalize(hipStream_t s, const SegTiling &t, const double *partial,
+                            const BParams &bp, BScalars *sc)
+{
+    hipLaunchKernelGGL(k_b_init_finalize, dim3(t.n_inst), dim3(TILE), 0, s, t.groups, t.inst_grp,
+                       partial, bp, sc);
+}
+
+void launch_b_set_direction(hipStream_t s, const SegTiling &t, const float *dinv32,
+                            const float *r32, float *p32, const BScalars *sc)
+{
+    hipLaunchKernelGGL(k_b_set_direction, dim3(t.groups), dim3(TILE), 0, s, t, dinv32, r32, p32, sc);
+}
+
+void launch_build_csr(hipStream_t s, int64_t n_rows, SellView base, const float *A32,
+                      const int32_t *rptr, int32_t *col_csr, float *val_csr)
+{
+    if (n_rows > 0)
+        hipLaunchKernelGGL(k_build_csr, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, s,
+                           n_rows, base.slice_ptr, base.col, A32, rptr, col_csr, val_csr);
+}
+
+void launch_b_spmv(hipStream_t s, const SegTiling &t, const IterMatrix &A, const float *p32,
+                   float *q32, double *part_pq, const BScalars *sc, hipEvent_t e0, hipEvent_t e1)
+{
+    if (A.format == 1) {
+        if (A.lpr == 16)
+            spmv_launch(k_b_spmv_csr<16>, s, t, A.rptr, A, p32, q32, part_pq, sc, e0, e1);
+        else if (A.lpr == 8)
+            spmv_launch(k_b_spmv_csr<8>, s, t, A.rptr, A, p32, q32, part_pq, sc, e0, e1);
+        else
+            spmv_launch(k_b_spmv_csr<4>, s, t, A.rptr, A, p32, q32, part_pq, sc, e0, e1);
+    } else {
+        if (A.lpr == 4)
+            spmv_launch(k_b_spmv<4>, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
+        else if (A.lpr == 2)
+            spmv_launch(k_b_spmv<2>, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
+        else
+            spmv_launch(k_b_spmv<1>, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
+    }
+}
+
+void launch_b_iteration(hipStream_t s, const SegTiling &t, const IterMatrix &A, const BParams &bp,
+                        const float *dinv32, float *p32, float *q32, float *delta, float *r32,
+                        double *part_pq, double *part_rz, BScalars *sc, hipEvent_t ev_start,
+                        hipEvent_t ev_stop)
+{
+    launch_b_spmv(s, t, A, p32, q32, part_pq, sc, ev_start, ev_stop);
+    hipLaunchKernelGGL(k_b_alpha, dim3(t.n_inst), dim3(TILE), 0, s, t.groups, t.inst_grp, part_pq,
+                       sc);
+    hipLaunchKernelGGL(k_b_update, dim3(t.groups), dim3(TILE), 0, s, t, dinv32, p32, q32, delta, r32,
+                       part_rz, sc);
+    hipLaunchKernelGGL(k_b_beta, dim3(t.n_inst), dim3(TILE), 0, s, t.groups, t.inst_grp, part_rz, bp,
+                       sc);
+    hipLaunchKernelGGL(k_b_direction, dim3(t.groups), dim3(TILE), 0, s, t, dinv32, r32, p32, sc);
+}
+
+void launch_b_replacement(hipStream_t s, const SegTiling &t, SellView P, const BParams &bp,
+                          const double *Av, double *x, float *delta, const double *b,
+                          const double *dinv, const float *dinv32, float *r32, float *p32,
+                          double *partial, BScalars *sc)
+{
+    hipLaunchKernelGGL(k_b_flush, dim3(t.groups), dim3(TILE), 0, s, t, x, delta, sc);
+    hipLaunchKernelGGL(k_b_true_residual, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av,
+                       x, b, dinv, dinv32, r32, partial, sc);
+    hipLaunchKernelGGL(k_b_replace_finalize, dim3(t.n_inst), dim3(TILE), 0, s, t.groups, t.inst_grp,
+                       partial, bp, sc);
+    hipLaunchKernelGGL(k_b_redirect, dim3(t.groups), dim3(TILE), 0, s, t, dinv32, r32, p32, sc);
+}
+
+}  // namespace mdx

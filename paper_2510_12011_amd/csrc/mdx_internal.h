@@ -80,13 +80,15 @@ int ionic_nstates(int kind);
 int ionic_nparams(int kind);
 void ionic_defaults(int kind, double *params);
 // params: host array of ionic_nparams(kind) values (passed by value to kernels)
+// tile_real (optional): per-tile count of real rows of the batched layout;
+// rows beyond it are padding (no cell; out = 0, state untouched)
 void launch_ionic_init(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
-                       double *V, double *Vprev, double *u);
+                       double *V, double *Vprev, double *u, const int32_t *tile_real = nullptr);
 // u advanced in place from V; out[i] = istim[i] - cm * I_ion/Cm if raw == 0,
 // or I_ion/Cm (mV/ms) if raw != 0.  istim may be null (no active stimulus).
 void launch_ionic_step(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                        double dt, double cm, const double *V, double *u, const double *istim,
-                       double *out, int raw);
+                       double *out, int raw, const int32_t *tile_real = nullptr);
 
 // Mixed-precision form: gates in FP32 (g32, ionic_gate_rows(kind) rows of ld
 // floats), concentrations and the current in FP64 (u).  The FP64 array u
@@ -96,7 +98,8 @@ int ionic_gate_rows(int kind);
 int ionic_gate_row0(int kind);
 void launch_ionic_step_mixed(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                              double dt, double cm, const double *V, double *u, float *g32,
-                             const double *istim, double *out);
+                             const double *istim, double *out,
+                             const int32_t *tile_real = nullptr);
 void launch_gates_to_f32(hipStream_t s, int kind, int64_t ld, const double *u, float *g32);
 void launch_gates_to_f64(hipStream_t s, int kind, int64_t ld, const float *g32, double *u);
 
@@ -158,6 +161,100 @@ void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, c
 void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
                    double *r, float *r32, float *delta, const Scalars *sc);
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv);
+
+// ---- batched form (mdx_batch.hip) -----------------------------------------
+// Several independent systems ("instances") share one block-diagonal matrix.
+// Each instance's rows form a contiguous range that starts on a TILE
+// boundary; the rows between its last real row and the next boundary are
+// padding (empty rows, zero vectors, excluded from the ionic update by the
+// per-tile count of real rows).  Every workgroup works for exactly one
+// instance: entry g of the group table is {instance, first tile, end tile}
+// and the groups of instance i are [inst_grp[i], inst_grp[i+1]), so a
+// producer's per-group partials of one instance are contiguous and one
+// finalize workgroup per instance reduces them in a fixed order.
+struct SegTiling {
+    int groups;                 // workgroups launched
+    int n_inst;
+    const int4 *grp;            // [groups] {instance, tile begin, tile end, 0}
+    const int32_t *inst_grp;    // [n_inst + 1] first group of each instance
+};
+
+// Per-instance solver state of the batched mixed-precision PCG.  Only the
+// finalize kernels (one workgroup per instance) write it; every other kernel
+// reads it, so kernel boundaries order all accesses.
+struct alignas(128) BScalars {
+    double rho;         // r.z of the current iteration
+    double alpha, beta;
+    double ref;         // denominator of the relative stopping test
+    double floor_;      // rounding floor 1e-15 ||D^-1 b||
+    double z0, znorm;
+    int32_t done;       // finished: converged, failed or non-finite
+    int32_t iters;      // iterations of the finished solve
+    int32_t it;         // iterations completed so far
+    int32_t replace;    // residual replacement pending (iteration kernels idle)
+    int32_t redirect;   // replacement did not stop: p = z + beta p pending
+    int32_t nonfinite;  // a non-finite value reached a reduction
+    int32_t failed;     // iteration cap reached without convergence
+    int32_t pad_;
+};
+
+struct BParams {
+    double atol, rtol;
+    int max_iter;       // per step
+    int rr;             // replacement interval (0: only at the stopping test and the cap)
+    int rel_mode;       // 0: relative to ||z_0||, 1: relative to ||D^-1 b||
+};
+
+// Alternative layout of the iteration matrix for lpr lanes per row
+// (lpr in {1, 2, 4}; 64 / lpr rows per wavefront): slices of 64/lpr rows;
+// step j of the row in slice position s and sub-lane u holds entry
+// j*lpr + u of that row at slice_ptr[slice] + 64*j + s*lpr + u.  lpr = 1 is
+// the base layout.  sell_width(lpr) gives slice widths (steps) from row
+// lengths; launch_relayout fills col / FP32 values from the base layout.
+void launch_relayout(hipStream_t s, int lpr, int64_t n_slices, const int64_t *sptr_new,
+                     SellView base, const float *A32, int32_t *col_new, float *A32_new);
+
+// The iteration matrix as the SpMV reads it: sliced ELL (format 0, lpr in
+// {1, 2, 4}, slice pointers sptr) or CSR (format 1, lpr in {4, 8, 16} lanes
+// reading each row's contiguous entries, row pointers rptr), both in the
+// internal row order with the FP32 values.
+struct IterMatrix {
+    int format;
+    int lpr;
+    const int64_t *sptr;
+    const int32_t *rptr;
+    const int32_t *col;
+    const float *val;
+};
+// CSR copy of the FP32 iteration matrix from the base sliced layout (rptr:
+// row pointers of the real entries, already on the device)
+void launch_build_csr(hipStream_t s, int64_t n_rows, SellView base, const float *A32,
+                      const int32_t *rptr, int32_t *col_csr, float *val_csr);
+
+void launch_b_rhs_init(hipStream_t s, const SegTiling &t, SellView P, const double *Mv,
+                       const double *Kv, const double *dinv, const float *dinv32,
+                       const StepParams &sp, const double *V, const double *Vprev,
+                       const double *src, double *x, double *b, float *r32, float *delta,
+                       double *partial);
+void launch_b_init_finalize(hipStream_t s, const SegTiling &t, const double *partial,
+                            const BParams &bp, BScalars *sc);
+void launch_b_set_direction(hipStream_t s, const SegTiling &t, const float *dinv32,
+                            const float *r32, float *p32, const BScalars *sc);
+// one PCG iteration of every running instance: q = A p (+p.q), alpha,
+// update (+r.z, z.z), test / beta, direction
+void launch_b_iteration(hipStream_t s, const SegTiling &t, const IterMatrix &A,
+                        const BParams &bp, const float *dinv32, float *p32, float *q32,
+                        float *delta, float *r32, double *part_pq, double *part_rz, BScalars *sc,
+                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// flush, true residual, finalize, redirect for instances with a pending replacement
+void launch_b_replacement(hipStream_t s, const SegTiling &t, SellView P, const BParams &bp,
+                          const double *Av, double *x, float *delta, const double *b,
+                          const double *dinv, const float *dinv32, float *r32, float *p32,
+                          double *partial, BScalars *sc);
+// the SpMV of the iteration alone (timing by the autotuner): q = A p, partial p.q
+void launch_b_spmv(hipStream_t s, const SegTiling &t, const IterMatrix &A,
+                   const float *p32, float *q32, double *part_pq, const BScalars *sc,
+                   hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // ---- solver (mdx_solver.hip) ---------------------------------------------
 void launch_fill(hipStream_t s, int64_t n, double v, double *x);

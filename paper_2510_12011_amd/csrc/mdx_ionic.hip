@@ -286,16 +286,29 @@ __device__ double tt_point(const IonicParams &P, double dt, double V, double *c,
     return tt_currents(P, V, vo, y).total();
 }
 
+// Row i holds a cell: i < n, or, with the per-tile count of real rows of the
+// batched layout (padding rows at the end of each instance's last tile),
+// (i mod TILE) < tile_real[i / TILE].
+__device__ __forceinline__ bool real_row(int64_t i, int64_t n, const int32_t *tile_real)
+{
+    return tile_real ? (int)(i & (TILE - 1)) < tile_real[i / TILE] : i < n;
+}
+
 // ---------------------------------------------------------------------------
 template <int KIND>
 __global__ __launch_bounds__(256) void k_ionic_step(IonicParams P, int64_t n, int64_t ld, double dt,
                                                     double cm, const double *__restrict__ V,
                                                     double *__restrict__ u,
                                                     const double *__restrict__ istim,
-                                                    double *__restrict__ out, int raw)
+                                                    double *__restrict__ out, int raw,
+                                                    const int32_t *__restrict__ tile_real)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (!real_row(i, n, tile_real)) {
+        out[i] = 0.0;
+        return;
+    }
     double v = V[i];
     double iion = 0.0;
     if constexpr (KIND == MDX_KIND_MS) {
@@ -324,11 +337,12 @@ template <int KIND>
 __global__ __launch_bounds__(256) void k_ionic_init(IonicParams P, int64_t n, int64_t ld,
                                                     double *__restrict__ V,
                                                     double *__restrict__ Vprev,
-                                                    double *__restrict__ u)
+                                                    double *__restrict__ u,
+                                                    const int32_t *__restrict__ tile_real)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ld) return;
-    bool real = i < n;
+    const bool real = real_row(i, n, tile_real);
     double v0 = 0.0;
     if constexpr (KIND == MDX_KIND_MS) {
         v0 = P.v[5];
@@ -353,10 +367,15 @@ __global__ __launch_bounds__(256) void k_ionic_step_mixed(IonicParams P, int64_t
                                                           double *__restrict__ u,
                                                           float *__restrict__ g32,
                                                           const double *__restrict__ istim,
-                                                          double *__restrict__ out)
+                                                          double *__restrict__ out,
+                                                          const int32_t *__restrict__ tile_real)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (!real_row(i, n, tile_real)) {
+        out[i] = 0.0;
+        return;
+    }
     const double v = V[i];
     double iion = 0.0;
     if constexpr (KIND == MDX_KIND_MS) {
@@ -421,34 +440,34 @@ void ionic_defaults(int kind, double *params)
 }
 
 void launch_ionic_init(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
-                       double *V, double *Vprev, double *u)
+                       double *V, double *Vprev, double *u, const int32_t *tile_real)
 {
     IonicParams P = pack(kind, params);
     dim3 grid((unsigned)((ld + 255) / 256)), block(256);
     if (kind == 1)
-        hipLaunchKernelGGL(k_ionic_init<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, V, Vprev, u);
+        hipLaunchKernelGGL(k_ionic_init<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, V, Vprev, u, tile_real);
     else if (kind == 2)
-        hipLaunchKernelGGL(k_ionic_init<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, V, Vprev, u);
+        hipLaunchKernelGGL(k_ionic_init<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, V, Vprev, u, tile_real);
     else
-        hipLaunchKernelGGL(k_ionic_init<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, V, Vprev, u);
+        hipLaunchKernelGGL(k_ionic_init<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, V, Vprev, u, tile_real);
 }
 
 void launch_ionic_step(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                        double dt, double cm, const double *V, double *u, const double *istim,
-                       double *out, int raw)
+                       double *out, int raw, const int32_t *tile_real)
 {
     if (n <= 0) return;
     IonicParams P = pack(kind, params);
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (kind == 1)
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw);
+                           istim, out, raw, tile_real);
     else if (kind == 2)
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw);
+                           istim, out, raw, tile_real);
     else
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw);
+                           istim, out, raw, tile_real);
 }
 
 int ionic_gate_rows(int kind) { return kind == 1 ? 1 : kind == 2 ? 12 : 0; }
@@ -456,20 +475,20 @@ int ionic_gate_row0(int kind) { return kind == 1 ? 0 : kind == 2 ? 6 : 0; }
 
 void launch_ionic_step_mixed(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                              double dt, double cm, const double *V, double *u, float *g32,
-                             const double *istim, double *out)
+                             const double *istim, double *out, const int32_t *tile_real)
 {
     if (n <= 0) return;
     IonicParams P = pack(kind, params);
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (kind == 1)
         hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, dt, cm, V,
-                           u, g32, istim, out);
+                           u, g32, istim, out, tile_real);
     else if (kind == 2)
         hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, dt, cm, V,
-                           u, g32, istim, out);
+                           u, g32, istim, out, tile_real);
     else
         hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, dt, cm,
-                           V, u, g32, istim, out);
+                           V, u, g32, istim, out, tile_real);
 }
 
 void launch_gates_to_f32(hipStream_t s, int kind, int64_t ld, const double *u, float *g32)

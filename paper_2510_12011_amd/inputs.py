@@ -14,8 +14,11 @@ Meshes
   Kuhn (Freudenthal) tetrahedra that share the main diagonal of the hex; the
   split is conforming, so neighbouring hexes agree on their shared faces.
   Node numbering runs z fastest, then y, then x.
-* ``ellipsoid_shell``: a truncated ellipsoidal shell (ventricle-like) meshed by
-  Delaunay tetrahedralisation of a jittered lattice, with helical fibres.
+* ``ellipsoid_shell``: a truncated ellipsoidal shell (ventricle-like) built
+  as a curvilinear hexahedral grid split into Kuhn tets, with helical fibres.
+* ``shell_cap``: a truncated ellipsoidal shell meshed as unstructured tets
+  (Delaunay tetrahedralisation of a jittered lattice), with helical fibres;
+  ``batch_shells`` draws a seeded cohort of them for the batched form.
 """
 from __future__ import annotations
 
@@ -294,6 +297,7 @@ def ellipsoid_shell(a: float = 35.0, b: float = 30.0, c: float = 45.0, wall: flo
     e_p /= np.linalg.norm(e_p, axis=1, keepdims=True)
     e_t /= np.linalg.norm(e_t, axis=1, keepdims=True)
     fib = np.cos(alpha)[:, None] * e_p + np.sin(alpha)[:, None] * e_t
+    fib /= np.linalg.norm(fib, axis=1, keepdims=True)
     mesh = Mesh(xyz=xyz, tets=tets, grid=grid, fibre=fib, region=np.zeros(tets.shape[0], np.int32),
                 shape=(n_r, n_t, n_p))
     mesh.r_frac = np.repeat(rr, (n_t + 1) * n_p)        # per-node radial fraction
@@ -303,7 +307,10 @@ def ellipsoid_shell(a: float = 35.0, b: float = 30.0, c: float = 45.0, wall: flo
 
 def endocardial_site(mesh: Mesh, seed: int, radius: float = 1.5) -> np.ndarray:
     """Nodes within `radius` mm of a random endocardial node (seeded)."""
-    endo = np.nonzero(np.isclose(mesh.r_frac, mesh.r_in))[0]
+    if hasattr(mesh, "endo"):
+        endo = np.nonzero(mesh.endo)[0]
+    else:
+        endo = np.nonzero(np.isclose(mesh.r_frac, mesh.r_in))[0]
     rng = np.random.default_rng(seed)
     centre = mesh.grid[endo[rng.integers(endo.shape[0])]]
     d = np.linalg.norm(mesh.grid - centre, axis=1)
@@ -323,3 +330,184 @@ def shell_run(n_nodes: int = 1_200_000, ionic: str = "tt", dt: float = 0.02, n_s
                    sigma_l=0.17 * sigma_scale, sigma_t=0.019 * sigma_scale, chi=140.0, cm=0.01,
                    theta=0.5, ionic=ionic, dt=dt, n_steps=n_steps, stimuli=[stim], rtol=rtol,
                    rel_mode=rel_mode)
+
+
+# ---------------------------------------------------------------------------
+# unstructured shells and the batched cohort
+# ---------------------------------------------------------------------------
+def _cap_map(P, a, b, c, wall, rd, r_in):
+    """Parametric cylinder (disk of radius rd, height wall) -> ellipsoidal
+    cap shell.  The disk radius maps linearly to the polar angle (0 at the
+    apex, pi/2 at the equator), height to the radial fraction."""
+    u, v = P[..., 0] / rd, P[..., 1] / rd
+    rho = np.hypot(u, v)
+    f = 0.5 * np.pi * np.sinc(0.5 * rho)          # sin(pi rho / 2) / rho, smooth at 0
+    R = r_in + (1.0 - r_in) * (P[..., 2] / wall)
+    return np.stack([a * R * f * u, b * R * f * v, c * R * np.cos(0.5 * np.pi * rho)], axis=-1)
+
+
+def shell_cap(a: float = 35.0, b: float = 30.0, c: float = 45.0, wall: float = 9.0,
+              n_nodes: int = 100_000, seed: int = 0, jitter: float = 0.25,
+              fibre_endo_deg: float = 60.0, fibre_epi_deg: float = -60.0,
+              q_min: float = 0.05) -> Mesh:
+    """Truncated ellipsoidal shell (apex to the equatorial plane z = 0),
+    epicardial semi-axes (a, b, c) mm with c along z, wall thickness `wall`,
+    meshed with unstructured P1 tets.
+
+    A cubic lattice of about `n_nodes` points fills a parametric cylinder
+    (disk x wall depth); every coordinate is jittered by up to `jitter` of the
+    spacing (seeded); the points are Delaunay-tetrahedralised
+    (scipy.spatial.Delaunay, i.e. Qhull), tets of normalised quality
+    6 sqrt(2) vol / l_rms^3 below `q_min` (slivers) are dropped with any node
+    they leave unused, and the cylinder is mapped onto the shell (disk radius
+    to polar angle, depth to the radial fraction).  Fibres: helical angle
+    linear in depth from `fibre_endo_deg` (endocardium) to `fibre_epi_deg`
+    (epicardium), from the circumferential direction towards the long axis,
+    at element centroids.  mesh.endo marks the endocardial lattice layer."""
+    from scipy.spatial import Delaunay
+    rm = (a + b + c) / 3.0
+    r_in = 1.0 - wall / rm
+    rd = 0.5 * np.pi * rm
+    h = (np.pi * rd * rd * wall / n_nodes) ** (1.0 / 3.0)
+    for _ in range(3):   # match the lattice count to n_nodes
+        nz = max(2, int(round(wall / h)))
+        nd = int(np.ceil(rd / h))
+        xs = np.arange(-nd, nd + 1) * h
+        cnt = int(((xs[:, None] ** 2 + xs[None, :] ** 2) <= rd * rd).sum()) * (nz + 1)
+        h *= (cnt / n_nodes) ** (1.0 / 3.0)
+    nz = max(2, int(round(wall / h)))
+    hz = wall / nz
+    nd = int(np.ceil(rd / h))
+    xs = np.arange(-nd, nd + 1) * h
+    X, Y, Z = np.meshgrid(xs, xs, np.arange(nz + 1) * hz, indexing="ij")
+    keep = (X * X + Y * Y) <= rd * rd
+    grid_p = np.stack([X[keep], Y[keep], Z[keep]], axis=1)
+    layer = np.rint(grid_p[:, 2] / hz).astype(np.int64)
+    rng = np.random.default_rng(seed)
+    P = grid_p + rng.uniform(-jitter, jitter, grid_p.shape) * np.array([h, h, hz])
+    tets = Delaunay(P).simplices.astype(np.int64)
+    e = P[tets]
+    vol = np.einsum("ij,ij->i", e[:, 1] - e[:, 0], np.cross(e[:, 2] - e[:, 0], e[:, 3] - e[:, 0])) / 6.0
+    l2 = sum(((e[:, i] - e[:, j]) ** 2).sum(1) for i in range(4) for j in range(i + 1, 4)) / 6.0
+    q = 6.0 * np.sqrt(2.0) * np.abs(vol) / l2 ** 1.5
+    tets = tets[q >= q_min]
+    used = np.zeros(P.shape[0], bool)
+    used[tets.ravel()] = True
+    new_id = np.cumsum(used) - 1
+    tets = new_id[tets]
+    P, grid_p, layer = P[used], grid_p[used], layer[used]
+    xyz = _cap_map(P, a, b, c, wall, rd, r_in)
+    grid = _cap_map(grid_p, a, b, c, wall, rd, r_in)
+    # orient positively in physical space
+    e = xyz[tets]
+    det = np.einsum("ij,ij->i", e[:, 1] - e[:, 0], np.cross(e[:, 2] - e[:, 0], e[:, 3] - e[:, 0]))
+    flip = det < 0
+    tets[flip, 2], tets[flip, 3] = tets[flip, 3].copy(), tets[flip, 2].copy()
+    # fibres at parametric centroids
+    cen = P[tets].mean(axis=1)
+    rho = np.hypot(cen[:, 0], cen[:, 1]) / rd
+    th, ph = 0.5 * np.pi * rho, np.arctan2(cen[:, 1], cen[:, 0])
+    depth = np.clip(cen[:, 2] / wall, 0.0, 1.0)
+    alpha = np.deg2rad(fibre_endo_deg + (fibre_epi_deg - fibre_endo_deg) * depth)
+    e_p = np.stack([-a * np.sin(ph), b * np.cos(ph), np.zeros_like(ph)], axis=1)
+    e_t = np.stack([a * np.cos(th) * np.cos(ph), b * np.cos(th) * np.sin(ph), -c * np.sin(th)],
+                   axis=1)
+    e_p /= np.linalg.norm(e_p, axis=1, keepdims=True)
+    e_t /= np.linalg.norm(e_t, axis=1, keepdims=True)
+    fib = np.cos(alpha)[:, None] * e_p + np.sin(alpha)[:, None] * e_t
+    fib /= np.linalg.norm(fib, axis=1, keepdims=True)
+    mesh = Mesh(xyz=xyz, tets=tets.astype(np.int32), grid=grid, fibre=fib,
+                region=np.zeros(tets.shape[0], np.int32), shape=(nz, nd))
+    mesh.endo = layer == 0
+    return mesh
+
+
+@dataclass
+class Instance:
+    """One member of a batch: its own mesh, conductivities and stimuli."""
+    mesh: Mesh
+    sigma_l: float
+    sigma_t: float
+    stimuli: list
+
+
+@dataclass
+class BatchSpec:
+    """Independent monodomain problems advanced together (batched form)."""
+    name: str
+    instances: list
+    chi: float
+    cm: float
+    theta: float
+    ionic: str
+    dt: float
+    n_steps: int
+    rtol: float = 1e-8
+    atol: float = 0.0
+    rel_mode: int = 1
+    max_iter: int = 1000
+    warm_start: int = 1
+    precision: str = "mixed"
+    rr_interval: int = 50
+
+    @property
+    def n_nodes(self) -> int:
+        return sum(i.mesh.n_nodes for i in self.instances)
+
+    def node_ptr(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum([i.mesh.n_nodes for i in self.instances])]).astype(
+            np.int64)
+
+    def instance_spec(self, k: int) -> RunSpec:
+        """Instance k as a stand-alone run."""
+        it = self.instances[k]
+        return RunSpec(name=f"{self.name}_inst{k}", mesh=it.mesh, sigma_l=it.sigma_l,
+                       sigma_t=it.sigma_t, chi=self.chi, cm=self.cm, theta=self.theta,
+                       ionic=self.ionic, dt=self.dt, n_steps=self.n_steps, stimuli=it.stimuli,
+                       rtol=self.rtol, atol=self.atol, rel_mode=self.rel_mode,
+                       max_iter=self.max_iter, warm_start=self.warm_start,
+                       precision=self.precision, rr_interval=self.rr_interval)
+
+
+def _cap_job(args):
+    return shell_cap(**args)
+
+
+def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
+                 n_min: int = 50_000, n_max: int = 400_000, n_steps: int = 5000,
+                 dt: float = 0.01, ionic: str = "ms", workers: int = 1,
+                 axes_mm: tuple = (25.0, 45.0), wall_mm: tuple = (6.0, 12.0),
+                 stim_radius: float = 1.5) -> BatchSpec:
+    """A seeded cohort of unstructured ellipsoidal shells: semi-axes
+    U(axes_mm) (default 25-45 mm, the longest along z), wall U(wall_mm)
+    (default 6-12 mm), node targets log-uniform in [n_min, n_max] rescaled to
+    sum to about total_nodes (and clipped to the range), sigma (0.17, 0.019)
+    S/m times U(0.5, 1.5), stimulus 0.5 uA/mm^2 for 2 ms on the nodes within
+    stim_radius mm of a random endocardial node; Mitchell-Schaeffer cells,
+    chi 140/mm, Cm 0.01 uF/mm^2, theta 0.5, relative tolerance 1e-8 of
+    ||D^-1 b||, mixed precision."""
+    rng = np.random.default_rng(seed)
+    axes = np.sort(rng.uniform(axes_mm[0], axes_mm[1], (n_inst, 3)), axis=1)
+    walls = rng.uniform(wall_mm[0], wall_mm[1], n_inst)
+    n = np.exp(rng.uniform(np.log(n_min), np.log(n_max), n_inst))
+    for _ in range(20):
+        n = np.clip(n * (total_nodes / n.sum()), n_min, n_max)
+    scale = rng.uniform(0.5, 1.5, n_inst)
+    sites = rng.integers(0, 2 ** 31 - 1, n_inst)
+    jobs = [dict(a=float(axes[i, 0]), b=float(axes[i, 1]), c=float(axes[i, 2]),
+                 wall=float(walls[i]), n_nodes=int(n[i]), seed=int(seed * 1000 + i))
+            for i in range(n_inst)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            meshes = pool.map(_cap_job, jobs, chunksize=1)
+    else:
+        meshes = [shell_cap(**j) for j in jobs]
+    inst = []
+    for i, m in enumerate(meshes):
+        stim = Stimulus(endocardial_site(m, int(sites[i]), stim_radius), 0.0, 2.0,
+                        50.0 * UA_PER_CM2_TO_PER_MM2)
+        inst.append(Instance(mesh=m, sigma_l=0.17 * scale[i], sigma_t=0.019 * scale[i],
+                             stimuli=[stim]))
+    return BatchSpec(name=f"shells{n_inst}_{sum(m.n_nodes for m in meshes)}", instances=inst,
+                     chi=140.0, cm=0.01, theta=0.5, ionic=ionic, dt=dt, n_steps=n_steps)

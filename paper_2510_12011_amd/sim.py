@@ -80,6 +80,20 @@ class Simulation:
                                          tets.shape[0], _ptr(tets), _ptr(region), _ptr(fibre)))
         self.n = xyz.shape[0]
 
+    def set_mesh_batch(self, node_ptr, xyz, tets, region=None, fibre=None, unit_conversion=1.0):
+        """Several meshes as one batched context: instance i owns the nodes
+        [node_ptr[i], node_ptr[i+1]) of the concatenated arrays."""
+        ptr = np.ascontiguousarray(node_ptr, np.int64)
+        xyz = np.ascontiguousarray(xyz, np.float64)
+        tets = np.ascontiguousarray(tets, np.int32)
+        region = None if region is None else np.ascontiguousarray(region, np.int32)
+        fibre = None if fibre is None else np.ascontiguousarray(fibre, np.float64)
+        self._check(L.lib().mdx_set_mesh_batch(self._h, ptr.shape[0] - 1, _ptr(ptr), xyz.shape[0],
+                                               _ptr(xyz), unit_conversion, tets.shape[0],
+                                               _ptr(tets), _ptr(region), _ptr(fibre)))
+        self.n = xyz.shape[0]
+        self.node_ptr = ptr
+
     def add_conductivity(self, region_ids, il, it):
         ids = np.ascontiguousarray(np.atleast_1d(region_ids), np.int32)
         self._check(L.lib().mdx_add_conductivity(self._h, ids.shape[0], _ptr(ids), il, it))
@@ -148,11 +162,36 @@ class Simulation:
         self._check(L.lib().mdx_get_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in L.Stats._fields_}
 
-    def set_tuning(self, max_groups=None, iter_scheme=None):
-        if max_groups is not None:
-            self._check(L.lib().mdx_set_tuning(self._h, L.MDX_TUNE_MAX_GROUPS, int(max_groups)))
-        if iter_scheme is not None:
-            self._check(L.lib().mdx_set_tuning(self._h, L.MDX_TUNE_ITER_SCHEME, int(iter_scheme)))
+    def set_tuning(self, max_groups=None, iter_scheme=None, lanes_per_row=None,
+                   tiles_per_group=None, graph=None, fmt=None):
+        """fmt: 'sell' or 'csr' (batched iteration SpMV storage), set before
+        lanes_per_row."""
+        f = None if fmt is None else {"sell": 0, "csr": 1}[fmt]
+        for key, v in ((L.MDX_TUNE_MAX_GROUPS, max_groups), (L.MDX_TUNE_ITER_SCHEME, iter_scheme),
+                       (L.MDX_TUNE_FORMAT, f),
+                       (L.MDX_TUNE_LANES_PER_ROW, lanes_per_row),
+                       (L.MDX_TUNE_TILES_PER_GROUP, tiles_per_group),
+                       (L.MDX_TUNE_GRAPH, None if graph is None else int(bool(graph)))):
+            if v is not None:
+                self._check(L.lib().mdx_set_tuning(self._h, key, int(v)))
+
+    def instance_iterations(self, n):
+        """Batched context: PCG iterations [n steps, n_inst] (-1: not converged)."""
+        k = self.node_ptr.shape[0] - 1
+        it = np.zeros((n, k), np.int32)
+        self._check(L.lib().mdx_get_instance_iterations(self._h, n, _ptr(it)))
+        return it
+
+    def autotune(self, reps=20):
+        """Batched context: time the SpMV variants, install the fastest."""
+        r = L.TuneReport()
+        self._check(L.lib().mdx_autotune(self._h, int(reps), C.byref(r)))
+        fmts = ("sell", "csr")
+        cands = [(fmts[r.cand_format[i]], r.cand_lanes_per_row[i], r.cand_tiles_per_group[i],
+                  r.cand_seconds[i]) for i in range(r.n_candidates)]
+        return dict(fmt=fmts[r.format], lanes_per_row=r.lanes_per_row,
+                    tiles_per_group=r.tiles_per_group, seconds=r.seconds, bytes=r.bytes,
+                    candidates=cands)
 
     def set_profiling(self, every_n=1):
         """Time the SpMV launches of every every_n-th step (0: off)."""
@@ -222,3 +261,44 @@ def from_spec(spec, device: int = 0, ionic_params=None, prepare=True,
     if prepare:
         sim.prepare(spec.dt)
     return sim
+
+
+def batch_from_spec(bspec, device: int = 0, ionic_params=None, prepare=True) -> Simulation:
+    """Build a batched Simulation from an inputs.BatchSpec: the instances'
+    meshes concatenated, instance k's elements tagged region k with its own
+    conductivities, its stimuli moved to the concatenated numbering."""
+    sim = Simulation(device)
+    ptr = bspec.node_ptr()
+    inst = bspec.instances
+    xyz = np.concatenate([i.mesh.xyz for i in inst])
+    tets = np.concatenate([i.mesh.tets + ptr[k] for k, i in enumerate(inst)]).astype(np.int32)
+    region = np.concatenate([np.full(i.mesh.n_tets, k, np.int32) for k, i in enumerate(inst)])
+    fibre = (None if any(i.mesh.fibre is None for i in inst) else
+             np.concatenate([i.mesh.fibre for i in inst]))
+    sim.set_mesh_batch(ptr, xyz, tets, region, fibre)
+    for k, i in enumerate(inst):
+        sim.add_conductivity([k], i.sigma_l, i.sigma_t)
+    sim.set_tissue(bspec.chi, bspec.cm, bspec.theta)
+    sim.set_ionic(bspec.ionic, ionic_params)
+    for k, i in enumerate(inst):
+        for s in i.stimuli:
+            sim.add_stimulus(np.asarray(s.nodes) + ptr[k], s.start, s.duration, s.intensity)
+    sim.set_solver(bspec.atol, bspec.rtol, bspec.rel_mode, bspec.max_iter, bspec.warm_start,
+                   PRECISION[bspec.precision], bspec.rr_interval)
+    if prepare:
+        sim.prepare(bspec.dt)
+    return sim
+
+
+def batch_of_one(spec, device: int = 0, ionic_params=None, prepare=True) -> Simulation:
+    """A single RunSpec as a batched context of one instance (same solver as
+    a batch, for comparing a batch member with its stand-alone run)."""
+    from .inputs import BatchSpec, Instance
+    b = BatchSpec(name=spec.name, instances=[Instance(spec.mesh, spec.sigma_l, spec.sigma_t,
+                                                      spec.stimuli)],
+                  chi=spec.chi, cm=spec.cm, theta=spec.theta, ionic=spec.ionic, dt=spec.dt,
+                  n_steps=spec.n_steps, rtol=spec.rtol, atol=spec.atol, rel_mode=spec.rel_mode,
+                  max_iter=spec.max_iter, warm_start=spec.warm_start,
+                  precision=spec.precision if spec.precision != "fp64" else "mixed",
+                  rr_interval=spec.rr_interval)
+    return batch_from_spec(b, device, ionic_params, prepare)

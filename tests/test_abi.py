@@ -136,3 +136,66 @@ def test_workspace_sizing_and_pattern_stats(host_ctx):
     assert lib.mdx_workspace_size(host_ctx, C.byref(a), C.byref(b)) == L.MDX_OK
     assert a.value - ms_bytes >= 17 * 8 * m.n_nodes
     assert a.value % 256 == 0 and b.value % 256 == 0
+
+
+def _two_boxes():
+    a = inputs.kuhn_box(3, 2, 2, 1.5, 1.0, 1.0, fibre=(1.0, 0.0, 0.0))
+    b = inputs.kuhn_box(2, 4, 3, 1.0, 2.0, 1.5, jitter=0.05, seed=1, fibre=(0.0, 1.0, 0.0))
+    xyz = np.ascontiguousarray(np.concatenate([a.xyz, b.xyz + 5.0]))
+    tets = np.ascontiguousarray(np.concatenate([a.tets, b.tets + a.n_nodes]).astype(np.int32))
+    fib = np.ascontiguousarray(np.concatenate([a.fibre, b.fibre]))
+    ptr = np.array([0, a.n_nodes, a.n_nodes + b.n_nodes], np.int64)
+    return a, b, xyz, tets, fib, ptr
+
+
+def test_batch_validation(host_ctx):
+    """Instances must partition the nodes, and no element may join two."""
+    lib = L.lib()
+    a, b, xyz, tets, fib, ptr = _two_boxes()
+    n, ne = xyz.shape[0], tets.shape[0]
+    ok = lib.mdx_set_mesh_batch(host_ctx, 2, _p(ptr), n, _p(xyz), 1.0, ne, _p(tets), None, _p(fib))
+    assert ok == L.MDX_OK
+    bad_ptr = np.array([0, a.n_nodes, n - 1], np.int64)
+    assert lib.mdx_set_mesh_batch(host_ctx, 2, _p(bad_ptr), n, _p(xyz), 1.0, ne, _p(tets), None,
+                                  _p(fib)) == L.MDX_ERR_INVALID_ARG
+    empty = np.array([0, 0, n], np.int64)
+    assert lib.mdx_set_mesh_batch(host_ctx, 2, _p(empty), n, _p(xyz), 1.0, ne, _p(tets), None,
+                                  _p(fib)) == L.MDX_ERR_INVALID_ARG
+    cross = tets.copy()
+    cross[0, 3] = a.n_nodes + 2                 # element of instance 0 touching instance 1
+    assert lib.mdx_set_mesh_batch(host_ctx, 2, _p(ptr), n, _p(xyz), 1.0, ne, _p(cross), None,
+                                  _p(fib)) == L.MDX_ERR_BAD_MESH
+    assert "two instances" in _err(host_ctx)
+    assert lib.mdx_set_mesh_batch(host_ctx, 0, _p(ptr), n, _p(xyz), 1.0, ne, _p(tets), None,
+                                  _p(fib)) == L.MDX_ERR_INVALID_ARG
+
+
+def test_batch_layout_is_block_diagonal(host_ctx):
+    """The batched pattern holds exactly the instances' own patterns (no
+    coupling), each instance's rows padded to whole 256-row tiles."""
+    lib = L.lib()
+    a, b, xyz, tets, fib, ptr = _two_boxes()
+    n, ne = xyz.shape[0], tets.shape[0]
+    assert lib.mdx_set_mesh(host_ctx, a.n_nodes, _p(np.ascontiguousarray(a.xyz)), 1.0, a.n_tets,
+                            _p(np.ascontiguousarray(a.tets)), None, None) == L.MDX_OK
+    sa = L.Stats()
+    lib.mdx_get_stats(host_ctx, C.byref(sa))
+    bx, bt = np.ascontiguousarray(b.xyz), np.ascontiguousarray(b.tets)
+    assert lib.mdx_set_mesh(host_ctx, b.n_nodes, _p(bx), 1.0, b.n_tets, _p(bt), None,
+                            None) == L.MDX_OK
+    sb = L.Stats()
+    lib.mdx_get_stats(host_ctx, C.byref(sb))
+    assert lib.mdx_set_mesh_batch(host_ctx, 2, _p(ptr), n, _p(xyz), 1.0, ne, _p(tets), None,
+                                  _p(fib)) == L.MDX_OK
+    st = L.Stats()
+    lib.mdx_get_stats(host_ctx, C.byref(st))
+    assert st.nnz == sa.nnz + sb.nnz
+    assert st.n_sell_slots == sa.n_sell_slots + sb.n_sell_slots
+    assert st.bandwidth == max(sa.bandwidth, sb.bandwidth)
+    # internal rows of a batch include padding: no node order to return
+    order = np.zeros(n, np.int32)
+    assert lib.mdx_get_node_order(host_ctx, _p(order)) == L.MDX_ERR_UNSUPPORTED
+    # batched-only calls on an unprepared context fail cleanly
+    assert lib.mdx_autotune(host_ctx, 5, None) == L.MDX_ERR_STATE
+    assert lib.mdx_set_tuning(host_ctx, L.MDX_TUNE_LANES_PER_ROW, 2) == L.MDX_ERR_STATE
+    assert lib.mdx_set_tuning(host_ctx, L.MDX_TUNE_GRAPH, 2) == L.MDX_ERR_INVALID_ARG
