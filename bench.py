@@ -67,6 +67,102 @@ def cpu_baseline(spec, steps, threads=None):
                       f"(mean {float(np.mean(it)):.1f} CG iterations/step), setup excluded"}
 
 
+def learned_workload(args):
+    """The learned form: one ~1.2M-node ellipsoidal shell, ten Tusscher-Panfilov,
+    dt 0.02 ms, rtol 1e-8 of ||D^-1 b||.  The network is trained on the GPU
+    (library kernels) on trajectories of the plain solver from random
+    endocardial sites; then a held-out site is run twice from rest for the
+    same K steps: learned warm start + mixed precision (the value) and the
+    plain FP64 PCG with the paper's extrapolated warm start (the comparison),
+    both to the same tolerance."""
+    import torch
+    from paper_2510_12011_amd import _lib as L, inputs, learn, sim
+    t0 = time.perf_counter()
+    mesh = inputs.ellipsoid_shell(n_nodes=1_200_000, seed=1000)
+    n = mesh.n_nodes
+
+    def spec(site, steps):
+        return inputs.shell_run(mesh=mesh, ionic="tt", dt=0.02, n_steps=steps, site_seed=site)
+
+    Xs, Ds = [], []
+    for site in range(1, args.train_sites + 1):
+        s = sim.from_spec(spec(site, args.train_steps))
+        X, dV = learn.record(s, args.train_steps, every=10, seed=site)
+        keep = torch.randperm(X.shape[0], device=X.device)[:2_000_000]
+        Xs.append(X[keep])
+        Ds.append(dV[keep])
+        trainer = s
+    X, dV = torch.cat(Xs), torch.cat(Ds)
+    params, norm, hist = learn.fit(trainer, X, dV, epochs=6, batch=8192, lr=2e-3)
+    del Xs, Ds, X, dV
+    print(f"[bench] shell {n} nodes; trained on {args.train_sites} sites x {args.train_steps} "
+          f"steps, loss {hist[0]:.4f} -> {hist[-1]:.4f}, setup {time.perf_counter() - t0:.1f} s",
+          flush=True)
+
+    def timed(precision, ws, mlp):
+        s = sim.from_spec(spec(101, args.steps), precision=precision)
+        if mlp:
+            learn.install(s, params, norm)
+        s.set_solver(0.0, 1e-8, 1, 1000, ws, sim.PRECISION[precision], 50)
+        if args.warmup:
+            s.run(args.warmup)
+            s.prepare(s.dt)
+            if mlp:
+                learn.install(s, params, norm)
+        s.set_profiling(args.profile_every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, status = s.run(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        it = s.iterations(args.steps)
+        st = s.stats()
+        V = s.get_state()["V"]
+        print(f"[bench] {precision} warm start {'MLP' if mlp else 'extrapolated'}: "
+              f"{args.steps} steps in {el:.3f} s, mean CG iterations {it.mean():.2f}, "
+              f"fallbacks {st['fallbacks']}, status {status}", flush=True)
+        return dict(seconds=el, iters=it, stats=st, V=V)
+
+    lrn = timed("mixed", L.MDX_WS_MLP, True)
+    ref = timed("fp64", L.MDX_WS_EXTRAP, False)
+    value = n * args.steps / lrn["seconds"]
+    plain = n * args.steps / ref["seconds"]
+    dv = float(np.linalg.norm(lrn["V"] - ref["V"]) / np.linalg.norm(ref["V"]))
+    st = lrn["stats"]
+    launches = max(1, st["spmv_timed"])
+    spmv_avg = st["spmv_seconds"] / launches
+    bytes_avg = st["spmv_bytes"] / launches
+    achieved = bytes_avg / spmv_avg / 1e9
+    desc = (f"learned form: ellipsoidal shell {n} nodes (Kuhn-split curvilinear grid), ten "
+            f"Tusscher-Panfilov, dt 0.02 ms, rtol 1e-8 of ||D^-1 b||; per-node MLP warm start "
+            f"(BF16 MFMA, trained on the GPU) + mixed FP32/FP64 PCG vs plain FP64 PCG with the "
+            f"extrapolated warm start, held-out stimulus site, both from rest")
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF*steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * lrn["seconds"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64+bf16", "data": "synthetic",
+        "config": {"workload": desc, "n_nodes": n, "nnz": st["nnz"], "dt_ms": 0.02,
+                   "rtol": 1e-8, "plain_fp64_dof_steps_per_s": plain,
+                   "speedup_vs_plain_fp64": value / plain,
+                   "mean_cg_iters_learned_mixed": float(lrn["iters"].mean()),
+                   "mean_cg_iters_plain_fp64": float(ref["iters"].mean()),
+                   "fallbacks": int(st["fallbacks"]),
+                   "final_V_rel_l2_learned_vs_plain": dv,
+                   "train_sites": args.train_sites, "train_steps": args.train_steps},
+        "roofline": {"bound": "hbm", "kernel": "k_spmv32_dot", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": bytes_avg,
+                     "avg_launch_us": 1e6 * spmv_avg, "launches_timed": st["spmv_timed"],
+                     "sampled_every_n_steps": args.profile_every,
+                     "cache_resident": bool(8 * st["nnz"] < 256e6)},
+    }
+    if not args.no_cpu:
+        print(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps", flush=True)
+        out["cpu_baseline"] = cpu_baseline(spec(101, args.cpu_steps), args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
 def batched_workload(args):
     """The batched form: 64 unstructured ellipsoidal shells (about 12M
     nodes), Mitchell-Schaeffer, mixed precision, one block-diagonal solve per
@@ -87,6 +183,9 @@ def batched_workload(args):
     rep = s.autotune(reps=10)
     print(f"[bench] autotune: {rep['fmt']}, {rep['lanes_per_row']} lanes/row, "
           f"{rep['tiles_per_group']} tiles/group, {rep['seconds'] * 1e6:.1f} us", flush=True)
+    for c in rep["candidates"]:
+        print(f"[bench]   candidate {c[0]:4s} lanes/row {c[1]:2d} tiles/group {c[2]}: "
+              f"{c[3] * 1e6:8.1f} us, {rep['bytes'] / c[3] / 1e9:7.1f} GB/s", flush=True)
     if args.warmup:
         s.set_tuning(graph=True)
         s.run(args.warmup)
@@ -122,7 +221,9 @@ def batched_workload(args):
                    "spmv_format": rep["fmt"], "lanes_per_row": rep["lanes_per_row"],
                    "tiles_per_group": rep["tiles_per_group"], "graph": not args.no_graph,
                    "mean_cg_iters": float(its.mean()), "max_cg_iters": int(its.max())},
-        "roofline": {"bound": "hbm", "kernel": "k_b_spmv" if rep["fmt"] == "sell" else "k_b_spmv_csr",
+        "roofline": {"bound": "hbm",
+                     "kernel": {"sell": "k_b_spmv", "csr": "k_b_spmv_csr",
+                                "sell4": "k_b_spmv_v4"}[rep["fmt"]],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": bytes_avg, "avg_launch_us": 1e6 * spmv_avg,
@@ -158,6 +259,8 @@ def main():
     ap.add_argument("--instances", type=int, default=64, help="batched workload")
     ap.add_argument("--total-nodes", type=int, default=12_000_000, help="batched workload")
     ap.add_argument("--no-graph", action="store_true", help="batched workload")
+    ap.add_argument("--train-sites", type=int, default=4, help="learned workload")
+    ap.add_argument("--train-steps", type=int, default=1500, help="learned workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method runs one simulation per GPU and "
@@ -165,6 +268,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return batched_workload(args)
+    if args.workload == "learned":
+        return learned_workload(args)
 
     import torch
     from paper_2510_12011_amd import sim

@@ -199,8 +199,10 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
  *                        direction is formed per gathered column inside
  *                        the SpMV);
  *   MDX_TUNE_FORMAT      batched context: storage the iteration's FP32 SpMV
- *                        reads, 0 sliced ELL (default; 1 lane per row) or
- *                        1 CSR (no padding; 8 lanes per row);
+ *                        reads, 0 sliced ELL (default; 1 lane per row),
+ *                        1 CSR (no padding; 8 lanes per row) or 2 sliced
+ *                        ELL with 4 consecutive entries per lane and
+ *                        16-byte loads (1 lane per row);
  *   MDX_TUNE_LANES_PER_ROW   batched context: lanes of a wavefront per row in
  *                        that SpMV: 1, 2 or 4 for sliced ELL (64, 32 or 16
  *                        rows per wavefront), 4, 8 or 16 for CSR;
@@ -262,8 +264,9 @@ typedef struct {
 } mdx_tune_report;
 /* Autotuner of a prepared batched context: times reps launches (1..1000) of
  * the iteration's FP32 SpMV on the context's own matrix for sliced ELL with
- * 1, 2, 4 lanes per row (64, 32, 16 rows per wavefront) and CSR with 4, 8,
- * 16 lanes per row (16, 8, 4 rows per wavefront), each with 1, 2, 4, 8 tiles
+ * 1, 2, 4 lanes per row (64, 32, 16 rows per wavefront), sliced ELL with
+ * 4-entry vector loads, and CSR with 4, 8, 16 lanes per row (16, 8, 4 rows
+ * per wavefront), each with 1, 2, 4, 8 tiles
  * per workgroup, and installs the fastest (as the MDX_TUNE_FORMAT,
  * MDX_TUNE_LANES_PER_ROW and MDX_TUNE_TILES_PER_GROUP keys would).  Results
  * of later steps change only by the FP32 summation order of the SpMV.

@@ -114,11 +114,12 @@ struct mdx_ctx {
     std::vector<int64_t> inst_row0;       // internal rows, n_inst + 1 (last: npad)
     std::vector<int64_t> inst_nnz;
     std::vector<int32_t> tile_real;       // real rows of each tile
-    int64_t nslots_lpr[3] = {0, 0, 0};    // slots of the lanes-per-row layouts 1, 2, 4
+    int64_t nslots_lpr[4] = {0, 0, 0, 0}; // slots of the layouts lpr 1, 2, 4 and 4-entry chunks
     int fmt = 0;                          // iteration SpMV format: 0 sliced ELL, 1 CSR
     bool csr_built = false;
     int lpr = 1;                          // lanes per row of the iteration SpMV
-    int lpr_built = 0;                    // layout held in sptr_t / col_t / A32_t (0: none)
+    int lpr_built = 0;                    // layout in sptr_t / col_t / A32_t: 2, 4 (lanes
+                                          // per row), 5 (4-entry chunks), 0 none
     int tpb_b = 1;                        // tiles per workgroup
     SegTiling seg{};
     BScalars *bsc_host = nullptr;         // pinned, n_inst
@@ -349,7 +350,8 @@ void compute_layout(mdx_ctx *c)
         L.grp = take(sizeof(int4) * (n_tiles + ni));
         L.inst_grp = take(sizeof(int32_t) * (ni + 1));
         L.bsc = take(sizeof(BScalars) * ni);
-        const size_t alt = c->batched ? (size_t)std::max(c->nslots_lpr[1], c->nslots_lpr[2]) : 1;
+        const size_t alt =
+            c->batched ? (size_t)std::max({c->nslots_lpr[1], c->nslots_lpr[2], c->nslots_lpr[3]}) : 1;
         L.sptr_t = take(sizeof(int64_t) * (c->batched ? np / (SLICE / 4) + 1 : 1));
         L.col_t = take(sizeof(int32_t) * alt);
         L.A32_t = take(sizeof(float) * alt);
@@ -523,6 +525,37 @@ mdx_status build_lpr_layout(mdx_ctx *c, int lpr)
     return MDX_OK;
 }
 
+// slice pointers of the 4-entry-chunk layout: widths rounded up to 4
+std::vector<int64_t> v4_slices(const mdx_ctx *c)
+{
+    const int64_t ns = c->npad / SLICE;
+    std::vector<int64_t> sp(ns + 1, 0);
+    for (int64_t sl = 0; sl < ns; ++sl) {
+        const int64_t w = (c->slice_ptr[sl + 1] - c->slice_ptr[sl]) / SLICE;
+        sp[sl + 1] = sp[sl] + (w + 3) / 4 * 4 * SLICE;
+    }
+    return sp;
+}
+
+mdx_status build_v4_layout(mdx_ctx *c)
+{
+    mdx_ctx *ctx = c;   // for HIPCHK
+    if (c->lpr_built == 5) return MDX_OK;
+    std::vector<int64_t> sp = v4_slices(c);
+    if (sp.back() != c->nslots_lpr[3])
+        return fail(c, MDX_ERR_STATE, "internal layout inconsistent (4-entry chunks)");
+    HIPCHK(hipMemcpyAsync(c->dev<int64_t>(c->L.sptr_t), sp.data(), sizeof(int64_t) * sp.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    SellView base{c->dev<int64_t>(c->L.slice_ptr), c->dev<int32_t>(c->L.col)};
+    launch_relayout_v4(c->stream, (int64_t)sp.size() - 1, c->dev<int64_t>(c->L.sptr_t), base,
+                       c->dev<float>(c->L.A32), c->dev<int32_t>(c->L.col_t),
+                       c->dev<float>(c->L.A32_t));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->lpr_built = 5;
+    return MDX_OK;
+}
+
 // CSR copy of the FP32 iteration matrix (real entries only)
 mdx_status build_csr(mdx_ctx *c)
 {
@@ -550,10 +583,14 @@ mdx_status set_iter_layout(mdx_ctx *c, int fmt, int lpr)
         return fail(c, MDX_ERR_INVALID_ARG, "sliced ELL takes 1, 2 or 4 lanes per row");
     if (fmt == 1 && lpr != 4 && lpr != 8 && lpr != 16)
         return fail(c, MDX_ERR_INVALID_ARG, "CSR takes 4, 8 or 16 lanes per row");
+    if (fmt == 2 && lpr != 1)
+        return fail(c, MDX_ERR_INVALID_ARG, "4-entry-chunk layout takes 1 lane per row");
     if (fmt == 0) {
         if (mdx_status e = build_lpr_layout(c, lpr)) return e;
-    } else {
+    } else if (fmt == 1) {
         if (mdx_status e = build_csr(c)) return e;
+    } else {
+        if (mdx_status e = build_v4_layout(c)) return e;
     }
     c->fmt = fmt;
     c->lpr = lpr;
@@ -571,7 +608,7 @@ IterMatrix iter_matrix(const mdx_ctx *c)
         A.rptr = c->dev<int32_t>(L.csr_ptr);
         A.col = c->dev<int32_t>(L.csr_col);
         A.val = c->dev<float>(L.csr_val);
-    } else if (c->lpr == 1) {
+    } else if (c->lpr == 1 && c->fmt == 0) {
         A.sptr = c->dev<int64_t>(L.slice_ptr);
         A.col = c->dev<int32_t>(L.col);
         A.val = c->dev<float>(L.A32);
@@ -670,6 +707,18 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
     }
     order.clear();
     order.shrink_to_fit();
+    if (batched) {
+        // irregular meshes: rows sorted by length (longest first) inside each
+        // 256-row tile, so the 64-row slices hold rows of similar length and
+        // the sliced layout pads little; padding rows stay at the tile's end
+        auto deg = [&](int32_t o) { return gptr[o + 1] - gptr[o]; };
+        for (int64_t t0 = 0; t0 < npad; t0 += TILE) {
+            int64_t t1 = t0;
+            while (t1 < t0 + TILE && perm[t1] >= 0) ++t1;
+            std::stable_sort(perm.begin() + t0, perm.begin() + t1,
+                             [&](int32_t a, int32_t b) { return deg(a) > deg(b); });
+        }
+    }
     for (int64_t r = 0; r < npad; ++r)
         if (perm[r] >= 0) iperm[perm[r]] = (int32_t)r;
     std::vector<int32_t> tile_real(npad / TILE, 0);
@@ -712,8 +761,10 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
             colv[base + j * SLICE] = j < (int64_t)cols.size() ? cols[j] : (int32_t)r;
     }
     // slot counts of the 2- and 4-lanes-per-row layouts (autotuner candidates)
-    int64_t nsl[3] = {sptr[nslices], 0, 0};
-    if (batched)
+    int64_t nsl[4] = {sptr[nslices], 0, 0, 0};
+    if (batched) {
+        for (int64_t sl = 0; sl < nslices; ++sl)
+            nsl[3] += ((sptr[sl + 1] - sptr[sl]) / SLICE + 3) / 4 * 4 * SLICE;
         for (int li = 1; li < 3; ++li) {
             const int lpr = 1 << li, H = SLICE / lpr;
             int64_t tot = 0;
@@ -724,6 +775,7 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
             }
             nsl[li] = tot;
         }
+    }
 
     ctx->n = n_nodes;
     ctx->m = n_tets;
@@ -749,7 +801,7 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
     ctx->inst_row0.swap(row0);
     ctx->inst_nnz.swap(inst_nnz);
     ctx->tile_real.swap(tile_real);
-    for (int li = 0; li < 3; ++li) ctx->nslots_lpr[li] = nsl[li];
+    for (int li = 0; li < 4; ++li) ctx->nslots_lpr[li] = nsl[li];
     ctx->fmt = 0;
     ctx->lpr = 1;
     ctx->lpr_built = 0;
@@ -1662,7 +1714,7 @@ mdx_status mdx_autotune(mdx_ctx *ctx, int32_t reps, mdx_tune_report *rep)
     mdx_tune_report r{};
     double best = std::numeric_limits<double>::infinity();
     int best_fmt = 0, best_lpr = 1, best_tpb = ctx->tpb_b;
-    const int layouts[6][2] = {{0, 1}, {0, 2}, {0, 4}, {1, 4}, {1, 8}, {1, 16}};
+    const int layouts[7][2] = {{0, 1}, {0, 2}, {0, 4}, {2, 1}, {1, 4}, {1, 8}, {1, 16}};
     const int tpbs[4] = {1, 2, 4, 8};
     mdx_status st_ = MDX_OK;
     for (const auto &lay : layouts) {
@@ -1758,7 +1810,7 @@ mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value)
         ctx->iter_scheme = (int)value;
         return MDX_OK;
     case MDX_TUNE_FORMAT:
-        if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "format is 0 or 1");
+        if (value < 0 || value > 2) return fail(ctx, MDX_ERR_INVALID_ARG, "format is 0, 1 or 2");
         if (!ctx->batched || !ctx->prepared)
             return fail(ctx, MDX_ERR_STATE, "needs a prepared batched context");
         GUARD_BEGIN

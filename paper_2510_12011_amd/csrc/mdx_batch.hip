@@ -20,8 +20,10 @@
 // host stops when every instance is done.
 //
 // The iteration's SpMV takes the matrix in the layout chosen by the
-// autotuner: lpr lanes per row (64/lpr rows per wavefront), the lanes of a
-// row summed by a butterfly over adjacent lanes.
+// autotuner: sliced ELL with lpr lanes per row (64/lpr rows per wavefront,
+// the lanes of a row summed by a butterfly over adjacent lanes), sliced ELL
+// read with 16-byte vector loads (4 entries per lane and load), or CSR with
+// 4-16 lanes per row.
 #include "mdx_device.h"
 #include "mdx_internal.h"
 
@@ -78,6 +80,39 @@ __global__ __launch_bounds__(256) void k_relayout(int lpr, int64_t n_slices,
             A32_new[e] = 0.0f;
         }
     }
+}
+
+// base layout -> 64-row slices whose lanes hold 4 consecutive entries of
+// their row per 256-slot step (entry k of the row in slice position l at
+// sptr_new[slice] + 256 (k / 4) + 4 l + k % 4), for 16-byte vector loads
+__global__ __launch_bounds__(256) void k_relayout_v4(int64_t n_slices,
+                                                     const int64_t *__restrict__ sptr_new,
+                                                     const int64_t *__restrict__ sptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const float *__restrict__ A32,
+                                                     int32_t *__restrict__ col_new,
+                                                     float *__restrict__ A32_new)
+{
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sl = tid / SLICE;
+    if (sl >= n_slices) return;
+    const int lane = (int)(tid % SLICE);
+    const int64_t row = sl * SLICE + lane;
+    const int64_t bbase = sptr[sl] + lane;
+    const int64_t bw = (sptr[sl + 1] - sptr[sl]) / SLICE;
+    const int64_t w4 = (sptr_new[sl + 1] - sptr_new[sl]) / (4 * SLICE);
+    for (int64_t c = 0; c < w4; ++c)
+        for (int i = 0; i < 4; ++i) {
+            const int64_t k = 4 * c + i;
+            const int64_t e = sptr_new[sl] + c * 4 * SLICE + 4 * lane + i;
+            if (k < bw) {
+                col_new[e] = col[bbase + k * SLICE];
+                A32_new[e] = A32[bbase + k * SLICE];
+            } else {
+                col_new[e] = (int32_t)row;
+                A32_new[e] = 0.0f;
+            }
+        }
 }
 
 __global__ __launch_bounds__(256) void k_build_csr(int64_t n_rows, const int64_t *__restrict__ sptr,
@@ -221,6 +256,40 @@ __global__ __launch_bounds__(256) void k_b_spmv(SegTiling t, const int64_t *__re
                 acc[0] += (double)p[row] * (double)sum;
             }
         }
+    }
+    write_partials<1>(acc, partial, t.groups, g);
+}
+
+// q = A p, vector-load sliced layout: one lane per row, 4 entries per load
+__global__ __launch_bounds__(256) void k_b_spmv_v4(SegTiling t, const int64_t *__restrict__ sptr,
+                                                   const int32_t *__restrict__ col,
+                                                   const float *__restrict__ A,
+                                                   const float *__restrict__ p,
+                                                   float *__restrict__ q,
+                                                   double *__restrict__ partial,
+                                                   const BScalars *__restrict__ sc)
+{
+    const int g = logical_group(t.groups);
+    const int4 gr = t.grp[g];
+    if (idle(sc[gr.x])) return;
+    const int lane = threadIdx.x & (SLICE - 1);
+    double acc[1] = {0.0};
+    for (int tile = gr.y; tile < gr.z; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        const int64_t beg = sptr[sl] + 4 * lane, end = sptr[sl + 1];
+        float sum = 0.0f;
+#pragma unroll 2
+        for (int64_t e = beg; e < end; e += 4 * SLICE) {
+            const int4 c = *reinterpret_cast<const int4 *>(col + e);
+            const float4 a = *reinterpret_cast<const float4 *>(A + e);
+            sum += a.x * p[c.x];
+            sum += a.y * p[c.y];
+            sum += a.z * p[c.z];
+            sum += a.w * p[c.w];
+        }
+        q[row] = sum;
+        acc[0] += (double)p[row] * (double)sum;
     }
     write_partials<1>(acc, partial, t.groups, g);
 }
@@ -493,6 +562,15 @@ void launch_b_set_direction(hipStream_t s, const SegTiling &t, const float *dinv
     hipLaunchKernelGGL(k_b_set_direction, dim3(t.groups), dim3(TILE), 0, s, t, dinv32, r32, p32, sc);
 }
 
+void launch_relayout_v4(hipStream_t s, int64_t n_slices, const int64_t *sptr_new, SellView base,
+                        const float *A32, int32_t *col_new, float *A32_new)
+{
+    const int64_t threads = n_slices * SLICE;
+    if (threads > 0)
+        hipLaunchKernelGGL(k_relayout_v4, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                           n_slices, sptr_new, base.slice_ptr, base.col, A32, col_new, A32_new);
+}
+
 void launch_build_csr(hipStream_t s, int64_t n_rows, SellView base, const float *A32,
                       const int32_t *rptr, int32_t *col_csr, float *val_csr)
 {
@@ -504,7 +582,9 @@ void launch_build_csr(hipStream_t s, int64_t n_rows, SellView base, const float 
 void launch_b_spmv(hipStream_t s, const SegTiling &t, const IterMatrix &A, const float *p32,
                    float *q32, double *part_pq, const BScalars *sc, hipEvent_t e0, hipEvent_t e1)
 {
-    if (A.format == 1) {
+    if (A.format == 2) {
+        spmv_launch(k_b_spmv_v4, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
+    } else if (A.format == 1) {
         if (A.lpr == 16)
             spmv_launch(k_b_spmv_csr<16>, s, t, A.rptr, A, p32, q32, part_pq, sc, e0, e1);
         else if (A.lpr == 8)

@@ -215,9 +215,10 @@ void launch_relayout(hipStream_t s, int lpr, int64_t n_slices, const int64_t *sp
                      SellView base, const float *A32, int32_t *col_new, float *A32_new);
 
 // The iteration matrix as the SpMV reads it: sliced ELL (format 0, lpr in
-// {1, 2, 4}, slice pointers sptr) or CSR (format 1, lpr in {4, 8, 16} lanes
-// reading each row's contiguous entries, row pointers rptr), both in the
-// internal row order with the FP32 values.
+// {1, 2, 4}, slice pointers sptr), CSR (format 1, lpr in {4, 8, 16} lanes
+// reading each row's contiguous entries, row pointers rptr) or sliced ELL
+// with 4-entry lane chunks (format 2, lpr 1), all in the internal row order
+// with the FP32 values.
 struct IterMatrix {
     int format;
     int lpr;
@@ -226,6 +227,10 @@ struct IterMatrix {
     const int32_t *col;
     const float *val;
 };
+// format 2: sliced ELL whose lanes load 4 consecutive entries of their row
+// (entry k of slice position l at sptr[slice] + 256 (k / 4) + 4 l + k % 4)
+void launch_relayout_v4(hipStream_t s, int64_t n_slices, const int64_t *sptr_new, SellView base,
+                        const float *A32, int32_t *col_new, float *A32_new);
 // CSR copy of the FP32 iteration matrix from the base sliced layout (rptr:
 // row pointers of the real entries, already on the device)
 void launch_build_csr(hipStream_t s, int64_t n_rows, SellView base, const float *A32,

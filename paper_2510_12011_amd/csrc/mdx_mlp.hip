@@ -157,24 +157,132 @@ __device__ __forceinline__ void forward_tile(const MlpLds &w, float4 x, Tile &T,
     T.y = s + w.b4;
 }
 
+// ---------------------------------------------------------------------------
+// Inference (the warm start of every time step).  Same function as
+// forward_tile with every layer on the MFMA:
+//   layer 1: K = 8 (the 4 features and 4 zero rows); the FP32 features enter
+//            as a BF16 pair hi + lo (x = hi + lo to about 2^-17 relative), so
+//            two MFMAs reproduce BF16(W1) x in FP32;
+//   biases:  FP32, loaded as the accumulators' initial values;
+//   BF16 rounding of the activations by the hardware conversion
+//   (round to nearest even, as f2bf).
+// No pre-activations are kept, so several wavefronts share a SIMD.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x2n __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned pack_bf16(float a, float b)
+{
+    f32x2 v = {a, b};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2n));
+}
+__device__ __forceinline__ bf16x4 pack_bf16x4(float a, float b, float c, float d)
+{
+    u32x2 u = {pack_bf16(a, b), pack_bf16(c, d)};
+    return __builtin_bit_cast(bf16x4, u);
+}
+
+struct alignas(16) InferLds {
+    float b1[NH], b2[NH], b3[NH], w4[NH];   // FP32 biases, BF16-rounded w4
+    unsigned short w1[NH * 8];              // BF16 W1, columns 4..7 zero
+    unsigned short w2[NH * WSTRIDE];
+    unsigned short w3[NH * WSTRIDE];
+    float b4;
+};
+
+// bias (or w4) values of the units held by this lane in output tile ot, in
+// accumulator order: v = 4 g + j -> unit 32 ot + 8 g + 4 half + j
+__device__ __forceinline__ f32x16 unit_frag(const float *v, int ot, int half)
+{
+    f32x16 r;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float4 q = *reinterpret_cast<const float4 *>(v + 32 * ot + 8 * g + 4 * half);
+        r[4 * g + 0] = q.x;
+        r[4 * g + 1] = q.y;
+        r[4 * g + 2] = q.z;
+        r[4 * g + 3] = q.w;
+    }
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P, int64_t n,
                                                      const float *__restrict__ X,
                                                      float *__restrict__ y)
 {
-    __shared__ MlpLds w;
-    load_weights(P, w);
+    __shared__ InferLds w;
+    for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {
+        const int o = i / NH, k = i % NH;
+        w.w2[o * WSTRIDE + k] = f2bf(P[OFF_W2 + i]);
+        w.w3[o * WSTRIDE + k] = f2bf(P[OFF_W3 + i]);
+    }
+    for (int i = threadIdx.x; i < NH * 8; i += blockDim.x) {
+        const int o = i / 8, k = i % 8;
+        w.w1[i] = k < 4 ? f2bf(P[OFF_W1 + 4 * o + k]) : (unsigned short)0;
+    }
+    for (int i = threadIdx.x; i < NH; i += blockDim.x) {
+        w.b1[i] = P[OFF_B1 + i];
+        w.b2[i] = P[OFF_B2 + i];
+        w.b3[i] = P[OFF_B3 + i];
+        w.w4[i] = round_bf(P[OFF_W4 + i]);
+    }
+    if (threadIdx.x == 0) w.b4 = P[OFF_B4];
     __syncthreads();
-    const int lane = threadIdx.x & 63;
+
+    const int lane = threadIdx.x & 63, half = lane >> 5;
     const int64_t n_tiles = (n + 31) / 32;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
-    Tile T;
     for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; tile < n_tiles;
          tile += waves) {
         const int64_t node = tile * 32 + (lane & 31);
         float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (node < n) x = reinterpret_cast<const float4 *>(X)[node];
-        forward_tile(w, x, T, false);
-        if (lane < 32 && node < n) y[node] = T.y;
+        if (half == 0 && node < n) x = reinterpret_cast<const float4 *>(X)[node];
+        const bf16x4 xh = pack_bf16x4(x.x, x.y, x.z, x.w);
+        const float4 xr = make_float4(x.x - bf2f((unsigned short)xh[0]),
+                                      x.y - bf2f((unsigned short)xh[1]),
+                                      x.z - bf2f((unsigned short)xh[2]),
+                                      x.w - bf2f((unsigned short)xh[3]));
+        const bf16x4 xl = pack_bf16x4(xr.x, xr.y, xr.z, xr.w);
+        // layer 1
+        bf16x4 h1[8];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot) {
+            const bf16x4 a =
+                *reinterpret_cast<const bf16x4 *>(w.w1 + (32 * ot + (lane & 31)) * 8 + 4 * half);
+            f32x16 acc = unit_frag(w.b1, ot, half);
+            acc = mfma(a, xh, acc);
+            acc = mfma(a, xl, acc);
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                h1[4 * ot + g] = pack_bf16x4(fmaxf(acc[4 * g], 0.f), fmaxf(acc[4 * g + 1], 0.f),
+                                             fmaxf(acc[4 * g + 2], 0.f), fmaxf(acc[4 * g + 3], 0.f));
+        }
+        // layer 2
+        bf16x4 h2[8];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot) {
+            f32x16 acc = unit_frag(w.b2, ot, half);
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) acc = mfma(frag_w(w.w2, ot, ks, lane), h1[ks], acc);
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                h2[4 * ot + g] = pack_bf16x4(fmaxf(acc[4 * g], 0.f), fmaxf(acc[4 * g + 1], 0.f),
+                                             fmaxf(acc[4 * g + 2], 0.f), fmaxf(acc[4 * g + 3], 0.f));
+        }
+        // layer 3 and the output unit
+        float s = 0.0f;
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot) {
+            f32x16 acc = unit_frag(w.b3, ot, half);
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) acc = mfma(frag_w(w.w3, ot, ks, lane), h2[ks], acc);
+            const f32x16 w4 = unit_frag(w.w4, ot, half);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) s += w4[v] * fmaxf(acc[v], 0.0f);
+        }
+        s += __shfl_xor(s, 32, 64);
+        if (half == 0 && node < n) y[node] = s + w.b4;
     }
 }
 
@@ -406,7 +514,7 @@ void launch_mlp_forward(hipStream_t s, const float *P, int64_t n, const float *X
 {
     if (n <= 0) return;
     const int64_t tiles = (n + 31) / 32;
-    const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 2048);
+    const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 1024);
     hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, s, P, n, X, y);
 }
 

@@ -164,9 +164,9 @@ class Simulation:
 
     def set_tuning(self, max_groups=None, iter_scheme=None, lanes_per_row=None,
                    tiles_per_group=None, graph=None, fmt=None):
-        """fmt: 'sell' or 'csr' (batched iteration SpMV storage), set before
-        lanes_per_row."""
-        f = None if fmt is None else {"sell": 0, "csr": 1}[fmt]
+        """fmt: 'sell', 'csr' or 'sell4' (batched iteration SpMV storage),
+        set before lanes_per_row."""
+        f = None if fmt is None else {"sell": 0, "csr": 1, "sell4": 2}[fmt]
         for key, v in ((L.MDX_TUNE_MAX_GROUPS, max_groups), (L.MDX_TUNE_ITER_SCHEME, iter_scheme),
                        (L.MDX_TUNE_FORMAT, f),
                        (L.MDX_TUNE_LANES_PER_ROW, lanes_per_row),
@@ -186,7 +186,7 @@ class Simulation:
         """Batched context: time the SpMV variants, install the fastest."""
         r = L.TuneReport()
         self._check(L.lib().mdx_autotune(self._h, int(reps), C.byref(r)))
-        fmts = ("sell", "csr")
+        fmts = ("sell", "csr", "sell4")
         cands = [(fmts[r.cand_format[i]], r.cand_lanes_per_row[i], r.cand_tiles_per_group[i],
                   r.cand_seconds[i]) for i in range(r.n_candidates)]
         return dict(fmt=fmts[r.format], lanes_per_row=r.lanes_per_row,

@@ -176,15 +176,16 @@ def test_batch_layout_is_block_diagonal(host_ctx):
     lib = L.lib()
     a, b, xyz, tets, fib, ptr = _two_boxes()
     n, ne = xyz.shape[0], tets.shape[0]
-    assert lib.mdx_set_mesh(host_ctx, a.n_nodes, _p(np.ascontiguousarray(a.xyz)), 1.0, a.n_tets,
-                            _p(np.ascontiguousarray(a.tets)), None, None) == L.MDX_OK
-    sa = L.Stats()
-    lib.mdx_get_stats(host_ctx, C.byref(sa))
-    bx, bt = np.ascontiguousarray(b.xyz), np.ascontiguousarray(b.tets)
-    assert lib.mdx_set_mesh(host_ctx, b.n_nodes, _p(bx), 1.0, b.n_tets, _p(bt), None,
-                            None) == L.MDX_OK
-    sb = L.Stats()
-    lib.mdx_get_stats(host_ctx, C.byref(sb))
+    # each instance alone, as a batch of one (same ordering rules)
+    stats = []
+    for m in (a, b):
+        one = np.array([0, m.n_nodes], np.int64)
+        mx, mt = np.ascontiguousarray(m.xyz), np.ascontiguousarray(m.tets)
+        assert lib.mdx_set_mesh_batch(host_ctx, 1, _p(one), m.n_nodes, _p(mx), 1.0, m.n_tets,
+                                      _p(mt), None, None) == L.MDX_OK
+        stats.append(L.Stats())
+        lib.mdx_get_stats(host_ctx, C.byref(stats[-1]))
+    sa, sb = stats
     assert lib.mdx_set_mesh_batch(host_ctx, 2, _p(ptr), n, _p(xyz), 1.0, ne, _p(tets), None,
                                   _p(fib)) == L.MDX_OK
     st = L.Stats()

@@ -108,8 +108,8 @@ def test_graph_replay_matches_eager(bspec, batch_run):
         assert np.array_equal(a, b), np.abs(a - b).max()
 
 
-@pytest.mark.parametrize("fmt,lpr", [("sell", 2), ("sell", 4), ("csr", 4), ("csr", 8),
-                                     ("csr", 16)])
+@pytest.mark.parametrize("fmt,lpr", [("sell", 2), ("sell", 4), ("sell4", 1), ("csr", 4),
+                                     ("csr", 8), ("csr", 16)])
 def test_lanes_per_row_layouts(bspec, batch_run, fmt, lpr):
     from paper_2510_12011_amd import sim
     print(f"[case] {fmt}, lanes per row {lpr}", flush=True)
