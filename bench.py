@@ -1,12 +1,17 @@
 """Benchmark of the monodomain hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload slab]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload learned]
 
 A step is one time step of the whole hot path (ionic update, fused RHS and
-initial residual, Jacobi-PCG to tolerance, activation times) on the
-workload's synthetic mesh.  W untimed steps run first, the state is reset to
-rest, then exactly K steps are timed between device synchronisations.  The
+initial residual, warm start, Jacobi-PCG to tolerance, activation times) on
+the workload's synthetic mesh.  W untimed steps run first, the state is reset
+to rest, then exactly K steps are timed between device synchronisations.  The
 value is DOF*steps/s = n_nodes * K / seconds.
+
+Workloads: learned (default: the learned warm start + mixed precision
+against plain FP64 PCG on a 1.2M-node shell at equal accuracy), slab (plain
+FP64, 442,401 nodes), precision / precision_fp64 (3.45M-node slab), batched
+(64 shells, 12M nodes), tiny.
 
 Also reported, as one JSON line:
   roofline      the dominant kernel (PCG SpMV with fused p.q): algorithmic
@@ -68,13 +73,19 @@ def cpu_baseline(spec, steps, threads=None):
 
 
 def learned_workload(args):
-    """The learned form: one ~1.2M-node ellipsoidal shell, ten Tusscher-Panfilov,
-    dt 0.02 ms, rtol 1e-8 of ||D^-1 b||.  The network is trained on the GPU
-    (library kernels) on trajectories of the plain solver from random
-    endocardial sites; then a held-out site is run twice from rest for the
-    same K steps: learned warm start + mixed precision (the value) and the
-    plain FP64 PCG with the paper's extrapolated warm start (the comparison),
-    both to the same tolerance."""
+    """The learned form (the headline): one ~1.2M-node ellipsoidal shell, ten
+    Tusscher-Panfilov, dt 0.02 ms, stopping on ||D^-1 r|| relative to
+    ||D^-1 b||.  The network is trained on the GPU (library kernels) on
+    trajectories of the plain solver from random endocardial sites.  A
+    held-out site is then run from rest for the same K steps by
+      * learned warm start + mixed precision,
+      * plain FP64 PCG with the paper's extrapolated warm start,
+      * plain FP64 PCG with the previous-step warm start (the judge of the
+        network's iteration savings),
+    at the workload's tolerance 1e-8, and by the first two again at 3e-9,
+    where both meet the accuracy bar with margin ("equal accuracy").  The
+    accuracy of every run is measured against plain FP64 at 1e-12.  The value
+    is learned + mixed at equal accuracy."""
     import torch
     from paper_2510_12011_amd import _lib as L, inputs, learn, sim
     t0 = time.perf_counter()
@@ -84,11 +95,13 @@ def learned_workload(args):
     def spec(site, steps):
         return inputs.shell_run(mesh=mesh, ionic="tt", dt=0.02, n_steps=steps, site_seed=site)
 
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(0)
     Xs, Ds = [], []
     for site in range(1, args.train_sites + 1):
         s = sim.from_spec(spec(site, args.train_steps))
         X, dV = learn.record(s, args.train_steps, every=10, seed=site)
-        keep = torch.randperm(X.shape[0], device=X.device)[:2_000_000]
+        keep = torch.randperm(X.shape[0], device=X.device, generator=g)[:2_000_000]
         Xs.append(X[keep])
         Ds.append(dV[keep])
         trainer = s
@@ -99,17 +112,19 @@ def learned_workload(args):
           f"steps, loss {hist[0]:.4f} -> {hist[-1]:.4f}, setup {time.perf_counter() - t0:.1f} s",
           flush=True)
 
-    def timed(precision, ws, mlp):
+    def timed(precision, ws, rtol, profile=False):
         s = sim.from_spec(spec(101, args.steps), precision=precision)
+        mlp = ws == L.MDX_WS_MLP
         if mlp:
             learn.install(s, params, norm)
-        s.set_solver(0.0, 1e-8, 1, 1000, ws, sim.PRECISION[precision], 50)
+        s.set_solver(0.0, rtol, 1, 1000, ws, sim.PRECISION[precision], 50)
         if args.warmup:
             s.run(args.warmup)
             s.prepare(s.dt)
             if mlp:
                 learn.install(s, params, norm)
-        s.set_profiling(args.profile_every)
+        if profile:
+            s.set_profiling(args.profile_every)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, status = s.run(args.steps)
@@ -117,38 +132,56 @@ def learned_workload(args):
         el = time.perf_counter() - t1
         it = s.iterations(args.steps)
         st = s.stats()
-        V = s.get_state()["V"]
-        print(f"[bench] {precision} warm start {'MLP' if mlp else 'extrapolated'}: "
-              f"{args.steps} steps in {el:.3f} s, mean CG iterations {it.mean():.2f}, "
-              f"fallbacks {st['fallbacks']}, status {status}", flush=True)
-        return dict(seconds=el, iters=it, stats=st, V=V)
+        state = s.get_state()
+        name = {L.MDX_WS_MLP: "MLP", L.MDX_WS_EXTRAP: "extrapolated", L.MDX_WS_PREV: "previous"}[ws]
+        print(f"[bench] {precision} warm start {name}, rtol {rtol:g}: {args.steps} steps in "
+              f"{el:.3f} s, mean CG iterations {it.mean():.2f}, fallbacks {st['fallbacks']}, "
+              f"status {status}", flush=True)
+        return dict(seconds=el, iters=float(it.mean()), stats=st, V=state["V"], lat=state["lat"],
+                    rate=n * args.steps / el)
 
-    lrn = timed("mixed", L.MDX_WS_MLP, True)
-    ref = timed("fp64", L.MDX_WS_EXTRAP, False)
-    value = n * args.steps / lrn["seconds"]
-    plain = n * args.steps / ref["seconds"]
-    dv = float(np.linalg.norm(lrn["V"] - ref["V"]) / np.linalg.norm(ref["V"]))
+    eq = 3e-9
+    runs = {
+        "learned_mixed_1e-8": timed("mixed", L.MDX_WS_MLP, 1e-8),
+        "plain_fp64_1e-8": timed("fp64", L.MDX_WS_EXTRAP, 1e-8),
+        "plain_fp64_prev_1e-8": timed("fp64", L.MDX_WS_PREV, 1e-8),
+        "learned_mixed_3e-9": timed("mixed", L.MDX_WS_MLP, eq, profile=True),
+        "plain_fp64_3e-9": timed("fp64", L.MDX_WS_EXTRAP, eq),
+    }
+    tight = timed("fp64", L.MDX_WS_EXTRAP, 1e-12)
+    summary = {}
+    for key, r in runs.items():
+        e = float(np.linalg.norm(r["V"] - tight["V"]) / np.linalg.norm(tight["V"]))
+        fa, fb = np.isfinite(r["lat"]), np.isfinite(tight["lat"])
+        both = fa & fb
+        lat = float(np.abs(r["lat"][both] - tight["lat"][both]).max()) if both.any() else 0.0
+        summary[key] = {"dof_steps_per_s": r["rate"], "mean_cg_iters": r["iters"],
+                        "V_rel_l2": e, "lat_max_diff_ms": lat,
+                        "lat_activation_mismatch": int((fa != fb).sum())}
+        print(f"[bench] {key}: {r['rate']:.3e} DOF*steps/s, V rel L2 {e:.2e}, LAT max diff "
+              f"{lat:g} ms", flush=True)
+    lrn = runs["learned_mixed_3e-9"]
+    value = lrn["rate"]
     st = lrn["stats"]
     launches = max(1, st["spmv_timed"])
     spmv_avg = st["spmv_seconds"] / launches
     bytes_avg = st["spmv_bytes"] / launches
     achieved = bytes_avg / spmv_avg / 1e9
     desc = (f"learned form: ellipsoidal shell {n} nodes (Kuhn-split curvilinear grid), ten "
-            f"Tusscher-Panfilov, dt 0.02 ms, rtol 1e-8 of ||D^-1 b||; per-node MLP warm start "
-            f"(BF16 MFMA, trained on the GPU) + mixed FP32/FP64 PCG vs plain FP64 PCG with the "
-            f"extrapolated warm start, held-out stimulus site, both from rest")
+            f"Tusscher-Panfilov, dt 0.02 ms; per-node MLP warm start (BF16 MFMA, trained on the "
+            f"GPU) + mixed FP32/FP64 PCG vs plain FP64 PCG (extrapolated warm start), both to "
+            f"rtol 3e-9 of ||D^-1 b|| (equal accuracy, measured against FP64 at 1e-12), "
+            f"held-out stimulus site, from rest")
     out = {
         "metric": METRIC, "value": value, "unit": "DOF*steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * lrn["seconds"] / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64+bf16", "data": "synthetic",
         "config": {"workload": desc, "n_nodes": n, "nnz": st["nnz"], "dt_ms": 0.02,
-                   "rtol": 1e-8, "plain_fp64_dof_steps_per_s": plain,
-                   "speedup_vs_plain_fp64": value / plain,
-                   "mean_cg_iters_learned_mixed": float(lrn["iters"].mean()),
-                   "mean_cg_iters_plain_fp64": float(ref["iters"].mean()),
-                   "fallbacks": int(st["fallbacks"]),
-                   "final_V_rel_l2_learned_vs_plain": dv,
+                   "rtol": eq, "plain_fp64_dof_steps_per_s": runs["plain_fp64_3e-9"]["rate"],
+                   "speedup_vs_plain_fp64": value / runs["plain_fp64_3e-9"]["rate"],
+                   "accuracy_reference": "plain FP64 PCG at rtol 1e-12, same steps",
+                   "runs": summary, "fallbacks": int(st["fallbacks"]),
                    "train_sites": args.train_sites, "train_steps": args.train_steps},
         "roofline": {"bound": "hbm", "kernel": "k_spmv32_dot", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -250,9 +283,14 @@ def batched_workload(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="slab")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: learned 3000, slab 10000, batched 1000, "
+                         "precision 2000, tiny 500)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before the timed region (default: 0 learned, 10 batched, "
+                         "100 otherwise)")
+    ap.add_argument("--workload", default="learned",
+                    choices=["learned", "slab", "precision", "precision_fp64", "batched", "tiny"])
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-every", type=int, default=10)
@@ -260,12 +298,17 @@ def main():
     ap.add_argument("--total-nodes", type=int, default=12_000_000, help="batched workload")
     ap.add_argument("--no-graph", action="store_true", help="batched workload")
     ap.add_argument("--train-sites", type=int, default=4, help="learned workload")
-    ap.add_argument("--train-steps", type=int, default=1500, help="learned workload")
+    ap.add_argument("--train-steps", type=int, default=2000, help="learned workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method runs one simulation per GPU and "
               "this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.steps is None:
+        args.steps = {"learned": 3000, "slab": 10000, "batched": 1000, "precision": 2000,
+                      "precision_fp64": 2000, "tiny": 500}[args.workload]
+    if args.warmup is None:
+        args.warmup = {"learned": 0, "batched": 10}.get(args.workload, 100)
     if args.workload == "batched":
         return batched_workload(args)
     if args.workload == "learned":

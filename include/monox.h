@@ -329,7 +329,9 @@ MDX_API mdx_status mdx_mlp_adam(mdx_ctx *ctx, float *params, float *m, float *v,
 /* Install the network for MDX_WS_MLP.  params: HOST FP32 [MDX_MLP_NPARAM];
  * norm: HOST [9] = feature means (4), feature standard deviations (4),
  * output scale.  Features of node i at step n: V^n, V^n - V^{n-1},
- * (I_stim - I_ion)/Cm (mV/ms), (K V^n)_i / K_ii; guess x0 = V^n + scale y.
+ * (I_stim - I_ion)/Cm (mV/ms), (K V^{n-1})_i / K_ii (the neighbour aggregate
+ * of the previous step's right-hand side); guess x0 = V^n + scale y,
+ * used when its initial residual ||D^-1 r0|| is below that of x0 = V^n.
  * Requires a prepared context; the network lives in the workspace. */
 MDX_API mdx_status mdx_set_mlp(mdx_ctx *ctx, const float *params, const double *norm);
 /* Training-data recorder: when non-NULL, every step of mdx_run writes the

@@ -50,7 +50,7 @@ struct Layout {
     size_t slice_ptr, col, Mv, Kv, Av, dinv, vec[3], r, p, p2, q, b, s, istim, u, lat, lrt, stim_idx,
         partial, scalars;
     size_t A32, dinv32, r32, p32, q32, delta, g32;   // mixed-precision form
-    size_t kdiag, feat, mlp_y, mlp_params;            // learned warm start
+    size_t kdiag, kvp, feat, mlp_y, mlp_params;       // learned warm start
     size_t tile_real, grp, inst_grp, bsc, sptr_t, col_t, A32_t;   // batched form
     size_t csr_ptr, csr_col, csr_val;
     size_t total;
@@ -101,6 +101,7 @@ struct mdx_ctx {
     bool mlp_set = false;
     MlpNorm mlp_norm{{0.f, 0.f, 0.f, 0.f}, {1.f, 1.f, 1.f, 1.f}, 0.f};
     float *rec_X = nullptr, *rec_dV = nullptr;   // training-data recorder
+    bool kvp_valid = false;   // kvp holds (K V^{n-1})_i / K_ii of the current state
 
     // launch-shape tuning
     int max_groups = kMaxGroups;
@@ -341,6 +342,7 @@ void compute_layout(mdx_ctx *c)
     L.delta = take(sizeof(float) * np);
     L.g32 = take(sizeof(float) * np * std::max(1, ionic_gate_rows(c->ionic_kind)));
     L.kdiag = take(sizeof(double) * np);
+    L.kvp = take(sizeof(float) * np);
     L.feat = take(sizeof(float) * 4 * np);
     L.mlp_y = take(sizeof(float) * np);
     L.mlp_params = take(sizeof(float) * mlp_nparams());
@@ -1381,6 +1383,8 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
         launch_fill(st, ctx->npad, 0.0, ctx->dev<double>(off));
     launch_fill(st, ctx->npad * 2, 0.0, ctx->dev<double>(L.feat));   // 4 floats per row
     launch_fill(st, ctx->npad / 2, 0.0, ctx->dev<double>(L.mlp_y));
+    launch_fill(st, ctx->npad / 2, 0.0, ctx->dev<double>(L.kvp));
+    ctx->kvp_valid = false;
     // FP32 vectors: zero bits (float zero) via the double fill over half the count
     for (size_t off : {L.r32, L.p32, L.q32, L.delta})
         launch_fill(st, ctx->npad / 2, 0.0, ctx->dev<double>(off));
@@ -1459,6 +1463,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         return fail(ctx, MDX_ERR_STATE, "warm start MDX_WS_MLP needs mdx_set_mlp first");
     double *kdiag = ctx->dev<double>(L.kdiag);
     float *feat = ctx->dev<float>(L.feat), *mlp_y = ctx->dev<float>(L.mlp_y);
+    float *kvp = ctx->dev<float>(L.kvp);
     const float *mlp_params = ctx->dev<float>(L.mlp_params);
     float *A32 = ctx->dev<float>(L.A32);
     float *dinv32 = ctx->dev<float>(L.dinv32), *r32 = ctx->dev<float>(L.r32);
@@ -1486,25 +1491,32 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                               ctx->dt, ctx->cm, V, u, istim, s, 0);
 
         // ---- right-hand side, warm start, initial residual ----
+        // the learned warm start and the recorder need the neighbour feature
+        // (K V^{n-1})_i / K_ii, kept up to date by the right-hand-side pass
+        const bool want_kvp = learned || ctx->rec_X;
+        if (want_kvp && !ctx->kvp_valid) launch_kv_feature(st, T, P, Kv, kdiag, Vprev, kvp);
         if (learned) {
-            launch_rhs_features(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm, ctx->n, V, Vprev,
-                                s, b, feat, ctx->rec_X, part0);
+            launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm, feat,
+                            ctx->rec_X);
             launch_mlp_forward(st, mlp_params, ctx->n, feat, mlp_y);   // padding rows keep y = 0
-            launch_two_residuals(st, T, P, Av, dinv, ctx->mlp_norm.out_scale, V, mlp_y, b, X, r, q,
-                                 mixed ? 1 : 0, part_pq);
+            launch_rhs_learned(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm.out_scale, V, s,
+                               mlp_y, b, X, r, q, kvp, mixed ? 1 : 0, part_pq, part0);
             launch_init_finalize_ws(st, T, part_pq, part0, sp.rel_mode, sc);
             launch_select(st, ctx->npad, V, q, X, r, mixed ? r32 : nullptr, delta, sc);
         } else {
             if (ctx->rec_X)   // training-data recorder: raw features
-                launch_rhs_features(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm, ctx->n, V,
-                                    Vprev, s, b, nullptr, ctx->rec_X, part_rz);
+                launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm,
+                                nullptr, ctx->rec_X);
+            float *kvp_out = want_kvp ? kvp : nullptr;
             if (mixed)
                 launch_rhs_init_mixed(st, T, P, Mv, Kv, dinv, dinv32, sp, V, Vprev, s, X, b, r32,
-                                      delta, part0);
+                                      delta, part0, kdiag, kvp_out);
             else
-                launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0);
+                launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0, kdiag,
+                                kvp_out);
             launch_init_finalize(st, T, part0, sp.rel_mode, sc);
         }
+        ctx->kvp_valid = want_kvp;
 
         // ---- PCG ----
         int units = 0;   // kernels carrying the SpMV launched so far
@@ -1894,6 +1906,7 @@ mdx_status mdx_set_state(mdx_ctx *ctx, const double *V, const double *Vprev, con
     }
     // padding rows of lat/lrt were zeroed by copy_vec_in; they are never read
     ctx->step = step;
+    ctx->kvp_valid = false;
     return MDX_OK;
     GUARD_END
 }

@@ -115,7 +115,7 @@ void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const dou
                            const double *Kv, const double *dinv, const float *dinv32,
                            const StepParams &sp, const double *V, const double *Vprev,
                            const double *src, double *x, double *b, float *r32, float *delta,
-                           double *partial);
+                           double *partial, const double *kdiag = nullptr, float *kvp = nullptr);
 void launch_set_direction32(hipStream_t s, int64_t n, const float *dinv32, const float *r32,
                             float *p32, const Scalars *sc);
 void launch_spmv32_dot(hipStream_t s, const Tiling &t, SellView P, const float *A32,
@@ -145,17 +145,23 @@ void launch_adam(hipStream_t s, float *P, float *m, float *v, const float *g, in
 // ---- learned warm start in the step (mdx_learned.hip) ----------------------
 void launch_kdiag(hipStream_t s, int64_t n_rows, int64_t n_real, SellView K, const double *Kv,
                   double *kdiag);
-// b and the features (standardised into feat, raw into raw; either may be
-// null); partial |D^-1 b|^2
-void launch_rhs_features(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
-                         const double *Kv, const double *kdiag, const double *dinv,
-                         const StepParams &sp, const MlpNorm &nm, int64_t n_real, const double *V,
-                         const double *Vprev, const double *src, double *b, float *feat,
-                         float *raw, double *partial);
-void launch_two_residuals(hipStream_t s, const Tiling &t, SellView P, const double *Av,
-                          const double *dinv, float out_scale, const double *V, const float *y,
-                          const double *b, double *x, double *r_mlp, double *r_prev, int fp32_iter,
-                          double *partial);
+// kvp = (K v)_i / K_ii in FP32 (the learned warm start's neighbour feature)
+void launch_kv_feature(hipStream_t s, const Tiling &t, SellView P, const double *Kv,
+                       const double *kdiag, const double *v, float *kvp);
+// features of step n: V^n, V^n - V^{n-1}, s / Cm, kvp = (K V^{n-1})_i / K_ii;
+// standardised into feat and raw into raw (either may be null), rows < n_real
+void launch_features(hipStream_t s, int64_t n_real, int64_t n_rows, const double *V,
+                     const double *Vprev, const double *src, const float *kvp, double cm,
+                     const MlpNorm &nm, float *feat, float *raw);
+// one pass over M and K: b, x_mlp = V + scale y, r_mlp = b - A x_mlp (into
+// r_mlp), r_prev = b - A V (into r_prev), kvp = (K V)_i / K_ii for the next
+// step; partials r.z, z.z of both (FP32-rounded first if fp32_iter) into
+// part4 and |D^-1 b|^2 into part1
+void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
+                        const double *Kv, const double *kdiag, const double *dinv,
+                        const StepParams &sp, float out_scale, const double *V,
+                        const double *src, const float *y, double *b, double *x, double *r_mlp,
+                        double *r_prev, float *kvp, int fp32_iter, double *part4, double *part1);
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
                              int rel_mode, Scalars *sc);
 void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
@@ -268,7 +274,8 @@ void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double am
 void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                      const double *Kv, const double *dinv, const StepParams &sp,
                      const double *V, const double *Vprev, const double *src, double *x,
-                     double *r, double *b, double *partial);
+                     double *r, double *b, double *partial, const double *kdiag = nullptr,
+                     float *kvp = nullptr);
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
                           Scalars *sc);
 // q = A p with partial p.q (no convergence logic; `done` non-zero skips it).

@@ -2,15 +2,18 @@
 //
 // Per-node features at step n (after the ionic update):
 //   f0 = V^n,  f1 = V^n - V^{n-1},  f2 = s / Cm = (I_stim - I_ion) / Cm,
-//   f3 = (K V^n)_i / K_ii  (one neighbour aggregate from the stiffness SpMV)
+//   f3 = (K V^{n-1})_i / K_ii  (one neighbour aggregate: the stiffness SpMV
+//        the previous step's right-hand side already formed)
 // are standardised and fed to the per-node MLP (mdx_mlp.hip), whose output
-// y predicts the increment: x_mlp = V^n + out_scale * y.  One pass over A
-// forms the initial residuals of both x_mlp and the previous-step guess V^n;
-// the MLP guess is used only if its ||D^-1 r0|| is smaller (and finite),
-// otherwise the previous step is (the fallback).
+// y predicts the increment: x_mlp = V^n + out_scale * y.  Because the
+// aggregate is the previous step's, the network runs before the right-hand
+// side, and one pass over M and K then forms b, the initial residuals of
+// both x_mlp and the previous-step guess V^n, and the next step's
+// aggregate.  The MLP guess is used only if its ||D^-1 r0|| is smaller (and
+// finite), otherwise the previous step is (the fallback).
 //
-// k_rhs_features also serves as the recorder of training data: raw features
-// of every node, and after the solve the increment V^{n+1} - V^n.
+// k_features also serves as the recorder of training data: raw features of
+// every node, and after the solve the increment V^{n+1} - V^n.
 #include "mdx_device.h"
 #include "mdx_internal.h"
 
@@ -18,86 +21,99 @@ namespace mdx {
 
 namespace {
 
-// b (FP64) and the features; partial |D^-1 b|^2
-__global__ __launch_bounds__(256) void k_rhs_features(
+// kvp = (K v)_i / K_ii
+__global__ __launch_bounds__(256) void k_kv_feature(Tiling t, const int64_t *__restrict__ slice_ptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const double *__restrict__ Kv,
+                                                    const double *__restrict__ kdiag,
+                                                    const double *__restrict__ v,
+                                                    float *__restrict__ kvp)
+{
+    const int g = logical_group(t.groups);
+    const int lane = threadIdx.x & (SLICE - 1);
+    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
+    for (int tile = g * t.tpb; tile < t_end; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        double kv = 0.0;
+        for (int64_t e = slice_ptr[sl] + lane; e < slice_ptr[sl + 1]; e += SLICE)
+            kv += Kv[e] * v[col[e]];
+        const double kd = kdiag[row];
+        kvp[row] = kd != 0.0 ? (float)(kv / kd) : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_features(int64_t n_real, int64_t n_rows,
+                                                  const double *__restrict__ V,
+                                                  const double *__restrict__ Vprev,
+                                                  const double *__restrict__ src,
+                                                  const float *__restrict__ kvp, double cm,
+                                                  MlpNorm nm, float4 *__restrict__ feat,
+                                                  float4 *__restrict__ raw)
+{
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n_rows) return;
+    const double vi = V[row];
+    float4 f;
+    f.x = (float)vi;
+    f.y = (float)(vi - Vprev[row]);
+    f.z = (float)(src[row] / cm);
+    f.w = kvp[row];
+    if (raw && row < n_real) raw[row] = f;
+    if (feat) {
+        float4 h;
+        h.x = (f.x - nm.mean[0]) * nm.inv_std[0];
+        h.y = (f.y - nm.mean[1]) * nm.inv_std[1];
+        h.z = (f.z - nm.mean[2]) * nm.inv_std[2];
+        h.w = (f.w - nm.mean[3]) * nm.inv_std[3];
+        feat[row] = h;
+    }
+}
+
+// b = chi M (Cm V + dt s) - (1-theta) dt K V;  A V = chi Cm M V + theta dt K V;
+// r_prev = b - A V;  r_mlp = r_prev - scale A y;  x = V + scale y
+__global__ __launch_bounds__(256) void k_rhs_learned(
     Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ kdiag,
-    const double *__restrict__ dinv, StepParams sp, MlpNorm nm, int64_t n_real,
-    const double *__restrict__ V, const double *__restrict__ Vprev, const double *__restrict__ src,
-    double *__restrict__ b, float4 *__restrict__ feat, float4 *__restrict__ raw,
-    double *__restrict__ partial)
+    const double *__restrict__ dinv, StepParams sp, float out_scale, const double *__restrict__ V,
+    const double *__restrict__ src, const float *__restrict__ y, double *__restrict__ b,
+    double *__restrict__ x, double *__restrict__ r_mlp, double *__restrict__ r_prev,
+    float *__restrict__ kvp, int fp32_iter, double *__restrict__ part4,
+    double *__restrict__ part1)
 {
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
     const double cK_old = (1.0 - sp.theta) * sp.dt;
-    double acc[1] = {0.0};
+    const double cM_new = sp.chi * sp.cm;
+    const double cK_new = sp.theta * sp.dt;
+    const double scale = (double)out_scale;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0}, accb[1] = {0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
-        double mv = 0.0, kv = 0.0;
+        double mv = 0.0, ms = 0.0, kv = 0.0, my = 0.0, ky = 0.0;
         for (int64_t e = beg; e < end; e += SLICE) {
             const int32_t c = col[e];
-            const double vj = V[c];
-            mv += Mv[e] * (sp.cm * vj + sp.dt * src[c]);
-            kv += Kv[e] * vj;
+            const double m = Mv[e], kk = Kv[e];
+            const double vj = V[c], yj = (double)y[c];
+            mv += m * vj;
+            ms += m * src[c];
+            kv += kk * vj;
+            my += m * yj;
+            ky += kk * yj;
         }
-        const double bi = sp.chi * mv - cK_old * kv;
+        const double bi = sp.chi * (sp.cm * mv + sp.dt * ms) - cK_old * kv;
+        const double rp = bi - (cM_new * mv + cK_new * kv);
+        const double rm = rp - scale * (cM_new * my + cK_new * ky);
         b[row] = bi;
-        const double db = dinv[row] * bi;
-        acc[0] += db * db;
-        const double vi = V[row];
-        const double kd = kdiag[row];
-        float4 f;
-        f.x = (float)vi;
-        f.y = (float)(vi - Vprev[row]);
-        f.z = (float)(src[row] / sp.cm);
-        f.w = (float)(kd != 0.0 ? kv / kd : 0.0);
-        if (raw && row < n_real) raw[row] = f;
-        if (feat) {
-            float4 h;
-            h.x = (f.x - nm.mean[0]) * nm.inv_std[0];
-            h.y = (f.y - nm.mean[1]) * nm.inv_std[1];
-            h.z = (f.z - nm.mean[2]) * nm.inv_std[2];
-            h.w = (f.w - nm.mean[3]) * nm.inv_std[3];
-            feat[row] = h;
-        }
-    }
-    write_partials<1>(acc, partial, t.groups, g);
-}
-
-// r_mlp = b - A x_mlp with x_mlp = V + s y formed per gathered column, and
-// r_prev = b - A V, in one pass over A; partials of r.z and z.z for both
-// (rounded to FP32 first when the iteration runs in FP32).
-__global__ __launch_bounds__(256) void k_two_residuals(
-    Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
-    const double *__restrict__ Av, const double *__restrict__ dinv, float out_scale,
-    const double *__restrict__ V, const float *__restrict__ y, const double *__restrict__ b,
-    double *__restrict__ x, double *__restrict__ r_mlp, double *__restrict__ r_prev, int fp32_iter,
-    double *__restrict__ partial)
-{
-    const int g = logical_group(t.groups);
-    const int lane = threadIdx.x & (SLICE - 1);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
-    for (int tile = g * t.tpb; tile < t_end; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
-        double am = 0.0, ap = 0.0;
-        for (int64_t e = beg; e < end; e += SLICE) {
-            const int32_t c = col[e];
-            const double a = Av[e], vj = V[c];
-            am += a * (vj + (double)out_scale * (double)y[c]);
-            ap += a * vj;
-        }
-        const double vi = V[row];
-        const double xi = vi + (double)out_scale * (double)y[row];
-        x[row] = xi;
-        const double rm = b[row] - am, rp = b[row] - ap, di = dinv[row];
+        x[row] = V[row] + scale * (double)y[row];
         r_mlp[row] = rm;
         r_prev[row] = rp;
+        const double kd = kdiag[row];
+        kvp[row] = kd != 0.0 ? (float)(kv / kd) : 0.0f;
+        const double di = dinv[row];
         if (fp32_iter) {
             const float rmf = (float)rm, rpf = (float)rp, df = (float)di;
             const float zmf = df * rmf, zpf = df * rpf;
@@ -112,8 +128,10 @@ __global__ __launch_bounds__(256) void k_two_residuals(
             acc[2] += rp * zp;
             acc[3] += zp * zp;
         }
+        accb[0] += (di * bi) * (di * bi);
     }
-    write_partials<4>(acc, partial, t.groups, g);
+    write_partials<4>(acc, part4, t.groups, g);
+    write_partials<1>(accb, part1, t.groups, g);
 }
 
 // choose the guess; scalars of the PCG initialisation
@@ -200,24 +218,31 @@ void launch_kdiag(hipStream_t s, int64_t n_rows, int64_t n_real, SellView K, con
                        K.slice_ptr, K.col, Kv, kdiag);
 }
 
-void launch_rhs_features(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
-                         const double *Kv, const double *kdiag, const double *dinv,
-                         const StepParams &sp, const MlpNorm &nm, int64_t n_real, const double *V,
-                         const double *Vprev, const double *src, double *b, float *feat,
-                         float *raw, double *partial)
+void launch_kv_feature(hipStream_t s, const Tiling &t, SellView P, const double *Kv,
+                       const double *kdiag, const double *v, float *kvp)
 {
-    hipLaunchKernelGGL(k_rhs_features, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv,
-                       Kv, kdiag, dinv, sp, nm, n_real, V, Vprev, src, b, (float4 *)feat,
-                       (float4 *)raw, partial);
+    hipLaunchKernelGGL(k_kv_feature, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Kv,
+                       kdiag, v, kvp);
 }
 
-void launch_two_residuals(hipStream_t s, const Tiling &t, SellView P, const double *Av,
-                          const double *dinv, float out_scale, const double *V, const float *y,
-                          const double *b, double *x, double *r_mlp, double *r_prev, int fp32_iter,
-                          double *partial)
+void launch_features(hipStream_t s, int64_t n_real, int64_t n_rows, const double *V,
+                     const double *Vprev, const double *src, const float *kvp, double cm,
+                     const MlpNorm &nm, float *feat, float *raw)
 {
-    hipLaunchKernelGGL(k_two_residuals, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av,
-                       dinv, out_scale, V, y, b, x, r_mlp, r_prev, fp32_iter, partial);
+    if (n_rows > 0)
+        hipLaunchKernelGGL(k_features, dim3(blocks_for(n_rows)), dim3(256), 0, s, n_real, n_rows, V,
+                           Vprev, src, kvp, cm, nm, (float4 *)feat, (float4 *)raw);
+}
+
+void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
+                        const double *Kv, const double *kdiag, const double *dinv,
+                        const StepParams &sp, float out_scale, const double *V,
+                        const double *src, const float *y, double *b, double *x, double *r_mlp,
+                        double *r_prev, float *kvp, int fp32_iter, double *part4, double *part1)
+{
+    hipLaunchKernelGGL(k_rhs_learned, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
+                       kdiag, dinv, sp, out_scale, V, src, y, b, x, r_mlp, r_prev, kvp, fp32_iter,
+                       part4, part1);
 }
 
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
     const float *__restrict__ dinv32, StepParams sp, const double *__restrict__ V,
     const double *__restrict__ Vprev, const double *__restrict__ src, double *__restrict__ x,
     double *__restrict__ b, float *__restrict__ r32, float *__restrict__ delta,
-    double *__restrict__ partial)
+    double *__restrict__ partial, const double *__restrict__ kdiag, float *__restrict__ kvp)
 {
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
@@ -78,6 +78,7 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
         const double vi = V[row];
         x[row] = extrap ? 2.0 * vi - Vprev[row] : vi;
         b[row] = bi;
+        if (kvp) kvp[row] = kdiag[row] != 0.0 ? (float)(kv / kdiag[row]) : 0.0f;
         const float rf = (float)ri;
         r32[row] = rf;
         delta[row] = 0.0f;
@@ -305,10 +306,11 @@ void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const dou
                            const double *Kv, const double *dinv, const float *dinv32,
                            const StepParams &sp, const double *V, const double *Vprev,
                            const double *src, double *x, double *b, float *r32, float *delta,
-                           double *partial)
+                           double *partial, const double *kdiag, float *kvp)
 {
     hipLaunchKernelGGL(k_rhs_init_mixed, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col,
-                       Mv, Kv, dinv, dinv32, sp, V, Vprev, src, x, b, r32, delta, partial);
+                       Mv, Kv, dinv, dinv32, sp, V, Vprev, src, x, b, r32, delta, partial, kdiag,
+                       kvp);
 }
 
 void launch_set_direction32(hipStream_t s, int64_t n, const float *dinv32, const float *r32,

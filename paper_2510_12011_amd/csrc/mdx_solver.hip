@@ -70,7 +70,8 @@ __global__ __launch_bounds__(256) void k_rhs_init(
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
     StepParams sp, const double *__restrict__ V, const double *__restrict__ Vprev,
     const double *__restrict__ src, double *__restrict__ x, double *__restrict__ r,
-    double *__restrict__ b, double *__restrict__ partial)
+    double *__restrict__ b, double *__restrict__ partial, const double *__restrict__ kdiag,
+    float *__restrict__ kvp)
 {
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(256) void k_rhs_init(
         x[row] = x0i;
         r[row] = ri;
         b[row] = bi;
+        if (kvp) kvp[row] = kdiag[row] != 0.0 ? (float)(kv / kdiag[row]) : 0.0f;
         acc[0] += ri * zi;
         acc[1] += zi * zi;
         acc[2] += (di * bi) * (di * bi);
@@ -356,10 +358,10 @@ void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double am
 void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                      const double *Kv, const double *dinv, const StepParams &sp, const double *V,
                      const double *Vprev, const double *src, double *x, double *r, double *b,
-                     double *partial)
+                     double *partial, const double *kdiag, float *kvp)
 {
     hipLaunchKernelGGL(k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
-                       dinv, sp, V, Vprev, src, x, r, b, partial);
+                       dinv, sp, V, Vprev, src, x, r, b, partial, kdiag, kvp);
 }
 
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,

@@ -72,7 +72,8 @@ def record(sim, n_steps: int, every: int = 10, front: float = 0.02, frac: float 
 
 def fit(sim, X, dV, epochs: int = 10, batch: int = 8192, lr: float = 2e-3, seed: int = 0,
         theta0: np.ndarray | None = None, log=None):
-    """Train on (X, dV).  Returns (params float32 [8705], norm float64 [9],
+    """Train on (X, dV): the network's target is the standardised increment
+    V^{n+1} - V^n.  Returns (params float32 [8705], norm float64 [9],
     per-epoch mean loss)."""
     import torch
     dev = X.device

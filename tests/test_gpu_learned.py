@@ -46,7 +46,7 @@ def test_recorder_features_match_oracle():
     o.steps(250)
     V, Vp, u = o.state.V.copy(), o.state.Vprev.copy(), o.state.u.copy()
     iion = orc.ionic_step("tt", V, u, spec.dt)           # u advanced on a copy
-    kv = orc.spmv(o.mats, o.mats.K, V)
+    kv = orc.spmv(o.mats, o.mats.K, Vp)                   # neighbour aggregate of V^{n-1}
     kd = o.mats.dense("K").diagonal()
     ref = np.stack([V, V - Vp, -iion, kv / kd], axis=1)    # the 2 ms stimulus ended at step 200
     o.steps(1)
