@@ -297,6 +297,9 @@ def main():
     ap.add_argument("--instances", type=int, default=64, help="batched workload")
     ap.add_argument("--total-nodes", type=int, default=12_000_000, help="batched workload")
     ap.add_argument("--no-graph", action="store_true", help="batched workload")
+    ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-MiB device buffer 3 times (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     ap.add_argument("--train-sites", type=int, default=4, help="learned workload")
     ap.add_argument("--train-steps", type=int, default=2000, help="learned workload")
     args = ap.parse_args()
@@ -310,10 +313,29 @@ def main():
     if args.warmup is None:
         args.warmup = {"learned": 0, "batched": 10}.get(args.workload, 100)
     if args.workload == "batched":
-        return batched_workload(args)
-    if args.workload == "learned":
-        return learned_workload(args)
+        batched_workload(args)
+    elif args.workload == "learned":
+        learned_workload(args)
+    else:
+        single_workload(args)
+    if args.copy_check:
+        copy_check(args.copy_check)
 
+
+def copy_check(mib):
+    """Device-to-device copies of a known size: each reads and writes
+    mib MiB, so a byte counter's reading on them gives its scale."""
+    import torch
+    a = torch.ones(mib * 262144, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[bench] copy check: 3 copies of {mib} MiB ({mib * 1048576} bytes read and written each)",
+          flush=True)
+
+
+def single_workload(args):
     import torch
     from paper_2510_12011_amd import sim
 
