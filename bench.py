@@ -38,6 +38,25 @@ sys.path.insert(0, ROOT)
 METRIC = ("DOF·steps/s at equal accuracy, learned+FP32 vs plain FP64 PCG; "
           "SpMV HBM GB/s")
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "learned_shell_1.26M_hbm_traffic.md")
+
+
+def measured_traffic(kernel, source):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if the summary is missing or the kernel's source file changed
+    since the counters were taken (its recorded sha256 differs)."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = open(os.path.join(ROOT, source), "rb").read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch %s: (\S+)" % re.escape(kernel), text)
+    h = re.search(r"source_sha256 %s: (\w+)" % re.escape(source), text)
+    if not m or not h or hashlib.sha256(src).hexdigest() != h.group(1):
+        return None
+    return float(m.group(1))
 
 
 def workload(name):
@@ -185,7 +204,10 @@ def learned_workload(args):
                    "train_sites": args.train_sites, "train_steps": args.train_steps},
         "roofline": {"bound": "hbm", "kernel": "k_spmv32_dot", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": bytes_avg,
+                     "traffic": measured_traffic("k_spmv32_dot",
+                                                 "paper_2510_12011_amd/csrc/mdx_mixed.hip"),
+                     "traffic_source": "profiles/learned_shell_1.26M_hbm_traffic.md",
+                     "bytes_per_launch": bytes_avg,
                      "avg_launch_us": 1e6 * spmv_avg, "launches_timed": st["spmv_timed"],
                      "sampled_every_n_steps": args.profile_every,
                      "cache_resident": bool(8 * st["nnz"] < 256e6)},
