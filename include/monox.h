@@ -193,7 +193,7 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
 
 /* Launch-shape tuning (no effect on results beyond rounding order):
  *   MDX_TUNE_MAX_GROUPS  cap on workgroups of the row-tiled kernels
- *                        (16..65536, default 4096);
+ *                        (16..65536, default 2048);
  *   MDX_TUNE_ITER_SCHEME PCG iteration as three kernels (0: SpMV, update,
  *                        direction; default) or two kernels (1: the
  *                        direction is formed per gathered column inside
@@ -207,7 +207,7 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
  *                        that SpMV: 1, 2 or 4 for sliced ELL (64, 32 or 16
  *                        rows per wavefront), 4, 8 or 16 for CSR;
  *   MDX_TUNE_TILES_PER_GROUP batched context: 256-row tiles per workgroup
- *                        (default: about 4096 workgroups);
+ *                        (default 1);
  *   MDX_TUNE_GRAPH       batched context: 1 to replay each time step's work
  *                        up to the convergence check as a captured HIP graph
  *                        (one per iteration count and buffer rotation), 0 to

@@ -34,7 +34,7 @@ using namespace mdx;
 
 namespace {
 
-constexpr int kMaxGroups = 4096;      // default cap on row-tiled workgroups
+constexpr int kMaxGroups = 2048;      // default cap on row-tiled workgroups
 constexpr int kPartialCap = 65536;    // partial slots per reduction (>= any cap)
 constexpr size_t kAlign = 256;
 
@@ -1483,10 +1483,12 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
         std::memset((void *)ctx->bsc_host, 0, sizeof(BScalars) * ctx->n_inst);
         HIPCHK(hipMemcpyAsync(ctx->dev<BScalars>(L.bsc), ctx->bsc_host,
                               sizeof(BScalars) * ctx->n_inst, hipMemcpyHostToDevice, st));
-        // default: about 4096 workgroups
-        const int64_t n_tiles = ctx->npad / TILE;
-        const int tpb = (int)std::max<int64_t>(1, (n_tiles + kMaxGroups - 1) / kMaxGroups);
-        if (mdx_status e = install_groups(ctx, tpb)) return e;
+        // default: one tile per workgroup (the per-instance partials are
+        // reduced once, not by every consumer), more if the partial slots
+        // would not hold them
+        const int64_t slots = ctx->npad / TILE + ctx->n_inst;
+        const int tpb = (int)std::max<int64_t>(1, (slots + kPartialCap - 1) / kPartialCap + 1);
+        if (mdx_status e = install_groups(ctx, slots <= kPartialCap ? 1 : tpb)) return e;
     }
     ctx->dt = dt;
     ctx->step = 0;

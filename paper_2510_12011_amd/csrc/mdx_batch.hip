@@ -394,7 +394,7 @@ __global__ __launch_bounds__(256) void k_b_beta(int groups, const int32_t *__res
     }
     const bool pass = zn < bp.atol || zn < bp.rtol * s.ref || zn <= s.floor_;
     if (pass || (bp.rr > 0 && it % bp.rr == 0) || it >= bp.max_iter) {
-        s.replace = 1;
+        s.replace = pass ? 1 : 2;   // 1: the recursive residual passed the test
         return;
     }
     s.beta = v[0] / s.rho;
@@ -476,6 +476,7 @@ __global__ __launch_bounds__(256) void k_b_replace_finalize(int groups,
     if (threadIdx.x != 0) return;
     const double zn = sqrt(v[1]);
     const int it = s.it;
+    const int why = s.replace;
     s.znorm = zn;
     s.replace = 0;
     if (!(zn == zn) || !(v[0] == v[0])) {
@@ -495,7 +496,9 @@ __global__ __launch_bounds__(256) void k_b_replace_finalize(int groups,
         s.iters = it;
         return;
     }
-    s.beta = v[0] / s.rho;
+    // restart (p = z) after the recursive residual passed but the true one did
+    // not; keep the recurrence after a periodic replacement
+    s.beta = why == 1 ? 0.0 : v[0] / s.rho;
     s.rho = v[0];
     s.redirect = 1;
 }

@@ -46,7 +46,8 @@ struct alignas(256) Scalars {
     int32_t nonfinite;  // a non-finite V was produced
     int32_t zero;       // always 0 (for launches that must not early-exit)
     // mixed-precision form: residual replacement protocol
-    int32_t replace;    // a replacement is pending (iteration kernels idle)
+    int32_t replace;    // a replacement is pending (iteration kernels idle): 1 the
+                        // recursive residual passed the test, 2 periodic or cap
     int32_t redirect;   // a replacement did not stop: p = z + beta p pending
     int32_t it_next;    // iterations completed (index of the next one)
     int32_t use_mlp;    // learned warm start: the MLP guess was chosen this step
@@ -197,7 +198,8 @@ struct alignas(128) BScalars {
     int32_t done;       // finished: converged, failed or non-finite
     int32_t iters;      // iterations of the finished solve
     int32_t it;         // iterations completed so far
-    int32_t replace;    // residual replacement pending (iteration kernels idle)
+    int32_t replace;    // replacement pending (iteration kernels idle): 1 after the
+                        // recursive residual passed the test, 2 periodic or cap
     int32_t redirect;   // replacement did not stop: p = z + beta p pending
     int32_t nonfinite;  // a non-finite value reached a reduction
     int32_t failed;     // iteration cap reached without convergence

@@ -295,8 +295,11 @@ __device__ __forceinline__ bool real_row(int64_t i, int64_t n, const int32_t *ti
 }
 
 // ---------------------------------------------------------------------------
+// Three workgroups of 256 per CU (12 wavefronts, 168 registers each): the
+// ten Tusscher-Panfilov update is latency bound at the two wavefronts per SIMD
+// its unconstrained 222 registers allow; a few spilled values cost less.
 template <int KIND>
-__global__ __launch_bounds__(256) void k_ionic_step(IonicParams P, int64_t n, int64_t ld, double dt,
+__global__ __launch_bounds__(256, 3) void k_ionic_step(IonicParams P, int64_t n, int64_t ld, double dt,
                                                     double cm, const double *__restrict__ V,
                                                     double *__restrict__ u,
                                                     const double *__restrict__ istim,
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(256) void k_ionic_init(IonicParams P, int64_t n, in
 // the current in FP64 (u[s * ld + i], rows 0..5 for the ten Tusscher-Panfilov
 // model; Mitchell-Schaeffer has only its gate h).
 template <int KIND>
-__global__ __launch_bounds__(256) void k_ionic_step_mixed(IonicParams P, int64_t n, int64_t ld,
+__global__ __launch_bounds__(256, 4) void k_ionic_step_mixed(IonicParams P, int64_t n, int64_t ld,
                                                           double dt, double cm,
                                                           const double *__restrict__ V,
                                                           double *__restrict__ u,

@@ -15,8 +15,10 @@
 // r64 = b - A x64 in FP64 -- the stopping test
 // is then applied to that true residual, so the solve stops on the same
 // criterion as the FP64 path.  If the true residual does not pass, the
-// iteration continues from r = r64 with beta = rho_new / rho_old
-// (residual replacement keeps the search direction).
+// iteration continues from r = r64: after a periodic replacement with
+// beta = rho_new / rho_old (the search direction is kept), after one
+// triggered by the recursive residual passing the test with p = z (the
+// recursion had drifted from the true residual; restart).
 //
 // Kernels queued after convergence or while a replacement is pending return
 // at their first instruction; the replacement kernels return unless one is
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(256) void k_cg_direction32(Tiling t, int k, int rr,
     const bool pass = zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_;
     if (pass || (rr > 0 && (k + 1) % rr == 0) || k + 1 >= max_iter) {
         if (lead) {
-            sc->replace = 1;
+            sc->replace = pass ? 1 : 2;   // 1: the recursive residual passed the test
             sc->it_next = k + 1;
             sc->znorm = zn;
         }
@@ -262,6 +264,7 @@ __global__ __launch_bounds__(256) void k_replace_finalize(int groups, int max_it
     if (threadIdx.x != 0) return;
     const double zn = sqrt(v[1]);
     const int it = sc->it_next;
+    const int why = sc->replace;
     sc->znorm = zn;
     sc->replace = 0;
     if (!(zn == zn)) {
@@ -276,7 +279,11 @@ __global__ __launch_bounds__(256) void k_replace_finalize(int groups, int max_it
         return;
     }
     if (it >= max_iter || it < 1) return;   // cap: the host reports no convergence
-    sc->beta = v[0] / sc->rho[(it - 1) & 1];
+    // The recursive FP32 residual passed but the true one did not: the two have
+    // drifted apart, rho of the recursion is no measure of the true residual,
+    // and CG restarts from it (p = z).  A periodic replacement keeps the
+    // recurrence (beta = rho_new / rho_old).
+    sc->beta = why == 1 ? 0.0 : v[0] / sc->rho[(it - 1) & 1];
     sc->rho[it & 1] = v[0];
     sc->redirect = 1;
 }

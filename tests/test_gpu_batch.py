@@ -138,3 +138,25 @@ def test_autotune_installs_fastest(bspec, batch_run):
     assert st == 0
     errs = [_rel_l2(a, b) for a, b in zip(v, batch_run["v"])]
     assert max(errs) <= V_REL_L2
+
+
+def test_batch_converges_relative_to_initial_residual(bspec):
+    """Per-instance stopping relative to ||z0|| at 1e-10 (see the mixed-form
+    test of the same name): every instance converges every step and matches
+    its oracle run."""
+    from paper_2510_12011_amd import sim
+    import copy
+    b = copy.copy(bspec)
+    b.instances = bspec.instances[:2]
+    b.rel_mode, b.rtol = 0, 1e-10
+    print("[case] batch of 2, rtol 1e-10 of ||z0||", flush=True)
+    s = sim.batch_from_spec(b)
+    v, st = s.run(200, 100)
+    its = s.instance_iterations(200)
+    assert st == 0 and (its >= 0).all() and its.max() < 100
+    ptr = b.node_ptr()
+    for k in range(2):
+        o = orc.Oracle(b.instance_spec(k))
+        v_or, _ = o.steps(200, out_every=100)
+        errs = [_rel_l2(a, c) for a, c in zip(_split(v, ptr)[k], v_or)]
+        assert max(errs) <= V_REL_L2, errs

@@ -134,3 +134,22 @@ def test_fp32_gates_option_error_is_reported():
     err = max(_rel_l2(a, b) for a, b in zip(v_gpu, v_or))
     print(f"  fp32 gates vs oracle: V rel L2 max {err:.2e}", flush=True)
     assert err <= 1e-4
+
+
+def test_mixed_converges_relative_to_initial_residual():
+    """Stopping relative to ||z0|| (the paper's test) at 1e-10: with a good
+    warm start ||z0|| is tiny, so the FP32 recursion drifts below the true
+    residual before the target is met; the residual replacement must restart
+    CG from the true residual rather than keep the drifted recurrence.  Every
+    step converges and V matches the oracle."""
+    spec = inputs.slab(h=0.5, n_steps=300)
+    spec.rtol, spec.rel_mode = 1e-10, 0
+    s = _sim(spec, "mixed")
+    v_gpu, status = s.run(300, 100)
+    it = s.iterations(300)
+    print(f"  mixed, rtol 1e-10 of ||z0||: iterations {it.min()}..{it.max()}, status {status}",
+          flush=True)
+    assert status == 0 and (it >= 0).all() and it.max() < 100
+    o = orc.Oracle(spec)
+    v_or, _ = o.steps(300, out_every=100)
+    assert max(_rel_l2(a, b) for a, b in zip(v_gpu, v_or)) <= V_REL_L2
