@@ -277,8 +277,8 @@ def batched_workload(args):
                    "tiles_per_group": rep["tiles_per_group"], "graph": not args.no_graph,
                    "mean_cg_iters": float(its.mean()), "max_cg_iters": int(its.max())},
         "roofline": {"bound": "hbm",
-                     "kernel": {"sell": "k_b_spmv", "csr": "k_b_spmv_csr",
-                                "sell4": "k_b_spmv_v4"}[rep["fmt"]],
+                     "kernel": {"sell": "k_b_spmv", "csr": "k_b_spmv_csr", "sell4": "k_b_spmv_v4",
+                                "sell4nt": "k_b_spmv_v4"}[rep["fmt"]],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": bytes_avg, "avg_launch_us": 1e6 * spmv_avg,

@@ -200,9 +200,10 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
  *                        the SpMV);
  *   MDX_TUNE_FORMAT      batched context: storage the iteration's FP32 SpMV
  *                        reads, 0 sliced ELL (default; 1 lane per row),
- *                        1 CSR (no padding; 8 lanes per row) or 2 sliced
+ *                        1 CSR (no padding; 8 lanes per row), 2 sliced
  *                        ELL with 4 consecutive entries per lane and
- *                        16-byte loads (1 lane per row);
+ *                        16-byte loads (1 lane per row), or 3 the same
+ *                        with non-temporal loads of the matrix;
  *   MDX_TUNE_LANES_PER_ROW   batched context: lanes of a wavefront per row in
  *                        that SpMV: 1, 2 or 4 for sliced ELL (64, 32 or 16
  *                        rows per wavefront), 4, 8 or 16 for CSR;
@@ -212,6 +213,11 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
  *                        up to the convergence check as a captured HIP graph
  *                        (one per iteration count and buffer rotation), 0 to
  *                        launch it kernel by kernel (default 0).
+ *   MDX_TUNE_NONTEMPORAL matrix streams (values, column indices) read with the
+ *                        non-temporal cache hint: -1 (default) for each
+ *                        kernel whose streams exceed 256 MiB (larger than
+ *                        the Infinity Cache can keep between products), 0
+ *                        never, 1 always.
  * MAX_GROUPS and ITER_SCHEME take effect at the next mdx_prepare / mdx_run;
  * the batched keys need a prepared batched context and act at once. */
 enum {
@@ -220,7 +226,8 @@ enum {
     MDX_TUNE_LANES_PER_ROW = 3,
     MDX_TUNE_TILES_PER_GROUP = 4,
     MDX_TUNE_GRAPH = 5,
-    MDX_TUNE_FORMAT = 6
+    MDX_TUNE_FORMAT = 6,
+    MDX_TUNE_NONTEMPORAL = 7
 };
 MDX_API mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value);
 
@@ -265,7 +272,8 @@ typedef struct {
 /* Autotuner of a prepared batched context: times reps launches (1..1000) of
  * the iteration's FP32 SpMV on the context's own matrix for sliced ELL with
  * 1, 2, 4 lanes per row (64, 32, 16 rows per wavefront), sliced ELL with
- * 4-entry vector loads, and CSR with 4, 8, 16 lanes per row (16, 8, 4 rows
+ * 4-entry vector loads (plain or non-temporal), and CSR with 4, 8, 16 lanes
+ * per row (16, 8, 4 rows
  * per wavefront), each with 1, 2, 4, 8 tiles
  * per workgroup, and installs the fastest (as the MDX_TUNE_FORMAT,
  * MDX_TUNE_LANES_PER_ROW and MDX_TUNE_TILES_PER_GROUP keys would).  Results

@@ -30,6 +30,7 @@ MDX_PREC_FP64, MDX_PREC_MIXED, MDX_PREC_MIXED_GATES32 = 0, 1, 2
 MDX_MAT_M, MDX_MAT_K, MDX_MAT_A = 0, 1, 2
 MDX_TUNE_MAX_GROUPS, MDX_TUNE_ITER_SCHEME = 1, 2
 MDX_TUNE_LANES_PER_ROW, MDX_TUNE_TILES_PER_GROUP, MDX_TUNE_GRAPH, MDX_TUNE_FORMAT = 3, 4, 5, 6
+MDX_TUNE_NONTEMPORAL = 7
 MDX_TUNE_MAX_CANDIDATES = 32
 
 

@@ -35,6 +35,9 @@ using namespace mdx;
 namespace {
 
 constexpr int kMaxGroups = 2048;      // default cap on row-tiled workgroups
+// matrix streams above this size are read with the non-temporal hint (they do
+// not stay in the 256 MB Infinity Cache between products anyway)
+constexpr double kStreamCacheBytes = 256.0 * 1024 * 1024;
 constexpr int kPartialCap = 65536;    // partial slots per reduction (>= any cap)
 constexpr size_t kAlign = 256;
 
@@ -52,7 +55,7 @@ struct Layout {
     size_t A32, dinv32, r32, p32, q32, delta, g32;   // mixed-precision form
     size_t kdiag, kvp, feat, mlp_y, mlp_params;       // learned warm start
     size_t tile_real, grp, inst_grp, bsc, sptr_t, col_t, A32_t;   // batched form
-    size_t csr_ptr, csr_col, csr_val;
+    size_t csr_ptr, csr_col, csr_val, gv;
     size_t total;
     size_t x_xyz, x_tets, x_fibre, x_sig, x_vol, x_ek, x_cptr, x_contrib, x_total;
 };
@@ -106,6 +109,7 @@ struct mdx_ctx {
     // launch-shape tuning
     int max_groups = kMaxGroups;
     int iter_scheme = 0;
+    int nt_mode = -1;   // non-temporal matrix loads: -1 by stream size, 0 never, 1 always
 
     // batched form: instances, each a contiguous row range starting on a
     // TILE boundary (a single-mesh context has one instance, rows [0, n))
@@ -422,6 +426,7 @@ void compute_layout(mdx_ctx *c)
         L.csr_ptr = take(sizeof(int32_t) * (c->batched ? np + 1 : 1));
         L.csr_col = take(sizeof(int32_t) * cnz);
         L.csr_val = take(sizeof(float) * cnz);
+        L.gv = take(sizeof(double) * 4 * (c->batched ? np : 1));
     }
     L.total = o;
 
@@ -506,6 +511,13 @@ void release_graphs(mdx_ctx *ctx)
     for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
     ctx->graphs.clear();
 }
+
+// non-temporal hint for a kernel whose matrix streams total `bytes`
+bool use_nt(const mdx_ctx *c, double bytes)
+{
+    return c->nt_mode < 0 ? bytes > kStreamCacheBytes : c->nt_mode != 0;
+}
+double slots(const mdx_ctx *c) { return (double)c->nslots; }
 
 // rows covered by the pointwise kernels and their padding mask: the real
 // rows are a prefix in a single-mesh context and interleaved with padding
@@ -646,8 +658,8 @@ mdx_status set_iter_layout(mdx_ctx *c, int fmt, int lpr)
         return fail(c, MDX_ERR_INVALID_ARG, "sliced ELL takes 1, 2 or 4 lanes per row");
     if (fmt == 1 && lpr != 4 && lpr != 8 && lpr != 16)
         return fail(c, MDX_ERR_INVALID_ARG, "CSR takes 4, 8 or 16 lanes per row");
-    if (fmt == 2 && lpr != 1)
-        return fail(c, MDX_ERR_INVALID_ARG, "4-entry-chunk layout takes 1 lane per row");
+    if (fmt >= 2 && lpr != 1)
+        return fail(c, MDX_ERR_INVALID_ARG, "4-entry-chunk layouts take 1 lane per row");
     if (fmt == 0) {
         if (mdx_status e = build_lpr_layout(c, lpr)) return e;
     } else if (fmt == 1) {
@@ -667,6 +679,7 @@ IterMatrix iter_matrix(const mdx_ctx *c)
     IterMatrix A{};
     A.format = c->fmt;
     A.lpr = c->lpr;
+    A.nt = use_nt(c, 8.0 * slots(c));
     if (c->fmt == 1) {
         A.rptr = c->dev<int32_t>(L.csr_ptr);
         A.col = c->dev<int32_t>(L.csr_col);
@@ -946,8 +959,9 @@ void enqueue_batched_step(mdx_ctx *c, hipStream_t st, int iters, const double *i
     else
         launch_ionic_step(st, c->ionic_kind, c->ionic_params.data(), c->npad, c->npad, c->dt, c->cm,
                           V, q.u, istim, q.s, 0, row_mask(c));
-    launch_b_rhs_init(st, c->seg, q.P, q.Mv, q.Kv, q.dinv, q.dinv32, sp, V, Vprev, q.s, X, q.b, q.r32,
-                      q.delta, q.part0);
+    launch_b_rhs_init(st, c->seg, q.P, q.Mv, q.Kv, q.dinv, q.dinv32, sp, c->npad, V, Vprev, q.s,
+                      c->dev<double>(c->L.gv), X, q.b, q.r32, q.delta, q.part0,
+                      use_nt(c, 20.0 * slots(c)));
     launch_b_init_finalize(st, c->seg, q.part0, bp, q.bsc);
     launch_b_set_direction(st, c->seg, q.dinv32, q.r32, q.p32, q.bsc);
     for (int i = 0; i < iters; ++i) {
@@ -960,7 +974,7 @@ void enqueue_batched_step(mdx_ctx *c, hipStream_t st, int iters, const double *i
                            q.part_rz, q.bsc, e0, e1);
     }
     launch_b_replacement(st, c->seg, q.P, bp, q.Av, X, q.delta, q.b, q.dinv, q.dinv32, q.r32, q.p32,
-                         q.part0, q.bsc);
+                         q.part0, q.bsc, use_nt(c, 12.0 * slots(c)));
 }
 
 mdx_status fetch_bscalars(mdx_ctx *c, hipStream_t st)
@@ -1045,7 +1059,7 @@ mdx_status run_batched(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double 
             launch_b_iteration(st, ctx->seg, q.IM, bp, q.dinv32, q.p32, q.q32, q.delta, q.r32,
                                q.part_pq, q.part_rz, q.bsc, e0, e1);
             launch_b_replacement(st, ctx->seg, q.P, bp, q.Av, X, q.delta, q.b, q.dinv, q.dinv32, q.r32,
-                                 q.p32, q.part0, q.bsc);
+                                 q.p32, q.part0, q.bsc, use_nt(ctx, 12.0 * slots(ctx)));
             HIPCHK(hipGetLastError());
             ++units;
             if (mdx_status e = fetch_bscalars(ctx, st)) return e;
@@ -1542,6 +1556,10 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     mdx_status result = MDX_OK;
     ctx->iters_hist.clear();
     int64_t n_out = 0;
+    // non-temporal hints by the size of each kernel's matrix streams
+    const bool nt_rhs = use_nt(ctx, 20.0 * slots(ctx));     // M, K and columns
+    const bool nt_iter64 = use_nt(ctx, 12.0 * slots(ctx));  // FP64 A and columns
+    const bool nt_iter32 = use_nt(ctx, 8.0 * slots(ctx));   // FP32 A and columns
     auto t_start = std::chrono::steady_clock::now();
 
     for (int64_t j = 0; j < n_steps; ++j) {
@@ -1570,7 +1588,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                             ctx->rec_X);
             launch_mlp_forward(st, mlp_params, ctx->n, feat, mlp_y);   // padding rows keep y = 0
             launch_rhs_learned(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm.out_scale, V, s,
-                               mlp_y, b, X, r, q, kvp, mixed ? 1 : 0, part_pq, part0);
+                               mlp_y, b, X, r, q, kvp, mixed ? 1 : 0, part_pq, part0, nt_rhs);
             launch_init_finalize_ws(st, T, part_pq, part0, sp.rel_mode, sc);
             launch_select(st, ctx->npad, V, q, X, r, mixed ? r32 : nullptr, delta, sc);
         } else {
@@ -1580,10 +1598,10 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             float *kvp_out = want_kvp ? kvp : nullptr;
             if (mixed)
                 launch_rhs_init_mixed(st, T, P, Mv, Kv, dinv, dinv32, sp, V, Vprev, s, X, b, r32,
-                                      delta, part0, kdiag, kvp_out);
+                                      delta, part0, kdiag, kvp_out, nt_rhs);
             else
                 launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0, kdiag,
-                                kvp_out);
+                                kvp_out, nt_rhs);
             launch_init_finalize(st, T, part0, sp.rel_mode, sc);
         }
         ctx->kvp_valid = want_kvp;
@@ -1603,7 +1621,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                         e0 = ctx->ev[2 * units];
                         e1 = ctx->ev[2 * units + 1];
                     }
-                    launch_spmv32_dot(st, T, P, A32, p32, q32, part_pq, sc, e0, e1);
+                    launch_spmv32_dot(st, T, P, A32, p32, q32, part_pq, sc, e0, e1, nt_iter32);
                     launch_cg_update32(st, T, it + i, part_pq, dinv32, p32, q32, delta, r32, part_rz,
                                        sc);
                     launch_cg_direction32(st, T, it + i, ctx->opts.rr_interval, max_iter, part_rz,
@@ -1611,7 +1629,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                     ++units;
                 }
                 launch_replacement(st, T, P, max_iter, Av, X, delta, b, dinv, dinv32, r32, p32,
-                                   part0, sc);
+                                   part0, sc, nt_iter64);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
                 auto w0 = std::chrono::steady_clock::now();
@@ -1643,7 +1661,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                     }
                     launch_cg_direction_spmv(st, T, u_, max_iter, P, Av, dinv, r,
                                              pbuf[(u_ + 1) & 1], pbuf[u_ & 1], q, part_rz,
-                                             part_pq, sc, e0, e1);
+                                             part_pq, sc, e0, e1, nt_iter64);
                 }
                 units += c;
                 HIPCHK(hipGetLastError());
@@ -1672,7 +1690,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                         e0 = ctx->ev[2 * it];
                         e1 = ctx->ev[2 * it + 1];
                     }
-                    launch_spmv_dot(st, T, P, Av, p, q, part_pq, &sc->done, e0, e1);
+                    launch_spmv_dot(st, T, P, Av, p, q, part_pq, &sc->done, e0, e1, nt_iter64);
                     launch_cg_update(st, T, it, part_pq, dinv, p, q, X, r, part_rz, sc);
                     launch_cg_direction(st, T, it, part_rz, dinv, r, p, sc);
                 }
@@ -1796,7 +1814,7 @@ mdx_status mdx_autotune(mdx_ctx *ctx, int32_t reps, mdx_tune_report *rep)
     mdx_tune_report r{};
     double best = std::numeric_limits<double>::infinity();
     int best_fmt = 0, best_lpr = 1, best_tpb = ctx->tpb_b;
-    const int layouts[7][2] = {{0, 1}, {0, 2}, {0, 4}, {2, 1}, {1, 4}, {1, 8}, {1, 16}};
+    const int layouts[8][2] = {{0, 1}, {0, 2}, {0, 4}, {2, 1}, {3, 1}, {1, 4}, {1, 8}, {1, 16}};
     const int tpbs[4] = {1, 2, 4, 8};
     mdx_status st_ = MDX_OK;
     for (const auto &lay : layouts) {
@@ -1892,7 +1910,7 @@ mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value)
         ctx->iter_scheme = (int)value;
         return MDX_OK;
     case MDX_TUNE_FORMAT:
-        if (value < 0 || value > 2) return fail(ctx, MDX_ERR_INVALID_ARG, "format is 0, 1 or 2");
+        if (value < 0 || value > 3) return fail(ctx, MDX_ERR_INVALID_ARG, "format is 0..3");
         if (!ctx->batched || !ctx->prepared)
             return fail(ctx, MDX_ERR_STATE, "needs a prepared batched context");
         GUARD_BEGIN
@@ -1913,6 +1931,11 @@ mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value)
             return fail(ctx, MDX_ERR_INVALID_ARG, "tiles per group must lie in [1, 2^20]");
         return install_groups(ctx, (int)value);
         GUARD_END
+    case MDX_TUNE_NONTEMPORAL:
+        if (value < -1 || value > 1) return fail(ctx, MDX_ERR_INVALID_ARG, "use -1, 0 or 1");
+        ctx->nt_mode = (int)value;
+        release_graphs(ctx);
+        return MDX_OK;
     case MDX_TUNE_GRAPH:
         if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "graph is 0 or 1");
         ctx->use_graph = value != 0;
@@ -2028,7 +2051,7 @@ mdx_status mdx_spmv(mdx_ctx *ctx, int32_t which, const double *x, double *y)
     SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
     Scalars *sc = ctx->dev<Scalars>(L.scalars);
     launch_spmv_dot(ctx->stream, ctx->tiling, P, ctx->dev<double>(off), p, q,
-                    ctx->dev<double>(L.partial) + 3 * kPartialCap, &sc->zero);
+                    ctx->dev<double>(L.partial) + 3 * kPartialCap, &sc->zero, nullptr, nullptr, false);
     HIPCHK(hipGetLastError());
     return copy_vec_out(ctx, q, y);
     GUARD_END

@@ -33,6 +33,9 @@ namespace mdx {
 
 namespace {
 
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ bool stopped(const BScalars &s) { return s.done != 0; }
 __device__ __forceinline__ bool idle(const BScalars &s) { return s.done != 0 || s.replace != 0; }
 
@@ -132,14 +135,34 @@ __global__ __launch_bounds__(256) void k_build_csr(int64_t n_rows, const int64_t
     }
 }
 
+// Per node, the three values the right-hand-side pass gathers, as one
+// 32-byte record: {Cm V + dt s, V, x0, 0} (x0 = 2 V - V_prev or V), so each
+// nonzero costs one gather instead of three scattered ones.
+__global__ __launch_bounds__(256) void k_b_gather_prep(int64_t n, StepParams sp,
+                                                       const double *__restrict__ V,
+                                                       const double *__restrict__ Vprev,
+                                                       const double *__restrict__ src,
+                                                       double4 *__restrict__ gv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = V[i];
+    double4 r;
+    r.x = sp.cm * v + sp.dt * src[i];
+    r.y = v;
+    r.z = sp.warm_start == 1 ? 2.0 * v - Vprev[i] : v;
+    r.w = 0.0;
+    gv[i] = r;
+}
+
 // ---------------------------------------------------------------------------
+template <bool NT>
 __global__ __launch_bounds__(256) void k_b_rhs_init(
     SegTiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
-    const float *__restrict__ dinv32, StepParams sp, const double *__restrict__ V,
-    const double *__restrict__ Vprev, const double *__restrict__ src, double *__restrict__ x,
-    double *__restrict__ b, float *__restrict__ r32, float *__restrict__ delta,
-    double *__restrict__ partial)
+    const float *__restrict__ dinv32, StepParams sp, const double4 *__restrict__ gv,
+    double *__restrict__ x, double *__restrict__ b, float *__restrict__ r32,
+    float *__restrict__ delta, double *__restrict__ partial)
 {
     const int g = logical_group(t.groups);
     const int4 gr = t.grp[g];
@@ -147,7 +170,6 @@ __global__ __launch_bounds__(256) void k_b_rhs_init(
     const double cK_old = (1.0 - sp.theta) * sp.dt;
     const double cM_new = sp.chi * sp.cm;
     const double cK_new = sp.theta * sp.dt;
-    const bool extrap = sp.warm_start == 1;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int tile = gr.y; tile < gr.z; ++tile) {
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
@@ -155,19 +177,17 @@ __global__ __launch_bounds__(256) void k_b_rhs_init(
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
         double mv = 0.0, kv = 0.0, mx = 0.0, kx = 0.0;
         for (int64_t e = beg; e < end; e += SLICE) {
-            const int32_t c = col[e];
-            const double m = Mv[e], kk = Kv[e];
-            const double vj = V[c];
-            const double x0j = extrap ? 2.0 * vj - Vprev[c] : vj;
-            mv += m * (sp.cm * vj + sp.dt * src[c]);
-            kv += kk * vj;
-            mx += m * x0j;
-            kx += kk * x0j;
+            const int32_t c = ld_stream<NT>(col + e);
+            const double m = ld_stream<NT>(Mv + e), kk = ld_stream<NT>(Kv + e);
+            const double4 gj = gv[c];
+            mv += m * gj.x;
+            kv += kk * gj.y;
+            mx += m * gj.z;
+            kx += kk * gj.z;
         }
         const double bi = sp.chi * mv - cK_old * kv;
         const double ri = bi - (cM_new * mx + cK_new * kx);
-        const double vi = V[row];
-        x[row] = extrap ? 2.0 * vi - Vprev[row] : vi;
+        x[row] = gv[row].z;
         b[row] = bi;
         const float rf = (float)ri;
         r32[row] = rf;
@@ -225,7 +245,7 @@ __global__ __launch_bounds__(256) void k_b_set_direction(SegTiling t,
 }
 
 // q = A p (FP32, lpr lanes per row), partial p.q (FP64 accumulation)
-template <int LPR>
+template <int LPR, bool NT>
 __global__ __launch_bounds__(256) void k_b_spmv(SegTiling t, const int64_t *__restrict__ sptr,
                                                 const int32_t *__restrict__ col,
                                                 const float *__restrict__ A,
@@ -248,7 +268,7 @@ __global__ __launch_bounds__(256) void k_b_spmv(SegTiling t, const int64_t *__re
             const int64_t beg = sptr[sl] + lane, end = sptr[sl + 1];
             float sum = 0.0f;
 #pragma unroll 4
-            for (int64_t e = beg; e < end; e += SLICE) sum += A[e] * p[col[e]];
+            for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(A + e) * p[ld_stream<NT>(col + e)];
             if constexpr (LPR >= 4) sum += __shfl_xor(sum, 2, 64);
             if constexpr (LPR >= 2) sum += __shfl_xor(sum, 1, 64);
             if ((lane & (LPR - 1)) == 0) {
@@ -260,7 +280,10 @@ __global__ __launch_bounds__(256) void k_b_spmv(SegTiling t, const int64_t *__re
     write_partials<1>(acc, partial, t.groups, g);
 }
 
-// q = A p, vector-load sliced layout: one lane per row, 4 entries per load
+// q = A p, vector-load sliced layout: one lane per row, 4 entries per load.
+// NT: the matrix streams are read with the non-temporal hint (each value is
+// read once per product), leaving the caches to the gathered vector.
+template <bool NT>
 __global__ __launch_bounds__(256) void k_b_spmv_v4(SegTiling t, const int64_t *__restrict__ sptr,
                                                    const int32_t *__restrict__ col,
                                                    const float *__restrict__ A,
@@ -281,12 +304,19 @@ __global__ __launch_bounds__(256) void k_b_spmv_v4(SegTiling t, const int64_t *_
         float sum = 0.0f;
 #pragma unroll 2
         for (int64_t e = beg; e < end; e += 4 * SLICE) {
-            const int4 c = *reinterpret_cast<const int4 *>(col + e);
-            const float4 a = *reinterpret_cast<const float4 *>(A + e);
-            sum += a.x * p[c.x];
-            sum += a.y * p[c.y];
-            sum += a.z * p[c.z];
-            sum += a.w * p[c.w];
+            i32x4 c;
+            f32x4 a;
+            if constexpr (NT) {
+                c = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(col + e));
+                a = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(A + e));
+            } else {
+                c = *reinterpret_cast<const i32x4 *>(col + e);
+                a = *reinterpret_cast<const f32x4 *>(A + e);
+            }
+            sum += a[0] * p[c[0]];
+            sum += a[1] * p[c[1]];
+            sum += a[2] * p[c[2]];
+            sum += a[3] * p[c[3]];
         }
         q[row] = sum;
         acc[0] += (double)p[row] * (double)sum;
@@ -296,7 +326,7 @@ __global__ __launch_bounds__(256) void k_b_spmv_v4(SegTiling t, const int64_t *_
 
 // q = A p with A in CSR: LPR lanes per row stride through the row's
 // contiguous entries, then a butterfly over the row's lanes
-template <int LPR>
+template <int LPR, bool NT>
 __global__ __launch_bounds__(256) void k_b_spmv_csr(SegTiling t, const int32_t *__restrict__ rptr,
                                                     const int32_t *__restrict__ col,
                                                     const float *__restrict__ A,
@@ -318,7 +348,8 @@ __global__ __launch_bounds__(256) void k_b_spmv_csr(SegTiling t, const int32_t *
             const int64_t row = (int64_t)tile * TILE + pass * (TILE / LPR) + w * H + lane / LPR;
             const int32_t end = rptr[row + 1];
             float sum = 0.0f;
-            for (int32_t e = rptr[row] + sub; e < end; e += LPR) sum += A[e] * p[col[e]];
+            for (int32_t e = rptr[row] + sub; e < end; e += LPR)
+                sum += ld_stream<NT>(A + e) * p[ld_stream<NT>(col + e)];
 #pragma unroll
             for (int off = LPR / 2; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
             if (sub == 0) {
@@ -434,6 +465,7 @@ __global__ __launch_bounds__(256) void k_b_flush(SegTiling t, double *__restrict
 }
 
 // r64 = b - A x64 (FP64 values), r32 = r64; partials r32.z32, |D^-1 r64|^2
+template <bool NT>
 __global__ __launch_bounds__(256) void k_b_true_residual(
     SegTiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
     const double *__restrict__ Av, const double *__restrict__ x, const double *__restrict__ b,
@@ -451,7 +483,7 @@ __global__ __launch_bounds__(256) void k_b_true_residual(
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
         double ax = 0.0;
 #pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) ax += Av[e] * x[col[e]];
+        for (int64_t e = beg; e < end; e += SLICE) ax += ld_stream<NT>(Av + e) * x[ld_stream<NT>(col + e)];
         const double ri = b[row] - ax;
         const float rf = (float)ri;
         r32[row] = rf;
@@ -544,12 +576,14 @@ void launch_relayout(hipStream_t s, int lpr, int64_t n_slices, const int64_t *sp
 
 void launch_b_rhs_init(hipStream_t s, const SegTiling &t, SellView P, const double *Mv,
                        const double *Kv, const double *dinv, const float *dinv32,
-                       const StepParams &sp, const double *V, const double *Vprev,
-                       const double *src, double *x, double *b, float *r32, float *delta,
-                       double *partial)
+                       const StepParams &sp, int64_t n_rows, const double *V, const double *Vprev,
+                       const double *src, double *gv, double *x, double *b, float *r32,
+                       float *delta, double *partial, bool nt)
 {
-    hipLaunchKernelGGL(k_b_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
-                       dinv, dinv32, sp, V, Vprev, src, x, b, r32, delta, partial);
+    hipLaunchKernelGGL(k_b_gather_prep, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, s,
+                       n_rows, sp, V, Vprev, src, (double4 *)gv);
+    MDX_LAUNCH_NT(nt, k_b_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
+                  dinv, dinv32, sp, (const double4 *)gv, x, b, r32, delta, partial);
 }
 
 void launch_b_init_finalize(hipStream_t s, const SegTiling &t, const double *partial,
@@ -586,21 +620,29 @@ void launch_b_spmv(hipStream_t s, const SegTiling &t, const IterMatrix &A, const
                    float *q32, double *part_pq, const BScalars *sc, hipEvent_t e0, hipEvent_t e1)
 {
     if (A.format == 2) {
-        spmv_launch(k_b_spmv_v4, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
+        spmv_launch(k_b_spmv_v4<false>, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
+    } else if (A.format == 3) {
+        spmv_launch(k_b_spmv_v4<true>, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
     } else if (A.format == 1) {
         if (A.lpr == 16)
-            spmv_launch(k_b_spmv_csr<16>, s, t, A.rptr, A, p32, q32, part_pq, sc, e0, e1);
+            spmv_launch(A.nt ? k_b_spmv_csr<16, true> : k_b_spmv_csr<16, false>, s, t, A.rptr, A, p32,
+                        q32, part_pq, sc, e0, e1);
         else if (A.lpr == 8)
-            spmv_launch(k_b_spmv_csr<8>, s, t, A.rptr, A, p32, q32, part_pq, sc, e0, e1);
+            spmv_launch(A.nt ? k_b_spmv_csr<8, true> : k_b_spmv_csr<8, false>, s, t, A.rptr, A, p32,
+                        q32, part_pq, sc, e0, e1);
         else
-            spmv_launch(k_b_spmv_csr<4>, s, t, A.rptr, A, p32, q32, part_pq, sc, e0, e1);
+            spmv_launch(A.nt ? k_b_spmv_csr<4, true> : k_b_spmv_csr<4, false>, s, t, A.rptr, A, p32,
+                        q32, part_pq, sc, e0, e1);
     } else {
         if (A.lpr == 4)
-            spmv_launch(k_b_spmv<4>, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
+            spmv_launch(A.nt ? k_b_spmv<4, true> : k_b_spmv<4, false>, s, t, A.sptr, A, p32, q32,
+                        part_pq, sc, e0, e1);
         else if (A.lpr == 2)
-            spmv_launch(k_b_spmv<2>, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
+            spmv_launch(A.nt ? k_b_spmv<2, true> : k_b_spmv<2, false>, s, t, A.sptr, A, p32, q32,
+                        part_pq, sc, e0, e1);
         else
-            spmv_launch(k_b_spmv<1>, s, t, A.sptr, A, p32, q32, part_pq, sc, e0, e1);
+            spmv_launch(A.nt ? k_b_spmv<1, true> : k_b_spmv<1, false>, s, t, A.sptr, A, p32, q32,
+                        part_pq, sc, e0, e1);
     }
 }
 
@@ -622,11 +664,11 @@ void launch_b_iteration(hipStream_t s, const SegTiling &t, const IterMatrix &A, 
 void launch_b_replacement(hipStream_t s, const SegTiling &t, SellView P, const BParams &bp,
                           const double *Av, double *x, float *delta, const double *b,
                           const double *dinv, const float *dinv32, float *r32, float *p32,
-                          double *partial, BScalars *sc)
+                          double *partial, BScalars *sc, bool nt)
 {
     hipLaunchKernelGGL(k_b_flush, dim3(t.groups), dim3(TILE), 0, s, t, x, delta, sc);
-    hipLaunchKernelGGL(k_b_true_residual, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av,
-                       x, b, dinv, dinv32, r32, partial, sc);
+    MDX_LAUNCH_NT(nt, k_b_true_residual, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av,
+                  x, b, dinv, dinv32, r32, partial, sc);
     hipLaunchKernelGGL(k_b_replace_finalize, dim3(t.n_inst), dim3(TILE), 0, s, t.groups, t.inst_grp,
                        partial, bp, sc);
     hipLaunchKernelGGL(k_b_redirect, dim3(t.groups), dim3(TILE), 0, s, t, dinv32, r32, p32, sc);

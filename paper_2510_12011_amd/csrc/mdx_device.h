@@ -15,6 +15,28 @@ static __device__ __forceinline__ int logical_group(int nb)
     return x * q + min(x, rem) + j;
 }
 
+// Load of a matrix stream (values, column indices).  With NT the load carries
+// the non-temporal hint: a matrix larger than the Infinity Cache is read once
+// per product and would only evict the gathered vectors; a smaller one is
+// better left to stay cache-resident across products (NT = false).  The host
+// picks NT per kernel from the size of the streams it reads.
+template <bool NT, class T>
+static __device__ __forceinline__ T ld_stream(const T *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+#define MDX_LAUNCH_NT(nt, kernel, ...)                                                       \
+    do {                                                                                     \
+        if (nt)                                                                              \
+            hipLaunchKernelGGL(kernel<true>, __VA_ARGS__);                                   \
+        else                                                                                 \
+            hipLaunchKernelGGL(kernel<false>, __VA_ARGS__);                                  \
+    } while (0)
+
 static __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll

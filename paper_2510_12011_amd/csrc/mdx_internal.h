@@ -116,12 +116,12 @@ void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const dou
                            const double *Kv, const double *dinv, const float *dinv32,
                            const StepParams &sp, const double *V, const double *Vprev,
                            const double *src, double *x, double *b, float *r32, float *delta,
-                           double *partial, const double *kdiag = nullptr, float *kvp = nullptr);
+                           double *partial, const double *kdiag, float *kvp, bool nt);
 void launch_set_direction32(hipStream_t s, int64_t n, const float *dinv32, const float *r32,
                             float *p32, const Scalars *sc);
 void launch_spmv32_dot(hipStream_t s, const Tiling &t, SellView P, const float *A32,
                        const float *p, float *q, double *partial, Scalars *sc,
-                       hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                       hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
 void launch_cg_update32(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
                         const float *dinv32, const float *p, const float *q, float *delta,
                         float *r, double *partial_rz, Scalars *sc);
@@ -131,7 +131,8 @@ void launch_cg_direction32(hipStream_t s, const Tiling &t, int k, int rr, int ma
 // flush, true residual, finalize, redirect (all no-ops unless a replacement is pending)
 void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const double *Av,
                         double *x, float *delta, const double *b, const double *dinv,
-                        const float *dinv32, float *r32, float *p32, double *partial, Scalars *sc);
+                        const float *dinv32, float *r32, float *p32, double *partial, Scalars *sc,
+                        bool nt);
 
 // ---- learned warm start network (mdx_mlp.hip) ------------------------------
 int mlp_nparams();
@@ -162,7 +163,8 @@ void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double
                         const double *Kv, const double *kdiag, const double *dinv,
                         const StepParams &sp, float out_scale, const double *V,
                         const double *src, const float *y, double *b, double *x, double *r_mlp,
-                        double *r_prev, float *kvp, int fp32_iter, double *part4, double *part1);
+                        double *r_prev, float *kvp, int fp32_iter, double *part4, double *part1,
+                        bool nt);
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
                              int rel_mode, Scalars *sc);
 void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
@@ -230,6 +232,7 @@ void launch_relayout(hipStream_t s, int lpr, int64_t n_slices, const int64_t *sp
 struct IterMatrix {
     int format;
     int lpr;
+    bool nt;            // formats 0, 1: matrix streams read with the non-temporal hint
     const int64_t *sptr;
     const int32_t *rptr;
     const int32_t *col;
@@ -244,11 +247,12 @@ void launch_relayout_v4(hipStream_t s, int64_t n_slices, const int64_t *sptr_new
 void launch_build_csr(hipStream_t s, int64_t n_rows, SellView base, const float *A32,
                       const int32_t *rptr, int32_t *col_csr, float *val_csr);
 
+// gv: scratch of 4 doubles per row (the gathered per-node values)
 void launch_b_rhs_init(hipStream_t s, const SegTiling &t, SellView P, const double *Mv,
                        const double *Kv, const double *dinv, const float *dinv32,
-                       const StepParams &sp, const double *V, const double *Vprev,
-                       const double *src, double *x, double *b, float *r32, float *delta,
-                       double *partial);
+                       const StepParams &sp, int64_t n_rows, const double *V, const double *Vprev,
+                       const double *src, double *gv, double *x, double *b, float *r32,
+                       float *delta, double *partial, bool nt);
 void launch_b_init_finalize(hipStream_t s, const SegTiling &t, const double *partial,
                             const BParams &bp, BScalars *sc);
 void launch_b_set_direction(hipStream_t s, const SegTiling &t, const float *dinv32,
@@ -263,7 +267,7 @@ void launch_b_iteration(hipStream_t s, const SegTiling &t, const IterMatrix &A,
 void launch_b_replacement(hipStream_t s, const SegTiling &t, SellView P, const BParams &bp,
                           const double *Av, double *x, float *delta, const double *b,
                           const double *dinv, const float *dinv32, float *r32, float *p32,
-                          double *partial, BScalars *sc);
+                          double *partial, BScalars *sc, bool nt);
 // the SpMV of the iteration alone (timing by the autotuner): q = A p, partial p.q
 void launch_b_spmv(hipStream_t s, const SegTiling &t, const IterMatrix &A,
                    const float *p32, float *q32, double *part_pq, const BScalars *sc,
@@ -276,21 +280,21 @@ void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double am
 void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                      const double *Kv, const double *dinv, const StepParams &sp,
                      const double *V, const double *Vprev, const double *src, double *x,
-                     double *r, double *b, double *partial, const double *kdiag = nullptr,
-                     float *kvp = nullptr);
+                     double *r, double *b, double *partial, const double *kdiag, float *kvp,
+                     bool nt);
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
                           Scalars *sc);
 // q = A p with partial p.q (no convergence logic; `done` non-zero skips it).
 // ev_start/ev_stop: optional events recorded around the dispatch
 void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *Av,
                      const double *p, double *q, double *partial, const int32_t *done,
-                     hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                     hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
 // PCG iteration k, first half (test of ||z_k||, beta_k, q = A p_k, partial p_k.q)
 void launch_cg_direction_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
                               const double *Av, const double *dinv, const double *r,
                               const double *p_prev, double *p_cur, double *q,
                               const double *partial_rz, double *partial_pq, Scalars *sc,
-                              hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                              hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
 // three-kernel scheme: direction update (test, beta, p = z + beta p) and p_0 = z_0
 void launch_cg_direction(hipStream_t s, const Tiling &t, int k, const double *partial_rz,
                          const double *dinv, const double *r, double *p, Scalars *sc);

@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256) void k_stim_add(int64_t n_idx, const int32_t *
     if (j < n_idx) istim[idx[j]] += amp;   // node lists are duplicate-free
 }
 
+template <bool NT>
 __global__ __launch_bounds__(256) void k_rhs_init(
     Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
@@ -87,8 +88,8 @@ __global__ __launch_bounds__(256) void k_rhs_init(
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
         double mv = 0.0, kv = 0.0, mx = 0.0, kx = 0.0;
         for (int64_t e = beg; e < end; e += SLICE) {
-            const int32_t c = col[e];
-            const double m = Mv[e], kk = Kv[e];
+            const int32_t c = ld_stream<NT>(col + e);
+            const double m = ld_stream<NT>(Mv + e), kk = ld_stream<NT>(Kv + e);
             const double vj = V[c];
             const double x0j = extrap ? 2.0 * vj - Vprev[c] : vj;
             mv += m * (sp.cm * vj + sp.dt * src[c]);
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(256) void k_init_finalize(int groups, const double 
     }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__restrict__ slice_ptr,
                                                   const int32_t *__restrict__ col,
                                                   const double *__restrict__ Av,
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__res
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
         double sum = 0.0;
 #pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) sum += Av[e] * p[col[e]];
+        for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(Av + e) * p[ld_stream<NT>(col + e)];
         q[row] = sum;
         acc[0] += p[row] * sum;
     }
@@ -169,6 +171,7 @@ __global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__res
 // gathered column, so no separate direction pass is needed; own rows store
 // p_k (double-buffered against p_{k-1}) and a partial of p_k . q.
 // k == max_iter only tests.
+template <bool NT>
 __global__ __launch_bounds__(256) void k_cg_direction_spmv(
     Tiling t, int k, int max_iter, const int64_t *__restrict__ slice_ptr,
     const int32_t *__restrict__ col, const double *__restrict__ Av,
@@ -218,14 +221,14 @@ __global__ __launch_bounds__(256) void k_cg_direction_spmv(
         if (k == 0) {
 #pragma unroll 4
             for (int64_t e = beg; e < end; e += SLICE) {
-                const int32_t c = col[e];
-                sum += Av[e] * (dinv[c] * r[c]);
+                const int32_t c = ld_stream<NT>(col + e);
+                sum += ld_stream<NT>(Av + e) * (dinv[c] * r[c]);
             }
         } else {
 #pragma unroll 4
             for (int64_t e = beg; e < end; e += SLICE) {
-                const int32_t c = col[e];
-                sum += Av[e] * (dinv[c] * r[c] + beta * p_prev[c]);
+                const int32_t c = ld_stream<NT>(col + e);
+                sum += ld_stream<NT>(Av + e) * (dinv[c] * r[c] + beta * p_prev[c]);
             }
         }
         const double pi = k == 0 ? dinv[row] * r[row] : dinv[row] * r[row] + beta * p_prev[row];
@@ -358,10 +361,10 @@ void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double am
 void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                      const double *Kv, const double *dinv, const StepParams &sp, const double *V,
                      const double *Vprev, const double *src, double *x, double *r, double *b,
-                     double *partial, const double *kdiag, float *kvp)
+                     double *partial, const double *kdiag, float *kvp, bool nt)
 {
-    hipLaunchKernelGGL(k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
-                       dinv, sp, V, Vprev, src, x, r, b, partial, kdiag, kvp);
+    MDX_LAUNCH_NT(nt, k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
+                  dinv, sp, V, Vprev, src, x, r, b, partial, kdiag, kvp);
 }
 
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
@@ -372,30 +375,31 @@ void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial,
 
 void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *Av, const double *p,
                      double *q, double *partial, const int32_t *done, hipEvent_t ev_start,
-                     hipEvent_t ev_stop)
+                     hipEvent_t ev_stop, bool nt)
 {
+    auto kern = nt ? &k_spmv_dot<true> : &k_spmv_dot<false>;
     if (ev_start)
-        hipExtLaunchKernelGGL(k_spmv_dot, dim3(t.groups), dim3(TILE), 0, s, ev_start, ev_stop, 0, t,
+        hipExtLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, ev_start, ev_stop, 0, t,
                               P.slice_ptr, P.col, Av, p, q, partial, done);
     else
-        hipLaunchKernelGGL(k_spmv_dot, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av,
-                           p, q, partial, done);
+        hipLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av, p, q,
+                           partial, done);
 }
 
 void launch_cg_direction_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
                               const double *Av, const double *dinv, const double *r,
                               const double *p_prev, double *p_cur, double *q,
                               const double *partial_rz, double *partial_pq, Scalars *sc,
-                              hipEvent_t ev_start, hipEvent_t ev_stop)
+                              hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
 {
+    auto kern = nt ? &k_cg_direction_spmv<true> : &k_cg_direction_spmv<false>;
     if (ev_start)
-        hipExtLaunchKernelGGL(k_cg_direction_spmv, dim3(t.groups), dim3(TILE), 0, s, ev_start,
-                              ev_stop, 0, t, k, max_iter, P.slice_ptr, P.col, Av, dinv, r, p_prev,
-                              p_cur, q, partial_rz, partial_pq, sc);
+        hipExtLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, ev_start, ev_stop, 0, t, k,
+                              max_iter, P.slice_ptr, P.col, Av, dinv, r, p_prev, p_cur, q,
+                              partial_rz, partial_pq, sc);
     else
-        hipLaunchKernelGGL(k_cg_direction_spmv, dim3(t.groups), dim3(TILE), 0, s, t, k, max_iter,
-                           P.slice_ptr, P.col, Av, dinv, r, p_prev, p_cur, q, partial_rz,
-                           partial_pq, sc);
+        hipLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, t, k, max_iter, P.slice_ptr,
+                           P.col, Av, dinv, r, p_prev, p_cur, q, partial_rz, partial_pq, sc);
 }
 
 void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,

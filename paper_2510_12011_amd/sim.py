@@ -163,12 +163,12 @@ class Simulation:
         return {f: getattr(s, f) for f, _ in L.Stats._fields_}
 
     def set_tuning(self, max_groups=None, iter_scheme=None, lanes_per_row=None,
-                   tiles_per_group=None, graph=None, fmt=None):
-        """fmt: 'sell', 'csr' or 'sell4' (batched iteration SpMV storage),
-        set before lanes_per_row."""
-        f = None if fmt is None else {"sell": 0, "csr": 1, "sell4": 2}[fmt]
+                   tiles_per_group=None, graph=None, fmt=None, nontemporal=None):
+        """fmt: 'sell', 'csr', 'sell4' or 'sell4nt' (batched iteration SpMV
+        storage), set before lanes_per_row."""
+        f = None if fmt is None else {"sell": 0, "csr": 1, "sell4": 2, "sell4nt": 3}[fmt]
         for key, v in ((L.MDX_TUNE_MAX_GROUPS, max_groups), (L.MDX_TUNE_ITER_SCHEME, iter_scheme),
-                       (L.MDX_TUNE_FORMAT, f),
+                       (L.MDX_TUNE_FORMAT, f), (L.MDX_TUNE_NONTEMPORAL, nontemporal),
                        (L.MDX_TUNE_LANES_PER_ROW, lanes_per_row),
                        (L.MDX_TUNE_TILES_PER_GROUP, tiles_per_group),
                        (L.MDX_TUNE_GRAPH, None if graph is None else int(bool(graph)))):
@@ -186,7 +186,7 @@ class Simulation:
         """Batched context: time the SpMV variants, install the fastest."""
         r = L.TuneReport()
         self._check(L.lib().mdx_autotune(self._h, int(reps), C.byref(r)))
-        fmts = ("sell", "csr", "sell4")
+        fmts = ("sell", "csr", "sell4", "sell4nt")
         cands = [(fmts[r.cand_format[i]], r.cand_lanes_per_row[i], r.cand_tiles_per_group[i],
                   r.cand_seconds[i]) for i in range(r.n_candidates)]
         return dict(fmt=fmts[r.format], lanes_per_row=r.lanes_per_row,
