@@ -125,7 +125,7 @@ def learned_workload(args):
         Ds.append(dV[keep])
         trainer = s
     X, dV = torch.cat(Xs), torch.cat(Ds)
-    params, norm, hist = learn.fit(trainer, X, dV, epochs=6, batch=8192, lr=2e-3)
+    params, norm, hist = learn.fit(trainer, X, dV, epochs=args.train_epochs, batch=8192, lr=2e-3)
     del Xs, Ds, X, dV
     print(f"[bench] shell {n} nodes; trained on {args.train_sites} sites x {args.train_steps} "
           f"steps, loss {hist[0]:.4f} -> {hist[-1]:.4f}, setup {time.perf_counter() - t0:.1f} s",
@@ -322,8 +322,9 @@ def main():
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB device buffer 3 times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
-    ap.add_argument("--train-sites", type=int, default=4, help="learned workload")
+    ap.add_argument("--train-sites", type=int, default=8, help="learned workload")
     ap.add_argument("--train-steps", type=int, default=2000, help="learned workload")
+    ap.add_argument("--train-epochs", type=int, default=10, help="learned workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method runs one simulation per GPU and "

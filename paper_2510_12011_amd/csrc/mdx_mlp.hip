@@ -235,6 +235,10 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
     for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; tile < n_tiles;
          tile += waves) {
+        // weights are re-read from LDS for every tile: held in registers
+        // across tiles they would take ~200 VGPRs and leave one wavefront
+        // per SIMD to hide the latency of the layer chain
+        asm volatile("" ::: "memory");
         const int64_t node = tile * 32 + (lane & 31);
         float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
         if (half == 0 && node < n) x = reinterpret_cast<const float4 *>(X)[node];
