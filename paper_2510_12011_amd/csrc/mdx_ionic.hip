@@ -47,6 +47,15 @@ __device__ __forceinline__ float rush_larsen(float y, float y_inf, float tau, fl
 {
     return y - (y_inf - y) * expm1f(-dt / tau);
 }
+// the same step given the rate 1/tau
+__device__ __forceinline__ double rush_larsen_rate(double y, double y_inf, double rate, double dt)
+{
+    return y_inf - (y_inf - y) * exp(-dt * rate);
+}
+__device__ __forceinline__ float rush_larsen_rate(float y, float y_inf, float rate, float dt)
+{
+    return y - (y_inf - y) * expm1f(-dt * rate);
+}
 
 // ---------------------------------------------------------------------------
 // Mitchell-Schaeffer: params tau_in, tau_out, tau_open, tau_close, u_gate,
@@ -104,17 +113,28 @@ struct VOnly {
 __device__ __forceinline__ VOnly v_only(double V)
 {
     VOnly o;
-    double w = 2.0 * (V - 15.0) / RTONF;
+    double w = (V - 15.0) * (2.0 / RTONF);
     o.ical_ew = exp(w);
     o.ical_drive = 2.0 * Far * (w == 0.0 ? 1.0 : w / expm1(w));
-    double phi = V / RTONF;
+    double phi = V * (1.0 / RTONF);
     o.nak_den = 1.0 + 0.1245 * exp(-0.1 * phi) + 0.0353 * exp(-phi);
     o.ncx_up = exp(NCX_GAMMA * phi);
     o.ncx_down = exp((NCX_GAMMA - 1.0) * phi);
     o.ncx_sat = 1.0 + K_SAT * o.ncx_down;
-    o.ipk = 1.0 / (1.0 + exp((25.0 - V) / 5.98));
+    o.ipk = 1.0 / (1.0 + exp((25.0 - V) * (1.0 / 5.98)));
     return o;
 }
+
+// Products of the gating variables that enter the currents, formed in FP64
+// from the stored gates: the currents need these five numbers, not the
+// twelve gates, which keeps the live set of a thread small.
+struct GateProducts {
+    double to;    // r s           (transient outward)
+    double kr;    // xr1 xr2       (rapid delayed rectifier)
+    double ks;    // xs^2          (slow delayed rectifier)
+    double na;    // m^3 h j       (fast sodium)
+    double cal;   // d f f2 fCass  (L-type calcium)
+};
 
 struct Currents {
     double iK1, ito, iKr, iKs, iCaL, iNaK, iNa, ibNa, iNaCa, ibCa, ipK, ipCa;
@@ -124,129 +144,184 @@ struct Currents {
     }
 };
 
+// currents at V and the concentration-type states c[0..5] (Ki Nai Cai CaSR
+// CaSS Rbar) and gates summarised by gp
 __device__ __forceinline__ Currents tt_currents(const IonicParams &P, double V, const VOnly &vo,
-                                                const double *y)
+                                                const double *c, const GateProducts &gp)
 {
     const double gNa = P.v[0], gK1 = P.v[1], gto = P.v[2], gKr = P.v[3], gKs = P.v[4];
     const double gCaL = P.v[5], gbNa = P.v[6], gbCa = P.v[7], gpCa = P.v[8], gpK = P.v[9];
     const double pNaK = P.v[10], kNaCa = P.v[11];
-    const double ki = y[KI], nai = y[NAI], cai = y[CAI];
+    const double ki = c[KI], nai = c[NAI], cai = c[CAI];
     const double e_k = RTONF * log(K_O / ki);
     const double e_na = RTONF * log(NA_O / nai);
     const double e_ks = RTONF * log((K_O + P_KNA * NA_O) / (ki + P_KNA * nai));
     const double e_ca = 0.5 * RTONF * log(CA_O / cai);
     const double ko_scale = sqrt(K_O / 5.4);
-    Currents c;
-    // inward rectifier: steady-state rectification a/(a+b)
-    double a_k1 = 0.1 / (1.0 + exp(0.06 * (V - e_k - 200.0)));
-    double b_k1 = (3.0 * exp(0.0002 * (V - e_k + 100.0)) + exp(0.1 * (V - e_k - 10.0)))
-                / (1.0 + exp(-0.5 * (V - e_k)));
-    c.iK1 = gK1 * ko_scale * (a_k1 / (a_k1 + b_k1)) * (V - e_k);
-    c.ito = gto * y[RG] * y[SG] * (V - e_k);
-    c.iKr = gKr * ko_scale * y[XR1] * y[XR2] * (V - e_k);
-    c.iKs = gKs * y[XS] * y[XS] * (V - e_ks);
-    double m = y[MG];
-    c.iNa = gNa * m * m * m * y[HG] * y[JG] * (V - e_na);
-    c.ibNa = gbNa * (V - e_na);
-    c.iCaL = gCaL * y[DG] * y[FG] * y[F2G] * y[FCASS] * vo.ical_drive
-           * (0.25 * y[CASS] * vo.ical_ew - CA_O);
-    c.ibCa = gbCa * (V - e_ca);
-    c.iNaK = pNaK * (K_O / (K_O + KM_K)) * (nai / (nai + KM_NA)) / vo.nak_den;
+    Currents cu;
+    // inward rectifier: steady-state rectification a/(a+b) with
+    // a = 0.1/(1+e1), b = q/(1+e2), formed as 0.1(1+e2) / (0.1(1+e2) + q(1+e1))
+    const double a_k1 = 0.1 * (1.0 + exp(-0.5 * (V - e_k)));
+    const double b_k1 = (3.0 * exp(0.0002 * (V - e_k + 100.0)) + exp(0.1 * (V - e_k - 10.0)))
+                      * (1.0 + exp(0.06 * (V - e_k - 200.0)));
+    cu.iK1 = gK1 * ko_scale * (a_k1 / (a_k1 + b_k1)) * (V - e_k);
+    cu.ito = gto * gp.to * (V - e_k);
+    cu.iKr = gKr * ko_scale * gp.kr * (V - e_k);
+    cu.iKs = gKs * gp.ks * (V - e_ks);
+    cu.iNa = gNa * gp.na * (V - e_na);
+    cu.ibNa = gbNa * (V - e_na);
+    cu.iCaL = gCaL * gp.cal * vo.ical_drive * (0.25 * c[CASS] * vo.ical_ew - CA_O);
+    cu.ibCa = gbCa * (V - e_ca);
+    cu.iNaK = pNaK * (K_O / (K_O + KM_K)) * nai / ((nai + KM_NA) * vo.nak_den);
     constexpr double nao3 = NA_O * NA_O * NA_O;
     constexpr double ncx_den = (KM_NAI * KM_NAI * KM_NAI + nao3) * (KM_CA + CA_O);
-    c.iNaCa = kNaCa * (vo.ncx_up * nai * nai * nai * CA_O - vo.ncx_down * nao3 * cai * NCX_ALPHA)
-            / (ncx_den * vo.ncx_sat);
-    c.ipCa = gpCa * cai / (K_PCA + cai);
-    c.ipK = gpK * vo.ipk * (V - e_k);
-    return c;
+    cu.iNaCa = kNaCa * (vo.ncx_up * nai * nai * nai * CA_O - vo.ncx_down * nao3 * cai * NCX_ALPHA)
+             / (ncx_den * vo.ncx_sat);
+    cu.ipCa = gpCa * cai / (K_PCA + cai);
+    cu.ipK = gpK * vo.ipk * (V - e_k);
+    return cu;
 }
 
 __device__ __forceinline__ double sq(double x) { return x * x; }
 
-
-
 // Gating variables of the model advanced by Rush-Larsen at V^k, in precision
-// T.  g[0..11] = xr1 xr2 xs m h j d f f2 fCass s r; cass is CaSS^k.
+// T, streamed one at a time: gate s (xr1 xr2 xs m h j d f f2 fCass s r) is
+// read from g[s * ld], advanced and written back at once.  po and pn receive
+// the gate products before and after the step; cass is CaSS^k.
 template <typename T>
-__device__ __forceinline__ void tt_gates(T V, T dt, T cass, T *g)
+__device__ __forceinline__ void tt_gates(T V, T dt, T cass, T *__restrict__ g, int64_t ld,
+                                         GateProducts &po, GateProducts &pn)
 {
     const T one = T(1);
     auto sqt = [](T x) { return x * x; };
-    // fast sodium m, h, j
-    T m_inf = one / sqt(one + ex((T(-56.86) - V) / T(9.03)));
-    T tau_m = (one / (one + ex((T(-60.0) - V) / T(5.0))))
-            * (T(0.1) / (one + ex((V + T(35.0)) / T(5.0))) + T(0.1) / (one + ex((V - T(50.0)) / T(200.0))));
-    T h_inf = one / sqt(one + ex((V + T(71.55)) / T(7.43)));
-    T alpha_h, beta_h, alpha_j, beta_j;
-    if (V < T(-40.0)) {
-        alpha_h = T(0.057) * ex(-(V + T(80.0)) / T(6.8));
-        beta_h = T(2.7) * ex(T(0.079) * V) + T(3.1e5) * ex(T(0.3485) * V);
-        alpha_j = (T(-25428.0) * ex(T(0.2444) * V) - T(6.948e-6) * ex(T(-0.04391) * V)) * (V + T(37.78))
-                / (one + ex(T(0.311) * (V + T(79.23))));
-        beta_j = T(0.02424) * ex(T(-0.01052) * V) / (one + ex(T(-0.1378) * (V + T(40.14))));
-    } else {
-        alpha_h = T(0.0);
-        beta_h = T(0.77) / (T(0.13) * (one + ex(-(V + T(10.66)) / T(11.1))));
-        alpha_j = T(0.0);
-        beta_j = T(0.6) * ex(T(0.057) * V) / (one + ex(T(-0.1) * (V + T(32.0))));
-    }
-    // rapid and slow delayed rectifiers
-    T xr1_inf = one / (one + ex((T(-26.0) - V) / T(7.0)));
-    T tau_xr1 = (T(450.0) / (one + ex((T(-45.0) - V) / T(10.0)))) * (T(6.0) / (one + ex((V + T(30.0)) / T(11.5))));
-    T xr2_inf = one / (one + ex((V + T(88.0)) / T(24.0)));
-    T tau_xr2 = (T(3.0) / (one + ex((T(-60.0) - V) / T(20.0)))) * (T(1.12) / (one + ex((V - T(60.0)) / T(20.0))));
-    T xs_inf = one / (one + ex((T(-5.0) - V) / T(14.0)));
-    T tau_xs = (T(1400.0) / sqr_root(one + ex((T(5.0) - V) / T(6.0)))) * (one / (one + ex((V - T(35.0)) / T(15.0))))
-             + T(80.0);
-    // transient outward r, s (endocardial s)
-    T r_inf = one / (one + ex((T(20.0) - V) / T(6.0)));
-    T tau_r = T(9.5) * ex(-sqt(V + T(40.0)) / T(1800.0)) + T(0.8);
-    T s_inf = one / (one + ex((V + T(28.0)) / T(5.0)));
-    T tau_s = T(1000.0) * ex(-sqt(V + T(67.0)) / T(1000.0)) + T(8.0);
-    // L-type calcium d, f, f2, fCass
-    T d_inf = one / (one + ex((T(-8.0) - V) / T(7.5)));
-    T tau_d = (T(1.4) / (one + ex((T(-35.0) - V) / T(13.0))) + T(0.25)) * (T(1.4) / (one + ex((V + T(5.0)) / T(5.0))))
-            + one / (one + ex((T(50.0) - V) / T(20.0)));
-    T f_inf = one / (one + ex((V + T(20.0)) / T(7.0)));
-    T tau_f = T(1102.5) * ex(-sqt(V + T(27.0)) / T(225.0)) + T(200.0) / (one + ex((T(13.0) - V) / T(10.0)))
-            + T(180.0) / (one + ex((V + T(30.0)) / T(10.0))) + T(20.0);
-    T f2_inf = T(0.67) / (one + ex((V + T(35.0)) / T(7.0))) + T(0.33);
-    T tau_f2 = T(562.0) * ex(-sqt(V + T(27.0)) / T(240.0)) + T(31.0) / (one + ex((T(25.0) - V) / T(10.0)))
-             + T(80.0) / (one + ex((V + T(30.0)) / T(10.0)));
-    T cass_ratio2 = sqt(cass / T(0.05));
-    T fcass_inf = T(0.6) / (one + cass_ratio2) + T(0.4);
-    T tau_fcass = T(80.0) / (one + cass_ratio2) + T(2.0);
+    // advance gate s towards y_inf with time constant tau; old value to y0
+    auto adv = [&](int s, T y_inf, T tau, double &y0) -> double {
+        const T y = g[s * ld];
+        const T y1 = rush_larsen(y, y_inf, tau, dt);
+        g[s * ld] = y1;
+        y0 = (double)y;
+        return (double)y1;
+    };
+    auto adv_rate = [&](int s, T y_inf, T rate, double &y0) -> double {
+        const T y = g[s * ld];
+        const T y1 = rush_larsen_rate(y, y_inf, rate, dt);
+        g[s * ld] = y1;
+        y0 = (double)y;
+        return (double)y1;
+    };
+    double o0, o1, o2, n0, n1, n2;
 
-    g[0] = rush_larsen(g[0], xr1_inf, tau_xr1, dt);
-    g[1] = rush_larsen(g[1], xr2_inf, tau_xr2, dt);
-    g[2] = rush_larsen(g[2], xs_inf, tau_xs, dt);
-    g[3] = rush_larsen(g[3], m_inf, tau_m, dt);
-    g[4] = rush_larsen(g[4], h_inf, one / (alpha_h + beta_h), dt);
-    g[5] = rush_larsen(g[5], h_inf, one / (alpha_j + beta_j), dt);
-    g[6] = rush_larsen(g[6], d_inf, tau_d, dt);
-    g[7] = rush_larsen(g[7], f_inf, tau_f, dt);
-    g[8] = rush_larsen(g[8], f2_inf, tau_f2, dt);
-    g[9] = rush_larsen(g[9], fcass_inf, tau_fcass, dt);
-    g[10] = rush_larsen(g[10], s_inf, tau_s, dt);
-    g[11] = rush_larsen(g[11], r_inf, tau_r, dt);
+    // rapid delayed rectifier xr1, xr2
+    {
+        T inf = one / (one + ex((T(-26.0) - V) * T(1.0 / 7.0)));
+        // 450/(1+a) * 6/(1+b) with one division
+        T tau = T(450.0 * 6.0) / ((one + ex((T(-45.0) - V) * T(1.0 / 10.0))) * (one + ex((V + T(30.0)) * T(1.0 / 11.5))));
+        n0 = adv(0, inf, tau, o0);
+    }
+    {
+        T inf = one / (one + ex((V + T(88.0)) * T(1.0 / 24.0)));
+        T tau = T(3.0 * 1.12) / ((one + ex((T(-60.0) - V) * T(1.0 / 20.0))) * (one + ex((V - T(60.0)) * T(1.0 / 20.0))));
+        n1 = adv(1, inf, tau, o1);
+    }
+    po.kr = o0 * o1;
+    pn.kr = n0 * n1;
+    // slow delayed rectifier xs
+    {
+        T inf = one / (one + ex((T(-5.0) - V) * T(1.0 / 14.0)));
+        T tau = T(1400.0) / (sqr_root(one + ex((T(5.0) - V) * T(1.0 / 6.0))) * (one + ex((V - T(35.0)) * T(1.0 / 15.0))))
+              + T(80.0);
+        n0 = adv(2, inf, tau, o0);
+    }
+    po.ks = o0 * o0;
+    pn.ks = n0 * n0;
+    // fast sodium m, h, j
+    {
+        T inf = one / sqt(one + ex((T(-56.86) - V) * T(1.0 / 9.03)));
+        T tau = (one / (one + ex((T(-60.0) - V) * T(1.0 / 5.0))))
+              * (T(0.1) / (one + ex((V + T(35.0)) * T(1.0 / 5.0))) + T(0.1) / (one + ex((V - T(50.0)) * T(1.0 / 200.0))));
+        n0 = adv(3, inf, tau, o0);
+    }
+    {
+        T h_inf = one / sqt(one + ex((V + T(71.55)) * T(1.0 / 7.43)));
+        T alpha_h, beta_h, alpha_j, beta_j;
+        if (V < T(-40.0)) {
+            alpha_h = T(0.057) * ex(-(V + T(80.0)) * T(1.0 / 6.8));
+            beta_h = T(2.7) * ex(T(0.079) * V) + T(3.1e5) * ex(T(0.3485) * V);
+            alpha_j = (T(-25428.0) * ex(T(0.2444) * V) - T(6.948e-6) * ex(T(-0.04391) * V)) * (V + T(37.78))
+                    / (one + ex(T(0.311) * (V + T(79.23))));
+            beta_j = T(0.02424) * ex(T(-0.01052) * V) / (one + ex(T(-0.1378) * (V + T(40.14))));
+        } else {
+            alpha_h = T(0.0);
+            beta_h = T(0.77 / 0.13) / (one + ex(-(V + T(10.66)) * T(1.0 / 11.1)));
+            alpha_j = T(0.0);
+            beta_j = T(0.6) * ex(T(0.057) * V) / (one + ex(T(-0.1) * (V + T(32.0))));
+        }
+        n1 = adv_rate(4, h_inf, alpha_h + beta_h, o1);
+        n2 = adv_rate(5, h_inf, alpha_j + beta_j, o2);
+    }
+    po.na = o0 * o0 * o0 * o1 * o2;
+    pn.na = n0 * n0 * n0 * n1 * n2;
+    // L-type calcium d, f, f2, fCass
+    {
+        T inf = one / (one + ex((T(-8.0) - V) * T(1.0 / 7.5)));
+        T tau = (T(1.4) / (one + ex((T(-35.0) - V) * T(1.0 / 13.0))) + T(0.25)) * (T(1.4) / (one + ex((V + T(5.0)) * T(1.0 / 5.0))))
+              + one / (one + ex((T(50.0) - V) * T(1.0 / 20.0)));
+        n0 = adv(6, inf, tau, o0);
+    }
+    {
+        T inf = one / (one + ex((V + T(20.0)) * T(1.0 / 7.0)));
+        T tau = T(1102.5) * ex(-sqt(V + T(27.0)) * T(1.0 / 225.0)) + T(200.0) / (one + ex((T(13.0) - V) * T(1.0 / 10.0)))
+              + T(180.0) / (one + ex((V + T(30.0)) * T(1.0 / 10.0))) + T(20.0);
+        n1 = adv(7, inf, tau, o1);
+    }
+    po.cal = o0 * o1;
+    pn.cal = n0 * n1;
+    {
+        T inf = T(0.67) / (one + ex((V + T(35.0)) * T(1.0 / 7.0))) + T(0.33);
+        T tau = T(562.0) * ex(-sqt(V + T(27.0)) * T(1.0 / 240.0)) + T(31.0) / (one + ex((T(25.0) - V) * T(1.0 / 10.0)))
+              + T(80.0) / (one + ex((V + T(30.0)) * T(1.0 / 10.0)));
+        n0 = adv(8, inf, tau, o0);
+    }
+    {
+        T ratio2 = sqt(cass * T(1.0 / 0.05));
+        T inf = T(0.6) / (one + ratio2) + T(0.4);
+        T tau = T(80.0) / (one + ratio2) + T(2.0);
+        n1 = adv(9, inf, tau, o1);
+    }
+    po.cal = po.cal * o0 * o1;
+    pn.cal = pn.cal * n0 * n1;
+    // transient outward s (endocardial), r
+    {
+        T inf = one / (one + ex((V + T(28.0)) * T(1.0 / 5.0)));
+        T tau = T(1000.0) * ex(-sqt(V + T(67.0)) * T(1.0 / 1000.0)) + T(8.0);
+        n0 = adv(10, inf, tau, o0);
+    }
+    {
+        T inf = one / (one + ex((T(20.0) - V) * T(1.0 / 6.0)));
+        T tau = T(9.5) * ex(-sqt(V + T(40.0)) * T(1.0 / 1800.0)) + T(0.8);
+        n1 = adv(11, inf, tau, o1);
+    }
+    po.to = o1 * o0;
+    pn.to = n1 * n0;
 }
 
 // One step of the model at one node: concentration-type states c[0..5]
-// (Ki Nai Cai CaSR CaSS Rbar) by forward Euler in FP64, gates g[0..11] by
-// Rush-Larsen in precision G; returns I_ion(V^k, u^{k+1}) / Cm in FP64.
+// (Ki Nai Cai CaSR CaSS Rbar) by forward Euler in FP64, gates (g[s * ld],
+// s = 0..11) by Rush-Larsen in precision G; returns I_ion(V^k, u^{k+1}) / Cm
+// in FP64.
 template <typename G>
-__device__ double tt_point(const IonicParams &P, double dt, double V, double *c, G *g)
+__device__ double tt_point(const IonicParams &P, double dt, double V, double *c,
+                           G *__restrict__ g, int64_t ld)
 {
-    double y[TT_NS];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) y[s] = c[s];
-#pragma unroll
-    for (int s = 0; s < 12; ++s) y[6 + s] = (double)g[s];
     const VOnly vo = v_only(V);
-    const Currents cur = tt_currents(P, V, vo, y);
+    const double cai = c[CAI], casr = c[CASR], cass = c[CASS], rbar = c[RBAR];
+
+    // ---- gating variables at V^k (their products at u^k and u^{k+1}) ----
+    GateProducts po, pn;
+    tt_gates<G>((G)V, (G)dt, (G)cass, g, ld, po, pn);
 
     // ---- calcium subsystem and ion concentrations: rates at (V^k, u^k) ----
-    const double cai = y[CAI], casr = y[CASR], cass = y[CASS], rbar = y[RBAR];
+    const Currents cur = tt_currents(P, V, vo, c, po);
     double kcasr = MAX_SR - (MAX_SR - MIN_SR) / (1.0 + sq(EC_SR / casr));
     double k1 = K1_PRIME / kcasr;
     double k2 = K2_PRIME * kcasr;
@@ -259,16 +334,13 @@ __device__ double tt_point(const IonicParams &P, double dt, double V, double *c,
     double buf_sr = 1.0 / (1.0 + BUF_SR * KBUF_SR / sq(casr + KBUF_SR));
     double buf_ss = 1.0 / (1.0 + BUF_SS * KBUF_SS / sq(cass + KBUF_SS));
     double d_rbar = -k2 * cass * rbar + K4 * (1.0 - rbar);
-    double d_cai = buf_c * ((i_leak - i_up) * VOLSR / VOLC + i_xfer
-                            - (cur.ibCa + cur.ipCa - 2.0 * cur.iNaCa) * CAPAC / (2.0 * VOLC * Far));
+    double d_cai = buf_c * ((i_leak - i_up) * (VOLSR / VOLC) + i_xfer
+                            - (cur.ibCa + cur.ipCa - 2.0 * cur.iNaCa) * (CAPAC / (2.0 * VOLC * Far)));
     double d_casr = buf_sr * (i_up - i_rel - i_leak);
-    double d_cass = buf_ss * (-cur.iCaL * CAPAC / (2.0 * VOLSS * Far) + i_rel * VOLSR / VOLSS
-                              - i_xfer * VOLC / VOLSS);
-    double d_nai = -(cur.iNa + cur.ibNa + 3.0 * cur.iNaK + 3.0 * cur.iNaCa) * CAPAC / (VOLC * Far);
-    double d_ki = -(cur.iK1 + cur.ito + cur.iKr + cur.iKs - 2.0 * cur.iNaK + cur.ipK) * CAPAC / (VOLC * Far);
-
-    // ---- gating variables at V^k ----
-    tt_gates<G>((G)V, (G)dt, (G)cass, g);
+    double d_cass = buf_ss * (-cur.iCaL * (CAPAC / (2.0 * VOLSS * Far)) + i_rel * (VOLSR / VOLSS)
+                              - i_xfer * (VOLC / VOLSS));
+    double d_nai = -(cur.iNa + cur.ibNa + 3.0 * cur.iNaK + 3.0 * cur.iNaCa) * (CAPAC / (VOLC * Far));
+    double d_ki = -(cur.iK1 + cur.ito + cur.iKr + cur.iKs - 2.0 * cur.iNaK + cur.ipK) * (CAPAC / (VOLC * Far));
 
     // ---- forward Euler for the concentration-type states ----
     c[KI] = c[KI] + dt * d_ki;
@@ -279,11 +351,7 @@ __device__ double tt_point(const IonicParams &P, double dt, double V, double *c,
     c[RBAR] = rbar + dt * d_rbar;
 
     // ---- I_ion(V^k, u^{k+1}) ----
-#pragma unroll
-    for (int s = 0; s < 6; ++s) y[s] = c[s];
-#pragma unroll
-    for (int s = 0; s < 12; ++s) y[6 + s] = (double)g[s];
-    return tt_currents(P, V, vo, y).total();
+    return tt_currents(P, V, vo, c, pn).total();
 }
 
 // Row i holds a cell: i < n, or, with the per-tile count of real rows of the
@@ -295,11 +363,12 @@ __device__ __forceinline__ bool real_row(int64_t i, int64_t n, const int32_t *ti
 }
 
 // ---------------------------------------------------------------------------
-// Three workgroups of 256 per CU (12 wavefronts, 168 registers each): the
-// ten Tusscher-Panfilov update is latency bound at the two wavefronts per SIMD
-// its unconstrained 222 registers allow; a few spilled values cost less.
+// The ten Tusscher-Panfilov update is latency bound (a chain of FP64
+// exponentials per node); streaming the gates through tt_gates keeps it at
+// ~123 registers, four wavefronts per SIMD with no spills.  A tighter bound
+// spills more than it gains.
 template <int KIND>
-__global__ __launch_bounds__(256, 3) void k_ionic_step(IonicParams P, int64_t n, int64_t ld, double dt,
+__global__ __launch_bounds__(256) void k_ionic_step(IonicParams P, int64_t n, int64_t ld, double dt,
                                                     double cm, const double *__restrict__ V,
                                                     double *__restrict__ u,
                                                     const double *__restrict__ istim,
@@ -319,16 +388,12 @@ __global__ __launch_bounds__(256, 3) void k_ionic_step(IonicParams P, int64_t n,
         iion = ms_point<double>(P, dt, v, h);
         u[i] = h;
     } else if constexpr (KIND == MDX_KIND_TT) {
-        double c[6], g[12];
+        double c[6];
 #pragma unroll
         for (int s = 0; s < 6; ++s) c[s] = u[s * ld + i];
-#pragma unroll
-        for (int s = 0; s < 12; ++s) g[s] = u[(6 + s) * ld + i];
-        iion = tt_point<double>(P, dt, v, c, g);
+        iion = tt_point<double>(P, dt, v, c, u + 6 * ld + i, ld);
 #pragma unroll
         for (int s = 0; s < 6; ++s) u[s * ld + i] = c[s];
-#pragma unroll
-        for (int s = 0; s < 12; ++s) u[(6 + s) * ld + i] = g[s];
     }
     if (raw)
         out[i] = iion;
@@ -364,7 +429,7 @@ __global__ __launch_bounds__(256) void k_ionic_init(IonicParams P, int64_t n, in
 // the current in FP64 (u[s * ld + i], rows 0..5 for the ten Tusscher-Panfilov
 // model; Mitchell-Schaeffer has only its gate h).
 template <int KIND>
-__global__ __launch_bounds__(256, 4) void k_ionic_step_mixed(IonicParams P, int64_t n, int64_t ld,
+__global__ __launch_bounds__(256) void k_ionic_step_mixed(IonicParams P, int64_t n, int64_t ld,
                                                           double dt, double cm,
                                                           const double *__restrict__ V,
                                                           double *__restrict__ u,
@@ -387,16 +452,11 @@ __global__ __launch_bounds__(256, 4) void k_ionic_step_mixed(IonicParams P, int6
         g32[i] = h;
     } else if constexpr (KIND == MDX_KIND_TT) {
         double c[6];
-        float g[12];
 #pragma unroll
         for (int s = 0; s < 6; ++s) c[s] = u[s * ld + i];
-#pragma unroll
-        for (int s = 0; s < 12; ++s) g[s] = g32[s * ld + i];
-        iion = tt_point<float>(P, dt, v, c, g);
+        iion = tt_point<float>(P, dt, v, c, g32 + i, ld);
 #pragma unroll
         for (int s = 0; s < 6; ++s) u[s * ld + i] = c[s];
-#pragma unroll
-        for (int s = 0; s < 12; ++s) g32[s * ld + i] = g[s];
     }
     out[i] = (istim ? istim[i] : 0.0) - cm * iion;
 }
