@@ -111,6 +111,9 @@ typedef struct {
     double spmv_bytes;        /* algorithmic bytes moved by those launches   */
     double host_wait_seconds; /* host time blocked on the stream in mdx_run  */
     int64_t fallbacks;        /* learned warm start: steps that used V^k     */
+    int64_t col_index_bytes;  /* bytes per stored column index the per-step  */
+                              /* kernels of a single mesh read: 2 (16-bit    */
+                              /* offsets, MDX_TUNE_COMPACT_COLUMNS) or 4     */
 } mdx_stats;
 
 /* ---- context -------------------------------------------------------- */
@@ -218,6 +221,13 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
  *                        kernel whose streams exceed 256 MiB (larger than
  *                        the Infinity Cache can keep between products), 0
  *                        never, 1 always.
+ *   MDX_TUNE_COMPACT_COLUMNS  1 (default): where every 64-row slice's
+ *                        columns span fewer than 2^16 indices (RCM keeps
+ *                        them within about twice the matrix bandwidth), the
+ *                        per-step kernels of a single mesh read the column
+ *                        indices as 16-bit offsets from a per-slice base,
+ *                        2 bytes per stored entry instead of 4; 0 reads the
+ *                        32-bit indices.  Results are bitwise the same.
  * MAX_GROUPS and ITER_SCHEME take effect at the next mdx_prepare / mdx_run;
  * the batched keys need a prepared batched context and act at once. */
 enum {
@@ -227,7 +237,8 @@ enum {
     MDX_TUNE_TILES_PER_GROUP = 4,
     MDX_TUNE_GRAPH = 5,
     MDX_TUNE_FORMAT = 6,
-    MDX_TUNE_NONTEMPORAL = 7
+    MDX_TUNE_NONTEMPORAL = 7,
+    MDX_TUNE_COMPACT_COLUMNS = 8
 };
 MDX_API mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value);
 

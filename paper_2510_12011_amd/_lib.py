@@ -31,6 +31,7 @@ MDX_MAT_M, MDX_MAT_K, MDX_MAT_A = 0, 1, 2
 MDX_TUNE_MAX_GROUPS, MDX_TUNE_ITER_SCHEME = 1, 2
 MDX_TUNE_LANES_PER_ROW, MDX_TUNE_TILES_PER_GROUP, MDX_TUNE_GRAPH, MDX_TUNE_FORMAT = 3, 4, 5, 6
 MDX_TUNE_NONTEMPORAL = 7
+MDX_TUNE_COMPACT_COLUMNS = 8
 MDX_TUNE_MAX_CANDIDATES = 32
 
 
@@ -47,7 +48,8 @@ class Stats(C.Structure):
                 ("bandwidth", C.c_int64), ("step_loop_seconds", C.c_double),
                 ("spmv_timed", C.c_int64), ("spmv_seconds", C.c_double),
                 ("spmv_work", C.c_int64), ("spmv_bytes", C.c_double),
-                ("host_wait_seconds", C.c_double), ("fallbacks", C.c_int64)]
+                ("host_wait_seconds", C.c_double), ("fallbacks", C.c_int64),
+                ("col_index_bytes", C.c_int64)]
 
 
 class TuneReport(C.Structure):

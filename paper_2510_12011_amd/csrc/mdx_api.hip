@@ -50,8 +50,8 @@ struct Stim {
 
 // byte offsets of every array inside the persistent workspace / setup scratch
 struct Layout {
-    size_t slice_ptr, col, Mv, Kv, Av, dinv, vec[3], r, p, p2, q, b, s, istim, u, lat, lrt, stim_idx,
-        partial, scalars;
+    size_t slice_ptr, col, col16, cbase, Mv, Kv, Av, dinv, vec[3], r, p, p2, q, b, s, istim, u, lat,
+        lrt, stim_idx, partial, scalars;
     size_t A32, dinv32, r32, p32, q32, delta, g32;   // mixed-precision form
     size_t kdiag, kvp, feat, mlp_y, mlp_params;       // learned warm start
     size_t tile_real, grp, inst_grp, bsc, sptr_t, col_t, A32_t;   // batched form
@@ -84,6 +84,10 @@ struct mdx_ctx {
     int64_t npad = 0, nslices = 0, nslots = 0, nnz = 0, bandwidth = 0;
     std::vector<int64_t> slice_ptr;
     std::vector<int32_t> col_sell, rowlen;
+    // compact columns: col_sell[e] = cbase[slice] + col16[e] when every
+    // slice's columns span fewer than 2^16 indices (else both empty)
+    std::vector<uint16_t> col16;
+    std::vector<int32_t> cbase;
     std::vector<int64_t> stim_off;      // offsets of each stimulus in the device list
 
     // device memory
@@ -110,6 +114,7 @@ struct mdx_ctx {
     int max_groups = kMaxGroups;
     int iter_scheme = 0;
     int nt_mode = -1;   // non-temporal matrix loads: -1 by stream size, 0 never, 1 always
+    bool compact_cols = true;   // per-step kernels read col16 when it exists
 
     // batched form: instances, each a contiguous row range starting on a
     // TILE boundary (a single-mesh context has one instance, rows [0, n))
@@ -357,6 +362,42 @@ void hilbert_order(const std::vector<double> &xyz, int64_t p0, int64_t p1,
     for (auto &kv : key) out.push_back(kv.second);
 }
 
+// 16-bit column offsets from each slice's smallest column, when every
+// slice's columns span fewer than 2^16 indices
+void compact_columns(mdx_ctx *c)
+{
+    c->col16.clear();
+    c->cbase.clear();
+    std::vector<int32_t> base(c->nslices);
+    for (int64_t sl = 0; sl < c->nslices; ++sl) {
+        int32_t lo = INT32_MAX, hi = -1;
+        for (int64_t e = c->slice_ptr[sl]; e < c->slice_ptr[sl + 1]; ++e) {
+            lo = std::min(lo, c->col_sell[e]);
+            hi = std::max(hi, c->col_sell[e]);
+        }
+        if (hi < 0) lo = 0;
+        if ((int64_t)hi - lo >= 65536) return;
+        base[sl] = lo;
+    }
+    std::vector<uint16_t> off(c->col_sell.size());
+    for (int64_t sl = 0; sl < c->nslices; ++sl)
+        for (int64_t e = c->slice_ptr[sl]; e < c->slice_ptr[sl + 1]; ++e)
+            off[e] = (uint16_t)(c->col_sell[e] - base[sl]);
+    c->col16.swap(off);
+    c->cbase.swap(base);
+}
+
+// the pattern as the per-step kernels read it
+SellView step_view(const mdx_ctx *c)
+{
+    SellView P{c->dev<int64_t>(c->L.slice_ptr), c->dev<int32_t>(c->L.col)};
+    if (c->compact_cols && !c->col16.empty()) {
+        P.col16 = c->dev<uint16_t>(c->L.col16);
+        P.cbase = c->dev<int32_t>(c->L.cbase);
+    }
+    return P;
+}
+
 // position of column c in new-row r of the sliced-ELL pattern, or -1
 int64_t sell_slot(const mdx_ctx *c, int64_t r, int32_t colv)
 {
@@ -379,6 +420,8 @@ void compute_layout(mdx_ctx *c)
     const size_t np = (size_t)c->npad, ns = (size_t)c->nslots;
     L.slice_ptr = take(sizeof(int64_t) * (c->nslices + 1));
     L.col = take(sizeof(int32_t) * ns);
+    L.col16 = take(sizeof(uint16_t) * std::max<size_t>(c->col16.size(), 1));
+    L.cbase = take(sizeof(int32_t) * std::max<size_t>(c->cbase.size(), 1));
     L.Mv = take(sizeof(double) * ns);
     L.Kv = take(sizeof(double) * ns);
     L.Av = take(sizeof(double) * ns);
@@ -878,6 +921,7 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
     ctx->slice_ptr.swap(sptr);
     ctx->col_sell.swap(colv);
     ctx->rowlen.swap(rowlen);
+    compact_columns(ctx);
     ctx->batched = batched;
     ctx->n_inst = n_inst;
     ctx->inst_node_ptr.assign(node_ptr, node_ptr + n_inst + 1);
@@ -1398,6 +1442,14 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
                         (long long)sl);
     for (int32_t c : ctx->col_sell)
         if (c < 0 || c >= ctx->npad) return fail(ctx, MDX_ERR_BAD_MESH, "column out of range");
+    if (!ctx->col16.empty()) {
+        if ((int64_t)ctx->col16.size() != ctx->nslots || (int64_t)ctx->cbase.size() != ctx->nslices)
+            return fail(ctx, MDX_ERR_BAD_MESH, "internal layout inconsistent (16-bit columns)");
+        for (int64_t sl = 0; sl < ctx->nslices; ++sl)
+            for (int64_t e = ctx->slice_ptr[sl]; e < ctx->slice_ptr[sl + 1]; ++e)
+                if (ctx->cbase[sl] + (int32_t)ctx->col16[e] != ctx->col_sell[e])
+                    return fail(ctx, MDX_ERR_BAD_MESH, "16-bit column mismatch");
+    }
     for (int32_t code : contrib)
         if (code < 0 || code >= 16 * ctx->m)
             return fail(ctx, MDX_ERR_BAD_MESH, "contribution out of range");
@@ -1425,6 +1477,12 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
                           sizeof(int64_t) * (ctx->nslices + 1), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ctx->dev<int32_t>(L.col), ctx->col_sell.data(),
                           sizeof(int32_t) * ctx->nslots, hipMemcpyHostToDevice, st));
+    if (!ctx->col16.empty()) {
+        HIPCHK(hipMemcpyAsync(ctx->dev<uint16_t>(L.col16), ctx->col16.data(),
+                              sizeof(uint16_t) * ctx->nslots, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ctx->dev<int32_t>(L.cbase), ctx->cbase.data(),
+                              sizeof(int32_t) * ctx->nslices, hipMemcpyHostToDevice, st));
+    }
     // stimulus node lists in the new numbering
     std::vector<int32_t> sidx;
     ctx->stim_off.assign(1, 0);
@@ -1528,7 +1586,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     const Layout &L = ctx->L;
     hipStream_t st = ctx->stream;
     const Tiling &T = ctx->tiling;
-    SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
+    const SellView P = step_view(ctx);
     double *Mv = ctx->dev<double>(L.Mv), *Kv = ctx->dev<double>(L.Kv), *Av = ctx->dev<double>(L.Av);
     double *dinv = ctx->dev<double>(L.dinv);
     double *r = ctx->dev<double>(L.r), *q = ctx->dev<double>(L.q);
@@ -1557,9 +1615,10 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     ctx->iters_hist.clear();
     int64_t n_out = 0;
     // non-temporal hints by the size of each kernel's matrix streams
-    const bool nt_rhs = use_nt(ctx, 20.0 * slots(ctx));     // M, K and columns
-    const bool nt_iter64 = use_nt(ctx, 12.0 * slots(ctx));  // FP64 A and columns
-    const bool nt_iter32 = use_nt(ctx, 8.0 * slots(ctx));   // FP32 A and columns
+    const double cbytes = P.col16 ? 2.0 : 4.0;              // per stored column index
+    const bool nt_rhs = use_nt(ctx, (16.0 + cbytes) * slots(ctx));   // M, K and columns
+    const bool nt_iter64 = use_nt(ctx, (8.0 + cbytes) * slots(ctx));  // FP64 A and columns
+    const bool nt_iter32 = use_nt(ctx, (4.0 + cbytes) * slots(ctx));  // FP32 A and columns
     auto t_start = std::chrono::steady_clock::now();
 
     for (int64_t j = 0; j < n_steps; ++j) {
@@ -1725,7 +1784,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             ctx->stats.spmv_work += work;
             // per nonzero: value + column; per row: p read once, q written once
             // (the two-kernel FP64 scheme also reads r, D^-1, p_{k-1}, writes p_k)
-            const double per_nnz = mixed ? 8.0 : 12.0;
+            const double per_nnz = (mixed ? 4.0 : 8.0) + cbytes;
             const double per_row = mixed ? 8.0 : ctx->iter_scheme == 1 ? 40.0 : 16.0;
             ctx->stats.spmv_bytes +=
                 (double)work * (per_nnz * (double)ctx->nnz + per_row * (double)ctx->n);
@@ -1874,6 +1933,7 @@ mdx_status mdx_get_stats(mdx_ctx *ctx, mdx_stats *out)
     out->nnz = ctx->nnz;
     out->n_sell_slots = ctx->nslots;
     out->bandwidth = ctx->bandwidth;
+    out->col_index_bytes = !ctx->batched && ctx->compact_cols && !ctx->col16.empty() ? 2 : 4;
     return MDX_OK;
 }
 
@@ -1935,6 +1995,10 @@ mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value)
         if (value < -1 || value > 1) return fail(ctx, MDX_ERR_INVALID_ARG, "use -1, 0 or 1");
         ctx->nt_mode = (int)value;
         release_graphs(ctx);
+        return MDX_OK;
+    case MDX_TUNE_COMPACT_COLUMNS:
+        if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "use 0 or 1");
+        ctx->compact_cols = value != 0;
         return MDX_OK;
     case MDX_TUNE_GRAPH:
         if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "graph is 0 or 1");
@@ -2048,7 +2112,7 @@ mdx_status mdx_spmv(mdx_ctx *ctx, int32_t which, const double *x, double *y)
     size_t off = which == MDX_MAT_M ? L.Mv : which == MDX_MAT_K ? L.Kv : L.Av;
     double *p = ctx->dev<double>(L.p), *q = ctx->dev<double>(L.q);
     if (mdx_status e = copy_vec_in(ctx, x, p)) return e;
-    SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
+    const SellView P = step_view(ctx);
     Scalars *sc = ctx->dev<Scalars>(L.scalars);
     launch_spmv_dot(ctx->stream, ctx->tiling, P, ctx->dev<double>(off), p, q,
                     ctx->dev<double>(L.partial) + 3 * kPartialCap, &sc->zero, nullptr, nullptr, false);

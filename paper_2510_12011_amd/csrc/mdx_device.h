@@ -29,6 +29,16 @@ static __device__ __forceinline__ T ld_stream(const T *p)
         return *p;
 }
 
+// first column of slice sl for 16-bit offsets, 0 for 32-bit columns
+template <typename CI>
+static __device__ __forceinline__ int32_t slice_base(const Cols<CI> &c, int64_t sl)
+{
+    if constexpr (sizeof(CI) == 2)
+        return c.base[sl];
+    else
+        return 0;
+}
+
 #define MDX_LAUNCH_NT(nt, kernel, ...)                                                       \
     do {                                                                                     \
         if (nt)                                                                              \
@@ -36,6 +46,24 @@ static __device__ __forceinline__ T ld_stream(const T *p)
         else                                                                                 \
             hipLaunchKernelGGL(kernel<false>, __VA_ARGS__);                                  \
     } while (0)
+
+// Launch kernel<NT, CI> on the column stream of SellView P: the launch
+// arguments name that stream `cols`.
+#define MDX_LAUNCH_SELL(P, nt, kernel, ...)                                                  \
+    with_cols((P), (nt), [&](auto ntc_, auto cols) {                                         \
+        auto kern_ = &kernel<decltype(ntc_)::value, typename decltype(cols)::index_type>;    \
+        hipLaunchKernelGGL(kern_, __VA_ARGS__);                                              \
+    })
+
+// the same with start/stop events recorded around the launch
+#define MDX_LAUNCH_SELL_EV(P, nt, e0, e1, kernel, grid, block, shm, st, ...)                 \
+    with_cols((P), (nt), [&](auto ntc_, auto cols) {                                         \
+        auto kern_ = &kernel<decltype(ntc_)::value, typename decltype(cols)::index_type>;    \
+        if (e0)                                                                              \
+            hipExtLaunchKernelGGL(kern_, grid, block, shm, st, e0, e1, 0, __VA_ARGS__);       \
+        else                                                                                 \
+            hipLaunchKernelGGL(kern_, grid, block, shm, st, __VA_ARGS__);                    \
+    })
 
 static __device__ __forceinline__ double wave_sum(double v)
 {

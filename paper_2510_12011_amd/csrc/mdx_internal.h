@@ -9,10 +9,15 @@
 // order, each row's columns ascending; short rows are padded with (col = row,
 // value = 0).  The row count is padded to a multiple of TILE with empty rows
 // whose vectors stay zero.  M, K and A share one pattern (slice_ptr, col).
+// When every slice's columns span fewer than 2^16 indices (RCM keeps a
+// slice's columns within about twice the bandwidth), the per-step kernels
+// read the columns as 16-bit offsets from a per-slice base instead: 2 bytes
+// per stored entry instead of 4.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace mdx {
 
@@ -64,7 +69,32 @@ struct MlpNorm {
 struct SellView {
     const int64_t *slice_ptr;
     const int32_t *col;
+    const uint16_t *col16 = nullptr;   // 16-bit column offsets (null: read col)
+    const int32_t *cbase = nullptr;    // per-slice base of col16
 };
+
+// Column stream of the sliced ELL as a kernel reads it: CI = int32_t (the
+// columns themselves) or uint16_t (offsets from base[slice]).
+template <typename CI>
+struct Cols {
+    using index_type = CI;
+    const CI *idx;
+    const int32_t *base;
+};
+
+// Calls f(std::integral_constant<bool, NT>{}, Cols<CI>{...}) for the column
+// stream P provides and the non-temporal choice nt.
+template <class F>
+void with_cols(const SellView &P, bool nt, F &&f)
+{
+    if (P.col16) {
+        const Cols<uint16_t> c{P.col16, P.cbase};
+        if (nt) f(std::true_type{}, c); else f(std::false_type{}, c);
+    } else {
+        const Cols<int32_t> c{P.col, nullptr};
+        if (nt) f(std::true_type{}, c); else f(std::false_type{}, c);
+    }
+}
 
 // ---- assembly (mdx_assembly.hip) -----------------------------------------
 void launch_element(hipStream_t s, int64_t m, const double *xyz, const int32_t *tets,

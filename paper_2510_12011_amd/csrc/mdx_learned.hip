@@ -22,9 +22,9 @@ namespace mdx {
 namespace {
 
 // kvp = (K v)_i / K_ii
-template <bool NT>
+template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_kv_feature(Tiling t, const int64_t *__restrict__ slice_ptr,
-                                                    const int32_t *__restrict__ col,
+                                                    Cols<CI> col,
                                                     const double *__restrict__ Kv,
                                                     const double *__restrict__ kdiag,
                                                     const double *__restrict__ v,
@@ -36,9 +36,10 @@ __global__ __launch_bounds__(256) void k_kv_feature(Tiling t, const int64_t *__r
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
         const int64_t sl = row / SLICE;
+        const int32_t cb = slice_base(col, sl);
         double kv = 0.0;
         for (int64_t e = slice_ptr[sl] + lane; e < slice_ptr[sl + 1]; e += SLICE)
-            kv += ld_stream<NT>(Kv + e) * v[ld_stream<NT>(col + e)];
+            kv += ld_stream<NT>(Kv + e) * v[cb + (int32_t)ld_stream<NT>(col.idx + e)];
         const double kd = kdiag[row];
         kvp[row] = kd != 0.0 ? (float)(kv / kd) : 0.0f;
     }
@@ -73,9 +74,9 @@ __global__ __launch_bounds__(256) void k_features(int64_t n_real, int64_t n_rows
 
 // b = chi M (Cm V + dt s) - (1-theta) dt K V;  A V = chi Cm M V + theta dt K V;
 // r_prev = b - A V;  r_mlp = r_prev - scale A y;  x = V + scale y
-template <bool NT>
+template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_rhs_learned(
-    Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    Tiling t, const int64_t *__restrict__ slice_ptr, Cols<CI> col,
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ kdiag,
     const double *__restrict__ dinv, StepParams sp, float out_scale, const double *__restrict__ V,
     const double *__restrict__ src, const float *__restrict__ y, double *__restrict__ b,
@@ -95,9 +96,10 @@ __global__ __launch_bounds__(256) void k_rhs_learned(
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int32_t cb = slice_base(col, sl);
         double mv = 0.0, ms = 0.0, kv = 0.0, my = 0.0, ky = 0.0;
         for (int64_t e = beg; e < end; e += SLICE) {
-            const int32_t c = ld_stream<NT>(col + e);
+            const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
             const double m = ld_stream<NT>(Mv + e), kk = ld_stream<NT>(Kv + e);
             const double vj = V[c], yj = (double)y[c];
             mv += m * vj;
@@ -223,8 +225,8 @@ void launch_kdiag(hipStream_t s, int64_t n_rows, int64_t n_real, SellView K, con
 void launch_kv_feature(hipStream_t s, const Tiling &t, SellView P, const double *Kv,
                        const double *kdiag, const double *v, float *kvp)
 {
-    hipLaunchKernelGGL(k_kv_feature<false>, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col,
-                       Kv, kdiag, v, kvp);
+    MDX_LAUNCH_SELL(P, false, k_kv_feature, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
+                    Kv, kdiag, v, kvp);
 }
 
 void launch_features(hipStream_t s, int64_t n_real, int64_t n_rows, const double *V,
@@ -243,9 +245,9 @@ void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double
                         double *r_prev, float *kvp, int fp32_iter, double *part4, double *part1,
                         bool nt)
 {
-    MDX_LAUNCH_NT(nt, k_rhs_learned, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
-                  kdiag, dinv, sp, out_scale, V, src, y, b, x, r_mlp, r_prev, kvp, fp32_iter, part4,
-                  part1);
+    MDX_LAUNCH_SELL(P, nt, k_rhs_learned, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols, Mv,
+                    Kv, kdiag, dinv, sp, out_scale, V, src, y, b, x, r_mlp, r_prev, kvp, fp32_iter,
+                    part4, part1);
 }
 
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,

@@ -44,9 +44,9 @@ __global__ __launch_bounds__(256) void k_to_f32(int64_t n, const double *__restr
 
 // b, x0 and r0 = b - A x0 in FP64 (FP64 M and K); r32 = r0; delta = 0;
 // partials: r32.z32 (FP64 accumulation), |D^-1 r0|^2, |D^-1 b|^2.
-template <bool NT>
+template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_rhs_init_mixed(
-    Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    Tiling t, const int64_t *__restrict__ slice_ptr, Cols<CI> col,
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
     const float *__restrict__ dinv32, StepParams sp, const double *__restrict__ V,
     const double *__restrict__ Vprev, const double *__restrict__ src, double *__restrict__ x,
@@ -65,9 +65,10 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int32_t cb = slice_base(col, sl);
         double mv = 0.0, kv = 0.0, mx = 0.0, kx = 0.0;
         for (int64_t e = beg; e < end; e += SLICE) {
-            const int32_t c = ld_stream<NT>(col + e);
+            const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
             const double m = ld_stream<NT>(Mv + e), kk = ld_stream<NT>(Kv + e);
             const double vj = V[c];
             const double x0j = extrap ? 2.0 * vj - Vprev[c] : vj;
@@ -105,9 +106,9 @@ __global__ __launch_bounds__(256) void k_set_direction32(int64_t n, const float 
 }
 
 // q = A p in FP32; partial p.q in FP64
-template <bool NT>
+template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_spmv32_dot(Tiling t, const int64_t *__restrict__ slice_ptr,
-                                                    const int32_t *__restrict__ col,
+                                                    Cols<CI> col,
                                                     const float *__restrict__ A32,
                                                     const float *__restrict__ p,
                                                     float *__restrict__ q,
@@ -124,9 +125,10 @@ __global__ __launch_bounds__(256) void k_spmv32_dot(Tiling t, const int64_t *__r
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int32_t cb = slice_base(col, sl);
         float sum = 0.0f;
 #pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(A32 + e) * p[ld_stream<NT>(col + e)];
+        for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(A32 + e) * p[cb + (int32_t)ld_stream<NT>(col.idx + e)];
         q[row] = sum;
         acc[0] += (double)p[row] * (double)sum;
     }
@@ -225,9 +227,9 @@ __global__ __launch_bounds__(256) void k_flush(int64_t n, double *__restrict__ x
 
 // replacement, part 2: r64 = b - A x64 in FP64, r32 = r64; partials r32.z32
 // and |D^-1 r64|^2
-template <bool NT>
+template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_true_residual(
-    Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    Tiling t, const int64_t *__restrict__ slice_ptr, Cols<CI> col,
     const double *__restrict__ Av, const double *__restrict__ x, const double *__restrict__ b,
     const double *__restrict__ dinv, const float *__restrict__ dinv32, float *__restrict__ r32,
     double *__restrict__ partial, const Scalars *__restrict__ sc)
@@ -241,9 +243,10 @@ __global__ __launch_bounds__(256) void k_true_residual(
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int32_t cb = slice_base(col, sl);
         double ax = 0.0;
 #pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) ax += ld_stream<NT>(Av + e) * x[ld_stream<NT>(col + e)];
+        for (int64_t e = beg; e < end; e += SLICE) ax += ld_stream<NT>(Av + e) * x[cb + (int32_t)ld_stream<NT>(col.idx + e)];
         const double ri = b[row] - ax;
         const float rf = (float)ri;
         r32[row] = rf;
@@ -318,8 +321,8 @@ void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const dou
                            const double *src, double *x, double *b, float *r32, float *delta,
                            double *partial, const double *kdiag, float *kvp, bool nt)
 {
-    MDX_LAUNCH_NT(nt, k_rhs_init_mixed, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv,
-                  Kv, dinv, dinv32, sp, V, Vprev, src, x, b, r32, delta, partial, kdiag, kvp);
+    MDX_LAUNCH_SELL(P, nt, k_rhs_init_mixed, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
+                    Mv, Kv, dinv, dinv32, sp, V, Vprev, src, x, b, r32, delta, partial, kdiag, kvp);
 }
 
 void launch_set_direction32(hipStream_t s, int64_t n, const float *dinv32, const float *r32,
@@ -333,13 +336,8 @@ void launch_spmv32_dot(hipStream_t s, const Tiling &t, SellView P, const float *
                        const float *p, float *q, double *partial, Scalars *sc,
                        hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
 {
-    auto kern = nt ? &k_spmv32_dot<true> : &k_spmv32_dot<false>;
-    if (ev_start)
-        hipExtLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, ev_start, ev_stop, 0, t,
-                              P.slice_ptr, P.col, A32, p, q, partial, sc);
-    else
-        hipLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, A32, p, q,
-                           partial, sc);
+    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_spmv32_dot, dim3(t.groups), dim3(TILE), 0, s, t,
+                       P.slice_ptr, cols, A32, p, q, partial, sc);
 }
 
 void launch_cg_update32(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
@@ -365,8 +363,8 @@ void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter
 {
     const int64_t n = t.n_rows;
     hipLaunchKernelGGL(k_flush, dim3(blocks_for(n)), dim3(256), 0, s, n, x, delta, sc);
-    MDX_LAUNCH_NT(nt, k_true_residual, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av, x,
-                  b, dinv, dinv32, r32, partial, sc);
+    MDX_LAUNCH_SELL(P, nt, k_true_residual, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
+                    Av, x, b, dinv, dinv32, r32, partial, sc);
     hipLaunchKernelGGL(k_replace_finalize, dim3(1), dim3(TILE), 0, s, t.groups, max_iter, partial,
                        sc);
     hipLaunchKernelGGL(k_redirect, dim3(blocks_for(n)), dim3(256), 0, s, n, dinv32, r32, p32, sc);

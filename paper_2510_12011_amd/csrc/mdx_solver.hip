@@ -65,9 +65,9 @@ __global__ __launch_bounds__(256) void k_stim_add(int64_t n_idx, const int32_t *
     if (j < n_idx) istim[idx[j]] += amp;   // node lists are duplicate-free
 }
 
-template <bool NT>
+template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_rhs_init(
-    Tiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    Tiling t, const int64_t *__restrict__ slice_ptr, Cols<CI> col,
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
     StepParams sp, const double *__restrict__ V, const double *__restrict__ Vprev,
     const double *__restrict__ src, double *__restrict__ x, double *__restrict__ r,
@@ -86,9 +86,10 @@ __global__ __launch_bounds__(256) void k_rhs_init(
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int32_t cb = slice_base(col, sl);
         double mv = 0.0, kv = 0.0, mx = 0.0, kx = 0.0;
         for (int64_t e = beg; e < end; e += SLICE) {
-            const int32_t c = ld_stream<NT>(col + e);
+            const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
             const double m = ld_stream<NT>(Mv + e), kk = ld_stream<NT>(Kv + e);
             const double vj = V[c];
             const double x0j = extrap ? 2.0 * vj - Vprev[c] : vj;
@@ -136,9 +137,9 @@ __global__ __launch_bounds__(256) void k_init_finalize(int groups, const double 
     }
 }
 
-template <bool NT>
+template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__restrict__ slice_ptr,
-                                                  const int32_t *__restrict__ col,
+                                                  Cols<CI> col,
                                                   const double *__restrict__ Av,
                                                   const double *__restrict__ p,
                                                   double *__restrict__ q,
@@ -154,9 +155,10 @@ __global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__res
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int32_t cb = slice_base(col, sl);
         double sum = 0.0;
 #pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(Av + e) * p[ld_stream<NT>(col + e)];
+        for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(Av + e) * p[cb + (int32_t)ld_stream<NT>(col.idx + e)];
         q[row] = sum;
         acc[0] += p[row] * sum;
     }
@@ -171,10 +173,10 @@ __global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__res
 // gathered column, so no separate direction pass is needed; own rows store
 // p_k (double-buffered against p_{k-1}) and a partial of p_k . q.
 // k == max_iter only tests.
-template <bool NT>
+template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_cg_direction_spmv(
     Tiling t, int k, int max_iter, const int64_t *__restrict__ slice_ptr,
-    const int32_t *__restrict__ col, const double *__restrict__ Av,
+    Cols<CI> col, const double *__restrict__ Av,
     const double *__restrict__ dinv, const double *__restrict__ r,
     const double *__restrict__ p_prev, double *__restrict__ p_cur, double *__restrict__ q,
     const double *__restrict__ partial_rz, double *__restrict__ partial_pq,
@@ -217,17 +219,18 @@ __global__ __launch_bounds__(256) void k_cg_direction_spmv(
         const int64_t row = (int64_t)tile * TILE + threadIdx.x;
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int32_t cb = slice_base(col, sl);
         double sum = 0.0;
         if (k == 0) {
 #pragma unroll 4
             for (int64_t e = beg; e < end; e += SLICE) {
-                const int32_t c = ld_stream<NT>(col + e);
+                const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
                 sum += ld_stream<NT>(Av + e) * (dinv[c] * r[c]);
             }
         } else {
 #pragma unroll 4
             for (int64_t e = beg; e < end; e += SLICE) {
-                const int32_t c = ld_stream<NT>(col + e);
+                const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
                 sum += ld_stream<NT>(Av + e) * (dinv[c] * r[c] + beta * p_prev[c]);
             }
         }
@@ -363,8 +366,8 @@ void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *M
                      const double *Vprev, const double *src, double *x, double *r, double *b,
                      double *partial, const double *kdiag, float *kvp, bool nt)
 {
-    MDX_LAUNCH_NT(nt, k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Mv, Kv,
-                  dinv, sp, V, Vprev, src, x, r, b, partial, kdiag, kvp);
+    MDX_LAUNCH_SELL(P, nt, k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols, Mv,
+                    Kv, dinv, sp, V, Vprev, src, x, r, b, partial, kdiag, kvp);
 }
 
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
@@ -377,13 +380,8 @@ void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *A
                      double *q, double *partial, const int32_t *done, hipEvent_t ev_start,
                      hipEvent_t ev_stop, bool nt)
 {
-    auto kern = nt ? &k_spmv_dot<true> : &k_spmv_dot<false>;
-    if (ev_start)
-        hipExtLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, ev_start, ev_stop, 0, t,
-                              P.slice_ptr, P.col, Av, p, q, partial, done);
-    else
-        hipLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, Av, p, q,
-                           partial, done);
+    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_spmv_dot, dim3(t.groups), dim3(TILE), 0, s, t,
+                       P.slice_ptr, cols, Av, p, q, partial, done);
 }
 
 void launch_cg_direction_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
@@ -392,14 +390,9 @@ void launch_cg_direction_spmv(hipStream_t s, const Tiling &t, int k, int max_ite
                               const double *partial_rz, double *partial_pq, Scalars *sc,
                               hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
 {
-    auto kern = nt ? &k_cg_direction_spmv<true> : &k_cg_direction_spmv<false>;
-    if (ev_start)
-        hipExtLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, ev_start, ev_stop, 0, t, k,
-                              max_iter, P.slice_ptr, P.col, Av, dinv, r, p_prev, p_cur, q,
-                              partial_rz, partial_pq, sc);
-    else
-        hipLaunchKernelGGL(kern, dim3(t.groups), dim3(TILE), 0, s, t, k, max_iter, P.slice_ptr,
-                           P.col, Av, dinv, r, p_prev, p_cur, q, partial_rz, partial_pq, sc);
+    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_cg_direction_spmv, dim3(t.groups), dim3(TILE), 0,
+                       s, t, k, max_iter, P.slice_ptr, cols, Av, dinv, r, p_prev, p_cur, q,
+                       partial_rz, partial_pq, sc);
 }
 
 void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,

@@ -200,3 +200,36 @@ def test_batch_layout_is_block_diagonal(host_ctx):
     assert lib.mdx_autotune(host_ctx, 5, None) == L.MDX_ERR_STATE
     assert lib.mdx_set_tuning(host_ctx, L.MDX_TUNE_LANES_PER_ROW, 2) == L.MDX_ERR_STATE
     assert lib.mdx_set_tuning(host_ctx, L.MDX_TUNE_GRAPH, 2) == L.MDX_ERR_INVALID_ARG
+
+
+def test_compact_columns_choice(host_ctx):
+    """The per-step kernels read 16-bit column offsets when every 64-row
+    slice's columns span fewer than 2^16 indices (an RCM-ordered slab), and
+    32-bit columns otherwise (a fan whose apex couples to every node) or when
+    the tuning key turns them off."""
+    lib = L.lib()
+    m = inputs.slab(h=0.5).mesh
+    xyz, tets = np.ascontiguousarray(m.xyz), np.ascontiguousarray(m.tets)
+    assert lib.mdx_set_mesh(host_ctx, xyz.shape[0], _p(xyz), 1.0, tets.shape[0], _p(tets),
+                            None, None) == L.MDX_OK
+    st = L.Stats()
+
+    def width():
+        assert lib.mdx_get_stats(host_ctx, C.byref(st)) == L.MDX_OK
+        return st.col_index_bytes
+
+    assert width() == 2
+    assert lib.mdx_set_tuning(host_ctx, L.MDX_TUNE_COMPACT_COLUMNS, 0) == L.MDX_OK
+    assert width() == 4
+    assert lib.mdx_set_tuning(host_ctx, L.MDX_TUNE_COMPACT_COLUMNS, 2) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_set_tuning(host_ctx, L.MDX_TUNE_COMPACT_COLUMNS, 1) == L.MDX_OK
+    # fan: apex 0 and a helix of nodes 1..N; element i = (0, i, i+1, i+2)
+    N = 70_000
+    t = 0.3 * np.arange(N)
+    ring = np.stack([np.cos(t), np.sin(t), 0.05 * np.arange(N)], axis=1)
+    fxyz = np.ascontiguousarray(np.concatenate([[[0.0, 0.0, -5.0]], ring]))
+    i = np.arange(1, N - 1, dtype=np.int32)
+    ftets = np.ascontiguousarray(np.stack([np.zeros_like(i), i, i + 1, i + 2], axis=1))
+    assert lib.mdx_set_mesh(host_ctx, N + 1, _p(fxyz), 1.0, ftets.shape[0], _p(ftets),
+                            None, None) == L.MDX_OK
+    assert width() == 4
