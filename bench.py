@@ -202,9 +202,9 @@ def learned_workload(args):
                    "accuracy_reference": "plain FP64 PCG at rtol 1e-12, same steps",
                    "runs": summary, "fallbacks": int(st["fallbacks"]),
                    "train_sites": args.train_sites, "train_steps": args.train_steps},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv32_dot", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_cg_spmv32", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("k_spmv32_dot",
+                     "traffic": measured_traffic("k_cg_spmv32",
                                                  "paper_2510_12011_amd/csrc/mdx_mixed.hip"),
                      "traffic_source": "profiles/learned_shell_1.26M_hbm_traffic.md",
                      "bytes_per_launch": bytes_avg,
@@ -412,7 +412,7 @@ def single_workload(args):
                    "stopping": "relative to ||z0||" if spec.rel_mode == 0 else "relative to ||D^-1 b||",
                    "warm_start": "2V^k - V^(k-1)", "mean_cg_iters": float(iters.mean()),
                    "max_cg_iters": int(iters.max())},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv_dot" if prec == "fp64" else "k_spmv32_dot",
+        "roofline": {"bound": "hbm", "kernel": "k_spmv_dot" if prec == "fp64" else "k_cg_spmv32",
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_launch": bytes_avg,

@@ -52,7 +52,7 @@ struct Stim {
 struct Layout {
     size_t slice_ptr, col, col16, cbase, Mv, Kv, Av, dinv, vec[3], r, p, p2, q, b, s, istim, u, lat,
         lrt, stim_idx, partial, scalars;
-    size_t A32, dinv32, r32, p32, q32, delta, g32;   // mixed-precision form
+    size_t A32, dinv32, r32, z32, p32, q32, delta, g32;   // mixed-precision form
     size_t kdiag, kvp, feat, mlp_y, mlp_params;       // learned warm start
     size_t tile_real, grp, inst_grp, bsc, sptr_t, col_t, A32_t;   // batched form
     size_t csr_ptr, csr_col, csr_val, gv;
@@ -445,6 +445,7 @@ void compute_layout(mdx_ctx *c)
     L.A32 = take(sizeof(float) * ns);
     L.dinv32 = take(sizeof(float) * np);
     L.r32 = take(sizeof(float) * np);
+    L.z32 = take(sizeof(float) * np);
     L.p32 = take(sizeof(float) * np);
     L.q32 = take(sizeof(float) * np);
     L.delta = take(sizeof(float) * np);
@@ -1526,7 +1527,7 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     launch_fill(st, ctx->npad / 2, 0.0, ctx->dev<double>(L.kvp));
     ctx->kvp_valid = false;
     // FP32 vectors: zero bits (float zero) via the double fill over half the count
-    for (size_t off : {L.r32, L.p32, L.q32, L.delta})
+    for (size_t off : {L.r32, L.z32, L.p32, L.q32, L.delta})
         launch_fill(st, ctx->npad / 2, 0.0, ctx->dev<double>(off));
     launch_gates_to_f32(st, ctx->ionic_kind, ctx->npad, ctx->dev<double>(L.u), ctx->dev<float>(L.g32));
     const double inf = std::numeric_limits<double>::infinity();
@@ -1610,6 +1611,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     float *A32 = ctx->dev<float>(L.A32);
     float *dinv32 = ctx->dev<float>(L.dinv32), *r32 = ctx->dev<float>(L.r32);
     float *p32 = ctx->dev<float>(L.p32), *q32 = ctx->dev<float>(L.q32);
+    float *z32 = ctx->dev<float>(L.z32);
     float *delta = ctx->dev<float>(L.delta), *g32 = ctx->dev<float>(L.g32);
     mdx_status result = MDX_OK;
     ctx->iters_hist.clear();
@@ -1649,7 +1651,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             launch_rhs_learned(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm.out_scale, V, s,
                                mlp_y, b, X, r, q, kvp, mixed ? 1 : 0, part_pq, part0, nt_rhs);
             launch_init_finalize_ws(st, T, part_pq, part0, sp.rel_mode, sc);
-            launch_select(st, ctx->npad, V, q, X, r, mixed ? r32 : nullptr, delta, sc);
+            launch_select(st, ctx->npad, V, q, X, r, dinv32, mixed ? r32 : nullptr, z32, delta, sc);
         } else {
             if (ctx->rec_X)   // training-data recorder: raw features
                 launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm,
@@ -1657,7 +1659,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             float *kvp_out = want_kvp ? kvp : nullptr;
             if (mixed)
                 launch_rhs_init_mixed(st, T, P, Mv, Kv, dinv, dinv32, sp, V, Vprev, s, X, b, r32,
-                                      delta, part0, kdiag, kvp_out, nt_rhs);
+                                      z32, delta, part0, kdiag, kvp_out, nt_rhs);
             else
                 launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0, kdiag,
                                 kvp_out, nt_rhs);
@@ -1669,7 +1671,9 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         int units = 0;   // kernels carrying the SpMV launched so far
         bool done = false;
         if (mixed) {
-            launch_set_direction32(st, ctx->npad, dinv32, r32, p32, sc);
+            // two kernels per iteration; a chunk ends with the test of its
+            // last update and the (conditional) replacement
+            const int rr = ctx->opts.rr_interval;
             int it = 0;
             int chunk = std::max(1, ctx->last_iters);
             for (int guard = 0; !done && it < max_iter && guard < 2 * max_iter + 8; ++guard) {
@@ -1680,14 +1684,14 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                         e0 = ctx->ev[2 * units];
                         e1 = ctx->ev[2 * units + 1];
                     }
-                    launch_spmv32_dot(st, T, P, A32, p32, q32, part_pq, sc, e0, e1, nt_iter32);
-                    launch_cg_update32(st, T, it + i, part_pq, dinv32, p32, q32, delta, r32, part_rz,
-                                       sc);
-                    launch_cg_direction32(st, T, it + i, ctx->opts.rr_interval, max_iter, part_rz,
-                                          dinv32, r32, p32, sc);
+                    launch_cg_spmv32(st, T, it + i, rr, max_iter, P, A32, z32, p32, q32, part_rz,
+                                     part_pq, sc, e0, e1, nt_iter32);
+                    launch_cg_update32(st, T, it + i, part_pq, dinv32, p32, q32, delta, r32, z32,
+                                       part_rz, sc);
                     ++units;
                 }
-                launch_replacement(st, T, P, max_iter, Av, X, delta, b, dinv, dinv32, r32, p32,
+                launch_cg_test32(st, T, it + c, rr, max_iter, part_rz, sc);
+                launch_replacement(st, T, P, max_iter, Av, X, delta, b, dinv, dinv32, r32, z32,
                                    part0, sc, nt_iter64);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
@@ -1782,10 +1786,12 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             const int64_t work = std::min<int64_t>(
                 mixed ? ctx->sc_host->it_next : (done ? iters : max_iter), timed);
             ctx->stats.spmv_work += work;
-            // per nonzero: value + column; per row: p read once, q written once
-            // (the two-kernel FP64 scheme also reads r, D^-1, p_{k-1}, writes p_k)
+            // per nonzero: value + column.  Per row: FP64, p read once and q
+            // written once (the two-kernel FP64 scheme also reads r, D^-1,
+            // p_{k-1} and writes p_k); FP32, z read once, p and q read and
+            // written (q = A z + beta q, p = z + beta p)
             const double per_nnz = (mixed ? 4.0 : 8.0) + cbytes;
-            const double per_row = mixed ? 8.0 : ctx->iter_scheme == 1 ? 40.0 : 16.0;
+            const double per_row = mixed ? 20.0 : ctx->iter_scheme == 1 ? 40.0 : 16.0;
             ctx->stats.spmv_bytes +=
                 (double)work * (per_nnz * (double)ctx->nnz + per_row * (double)ctx->n);
         }

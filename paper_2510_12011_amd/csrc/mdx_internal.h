@@ -53,10 +53,11 @@ struct alignas(256) Scalars {
     // mixed-precision form: residual replacement protocol
     int32_t replace;    // a replacement is pending (iteration kernels idle): 1 the
                         // recursive residual passed the test, 2 periodic or cap
-    int32_t redirect;   // a replacement did not stop: p = z + beta p pending
+    int32_t restart_it; // iteration whose rho and beta were set by the
+                        // initialisation or a replacement (no test there)
     int32_t it_next;    // iterations completed (index of the next one)
     int32_t use_mlp;    // learned warm start: the MLP guess was chosen this step
-    double beta;        // beta after a replacement
+    double beta;        // beta of iteration restart_it
 };
 
 // standardisation of the learned warm start's features and output scale
@@ -145,23 +146,24 @@ void launch_to_f32(hipStream_t s, int64_t n, const double *a, float *b);
 void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                            const double *Kv, const double *dinv, const float *dinv32,
                            const StepParams &sp, const double *V, const double *Vprev,
-                           const double *src, double *x, double *b, float *r32, float *delta,
-                           double *partial, const double *kdiag, float *kvp, bool nt);
-void launch_set_direction32(hipStream_t s, int64_t n, const float *dinv32, const float *r32,
-                            float *p32, const Scalars *sc);
-void launch_spmv32_dot(hipStream_t s, const Tiling &t, SellView P, const float *A32,
-                       const float *p, float *q, double *partial, Scalars *sc,
-                       hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
+                           const double *src, double *x, double *b, float *r32, float *z32,
+                           float *delta, double *partial, const double *kdiag, float *kvp, bool nt);
+// iteration k: test (or restart point), q = A z + beta q, p = z + beta p, partial p.q
+void launch_cg_spmv32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter, SellView P,
+                      const float *A32, const float *z, float *p, float *q,
+                      const double *partial_rz, double *partial_pq, Scalars *sc,
+                      hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
+// iteration k: alpha, delta += alpha p, r -= alpha q, z = D^-1 r, partials r.z, z.z
 void launch_cg_update32(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
                         const float *dinv32, const float *p, const float *q, float *delta,
-                        float *r, double *partial_rz, Scalars *sc);
-void launch_cg_direction32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter,
-                           const double *partial_rz, const float *dinv32, const float *r, float *p,
-                           Scalars *sc);
-// flush, true residual, finalize, redirect (all no-ops unless a replacement is pending)
+                        float *r, float *z, double *partial_rz, Scalars *sc);
+// the test of iteration k alone (end of a chunk)
+void launch_cg_test32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter,
+                      const double *partial_rz, Scalars *sc);
+// flush, true residual, finalize (all no-ops unless a replacement is pending)
 void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const double *Av,
                         double *x, float *delta, const double *b, const double *dinv,
-                        const float *dinv32, float *r32, float *p32, double *partial, Scalars *sc,
+                        const float *dinv32, float *r32, float *z32, double *partial, Scalars *sc,
                         bool nt);
 
 // ---- learned warm start network (mdx_mlp.hip) ------------------------------
@@ -198,7 +200,8 @@ void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
                              int rel_mode, Scalars *sc);
 void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
-                   double *r, float *r32, float *delta, const Scalars *sc);
+                   double *r, const float *dinv32, float *r32, float *z32, float *delta,
+                   const Scalars *sc);
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv);
 
 // ---- batched form (mdx_batch.hip) -----------------------------------------

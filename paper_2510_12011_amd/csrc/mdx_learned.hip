@@ -161,16 +161,19 @@ __global__ __launch_bounds__(256) void k_init_finalize_ws(int groups, const doub
     sc->done = (z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
     sc->iters = 0;
     sc->replace = 0;
-    sc->redirect = 0;
+    sc->restart_it = 0;
+    sc->beta = 0.0;
     sc->it_next = 0;
 }
 
-// fallback: r = r_prev, x = V; then the FP32 residual / correction if the
-// iteration runs in FP32
+// fallback: r = r_prev, x = V; then the FP32 residual, z = D^-1 r and the
+// correction if the iteration runs in FP32
 __global__ __launch_bounds__(256) void k_select(int64_t n, const double *__restrict__ V,
                                                 const double *__restrict__ r_prev,
                                                 double *__restrict__ x, double *__restrict__ r,
-                                                float *__restrict__ r32, float *__restrict__ delta,
+                                                const float *__restrict__ dinv32,
+                                                float *__restrict__ r32, float *__restrict__ z32,
+                                                float *__restrict__ delta,
                                                 const Scalars *__restrict__ sc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -180,7 +183,9 @@ __global__ __launch_bounds__(256) void k_select(int64_t n, const double *__restr
         r[i] = r_prev[i];
     }
     if (r32) {
-        r32[i] = (float)r[i];
+        const float rf = (float)r[i];
+        r32[i] = rf;
+        z32[i] = dinv32[i] * rf;
         delta[i] = 0.0f;
     }
 }
@@ -257,10 +262,11 @@ void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, c
 }
 
 void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
-                   double *r, float *r32, float *delta, const Scalars *sc)
+                   double *r, const float *dinv32, float *r32, float *z32, float *delta,
+                   const Scalars *sc)
 {
-    hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(256), 0, s, n, V, r_prev, x, r, r32,
-                       delta, sc);
+    hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(256), 0, s, n, V, r_prev, x, r, dinv32,
+                       r32, z32, delta, sc);
 }
 
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv)

@@ -20,6 +20,17 @@
 // triggered by the recursive residual passing the test with p = z (the
 // recursion had drifted from the true residual; restart).
 //
+// Two kernels per iteration k (Algorithm 1's recurrences, regrouped):
+//   cg_spmv32    test of ||z_k|| on the previous update's partials (or, at a
+//                restart point, beta from the scalars); beta_k; then
+//                q = A p_k = A z_k + beta_k q_{k-1} and p_k = z_k + beta_k
+//                p_{k-1} by linearity of A: the gathers read z, the own rows
+//                update p and q; partial p_k . q
+//   cg_update32  alpha = rho_k / p_k.q; delta += alpha p; r -= alpha q;
+//                z = D^-1 r (stored); partials r.z, z.z
+// A chunk of iterations ends with cg_test32 (one workgroup), the same test,
+// so that a pass starts the replacement before the host reads the scalars.
+//
 // Kernels queued after convergence or while a replacement is pending return
 // at their first instruction; the replacement kernels return unless one is
 // pending.  Reductions are the deterministic two-level scheme of
@@ -50,8 +61,9 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
     const float *__restrict__ dinv32, StepParams sp, const double *__restrict__ V,
     const double *__restrict__ Vprev, const double *__restrict__ src, double *__restrict__ x,
-    double *__restrict__ b, float *__restrict__ r32, float *__restrict__ delta,
-    double *__restrict__ partial, const double *__restrict__ kdiag, float *__restrict__ kvp)
+    double *__restrict__ b, float *__restrict__ r32, float *__restrict__ z32,
+    float *__restrict__ delta, double *__restrict__ partial, const double *__restrict__ kdiag,
+    float *__restrict__ kvp)
 {
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
@@ -87,6 +99,7 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
         r32[row] = rf;
         delta[row] = 0.0f;
         const float zf = dinv32[row] * rf;
+        z32[row] = zf;
         const double zi = dinv[row] * ri, di = dinv[row] * bi;
         acc[0] += (double)rf * (double)zf;
         acc[1] += zi * zi;
@@ -95,28 +108,62 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
     write_partials<3>(acc, partial, t.groups, g);
 }
 
-__global__ __launch_bounds__(256) void k_set_direction32(int64_t n, const float *__restrict__ dinv32,
-                                                         const float *__restrict__ r32,
-                                                         float *__restrict__ p32,
-                                                         const Scalars *__restrict__ sc)
+// Stopping test of the mixed iteration on ||z_k|| (zn): 0 continue; 1 the
+// recursive residual passes; 2 periodic replacement (every rr iterations)
+// or the iteration cap.  A NaN stops the solve and flags it.
+__device__ __forceinline__ int test_z(Scalars *sc, double zn, int k, int rr, int max_iter,
+                                      bool lead)
 {
-    if (sc->done) return;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p32[i] = dinv32[i] * r32[i];
+    if (!(zn == zn)) {
+        if (lead) {
+            sc->nonfinite = 2;
+            sc->done = 1;
+            sc->iters = k;
+            sc->it_next = k;
+            sc->znorm = zn;
+        }
+        return -1;
+    }
+    const bool pass = zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_;
+    const int why = pass ? 1 : (rr > 0 && k % rr == 0) || k >= max_iter ? 2 : 0;
+    if (why && lead) {
+        sc->replace = why;
+        sc->it_next = k;
+        sc->znorm = zn;
+    }
+    return why;
 }
 
-// q = A p in FP32; partial p.q in FP64
+// Iteration k, first half (see the file comment).  All workgroups reduce the
+// same partials in the same order and take the same decision.
 template <bool NT, typename CI>
-__global__ __launch_bounds__(256) void k_spmv32_dot(Tiling t, const int64_t *__restrict__ slice_ptr,
-                                                    Cols<CI> col,
-                                                    const float *__restrict__ A32,
-                                                    const float *__restrict__ p,
-                                                    float *__restrict__ q,
-                                                    double *__restrict__ partial,
-                                                    Scalars *__restrict__ sc)
+__global__ __launch_bounds__(256) void k_cg_spmv32(Tiling t, int k, int rr, int max_iter,
+                                                   const int64_t *__restrict__ slice_ptr,
+                                                   Cols<CI> col, const float *__restrict__ A32,
+                                                   const float *__restrict__ z,
+                                                   float *__restrict__ p, float *__restrict__ q,
+                                                   const double *__restrict__ partial_rz,
+                                                   double *__restrict__ partial_pq,
+                                                   Scalars *__restrict__ sc)
 {
     if (halted(sc)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->redirect = 0;   // consumed by now
+    double beta;
+    if (sc->restart_it == k) {
+        beta = sc->beta;   // rho_k, beta_k set by the initialisation or the replacement
+    } else {
+        double v[2];
+        reduce_partials<2>(partial_rz, t.groups, v);
+        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+        const double zn = sqrt(v[1]);
+        if (test_z(sc, zn, k, rr, max_iter, lead)) return;
+        beta = v[0] / sc->rho[(k - 1) & 1];
+        if (lead) {
+            sc->rho[k & 1] = v[0];
+            sc->znorm = zn;
+        }
+    }
+    const bool fresh = beta == 0.0;   // p = z, q = A z: earlier p, q are not read
+    const float bf = (float)beta;
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
     double acc[1] = {0.0};
@@ -128,20 +175,25 @@ __global__ __launch_bounds__(256) void k_spmv32_dot(Tiling t, const int64_t *__r
         const int32_t cb = slice_base(col, sl);
         float sum = 0.0f;
 #pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(A32 + e) * p[cb + (int32_t)ld_stream<NT>(col.idx + e)];
-        q[row] = sum;
-        acc[0] += (double)p[row] * (double)sum;
+        for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(A32 + e) * z[cb + (int32_t)ld_stream<NT>(col.idx + e)];
+        const float pi = fresh ? z[row] : z[row] + bf * p[row];
+        const float qi = fresh ? sum : sum + bf * q[row];
+        p[row] = pi;
+        q[row] = qi;
+        acc[0] += (double)pi * (double)qi;
     }
-    write_partials<1>(acc, partial, t.groups, g);
+    write_partials<1>(acc, partial_pq, t.groups, g);
 }
 
+// Iteration k, second half: alpha_k = rho_k / (p_k . q); delta += alpha p;
+// r -= alpha q; z = D^-1 r; partials r.z and z.z for the next test.
 __global__ __launch_bounds__(256) void k_cg_update32(Tiling t, int k,
                                                      const double *__restrict__ partial_pq,
                                                      const float *__restrict__ dinv32,
                                                      const float *__restrict__ p,
                                                      const float *__restrict__ q,
                                                      float *__restrict__ delta,
-                                                     float *__restrict__ r,
+                                                     float *__restrict__ r, float *__restrict__ z,
                                                      double *__restrict__ partial_rz,
                                                      Scalars *__restrict__ sc)
 {
@@ -149,6 +201,7 @@ __global__ __launch_bounds__(256) void k_cg_update32(Tiling t, int k,
     double pq[1];
     reduce_partials<1>(partial_pq, t.groups, pq);
     const float alpha = (float)(sc->rho[k & 1] / pq[0]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->it_next = k + 1;
     const int g = logical_group(t.groups);
     double acc[2] = {0.0, 0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
@@ -158,58 +211,23 @@ __global__ __launch_bounds__(256) void k_cg_update32(Tiling t, int k,
         const float ri = r[i] - alpha * q[i];
         r[i] = ri;
         const float zi = dinv32[i] * ri;
+        z[i] = zi;
         acc[0] += (double)ri * (double)zi;
         acc[1] += (double)zi * (double)zi;
     }
     write_partials<2>(acc, partial_rz, t.groups, g);
 }
 
-// test of the recursive residual; request a replacement when it passes, every
-// rr iterations, or at the cap; otherwise beta and p = z + beta p
-__global__ __launch_bounds__(256) void k_cg_direction32(Tiling t, int k, int rr, int max_iter,
-                                                        const double *__restrict__ partial_rz,
-                                                        const float *__restrict__ dinv32,
-                                                        const float *__restrict__ r,
-                                                        float *__restrict__ p,
-                                                        Scalars *__restrict__ sc)
+// End of a chunk of iterations (one workgroup): the test k_cg_spmv32 would
+// apply at iteration k, so that a pass starts the replacement at once.
+__global__ __launch_bounds__(256) void k_cg_test32(int groups, int k, int rr, int max_iter,
+                                                   const double *__restrict__ partial_rz,
+                                                   Scalars *__restrict__ sc)
 {
-    if (halted(sc)) return;
+    if (halted(sc) || sc->restart_it == k) return;
     double v[2];
-    reduce_partials<2>(partial_rz, t.groups, v);
-    const double zn = sqrt(v[1]);
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (!(zn == zn)) {
-        if (lead) {
-            sc->nonfinite = 2;
-            sc->done = 1;
-            sc->iters = k + 1;
-            sc->it_next = k + 1;
-            sc->znorm = zn;
-        }
-        return;
-    }
-    const bool pass = zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_;
-    if (pass || (rr > 0 && (k + 1) % rr == 0) || k + 1 >= max_iter) {
-        if (lead) {
-            sc->replace = pass ? 1 : 2;   // 1: the recursive residual passed the test
-            sc->it_next = k + 1;
-            sc->znorm = zn;
-        }
-        return;
-    }
-    const double beta = v[0] / sc->rho[k & 1];
-    if (lead) {
-        sc->rho[(k + 1) & 1] = v[0];
-        sc->it_next = k + 1;
-        sc->znorm = zn;
-    }
-    const float bf = (float)beta;
-    const int g = logical_group(t.groups);
-    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
-    for (int tile = g * t.tpb; tile < t_end; ++tile) {
-        const int64_t i = (int64_t)tile * TILE + threadIdx.x;
-        p[i] = dinv32[i] * r[i] + bf * p[i];
-    }
+    reduce_partials<2>(partial_rz, groups, v);
+    test_z(sc, sqrt(v[1]), k, rr, max_iter, threadIdx.x == 0);
 }
 
 // replacement, part 1: x64 += delta, delta = 0
@@ -225,14 +243,14 @@ __global__ __launch_bounds__(256) void k_flush(int64_t n, double *__restrict__ x
     }
 }
 
-// replacement, part 2: r64 = b - A x64 in FP64, r32 = r64; partials r32.z32
-// and |D^-1 r64|^2
+// replacement, part 2: r64 = b - A x64 in FP64, r32 = r64, z32 = D^-1 r32;
+// partials r32.z32 and |D^-1 r64|^2
 template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_true_residual(
     Tiling t, const int64_t *__restrict__ slice_ptr, Cols<CI> col,
     const double *__restrict__ Av, const double *__restrict__ x, const double *__restrict__ b,
     const double *__restrict__ dinv, const float *__restrict__ dinv32, float *__restrict__ r32,
-    double *__restrict__ partial, const Scalars *__restrict__ sc)
+    float *__restrict__ z32, double *__restrict__ partial, const Scalars *__restrict__ sc)
 {
     if (!sc->replace || sc->done) return;
     const int g = logical_group(t.groups);
@@ -251,6 +269,7 @@ __global__ __launch_bounds__(256) void k_true_residual(
         const float rf = (float)ri;
         r32[row] = rf;
         const float zf = dinv32[row] * rf;
+        z32[row] = zf;
         const double zi = dinv[row] * ri;
         acc[0] += (double)rf * (double)zf;
         acc[1] += zi * zi;
@@ -259,7 +278,7 @@ __global__ __launch_bounds__(256) void k_true_residual(
 }
 
 // replacement, part 3 (one workgroup): stopping test on the true residual;
-// if it fails, rho and beta for continuing
+// if it fails, iteration it restarts from it with rho and beta set here
 __global__ __launch_bounds__(256) void k_replace_finalize(int groups, int max_iter,
                                                           const double *__restrict__ partial,
                                                           Scalars *__restrict__ sc)
@@ -291,19 +310,7 @@ __global__ __launch_bounds__(256) void k_replace_finalize(int groups, int max_it
     // recurrence (beta = rho_new / rho_old).
     sc->beta = why == 1 ? 0.0 : v[0] / sc->rho[(it - 1) & 1];
     sc->rho[it & 1] = v[0];
-    sc->redirect = 1;
-}
-
-// replacement, part 4: p = z + beta p after a replacement that did not stop
-__global__ __launch_bounds__(256) void k_redirect(int64_t n, const float *__restrict__ dinv32,
-                                                  const float *__restrict__ r,
-                                                  float *__restrict__ p,
-                                                  const Scalars *__restrict__ sc)
-{
-    if (!sc->redirect || sc->done) return;
-    const float bf = (float)sc->beta;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = dinv32[i] * r[i] + bf * p[i];
+    sc->restart_it = it;
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -318,56 +325,49 @@ void launch_to_f32(hipStream_t s, int64_t n, const double *a, float *b)
 void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                            const double *Kv, const double *dinv, const float *dinv32,
                            const StepParams &sp, const double *V, const double *Vprev,
-                           const double *src, double *x, double *b, float *r32, float *delta,
-                           double *partial, const double *kdiag, float *kvp, bool nt)
+                           const double *src, double *x, double *b, float *r32, float *z32,
+                           float *delta, double *partial, const double *kdiag, float *kvp, bool nt)
 {
     MDX_LAUNCH_SELL(P, nt, k_rhs_init_mixed, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
-                    Mv, Kv, dinv, dinv32, sp, V, Vprev, src, x, b, r32, delta, partial, kdiag, kvp);
+                    Mv, Kv, dinv, dinv32, sp, V, Vprev, src, x, b, r32, z32, delta, partial, kdiag,
+                    kvp);
 }
 
-void launch_set_direction32(hipStream_t s, int64_t n, const float *dinv32, const float *r32,
-                            float *p32, const Scalars *sc)
+void launch_cg_spmv32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter, SellView P,
+                      const float *A32, const float *z, float *p, float *q,
+                      const double *partial_rz, double *partial_pq, Scalars *sc,
+                      hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
 {
-    hipLaunchKernelGGL(k_set_direction32, dim3(blocks_for(n)), dim3(256), 0, s, n, dinv32, r32, p32,
-                       sc);
-}
-
-void launch_spmv32_dot(hipStream_t s, const Tiling &t, SellView P, const float *A32,
-                       const float *p, float *q, double *partial, Scalars *sc,
-                       hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
-{
-    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_spmv32_dot, dim3(t.groups), dim3(TILE), 0, s, t,
-                       P.slice_ptr, cols, A32, p, q, partial, sc);
+    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_cg_spmv32, dim3(t.groups), dim3(TILE), 0, s, t, k,
+                       rr, max_iter, P.slice_ptr, cols, A32, z, p, q, partial_rz, partial_pq, sc);
 }
 
 void launch_cg_update32(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
                         const float *dinv32, const float *p, const float *q, float *delta,
-                        float *r, double *partial_rz, Scalars *sc)
+                        float *r, float *z, double *partial_rz, Scalars *sc)
 {
     hipLaunchKernelGGL(k_cg_update32, dim3(t.groups), dim3(TILE), 0, s, t, k, partial_pq, dinv32, p,
-                       q, delta, r, partial_rz, sc);
+                       q, delta, r, z, partial_rz, sc);
 }
 
-void launch_cg_direction32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter,
-                           const double *partial_rz, const float *dinv32, const float *r, float *p,
-                           Scalars *sc)
+void launch_cg_test32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter,
+                      const double *partial_rz, Scalars *sc)
 {
-    hipLaunchKernelGGL(k_cg_direction32, dim3(t.groups), dim3(TILE), 0, s, t, k, rr, max_iter,
-                       partial_rz, dinv32, r, p, sc);
+    hipLaunchKernelGGL(k_cg_test32, dim3(1), dim3(TILE), 0, s, t.groups, k, rr, max_iter, partial_rz,
+                       sc);
 }
 
 void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const double *Av,
                         double *x, float *delta, const double *b, const double *dinv,
-                        const float *dinv32, float *r32, float *p32, double *partial, Scalars *sc,
+                        const float *dinv32, float *r32, float *z32, double *partial, Scalars *sc,
                         bool nt)
 {
     const int64_t n = t.n_rows;
     hipLaunchKernelGGL(k_flush, dim3(blocks_for(n)), dim3(256), 0, s, n, x, delta, sc);
     MDX_LAUNCH_SELL(P, nt, k_true_residual, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
-                    Av, x, b, dinv, dinv32, r32, partial, sc);
+                    Av, x, b, dinv, dinv32, r32, z32, partial, sc);
     hipLaunchKernelGGL(k_replace_finalize, dim3(1), dim3(TILE), 0, s, t.groups, max_iter, partial,
                        sc);
-    hipLaunchKernelGGL(k_redirect, dim3(blocks_for(n)), dim3(256), 0, s, n, dinv32, r32, p32, sc);
 }
 
 }  // namespace mdx
