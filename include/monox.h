@@ -197,10 +197,12 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
 /* Launch-shape tuning (no effect on results beyond rounding order):
  *   MDX_TUNE_MAX_GROUPS  cap on workgroups of the row-tiled kernels
  *                        (16..65536, default 2048);
- *   MDX_TUNE_ITER_SCHEME PCG iteration as three kernels (0: SpMV, update,
- *                        direction; default) or two kernels (1: the
- *                        direction is formed per gathered column inside
- *                        the SpMV);
+ *   MDX_TUNE_ITER_SCHEME plain FP64 PCG iteration as three kernels (0:
+ *                        SpMV, update, direction) or two kernels (1: the
+ *                        SpMV kernel forms q = A p = A z + beta q and
+ *                        p = z + beta p, A being linear, so its gathers
+ *                        read z only).  The mixed-precision iteration
+ *                        always takes the two-kernel form;
  *   MDX_TUNE_FORMAT      batched context: storage the iteration's FP32 SpMV
  *                        reads, 0 sliced ELL (default; 1 lane per row),
  *                        1 CSR (no padding; 8 lanes per row), 2 sliced

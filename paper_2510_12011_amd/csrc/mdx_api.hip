@@ -1709,22 +1709,21 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             // iteration u, which tests ||z_u||.  Units 0..c detect convergence
             // in <= c iterations with no idle launch.  First chunk: the
             // previous step's count; then one unit at a time.
+            double *p = pbuf[0], *z = pbuf[1];
             int chunk = std::max(1, ctx->last_iters) + 1;
             while (!done && units <= max_iter) {
                 const int c = std::min(chunk, max_iter + 1 - units);
                 for (int i = 0; i < c; ++i) {
                     const int u_ = units + i;
                     if (u_ >= 1)
-                        launch_cg_update(st, T, u_ - 1, part_pq, dinv, pbuf[(u_ - 1) & 1], q, X, r,
-                                         part_rz, sc);
+                        launch_cg_update(st, T, u_ - 1, part_pq, dinv, p, q, X, r, z, part_rz, sc);
                     hipEvent_t e0 = nullptr, e1 = nullptr;
                     if (ctx->profiling && 2 * u_ + 1 < (int)ctx->ev.size()) {
                         e0 = ctx->ev[2 * u_];
                         e1 = ctx->ev[2 * u_ + 1];
                     }
-                    launch_cg_direction_spmv(st, T, u_, max_iter, P, Av, dinv, r,
-                                             pbuf[(u_ + 1) & 1], pbuf[u_ & 1], q, part_rz,
-                                             part_pq, sc, e0, e1, nt_iter64);
+                    launch_cg_spmv(st, T, u_, max_iter, P, Av, dinv, r, z, p, q, part_rz, part_pq,
+                                   sc, e0, e1, nt_iter64);
                 }
                 units += c;
                 HIPCHK(hipGetLastError());
@@ -1754,7 +1753,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                         e1 = ctx->ev[2 * it + 1];
                     }
                     launch_spmv_dot(st, T, P, Av, p, q, part_pq, &sc->done, e0, e1, nt_iter64);
-                    launch_cg_update(st, T, it, part_pq, dinv, p, q, X, r, part_rz, sc);
+                    launch_cg_update(st, T, it, part_pq, dinv, p, q, X, r, nullptr, part_rz, sc);
                     launch_cg_direction(st, T, it, part_rz, dinv, r, p, sc);
                 }
                 units += c;
@@ -1786,10 +1785,10 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             const int64_t work = std::min<int64_t>(
                 mixed ? ctx->sc_host->it_next : (done ? iters : max_iter), timed);
             ctx->stats.spmv_work += work;
-            // per nonzero: value + column.  Per row: FP64, p read once and q
-            // written once (the two-kernel FP64 scheme also reads r, D^-1,
-            // p_{k-1} and writes p_k); FP32, z read once, p and q read and
-            // written (q = A z + beta q, p = z + beta p)
+            // per nonzero: value + column.  Per row: the three-kernel FP64
+            // scheme reads p once and writes q once; the two-kernel schemes
+            // read z once and read and write p and q (q = A z + beta q,
+            // p = z + beta p)
             const double per_nnz = (mixed ? 4.0 : 8.0) + cbytes;
             const double per_row = mixed ? 20.0 : ctx->iter_scheme == 1 ? 40.0 : 16.0;
             ctx->stats.spmv_bytes +=

@@ -322,21 +322,22 @@ void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial,
 void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *Av,
                      const double *p, double *q, double *partial, const int32_t *done,
                      hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
-// PCG iteration k, first half (test of ||z_k||, beta_k, q = A p_k, partial p_k.q)
-void launch_cg_direction_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
-                              const double *Av, const double *dinv, const double *r,
-                              const double *p_prev, double *p_cur, double *q,
-                              const double *partial_rz, double *partial_pq, Scalars *sc,
-                              hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
+// PCG iteration k, first half: test of ||z_k||, beta_k, q = A z_k + beta_k q,
+// p = z_k + beta_k p (in place), partial p_k.q
+void launch_cg_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
+                    const double *Av, const double *dinv, const double *r, const double *z,
+                    double *p, double *q, const double *partial_rz, double *partial_pq,
+                    Scalars *sc, hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
 // three-kernel scheme: direction update (test, beta, p = z + beta p) and p_0 = z_0
 void launch_cg_direction(hipStream_t s, const Tiling &t, int k, const double *partial_rz,
                          const double *dinv, const double *r, double *p, Scalars *sc);
 void launch_set_direction(hipStream_t s, int64_t n, const double *dinv, const double *r, double *p,
                           const Scalars *sc);
-// PCG iteration k, second half (alpha_k, x and r update, partials r.z, z.z)
+// PCG iteration k, second half (alpha_k, x and r update, z = D^-1 r stored
+// when z is non-null, partials r.z, z.z)
 void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
                       const double *dinv, const double *p, const double *q, double *x, double *r,
-                      double *partial_rz, Scalars *sc);
+                      double *z, double *partial_rz, Scalars *sc);
 void launch_epilogue(hipStream_t s, int64_t n, double t1, const double *Vold, const double *Vnew,
                      double *lat, double *lrt, Scalars *sc);
 

@@ -8,13 +8,16 @@
 //                 per-workgroup partials of r.z, z.z, |D^-1 b|^2
 //   init_finalize rho_0, ||z_0||, the stopping reference, done if z_0 is at the
 //                 rounding floor
-//   per iteration k (two kernels):
-//   cg_direction_spmv  (k >= 1) ||z_k||; stop if ||z_k|| < atol, < rtol * ref
+//   per iteration k (two kernels, the default):
+//   cg_spmv       (k >= 1) ||z_k||; stop if ||z_k|| < atol, < rtol * ref
 //                 or at the floor; beta_k = rho_k / rho_{k-1};
-//                 q = A p_k with p_k = z_k + beta_k p_{k-1} formed per gathered
-//                 column; partial p_k . q
+//                 q = A p_k = A z_k + beta_k q_{k-1} and p_k = z_k + beta_k
+//                 p_{k-1} (A is linear: the gathers read z only); partial
+//                 p_k . q
 //   cg_update     alpha = rho_k / p_k.q; x += alpha p_k; r -= alpha q;
-//                 z = D^-1 r; partials r.z, z.z
+//                 z = D^-1 r (stored); partials r.z, z.z
+//   or three kernels: spmv_dot (q = A p, partial p.q), cg_update,
+//   cg_direction (test, beta, p = z + beta p)
 //   spmv_dot      plain q = A p with partial p.q (inspection entry point)
 //   epilogue      activation / repolarisation times, non-finite check
 //
@@ -169,17 +172,17 @@ __global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__res
 // Iteration k, first half.  For k >= 1 every workgroup reduces the r.z and
 // z.z partials of the previous update, applies the stopping test to
 // ||z_k|| (Algorithm 1, with z formed before the test), and forms
-// beta_k = rho_k / rho_{k-1}.  Then q = A p_k, where the direction
-// p_k = D^-1 r_k + beta_k p_{k-1} (p_0 = z_0) is formed on the fly for every
-// gathered column, so no separate direction pass is needed; own rows store
-// p_k (double-buffered against p_{k-1}) and a partial of p_k . q.
+// beta_k = rho_k / rho_{k-1}.  Then, A being linear,
+//   q = A p_k = A z_k + beta_k q_{k-1},   p_k = z_k + beta_k p_{k-1}:
+// the gathers read z_k only (for k = 0, z_0 = D^-1 r_0 formed per gathered
+// column), own rows update p and q in place; partial p_k . q.
 // k == max_iter only tests.
 template <bool NT, typename CI>
-__global__ __launch_bounds__(256) void k_cg_direction_spmv(
+__global__ __launch_bounds__(256) void k_cg_spmv(
     Tiling t, int k, int max_iter, const int64_t *__restrict__ slice_ptr,
     Cols<CI> col, const double *__restrict__ Av,
     const double *__restrict__ dinv, const double *__restrict__ r,
-    const double *__restrict__ p_prev, double *__restrict__ p_cur, double *__restrict__ q,
+    const double *__restrict__ z, double *__restrict__ p, double *__restrict__ q,
     const double *__restrict__ partial_rz, double *__restrict__ partial_pq,
     Scalars *__restrict__ sc)
 {
@@ -221,36 +224,39 @@ __global__ __launch_bounds__(256) void k_cg_direction_spmv(
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
         const int32_t cb = slice_base(col, sl);
-        double sum = 0.0;
+        double sum = 0.0, pi, qi;
         if (k == 0) {
 #pragma unroll 4
             for (int64_t e = beg; e < end; e += SLICE) {
                 const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
                 sum += ld_stream<NT>(Av + e) * (dinv[c] * r[c]);
             }
+            pi = dinv[row] * r[row];
+            qi = sum;
         } else {
 #pragma unroll 4
-            for (int64_t e = beg; e < end; e += SLICE) {
-                const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
-                sum += ld_stream<NT>(Av + e) * (dinv[c] * r[c] + beta * p_prev[c]);
-            }
+            for (int64_t e = beg; e < end; e += SLICE)
+                sum += ld_stream<NT>(Av + e) * z[cb + (int32_t)ld_stream<NT>(col.idx + e)];
+            pi = z[row] + beta * p[row];
+            qi = sum + beta * q[row];
         }
-        const double pi = k == 0 ? dinv[row] * r[row] : dinv[row] * r[row] + beta * p_prev[row];
-        p_cur[row] = pi;
-        q[row] = sum;
-        acc[0] += pi * sum;
+        p[row] = pi;
+        q[row] = qi;
+        acc[0] += pi * qi;
     }
     write_partials<1>(acc, partial_pq, t.groups, g);
 }
 
 // Iteration k, second half: alpha_k = rho_k / (p_k . q); x += alpha p_k;
-// r -= alpha q; z = D^-1 r; partials r.z and z.z for the next test.
+// r -= alpha q; z = D^-1 r (stored when z is given); partials r.z and z.z
+// for the next test.
 __global__ __launch_bounds__(256) void k_cg_update(Tiling t, int k,
                                                    const double *__restrict__ partial_pq,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ p,
                                                    const double *__restrict__ q,
                                                    double *__restrict__ x, double *__restrict__ r,
+                                                   double *__restrict__ z,
                                                    double *__restrict__ partial_rz,
                                                    Scalars *__restrict__ sc)
 {
@@ -267,6 +273,7 @@ __global__ __launch_bounds__(256) void k_cg_update(Tiling t, int k,
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
         const double zi = dinv[i] * ri;
+        if (z) z[i] = zi;
         acc[0] += ri * zi;
         acc[1] += zi * zi;
     }
@@ -385,23 +392,22 @@ void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *A
                        P.slice_ptr, cols, Av, p, q, partial, done);
 }
 
-void launch_cg_direction_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
-                              const double *Av, const double *dinv, const double *r,
-                              const double *p_prev, double *p_cur, double *q,
-                              const double *partial_rz, double *partial_pq, Scalars *sc,
-                              hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
+void launch_cg_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
+                    const double *Av, const double *dinv, const double *r, const double *z,
+                    double *p, double *q, const double *partial_rz, double *partial_pq,
+                    Scalars *sc, hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
 {
-    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_cg_direction_spmv, dim3(t.groups), dim3(TILE), 0,
-                       s, t, k, max_iter, P.slice_ptr, cols, Av, dinv, r, p_prev, p_cur, q,
-                       partial_rz, partial_pq, sc);
+    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_cg_spmv, dim3(t.groups), dim3(TILE), 0, s, t, k,
+                       max_iter, P.slice_ptr, cols, Av, dinv, r, z, p, q, partial_rz, partial_pq,
+                       sc);
 }
 
 void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
                       const double *dinv, const double *p, const double *q, double *x, double *r,
-                      double *partial_rz, Scalars *sc)
+                      double *z, double *partial_rz, Scalars *sc)
 {
     hipLaunchKernelGGL(k_cg_update, dim3(t.groups), dim3(TILE), 0, s, t, k, partial_pq, dinv, p, q,
-                       x, r, partial_rz, sc);
+                       x, r, z, partial_rz, sc);
 }
 
 void launch_cg_direction(hipStream_t s, const Tiling &t, int k, const double *partial_rz,

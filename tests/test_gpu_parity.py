@@ -107,8 +107,10 @@ def test_ionic_step_parity(kind):
     assert n > 0
 
 
-def _compare_run(spec, n_steps, out_every, lat_bar=None):
+def _compare_run(spec, n_steps, out_every, lat_bar=None, scheme=None):
     s = _sim(spec)
+    if scheme is not None:
+        s.set_tuning(iter_scheme=scheme)
     o = orc.Oracle(spec)
     v_or, it_or = o.steps(n_steps, out_every=out_every)
     v_gpu, status = s.run(n_steps, out_every=out_every)
@@ -138,6 +140,14 @@ def test_trajectory_parity_box_tt():
     """Anisotropic jittered box, ten Tusscher-Panfilov, 400 steps."""
     spec = inputs.small_box(nx=10, ny=8, nz=6, ionic="tt", n_steps=400, stim_extent=0.5)
     _compare_run(spec, 400, 50)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_trajectory_parity_iteration_schemes(scheme):
+    """Both layouts of the PCG iteration (three kernels; two kernels with
+    q = A z + beta q) follow the oracle."""
+    spec = inputs.small_box(nx=10, ny=8, nz=6, ionic="tt", n_steps=300, stim_extent=0.5)
+    _compare_run(spec, 300, 100, scheme=scheme)
 
 
 @pytest.mark.parametrize("theta,ws,rel", [(1.0, 0, 0), (0.5, 0, 1), (0.0, 1, 0)])
