@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -102,6 +103,10 @@ struct mdx_ctx {
     std::vector<char> active;  // stimuli currently summed into istim
 
     Scalars *sc_host = nullptr;   // pinned
+    // end-of-chunk scalars: coherent pinned memory the device writes and the
+    // host polls (pub_dev: its device address)
+    Published *pub = nullptr, *pub_dev = nullptr;
+    int32_t pub_seq = 0;
     double *stage = nullptr;      // pinned, npad doubles
 
     // learned warm start
@@ -526,6 +531,29 @@ StepParams step_params(const mdx_ctx *c)
 }
 
 // Rebuild istim if the set of stimuli active at step k changed.
+// Wait for the publish numbered seq and copy the scalars it carries to
+// sc_host.  The host spins on the sequence number (no blocking sync, no copy
+// kernel); should the stream drain without it, the memory is not coherent as
+// promised and the call fails.
+mdx_status wait_published(mdx_ctx *ctx, hipStream_t st, int32_t seq)
+{
+    for (uint64_t n = 1; ctx->pub->seq != seq; ++n) {
+        if (n % 1024 == 0) {
+            const hipError_t q = hipStreamQuery(st);
+            if (q == hipSuccess) {
+                std::atomic_thread_fence(std::memory_order_seq_cst);
+                if (ctx->pub->seq == seq) break;
+                return fail(ctx, MDX_ERR_DEVICE, "published solver scalars not visible on the host");
+            }
+            if (q != hipErrorNotReady) HIPCHK(q);
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    std::memcpy(ctx->sc_host, (const void *)&ctx->pub->s, sizeof(Scalars));
+    return MDX_OK;
+}
+
 mdx_status update_stimulus(mdx_ctx *ctx, hipStream_t st, int64_t k, bool &any)
 {
     std::vector<char> want(ctx->stims.size(), 0);
@@ -1207,6 +1235,15 @@ mdx_status mdx_create(mdx_ctx **out, int device, void *stream)
         delete ctx;
         return MDX_ERR_DEVICE;
     }
+    if (hipHostMalloc((void **)&ctx->pub, sizeof(Published),
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&ctx->pub_dev, ctx->pub, 0) != hipSuccess) {
+        if (ctx->pub) (void)hipHostFree(ctx->pub);
+        (void)hipHostFree(ctx->sc_host);
+        delete ctx;
+        return MDX_ERR_DEVICE;
+    }
+    ctx->pub->seq = 0;
     *out = ctx;
     return MDX_OK;
 }
@@ -1228,6 +1265,7 @@ void mdx_destroy(mdx_ctx *ctx)
     }
     if (ctx->bsc_host) (void)hipHostFree(ctx->bsc_host);
     if (ctx->sc_host) (void)hipHostFree(ctx->sc_host);
+    if (ctx->pub) (void)hipHostFree(ctx->pub);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     delete ctx;
 }
@@ -1622,6 +1660,17 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     const bool nt_iter64 = use_nt(ctx, (8.0 + cbytes) * slots(ctx));  // FP64 A and columns
     const bool nt_iter32 = use_nt(ctx, (4.0 + cbytes) * slots(ctx));  // FP32 A and columns
     auto t_start = std::chrono::steady_clock::now();
+    double *lat = ctx->dev<double>(L.lat), *lrt = ctx->dev<double>(L.lrt);
+    // ionic update from Vk: s = I_stim - I_ion (with a guard: only if *guard)
+    auto queue_ionic = [&](const double *Vk, const double *istim_k, const int32_t *guard) {
+        if (gates32)
+            launch_ionic_step_mixed(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
+                                    ctx->dt, ctx->cm, Vk, u, g32, istim_k, s, nullptr, guard);
+        else
+            launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
+                              ctx->dt, ctx->cm, Vk, u, istim_k, s, 0, nullptr, guard);
+    };
+    bool ionic_queued = false;   // this step's ionic update was queued by the previous step
 
     for (int64_t j = 0; j < n_steps; ++j) {
         const int64_t k = ctx->step;
@@ -1632,12 +1681,8 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         const double *istim = any_stim ? ctx->dev<double>(L.istim) : nullptr;
 
         // ---- ionic update: s = I_stim - I_ion ----
-        if (gates32)
-            launch_ionic_step_mixed(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
-                                    ctx->dt, ctx->cm, V, u, g32, istim, s);
-        else
-            launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
-                              ctx->dt, ctx->cm, V, u, istim, s, 0);
+        if (!ionic_queued) queue_ionic(V, istim, nullptr);
+        ionic_queued = false;
 
         // ---- right-hand side, warm start, initial residual ----
         // the learned warm start and the recorder need the neighbour feature
@@ -1670,6 +1715,29 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         // ---- PCG ----
         int units = 0;   // kernels carrying the SpMV launched so far
         bool done = false;
+        // End of a chunk of iterations: the epilogue (activation times; it
+        // acts once the solve is done and is idempotent), the scalars
+        // published to host memory, and the next step's ionic update (it acts
+        // only if this solve is done), which keeps the device busy while the
+        // host reads the scalars and queues the rest of that step.
+        const double t1 = (double)(k + 1) * ctx->dt;
+        bool next_queued = false;
+        auto end_chunk = [&]() -> mdx_status {
+            launch_epilogue(st, ctx->n, t1, V, X, lat, lrt, sc, &sc->done);
+            launch_publish(st, sc, ctx->pub_dev, ++ctx->pub_seq);
+            if (j + 1 < n_steps) {
+                bool any_next = false;
+                if (mdx_status e = update_stimulus(ctx, st, k + 1, any_next)) return e;
+                queue_ionic(X, any_next ? ctx->dev<double>(L.istim) : nullptr, &sc->done);
+                next_queued = true;
+            }
+            HIPCHK(hipGetLastError());
+            auto w0 = std::chrono::steady_clock::now();
+            if (mdx_status e = wait_published(ctx, st, ctx->pub_seq)) return e;
+            ctx->stats.host_wait_seconds +=
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+            return MDX_OK;
+        };
         if (mixed) {
             // two kernels per iteration; a chunk ends with the test of its
             // last update and the (conditional) replacement
@@ -1693,12 +1761,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                 launch_cg_test32(st, T, it + c, rr, max_iter, part_rz, sc);
                 launch_replacement(st, T, P, max_iter, Av, X, delta, b, dinv, dinv32, r32, z32,
                                    part0, sc, nt_iter64);
-                HIPCHK(hipGetLastError());
-                HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-                auto w0 = std::chrono::steady_clock::now();
-                HIPCHK(hipStreamSynchronize(st));
-                ctx->stats.host_wait_seconds +=
-                    std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+                if (mdx_status e = end_chunk()) return e;
                 done = ctx->sc_host->done != 0;
                 it = ctx->sc_host->it_next;
                 chunk = 1;
@@ -1726,12 +1789,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                                    sc, e0, e1, nt_iter64);
                 }
                 units += c;
-                HIPCHK(hipGetLastError());
-                HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-                auto w0 = std::chrono::steady_clock::now();
-                HIPCHK(hipStreamSynchronize(st));
-                ctx->stats.host_wait_seconds +=
-                    std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+                if (mdx_status e = end_chunk()) return e;
                 done = ctx->sc_host->done != 0;
                 chunk = 1;
             }
@@ -1757,12 +1815,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                     launch_cg_direction(st, T, it, part_rz, dinv, r, p, sc);
                 }
                 units += c;
-                HIPCHK(hipGetLastError());
-                HIPCHK(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-                auto w0 = std::chrono::steady_clock::now();
-                HIPCHK(hipStreamSynchronize(st));
-                ctx->stats.host_wait_seconds +=
-                    std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+                if (mdx_status e = end_chunk()) return e;
                 done = ctx->sc_host->done != 0;
                 chunk = 1;
             }
@@ -1776,6 +1829,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         ctx->last_iters = done ? iters : max_iter;
         if (ctx->profiling) {
             const int timed = std::min(units, (int)ctx->ev.size() / 2);
+            if (timed > 0) HIPCHK(hipEventSynchronize(ctx->ev[2 * timed - 1]));
             for (int u_ = 0; u_ < timed; ++u_) {
                 float ms = 0.0f;
                 HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2 * u_], ctx->ev[2 * u_ + 1]));
@@ -1794,8 +1848,9 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             ctx->stats.spmv_bytes +=
                 (double)work * (per_nnz * (double)ctx->nnz + per_row * (double)ctx->n);
         }
-        launch_epilogue(st, ctx->n, (double)(k + 1) * ctx->dt, V, X, ctx->dev<double>(L.lat),
-                        ctx->dev<double>(L.lrt), sc);
+        ionic_queued = next_queued && done;
+        if (!done)   // iteration cap: the guarded epilogue did not act
+            launch_epilogue(st, ctx->n, t1, V, X, lat, lrt, sc);
         // rotate: V^{k+1} <- x, V^k -> V^{k-1}
         int old_prev = ctx->vb[1];
         ctx->vb[1] = ctx->vb[0];

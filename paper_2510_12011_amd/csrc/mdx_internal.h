@@ -60,6 +60,13 @@ struct alignas(256) Scalars {
     double beta;        // beta of iteration restart_it
 };
 
+// Scalars as published to host memory (coherent pinned): the host spins on
+// seq, written after the copy of s
+struct Published {
+    Scalars s;
+    alignas(64) volatile int32_t seq;
+};
+
 // standardisation of the learned warm start's features and output scale
 struct MlpNorm {
     float mean[4];
@@ -118,9 +125,13 @@ void launch_ionic_init(hipStream_t s, int kind, const double *params, int64_t n,
                        double *V, double *Vprev, double *u, const int32_t *tile_real = nullptr);
 // u advanced in place from V; out[i] = istim[i] - cm * I_ion/Cm if raw == 0,
 // or I_ion/Cm (mV/ms) if raw != 0.  istim may be null (no active stimulus).
+// With a guard, the kernel does nothing unless *guard is non-zero when it
+// runs (a step's update queued before its predecessor's solve is known to be
+// done).
 void launch_ionic_step(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                        double dt, double cm, const double *V, double *u, const double *istim,
-                       double *out, int raw, const int32_t *tile_real = nullptr);
+                       double *out, int raw, const int32_t *tile_real = nullptr,
+                       const int32_t *guard = nullptr);
 
 // Mixed-precision form: gates in FP32 (g32, ionic_gate_rows(kind) rows of ld
 // floats), concentrations and the current in FP64 (u).  The FP64 array u
@@ -131,7 +142,8 @@ int ionic_gate_row0(int kind);
 void launch_ionic_step_mixed(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                              double dt, double cm, const double *V, double *u, float *g32,
                              const double *istim, double *out,
-                             const int32_t *tile_real = nullptr);
+                             const int32_t *tile_real = nullptr,
+                             const int32_t *guard = nullptr);
 void launch_gates_to_f32(hipStream_t s, int kind, int64_t ld, const double *u, float *g32);
 void launch_gates_to_f64(hipStream_t s, int kind, int64_t ld, const float *g32, double *u);
 
@@ -338,7 +350,12 @@ void launch_set_direction(hipStream_t s, int64_t n, const double *dinv, const do
 void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
                       const double *dinv, const double *p, const double *q, double *x, double *r,
                       double *z, double *partial_rz, Scalars *sc);
+// activation / repolarisation times at t1 and the non-finite check; with a
+// guard, only once *guard is non-zero (idempotent: it may be queued after
+// every chunk of a solve)
 void launch_epilogue(hipStream_t s, int64_t n, double t1, const double *Vold, const double *Vnew,
-                     double *lat, double *lrt, Scalars *sc);
+                     double *lat, double *lrt, Scalars *sc, const int32_t *guard = nullptr);
+// the scalars copied to host-visible memory, then seq (after a system fence)
+void launch_publish(hipStream_t s, const Scalars *sc, Published *pub, int32_t seq);
 
 }  // namespace mdx

@@ -373,8 +373,10 @@ __global__ __launch_bounds__(256) void k_ionic_step(IonicParams P, int64_t n, in
                                                     double *__restrict__ u,
                                                     const double *__restrict__ istim,
                                                     double *__restrict__ out, int raw,
-                                                    const int32_t *__restrict__ tile_real)
+                                                    const int32_t *__restrict__ tile_real,
+                                                    const int32_t *__restrict__ guard)
 {
+    if (guard && !*guard) return;   // enqueued ahead of a solve that is not done
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (!real_row(i, n, tile_real)) {
@@ -436,8 +438,10 @@ __global__ __launch_bounds__(256) void k_ionic_step_mixed(IonicParams P, int64_t
                                                           float *__restrict__ g32,
                                                           const double *__restrict__ istim,
                                                           double *__restrict__ out,
-                                                          const int32_t *__restrict__ tile_real)
+                                                          const int32_t *__restrict__ tile_real,
+                                                          const int32_t *__restrict__ guard)
 {
+    if (guard && !*guard) return;   // enqueued ahead of a solve that is not done
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (!real_row(i, n, tile_real)) {
@@ -517,20 +521,20 @@ void launch_ionic_init(hipStream_t s, int kind, const double *params, int64_t n,
 
 void launch_ionic_step(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                        double dt, double cm, const double *V, double *u, const double *istim,
-                       double *out, int raw, const int32_t *tile_real)
+                       double *out, int raw, const int32_t *tile_real, const int32_t *guard)
 {
     if (n <= 0) return;
     IonicParams P = pack(kind, params);
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (kind == 1)
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw, tile_real);
+                           istim, out, raw, tile_real, guard);
     else if (kind == 2)
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw, tile_real);
+                           istim, out, raw, tile_real, guard);
     else
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw, tile_real);
+                           istim, out, raw, tile_real, guard);
 }
 
 int ionic_gate_rows(int kind) { return kind == 1 ? 1 : kind == 2 ? 12 : 0; }
@@ -538,20 +542,21 @@ int ionic_gate_row0(int kind) { return kind == 1 ? 0 : kind == 2 ? 6 : 0; }
 
 void launch_ionic_step_mixed(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                              double dt, double cm, const double *V, double *u, float *g32,
-                             const double *istim, double *out, const int32_t *tile_real)
+                             const double *istim, double *out, const int32_t *tile_real,
+                             const int32_t *guard)
 {
     if (n <= 0) return;
     IonicParams P = pack(kind, params);
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (kind == 1)
         hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, dt, cm, V,
-                           u, g32, istim, out, tile_real);
+                           u, g32, istim, out, tile_real, guard);
     else if (kind == 2)
         hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, dt, cm, V,
-                           u, g32, istim, out, tile_real);
+                           u, g32, istim, out, tile_real, guard);
     else
         hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, dt, cm,
-                           V, u, g32, istim, out, tile_real);
+                           V, u, g32, istim, out, tile_real, guard);
 }
 
 void launch_gates_to_f32(hipStream_t s, int kind, int64_t ld, const double *u, float *g32)

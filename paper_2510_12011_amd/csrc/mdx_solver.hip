@@ -339,8 +339,10 @@ __global__ __launch_bounds__(256) void k_set_direction(int64_t n, const double *
 __global__ __launch_bounds__(256) void k_epilogue(int64_t n, double t1, const double *__restrict__ Vold,
                                                   const double *__restrict__ Vnew,
                                                   double *__restrict__ lat, double *__restrict__ lrt,
-                                                  Scalars *__restrict__ sc)
+                                                  Scalars *__restrict__ sc,
+                                                  const int32_t *__restrict__ guard)
 {
+    if (guard && !*guard) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double vn = Vnew[i];
@@ -351,6 +353,21 @@ __global__ __launch_bounds__(256) void k_epilogue(int64_t n, double t1, const do
         lat[i] = t1;
     }
     if (!isinf(l) && l < t1 && isinf(lrt[i]) && vn < -70.0 && vn < Vold[i]) lrt[i] = t1;
+}
+
+// One wavefront: the scalars (whole 4-byte words) into host-visible memory,
+// a system-scope fence, then the sequence number the host waits for.
+__global__ __launch_bounds__(64) void k_publish(const Scalars *__restrict__ sc, Published *pub,
+                                                int32_t seq)
+{
+    static_assert(sizeof(Scalars) % 4 == 0, "whole words");
+    constexpr int words = (int)(sizeof(Scalars) / 4);
+    const int32_t *src = reinterpret_cast<const int32_t *>(sc);
+    int32_t *dst = reinterpret_cast<int32_t *>(&pub->s);
+    for (int w = threadIdx.x; w < words; w += 64) dst[w] = src[w];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) pub->seq = seq;
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -424,11 +441,16 @@ void launch_set_direction(hipStream_t s, int64_t n, const double *dinv, const do
 }
 
 void launch_epilogue(hipStream_t s, int64_t n, double t1, const double *Vold, const double *Vnew,
-                     double *lat, double *lrt, Scalars *sc)
+                     double *lat, double *lrt, Scalars *sc, const int32_t *guard)
 {
     if (n > 0)
         hipLaunchKernelGGL(k_epilogue, dim3(blocks_for(n)), dim3(256), 0, s, n, t1, Vold, Vnew, lat,
-                           lrt, sc);
+                           lrt, sc, guard);
+}
+
+void launch_publish(hipStream_t s, const Scalars *sc, Published *pub, int32_t seq)
+{
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, sc, pub, seq);
 }
 
 }  // namespace mdx
