@@ -11,7 +11,8 @@ value is DOF*steps/s = n_nodes * K / seconds.
 Workloads: learned (default: the learned warm start + mixed precision
 against plain FP64 PCG on a 1.2M-node shell at equal accuracy), slab (plain
 FP64, 442,401 nodes), precision / precision_fp64 (3.45M-node slab), batched
-(64 shells, 12M nodes), tiny.
+(64 shells, 12M nodes), tiny, nversion (the N-version verification problem at
+0.5 / 0.2 / 0.1 mm, each run to full activation).
 
 Also reported, as one JSON line:
   roofline      the dominant kernel (PCG SpMV with fused p.q): algorithmic
@@ -218,6 +219,54 @@ def learned_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def nversion_workload(args):
+    """The N-version verification problem (dt 0.005 ms) at 0.5, 0.2 and 0.1 mm,
+    each run from rest until every node has activated; activation times along
+    the P1-P8 diagonal.  The value is the 0.1 mm run's DOF*steps/s."""
+    import torch
+    from paper_2510_12011_amd import inputs, nversion as nv, sim
+    table, rate, n, steps01, el01 = {}, None, 0, 0, 0.0
+    for h in (0.5, 0.2, 0.1):
+        spec = inputs.nversion(h, 60000)
+        s = sim.from_spec(spec)
+        s.set_profiling(args.profile_every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, steps, _ = nv.run_to_activation(s, spec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        table[f"{h:g}"] = {"P1_ms": float(t[0]), "P8_ms": float(t[-1]), "steps": steps,
+                           "diagonal_ms": [round(float(v), 3) for v in t],
+                           "mean_cg_iters": s.stats()["cg_iters_total"] / steps}
+        print(f"[bench] dx {h}: {spec.mesh.n_nodes} nodes, {steps} steps in {el:.2f} s, "
+              f"activation P1 {t[0]:.3f} ms, P8 {t[-1]:.3f} ms", flush=True)
+        if h == 0.1:
+            n, steps01, el01 = spec.mesh.n_nodes, steps, el
+            rate = n * steps / el
+            st = s.stats()
+    launches = max(1, st["spmv_timed"])
+    spmv_avg = st["spmv_seconds"] / launches
+    bytes_avg = st["spmv_bytes"] / launches
+    achieved = bytes_avg / spmv_avg / 1e9
+    out = {
+        "metric": METRIC, "value": rate, "unit": "DOF*steps/s", "n_gpus": 1, "steps": steps01,
+        "warmup": 0, "ms_per_step": 1e3 * el01 / steps01, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "N-version problem (20x7x3 mm cuboid, TTP06, Table 2 sigma, "
+                               "50 uA/mm^3 corner stimulus, dt 0.005 ms), dx 0.1 mm run from "
+                               "rest to full activation; activation times along P1-P8 at "
+                               "dx 0.5, 0.2, 0.1 mm",
+                   "n_nodes": n, "activation": table},
+        "roofline": {"bound": "hbm", "kernel": "k_spmv_dot", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": bytes_avg,
+                     "avg_launch_us": 1e6 * spmv_avg, "launches_timed": st["spmv_timed"],
+                     "sampled_every_n_steps": args.profile_every,
+                     "cache_resident": bool(10 * st["nnz"] < 256e6)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def batched_workload(args):
     """The batched form: 64 unstructured ellipsoidal shells (about 12M
     nodes), Mitchell-Schaeffer, mixed precision, one block-diagonal solve per
@@ -307,12 +356,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: learned 3000, slab 10000, batched 1000, "
-                         "precision 2000, tiny 500)")
+                         "precision 2000, tiny 500; nversion runs to full activation)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps before the timed region (default: 0 learned, 10 batched, "
                          "100 otherwise)")
     ap.add_argument("--workload", default="learned",
-                    choices=["learned", "slab", "precision", "precision_fp64", "batched", "tiny"])
+                    choices=["learned", "slab", "precision", "precision_fp64", "batched", "tiny",
+                             "nversion"])
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-every", type=int, default=10)
@@ -327,16 +377,18 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=10, help="learned workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the method runs one simulation per GPU and "
-              "this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: a simulation runs on one GPU; the sharded "
+              "multi-GPU path is a design, not code (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:
         args.steps = {"learned": 3000, "slab": 10000, "batched": 1000, "precision": 2000,
-                      "precision_fp64": 2000, "tiny": 500}[args.workload]
+                      "precision_fp64": 2000, "tiny": 500, "nversion": 0}[args.workload]
     if args.warmup is None:
         args.warmup = {"learned": 0, "batched": 10}.get(args.workload, 100)
     if args.workload == "batched":
         batched_workload(args)
+    elif args.workload == "nversion":
+        nversion_workload(args)
     elif args.workload == "learned":
         learned_workload(args)
     else:

@@ -178,6 +178,24 @@ def tiny_cube(n: int = 20, jitter: float = 0.05, seed: int = 0,
                    stimuli=[stim], rtol=1e-10)
 
 
+def nversion(h: float = 0.1, n_steps: int = 40000) -> RunSpec:
+    """The N-version verification problem as the paper states it (its
+    verification section and Table 2): the 20 x 7 x 3 mm cuboid with fibres
+    along x, Kuhn tets of spacing h (0.5, 0.2 or 0.1 mm), no jitter,
+    sigma_l / sigma_t 0.1334177 / 0.0173515 S/m, chi 140 /mm, Cm
+    0.01 uF/mm^2, ten Tusscher-Panfilov, dt 0.005 ms.  The volumetric
+    stimulus of 50 uA/mm^3 is chi * I_stim, so I_stim = 50/140 uA/mm^2, on the
+    1.5 mm corner cube at P1 = (0, 0, 0) for 2 ms.  Solver as the slab's
+    (rtol 1e-10 of ||z0||)."""
+    nx, ny, nz = int(round(20 / h)), int(round(7 / h)), int(round(3 / h))
+    mesh = kuhn_box(nx, ny, nz, 20.0, 7.0, 3.0, fibre=(1.0, 0.0, 0.0))
+    chi = 140.0
+    stim = Stimulus(box_corner_nodes(mesh, 1.5), 0.0, 2.0, 50.0 / chi)
+    return RunSpec(name=f"nversion_h{h:g}", mesh=mesh, sigma_l=0.1334177, sigma_t=0.0173515,
+                   chi=chi, cm=0.01, theta=0.5, ionic="tt", dt=0.005, n_steps=n_steps,
+                   stimuli=[stim], rtol=1e-10, rel_mode=0)
+
+
 def slab(h: float = 0.1, n_steps: int = 10000, ionic: str = "tt",
          rtol: float = 1e-10, rel_mode: int = 0) -> RunSpec:
     """20 x 7 x 3 mm cuboid, structured grid of spacing h split into Kuhn
