@@ -143,6 +143,13 @@ MDX_API mdx_status mdx_set_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz
  * mdx_prepare. */
 MDX_API mdx_status mdx_add_conductivity(mdx_ctx *ctx, int32_t n_ids, const int32_t *region_ids,
                                 double il, double it);
+/* The same from intracellular (il, it) and extracellular (el, et)
+ * conductivities (S/m, all > 0), as the paper's add_conductivity takes them
+ * (its usage listing): the monodomain conductivity in each direction is the
+ * series combination s_i s_e / (s_i + s_e) (Table 2's 0.1334177 and
+ * 0.0173515 S/m are those of (0.17, 0.62) and (0.019, 0.20)). */
+MDX_API mdx_status mdx_add_conductivity_ie(mdx_ctx *ctx, int32_t n_ids, const int32_t *region_ids,
+                                   double il, double it, double el, double et);
 /* chi (1/mm) > 0, Cm (uF/mm^2) > 0, theta in [0, 1] (0.5: Crank-Nicolson) */
 MDX_API mdx_status mdx_set_tissue(mdx_ctx *ctx, double chi, double cm, double theta);
 /* Ionic model and its editable parameters (NULL: defaults).

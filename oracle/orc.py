@@ -142,8 +142,20 @@ def assemble(xyz, tets, fibre, sl, st):
     return Matrices(row_ptr, col, M, K)
 
 
+def series_conductivity(s_i, s_e):
+    """Monodomain conductivity of intra- and extracellular conductivities in
+    one direction: the two in series, s_i s_e / (s_i + s_e) (reproduces
+    Table 2's values from the intra/extra pairs)."""
+    return s_i * s_e / (s_i + s_e)
+
+
 def assemble_spec(spec):
     sl, st = spec.sigma_per_tet()
+    sl, st = sl.copy(), st.copy()
+    for ids, il, it, el, et in getattr(spec, "ie_regions", []):
+        sel = np.isin(spec.mesh.region, np.atleast_1d(ids))
+        sl[sel] = series_conductivity(il, el)
+        st[sel] = series_conductivity(it, et)
     return assemble(spec.mesh.xyz, spec.mesh.tets, spec.mesh.fibre, sl, st)
 
 

@@ -1307,6 +1307,18 @@ mdx_status mdx_add_conductivity(mdx_ctx *ctx, int32_t n_ids, const int32_t *regi
     GUARD_END
 }
 
+mdx_status mdx_add_conductivity_ie(mdx_ctx *ctx, int32_t n_ids, const int32_t *region_ids,
+                                   double il, double it, double el, double et)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    for (double v : {il, it, el, et})
+        if (!(v > 0.0) || !std::isfinite(v))
+            return fail(ctx, MDX_ERR_INVALID_ARG,
+                        "intra- and extracellular conductivities must be finite and > 0");
+    // monodomain conductivity per direction: intra- and extracellular in series
+    return mdx_add_conductivity(ctx, n_ids, region_ids, il * el / (il + el), it * et / (it + et));
+}
+
 mdx_status mdx_set_tissue(mdx_ctx *ctx, double chi, double cm, double theta)
 {
     if (!ctx) return MDX_ERR_INVALID_ARG;

@@ -157,6 +157,9 @@ class RunSpec:
     out_every: int = 100       # snapshot interval in steps
     precision: str = "fp64"    # "fp64" | "mixed"
     rr_interval: int = 50      # mixed: residual replacement interval
+    # regions given intra- and extracellular conductivities instead:
+    # entries (region ids, il, it, el, et) in S/m, applied after sigma_l/t
+    ie_regions: list = field(default_factory=list)
 
     def sigma_per_tet(self):
         m = self.mesh.n_tets

@@ -28,6 +28,9 @@ def _dptr(t):
 
 
 IONIC = {"none": L.MDX_IONIC_NONE, "ms": L.MDX_IONIC_MS, "tt": L.MDX_IONIC_TT}
+# theta of the integration schemes the paper tabulates
+THETA = {"forward_euler": 0.0, "crank_nicolson": 0.5, "galerkin": 2.0 / 3.0, "backward_euler": 1.0}
+
 PRECISION = {"fp64": L.MDX_PREC_FP64, "mixed": L.MDX_PREC_MIXED,
              "mixed_gates32": L.MDX_PREC_MIXED_GATES32}
 
@@ -98,7 +101,16 @@ class Simulation:
         ids = np.ascontiguousarray(np.atleast_1d(region_ids), np.int32)
         self._check(L.lib().mdx_add_conductivity(self._h, ids.shape[0], _ptr(ids), il, it))
 
+    def add_conductivity_ie(self, region_ids, il, it, el, et):
+        """Intra- (il, it) and extracellular (el, et) conductivities; the
+        library combines them per direction."""
+        ids = np.ascontiguousarray(np.atleast_1d(region_ids), np.int32)
+        self._check(L.lib().mdx_add_conductivity_ie(self._h, ids.shape[0], _ptr(ids), il, it,
+                                                    el, et))
+
     def set_tissue(self, chi, cm, theta=0.5):
+        """theta: a number in [0, 1] or a scheme name of THETA."""
+        theta = THETA[theta] if isinstance(theta, str) else theta
         self._check(L.lib().mdx_set_tissue(self._h, chi, cm, theta))
 
     def set_ionic(self, kind: str, params=None):
@@ -255,6 +267,8 @@ def from_spec(spec, device: int = 0, ionic_params=None, prepare=True,
     m = spec.mesh
     sim.set_mesh(m.xyz, m.tets, m.region, m.fibre)
     sim.add_conductivity(np.unique(m.region), spec.sigma_l, spec.sigma_t)
+    for ids, il, it, el, et in getattr(spec, "ie_regions", []):
+        sim.add_conductivity_ie(ids, il, it, el, et)
     sim.set_tissue(spec.chi, spec.cm, spec.theta)
     sim.set_ionic(spec.ionic, ionic_params)
     for s in spec.stimuli:

@@ -94,6 +94,9 @@ def test_validation_rejects_bad_parameters(host_ctx):
     assert lib.mdx_set_tissue(host_ctx, 140.0, 0.01, 0.5) == L.MDX_OK
     ids = np.array([0], np.int32)
     assert lib.mdx_add_conductivity(host_ctx, 1, _p(ids), -0.1, 0.1) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_add_conductivity_ie(host_ctx, 1, _p(ids), 0.17, 0.019, 0.0, 0.2) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_add_conductivity_ie(host_ctx, 1, _p(ids), 0.17, float("nan"), 0.62, 0.2) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_add_conductivity_ie(host_ctx, 1, _p(ids), 0.17, 0.019, 0.62, 0.2) == L.MDX_OK
     assert lib.mdx_set_ionic(host_ctx, 7, 0, None) == L.MDX_ERR_UNSUPPORTED
     p3 = np.ones(3)
     assert lib.mdx_set_ionic(host_ctx, L.MDX_IONIC_MS, 3, _p(p3)) == L.MDX_ERR_INVALID_ARG

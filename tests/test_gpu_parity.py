@@ -150,7 +150,7 @@ def test_trajectory_parity_iteration_schemes(scheme):
     _compare_run(spec, 300, 100, scheme=scheme)
 
 
-@pytest.mark.parametrize("theta,ws,rel", [(1.0, 0, 0), (0.5, 0, 1), (0.0, 1, 0)])
+@pytest.mark.parametrize("theta,ws,rel", [(1.0, 0, 0), (0.5, 0, 1), (0.0, 1, 0), (2.0 / 3.0, 1, 1)])
 def test_trajectory_parity_variants(theta, ws, rel):
     """Backward Euler / forward Euler theta, previous-step warm start,
     RHS-relative stopping."""
@@ -158,6 +158,18 @@ def test_trajectory_parity_variants(theta, ws, rel):
     spec.warm_start, spec.rel_mode = ws, rel
     if theta == 0.0:
         spec.dt = 0.002            # explicit diffusion needs a small step
+    _compare_run(spec, 200, 50)
+
+
+def test_trajectory_parity_intra_extra_conductivities():
+    """Two regions: one given monodomain sigma, the other intra- and
+    extracellular pairs (the values of the paper's usage listing) that the
+    library combines (mdx_add_conductivity_ie) and the oracle combines on
+    its own."""
+    spec = inputs.small_box(nx=10, ny=8, nz=6, ionic="ms", n_steps=200)
+    cx = spec.mesh.xyz[spec.mesh.tets].mean(axis=1)[:, 0]
+    spec.mesh.region = np.where(cx > 0.6, 1, 0).astype(np.int32)
+    spec.ie_regions = [([1], 0.5272, 0.2076, 1.0732, 0.4227)]
     _compare_run(spec, 200, 50)
 
 

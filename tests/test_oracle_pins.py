@@ -424,7 +424,7 @@ def _semi_discrete_run(dt, T, theta, lam=1.0):
     return abs(o.state.V - a(ns * dt) * phi).max()
 
 
-@pytest.mark.parametrize("theta,order", [(0.5, 2.0), (1.0, 1.0)])
+@pytest.mark.parametrize("theta,order", [(0.5, 2.0), (2.0 / 3.0, 1.0), (1.0, 1.0)])
 def test_time_order(theta, order):
     """Second order in dt for Crank-Nicolson, first for backward Euler,
     against the exact solution of the semi-discrete system.  A wrong sign or
@@ -432,3 +432,16 @@ def test_time_order(theta, order):
     errs = [_semi_discrete_run(dt, 2.0, theta) for dt in (0.2, 0.1, 0.05, 0.025)]
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates[-1] == pytest.approx(order, abs=0.1), (errs, rates)
+
+
+def test_series_conductivity_reproduces_table2():
+    """Table 2's monodomain conductivities (0.1334177 and 0.0173515 S/m, the
+    table's printed digits) are the intra- and extracellular pairs
+    (0.17, 0.62) and (0.019, 0.20) S/m in series; equal pairs give half, and
+    the result never exceeds either part."""
+    assert abs(orc.series_conductivity(0.17, 0.62) - 0.1334177) < 1e-7
+    assert abs(orc.series_conductivity(0.019, 0.20) - 0.0173515) < 1e-7
+    assert orc.series_conductivity(0.3, 0.3) == pytest.approx(0.15, abs=1e-15)
+    rng = np.random.default_rng(5)
+    a, b = rng.uniform(0.01, 1.0, 100), rng.uniform(0.01, 1.0, 100)
+    assert np.all(orc.series_conductivity(a, b) <= np.minimum(a, b))
