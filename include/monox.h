@@ -150,8 +150,14 @@ MDX_API mdx_status mdx_add_conductivity(mdx_ctx *ctx, int32_t n_ids, const int32
  * 0.0173515 S/m are those of (0.17, 0.62) and (0.019, 0.20)). */
 MDX_API mdx_status mdx_add_conductivity_ie(mdx_ctx *ctx, int32_t n_ids, const int32_t *region_ids,
                                    double il, double it, double el, double et);
-/* chi (1/mm) > 0, Cm (uF/mm^2) > 0, theta in [0, 1] (0.5: Crank-Nicolson) */
+/* chi (1/mm) > 0, Cm (uF/mm^2) > 0, theta in [0, 1] (the paper's table of
+ * schemes: 0 forward Euler, 0.5 Crank-Nicolson, 2/3 Galerkin, 1 backward
+ * Euler) */
 MDX_API mdx_status mdx_set_tissue(mdx_ctx *ctx, double chi, double cm, double theta);
+/* Mass matrix M of A and b (Eq. 2): 0 (default) the consistent P1 mass, 1
+ * the lumped mass (each row's sum on the diagonal).  Takes effect at the next
+ * mdx_prepare. */
+MDX_API mdx_status mdx_set_mass_lumping(mdx_ctx *ctx, int32_t lumped);
 /* Ionic model and its editable parameters (NULL: defaults).
  * MDX_IONIC_MS, 7 params: tau_in, tau_out, tau_open, tau_close, u_gate,
  *   v_rest, v_amp (defaults 0.3, 6, 120, 150, 0.13, -80, 100).

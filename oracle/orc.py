@@ -156,7 +156,17 @@ def assemble_spec(spec):
         sel = np.isin(spec.mesh.region, np.atleast_1d(ids))
         sl[sel] = series_conductivity(il, el)
         st[sel] = series_conductivity(it, et)
-    return assemble(spec.mesh.xyz, spec.mesh.tets, spec.mesh.fibre, sl, st)
+    mats = assemble(spec.mesh.xyz, spec.mesh.tets, spec.mesh.fibre, sl, st)
+    return lumped(mats) if getattr(spec, "lumped_mass", False) else mats
+
+
+def lumped(mats: Matrices) -> Matrices:
+    """The same matrices with M replaced by its row-sum lumping: each row's
+    entries summed onto its diagonal, the rest zero (same pattern)."""
+    rows = np.repeat(np.arange(mats.n), np.diff(mats.row_ptr))
+    sums = np.bincount(rows, weights=mats.M, minlength=mats.n)
+    M = np.where(mats.col == rows, sums[rows], 0.0)
+    return Matrices(mats.row_ptr, mats.col, M, mats.K)
 
 
 def spmv(mats: Matrices, val, x):

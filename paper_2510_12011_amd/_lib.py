@@ -84,6 +84,7 @@ _SIGS = {
     "mdx_add_conductivity": (C.c_int, [P, C.c_int32, P, C.c_double, C.c_double]),
     "mdx_add_conductivity_ie": (C.c_int, [P, C.c_int32, P, C.c_double, C.c_double, C.c_double,
                                           C.c_double]),
+    "mdx_set_mass_lumping": (C.c_int, [P, C.c_int32]),
     "mdx_set_tissue": (C.c_int, [P, C.c_double, C.c_double, C.c_double]),
     "mdx_set_ionic": (C.c_int, [P, C.c_int32, C.c_int32, P]),
     "mdx_add_stimulus": (C.c_int, [P, C.c_int64, P, C.c_double, C.c_double, C.c_double]),

@@ -75,6 +75,7 @@ struct mdx_ctx {
     std::vector<double> fibre;     // empty: isotropic
     std::map<int32_t, std::pair<double, double>> cond;
     double chi = 140.0, cm = 0.01, theta = 0.5;
+    bool lumped = false;   // mass lumping (row sums on the diagonal)
     int ionic_kind = 0;
     std::vector<double> ionic_params;
     std::vector<Stim> stims;
@@ -1319,6 +1320,15 @@ mdx_status mdx_add_conductivity_ie(mdx_ctx *ctx, int32_t n_ids, const int32_t *r
     return mdx_add_conductivity(ctx, n_ids, region_ids, il * el / (il + el), it * et / (it + et));
 }
 
+mdx_status mdx_set_mass_lumping(mdx_ctx *ctx, int32_t lumped)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (lumped != 0 && lumped != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "lumped is 0 or 1");
+    ctx->lumped = lumped != 0;
+    ctx->prepared = false;
+    return MDX_OK;
+}
+
 mdx_status mdx_set_tissue(mdx_ctx *ctx, double chi, double cm, double theta)
 {
     if (!ctx) return MDX_ERR_INVALID_ARG;
@@ -1551,6 +1561,9 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
                    (double *)(x + L.x_sig), (double *)(x + L.x_vol), (double *)(x + L.x_ek));
     launch_gather(st, ctx->nslots, (int64_t *)(x + L.x_cptr), (int32_t *)(x + L.x_contrib),
                   (double *)(x + L.x_vol), (double *)(x + L.x_ek), Mv, Kv);
+    if (ctx->lumped)
+        launch_lump(st, ctx->npad, SellView{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)},
+                    Mv);
     launch_system(st, ctx->nslots, Mv, Kv, ctx->chi * ctx->cm, ctx->theta * dt, Av);
     SellView P{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)};
     launch_dinv(st, ctx->npad, span_rows(ctx), P, Av, ctx->dev<double>(L.dinv));

@@ -95,6 +95,27 @@ __global__ __launch_bounds__(256) void k_system(int64_t n_slots, const double *_
     if (s < n_slots) Av[s] = cM * Mv[s] + cK * Kv[s];
 }
 
+// Lumped mass: each row's entries summed onto its diagonal, every other
+// entry zero.  The diagonal is the row's first slot with col == row (the
+// padding slots after a row's real entries also carry col == row).
+__global__ __launch_bounds__(256) void k_lump(int64_t n_rows, const int64_t *__restrict__ slice_ptr,
+                                              const int32_t *__restrict__ col,
+                                              double *__restrict__ Mv)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int64_t sl = r / SLICE;
+    const int lane = (int)(r % SLICE);
+    double sum = 0.0;
+    for (int64_t e = slice_ptr[sl] + lane; e < slice_ptr[sl + 1]; e += SLICE) sum += Mv[e];
+    bool placed = false;
+    for (int64_t e = slice_ptr[sl] + lane; e < slice_ptr[sl + 1]; e += SLICE) {
+        const bool diag = !placed && col[e] == r;
+        Mv[e] = diag ? sum : 0.0;
+        placed = placed || diag;
+    }
+}
+
 // dinv[r] = 1 / A_rr; the padding entries carry col = row and value 0, so the
 // sum over all entries with col == row is the diagonal.  Padding rows: 0.
 __global__ __launch_bounds__(256) void k_dinv(int64_t n_rows, int64_t n_real,
@@ -144,6 +165,13 @@ void launch_system(hipStream_t s, int64_t n_slots, const double *Mv, const doubl
     if (n_slots > 0)
         hipLaunchKernelGGL(k_system, dim3(blocks_for(n_slots)), dim3(256), 0, s, n_slots, Mv, Kv,
                            cM, cK, Av);
+}
+
+void launch_lump(hipStream_t s, int64_t n_rows, SellView A, double *Mv)
+{
+    if (n_rows > 0)
+        hipLaunchKernelGGL(k_lump, dim3(blocks_for(n_rows)), dim3(256), 0, s, n_rows, A.slice_ptr,
+                           A.col, Mv);
 }
 
 void launch_dinv(hipStream_t s, int64_t n_rows, int64_t n_real, SellView A, const double *Av,

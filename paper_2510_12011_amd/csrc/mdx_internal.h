@@ -111,6 +111,8 @@ void launch_gather(hipStream_t s, int64_t n_slots, const int64_t *cptr, const in
                    const double *elem_vol, const double *elem_k, double *Mv, double *Kv);
 void launch_system(hipStream_t s, int64_t n_slots, const double *Mv, const double *Kv,
                    double cM, double cK, double *Av);
+// mass lumping in place: row sums onto the diagonal, other entries zero
+void launch_lump(hipStream_t s, int64_t n_rows, SellView A, double *Mv);
 void launch_dinv(hipStream_t s, int64_t n_rows, int64_t n_real, SellView A, const double *Av,
                  double *dinv);
 

@@ -160,6 +160,7 @@ class RunSpec:
     # regions given intra- and extracellular conductivities instead:
     # entries (region ids, il, it, el, et) in S/m, applied after sigma_l/t
     ie_regions: list = field(default_factory=list)
+    lumped_mass: bool = False  # M lumped (row sums on the diagonal)
 
     def sigma_per_tet(self):
         m = self.mesh.n_tets

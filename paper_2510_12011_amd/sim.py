@@ -113,6 +113,9 @@ class Simulation:
         theta = THETA[theta] if isinstance(theta, str) else theta
         self._check(L.lib().mdx_set_tissue(self._h, chi, cm, theta))
 
+    def set_mass_lumping(self, lumped: bool):
+        self._check(L.lib().mdx_set_mass_lumping(self._h, int(bool(lumped))))
+
     def set_ionic(self, kind: str, params=None):
         k = IONIC[kind]
         p = None if params is None else np.ascontiguousarray(params, np.float64)
@@ -270,6 +273,8 @@ def from_spec(spec, device: int = 0, ionic_params=None, prepare=True,
     for ids, il, it, el, et in getattr(spec, "ie_regions", []):
         sim.add_conductivity_ie(ids, il, it, el, et)
     sim.set_tissue(spec.chi, spec.cm, spec.theta)
+    if getattr(spec, "lumped_mass", False):
+        sim.set_mass_lumping(True)
     sim.set_ionic(spec.ionic, ionic_params)
     for s in spec.stimuli:
         sim.add_stimulus(s.nodes, s.start, s.duration, s.intensity)

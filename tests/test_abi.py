@@ -97,6 +97,9 @@ def test_validation_rejects_bad_parameters(host_ctx):
     assert lib.mdx_add_conductivity_ie(host_ctx, 1, _p(ids), 0.17, 0.019, 0.0, 0.2) == L.MDX_ERR_INVALID_ARG
     assert lib.mdx_add_conductivity_ie(host_ctx, 1, _p(ids), 0.17, float("nan"), 0.62, 0.2) == L.MDX_ERR_INVALID_ARG
     assert lib.mdx_add_conductivity_ie(host_ctx, 1, _p(ids), 0.17, 0.019, 0.62, 0.2) == L.MDX_OK
+    assert lib.mdx_set_mass_lumping(host_ctx, 2) == L.MDX_ERR_INVALID_ARG
+    assert lib.mdx_set_mass_lumping(host_ctx, 1) == L.MDX_OK
+    assert lib.mdx_set_mass_lumping(host_ctx, 0) == L.MDX_OK
     assert lib.mdx_set_ionic(host_ctx, 7, 0, None) == L.MDX_ERR_UNSUPPORTED
     p3 = np.ones(3)
     assert lib.mdx_set_ionic(host_ctx, L.MDX_IONIC_MS, 3, _p(p3)) == L.MDX_ERR_INVALID_ARG

@@ -173,6 +173,14 @@ def test_trajectory_parity_intra_extra_conductivities():
     _compare_run(spec, 200, 50)
 
 
+def test_trajectory_parity_lumped_mass():
+    """Lumped mass in A and b (mdx_set_mass_lumping) follows the oracle's
+    own lumping."""
+    spec = inputs.small_box(nx=10, ny=8, nz=6, ionic="tt", n_steps=300, stim_extent=0.5)
+    spec.lumped_mass = True
+    _compare_run(spec, 300, 100)
+
+
 def test_coarse_slab_tt_full_length():
     """20 x 7 x 3 mm slab at h = 0.5 mm, ten Tusscher-Panfilov, 50 ms."""
     spec = inputs.slab(h=0.5, n_steps=5000)

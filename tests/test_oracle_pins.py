@@ -445,3 +445,22 @@ def test_series_conductivity_reproduces_table2():
     rng = np.random.default_rng(5)
     a, b = rng.uniform(0.01, 1.0, 100), rng.uniform(0.01, 1.0, 100)
     assert np.all(orc.series_conductivity(a, b) <= np.minimum(a, b))
+
+
+def test_lumped_mass():
+    """Row-sum lumping: a diagonal matrix with the consistent mass's row sums
+    (so total |Omega| and the charge balance are kept); on an unjittered Kuhn
+    grid every interior node carries exactly hx hy hz."""
+    sp = inputs.small_box(nx=6, ny=5, nz=4, jitter=0.0)
+    m = orc.assemble_spec(sp)
+    sp.lumped_mass = True
+    ml = orc.assemble_spec(sp)
+    D = ml.dense("M")
+    assert np.count_nonzero(D - np.diag(np.diag(D))) == 0
+    np.testing.assert_allclose(D.sum(axis=1), m.dense("M").sum(axis=1), rtol=1e-14)
+    assert D.sum() == pytest.approx(1.2 * 1.0 * 0.8, rel=1e-13)
+    np.testing.assert_array_equal(ml.K, m.K)
+    g = sp.mesh.grid
+    inner = ((g[:, 0] > 1e-9) & (g[:, 0] < 1.2 - 1e-9) & (g[:, 1] > 1e-9) & (g[:, 1] < 1.0 - 1e-9)
+             & (g[:, 2] > 1e-9) & (g[:, 2] < 0.8 - 1e-9))
+    np.testing.assert_allclose(np.diag(D)[inner], (1.2 / 6) * (1.0 / 5) * (0.8 / 4), rtol=1e-13)
