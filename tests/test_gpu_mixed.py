@@ -153,3 +153,21 @@ def test_mixed_converges_relative_to_initial_residual():
     o = orc.Oracle(spec)
     v_or, _ = o.steps(300, out_every=100)
     assert max(_rel_l2(a, b) for a, b in zip(v_gpu, v_or)) <= V_REL_L2
+
+
+def test_mixed_iteration_cap_follows_oracle():
+    """Mixed form with every solve stopped at the cap (max_iter 3): the
+    replacement at the cap flushes the FP32 correction, the run reports no
+    convergence, and V stays within the form's bar of the oracle's capped
+    FP64 solves."""
+    from paper_2510_12011_amd import _lib as L
+    spec = inputs.small_box(nx=10, ny=8, nz=6, ionic="ms", n_steps=300)
+    spec.max_iter = 3
+    s = _sim(spec, "mixed")
+    v_gpu, status = s.run(300, 100)
+    assert status == L.MDX_WARN_NOT_CONVERGED
+    o = orc.Oracle(spec)
+    v_or, _ = o.steps(300, out_every=100)
+    err = max(_rel_l2(a, b) for a, b in zip(v_gpu, v_or))
+    print(f"  capped mixed vs oracle: {err:.2e}", flush=True)
+    assert err <= 1e-5
