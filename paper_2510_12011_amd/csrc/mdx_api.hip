@@ -1710,18 +1710,28 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         ionic_queued = false;
 
         // ---- right-hand side, warm start, initial residual ----
+        // (the three-kernel FP64 iteration starts from p0 = z0, written by
+        // the pass that forms r0)
+        double *p0_fp64 = !mixed && ctx->iter_scheme == 0 ? pbuf[0] : nullptr;
         // the learned warm start and the recorder need the neighbour feature
         // (K V^{n-1})_i / K_ii, kept up to date by the right-hand-side pass
         const bool want_kvp = learned || ctx->rec_X;
         if (want_kvp && !ctx->kvp_valid) launch_kv_feature(st, T, P, Kv, kdiag, Vprev, kvp);
         if (learned) {
-            launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm, feat,
-                            ctx->rec_X);
-            launch_mlp_forward(st, mlp_params, ctx->n, feat, mlp_y);   // padding rows keep y = 0
+            // padding rows keep y = 0
+            if (ctx->rec_X) {   // the recorder also wants the raw features
+                launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm, feat,
+                                ctx->rec_X);
+                launch_mlp_forward(st, mlp_params, ctx->n, feat, mlp_y);
+            } else {
+                launch_mlp_forward_state(st, mlp_params, ctx->n, V, Vprev, s, kvp, ctx->cm,
+                                         ctx->mlp_norm, mlp_y);
+            }
             launch_rhs_learned(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm.out_scale, V, s,
                                mlp_y, b, X, r, q, kvp, mixed ? 1 : 0, part_pq, part0, nt_rhs);
             launch_init_finalize_ws(st, T, part_pq, part0, sp.rel_mode, sc);
-            launch_select(st, ctx->npad, V, q, X, r, dinv32, mixed ? r32 : nullptr, z32, delta, sc);
+            launch_select(st, ctx->npad, V, q, X, r, dinv, p0_fp64, dinv32, mixed ? r32 : nullptr,
+                          z32, delta, sc);
         } else {
             if (ctx->rec_X)   // training-data recorder: raw features
                 launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm,
@@ -1732,7 +1742,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                                       z32, delta, part0, kdiag, kvp_out, nt_rhs);
             else
                 launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0, kdiag,
-                                kvp_out, nt_rhs);
+                                kvp_out, p0_fp64, nt_rhs);
             launch_init_finalize(st, T, part0, sp.rel_mode, sc);
         }
         ctx->kvp_valid = want_kvp;
@@ -1823,8 +1833,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             // z.z), direction (test, beta, p = z + beta p).  Iteration it's
             // direction kernel tests ||z_{it+1}||.  First chunk: the previous
             // step's count; then one iteration at a time.
-            double *p = pbuf[0];
-            launch_set_direction(st, ctx->npad, dinv, r, p, sc);
+            double *p = pbuf[0];   // p0 = z0 from the right-hand-side pass
             int chunk = std::max(1, ctx->last_iters);
             while (!done && units < max_iter) {
                 const int c = std::min(chunk, max_iter - units);

@@ -185,6 +185,10 @@ int mlp_nparams();
 int mlp_grad_groups(int64_t n);
 size_t mlp_grad_scratch_bytes(int64_t n);
 void launch_mlp_forward(hipStream_t s, const float *P, int64_t n, const float *X, float *y);
+// the same with the features formed from the state (no feature pass)
+void launch_mlp_forward_state(hipStream_t s, const float *P, int64_t n, const double *V,
+                              const double *Vprev, const double *src, const float *kvp, double cm,
+                              const MlpNorm &nm, float *y);
 void launch_mlp_grad(hipStream_t s, const float *P, int64_t n, const float *X, const float *T,
                      float *grad, float *loss, float *partials);
 void launch_adam(hipStream_t s, float *P, float *m, float *v, const float *g, int t, double lr,
@@ -214,8 +218,8 @@ void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
                              int rel_mode, Scalars *sc);
 void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
-                   double *r, const float *dinv32, float *r32, float *z32, float *delta,
-                   const Scalars *sc);
+                   double *r, const double *dinv, double *p0, const float *dinv32, float *r32,
+                   float *z32, float *delta, const Scalars *sc);
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv);
 
 // ---- batched form (mdx_batch.hip) -----------------------------------------
@@ -328,7 +332,7 @@ void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *M
                      const double *Kv, const double *dinv, const StepParams &sp,
                      const double *V, const double *Vprev, const double *src, double *x,
                      double *r, double *b, double *partial, const double *kdiag, float *kvp,
-                     bool nt);
+                     double *p0, bool nt);
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
                           Scalars *sc);
 // q = A p with partial p.q (no convergence logic; `done` non-zero skips it).

@@ -171,6 +171,8 @@ __global__ __launch_bounds__(256) void k_init_finalize_ws(int groups, const doub
 __global__ __launch_bounds__(256) void k_select(int64_t n, const double *__restrict__ V,
                                                 const double *__restrict__ r_prev,
                                                 double *__restrict__ x, double *__restrict__ r,
+                                                const double *__restrict__ dinv,
+                                                double *__restrict__ p0,
                                                 const float *__restrict__ dinv32,
                                                 float *__restrict__ r32, float *__restrict__ z32,
                                                 float *__restrict__ delta,
@@ -182,6 +184,7 @@ __global__ __launch_bounds__(256) void k_select(int64_t n, const double *__restr
         x[i] = V[i];
         r[i] = r_prev[i];
     }
+    if (p0) p0[i] = dinv[i] * r[i];   // FP64 iteration: the first direction p0 = z0
     if (r32) {
         const float rf = (float)r[i];
         r32[i] = rf;
@@ -262,11 +265,11 @@ void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, c
 }
 
 void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
-                   double *r, const float *dinv32, float *r32, float *z32, float *delta,
-                   const Scalars *sc)
+                   double *r, const double *dinv, double *p0, const float *dinv32, float *r32,
+                   float *z32, float *delta, const Scalars *sc)
 {
-    hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(256), 0, s, n, V, r_prev, x, r, dinv32,
-                       r32, z32, delta, sc);
+    hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(256), 0, s, n, V, r_prev, x, r, dinv,
+                       p0, dinv32, r32, z32, delta, sc);
 }
 
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv)

@@ -207,9 +207,29 @@ __device__ __forceinline__ f32x16 unit_frag(const float *v, int ot, int half)
     return r;
 }
 
+// The network's input per node: stored standardised features (X), or the
+// features formed from the state as the feature pass forms them (same
+// expressions, so the same bits): V, V - V_prev, s / Cm, the neighbour
+// aggregate, standardised.
+struct FeatIn {
+    const float4 *X;
+    const double *V, *Vprev, *src;
+    const float *kvp;
+    double cm;
+    MlpNorm nm;
+    __device__ __forceinline__ float4 load(int64_t i) const
+    {
+        if (X) return X[i];
+        const double vi = V[i];
+        const float fx = (float)vi, fy = (float)(vi - Vprev[i]), fz = (float)(src[i] / cm);
+        const float fw = kvp[i];
+        return make_float4((fx - nm.mean[0]) * nm.inv_std[0], (fy - nm.mean[1]) * nm.inv_std[1],
+                           (fz - nm.mean[2]) * nm.inv_std[2], (fw - nm.mean[3]) * nm.inv_std[3]);
+    }
+};
+
 __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P, int64_t n,
-                                                     const float *__restrict__ X,
-                                                     float *__restrict__ y)
+                                                     FeatIn in, float *__restrict__ y)
 {
     __shared__ InferLds w;
     for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {
@@ -241,7 +261,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P
         asm volatile("" ::: "memory");
         const int64_t node = tile * 32 + (lane & 31);
         float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (half == 0 && node < n) x = reinterpret_cast<const float4 *>(X)[node];
+        if (half == 0 && node < n) x = in.load(node);
         const bf16x4 xh = pack_bf16x4(x.x, x.y, x.z, x.w);
         const float4 xr = make_float4(x.x - bf2f((unsigned short)xh[0]),
                                       x.y - bf2f((unsigned short)xh[1]),
@@ -519,7 +539,20 @@ void launch_mlp_forward(hipStream_t s, const float *P, int64_t n, const float *X
     if (n <= 0) return;
     const int64_t tiles = (n + 31) / 32;
     const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 1024);
-    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, s, P, n, X, y);
+    const FeatIn in{reinterpret_cast<const float4 *>(X), nullptr, nullptr, nullptr, nullptr, 1.0,
+                    MlpNorm{}};
+    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, s, P, n, in, y);
+}
+
+void launch_mlp_forward_state(hipStream_t s, const float *P, int64_t n, const double *V,
+                              const double *Vprev, const double *src, const float *kvp, double cm,
+                              const MlpNorm &nm, float *y)
+{
+    if (n <= 0) return;
+    const int64_t tiles = (n + 31) / 32;
+    const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 1024);
+    const FeatIn in{nullptr, V, Vprev, src, kvp, cm, nm};
+    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, s, P, n, in, y);
 }
 
 void launch_mlp_grad(hipStream_t s, const float *P, int64_t n, const float *X, const float *T,

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_rhs_init(
     StepParams sp, const double *__restrict__ V, const double *__restrict__ Vprev,
     const double *__restrict__ src, double *__restrict__ x, double *__restrict__ r,
     double *__restrict__ b, double *__restrict__ partial, const double *__restrict__ kdiag,
-    float *__restrict__ kvp)
+    float *__restrict__ kvp, double *__restrict__ p0)
 {
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256) void k_rhs_init(
         x[row] = x0i;
         r[row] = ri;
         b[row] = bi;
+        if (p0) p0[row] = zi;   // the first direction p0 = z0
         if (kvp) kvp[row] = kdiag[row] != 0.0 ? (float)(kv / kdiag[row]) : 0.0f;
         acc[0] += ri * zi;
         acc[1] += zi * zi;
@@ -389,10 +390,10 @@ void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double am
 void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                      const double *Kv, const double *dinv, const StepParams &sp, const double *V,
                      const double *Vprev, const double *src, double *x, double *r, double *b,
-                     double *partial, const double *kdiag, float *kvp, bool nt)
+                     double *partial, const double *kdiag, float *kvp, double *p0, bool nt)
 {
     MDX_LAUNCH_SELL(P, nt, k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols, Mv,
-                    Kv, dinv, sp, V, Vprev, src, x, r, b, partial, kdiag, kvp);
+                    Kv, dinv, sp, V, Vprev, src, x, r, b, partial, kdiag, kvp, p0);
 }
 
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
