@@ -9,10 +9,13 @@
 // A = chi Cm M + theta dt K, the Jacobi diagonal, rest state.
 //
 // Time loop (mdx_run): per step the kernels of mdx_ionic.hip / mdx_solver.hip
-// are queued on the context's stream; PCG iterations are queued in chunks
-// (first chunk = last step's count) and the host reads the device-side
-// `done` flag once per chunk.  Kernels queued after convergence return at
-// their first instruction.
+// (mdx_mixed.hip, mdx_learned.hip for the forms) are queued on the context's
+// stream; PCG iterations are queued in chunks (first chunk = last step's
+// count).  A chunk ends with the guarded epilogue, a one-wave kernel that
+// publishes the solver scalars to coherent pinned host memory with a
+// sequence number, and the next step's ionic update guarded by the done flag;
+// the host spins on the sequence number.  Kernels queued after convergence
+// return at their first instruction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
