@@ -159,15 +159,42 @@ __device__ __forceinline__ void forward_tile(const MlpLds &w, float4 x, Tile &T,
 
 // ---------------------------------------------------------------------------
 // Inference (the warm start of every time step).  Same function as
-// forward_tile with every layer on the MFMA:
-//   layer 1: K = 8 (the 4 features and 4 zero rows); the FP32 features enter
-//            as a BF16 pair hi + lo (x = hi + lo to about 2^-17 relative), so
-//            two MFMAs reproduce BF16(W1) x in FP32;
+// forward_tile with every layer on v_mfma_f32_32x32x16_bf16 (K = 16, twice
+// the K of the training kernels' instruction per issue):
+//   layer 1: the FP32 features enter as a BF16 pair hi + lo (x = hi + lo to
+//            about 2^-17 relative): B rows 0..3 hi, 4..7 lo, 8..15 zero and
+//            A columns W1, W1, 0, so one MFMA gives BF16(W1) x in FP32;
+//   layers 2, 3: K-step s of a 64-unit layer reads, in lane half h, the
+//            accumulator registers 8 (s % 2) .. + 7 of the previous layer's
+//            output tile s / 2 -- units 16 s + 8 (j / 4) + 4 h + j % 4 for
+//            j = 0..7 -- so the weight fragment takes those columns (two
+//            8-byte LDS reads) and no data moves between lanes;
 //   biases:  FP32, loaded as the accumulators' initial values;
 //   BF16 rounding of the activations by the hardware conversion
 //   (round to nearest even, as f2bf).
 // No pre-activations are kept, so several wavefronts share a SIMD.
 // ---------------------------------------------------------------------------
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8n __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x16 mfma16(s16x8 a, s16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8n, a),
+                                                    __builtin_bit_cast(bf16x8n, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ s16x8 cat8(bf16x4 lo, bf16x4 hi)
+{
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+// A fragment of a hidden layer's W (64 x 64, LDS row stride WSTRIDE) for
+// output tile ot and K-step s: row 32 ot + l % 32, the columns listed above
+__device__ __forceinline__ s16x8 frag_w16(const unsigned short *w, int ot, int s, int lane)
+{
+    const unsigned short *row = w + (32 * ot + (lane & 31)) * WSTRIDE + 16 * s + 4 * (lane >> 5);
+    return cat8(*reinterpret_cast<const bf16x4 *>(row), *reinterpret_cast<const bf16x4 *>(row + 8));
+}
 typedef __bf16 bf16x2n __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
@@ -185,7 +212,7 @@ __device__ __forceinline__ bf16x4 pack_bf16x4(float a, float b, float c, float d
 
 struct alignas(16) InferLds {
     float b1[NH], b2[NH], b3[NH], w4[NH];   // FP32 biases, BF16-rounded w4
-    unsigned short w1[NH * 8];              // BF16 W1, columns 4..7 zero
+    unsigned short w1[NH * 16];             // BF16 [W1 W1 0]: columns 0..3, 4..7, 8..15
     unsigned short w2[NH * WSTRIDE];
     unsigned short w3[NH * WSTRIDE];
     float b4;
@@ -237,9 +264,9 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P
         w.w2[o * WSTRIDE + k] = f2bf(P[OFF_W2 + i]);
         w.w3[o * WSTRIDE + k] = f2bf(P[OFF_W3 + i]);
     }
-    for (int i = threadIdx.x; i < NH * 8; i += blockDim.x) {
-        const int o = i / 8, k = i % 8;
-        w.w1[i] = k < 4 ? f2bf(P[OFF_W1 + 4 * o + k]) : (unsigned short)0;
+    for (int i = threadIdx.x; i < NH * 16; i += blockDim.x) {
+        const int o = i / 16, k = i % 16;
+        w.w1[i] = k < 8 ? f2bf(P[OFF_W1 + 4 * o + (k & 3)]) : (unsigned short)0;
     }
     for (int i = threadIdx.x; i < NH; i += blockDim.x) {
         w.b1[i] = P[OFF_B1 + i];
@@ -269,14 +296,14 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P
                                       x.w - bf2f((unsigned short)xh[3]));
         const bf16x4 xl = pack_bf16x4(xr.x, xr.y, xr.z, xr.w);
         // layer 1
+        const s16x8 xb = cat8(xh, xl);
         bf16x4 h1[8];
 #pragma unroll
         for (int ot = 0; ot < 2; ++ot) {
-            const bf16x4 a =
-                *reinterpret_cast<const bf16x4 *>(w.w1 + (32 * ot + (lane & 31)) * 8 + 4 * half);
+            const s16x8 a =
+                *reinterpret_cast<const s16x8 *>(w.w1 + (32 * ot + (lane & 31)) * 16 + 8 * half);
             f32x16 acc = unit_frag(w.b1, ot, half);
-            acc = mfma(a, xh, acc);
-            acc = mfma(a, xl, acc);
+            acc = mfma16(a, xb, acc);
 #pragma unroll
             for (int g = 0; g < 4; ++g)
                 h1[4 * ot + g] = pack_bf16x4(fmaxf(acc[4 * g], 0.f), fmaxf(acc[4 * g + 1], 0.f),
@@ -288,7 +315,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P
         for (int ot = 0; ot < 2; ++ot) {
             f32x16 acc = unit_frag(w.b2, ot, half);
 #pragma unroll
-            for (int ks = 0; ks < 8; ++ks) acc = mfma(frag_w(w.w2, ot, ks, lane), h1[ks], acc);
+            for (int ks = 0; ks < 4; ++ks)
+                acc = mfma16(frag_w16(w.w2, ot, ks, lane), cat8(h1[2 * ks], h1[2 * ks + 1]), acc);
 #pragma unroll
             for (int g = 0; g < 4; ++g)
                 h2[4 * ot + g] = pack_bf16x4(fmaxf(acc[4 * g], 0.f), fmaxf(acc[4 * g + 1], 0.f),
@@ -300,7 +328,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P
         for (int ot = 0; ot < 2; ++ot) {
             f32x16 acc = unit_frag(w.b3, ot, half);
 #pragma unroll
-            for (int ks = 0; ks < 8; ++ks) acc = mfma(frag_w(w.w3, ot, ks, lane), h2[ks], acc);
+            for (int ks = 0; ks < 4; ++ks)
+                acc = mfma16(frag_w16(w.w3, ot, ks, lane), cat8(h2[2 * ks], h2[2 * ks + 1]), acc);
             const f32x16 w4 = unit_frag(w.w4, ot, half);
 #pragma unroll
             for (int v = 0; v < 16; ++v) s += w4[v] * fmaxf(acc[v], 0.0f);
