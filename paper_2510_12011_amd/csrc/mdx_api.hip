@@ -1741,7 +1741,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                                 nullptr, ctx->rec_X);
             float *kvp_out = want_kvp ? kvp : nullptr;
             if (mixed)
-                launch_rhs_init_mixed(st, T, P, Mv, Kv, dinv, dinv32, sp, V, Vprev, s, X, b, r32,
+                launch_rhs_init_mixed(st, T, P, Mv, Kv, dinv, dinv32, sp, V, Vprev, s, X, r, r32,
                                       z32, delta, part0, kdiag, kvp_out, nt_rhs);
             else
                 launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0, kdiag,
@@ -1797,8 +1797,8 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                     ++units;
                 }
                 launch_cg_test32(st, T, it + c, rr, max_iter, part_rz, sc);
-                launch_replacement(st, T, P, max_iter, Av, X, delta, b, dinv, dinv32, r32, z32,
-                                   part0, sc, nt_iter64);
+                launch_replacement(st, T, P, max_iter, A32, X, delta, r, dinv, dinv32, r32, z32,
+                                   part0, sc, nt_iter32);
                 if (mdx_status e = end_chunk()) return e;
                 done = ctx->sc_host->done != 0;
                 it = ctx->sc_host->it_next;

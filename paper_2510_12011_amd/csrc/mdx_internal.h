@@ -160,7 +160,7 @@ void launch_to_f32(hipStream_t s, int64_t n, const double *a, float *b);
 void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                            const double *Kv, const double *dinv, const float *dinv32,
                            const StepParams &sp, const double *V, const double *Vprev,
-                           const double *src, double *x, double *b, float *r32, float *z32,
+                           const double *src, double *x, double *r64, float *r32, float *z32,
                            float *delta, double *partial, const double *kdiag, float *kvp, bool nt);
 // iteration k: test (or restart point), q = A z + beta q, p = z + beta p, partial p.q
 void launch_cg_spmv32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter, SellView P,
@@ -174,9 +174,10 @@ void launch_cg_update32(hipStream_t s, const Tiling &t, int k, const double *par
 // the test of iteration k alone (end of a chunk)
 void launch_cg_test32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter,
                       const double *partial_rz, Scalars *sc);
-// flush, true residual, finalize (all no-ops unless a replacement is pending)
-void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const double *Av,
-                        double *x, float *delta, const double *b, const double *dinv,
+// true residual update (r64 -= A32 delta), flush, finalize (all no-ops
+// unless a replacement is pending)
+void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const float *A32,
+                        double *x, float *delta, double *r64, const double *dinv,
                         const float *dinv32, float *r32, float *z32, double *partial, Scalars *sc,
                         bool nt);
 

@@ -2,17 +2,19 @@
 // in the SpMV and the vector updates of every iteration, FP64 dot products,
 // FP64 right-hand side and solution, FP64 residual replacement.
 //
-// b, r0 = b - A x0 and every replaced residual use the FP64 matrices, so the
-// solve converges to the solution of the FP64 system: FP32-rounded K loses
-// its zero row sums (K 1 = 0 is what conserves charge) and a rounded A is not
-// the combination of rounded M and K, and either would add a small spurious
-// source at every step that accumulates over a run.
+// b and r0 = b - A x0 are formed with the FP64 matrices, so the solve
+// converges to the solution of the FP64 system: FP32-rounded K loses its zero
+// row sums (K 1 = 0 is what conserves charge) and a rounded A is not the
+// combination of rounded M and K, and either, applied to V itself, would add
+// a small spurious source at every step that accumulates over a run.
 //
 // The FP32 iteration solves for a correction: x64 stays fixed while
 // delta32 accumulates alpha p.  A replacement, triggered every rr
 // iterations, when the recursive residual passes the stopping test, or at
-// the iteration cap, flushes x64 += delta32 and recomputes the true residual
-// r64 = b - A x64 in FP64 -- the stopping test
+// the iteration cap, brings the true residual up to date in FP64,
+// r64 -= A delta32 (A's FP32 values, products exact in FP64: the rounding of
+// A enters only through the correction, about 6e-8 |delta| / |x| relative),
+// then flushes x64 += delta32 -- the stopping test
 // is then applied to that true residual, so the solve stops on the same
 // criterion as the FP64 path.  If the true residual does not pass, the
 // iteration continues from r = r64: after a periodic replacement with
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
     const float *__restrict__ dinv32, StepParams sp, const double *__restrict__ V,
     const double *__restrict__ Vprev, const double *__restrict__ src, double *__restrict__ x,
-    double *__restrict__ b, float *__restrict__ r32, float *__restrict__ z32,
+    double *__restrict__ r64, float *__restrict__ r32, float *__restrict__ z32,
     float *__restrict__ delta, double *__restrict__ partial, const double *__restrict__ kdiag,
     float *__restrict__ kvp)
 {
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
         const double ri = bi - (cM_new * mx + cK_new * kx);
         const double vi = V[row];
         x[row] = extrap ? 2.0 * vi - Vprev[row] : vi;
-        b[row] = bi;
+        r64[row] = ri;
         if (kvp) kvp[row] = kdiag[row] != 0.0 ? (float)(kv / kdiag[row]) : 0.0f;
         const float rf = (float)ri;
         r32[row] = rf;
@@ -230,7 +232,7 @@ __global__ __launch_bounds__(256) void k_cg_test32(int groups, int k, int rr, in
     test_z(sc, sqrt(v[1]), k, rr, max_iter, threadIdx.x == 0);
 }
 
-// replacement, part 1: x64 += delta, delta = 0
+// replacement, part 2: x64 += delta, delta = 0
 __global__ __launch_bounds__(256) void k_flush(int64_t n, double *__restrict__ x,
                                                float *__restrict__ delta,
                                                const Scalars *__restrict__ sc)
@@ -243,12 +245,15 @@ __global__ __launch_bounds__(256) void k_flush(int64_t n, double *__restrict__ x
     }
 }
 
-// replacement, part 2: r64 = b - A x64 in FP64, r32 = r64, z32 = D^-1 r32;
-// partials r32.z32 and |D^-1 r64|^2
+// replacement, part 1: the true residual of x64 + delta brought up to date
+// in FP64, r64 -= A delta, r32 = r64, z32 = D^-1 r32; partials r32.z32 and
+// |D^-1 r64|^2.  r64 starts as b - A x0 formed in FP64 by the right-hand-side
+// pass; each product of an FP32 value of A and the FP32 correction is exact
+// in FP64, so only A's FP32 rounding enters, and only through delta.
 template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_true_residual(
     Tiling t, const int64_t *__restrict__ slice_ptr, Cols<CI> col,
-    const double *__restrict__ Av, const double *__restrict__ x, const double *__restrict__ b,
+    const float *__restrict__ A32, const float *__restrict__ delta, double *__restrict__ r64,
     const double *__restrict__ dinv, const float *__restrict__ dinv32, float *__restrict__ r32,
     float *__restrict__ z32, double *__restrict__ partial, const Scalars *__restrict__ sc)
 {
@@ -262,10 +267,12 @@ __global__ __launch_bounds__(256) void k_true_residual(
         const int64_t sl = row / SLICE;
         const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
         const int32_t cb = slice_base(col, sl);
-        double ax = 0.0;
+        double ad = 0.0;
 #pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) ax += ld_stream<NT>(Av + e) * x[cb + (int32_t)ld_stream<NT>(col.idx + e)];
-        const double ri = b[row] - ax;
+        for (int64_t e = beg; e < end; e += SLICE)
+            ad += (double)ld_stream<NT>(A32 + e) * (double)delta[cb + (int32_t)ld_stream<NT>(col.idx + e)];
+        const double ri = r64[row] - ad;
+        r64[row] = ri;
         const float rf = (float)ri;
         r32[row] = rf;
         const float zf = dinv32[row] * rf;
@@ -325,11 +332,11 @@ void launch_to_f32(hipStream_t s, int64_t n, const double *a, float *b)
 void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                            const double *Kv, const double *dinv, const float *dinv32,
                            const StepParams &sp, const double *V, const double *Vprev,
-                           const double *src, double *x, double *b, float *r32, float *z32,
+                           const double *src, double *x, double *r64, float *r32, float *z32,
                            float *delta, double *partial, const double *kdiag, float *kvp, bool nt)
 {
     MDX_LAUNCH_SELL(P, nt, k_rhs_init_mixed, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
-                    Mv, Kv, dinv, dinv32, sp, V, Vprev, src, x, b, r32, z32, delta, partial, kdiag,
+                    Mv, Kv, dinv, dinv32, sp, V, Vprev, src, x, r64, r32, z32, delta, partial, kdiag,
                     kvp);
 }
 
@@ -357,15 +364,15 @@ void launch_cg_test32(hipStream_t s, const Tiling &t, int k, int rr, int max_ite
                        sc);
 }
 
-void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const double *Av,
-                        double *x, float *delta, const double *b, const double *dinv,
+void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const float *A32,
+                        double *x, float *delta, double *r64, const double *dinv,
                         const float *dinv32, float *r32, float *z32, double *partial, Scalars *sc,
                         bool nt)
 {
     const int64_t n = t.n_rows;
-    hipLaunchKernelGGL(k_flush, dim3(blocks_for(n)), dim3(256), 0, s, n, x, delta, sc);
     MDX_LAUNCH_SELL(P, nt, k_true_residual, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
-                    Av, x, b, dinv, dinv32, r32, z32, partial, sc);
+                    A32, delta, r64, dinv, dinv32, r32, z32, partial, sc);
+    hipLaunchKernelGGL(k_flush, dim3(blocks_for(n)), dim3(256), 0, s, n, x, delta, sc);
     hipLaunchKernelGGL(k_replace_finalize, dim3(1), dim3(TILE), 0, s, t.groups, max_iter, partial,
                        sc);
 }
