@@ -32,7 +32,8 @@
 #include <string.h>
 
 /* ------------------------------------------------------------------------ */
-/* Sparsity pattern: row i holds every node sharing a tetrahedron with i.    */
+/* Sparsity pattern: row i holds every node sharing an element with i       */
+/* (npe vertex ids per element: 4 for tetrahedra, 3 for surface triangles). */
 /* Columns sorted ascending.  Returns nnz; fills col only if cap >= nnz.     */
 /* ------------------------------------------------------------------------ */
 static int cmp_i32(const void *a, const void *b)
@@ -41,26 +42,26 @@ static int cmp_i32(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
-int64_t orc_pattern(int64_t n, int64_t m, const int32_t *tets,
-                    int64_t *row_ptr, int32_t *col, int64_t cap)
+int64_t orc_pattern_elems(int64_t n, int64_t m, int npe, const int32_t *el,
+                          int64_t *row_ptr, int32_t *col, int64_t cap)
 {
     int64_t *cnt = calloc((size_t)n + 1, sizeof(int64_t));
     for (int64_t e = 0; e < m; ++e)
-        for (int a = 0; a < 4; ++a) cnt[tets[4 * e + a] + 1] += 1;
+        for (int a = 0; a < npe; ++a) cnt[el[npe * e + a] + 1] += 1;
     for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
     int64_t *fill = malloc(sizeof(int64_t) * (size_t)n);
     int32_t *inc = malloc(sizeof(int32_t) * (size_t)(cnt[n] > 0 ? cnt[n] : 1));
     memcpy(fill, cnt, sizeof(int64_t) * (size_t)n);
     for (int64_t e = 0; e < m; ++e)
-        for (int a = 0; a < 4; ++a) inc[fill[tets[4 * e + a]]++] = (int32_t)e;
+        for (int a = 0; a < npe; ++a) inc[fill[el[npe * e + a]]++] = (int32_t)e;
 
     int32_t buf[4096];
     int64_t nnz = 0;
     row_ptr[0] = 0;
     for (int64_t i = 0; i < n; ++i) {
         int nb = 0;
-        for (int64_t t = cnt[i]; t < cnt[i + 1]; ++t)
-            for (int a = 0; a < 4; ++a) buf[nb++] = tets[4 * (int64_t)inc[t] + a];
+        for (int64_t t = cnt[i]; t < cnt[i + 1] && nb + npe <= 4096; ++t)
+            for (int a = 0; a < npe; ++a) buf[nb++] = el[npe * (int64_t)inc[t] + a];
         if (nb == 0) buf[nb++] = (int32_t)i; /* isolated node keeps its diagonal */
         qsort(buf, (size_t)nb, sizeof(int32_t), cmp_i32);
         int nu = 0;
@@ -72,6 +73,12 @@ int64_t orc_pattern(int64_t n, int64_t m, const int32_t *tets,
     }
     free(cnt); free(fill); free(inc);
     return nnz;
+}
+
+int64_t orc_pattern(int64_t n, int64_t m, const int32_t *tets,
+                    int64_t *row_ptr, int32_t *col, int64_t cap)
+{
+    return orc_pattern_elems(n, m, 4, tets, row_ptr, col, cap);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -169,6 +176,103 @@ int64_t orc_assemble(int64_t n, const double *xyz, int64_t m, const int32_t *tet
                 int64_t s = find_slot(row_ptr, col, t[a], t[b]);
                 Mv[s] += Me[4 * a + b];
                 Kv[s] += Ke[4 * a + b];
+            }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Element matrices of a P1 triangle of a surface mesh in 3D (the paper's    */
+/* "Software functionality" section admits triangular as well as           */
+/* tetrahedral elements).  With the edge matrix E = [x1-x0, x2-x0] (3x2)     */
+/* and its metric G = E^T E:                                                 */
+/*   area = sqrt(det G) / 2;                                                 */
+/*   the surface gradient of phi_a is E G^{-1} d_a, with the reference      */
+/*   gradients d_0 = (-1,-1), d_1 = (1,0), d_2 = (0,1);                      */
+/*   sigma = st I + (sl - st) f f^T, f the fibre's projection on the         */
+/*   triangle's plane, E G^{-1} E^T fib, normalised (isotropic st if there   */
+/*   is no fibre or it is normal to the triangle);                           */
+/*   K_e[a][b] = area * grad phi_a . sigma grad phi_b;                       */
+/*   M_e[a][b] = area/12 * (1 + delta_ab)  (exact consistent P1 mass).       */
+/* Me, Ke: 3x3 row-major.  Returns det G (zero for a degenerate triangle).   */
+/* ------------------------------------------------------------------------ */
+double orc_element_tri(const double *p0, const double *p1, const double *p2,
+                       const double *fib, double sl, double st, double *Me, double *Ke)
+{
+    double E[3][2];
+    for (int r = 0; r < 3; ++r) {
+        E[r][0] = p1[r] - p0[r];
+        E[r][1] = p2[r] - p0[r];
+    }
+    double G[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 3; ++r) G[i][j] += E[r][i] * E[r][j];
+    double detG = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+    if (!(detG > 0.0)) return 0.0;
+    double Gi[2][2] = {{G[1][1] / detG, -G[0][1] / detG}, {-G[1][0] / detG, G[0][0] / detG}};
+    double area = 0.5 * sqrt(detG);
+    /* E G^{-1} (3x2): maps reference gradients to surface gradients */
+    double EGi[3][2];
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 2; ++j) EGi[r][j] = E[r][0] * Gi[0][j] + E[r][1] * Gi[1][j];
+    const double d[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+    double g[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int r = 0; r < 3; ++r) g[a][r] = EGi[r][0] * d[a][0] + EGi[r][1] * d[a][1];
+
+    double f[3] = {0.0, 0.0, 0.0};
+    if (fib) {
+        double Etf[2] = {0.0, 0.0};
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 3; ++r) Etf[j] += E[r][j] * fib[r];
+        double pf[3], pn = 0.0;
+        for (int r = 0; r < 3; ++r) {
+            pf[r] = EGi[r][0] * Etf[0] + EGi[r][1] * Etf[1];
+            pn += pf[r] * pf[r];
+        }
+        pn = sqrt(pn);
+        double fn = sqrt(fib[0] * fib[0] + fib[1] * fib[1] + fib[2] * fib[2]);
+        /* a fibre (numerically) normal to the triangle leaves it isotropic */
+        if (pn > 1e-12 * fn)
+            for (int r = 0; r < 3; ++r) f[r] = pf[r] / pn;
+    }
+    double S[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            S[r][c] = (r == c ? st : 0.0) + (sl - st) * f[r] * f[c];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) s += g[a][r] * S[r][c] * g[b][c];
+            Ke[3 * a + b] = area * s;
+            Me[3 * a + b] = area / 12.0 * (a == b ? 2.0 : 1.0);
+        }
+    return detG;
+}
+
+/* Global M and K of a triangle surface mesh on the pattern from
+ * orc_pattern_elems (npe = 3).  Returns 0, or -(e+1) for the first
+ * degenerate triangle e. */
+int64_t orc_assemble_tri(int64_t n, const double *xyz, int64_t m, const int32_t *tris,
+                         const double *fibre, const double *sl, const double *st,
+                         const int64_t *row_ptr, const int32_t *col,
+                         double *Mv, double *Kv)
+{
+    memset(Mv, 0, sizeof(double) * (size_t)row_ptr[n]);
+    memset(Kv, 0, sizeof(double) * (size_t)row_ptr[n]);
+    double Me[9], Ke[9];
+    for (int64_t e = 0; e < m; ++e) {
+        const int32_t *t = tris + 3 * e;
+        double detG = orc_element_tri(xyz + 3 * t[0], xyz + 3 * t[1], xyz + 3 * t[2],
+                                      fibre ? fibre + 3 * e : NULL, sl[e], st[e], Me, Ke);
+        if (!(detG > 0.0)) return -(e + 1);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                int64_t s = find_slot(row_ptr, col, t[a], t[b]);
+                Mv[s] += Me[3 * a + b];
+                Kv[s] += Ke[3 * a + b];
             }
     }
     return 0;

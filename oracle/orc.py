@@ -49,6 +49,12 @@ def lib():
         L.orc_element.argtypes = [P, P, P, P, P, f64, f64, P, P]
         L.orc_assemble.restype = i64
         L.orc_assemble.argtypes = [i64, P, i64, P, P, P, P, P, P, P, P]
+        L.orc_pattern_elems.restype = i64
+        L.orc_pattern_elems.argtypes = [i64, i64, C.c_int, P, P, P, i64]
+        L.orc_element_tri.restype = f64
+        L.orc_element_tri.argtypes = [P, P, P, P, f64, f64, P, P]
+        L.orc_assemble_tri.restype = i64
+        L.orc_assemble_tri.argtypes = [i64, P, i64, P, P, P, P, P, P, P, P]
         L.orc_spmv.restype = None
         L.orc_spmv.argtypes = [i64, P, P, P, P, P]
         L.orc_pcg.restype = i32
@@ -96,12 +102,27 @@ def element(pts, fibre=None, sl=1.0, st=1.0):
     return Me.reshape(4, 4), Ke.reshape(4, 4), det
 
 
-def pattern(n, tets):
-    tets = _c(tets, np.int32)
+def element_tri(pts, fibre=None, sl=1.0, st=1.0):
+    """Element mass and stiffness of one surface triangle in 3D:
+    (Me[3,3], Ke[3,3], det of the metric E^T E)."""
+    pts = _c(pts, np.float64).reshape(3, 3)
+    fib = None if fibre is None else _c(fibre, np.float64)
+    Me = np.zeros(9)
+    Ke = np.zeros(9)
+    det = lib().orc_element_tri(_p(pts[0]), _p(pts[1]), _p(pts[2]), _p(fib),
+                                float(sl), float(st), _p(Me), _p(Ke))
+    return Me.reshape(3, 3), Ke.reshape(3, 3), det
+
+
+def pattern(n, elems):
+    """CSR pattern of an element mesh ([m, 4] tetrahedra or [m, 3]
+    surface triangles): row i holds every node sharing an element with i."""
+    elems = _c(elems, np.int32)
+    npe = elems.shape[1]
     row_ptr = np.zeros(n + 1, np.int64)
-    nnz = lib().orc_pattern(n, tets.shape[0], _p(tets), _p(row_ptr), None, 0)
+    nnz = lib().orc_pattern_elems(n, elems.shape[0], npe, _p(elems), _p(row_ptr), None, 0)
     col = np.zeros(nnz, np.int32)
-    lib().orc_pattern(n, tets.shape[0], _p(tets), _p(row_ptr), _p(col), nnz)
+    lib().orc_pattern_elems(n, elems.shape[0], npe, _p(elems), _p(row_ptr), _p(col), nnz)
     return row_ptr, col
 
 
@@ -125,7 +146,8 @@ class Matrices:
 
 
 def assemble(xyz, tets, fibre, sl, st):
-    """Global consistent mass M and stiffness K (CSR, sorted columns)."""
+    """Global consistent mass M and stiffness K (CSR, sorted columns) of a
+    tetrahedral mesh ([m, 4]) or a triangle surface mesh ([m, 3])."""
     xyz = _c(xyz, np.float64)
     tets = _c(tets, np.int32)
     n, m = xyz.shape[0], tets.shape[0]
@@ -135,8 +157,9 @@ def assemble(xyz, tets, fibre, sl, st):
     row_ptr, col = pattern(n, tets)
     M = np.zeros(col.shape[0])
     K = np.zeros(col.shape[0])
-    rc = lib().orc_assemble(n, _p(xyz), m, _p(tets), _p(fib), _p(sl), _p(st),
-                            _p(row_ptr), _p(col), _p(M), _p(K))
+    fn = lib().orc_assemble_tri if tets.shape[1] == 3 else lib().orc_assemble
+    rc = fn(n, _p(xyz), m, _p(tets), _p(fib), _p(sl), _p(st),
+            _p(row_ptr), _p(col), _p(M), _p(K))
     if rc != 0:
         raise ValueError(f"degenerate element {-rc - 1}")
     return Matrices(row_ptr, col, M, K)
@@ -245,6 +268,8 @@ class Oracle:
         self.spec = spec
         self.mats = assemble_spec(spec) if mats is None else mats
         self.kind = spec.ionic
+        if ionic_params is None:
+            ionic_params = getattr(spec, "ionic_params", None)
         self.params = (ionic_defaults(self.kind) if ionic_params is None
                        else _c(ionic_params, np.float64))
         n = spec.mesh.n_nodes

@@ -19,6 +19,10 @@ Meshes
 * ``shell_cap``: a truncated ellipsoidal shell meshed as unstructured tets
   (Delaunay tetrahedralisation of a jittered lattice), with helical fibres;
   ``batch_shells`` draws a seeded cohort of them for the batched form.
+* ``icosphere`` / ``ellipsoid_surface``: closed triangle surface meshes (the
+  icosahedron refined by edge midpoints, pushed onto the unit sphere, then
+  scaled to an ellipsoid), the stand-in for the paper's left-atrium surface
+  meshes (``atrium_surface``).
 """
 from __future__ import annotations
 
@@ -37,10 +41,11 @@ UA_PER_CM2_TO_PER_MM2 = 0.01    # I_stim: 50 uA/cm^2 -> 0.5 uA/mm^2
 
 @dataclass
 class Mesh:
-    """A P1 tetrahedral mesh in mm.
+    """A P1 mesh in mm: tetrahedra, or triangles of a surface in 3D.
 
     xyz     float64 [n, 3]  vertex coordinates (possibly jittered)
-    tets    int32   [m, 4]  vertex ids, 0-based, positively oriented
+    tets    int32   [m, 4]  vertex ids, 0-based, positively oriented; or
+                    [m, 3]  the vertex ids of surface triangles
     grid    float64 [n, 3]  unjittered coordinates (stimulus regions are
                             selected on these), equal to xyz if no jitter
     fibre   float64 [m, 3]  per-element fibre direction or None (isotropic)
@@ -161,6 +166,7 @@ class RunSpec:
     # entries (region ids, il, it, el, et) in S/m, applied after sigma_l/t
     ie_regions: list = field(default_factory=list)
     lumped_mass: bool = False  # M lumped (row sums on the diagonal)
+    ionic_params: tuple | None = None   # the cell model's parameters (None: defaults)
 
     def sigma_per_tet(self):
         m = self.mesh.n_tets
@@ -533,3 +539,95 @@ def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
                              stimuli=[stim]))
     return BatchSpec(name=f"shells{n_inst}_{sum(m.n_nodes for m in meshes)}", instances=inst,
                      chi=140.0, cm=0.01, theta=0.5, ionic=ionic, dt=dt, n_steps=n_steps)
+
+
+# ---------------------------------------------------------------------------
+# closed triangle surfaces (the atrial surface workload)
+# ---------------------------------------------------------------------------
+def icosphere(level: int):
+    """Unit-sphere triangulation: the regular icosahedron (12 vertices, 20
+    faces) with every triangle split into four at its edge midpoints
+    ``level`` times, each new vertex pushed onto the sphere.  Returns
+    (xyz [10*4^level + 2, 3], tris [20*4^level, 3] int32), faces oriented
+    outwards."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    xyz = np.array([(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0),
+                    (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+                    (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)], np.float64)
+    xyz /= np.linalg.norm(xyz, axis=1, keepdims=True)
+    tris = np.array([(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11),
+                     (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
+                     (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
+                     (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)], np.int64)
+    for _ in range(level):
+        n = xyz.shape[0]
+        a, b, c = tris[:, 0], tris[:, 1], tris[:, 2]
+        e = np.stack([np.concatenate([a, b, c]), np.concatenate([b, c, a])], axis=1)
+        key = np.minimum(e[:, 0], e[:, 1]) * n + np.maximum(e[:, 0], e[:, 1])
+        uk, inv = np.unique(key, return_inverse=True)
+        lo, hi = uk // n, uk % n
+        mid = xyz[lo] + xyz[hi]
+        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
+        xyz = np.concatenate([xyz, mid])
+        m_ab, m_bc, m_ca = (n + inv).reshape(3, -1)
+        tris = np.concatenate([np.stack([a, m_ab, m_ca], 1), np.stack([b, m_bc, m_ab], 1),
+                               np.stack([c, m_ca, m_bc], 1), np.stack([m_ab, m_bc, m_ca], 1)])
+    # orient outwards: (x1 - x0) x (x2 - x0) along the centroid
+    p = xyz[tris]
+    nrm = np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0])
+    flip = np.einsum("ij,ij->i", nrm, p.mean(axis=1)) < 0
+    tris[flip, 1], tris[flip, 2] = tris[flip, 2].copy(), tris[flip, 1].copy()
+    return xyz, tris.astype(np.int32)
+
+
+def ellipsoid_surface(level: int, axes=(40.0, 33.0, 30.0), fibres: bool = True) -> Mesh:
+    """Closed ellipsoidal surface (semi-axes in mm) from ``icosphere(level)``;
+    fibres (if asked) along z x c for each triangle's centroid c, which the
+    solver projects onto the triangle's plane."""
+    u, tris = icosphere(level)
+    xyz = u * np.asarray(axes, np.float64)
+    fib = None
+    if fibres:
+        cen = xyz[tris].mean(axis=1)
+        fib = np.stack([-cen[:, 1], cen[:, 0], np.zeros(cen.shape[0])], axis=1)
+    return Mesh(xyz=xyz, tets=tris, grid=xyz.copy(), fibre=fib,
+                region=np.zeros(tris.shape[0], np.int32), shape=(level,))
+
+
+# modified two-variable Mitchell-Schaeffer of the paper's left-atrium example:
+# tau_in, tau_out, tau_open, tau_close, u_gate (its u_crit, 0.1 there too, is
+# the same threshold here), v_rest, v_amp
+ATRIUM_MS_PARAMS = (0.15, 1.5, 105.0, 185.0, 0.1, -80.0, 100.0)
+
+
+def atrium_surface(level: int = 8, n_steps: int = 5000, axes=(40.0, 33.0, 30.0),
+                   radius: float = 2.0) -> RunSpec:
+    """Left-atrium-like surface workload, after the paper's atrium example:
+    a closed ellipsoidal triangle surface (level 8: 655,362 nodes, close to the
+    660,557-node atrial mesh it reports), isotropic 0.4 S/m, the modified
+    Mitchell-Schaeffer parameters above, dt 0.01 ms, a 50 uA/cm^2 stimulus for
+    2 ms on the nodes within ``radius`` mm of the +x apex, absolute and
+    relative tolerance 1e-5 (relative to ||D^-1 b||)."""
+    mesh = ellipsoid_surface(level, axes, fibres=False)
+    apex = np.array([axes[0], 0.0, 0.0])
+    nodes = np.flatnonzero(np.linalg.norm(mesh.xyz - apex, axis=1) <= radius).astype(np.int32)
+    stim = Stimulus(nodes, 0.0, 2.0, 50.0 * UA_PER_CM2_TO_PER_MM2)
+    return RunSpec(name=f"atrium_surface_{mesh.n_nodes}", mesh=mesh, sigma_l=0.4, sigma_t=0.4,
+                   chi=1400 * PER_CM_TO_PER_MM, cm=1.0 * UF_PER_CM2_TO_PER_MM2, theta=0.5,
+                   ionic="ms", dt=0.01, n_steps=n_steps, stimuli=[stim], rtol=1e-5, atol=1e-5,
+                   rel_mode=1, max_iter=100, ionic_params=ATRIUM_MS_PARAMS)
+
+
+def small_surface(level: int = 4, n_steps: int = 400, anisotropic: bool = True) -> RunSpec:
+    """A small ellipsoidal surface for parity runs (level 4: 2,562 nodes,
+    semi-axes 8 x 6.6 x 6 mm), tangent-projected azimuthal fibres with 0.4 /
+    0.1 S/m if ``anisotropic``, the atrial cell parameters, dt 0.01 ms."""
+    axes = (8.0, 6.6, 6.0)
+    mesh = ellipsoid_surface(level, axes, fibres=anisotropic)
+    apex = np.array([axes[0], 0.0, 0.0])
+    nodes = np.flatnonzero(np.linalg.norm(mesh.xyz - apex, axis=1) <= 1.2).astype(np.int32)
+    stim = Stimulus(nodes, 0.0, 2.0, 50.0 * UA_PER_CM2_TO_PER_MM2)
+    return RunSpec(name=f"small_surface_{mesh.n_nodes}", mesh=mesh, sigma_l=0.4,
+                   sigma_t=0.1 if anisotropic else 0.4, chi=1400 * PER_CM_TO_PER_MM,
+                   cm=1.0 * UF_PER_CM2_TO_PER_MM2, theta=0.5, ionic="ms", dt=0.01,
+                   n_steps=n_steps, stimuli=[stim], rtol=1e-10, ionic_params=ATRIUM_MS_PARAMS)
