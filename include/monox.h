@@ -137,6 +137,20 @@ MDX_API int mdx_version(void);
 MDX_API mdx_status mdx_set_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz,
                         double unit_conversion, int64_t n_tets, const int32_t *tets,
                         const int32_t *region, const double *fibre);
+/* Surface mesh (P1 triangles in 3D, the triangular elements the paper's
+ * "Software functionality" section admits beside tetrahedra).  The same
+ * arguments as mdx_set_mesh with tris: n_tris*3 ids (any orientation),
+ * region and fibre per triangle.  M and K are the P1 matrices of the
+ * surface: M_e = area/12 (1 + d_ab), K_e = area grad(phi_a) . sigma
+ * grad(phi_b) with gradients along the triangle and sigma built on the
+ * fibre's projection onto the triangle's plane (isotropic where that
+ * projection vanishes).  Rejects non-finite coordinates, ids out of range
+ * and triangles with |(x1 - x0) x (x2 - x0)| <= 1e-14 h^2.  The batched
+ * form takes tetrahedra only. */
+MDX_API mdx_status mdx_set_surface_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz,
+                                        double unit_conversion, int64_t n_tris,
+                                        const int32_t *tris, const int32_t *region,
+                                        const double *fibre);
 /* Conductivities (S/m) along (il) and across (it) the fibre for every
  * element whose region tag is in region_ids[0..n_ids).  Later calls override
  * earlier ones for the same tag.  Every tag present must be covered before

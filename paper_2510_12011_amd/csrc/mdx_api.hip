@@ -73,8 +73,9 @@ struct mdx_ctx {
 
     // problem statement (host copies, original numbering)
     int64_t n = 0, m = 0;
+    int npe = 4;                   // vertex ids per element: 4 tetrahedra, 3 surface triangles
     std::vector<double> xyz;       // mm
-    std::vector<int32_t> tets, region;
+    std::vector<int32_t> tets, region;   // tets: 4 ids per element (-1 after a triangle's 3)
     std::vector<double> fibre;     // empty: isotropic
     std::map<int32_t, std::pair<double, double>> cond;
     double chi = 140.0, cm = 0.01, theta = 0.5;
@@ -194,19 +195,21 @@ mdx_status fail(mdx_ctx *c, mdx_status st, const char *fmt, ...)
     }
 
 // ---------------------------------------------------------------------------
-// graph of the mesh: node -> neighbouring nodes (sharing a tet), no self
+// graph of the mesh: node -> neighbouring nodes (sharing an element), no
+// self.  Elements are 4-id records of which the first npe ids are used.
 // ---------------------------------------------------------------------------
-void node_graph(int64_t n, int64_t m, const int32_t *tets, std::vector<int64_t> &ptr,
+void node_graph(int64_t n, int64_t m, int npe, const int32_t *tets, std::vector<int64_t> &ptr,
                 std::vector<int32_t> &adj)
 {
     std::vector<int64_t> tptr(n + 1, 0);
-    for (int64_t q = 0; q < 4 * m; ++q) tptr[tets[q] + 1]++;
+    for (int64_t e = 0; e < m; ++e)
+        for (int a = 0; a < npe; ++a) tptr[tets[4 * e + a] + 1]++;
     for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
     std::vector<int32_t> tlist(tptr[n]);
     {
         std::vector<int64_t> pos(tptr.begin(), tptr.end() - 1);
         for (int64_t e = 0; e < m; ++e)
-            for (int a = 0; a < 4; ++a) tlist[pos[tets[4 * e + a]]++] = (int32_t)e;
+            for (int a = 0; a < npe; ++a) tlist[pos[tets[4 * e + a]]++] = (int32_t)e;
     }
     std::vector<int32_t> mark(n, -1);
     ptr.assign(n + 1, 0);
@@ -217,7 +220,7 @@ void node_graph(int64_t n, int64_t m, const int32_t *tets, std::vector<int64_t> 
         mark[i] = (int32_t)i;
         for (int64_t q = tptr[i]; q < tptr[i + 1]; ++q) {
             const int32_t *t = tets + 4 * (int64_t)tlist[q];
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < npe; ++a)
                 if (mark[t[a]] != (int32_t)i) {
                     mark[t[a]] = (int32_t)i;
                     adj.push_back(t[a]);
@@ -772,14 +775,16 @@ IterMatrix iter_matrix(const mdx_ctx *c)
     return A;
 }
 
+// npe: vertex ids per element in the caller's array (4 tetrahedra, 3 surface
+// triangles); inside, every element is a 4-id record (-1 after a triangle's 3)
 mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, bool batched,
                          int64_t n_nodes, const double *xyz, double unit_conversion,
-                         int64_t n_tets, const int32_t *tets, const int32_t *region,
-                         const double *fibre)
+                         int64_t n_tets, const int32_t *elems, const int32_t *region,
+                         const double *fibre, int npe = 4)
 {
     if (!ctx) return MDX_ERR_INVALID_ARG;
     GUARD_BEGIN
-    if (n_nodes <= 0 || n_tets <= 0 || !xyz || !tets)
+    if (n_nodes <= 0 || n_tets <= 0 || !xyz || !elems)
         return fail(ctx, MDX_ERR_INVALID_ARG, "empty mesh or null array");
     if (n_nodes >= (int64_t)1 << 31 || n_tets >= (int64_t)1 << 27)
         return fail(ctx, MDX_ERR_INVALID_ARG, "mesh too large (n < 2^31, tets < 2^27)");
@@ -789,10 +794,14 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
         if (!std::isfinite(xyz[i]))
             return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite coordinate at node %lld",
                         (long long)(i / 3));
-    for (int64_t q = 0; q < 4 * n_tets; ++q)
-        if (tets[q] < 0 || tets[q] >= n_nodes)
+    for (int64_t q = 0; q < npe * n_tets; ++q)
+        if (elems[q] < 0 || elems[q] >= n_nodes)
             return fail(ctx, MDX_ERR_BAD_MESH, "element %lld references node %d out of range",
-                        (long long)(q / 4), tets[q]);
+                        (long long)(q / npe), elems[q]);
+    std::vector<int32_t> tv((size_t)(4 * n_tets), -1);
+    for (int64_t e = 0; e < n_tets; ++e)
+        for (int a = 0; a < npe; ++a) tv[4 * e + a] = elems[npe * e + a];
+    const int32_t *tets = tv.data();
     if (node_ptr[0] != 0 || node_ptr[n_inst] != n_nodes)
         return fail(ctx, MDX_ERR_INVALID_ARG, "node_ptr must run from 0 to n_nodes");
     for (int32_t i = 0; i < n_inst; ++i)
@@ -802,7 +811,7 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
     for (int32_t i = 0; i < n_inst; ++i)
         std::fill(inst_of.begin() + node_ptr[i], inst_of.begin() + node_ptr[i + 1], i);
     for (int64_t e = 0; e < n_tets; ++e)
-        for (int a = 1; a < 4; ++a)
+        for (int a = 1; a < npe; ++a)
             if (inst_of[tets[4 * e + a]] != inst_of[tets[4 * e]])
                 return fail(ctx, MDX_ERR_BAD_MESH, "element %lld joins two instances",
                             (long long)e);
@@ -813,14 +822,15 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
                             (long long)(q / 3));
     std::vector<double> X(xyz, xyz + 3 * n_nodes);
     for (double &v : X) v /= unit_conversion;
-    // element quality: |det J| > 1e-14 h^3
+    // element quality: tetrahedra |det J| > 1e-14 h^3, triangles
+    // |(x1 - x0) x (x2 - x0)| > 1e-14 h^2
     for (int64_t e = 0; e < n_tets; ++e) {
         const int32_t *t = tets + 4 * e;
-        double d[3][3], h2 = 0.0;
-        for (int a = 1; a < 4; ++a)
+        double d[3][3] = {}, h2 = 0.0;
+        for (int a = 1; a < npe; ++a)
             for (int k = 0; k < 3; ++k) d[a - 1][k] = X[3 * t[a] + k] - X[3 * t[0] + k];
-        for (int a = 0; a < 4; ++a)
-            for (int b = a + 1; b < 4; ++b) {
+        for (int a = 0; a < npe; ++a)
+            for (int b = a + 1; b < npe; ++b) {
                 double s = 0.0;
                 for (int k = 0; k < 3; ++k) {
                     double w = X[3 * t[a] + k] - X[3 * t[b] + k];
@@ -828,6 +838,16 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
                 }
                 h2 = std::max(h2, s);
             }
+        if (npe == 3) {
+            const double cx = d[0][1] * d[1][2] - d[0][2] * d[1][1];
+            const double cy = d[0][2] * d[1][0] - d[0][0] * d[1][2];
+            const double cz = d[0][0] * d[1][1] - d[0][1] * d[1][0];
+            const double c2 = std::sqrt(cx * cx + cy * cy + cz * cz);
+            if (!(c2 > 1e-14 * h2))
+                return fail(ctx, MDX_ERR_BAD_MESH, "degenerate element %lld (2 area = %g)",
+                            (long long)e, c2);
+            continue;
+        }
         double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
                      d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
                      d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
@@ -844,7 +864,7 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
     // cache lines than in a level-by-level order)
     std::vector<int64_t> gptr;
     std::vector<int32_t> gadj;
-    node_graph(n_nodes, n_tets, tets, gptr, gadj);
+    node_graph(n_nodes, n_tets, npe, tets, gptr, gadj);
     std::vector<int32_t> order;
     if (batched) {
         order.reserve(n_nodes);
@@ -938,8 +958,9 @@ mdx_status set_mesh_impl(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, 
 
     ctx->n = n_nodes;
     ctx->m = n_tets;
+    ctx->npe = npe;
     ctx->xyz.swap(X);
-    ctx->tets.assign(tets, tets + 4 * n_tets);
+    ctx->tets.swap(tv);
     ctx->region.assign(n_tets, 0);
     if (region) ctx->region.assign(region, region + n_tets);
     ctx->fibre.clear();
@@ -1285,6 +1306,15 @@ mdx_status mdx_set_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz, double
                          fibre);
 }
 
+mdx_status mdx_set_surface_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz,
+                                double unit_conversion, int64_t n_tris, const int32_t *tris,
+                                const int32_t *region, const double *fibre)
+{
+    const int64_t ptr[2] = {0, n_nodes};
+    return set_mesh_impl(ctx, 1, ptr, false, n_nodes, xyz, unit_conversion, n_tris, tris, region,
+                         fibre, 3);
+}
+
 mdx_status mdx_set_mesh_batch(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr, int64_t n_nodes,
                               const double *xyz, double unit_conversion, int64_t n_tets,
                               const int32_t *tets, const int32_t *region, const double *fibre)
@@ -1472,13 +1502,16 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
         sig[2 * e] = it->second.first;
         sig[2 * e + 1] = it->second.second;
     }
-    // slot map: contributions (tet*16 + a*4 + b) per slot, ascending tet order
+    // slot map: contributions (element*16 + a*4 + b, a and b < npe) per slot,
+    // ascending element order
+    const int npe = ctx->npe;
+    const int64_t ncontrib = (int64_t)npe * npe * ctx->m;
     std::vector<int64_t> cptr(ctx->nslots + 1, 0);
-    std::vector<int64_t> slot_of(16 * ctx->m);
+    std::vector<int64_t> slot_of(16 * ctx->m, -1);
     for (int64_t e = 0; e < ctx->m; ++e) {
         const int32_t *t = &ctx->tets[4 * e];
-        for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) {
+        for (int a = 0; a < npe; ++a)
+            for (int b = 0; b < npe; ++b) {
                 int64_t s = sell_slot(ctx, ctx->iperm[t[a]], ctx->iperm[t[b]]);
                 if (s < 0) return fail(ctx, MDX_ERR_BAD_MESH, "pattern lookup failed");
                 slot_of[16 * e + 4 * a + b] = s;
@@ -1486,10 +1519,11 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
             }
     }
     for (int64_t s = 0; s < ctx->nslots; ++s) cptr[s + 1] += cptr[s];
-    std::vector<int32_t> contrib(16 * ctx->m);
+    std::vector<int32_t> contrib(ncontrib);
     {
         std::vector<int64_t> pos(cptr.begin(), cptr.end() - 1);
-        for (int64_t q = 0; q < 16 * ctx->m; ++q) contrib[pos[slot_of[q]]++] = (int32_t)q;
+        for (int64_t q = 0; q < 16 * ctx->m; ++q)
+            if (slot_of[q] >= 0) contrib[pos[slot_of[q]]++] = (int32_t)q;
     }
     slot_of.clear();
     slot_of.shrink_to_fit();
@@ -1497,7 +1531,7 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     // host-side check of everything the kernels index with, before any launch
     if (ctx->slice_ptr.size() != (size_t)ctx->nslices + 1 || ctx->slice_ptr[0] != 0 ||
         ctx->slice_ptr[ctx->nslices] != ctx->nslots || (int64_t)ctx->col_sell.size() != ctx->nslots ||
-        cptr[ctx->nslots] != 16 * ctx->m || ctx->npad % TILE != 0 || ctx->npad < ctx->n)
+        cptr[ctx->nslots] != ncontrib || ctx->npad % TILE != 0 || ctx->npad < ctx->n)
         return fail(ctx, MDX_ERR_BAD_MESH, "internal layout inconsistent");
     for (int64_t sl = 0; sl < ctx->nslices; ++sl)
         if (ctx->slice_ptr[sl + 1] < ctx->slice_ptr[sl] ||
@@ -1515,7 +1549,7 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
                     return fail(ctx, MDX_ERR_BAD_MESH, "16-bit column mismatch");
     }
     for (int32_t code : contrib)
-        if (code < 0 || code >= 16 * ctx->m)
+        if (code < 0 || code >= 16 * ctx->m || (code >> 2 & 3) >= npe || (code & 3) >= npe)
             return fail(ctx, MDX_ERR_BAD_MESH, "contribution out of range");
 
     HIPCHK(hipSetDevice(ctx->device));
@@ -1535,7 +1569,7 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
                           hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(x + L.x_cptr, cptr.data(), sizeof(int64_t) * (ctx->nslots + 1),
                           hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(x + L.x_contrib, contrib.data(), sizeof(int32_t) * 16 * ctx->m,
+    HIPCHK(hipMemcpyAsync(x + L.x_contrib, contrib.data(), sizeof(int32_t) * ncontrib,
                           hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ctx->dev<int64_t>(L.slice_ptr), ctx->slice_ptr.data(),
                           sizeof(int64_t) * (ctx->nslices + 1), hipMemcpyHostToDevice, st));
@@ -1559,10 +1593,10 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
                               sizeof(int32_t) * sidx.size(), hipMemcpyHostToDevice, st));
 
     double *Mv = ctx->dev<double>(L.Mv), *Kv = ctx->dev<double>(L.Kv), *Av = ctx->dev<double>(L.Av);
-    launch_element(st, ctx->m, (double *)(x + L.x_xyz), (int32_t *)(x + L.x_tets),
+    launch_element(st, npe, ctx->m, (double *)(x + L.x_xyz), (int32_t *)(x + L.x_tets),
                    ctx->fibre.empty() ? nullptr : (double *)(x + L.x_fibre),
                    (double *)(x + L.x_sig), (double *)(x + L.x_vol), (double *)(x + L.x_ek));
-    launch_gather(st, ctx->nslots, (int64_t *)(x + L.x_cptr), (int32_t *)(x + L.x_contrib),
+    launch_gather(st, npe, ctx->nslots, (int64_t *)(x + L.x_cptr), (int32_t *)(x + L.x_contrib),
                   (double *)(x + L.x_vol), (double *)(x + L.x_ek), Mv, Kv);
     if (ctx->lumped)
         launch_lump(st, ctx->npad, SellView{ctx->dev<int64_t>(L.slice_ptr), ctx->dev<int32_t>(L.col)},

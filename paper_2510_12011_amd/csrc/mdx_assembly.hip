@@ -8,9 +8,16 @@
 // normals: grad(phi_a) = n_a / (n_a . (x_a - x_b)), n_a the normal of the
 // face opposite vertex a.  The consistent P1 mass block is vol/20 (1 + d_ab).
 //
+// Surface triangles (P1 triangles in 3D, the "Software functionality"
+// section's triangular elements): one thread per triangle, with the normal
+// n = (x1 - x0) x (x2 - x0), area |n| / 2 and surface gradients
+// grad(phi_a) = n x (x_c - x_b) / |n|^2 for (a, b, c) cyclic; sigma is built
+// on the fibre's projection onto the triangle's plane, normalised (isotropic
+// where the projection vanishes).  The consistent mass is area/12 (1 + d_ab).
+//
 // Gather stage: one thread per matrix slot sums the contributions listed for
-// that slot (tet id * 16 + a * 4 + b), in ascending tet order.  No atomics,
-// so assembly is deterministic.
+// that slot (element id * 16 + a * 4 + b), in ascending element order.  No
+// atomics, so assembly is deterministic.
 #include "mdx_internal.h"
 
 namespace mdx {
@@ -66,10 +73,52 @@ __global__ __launch_bounds__(256) void k_element(int64_t m, const double *__rest
             out[4 * a + b] = vol * (st * dot3(g[a], g[b]) + (sl - st) * gf[a] * gf[b]);
 }
 
+// elements given as 4-id records; the 3x3 block of the 16-entry record
+__global__ __launch_bounds__(256) void k_element_tri(int64_t m, const double *__restrict__ xyz,
+                                                     const int32_t *__restrict__ tris,
+                                                     const double *__restrict__ fibre,
+                                                     const double *__restrict__ sig,
+                                                     double *__restrict__ elem_area,
+                                                     double *__restrict__ elem_k)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    v3 X[3];
+    for (int a = 0; a < 3; ++a) {
+        int64_t v = tris[4 * e + a];
+        X[a] = {xyz[3 * v], xyz[3 * v + 1], xyz[3 * v + 2]};
+    }
+    const v3 nrm = cross(sub(X[1], X[0]), sub(X[2], X[0]));
+    const double n2 = dot3(nrm, nrm);
+    v3 g[3];
+    for (int a = 0; a < 3; ++a) {
+        const v3 c = cross(nrm, sub(X[(a + 2) % 3], X[(a + 1) % 3]));
+        g[a] = {c.x / n2, c.y / n2, c.z / n2};
+    }
+    double sl = sig[2 * e], st = sig[2 * e + 1];
+    v3 f = {0.0, 0.0, 0.0};
+    if (fibre) {
+        const v3 fr = {fibre[3 * e], fibre[3 * e + 1], fibre[3 * e + 2]};
+        const double fn = dot3(fr, nrm) / n2;
+        const v3 ft = {fr.x - fn * nrm.x, fr.y - fn * nrm.y, fr.z - fn * nrm.z};
+        const double len = sqrt(dot3(ft, ft));
+        if (len > 1e-12 * sqrt(dot3(fr, fr))) f = {ft.x / len, ft.y / len, ft.z / len};
+    }
+    double gf[3];
+    for (int a = 0; a < 3; ++a) gf[a] = dot3(g[a], f);
+    const double area = 0.5 * sqrt(n2);
+    elem_area[e] = area;
+    double *out = elem_k + 16 * e;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            out[4 * a + b] = area * (st * dot3(g[a], g[b]) + (sl - st) * gf[a] * gf[b]);
+}
+
+// mass_den: 20 for tetrahedra (vol/20 (1 + d_ab)), 12 for triangles
 __global__ __launch_bounds__(256) void k_gather(int64_t n_slots, const int64_t *__restrict__ cptr,
                                                 const int32_t *__restrict__ contrib,
                                                 const double *__restrict__ elem_vol,
-                                                const double *__restrict__ elem_k,
+                                                const double *__restrict__ elem_k, double mass_den,
                                                 double *__restrict__ Mv, double *__restrict__ Kv)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,7 +129,7 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n_slots, const int64_t *
         int64_t e = code >> 4;
         int ab = code & 15;
         bool diag = (ab >> 2) == (ab & 3);
-        msum += elem_vol[e] * (diag ? 2.0 : 1.0) / 20.0;
+        msum += elem_vol[e] * (diag ? 2.0 : 1.0) / mass_den;
         ksum += elem_k[16 * e + ab];
     }
     Mv[s] = msum;
@@ -143,20 +192,25 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-void launch_element(hipStream_t s, int64_t m, const double *xyz, const int32_t *tets,
+void launch_element(hipStream_t s, int npe, int64_t m, const double *xyz, const int32_t *tets,
                     const double *fibre, const double *sig, double *elem_vol, double *elem_k)
 {
-    if (m > 0)
+    if (m <= 0) return;
+    if (npe == 3)
+        hipLaunchKernelGGL(k_element_tri, dim3(blocks_for(m)), dim3(256), 0, s, m, xyz, tets,
+                           fibre, sig, elem_vol, elem_k);
+    else
         hipLaunchKernelGGL(k_element, dim3(blocks_for(m)), dim3(256), 0, s, m, xyz, tets, fibre,
                            sig, elem_vol, elem_k);
 }
 
-void launch_gather(hipStream_t s, int64_t n_slots, const int64_t *cptr, const int32_t *contrib,
-                   const double *elem_vol, const double *elem_k, double *Mv, double *Kv)
+void launch_gather(hipStream_t s, int npe, int64_t n_slots, const int64_t *cptr,
+                   const int32_t *contrib, const double *elem_vol, const double *elem_k,
+                   double *Mv, double *Kv)
 {
     if (n_slots > 0)
         hipLaunchKernelGGL(k_gather, dim3(blocks_for(n_slots)), dim3(256), 0, s, n_slots, cptr,
-                           contrib, elem_vol, elem_k, Mv, Kv);
+                           contrib, elem_vol, elem_k, npe == 3 ? 12.0 : 20.0, Mv, Kv);
 }
 
 void launch_system(hipStream_t s, int64_t n_slots, const double *Mv, const double *Kv, double cM,

@@ -105,10 +105,12 @@ void with_cols(const SellView &P, bool nt, F &&f)
 }
 
 // ---- assembly (mdx_assembly.hip) -----------------------------------------
-void launch_element(hipStream_t s, int64_t m, const double *xyz, const int32_t *tets,
+// npe: 4 tetrahedra, 3 surface triangles (elements as 4-id records)
+void launch_element(hipStream_t s, int npe, int64_t m, const double *xyz, const int32_t *tets,
                     const double *fibre, const double *sig, double *elem_vol, double *elem_k);
-void launch_gather(hipStream_t s, int64_t n_slots, const int64_t *cptr, const int32_t *contrib,
-                   const double *elem_vol, const double *elem_k, double *Mv, double *Kv);
+void launch_gather(hipStream_t s, int npe, int64_t n_slots, const int64_t *cptr,
+                   const int32_t *contrib, const double *elem_vol, const double *elem_k,
+                   double *Mv, double *Kv);
 void launch_system(hipStream_t s, int64_t n_slots, const double *Mv, const double *Kv,
                    double cM, double cK, double *Av);
 // mass lumping in place: row sums onto the diagonal, other entries zero

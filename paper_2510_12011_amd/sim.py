@@ -75,12 +75,17 @@ class Simulation:
 
     # -- problem statement ----------------------------------------------
     def set_mesh(self, xyz, tets, region=None, fibre=None, unit_conversion=1.0):
+        """Tetrahedra ([m, 4] ids) or, given [m, 3] ids, a triangle surface
+        mesh in 3D; region and fibre are per element."""
         xyz = np.ascontiguousarray(xyz, np.float64)
         tets = np.ascontiguousarray(tets, np.int32)
+        if tets.ndim != 2 or tets.shape[1] not in (3, 4):
+            raise ValueError("elements must be an [m, 4] (tetrahedra) or [m, 3] (triangles) array")
         region = None if region is None else np.ascontiguousarray(region, np.int32)
         fibre = None if fibre is None else np.ascontiguousarray(fibre, np.float64)
-        self._check(L.lib().mdx_set_mesh(self._h, xyz.shape[0], _ptr(xyz), unit_conversion,
-                                         tets.shape[0], _ptr(tets), _ptr(region), _ptr(fibre)))
+        fn = L.lib().mdx_set_surface_mesh if tets.shape[1] == 3 else L.lib().mdx_set_mesh
+        self._check(fn(self._h, xyz.shape[0], _ptr(xyz), unit_conversion, tets.shape[0],
+                       _ptr(tets), _ptr(region), _ptr(fibre)))
         self.n = xyz.shape[0]
 
     def set_mesh_batch(self, node_ptr, xyz, tets, region=None, fibre=None, unit_conversion=1.0):
@@ -275,6 +280,8 @@ def from_spec(spec, device: int = 0, ionic_params=None, prepare=True,
     sim.set_tissue(spec.chi, spec.cm, spec.theta)
     if getattr(spec, "lumped_mass", False):
         sim.set_mass_lumping(True)
+    if ionic_params is None:
+        ionic_params = getattr(spec, "ionic_params", None)
     sim.set_ionic(spec.ionic, ionic_params)
     for s in spec.stimuli:
         sim.add_stimulus(s.nodes, s.start, s.duration, s.intensity)

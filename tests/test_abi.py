@@ -239,3 +239,26 @@ def test_compact_columns_choice(host_ctx):
     assert lib.mdx_set_mesh(host_ctx, N + 1, _p(fxyz), 1.0, ftets.shape[0], _p(ftets),
                             None, None) == L.MDX_OK
     assert width() == 4
+
+
+def test_surface_mesh_validation_and_pattern(host_ctx):
+    """Triangle surfaces: the icosphere's pattern is N + 2 #edges; ids out of
+    range and degenerate triangles are rejected."""
+    lib = L.lib()
+    xyz, tris = inputs.icosphere(3)
+    xyz = np.ascontiguousarray(xyz * 5.0)
+    n, m = xyz.shape[0], tris.shape[0]
+    assert lib.mdx_set_surface_mesh(host_ctx, n, _p(xyz), 1.0, m, _p(tris), None, None) == L.MDX_OK
+    st = L.Stats()
+    assert lib.mdx_get_stats(host_ctx, C.byref(st)) == L.MDX_OK
+    assert st.nnz == n + 2 * (3 * m // 2)
+    bad = tris.copy()
+    bad[5, 2] = n
+    assert lib.mdx_set_surface_mesh(host_ctx, n, _p(xyz), 1.0, m, _p(bad), None,
+                                    None) == L.MDX_ERR_BAD_MESH
+    assert "out of range" in _err(host_ctx)
+    deg = tris.copy()
+    deg[7, 2] = deg[7, 1]
+    assert lib.mdx_set_surface_mesh(host_ctx, n, _p(xyz), 1.0, m, _p(deg), None,
+                                    None) == L.MDX_ERR_BAD_MESH
+    assert "degenerate" in _err(host_ctx)
