@@ -12,7 +12,8 @@ Workloads: learned (default: the learned warm start + mixed precision
 against plain FP64 PCG on a 1.2M-node shell at equal accuracy), slab (plain
 FP64, 442,401 nodes), precision / precision_fp64 (3.45M-node slab), batched
 (64 shells, 12M nodes), tiny, nversion (the N-version verification problem at
-0.5 / 0.2 / 0.1 mm, each run to full activation).
+0.5 / 0.2 / 0.1 mm, each run to full activation), surface / surface_mixed (the
+atrial surface stand-in: 655,362-node closed triangle surface).
 
 Also reported, as one JSON line:
   roofline      the dominant kernel (PCG SpMV with fused p.q): algorithmic
@@ -75,6 +76,14 @@ def workload(name):
                 prec)
     if name == "tiny":
         return (inputs.tiny_cube(), "unit cube 20^3 hexes, Mitchell-Schaeffer, plain FP64", "fp64")
+    if name in ("surface", "surface_mixed"):
+        prec = "mixed" if name == "surface_mixed" else "fp64"
+        return (inputs.atrium_surface(),
+                "atrial surface stand-in: closed ellipsoidal triangle surface 40x33x30 mm "
+                "(655,362 nodes, 1,310,720 P1 triangles), modified Mitchell-Schaeffer with the "
+                "paper's atrial parameters, isotropic 0.4 S/m, dt 0.01 ms, apex stimulus, "
+                f"{'mixed FP32/FP64' if prec == 'mixed' else 'plain FP64'}, atol 1e-5 and "
+                "rtol 1e-5 of ||D^-1 b||", prec)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -356,13 +365,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: learned 3000, slab 10000, batched 1000, "
-                         "precision 2000, tiny 500; nversion runs to full activation)")
+                         "precision 2000, tiny 500, surface 5000; nversion runs to full "
+                         "activation)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps before the timed region (default: 0 learned, 10 batched, "
                          "100 otherwise)")
     ap.add_argument("--workload", default="learned",
                     choices=["learned", "slab", "precision", "precision_fp64", "batched", "tiny",
-                             "nversion"])
+                             "nversion", "surface", "surface_mixed"])
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-every", type=int, default=10)
@@ -382,7 +392,8 @@ def main():
         sys.exit(2)
     if args.steps is None:
         args.steps = {"learned": 3000, "slab": 10000, "batched": 1000, "precision": 2000,
-                      "precision_fp64": 2000, "tiny": 500, "nversion": 0}[args.workload]
+                      "precision_fp64": 2000, "tiny": 500, "nversion": 0, "surface": 5000,
+                      "surface_mixed": 5000}[args.workload]
     if args.warmup is None:
         args.warmup = {"learned": 0, "batched": 10}.get(args.workload, 100)
     if args.workload == "batched":
@@ -416,7 +427,7 @@ def single_workload(args):
 
     spec, desc, prec = workload(args.workload)
     n = spec.mesh.n_nodes
-    print(f"[bench] workload {args.workload}: {n} nodes, {spec.mesh.n_tets} tets, {prec}",
+    print(f"[bench] workload {args.workload}: {n} nodes, {spec.mesh.n_tets} elements, {prec}",
           flush=True)
     s = sim.from_spec(spec, precision=prec)
     st = s.stats()
@@ -459,7 +470,7 @@ def single_workload(args):
         "vs_baseline": None,
         "dtype": "f64" if prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n_nodes": n, "nnz": nnz, "n_tets": spec.mesh.n_tets,
+        "config": {"workload": desc, "n_nodes": n, "nnz": nnz, "n_elements": spec.mesh.n_tets,
                    "dt_ms": spec.dt, "rtol": spec.rtol,
                    "stopping": "relative to ||z0||" if spec.rel_mode == 0 else "relative to ||D^-1 b||",
                    "warm_start": "2V^k - V^(k-1)", "mean_cg_iters": float(iters.mean()),
