@@ -20,9 +20,11 @@ Also reported, as one JSON line:
                 bytes per launch (12 B per structural nonzero + 16 B per row)
                 over its mean duration, measured with HIP events attached to
                 every dispatch of that kernel in the timed region, against
-                8 TB/s
+                8 TB/s; beside it a measured triad ceiling (c = a + 1.5 b
+                over 1 GiB arrays)
   cpu_baseline  the CPU oracle (plain FP64 C, OpenMP) timed on this host on a
-                bounded prefix of the same workload
+                bounded prefix of the same workload, and on one thread over a
+                shorter prefix
 """
 from __future__ import annotations
 
@@ -95,10 +97,44 @@ def cpu_baseline(spec, steps, threads=None):
     t0 = time.perf_counter()
     _, it = o.steps(steps)
     dt = time.perf_counter() - t0
+    cores = orc.threads()
+    # the single-core figure, on a shorter prefix of the same run
+    s1 = max(1, steps // 8)
+    orc.lib().orc_set_threads(1)
+    o1 = orc.Oracle(spec, mats=o.mats)
+    t0 = time.perf_counter()
+    o1.steps(s1)
+    dt1 = time.perf_counter() - t0
+    orc.lib().orc_set_threads(cores)
     return {"value": spec.mesh.n_nodes * steps / dt, "unit": "DOF*steps/s",
-            "cores": orc.threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"first {steps} steps from rest of the same workload "
-                      f"(mean {float(np.mean(it)):.1f} CG iterations/step), setup excluded"}
+                      f"(mean {float(np.mean(it)):.1f} CG iterations/step), setup excluded",
+            "single_core": {"value": spec.mesh.n_nodes * s1 / dt1, "unit": "DOF*steps/s",
+                            "sample": f"first {s1} steps from rest, one thread"}}
+
+
+def triad_ceiling(mib=1024, reps=5):
+    """Achievable HBM rate: c = a + 1.5 b over three 1 GiB FP32 arrays (12
+    bytes per element moved), timed with events; the reference beside the
+    8 TB/s specification peak."""
+    import torch
+    n = mib * 262144
+    a = torch.rand(n, dtype=torch.float32, device="cuda:0")
+    b = torch.rand_like(a)
+    c = torch.empty_like(a)
+    for _ in range(2):
+        torch.add(a, b, alpha=1.5, out=c)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(a, b, alpha=1.5, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 12.0 * n / sec / 1e9
 
 
 def learned_workload(args):
@@ -162,20 +198,26 @@ def learned_workload(args):
         it = s.iterations(args.steps)
         st = s.stats()
         state = s.get_state()
+        del s
         name = {L.MDX_WS_MLP: "MLP", L.MDX_WS_EXTRAP: "extrapolated", L.MDX_WS_PREV: "previous"}[ws]
         print(f"[bench] {precision} warm start {name}, rtol {rtol:g}: {args.steps} steps in "
               f"{el:.3f} s, mean CG iterations {it.mean():.2f}, fallbacks {st['fallbacks']}, "
               f"status {status}", flush=True)
-        return dict(seconds=el, iters=float(it.mean()), stats=st, V=state["V"], lat=state["lat"],
-                    rate=n * args.steps / el)
+        return dict(seconds=el, iters=float(it.mean()), iters_p95=float(np.percentile(it, 95)),
+                    stats=st, V=state["V"], lat=state["lat"], rate=n * args.steps / el)
 
     eq = 3e-9
     runs = {
         "learned_mixed_1e-8": timed("mixed", L.MDX_WS_MLP, 1e-8),
         "plain_fp64_1e-8": timed("fp64", L.MDX_WS_EXTRAP, 1e-8),
         "plain_fp64_prev_1e-8": timed("fp64", L.MDX_WS_PREV, 1e-8),
+        # the rest of the warm start x precision table at the same tolerance
+        "learned_fp64_1e-8": timed("fp64", L.MDX_WS_MLP, 1e-8),
+        "extrap_mixed_1e-8": timed("mixed", L.MDX_WS_EXTRAP, 1e-8),
+        "prev_mixed_1e-8": timed("mixed", L.MDX_WS_PREV, 1e-8),
         "learned_mixed_3e-9": timed("mixed", L.MDX_WS_MLP, eq, profile=True),
         "plain_fp64_3e-9": timed("fp64", L.MDX_WS_EXTRAP, eq),
+        "extrap_mixed_3e-9": timed("mixed", L.MDX_WS_EXTRAP, eq),
     }
     tight = timed("fp64", L.MDX_WS_EXTRAP, 1e-12)
     summary = {}
@@ -185,6 +227,7 @@ def learned_workload(args):
         both = fa & fb
         lat = float(np.abs(r["lat"][both] - tight["lat"][both]).max()) if both.any() else 0.0
         summary[key] = {"dof_steps_per_s": r["rate"], "mean_cg_iters": r["iters"],
+                        "p95_cg_iters": r["iters_p95"],
                         "V_rel_l2": e, "lat_max_diff_ms": lat,
                         "lat_activation_mismatch": int((fa != fb).sum())}
         print(f"[bench] {key}: {r['rate']:.3e} DOF*steps/s, V rel L2 {e:.2e}, LAT max diff "
@@ -209,6 +252,7 @@ def learned_workload(args):
         "config": {"workload": desc, "n_nodes": n, "nnz": st["nnz"], "dt_ms": 0.02,
                    "rtol": eq, "plain_fp64_dof_steps_per_s": runs["plain_fp64_3e-9"]["rate"],
                    "speedup_vs_plain_fp64": value / runs["plain_fp64_3e-9"]["rate"],
+                   "speedup_vs_extrapolated_mixed": value / runs["extrap_mixed_3e-9"]["rate"],
                    "accuracy_reference": "plain FP64 PCG at rtol 1e-12, same steps",
                    "runs": summary, "fallbacks": int(st["fallbacks"]),
                    "train_sites": args.train_sites, "train_steps": args.train_steps},
@@ -222,6 +266,10 @@ def learned_workload(args):
                      "sampled_every_n_steps": args.profile_every,
                      "cache_resident": bool(8 * st["nnz"] < 256e6)},
     }
+    tri = triad_ceiling()
+    out["roofline"]["triad_GBs"] = tri
+    out["roofline"]["frac_of_triad"] = achieved / tri
+    print(f"[bench] triad ceiling {tri:.0f} GB/s", flush=True)
     if not args.no_cpu:
         print(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps", flush=True)
         out["cpu_baseline"] = cpu_baseline(spec(101, args.cpu_steps), args.cpu_steps)
@@ -484,6 +532,9 @@ def single_workload(args):
                      "launches_with_product": st["spmv_work"],
                      "cache_resident": bool((12 if prec == "fp64" else 8) * nnz < 256e6)},
     }
+    tri = triad_ceiling()
+    out["roofline"]["triad_GBs"] = tri
+    out["roofline"]["frac_of_triad"] = achieved / tri
     if not args.no_cpu:
         print(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps", flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)

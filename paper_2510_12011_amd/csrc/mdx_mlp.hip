@@ -238,23 +238,57 @@ __device__ __forceinline__ f32x16 unit_frag(const float *v, int ot, int half)
 // features formed from the state as the feature pass forms them (same
 // expressions, so the same bits): V, V - V_prev, s / Cm, the neighbour
 // aggregate, standardised.
+// fetch() issues a node's loads (zeros past n, or for lanes that hold no
+// node), form() turns them into the network's input, so that the loads of
+// the next nodes can be in flight while the current ones are computed.
+template <bool STATE>
+struct FeatRaw;
+template <>
+struct FeatRaw<false> {
+    float4 x;
+};
+template <>
+struct FeatRaw<true> {
+    double v, vp, s;
+    float k;
+};
+
 struct FeatIn {
     const float4 *X;
     const double *V, *Vprev, *src;
     const float *kvp;
     double cm;
     MlpNorm nm;
-    __device__ __forceinline__ float4 load(int64_t i) const
+    template <bool STATE>
+    __device__ __forceinline__ FeatRaw<STATE> fetch(int64_t i, bool ok) const
     {
-        if (X) return X[i];
-        const double vi = V[i];
-        const float fx = (float)vi, fy = (float)(vi - Vprev[i]), fz = (float)(src[i] / cm);
-        const float fw = kvp[i];
-        return make_float4((fx - nm.mean[0]) * nm.inv_std[0], (fy - nm.mean[1]) * nm.inv_std[1],
-                           (fz - nm.mean[2]) * nm.inv_std[2], (fw - nm.mean[3]) * nm.inv_std[3]);
+        if constexpr (STATE) {
+            FeatRaw<true> r{0.0, 0.0, 0.0, 0.0f};
+            if (ok) r = {V[i], Vprev[i], src[i], kvp[i]};
+            return r;
+        } else {
+            FeatRaw<false> r{make_float4(0.f, 0.f, 0.f, 0.f)};
+            if (ok) r.x = X[i];
+            return r;
+        }
+    }
+    template <bool STATE>
+    __device__ __forceinline__ float4 form(const FeatRaw<STATE> &r, bool ok) const
+    {
+        if (!ok) return make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (STATE) {
+            const float fx = (float)r.v, fy = (float)(r.v - r.vp), fz = (float)(r.s / cm);
+            return make_float4((fx - nm.mean[0]) * nm.inv_std[0],
+                               (fy - nm.mean[1]) * nm.inv_std[1],
+                               (fz - nm.mean[2]) * nm.inv_std[2],
+                               (r.k - nm.mean[3]) * nm.inv_std[3]);
+        } else {
+            return r.x;
+        }
     }
 };
 
+template <bool STATE>
 __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P, int64_t n,
                                                      FeatIn in, float *__restrict__ y)
 {
@@ -278,64 +312,105 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P
     __syncthreads();
 
     const int lane = threadIdx.x & 63, half = lane >> 5;
-    const int64_t n_tiles = (n + 31) / 32;
+    // two 32-node tiles per pass share every weight and bias fragment read
+    // from LDS (LDS bandwidth, not the matrix cores, bounds this kernel)
+    const int64_t n_pairs = ((n + 31) / 32 + 1) / 2;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; tile < n_tiles;
-         tile += waves) {
-        // weights are re-read from LDS for every tile: held in registers
-        // across tiles they would take ~200 VGPRs and leave one wavefront
+    const int64_t pr0 = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    FeatRaw<STATE> raw[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int64_t nd = (2 * pr0 + b) * 32 + (lane & 31);
+        raw[b] = in.fetch<STATE>(nd, pr0 < n_pairs && half == 0 && nd < n);
+    }
+    for (int64_t pr = pr0; pr < n_pairs; pr += waves) {
+        // weights are re-read from LDS for every pair: held in registers
+        // across pairs they would take ~200 VGPRs and leave one wavefront
         // per SIMD to hide the latency of the layer chain
         asm volatile("" ::: "memory");
-        const int64_t node = tile * 32 + (lane & 31);
-        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (half == 0 && node < n) x = in.load(node);
-        const bf16x4 xh = pack_bf16x4(x.x, x.y, x.z, x.w);
-        const float4 xr = make_float4(x.x - bf2f((unsigned short)xh[0]),
-                                      x.y - bf2f((unsigned short)xh[1]),
-                                      x.z - bf2f((unsigned short)xh[2]),
-                                      x.w - bf2f((unsigned short)xh[3]));
-        const bf16x4 xl = pack_bf16x4(xr.x, xr.y, xr.z, xr.w);
+        int64_t node[2];
+        s16x8 xb[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            node[b] = (2 * pr + b) * 32 + (lane & 31);
+            const float4 x = in.form<STATE>(raw[b], half == 0 && node[b] < n);
+            const bf16x4 xh = pack_bf16x4(x.x, x.y, x.z, x.w);
+            const float4 xr = make_float4(x.x - bf2f((unsigned short)xh[0]),
+                                          x.y - bf2f((unsigned short)xh[1]),
+                                          x.z - bf2f((unsigned short)xh[2]),
+                                          x.w - bf2f((unsigned short)xh[3]));
+            xb[b] = cat8(xh, pack_bf16x4(xr.x, xr.y, xr.z, xr.w));
+        }
+        // the next pair's loads, issued once this pair's inputs are formed
+        // (loads retire in order) and in flight during its layers
+        const int64_t pn = pr + waves;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t nd = (2 * pn + b) * 32 + (lane & 31);
+            raw[b] = in.fetch<STATE>(nd, pn < n_pairs && half == 0 && nd < n);
+        }
         // layer 1
-        const s16x8 xb = cat8(xh, xl);
-        bf16x4 h1[8];
+        bf16x4 h1[2][8];
 #pragma unroll
         for (int ot = 0; ot < 2; ++ot) {
             const s16x8 a =
                 *reinterpret_cast<const s16x8 *>(w.w1 + (32 * ot + (lane & 31)) * 16 + 8 * half);
-            f32x16 acc = unit_frag(w.b1, ot, half);
-            acc = mfma16(a, xb, acc);
+            const f32x16 bias = unit_frag(w.b1, ot, half);
 #pragma unroll
-            for (int g = 0; g < 4; ++g)
-                h1[4 * ot + g] = pack_bf16x4(fmaxf(acc[4 * g], 0.f), fmaxf(acc[4 * g + 1], 0.f),
-                                             fmaxf(acc[4 * g + 2], 0.f), fmaxf(acc[4 * g + 3], 0.f));
+            for (int b = 0; b < 2; ++b) {
+                const f32x16 acc = mfma16(a, xb[b], bias);
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    h1[b][4 * ot + g] =
+                        pack_bf16x4(fmaxf(acc[4 * g], 0.f), fmaxf(acc[4 * g + 1], 0.f),
+                                    fmaxf(acc[4 * g + 2], 0.f), fmaxf(acc[4 * g + 3], 0.f));
+            }
         }
         // layer 2
-        bf16x4 h2[8];
+        bf16x4 h2[2][8];
 #pragma unroll
         for (int ot = 0; ot < 2; ++ot) {
-            f32x16 acc = unit_frag(w.b2, ot, half);
+            f32x16 acc[2];
+            acc[0] = acc[1] = unit_frag(w.b2, ot, half);
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-                acc = mfma16(frag_w16(w.w2, ot, ks, lane), cat8(h1[2 * ks], h1[2 * ks + 1]), acc);
+            for (int ks = 0; ks < 4; ++ks) {
+                const s16x8 wf = frag_w16(w.w2, ot, ks, lane);
 #pragma unroll
-            for (int g = 0; g < 4; ++g)
-                h2[4 * ot + g] = pack_bf16x4(fmaxf(acc[4 * g], 0.f), fmaxf(acc[4 * g + 1], 0.f),
-                                             fmaxf(acc[4 * g + 2], 0.f), fmaxf(acc[4 * g + 3], 0.f));
+                for (int b = 0; b < 2; ++b)
+                    acc[b] = mfma16(wf, cat8(h1[b][2 * ks], h1[b][2 * ks + 1]), acc[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    h2[b][4 * ot + g] =
+                        pack_bf16x4(fmaxf(acc[b][4 * g], 0.f), fmaxf(acc[b][4 * g + 1], 0.f),
+                                    fmaxf(acc[b][4 * g + 2], 0.f), fmaxf(acc[b][4 * g + 3], 0.f));
         }
         // layer 3 and the output unit
-        float s = 0.0f;
+        float sum[2] = {0.0f, 0.0f};
 #pragma unroll
         for (int ot = 0; ot < 2; ++ot) {
-            f32x16 acc = unit_frag(w.b3, ot, half);
+            f32x16 acc[2];
+            acc[0] = acc[1] = unit_frag(w.b3, ot, half);
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-                acc = mfma16(frag_w16(w.w3, ot, ks, lane), cat8(h2[2 * ks], h2[2 * ks + 1]), acc);
+            for (int ks = 0; ks < 4; ++ks) {
+                const s16x8 wf = frag_w16(w.w3, ot, ks, lane);
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[b] = mfma16(wf, cat8(h2[b][2 * ks], h2[b][2 * ks + 1]), acc[b]);
+            }
             const f32x16 w4 = unit_frag(w.w4, ot, half);
 #pragma unroll
-            for (int v = 0; v < 16; ++v) s += w4[v] * fmaxf(acc[v], 0.0f);
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) sum[b] += w4[v] * fmaxf(acc[b][v], 0.0f);
         }
-        s += __shfl_xor(s, 32, 64);
-        if (half == 0 && node < n) y[node] = s + w.b4;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const float t = sum[b] + __shfl_xor(sum[b], 32, 64);
+            if (half == 0 && node[b] < n) y[node[b]] = t + w.b4;
+        }
     }
 }
 
@@ -563,14 +638,18 @@ size_t mlp_grad_scratch_bytes(int64_t n)
     return sizeof(float) * (size_t)(NPARAM + 1) * (size_t)mlp_grad_groups(n);
 }
 
+// inference grid: 144 registers per lane leave three wavefronts per SIMD,
+// i.e. three 256-thread workgroups per CU on 256 CUs, all resident at once
+constexpr int64_t kInferGroups = 768;
+
 void launch_mlp_forward(hipStream_t s, const float *P, int64_t n, const float *X, float *y)
 {
     if (n <= 0) return;
-    const int64_t tiles = (n + 31) / 32;
-    const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 1024);
+    const int64_t pairs = ((n + 31) / 32 + 1) / 2;
+    const int blocks = (int)std::min<int64_t>((pairs + 3) / 4, kInferGroups);
     const FeatIn in{reinterpret_cast<const float4 *>(X), nullptr, nullptr, nullptr, nullptr, 1.0,
                     MlpNorm{}};
-    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, s, P, n, in, y);
+    hipLaunchKernelGGL(k_mlp_forward<false>, dim3(blocks), dim3(256), 0, s, P, n, in, y);
 }
 
 void launch_mlp_forward_state(hipStream_t s, const float *P, int64_t n, const double *V,
@@ -578,10 +657,10 @@ void launch_mlp_forward_state(hipStream_t s, const float *P, int64_t n, const do
                               const MlpNorm &nm, float *y)
 {
     if (n <= 0) return;
-    const int64_t tiles = (n + 31) / 32;
-    const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 1024);
+    const int64_t pairs = ((n + 31) / 32 + 1) / 2;
+    const int blocks = (int)std::min<int64_t>((pairs + 3) / 4, kInferGroups);
     const FeatIn in{nullptr, V, Vprev, src, kvp, cm, nm};
-    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, s, P, n, in, y);
+    hipLaunchKernelGGL(k_mlp_forward<true>, dim3(blocks), dim3(256), 0, s, P, n, in, y);
 }
 
 void launch_mlp_grad(hipStream_t s, const float *P, int64_t n, const float *X, const float *T,

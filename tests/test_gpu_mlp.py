@@ -64,7 +64,7 @@ def test_nparams(ctx):
     assert L.lib().mdx_mlp_nparams() == mlp.N_PARAM
 
 
-@pytest.mark.parametrize("n", [1, 31, 1000, 70000])
+@pytest.mark.parametrize("n", [1, 31, 33, 1000, 1100, 70000])
 def test_forward_matches_oracle(ctx, n):
     rng = np.random.default_rng(n)
     theta = mlp.init_params(7)
