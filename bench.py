@@ -13,7 +13,8 @@ against plain FP64 PCG on a 1.2M-node shell at equal accuracy), slab (plain
 FP64, 442,401 nodes), precision / precision_fp64 (3.45M-node slab), batched
 (64 shells, 12M nodes), tiny, nversion (the N-version verification problem at
 0.5 / 0.2 / 0.1 mm, each run to full activation), surface / surface_mixed (the
-atrial surface stand-in: 655,362-node closed triangle surface).
+atrial surface stand-in: 655,362-node closed triangle surface), batched_surface
+(16 closed triangle surfaces advanced together).
 
 Also reported, as one JSON line:
   roofline      the dominant kernel (PCG SpMV with fused p.q): algorithmic
@@ -332,11 +333,19 @@ def batched_workload(args):
     import torch
     from paper_2510_12011_amd import inputs, sim
     t0 = time.perf_counter()
-    b = inputs.batch_shells(n_inst=args.instances, total_nodes=args.total_nodes, seed=0,
-                            workers=min(16, os.cpu_count() or 1))
+    surf = args.workload == "batched_surface"
+    if surf:
+        # a cohort of atrial-surface stand-ins: 16 closed ellipsoidal surfaces
+        # of 163,842 or 655,362 nodes (7,536,672 in all), semi-axes 20-40 mm
+        b = inputs.batch_surfaces(n_inst=16, levels=(7, 8), seed=0, n_steps=args.steps,
+                                  axes_mm=(20.0, 40.0), stim_radius=2.0)
+    else:
+        b = inputs.batch_shells(n_inst=args.instances, total_nodes=args.total_nodes, seed=0,
+                                workers=min(16, os.cpu_count() or 1))
     n = b.n_nodes
     sizes = [i.mesh.n_nodes for i in b.instances]
-    print(f"[bench] {len(sizes)} shells, {n} nodes ({min(sizes)}..{max(sizes)}), meshed in "
+    print(f"[bench] {len(sizes)} {'surfaces' if surf else 'shells'}, {n} nodes "
+          f"({min(sizes)}..{max(sizes)}), meshed in "
           f"{time.perf_counter() - t0:.1f} s", flush=True)
     t0 = time.perf_counter()
     s = sim.batch_from_spec(b)
@@ -372,6 +381,11 @@ def batched_workload(args):
             f"{min(sizes)}..{max(sizes)} nodes, {n} total), Mitchell-Schaeffer, sigma scaled "
             f"U(0.5,1.5), random endocardial sites, mixed FP32/FP64, rtol 1e-8 of ||D^-1 b||, "
             f"per-instance CG, HIP-graph steps")
+    if surf:
+        desc = (f"batched form: {len(sizes)} closed ellipsoidal triangle surfaces (atrial "
+                f"stand-ins, {min(sizes)}..{max(sizes)} nodes, {n} total), Mitchell-Schaeffer "
+                f"with the paper's atrial parameters, 0.4 S/m scaled U(0.5,1.5), random sites, "
+                f"mixed FP32/FP64, rtol 1e-8 of ||D^-1 b||, per-instance CG, HIP-graph steps")
     out = {
         "metric": METRIC, "value": n * args.steps / elapsed, "unit": "DOF*steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -403,7 +417,7 @@ def batched_workload(args):
             dof += sizes[k] * args.cpu_steps
         out["cpu_baseline"] = {"value": dof / t_cpu, "unit": "DOF*steps/s", "cores": orc.threads(),
                                "kind": "oracle",
-                               "sample": f"the 4 smallest shells, first {args.cpu_steps} steps "
+                               "sample": f"the 4 smallest instances, first {args.cpu_steps} steps "
                                          f"from rest each, setup excluded"}
     print(json.dumps(out), flush=True)
 
@@ -420,7 +434,7 @@ def main():
                          "100 otherwise)")
     ap.add_argument("--workload", default="learned",
                     choices=["learned", "slab", "precision", "precision_fp64", "batched", "tiny",
-                             "nversion", "surface", "surface_mixed"])
+                             "nversion", "surface", "surface_mixed", "batched_surface"])
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-every", type=int, default=10)
@@ -441,10 +455,10 @@ def main():
     if args.steps is None:
         args.steps = {"learned": 3000, "slab": 10000, "batched": 1000, "precision": 2000,
                       "precision_fp64": 2000, "tiny": 500, "nversion": 0, "surface": 5000,
-                      "surface_mixed": 5000}[args.workload]
+                      "surface_mixed": 5000, "batched_surface": 2000}[args.workload]
     if args.warmup is None:
-        args.warmup = {"learned": 0, "batched": 10}.get(args.workload, 100)
-    if args.workload == "batched":
+        args.warmup = {"learned": 0, "batched": 10, "batched_surface": 10}.get(args.workload, 100)
+    if args.workload in ("batched", "batched_surface"):
         batched_workload(args)
     elif args.workload == "nversion":
         nversion_workload(args)

@@ -145,8 +145,8 @@ MDX_API mdx_status mdx_set_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz
  * grad(phi_b) with gradients along the triangle and sigma built on the
  * fibre's projection onto the triangle's plane (isotropic where that
  * projection vanishes).  Rejects non-finite coordinates, ids out of range
- * and triangles with |(x1 - x0) x (x2 - x0)| <= 1e-14 h^2.  The batched
- * form takes tetrahedra only. */
+ * and triangles with |(x1 - x0) x (x2 - x0)| <= 1e-14 h^2.  Batches of
+ * surfaces: mdx_set_surface_mesh_batch. */
 MDX_API mdx_status mdx_set_surface_mesh(mdx_ctx *ctx, int64_t n_nodes, const double *xyz,
                                         double unit_conversion, int64_t n_tris,
                                         const int32_t *tris, const int32_t *region,
@@ -292,6 +292,15 @@ MDX_API mdx_status mdx_set_mesh_batch(mdx_ctx *ctx, int32_t n_inst, const int64_
                                       double unit_conversion, int64_t n_tets,
                                       const int32_t *tets, const int32_t *region,
                                       const double *fibre);
+/* The same for a batch of triangle surface meshes (the paper's cohort of
+ * atrial surfaces run one after another, here advanced together): tris
+ * n_tris*3 ids in the concatenated numbering, element rules as
+ * mdx_set_surface_mesh, batch rules as mdx_set_mesh_batch. */
+MDX_API mdx_status mdx_set_surface_mesh_batch(mdx_ctx *ctx, int32_t n_inst,
+                                              const int64_t *node_ptr, int64_t n_nodes,
+                                              const double *xyz, double unit_conversion,
+                                              int64_t n_tris, const int32_t *tris,
+                                              const int32_t *region, const double *fibre);
 /* PCG iterations of the last n steps of a batched context, per instance:
  * iters[s * n_inst + i] (HOST, n * n_inst; -1: the solve hit max_iter). */
 MDX_API mdx_status mdx_get_instance_iterations(mdx_ctx *ctx, int64_t n, int32_t *iters);

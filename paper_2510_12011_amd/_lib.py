@@ -78,6 +78,8 @@ _SIGS = {
     "mdx_last_error": (C.c_char_p, [P]),
     "mdx_set_mesh": (C.c_int, [P, C.c_int64, P, C.c_double, C.c_int64, P, P, P]),
     "mdx_set_surface_mesh": (C.c_int, [P, C.c_int64, P, C.c_double, C.c_int64, P, P, P]),
+    "mdx_set_surface_mesh_batch": (C.c_int, [P, C.c_int32, P, C.c_int64, P, C.c_double,
+                                             C.c_int64, P, P, P]),
     "mdx_set_mesh_batch": (C.c_int, [P, C.c_int32, P, C.c_int64, P, C.c_double, C.c_int64, P, P,
                                      P]),
     "mdx_get_instance_iterations": (C.c_int, [P, C.c_int64, P]),

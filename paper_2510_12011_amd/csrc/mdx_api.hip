@@ -1326,6 +1326,18 @@ mdx_status mdx_set_mesh_batch(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_
                          region, fibre);
 }
 
+mdx_status mdx_set_surface_mesh_batch(mdx_ctx *ctx, int32_t n_inst, const int64_t *node_ptr,
+                                      int64_t n_nodes, const double *xyz, double unit_conversion,
+                                      int64_t n_tris, const int32_t *tris, const int32_t *region,
+                                      const double *fibre)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (n_inst < 1 || n_inst > (1 << 20) || !node_ptr)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "n_inst must lie in [1, 2^20] with node_ptr given");
+    return set_mesh_impl(ctx, n_inst, node_ptr, true, n_nodes, xyz, unit_conversion, n_tris, tris,
+                         region, fibre, 3);
+}
+
 mdx_status mdx_add_conductivity(mdx_ctx *ctx, int32_t n_ids, const int32_t *region_ids, double il,
                                 double it)
 {

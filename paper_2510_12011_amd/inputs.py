@@ -477,6 +477,7 @@ class BatchSpec:
     warm_start: int = 1
     precision: str = "mixed"
     rr_interval: int = 50
+    ionic_params: tuple | None = None   # the cell model's parameters (None: defaults)
 
     @property
     def n_nodes(self) -> int:
@@ -494,7 +495,8 @@ class BatchSpec:
                        ionic=self.ionic, dt=self.dt, n_steps=self.n_steps, stimuli=it.stimuli,
                        rtol=self.rtol, atol=self.atol, rel_mode=self.rel_mode,
                        max_iter=self.max_iter, warm_start=self.warm_start,
-                       precision=self.precision, rr_interval=self.rr_interval)
+                       precision=self.precision, rr_interval=self.rr_interval,
+                       ionic_params=self.ionic_params)
 
 
 def _cap_job(args):
@@ -631,3 +633,30 @@ def small_surface(level: int = 4, n_steps: int = 400, anisotropic: bool = True) 
                    sigma_t=0.1 if anisotropic else 0.4, chi=1400 * PER_CM_TO_PER_MM,
                    cm=1.0 * UF_PER_CM2_TO_PER_MM2, theta=0.5, ionic="ms", dt=0.01,
                    n_steps=n_steps, stimuli=[stim], rtol=1e-10, ionic_params=ATRIUM_MS_PARAMS)
+
+
+def batch_surfaces(n_inst: int = 4, levels=(3, 4), seed: int = 0, n_steps: int = 400,
+                   axes_mm: tuple = (6.0, 9.0), stim_radius: float = 1.2,
+                   precision: str = "mixed") -> BatchSpec:
+    """A seeded cohort of closed ellipsoidal triangle surfaces (the paper's
+    batch of atrial surfaces, in small): refinement level drawn from
+    ``levels``, semi-axes U(axes_mm) sorted ascending, isotropic 0.4 S/m times
+    U(0.5, 1.5), stimulus 0.5 uA/mm^2 for 2 ms on the nodes within
+    stim_radius mm of a random node; the atrial Mitchell-Schaeffer
+    parameters, dt 0.01 ms, rtol 1e-8 of ||D^-1 b||."""
+    rng = np.random.default_rng(seed)
+    inst = []
+    for _ in range(n_inst):
+        level = int(rng.choice(levels))
+        axes = tuple(np.sort(rng.uniform(axes_mm[0], axes_mm[1], 3)))
+        mesh = ellipsoid_surface(level, axes, fibres=False)
+        c = mesh.xyz[rng.integers(mesh.n_nodes)]
+        nodes = np.flatnonzero(np.linalg.norm(mesh.xyz - c, axis=1) <= stim_radius)
+        sig = 0.4 * rng.uniform(0.5, 1.5)
+        inst.append(Instance(mesh=mesh, sigma_l=sig, sigma_t=sig,
+                             stimuli=[Stimulus(nodes.astype(np.int32), 0.0, 2.0,
+                                               50.0 * UA_PER_CM2_TO_PER_MM2)]))
+    return BatchSpec(name=f"batch_surfaces_{n_inst}", instances=inst,
+                     chi=1400 * PER_CM_TO_PER_MM, cm=1.0 * UF_PER_CM2_TO_PER_MM2, theta=0.5,
+                     ionic="ms", dt=0.01, n_steps=n_steps, rtol=1e-8, precision=precision,
+                     ionic_params=ATRIUM_MS_PARAMS)

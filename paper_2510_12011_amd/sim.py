@@ -94,11 +94,14 @@ class Simulation:
         ptr = np.ascontiguousarray(node_ptr, np.int64)
         xyz = np.ascontiguousarray(xyz, np.float64)
         tets = np.ascontiguousarray(tets, np.int32)
+        if tets.ndim != 2 or tets.shape[1] not in (3, 4):
+            raise ValueError("elements must be an [m, 4] (tetrahedra) or [m, 3] (triangles) array")
         region = None if region is None else np.ascontiguousarray(region, np.int32)
         fibre = None if fibre is None else np.ascontiguousarray(fibre, np.float64)
-        self._check(L.lib().mdx_set_mesh_batch(self._h, ptr.shape[0] - 1, _ptr(ptr), xyz.shape[0],
-                                               _ptr(xyz), unit_conversion, tets.shape[0],
-                                               _ptr(tets), _ptr(region), _ptr(fibre)))
+        fn = (L.lib().mdx_set_surface_mesh_batch if tets.shape[1] == 3
+              else L.lib().mdx_set_mesh_batch)
+        self._check(fn(self._h, ptr.shape[0] - 1, _ptr(ptr), xyz.shape[0], _ptr(xyz),
+                       unit_conversion, tets.shape[0], _ptr(tets), _ptr(region), _ptr(fibre)))
         self.n = xyz.shape[0]
         self.node_ptr = ptr
 
@@ -309,6 +312,8 @@ def batch_from_spec(bspec, device: int = 0, ionic_params=None, prepare=True) -> 
     for k, i in enumerate(inst):
         sim.add_conductivity([k], i.sigma_l, i.sigma_t)
     sim.set_tissue(bspec.chi, bspec.cm, bspec.theta)
+    if ionic_params is None:
+        ionic_params = getattr(bspec, "ionic_params", None)
     sim.set_ionic(bspec.ionic, ionic_params)
     for k, i in enumerate(inst):
         for s in i.stimuli:

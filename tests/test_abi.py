@@ -262,3 +262,21 @@ def test_surface_mesh_validation_and_pattern(host_ctx):
     assert lib.mdx_set_surface_mesh(host_ctx, n, _p(xyz), 1.0, m, _p(deg), None,
                                     None) == L.MDX_ERR_BAD_MESH
     assert "degenerate" in _err(host_ctx)
+
+
+def test_surface_batch_validation(host_ctx):
+    """A batch of two icospheres is accepted; a triangle joining the two
+    instances is rejected."""
+    lib = L.lib()
+    xa, ta = inputs.icosphere(2)
+    xyz = np.ascontiguousarray(np.concatenate([xa * 3.0, xa * 4.0 + 20.0]))
+    tris = np.ascontiguousarray(np.concatenate([ta, ta + xa.shape[0]]).astype(np.int32))
+    ptr = np.array([0, xa.shape[0], 2 * xa.shape[0]], np.int64)
+    n, m = xyz.shape[0], tris.shape[0]
+    assert lib.mdx_set_surface_mesh_batch(host_ctx, 2, _p(ptr), n, _p(xyz), 1.0, m, _p(tris), None,
+                                          None) == L.MDX_OK
+    bad = tris.copy()
+    bad[0, 1] = xa.shape[0] + 5
+    assert lib.mdx_set_surface_mesh_batch(host_ctx, 2, _p(ptr), n, _p(xyz), 1.0, m, _p(bad), None,
+                                          None) == L.MDX_ERR_BAD_MESH
+    assert "joins two instances" in _err(host_ctx)

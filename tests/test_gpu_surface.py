@@ -82,3 +82,29 @@ def test_atrial_surface_full_size_prefix():
     print(f"  V rel L2 max {max(errs):.2e}", flush=True)
     assert max(errs) <= 1e-9, errs
     assert abs(s.iterations(100).astype(int) - it_or).max() <= 1
+
+
+def test_batched_surfaces_match_oracle():
+    """A batch of four small atrial-parameter surfaces (the batched form, mixed
+    precision): every instance against its own oracle run, 1e-5 and LAT
+    within one step."""
+    from paper_2510_12011_amd import sim
+    b = inputs.batch_surfaces(n_inst=4, seed=3, n_steps=300)
+    print(f"[case] {b.name}: sizes {[i.mesh.n_nodes for i in b.instances]}", flush=True)
+    s = sim.batch_from_spec(b)
+    v, status = s.run(300, 100)
+    assert status == 0
+    lat, _ = s.times()
+    ptr = b.node_ptr()
+    for k in range(len(b.instances)):
+        spec = b.instance_spec(k)
+        o = orc.Oracle(spec)
+        v_or, _ = o.steps(300, out_every=100)
+        errs = [_rel_l2(a[ptr[k]:ptr[k + 1]], r) for a, r in zip(v, v_or)]
+        print(f"  instance {k}: V rel L2 max {max(errs):.2e}", flush=True)
+        assert max(errs) <= 1e-5, errs
+        lk, lo = lat[ptr[k]:ptr[k + 1]], o.state.lat
+        assert np.array_equal(np.isfinite(lk), np.isfinite(lo))
+        fin = np.isfinite(lo)
+        assert fin.any()
+        assert abs(lk[fin] - lo[fin]).max() <= spec.dt * (1 + 1e-9)
