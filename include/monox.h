@@ -348,6 +348,17 @@ MDX_API mdx_status mdx_get_matrix(mdx_ctx *ctx, int32_t which, int64_t *nnz, int
                           int32_t *cols, double *vals);
 /* y = which * x with the library's SpMV kernel; host x, y in original order */
 MDX_API mdx_status mdx_spmv(mdx_ctx *ctx, int32_t which, const double *x, double *y);
+/* One Jacobi-preconditioned CG solve (Algorithm 1) of A x = b with the
+ * context's system matrix A = chi Cm M + theta dt K, outside the time loop:
+ * host b and x0 (n values, original order) in, host x out; *iters (may be
+ * NULL) receives the iterations taken, or -1 if max_iter ran out.  Uses the
+ * solver options' atol, rtol, rel_mode and max_iter with the FP64 kernels
+ * of the time step (three per iteration), whatever the precision setting.
+ * Needs mdx_prepare; leaves the simulation state untouched.  Single-mesh
+ * contexts only (MDX_ERR_UNSUPPORTED on a batch); MDX_ERR_NONFINITE if the
+ * iteration produced a non-finite value.  Blocks until done. */
+MDX_API mdx_status mdx_solve(mdx_ctx *ctx, const double *b, const double *x0, double *x,
+                             int32_t *iters);
 /* One ionic update of the model set by mdx_set_ionic on n independent cells,
  * DEVICE arrays on ctx's device and stream: V[n]; u[nstates][n] (SoA)
  * advanced in place; iion[n] receives I_ion(V, u^{k+1}) / Cm in mV/ms.

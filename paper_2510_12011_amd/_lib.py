@@ -104,6 +104,7 @@ _SIGS = {
     "mdx_get_state": (C.c_int, [P, P, P, P, P, P, C.POINTER(C.c_int64)]),
     "mdx_set_state": (C.c_int, [P, P, P, P, P, P, C.c_int64]),
     "mdx_get_matrix": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int64), P, P, P]),
+    "mdx_solve": (C.c_int, [P, P, P, P, C.POINTER(C.c_int32)]),
     "mdx_spmv": (C.c_int, [P, C.c_int32, P, P]),
     "mdx_ionic_step": (C.c_int, [P, C.c_double, C.c_int64, P, P, P]),
     "mdx_mlp_nparams": (C.c_int32, []),

@@ -2264,6 +2264,50 @@ mdx_status mdx_spmv(mdx_ctx *ctx, int32_t which, const double *x, double *y)
     GUARD_END
 }
 
+mdx_status mdx_solve(mdx_ctx *ctx, const double *b, const double *x0, double *x, int32_t *iters)
+{
+    if (!ctx || !b || !x0 || !x) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
+    if (ctx->batched) return fail(ctx, MDX_ERR_UNSUPPORTED, "not available on a batched context");
+    GUARD_BEGIN
+    const Layout &L = ctx->L;
+    hipStream_t st = ctx->stream;
+    // per-step scratch only: the simulation state is untouched
+    double *bd = ctx->dev<double>(L.b), *X = ctx->vec(2), *r = ctx->dev<double>(L.r);
+    double *p = ctx->dev<double>(L.p), *q = ctx->dev<double>(L.q);
+    double *part0 = ctx->dev<double>(L.partial);
+    double *part_pq = part0 + 3 * kPartialCap, *part_rz = part0 + 6 * kPartialCap;
+    Scalars *sc = ctx->dev<Scalars>(L.scalars);
+    if (mdx_status e = copy_vec_in(ctx, b, bd)) return e;
+    if (mdx_status e = copy_vec_in(ctx, x0, X)) return e;
+    const Tiling &T = ctx->tiling;
+    const SellView P = step_view(ctx);
+    const double *Av = ctx->dev<double>(L.Av), *dinv = ctx->dev<double>(L.dinv);
+    launch_residual_init(st, T, P, Av, dinv, bd, X, r, p, part0);
+    launch_init_finalize(st, T, part0, ctx->opts.rel_mode, sc);
+    const int max_iter = ctx->opts.max_iter;
+    Scalars h{};
+    HIPCHK(hipMemcpyAsync(&h, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int it = 0;
+    while (!h.done && it < max_iter) {
+        const int c = std::min(8, max_iter - it);
+        for (int i = 0; i < c; ++i, ++it) {
+            launch_spmv_dot(st, T, P, Av, p, q, part_pq, &sc->done, nullptr, nullptr, false);
+            launch_cg_update(st, T, it, part_pq, dinv, p, q, X, r, nullptr, part_rz, sc);
+            launch_cg_direction(st, T, it, part_rz, dinv, r, p, sc);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&h, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if (iters) *iters = h.done ? h.iters : -1;
+    if (mdx_status e = copy_vec_out(ctx, X, x)) return e;
+    if (h.nonfinite) return fail(ctx, MDX_ERR_NONFINITE, "non-finite value in the solve");
+    return MDX_OK;
+    GUARD_END
+}
+
 mdx_status mdx_ionic_step(mdx_ctx *ctx, double dt, int64_t n, const double *V, double *u,
                           double *iion)
 {

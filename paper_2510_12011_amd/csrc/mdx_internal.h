@@ -336,6 +336,10 @@ void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *M
                      const double *V, const double *Vprev, const double *src, double *x,
                      double *r, double *b, double *partial, const double *kdiag, float *kvp,
                      double *p0, bool nt);
+// standalone solve: r = b - A x, p0 = z = D^-1 r, partials as the RHS pass
+void launch_residual_init(hipStream_t s, const Tiling &t, SellView P, const double *Av,
+                          const double *dinv, const double *b, const double *x, double *r,
+                          double *p0, double *partial);
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
                           Scalars *sc);
 // q = A p with partial p.q (no convergence logic; `done` non-zero skips it).

@@ -120,6 +120,38 @@ __global__ __launch_bounds__(256) void k_rhs_init(
     write_partials<3>(acc, partial, t.groups, g);
 }
 
+// Initial residual of a given system (the standalone solve): r = b - A x,
+// z = D^-1 r, p0 = z; partials r.z, z.z and |D^-1 b|^2 in the layout
+// k_init_finalize reads.
+template <bool NT, typename CI>
+__global__ __launch_bounds__(256) void k_residual_init(
+    Tiling t, const int64_t *__restrict__ slice_ptr, Cols<CI> col, const double *__restrict__ Av,
+    const double *__restrict__ dinv, const double *__restrict__ b, const double *__restrict__ x,
+    double *__restrict__ r, double *__restrict__ p0, double *__restrict__ partial)
+{
+    const int g = logical_group(t.groups);
+    const int lane = threadIdx.x & (SLICE - 1);
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int t_end = min((g + 1) * t.tpb, t.n_tiles);
+    for (int tile = g * t.tpb; tile < t_end; ++tile) {
+        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+        const int64_t sl = row / SLICE;
+        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int32_t cb = slice_base(col, sl);
+        double ax = 0.0;
+        for (int64_t e = beg; e < end; e += SLICE)
+            ax += ld_stream<NT>(Av + e) * x[cb + (int32_t)ld_stream<NT>(col.idx + e)];
+        const double di = dinv[row], bi = b[row];
+        const double ri = bi - ax, zi = di * ri;
+        r[row] = ri;
+        p0[row] = zi;
+        acc[0] += ri * zi;
+        acc[1] += zi * zi;
+        acc[2] += (di * bi) * (di * bi);
+    }
+    write_partials<3>(acc, partial, t.groups, g);
+}
+
 __global__ __launch_bounds__(256) void k_init_finalize(int groups, const double *__restrict__ partial,
                                                        int rel_mode, Scalars *__restrict__ sc)
 {
@@ -394,6 +426,14 @@ void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *M
 {
     MDX_LAUNCH_SELL(P, nt, k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols, Mv,
                     Kv, dinv, sp, V, Vprev, src, x, r, b, partial, kdiag, kvp, p0);
+}
+
+void launch_residual_init(hipStream_t s, const Tiling &t, SellView P, const double *Av,
+                          const double *dinv, const double *b, const double *x, double *r,
+                          double *p0, double *partial)
+{
+    MDX_LAUNCH_SELL(P, false, k_residual_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr,
+                    cols, Av, dinv, b, x, r, p0, partial);
 }
 
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,

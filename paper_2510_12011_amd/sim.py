@@ -252,6 +252,16 @@ class Simulation:
                                            _ptr(vals)))
         return rows, cols, vals
 
+    def solve(self, b, x0):
+        """One PCG solve of A x = b (the library's FP64 iteration, the solver
+        options' tolerances); returns (x, iterations or -1)."""
+        b = np.ascontiguousarray(b, np.float64)
+        x0 = np.ascontiguousarray(x0, np.float64)
+        x = np.empty_like(b)
+        it = C.c_int32(0)
+        self._check(L.lib().mdx_solve(self._h, _ptr(b), _ptr(x0), _ptr(x), C.byref(it)))
+        return x, it.value
+
     def spmv(self, which, x):
         w = {"M": L.MDX_MAT_M, "K": L.MDX_MAT_K, "A": L.MDX_MAT_A}[which]
         x = np.ascontiguousarray(x, np.float64)

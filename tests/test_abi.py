@@ -280,3 +280,11 @@ def test_surface_batch_validation(host_ctx):
     assert lib.mdx_set_surface_mesh_batch(host_ctx, 2, _p(ptr), n, _p(xyz), 1.0, m, _p(bad), None,
                                           None) == L.MDX_ERR_BAD_MESH
     assert "joins two instances" in _err(host_ctx)
+
+
+def test_solve_needs_a_prepared_single_mesh(host_ctx):
+    lib = L.lib()
+    v = np.zeros(4)
+    it = C.c_int32(0)
+    assert lib.mdx_solve(host_ctx, _p(v), _p(v), _p(v), C.byref(it)) == L.MDX_ERR_STATE
+    assert lib.mdx_solve(host_ctx, None, _p(v), _p(v), None) == L.MDX_ERR_INVALID_ARG

@@ -251,3 +251,37 @@ def test_slab_full_size_prefix_and_front():
         assert _rel_l2(a, b) <= V_REL_L2
     assert ((st["V"] > 0).sum() > 1000)       # a wave is in flight
     sys.stdout.flush()
+
+
+@pytest.mark.parametrize("spec_fn,rel_mode", [
+    (lambda: inputs.tiny_cube(n=8), 0),
+    (lambda: inputs.small_box(nx=6, ny=5, nz=4, jitter=0.2), 1),
+    (lambda: inputs.small_surface(3), 1),
+])
+def test_standalone_solve_matches_oracle_pcg(spec_fn, rel_mode):
+    """Algorithm 1 alone (mdx_solve) against the oracle's PCG on the same A,
+    random b and x0: solution to 1e-9, iteration count within one; the
+    iteration cap (x after max_iter iterations, count -1); b = 0 from x0 = 0
+    finishes at once."""
+    spec = spec_fn()
+    s = _sim(spec)
+    m = orc.assemble_spec(spec)
+    A = spec.chi * spec.cm * m.M + spec.theta * spec.dt * m.K
+    rng = np.random.default_rng(11)
+    b = rng.normal(size=m.n) * 0.01
+    x0 = rng.normal(size=m.n)
+    s.set_solver(0.0, 1e-10, rel_mode, 1000, 1, 0, 50)
+    x, it = s.solve(b, x0)
+    x_or, it_or, _ = orc.pcg(m, A, b, x0, atol=0.0, rtol=1e-10, rel_mode=rel_mode, max_iter=1000)
+    print(f"  iterations {it} vs oracle {it_or}, x rel err "
+          f"{np.linalg.norm(x - x_or) / np.linalg.norm(x_or):.2e}", flush=True)
+    assert it_or > 0 and abs(it - it_or) <= 1
+    assert np.linalg.norm(x - x_or) <= 1e-9 * np.linalg.norm(x_or)
+    s.set_solver(0.0, 1e-10, rel_mode, 3, 1, 0, 50)
+    x3, it3 = s.solve(b, x0)
+    x3_or, it3_or, _ = orc.pcg(m, A, b, x0, atol=0.0, rtol=1e-10, rel_mode=rel_mode, max_iter=3)
+    assert it3 == -1 and it3_or == -1
+    assert np.linalg.norm(x3 - x3_or) <= 1e-12 * np.linalg.norm(x3_or)
+    z = np.zeros(m.n)
+    xz, itz = s.solve(z, z)
+    assert itz == 0 and not xz.any()
