@@ -108,3 +108,23 @@ def test_batched_surfaces_match_oracle():
         fin = np.isfinite(lo)
         assert fin.any()
         assert abs(lk[fin] - lo[fin]).max() <= spec.dt * (1 + 1e-9)
+
+
+def test_surface_variants_lumped_theta1_two_regions():
+    """The 2,562-node surface with lumped mass, backward Euler (theta 1) and
+    the upper half (z > 0) a second region given intra/extracellular
+    conductivities: FP64 against the oracle to 1e-9, LAT within one step."""
+    spec = inputs.small_surface(4, n_steps=300)
+    p = spec.mesh.xyz[spec.mesh.tets].mean(axis=1)
+    spec.mesh.region = np.where(p[:, 2] > 0.0, 1, 0).astype(np.int32)
+    spec = dataclasses.replace(spec, theta=1.0, lumped_mass=True,
+                               ie_regions=[([1], 0.3, 0.1, 0.6, 0.3)])
+    s = _sim(spec)
+    o = orc.Oracle(spec)
+    v_or, _ = o.steps(300, out_every=100)
+    v_gpu, status = s.run(300, out_every=100)
+    assert status == 0
+    errs = [_rel_l2(a, b) for a, b in zip(v_gpu, v_or)]
+    print(f"  V rel L2 max {max(errs):.2e}", flush=True)
+    assert max(errs) <= 1e-9, errs
+    _lat_check(s, o, spec.dt)

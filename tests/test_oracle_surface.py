@@ -135,3 +135,19 @@ def test_degenerate_triangle_rejected():
     xyz = np.array([[0.0, 0, 0], [1, 0, 0], [2, 0, 0], [0, 1, 0]])
     with pytest.raises(ValueError):
         orc.assemble(xyz, np.array([[0, 1, 2], [0, 1, 3]], np.int32), None, 1.0, 1.0)
+
+
+def test_lumped_surface_mass_is_a_third_of_the_incident_areas():
+    # row-sum lumping of the P1 surface mass: node i gets area/3 of every
+    # triangle it belongs to (the consistent row sums are area/12 * (2+1+1))
+    xyz, tris = inputs.icosphere(2)
+    xyz = xyz * np.array([3.0, 2.0, 1.5])
+    mats = orc.lumped(orc.assemble(xyz, tris, None, 1.0, 1.0))
+    p = xyz[tris]
+    area = 0.5 * np.linalg.norm(np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), axis=1)
+    expect = np.zeros(xyz.shape[0])
+    for k in range(3):
+        np.add.at(expect, tris[:, k], area / 3.0)
+    D = mats.dense("M")
+    np.testing.assert_allclose(np.diag(D), expect, rtol=1e-13)
+    assert not (D - np.diag(np.diag(D))).any()
