@@ -55,23 +55,27 @@ int64_t orc_pattern_elems(int64_t n, int64_t m, int npe, const int32_t *el,
     for (int64_t e = 0; e < m; ++e)
         for (int a = 0; a < npe; ++a) inc[fill[el[npe * e + a]]++] = (int32_t)e;
 
-    int32_t buf[4096];
+    /* room for every vertex id of the most-shared node's elements */
+    int64_t max_inc = 1;
+    for (int64_t i = 0; i < n; ++i)
+        if (cnt[i + 1] - cnt[i] > max_inc) max_inc = cnt[i + 1] - cnt[i];
+    int32_t *buf = malloc(sizeof(int32_t) * (size_t)(npe * max_inc));
     int64_t nnz = 0;
     row_ptr[0] = 0;
     for (int64_t i = 0; i < n; ++i) {
-        int nb = 0;
-        for (int64_t t = cnt[i]; t < cnt[i + 1] && nb + npe <= 4096; ++t)
+        int64_t nb = 0;
+        for (int64_t t = cnt[i]; t < cnt[i + 1]; ++t)
             for (int a = 0; a < npe; ++a) buf[nb++] = el[npe * (int64_t)inc[t] + a];
         if (nb == 0) buf[nb++] = (int32_t)i; /* isolated node keeps its diagonal */
         qsort(buf, (size_t)nb, sizeof(int32_t), cmp_i32);
-        int nu = 0;
-        for (int q = 0; q < nb; ++q)
+        int64_t nu = 0;
+        for (int64_t q = 0; q < nb; ++q)
             if (q == 0 || buf[q] != buf[q - 1]) buf[nu++] = buf[q];
         if (col && nnz + nu <= cap) memcpy(col + nnz, buf, sizeof(int32_t) * (size_t)nu);
         nnz += nu;
         row_ptr[i + 1] = nnz;
     }
-    free(cnt); free(fill); free(inc);
+    free(cnt); free(fill); free(inc); free(buf);
     return nnz;
 }
 

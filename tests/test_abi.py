@@ -288,3 +288,20 @@ def test_solve_needs_a_prepared_single_mesh(host_ctx):
     it = C.c_int32(0)
     assert lib.mdx_solve(host_ctx, _p(v), _p(v), _p(v), C.byref(it)) == L.MDX_ERR_STATE
     assert lib.mdx_solve(host_ctx, None, _p(v), _p(v), None) == L.MDX_ERR_INVALID_ARG
+
+
+def test_surface_fan_pattern(host_ctx):
+    """A node shared by 2000 triangles: the library's pattern has N + 2 #edges
+    entries (2000 spokes and 2000 rim edges)."""
+    lib = L.lib()
+    k = 2000
+    ang = 2 * np.pi * np.arange(k) / k
+    xyz = np.ascontiguousarray(np.concatenate([[[0.0, 0.0, 0.0]],
+                                               np.stack([np.cos(ang), np.sin(ang), 0 * ang], 1)]))
+    tris = np.ascontiguousarray(np.stack([np.zeros(k, np.int32), 1 + np.arange(k),
+                                          1 + (np.arange(k) + 1) % k], axis=1).astype(np.int32))
+    assert lib.mdx_set_surface_mesh(host_ctx, k + 1, _p(xyz), 1.0, k, _p(tris), None,
+                                    None) == L.MDX_OK
+    st = L.Stats()
+    assert lib.mdx_get_stats(host_ctx, C.byref(st)) == L.MDX_OK
+    assert st.nnz == (k + 1) + 2 * (2 * k)

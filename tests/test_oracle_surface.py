@@ -151,3 +151,22 @@ def test_lumped_surface_mass_is_a_third_of_the_incident_areas():
     D = mats.dense("M")
     np.testing.assert_allclose(np.diag(D), expect, rtol=1e-13)
     assert not (D - np.diag(np.diag(D))).any()
+
+
+def test_pattern_of_a_node_shared_by_2000_triangles():
+    # a closed fan: the centre node shares all 2000 triangles, so its row
+    # holds every node; rim nodes see the centre and their two neighbours
+    k = 2000
+    ang = 2 * np.pi * np.arange(k) / k
+    xyz = np.concatenate([[[0.0, 0.0, 0.0]], np.stack([np.cos(ang), np.sin(ang), 0 * ang], 1)])
+    tris = np.stack([np.zeros(k, np.int32), 1 + np.arange(k), 1 + (np.arange(k) + 1) % k],
+                    axis=1).astype(np.int32)
+    row_ptr, col = orc.pattern(k + 1, tris)
+    assert row_ptr[1] - row_ptr[0] == k + 1
+    assert np.array_equal(col[:k + 1], np.arange(k + 1))
+    assert np.all(np.diff(row_ptr)[1:] == 4)
+    mats = orc.assemble(xyz, tris, None, 1.0, 1.0)
+    # the metric's determinant |e1|^2 |e2|^2 - (e1.e2)^2 cancels for these
+    # 0.18-degree slivers: relative rounding up to about eps / sin^2(angle),
+    # 2e-11 here
+    assert mats.M.sum() == pytest.approx(0.5 * k * np.sin(2 * np.pi / k), rel=1e-10)
