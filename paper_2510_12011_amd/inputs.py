@@ -596,7 +596,8 @@ def ellipsoid_surface(level: int, axes=(40.0, 33.0, 30.0), fibres: bool = True) 
                 region=np.zeros(tris.shape[0], np.int32), shape=(level,))
 
 
-# modified two-variable Mitchell-Schaeffer of the paper's left-atrium example:
+# modified two-variable Mitchell-Schaeffer of the paper's left-atrium example
+# ("Best Practices" section):
 # tau_in, tau_out, tau_open, tau_close, u_gate (its u_crit, 0.1 there too, is
 # the same threshold here), v_rest, v_amp
 ATRIUM_MS_PARAMS = (0.15, 1.5, 105.0, 185.0, 0.1, -80.0, 100.0)
@@ -604,9 +605,10 @@ ATRIUM_MS_PARAMS = (0.15, 1.5, 105.0, 185.0, 0.1, -80.0, 100.0)
 
 def atrium_surface(level: int = 8, n_steps: int = 5000, axes=(40.0, 33.0, 30.0),
                    radius: float = 2.0) -> RunSpec:
-    """Left-atrium-like surface workload, after the paper's atrium example:
-    a closed ellipsoidal triangle surface (level 8: 655,362 nodes, close to the
-    660,557-node atrial mesh it reports), isotropic 0.4 S/m, the modified
+    """Left-atrium-like surface workload, after the paper's atrium example
+    ("Best Practices" section; its surface timings are in "Performance
+    measurements"): a closed ellipsoidal triangle surface (level 8: 655,362
+    nodes, close to the 660,557-node atrial mesh it reports), isotropic 0.4 S/m, the modified
     Mitchell-Schaeffer parameters above, dt 0.01 ms, a 50 uA/cm^2 stimulus for
     2 ms on the nodes within ``radius`` mm of the +x apex, absolute and
     relative tolerance 1e-5 (relative to ||D^-1 b||)."""
