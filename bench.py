@@ -146,9 +146,11 @@ def learned_workload(args):
     held-out site is then run from rest for the same K steps by
       * learned warm start + mixed precision,
       * plain FP64 PCG with the paper's extrapolated warm start,
-      * plain FP64 PCG with the previous-step warm start (the judge of the
-        network's iteration savings),
-    at the workload's tolerance 1e-8, and by the first two again at 3e-9,
+      * plain FP64 PCG with the previous-step warm start (the yardstick of
+        the network's iteration savings),
+      * the remaining warm start x precision pairs,
+    at the workload's tolerance 1e-8, and by the first two (and extrapolated
+    + mixed) again at 3e-9,
     where both meet the accuracy bar with margin ("equal accuracy").  The
     accuracy of every run is measured against plain FP64 at 1e-12.  The value
     is learned + mixed at equal accuracy."""

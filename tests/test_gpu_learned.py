@@ -86,7 +86,7 @@ def test_trained_network_saves_iterations():
     """Train on 3 recorded trajectories of a ~100k-node shell (ten
     Tusscher-Panfilov, dt 0.02 ms, 40 ms each, random endocardial sites), then
     on a held-out site compare CG iterations per step with the previous-step
-    warm start (the judge) and the extrapolation 2V^k - V^{k-1}."""
+    warm start (the yardstick) and the extrapolation 2V^k - V^{k-1}."""
     from paper_2510_12011_amd import learn, _lib as L
     import torch
     mesh = inputs.ellipsoid_shell(n_nodes=100_000, seed=1000)
