@@ -170,3 +170,16 @@ def test_pattern_of_a_node_shared_by_2000_triangles():
     # 0.18-degree slivers: relative rounding up to about eps / sin^2(angle),
     # 2e-11 here
     assert mats.M.sum() == pytest.approx(0.5 * k * np.sin(2 * np.pi / k), rel=1e-10)
+
+
+def test_surface_inputs_are_seeded_and_carry_the_atrial_parameters():
+    a = inputs.batch_surfaces(n_inst=3, seed=5, n_steps=10)
+    b = inputs.batch_surfaces(n_inst=3, seed=5, n_steps=10)
+    for ia, ib in zip(a.instances, b.instances):
+        assert np.array_equal(ia.mesh.xyz, ib.mesh.xyz) and ia.sigma_l == ib.sigma_l
+        assert np.array_equal(ia.stimuli[0].nodes, ib.stimuli[0].nodes)
+        assert ia.mesh.tets.shape[1] == 3 and ia.stimuli[0].nodes.size > 0
+    assert a.instance_spec(1).ionic_params == inputs.ATRIUM_MS_PARAMS
+    sp = inputs.atrium_surface(level=3, n_steps=10)
+    assert sp.ionic_params == inputs.ATRIUM_MS_PARAMS and sp.mesh.n_nodes == 642
+    assert (sp.rtol, sp.atol, sp.rel_mode, sp.max_iter, sp.dt) == (1e-5, 1e-5, 1, 100, 0.01)
