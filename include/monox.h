@@ -206,8 +206,13 @@ MDX_API mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t sc
  * MDX_ERR_NONFINITE (state left as is, step counter at the failing step)
  * if V stopped being finite. */
 MDX_API mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_out);
-/* LAT and LRT (ms; +inf where not reached), host arrays of n_nodes or NULL */
+/* LAT and LRT (ms; +inf where not reached), host arrays of n_nodes or NULL.
+ * LAT_i: the first step time t^{k+1} at which V_i > 0; LRT_i: the first later
+ * step time at which V_i < -70 mV and falling ("Software functionality"). */
 MDX_API mdx_status mdx_get_times(mdx_ctx *ctx, double *lat, double *lrt);
+/* Action potential duration per node, APD_i = LRT_i - LAT_i (ms), +inf where
+ * the node has not both activated and repolarised; host array of n_nodes. */
+MDX_API mdx_status mdx_get_apd(mdx_ctx *ctx, double *apd);
 /* PCG iteration count of each of the last n steps (n <= steps run so far
  * in the last mdx_run call), -1 where max_iter was hit. */
 MDX_API mdx_status mdx_get_iterations(mdx_ctx *ctx, int64_t n, int32_t *iters);
@@ -333,7 +338,8 @@ MDX_API mdx_status mdx_autotune(mdx_ctx *ctx, int32_t reps, mdx_tune_report *rep
 /* ---- state (checkpoint / resume, parity checks) ----------------------- */
 /* V^k, V^{k-1}, states u (SoA, [nstates][n_nodes]), LAT, LRT and the step
  * index, all host arrays in original node order; any pointer may be NULL
- * on get.  set requires all of V, Vprev, u (if nstates > 0). */
+ * on get.  set requires all of V, Vprev, u (if nstates > 0), each finite
+ * (else MDX_ERR_INVALID_ARG); LAT and LRT may hold +inf. */
 MDX_API mdx_status mdx_get_state(mdx_ctx *ctx, double *V, double *Vprev, double *u,
                          double *lat, double *lrt, int64_t *step);
 MDX_API mdx_status mdx_set_state(mdx_ctx *ctx, const double *V, const double *Vprev,
@@ -351,7 +357,8 @@ MDX_API mdx_status mdx_spmv(mdx_ctx *ctx, int32_t which, const double *x, double
 /* One Jacobi-preconditioned CG solve (Algorithm 1) of A x = b with the
  * context's system matrix A = chi Cm M + theta dt K, outside the time loop:
  * host b and x0 (n values, original order) in, host x out; *iters (may be
- * NULL) receives the iterations taken, or -1 if max_iter ran out.  Uses the
+ * NULL) receives the iterations taken, or -1 if max_iter ran out.  Non-finite
+ * b or x0: MDX_ERR_INVALID_ARG.  Uses the
  * solver options' atol, rtol, rel_mode and max_iter with the FP64 kernels
  * of the time step (three per iteration), whatever the precision setting.
  * Needs mdx_prepare; leaves the simulation state untouched.  Single-mesh

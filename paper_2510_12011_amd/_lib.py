@@ -97,6 +97,7 @@ _SIGS = {
     "mdx_prepare": (C.c_int, [P, C.c_double, P, C.c_size_t]),
     "mdx_run": (C.c_int, [P, C.c_int64, C.c_int64, P]),
     "mdx_get_times": (C.c_int, [P, P, P]),
+    "mdx_get_apd": (C.c_int, [P, P]),
     "mdx_get_iterations": (C.c_int, [P, C.c_int64, P]),
     "mdx_get_stats": (C.c_int, [P, C.POINTER(Stats)]),
     "mdx_set_profiling": (C.c_int, [P, C.c_int32]),

@@ -1411,6 +1411,8 @@ mdx_status mdx_set_ionic(mdx_ctx *ctx, int32_t kind, int32_t n_params, const dou
     if (ctx->ionic_kind != kind) ctx->prepared = false;
     ctx->ionic_kind = kind;
     ctx->ionic_params = p;
+    // captured step graphs hold the parameters by value
+    release_graphs(ctx);
     return MDX_OK;
 }
 
@@ -1976,6 +1978,17 @@ mdx_status mdx_get_times(mdx_ctx *ctx, double *lat, double *lrt)
     return MDX_OK;
 }
 
+mdx_status mdx_get_apd(mdx_ctx *ctx, double *apd)
+{
+    if (!ctx || !apd) return MDX_ERR_INVALID_ARG;
+    if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
+    std::vector<double> lrt(ctx->n);
+    if (mdx_status e = mdx_get_times(ctx, apd, lrt.data())) return e;
+    for (int64_t i = 0; i < ctx->n; ++i)
+        apd[i] = std::isfinite(apd[i]) && std::isfinite(lrt[i]) ? lrt[i] - apd[i] : INFINITY;
+    return MDX_OK;
+}
+
 mdx_status mdx_get_iterations(mdx_ctx *ctx, int64_t n, int32_t *iters)
 {
     if (!ctx || (n > 0 && !iters)) return MDX_ERR_INVALID_ARG;
@@ -2188,6 +2201,10 @@ mdx_status mdx_set_state(mdx_ctx *ctx, const double *V, const double *Vprev, con
     for (int64_t i = 0; i < ctx->n; ++i)
         if (!std::isfinite(V[i]) || !std::isfinite(Vprev[i]))
             return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite V at node %lld", (long long)i);
+    for (int64_t i = 0; i < (int64_t)ns * ctx->n; ++i)
+        if (!std::isfinite(u[i]))
+            return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite ionic state %lld of node %lld",
+                        (long long)(i / ctx->n), (long long)(i % ctx->n));
     GUARD_BEGIN
     if (mdx_status e = copy_vec_in(ctx, V, ctx->vec(0))) return e;
     if (mdx_status e = copy_vec_in(ctx, Vprev, ctx->vec(1))) return e;
@@ -2269,6 +2286,9 @@ mdx_status mdx_solve(mdx_ctx *ctx, const double *b, const double *x0, double *x,
     if (!ctx || !b || !x0 || !x) return MDX_ERR_INVALID_ARG;
     if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
     if (ctx->batched) return fail(ctx, MDX_ERR_UNSUPPORTED, "not available on a batched context");
+    for (int64_t i = 0; i < ctx->n; ++i)
+        if (!std::isfinite(b[i]) || !std::isfinite(x0[i]))
+            return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite b or x0 at node %lld", (long long)i);
     GUARD_BEGIN
     const Layout &L = ctx->L;
     hipStream_t st = ctx->stream;

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_b_init_finalize(int groups,
     s.replace = 0;
     s.redirect = 0;
     s.failed = 0;
-    const bool finite = z0 == z0 && db == db && v[0] == v[0];
+    const bool finite = isfinite(z0) && isfinite(db) && isfinite(v[0]);
     s.nonfinite = finite ? 0 : 1;
     s.done = (!finite || z0 <= s.floor_ || z0 < bp.atol) ? 1 : 0;
 }
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(256) void k_b_beta(int groups, const int32_t *__res
     const int it = s.it + 1;
     s.it = it;
     s.znorm = zn;
-    if (!(zn == zn) || !(v[0] == v[0])) {
+    if (!isfinite(zn) || !isfinite(v[0])) {
         s.nonfinite = 1;
         s.done = 1;
         s.iters = it;
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(256) void k_b_replace_finalize(int groups,
     const int why = s.replace;
     s.znorm = zn;
     s.replace = 0;
-    if (!(zn == zn) || !(v[0] == v[0])) {
+    if (!isfinite(zn) || !isfinite(v[0])) {
         s.nonfinite = 1;
         s.done = 1;
         s.iters = it;

@@ -158,7 +158,11 @@ __global__ __launch_bounds__(256) void k_init_finalize_ws(int groups, const doub
     sc->znorm = z0;
     sc->ref = rel_mode == 1 ? db : z0;
     sc->floor_ = 1e-15 * db;
-    sc->done = (z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
+    // a non-finite start ends the solve and is reported; a finite one clears
+    // the flag of an earlier solve
+    const bool ok = isfinite(z0) && isfinite(db) && isfinite(rz);
+    sc->nonfinite = ok ? 0 : 2;
+    sc->done = (!ok || z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
     sc->iters = 0;
     sc->replace = 0;
     sc->restart_it = 0;

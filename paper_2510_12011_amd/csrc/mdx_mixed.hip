@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
 __device__ __forceinline__ int test_z(Scalars *sc, double zn, int k, int rr, int max_iter,
                                       bool lead)
 {
-    if (!(zn == zn)) {
+    if (!isfinite(zn)) {
         if (lead) {
             sc->nonfinite = 2;
             sc->done = 1;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_replace_finalize(int groups, int max_it
     const int why = sc->replace;
     sc->znorm = zn;
     sc->replace = 0;
-    if (!(zn == zn)) {
+    if (!isfinite(zn)) {
         sc->nonfinite = 2;
         sc->done = 1;
         sc->iters = it;

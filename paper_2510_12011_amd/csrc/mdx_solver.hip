@@ -165,7 +165,11 @@ __global__ __launch_bounds__(256) void k_init_finalize(int groups, const double 
         sc->znorm = z0;
         sc->ref = rel_mode == 1 ? db : z0;
         sc->floor_ = 1e-15 * db;
-        sc->done = (z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
+        // a non-finite start (NaN, or a norm that overflowed) ends the solve
+        // and is reported; a finite one clears the flag of an earlier solve
+        const bool finite = isfinite(z0) && isfinite(db) && isfinite(v[0]);
+        sc->nonfinite = finite ? 0 : 2;
+        sc->done = (!finite || z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
         sc->iters = 0;
         sc->replace = 0;
         sc->restart_it = 0;
@@ -226,7 +230,7 @@ __global__ __launch_bounds__(256) void k_cg_spmv(
         reduce_partials<2>(partial_rz, t.groups, v);
         const double zn = sqrt(v[1]);
         const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-        if (!(zn == zn)) {   // NaN: stop the solve and flag it
+        if (!isfinite(zn)) {   // NaN or overflow: stop the solve and flag it
             if (lead) {
                 sc->nonfinite = 2;
                 sc->done = 1;
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(256) void k_cg_direction(Tiling t, int k,
     reduce_partials<2>(partial_rz, t.groups, v);
     const double zn = sqrt(v[1]);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (!(zn == zn)) {
+    if (!isfinite(zn)) {
         if (lead) {
             sc->nonfinite = 2;
             sc->done = 1;

@@ -503,6 +503,23 @@ def _cap_job(args):
     return shell_cap(**args)
 
 
+def _gpu_may_be_live() -> bool:
+    """True when this process may already hold a GPU context: torch has
+    initialised its device runtime, or a profiler's preloaded library (which
+    initialises the GPU before the program starts) is in the environment.
+    Such a process is never forked; the meshes are then built serially."""
+    import os
+    import sys
+    pre = os.environ.get("LD_PRELOAD", "")
+    if "rocprof" in pre or any(k.startswith("ROCPROF") for k in os.environ):
+        return True
+    torch = sys.modules.get("torch")
+    try:
+        return bool(torch is not None and torch.cuda.is_initialized())
+    except Exception:
+        return True
+
+
 def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
                  n_min: int = 50_000, n_max: int = 400_000, n_steps: int = 5000,
                  dt: float = 0.01, ionic: str = "ms", workers: int = 1,
@@ -527,7 +544,7 @@ def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
     jobs = [dict(a=float(axes[i, 0]), b=float(axes[i, 1]), c=float(axes[i, 2]),
                  wall=float(walls[i]), n_nodes=int(n[i]), seed=int(seed * 1000 + i))
             for i in range(n_inst)]
-    if workers > 1:
+    if workers > 1 and not _gpu_may_be_live():
         import multiprocessing as mp
         with mp.get_context("fork").Pool(workers) as pool:
             meshes = pool.map(_cap_job, jobs, chunksize=1)

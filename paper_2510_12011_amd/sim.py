@@ -175,6 +175,13 @@ class Simulation:
         self._check(L.lib().mdx_get_times(self._h, _ptr(lat), _ptr(lrt)))
         return lat, lrt
 
+    def apd(self):
+        """Action potential duration per node, LRT - LAT (ms; inf where the
+        node has not activated and repolarised)."""
+        apd = np.zeros(self.n)
+        self._check(L.lib().mdx_get_apd(self._h, _ptr(apd)))
+        return apd
+
     def iterations(self, n):
         it = np.zeros(n, np.int32)
         self._check(L.lib().mdx_get_iterations(self._h, n, _ptr(it)))

@@ -121,12 +121,17 @@ def _compare_run(spec, n_steps, out_every, lat_bar=None, scheme=None):
     assert max(errs) <= V_REL_L2, errs
     assert abs(it_gpu.astype(int) - it_or).max() <= 1
     lat_g, lrt_g = s.times()
-    lat_o = o.state.lat
-    assert np.array_equal(np.isfinite(lat_g), np.isfinite(lat_o))
-    fin = np.isfinite(lat_o)
-    if fin.any():
-        assert abs(lat_g[fin] - lat_o[fin]).max() <= spec.dt * (1 + 1e-9)
+    _times_check(lat_g, o.state.lat, spec.dt)
+    _times_check(lrt_g, o.state.lrt, spec.dt)
     return s, o
+
+
+def _times_check(t_gpu, t_or, dt):
+    """The same nodes reached the event, each within one time step."""
+    assert np.array_equal(np.isfinite(t_gpu), np.isfinite(t_or))
+    fin = np.isfinite(t_or)
+    if fin.any():
+        assert abs(t_gpu[fin] - t_or[fin]).max() <= dt * (1 + 1e-9)
 
 
 def test_trajectory_parity_tiny_cube():
@@ -202,6 +207,33 @@ def test_trajectory_parity_lumped_mass():
     spec = inputs.small_box(nx=10, ny=8, nz=6, ionic="tt", n_steps=300, stim_extent=0.5)
     spec.lumped_mass = True
     _compare_run(spec, 300, 100)
+
+
+def test_trajectory_parity_two_stimuli_and_repolarisation():
+    """Two timed stimuli at opposite corners, the second starting at 3 ms
+    and overlapping the first in time, on an anisotropic box with the atrial
+    Mitchell-Schaeffer parameters, run for 250 ms at dt 0.05 ms: past every
+    node's repolarisation, so LRT ("Software functionality": back below -70
+    mV while falling) is compared node by node with the oracle's, as LAT is."""
+    spec = inputs.small_box(nx=10, ny=8, nz=6, ionic="ms", n_steps=5000, dt=0.05)
+    spec.ionic_params = inputs.ATRIUM_MS_PARAMS
+    far = np.flatnonzero((spec.mesh.grid[:, 0] >= 1.2 - 0.3 - 1e-9)
+                         & (spec.mesh.grid[:, 1] >= 1.0 - 0.3 - 1e-9)).astype(np.int32)
+    spec.stimuli.append(inputs.Stimulus(far, 3.0, 2.0, 0.4))
+    s, o = _compare_run(spec, 5000, 500)
+    lat, lrt = o.state.lat, o.state.lrt
+    assert np.isfinite(lat).all() and np.isfinite(lrt).all()
+    apd = s.apd()
+    np.testing.assert_allclose(apd, lrt - lat, rtol=0, atol=2 * spec.dt * (1 + 1e-9))
+    assert apd.min() > 50.0
+
+
+def test_surface_repolarisation_times():
+    """The 2,562-node ellipsoidal surface with the atrial cell parameters
+    over 250 ms (dt 0.01 ms): activation and repolarisation times of every
+    node against the oracle."""
+    spec = inputs.small_surface(4, n_steps=25000)
+    _compare_run(spec, 25000, 5000)
 
 
 def test_coarse_slab_tt_full_length():
@@ -285,3 +317,45 @@ def test_standalone_solve_matches_oracle_pcg(spec_fn, rel_mode):
     z = np.zeros(m.n)
     xz, itz = s.solve(z, z)
     assert itz == 0 and not xz.any()
+
+
+def test_nonfinite_is_reported_and_cleared():
+    """A stimulus so strong that the solve's norms overflow is reported as
+    MDX_ERR_NONFINITE at its first step (an overflowed norm is not taken for
+    convergence); the flag does not outlive that solve: after restoring a
+    finite state past that stimulus, the run continues normally and follows
+    the oracle from the same state.  Non-finite inputs to mdx_solve and
+    mdx_set_state are rejected on the host.  Every kernel exits normally
+    (max_iter 20 bounds each solve)."""
+    from paper_2510_12011_amd import _lib as L
+    spec = inputs.small_box(nx=8, ny=6, nz=5, ionic="ms", n_steps=300)
+    spec.max_iter = 20
+    corner = spec.stimuli[0].nodes
+    spec.stimuli = [inputs.Stimulus(corner, 0.0, 0.02, 1e308),
+                    inputs.Stimulus(corner, 0.1, 2.0, 0.5)]
+    s = _sim(spec)
+    with pytest.raises(L.MdxError) as e:
+        s.run(5)
+    assert e.value.status == L.MDX_ERR_NONFINITE
+    V0, u0 = orc.ionic_init("ms", spec.mesh.n_nodes, np.array(orc.ionic_defaults("ms")))
+    inf = np.full(spec.mesh.n_nodes, np.inf)
+    bad = u0.copy()
+    bad[0, 3] = np.nan
+    with pytest.raises(L.MdxError) as e:
+        s.set_state(V0, V0, bad, inf, inf, 10)
+    assert e.value.status == L.MDX_ERR_INVALID_ARG
+    s.set_state(V0, V0, u0, inf, inf, 10)
+    v_gpu, status = s.run(200, 100)
+    assert status == 0
+    o = orc.Oracle(spec)
+    o.state = orc.State(V0.copy(), V0.copy(), u0.copy(), inf.copy(), inf.copy(), 10)
+    v_or, _ = o.steps(200, out_every=100)
+    assert max(_rel_l2(a, b) for a, b in zip(v_gpu, v_or)) <= V_REL_L2
+    assert np.isfinite(s.times()[0]).sum() > 0
+    b = np.zeros(spec.mesh.n_nodes)
+    b[7] = np.nan
+    with pytest.raises(L.MdxError) as e:
+        s.solve(b, np.zeros_like(b))
+    assert e.value.status == L.MDX_ERR_INVALID_ARG
+    x, it = s.solve(np.ones_like(b), np.zeros_like(b))
+    assert it > 0 and np.isfinite(x).all()

@@ -55,7 +55,8 @@ def _lat_check(s, o, dt):
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-9), ("mixed", 1e-5)])
 def test_surface_trajectory_parity(precision, bar):
     """2,562-node ellipsoidal surface, anisotropic along projected fibres,
-    modified Mitchell-Schaeffer, 400 steps of 0.01 ms."""
+    two-variable Mitchell-Schaeffer with the atrial parameters, 400 steps of
+    0.01 ms."""
     spec = inputs.small_surface(4, n_steps=400)
     s = _sim(spec, precision=precision)
     o = orc.Oracle(spec)
