@@ -229,6 +229,9 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
 /* Launch-shape tuning (no effect on results beyond rounding order):
  *   MDX_TUNE_MAX_GROUPS  cap on workgroups of the row-tiled kernels
  *                        (16..65536, default 2048);
+ *   MDX_TUNE_SPMV_MAX_GROUPS cap on workgroups of the PCG iteration's SpMV
+ *                        kernel (16..65536, default 65536: one 256-row tile
+ *                        per workgroup up to 16.7M rows);
  *   MDX_TUNE_ITER_SCHEME plain FP64 PCG iteration as three kernels (0:
  *                        SpMV, update, direction) or two kernels (1: the
  *                        SpMV kernel forms q = A p = A z + beta q and
@@ -262,7 +265,8 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
  *                        indices as 16-bit offsets from a per-slice base,
  *                        2 bytes per stored entry instead of 4; 0 reads the
  *                        32-bit indices.  Results are bitwise the same.
- * MAX_GROUPS and ITER_SCHEME take effect at the next mdx_prepare / mdx_run;
+ * MAX_GROUPS, SPMV_MAX_GROUPS and ITER_SCHEME take effect at the next
+ * mdx_prepare / mdx_run;
  * the batched keys need a prepared batched context and act at once. */
 enum {
     MDX_TUNE_MAX_GROUPS = 1,
@@ -272,7 +276,8 @@ enum {
     MDX_TUNE_GRAPH = 5,
     MDX_TUNE_FORMAT = 6,
     MDX_TUNE_NONTEMPORAL = 7,
-    MDX_TUNE_COMPACT_COLUMNS = 8
+    MDX_TUNE_COMPACT_COLUMNS = 8,
+    MDX_TUNE_SPMV_MAX_GROUPS = 9
 };
 MDX_API mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value);
 

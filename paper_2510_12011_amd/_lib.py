@@ -32,6 +32,7 @@ MDX_TUNE_MAX_GROUPS, MDX_TUNE_ITER_SCHEME = 1, 2
 MDX_TUNE_LANES_PER_ROW, MDX_TUNE_TILES_PER_GROUP, MDX_TUNE_GRAPH, MDX_TUNE_FORMAT = 3, 4, 5, 6
 MDX_TUNE_NONTEMPORAL = 7
 MDX_TUNE_COMPACT_COLUMNS = 8
+MDX_TUNE_SPMV_MAX_GROUPS = 9
 MDX_TUNE_MAX_CANDIDATES = 32
 
 

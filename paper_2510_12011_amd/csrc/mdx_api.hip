@@ -100,7 +100,8 @@ struct mdx_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     Layout L{};
-    Tiling tiling{};
+    Tiling tiling{};        // vector and right-hand-side kernels
+    Tiling tiling_spmv{};   // the PCG iteration's SpMV kernel
     bool prepared = false;
     double dt = 0.0;
     int64_t step = 0;
@@ -122,6 +123,7 @@ struct mdx_ctx {
 
     // launch-shape tuning
     int max_groups = kMaxGroups;
+    int spmv_max_groups = kPartialCap;   // one 256-row tile per workgroup up to 16.7M rows
     int iter_scheme = 0;
     int nt_mode = -1;   // non-temporal matrix loads: -1 by stream size, 0 never, 1 always
     bool compact_cols = true;   // per-step kernels read col16 when it exists
@@ -1656,6 +1658,7 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     HIPCHK(hipStreamSynchronize(st));
 
     ctx->tiling = make_tiling(ctx->npad, ctx->max_groups);
+    ctx->tiling_spmv = make_tiling(ctx->npad, ctx->spmv_max_groups);
     release_graphs(ctx);
     ctx->fmt = 0;
     ctx->lpr = 1;
@@ -1701,6 +1704,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     const Layout &L = ctx->L;
     hipStream_t st = ctx->stream;
     const Tiling &T = ctx->tiling;
+    const Tiling &TS = ctx->tiling_spmv;
     const SellView P = step_view(ctx);
     double *Mv = ctx->dev<double>(L.Mv), *Kv = ctx->dev<double>(L.Kv), *Av = ctx->dev<double>(L.Av);
     double *dinv = ctx->dev<double>(L.dinv);
@@ -1763,7 +1767,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         // ---- right-hand side, warm start, initial residual ----
         // (the three-kernel FP64 iteration starts from p0 = z0, written by
         // the pass that forms r0)
-        double *p0_fp64 = !mixed && ctx->iter_scheme == 0 ? pbuf[0] : nullptr;
+        double *p0_fp64 = mixed ? nullptr : ctx->iter_scheme == 0 ? pbuf[0] : pbuf[1];
         // the learned warm start and the recorder need the neighbour feature
         // (K V^{n-1})_i / K_ii, kept up to date by the right-hand-side pass
         const bool want_kvp = learned || ctx->rec_X;
@@ -1825,8 +1829,8 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             return MDX_OK;
         };
         if (mixed) {
-            // two kernels per iteration; a chunk ends with the test of its
-            // last update and the (conditional) replacement
+            // a chunk of iterations (each ends with its stopping test), then
+            // the (conditional) residual replacement
             const int rr = ctx->opts.rr_interval;
             int it = 0;
             int chunk = std::max(1, ctx->last_iters);
@@ -1838,13 +1842,10 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                         e0 = ctx->ev[2 * units];
                         e1 = ctx->ev[2 * units + 1];
                     }
-                    launch_cg_spmv32(st, T, it + i, rr, max_iter, P, A32, z32, p32, q32, part_rz,
-                                     part_pq, sc, e0, e1, nt_iter32);
-                    launch_cg_update32(st, T, it + i, part_pq, dinv32, p32, q32, delta, r32, z32,
-                                       part_rz, sc);
+                    launch_cg_iteration32(st, TS, T, it + i, rr, max_iter, P, A32, dinv32, z32, p32,
+                                          q32, delta, r32, part_pq, part_rz, sc, e0, e1, nt_iter32);
                     ++units;
                 }
-                launch_cg_test32(st, T, it + c, rr, max_iter, part_rz, sc);
                 launch_replacement(st, T, P, max_iter, A32, X, delta, r, dinv, dinv32, r32, z32,
                                    part0, sc, nt_iter32);
                 if (mdx_status e = end_chunk()) return e;
@@ -1852,39 +1853,12 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                 it = ctx->sc_host->it_next;
                 chunk = 1;
             }
-        } else if (ctx->iter_scheme == 1) {
-            // Unit 0 is the first half of iteration 0; unit u >= 1 is the
-            // second half of iteration u-1 followed by the first half of
-            // iteration u, which tests ||z_u||.  Units 0..c detect convergence
-            // in <= c iterations with no idle launch.  First chunk: the
-            // previous step's count; then one unit at a time.
-            double *p = pbuf[0], *z = pbuf[1];
-            int chunk = std::max(1, ctx->last_iters) + 1;
-            while (!done && units <= max_iter) {
-                const int c = std::min(chunk, max_iter + 1 - units);
-                for (int i = 0; i < c; ++i) {
-                    const int u_ = units + i;
-                    if (u_ >= 1)
-                        launch_cg_update(st, T, u_ - 1, part_pq, dinv, p, q, X, r, z, part_rz, sc);
-                    hipEvent_t e0 = nullptr, e1 = nullptr;
-                    if (ctx->profiling && 2 * u_ + 1 < (int)ctx->ev.size()) {
-                        e0 = ctx->ev[2 * u_];
-                        e1 = ctx->ev[2 * u_ + 1];
-                    }
-                    launch_cg_spmv(st, T, u_, max_iter, P, Av, dinv, r, z, p, q, part_rz, part_pq,
-                                   sc, e0, e1, nt_iter64);
-                }
-                units += c;
-                if (mdx_status e = end_chunk()) return e;
-                done = ctx->sc_host->done != 0;
-                chunk = 1;
-            }
         } else {
-            // Three kernels per iteration: q = A p (+ p.q), update (+ r.z,
-            // z.z), direction (test, beta, p = z + beta p).  Iteration it's
-            // direction kernel tests ||z_{it+1}||.  First chunk: the previous
-            // step's count; then one iteration at a time.
-            double *p = pbuf[0];   // p0 = z0 from the right-hand-side pass
+            // FP64: a chunk of iterations (the previous step's count first,
+            // then one at a time); iteration it ends with the test of
+            // ||z_{it+1}||.  Scheme 0 starts from p0 = z0, scheme 1 from
+            // z0, both written by the pass that forms r0.
+            double *p = pbuf[0], *z = pbuf[1];
             int chunk = std::max(1, ctx->last_iters);
             while (!done && units < max_iter) {
                 const int c = std::min(chunk, max_iter - units);
@@ -1895,9 +1869,8 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                         e0 = ctx->ev[2 * it];
                         e1 = ctx->ev[2 * it + 1];
                     }
-                    launch_spmv_dot(st, T, P, Av, p, q, part_pq, &sc->done, e0, e1, nt_iter64);
-                    launch_cg_update(st, T, it, part_pq, dinv, p, q, X, r, nullptr, part_rz, sc);
-                    launch_cg_direction(st, T, it, part_rz, dinv, r, p, sc);
+                    launch_cg_iteration(st, TS, T, it, max_iter, ctx->iter_scheme, P, Av, dinv, r,
+                                        z, p, q, X, part_pq, part_rz, sc, e0, e1, nt_iter64);
                 }
                 units += c;
                 if (mdx_status e = end_chunk()) return e;
@@ -2121,6 +2094,13 @@ mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value)
         ctx->max_groups = (int)value;
         if (ctx->npad > 0) ctx->tiling = make_tiling(ctx->npad, ctx->max_groups);
         return MDX_OK;
+    case MDX_TUNE_SPMV_MAX_GROUPS:
+        if (value < 16 || value > kPartialCap)
+            return fail(ctx, MDX_ERR_INVALID_ARG, "spmv max_groups must lie in [16, %d]",
+                        kPartialCap);
+        ctx->spmv_max_groups = (int)value;
+        if (ctx->npad > 0) ctx->tiling_spmv = make_tiling(ctx->npad, ctx->spmv_max_groups);
+        return MDX_OK;
     case MDX_TUNE_ITER_SCHEME:
         if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "scheme is 0 or 1");
         ctx->iter_scheme = (int)value;
@@ -2313,9 +2293,8 @@ mdx_status mdx_solve(mdx_ctx *ctx, const double *b, const double *x0, double *x,
     while (!h.done && it < max_iter) {
         const int c = std::min(8, max_iter - it);
         for (int i = 0; i < c; ++i, ++it) {
-            launch_spmv_dot(st, T, P, Av, p, q, part_pq, &sc->done, nullptr, nullptr, false);
-            launch_cg_update(st, T, it, part_pq, dinv, p, q, X, r, nullptr, part_rz, sc);
-            launch_cg_direction(st, T, it, part_rz, dinv, r, p, sc);
+            launch_cg_iteration(st, ctx->tiling_spmv, T, it, max_iter, 0, P, Av, dinv, r, nullptr,
+                                p, q, X, part_pq, part_rz, sc, nullptr, nullptr, false);
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(&h, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));

@@ -90,6 +90,102 @@ __device__ __forceinline__ void group_sum(double (&v)[NV])
     __syncthreads();
 }
 
+// Sum NV values over a workgroup of any whole number of wavefronts (up to
+// 1024 threads); the totals are returned to every thread.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV])
+{
+    __shared__ double lds[16][NV];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) lds[w][k] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += lds[i][k];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// One workgroup (the finalize kernels: FIN threads) sums the `groups`
+// partials of a producer kernel, laid out partial[k * groups + g], in a fixed
+// order.
+constexpr int FIN = 1024;
+template <int NV>
+__device__ __forceinline__ void finalize_partials(const double *__restrict__ partial, int groups,
+                                                  double (&v)[NV])
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int g = threadIdx.x; g < groups; g += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += partial[k * groups + g];
+    block_sum<NV>(v);
+}
+
+// Product of one sliced-ELL row with a gathered vector x: the row's entries
+// are c[j * SLICE], a[j * SLICE] for j < w, where w is its slice's width
+// (uniform over the wavefront).  For a fixed width every column and value
+// load is issued before the first gather, so a row costs one memory round
+// trip for the streams and one for the gathers; entries are summed in
+// column order j = 0, 1, ... as a loop would.
+template <int W, bool NT, typename ACC, typename CI, typename TA, typename TX>
+__device__ __forceinline__ ACC sell_row_w(const CI *__restrict__ c, const TA *__restrict__ a,
+                                          const TX *__restrict__ x, int32_t cb)
+{
+    CI cc[W];
+    TA aa[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        cc[j] = ld_stream<NT>(c + j * SLICE);
+        aa[j] = ld_stream<NT>(a + j * SLICE);
+    }
+    TX xx[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) xx[j] = x[cb + (int32_t)cc[j]];
+    ACC s = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) s += (ACC)aa[j] * (ACC)xx[j];
+    return s;
+}
+
+constexpr int SELL_UNROLLED = 24;   // widest slice with a fixed-width body
+template <bool NT, typename ACC, typename CI, typename TA, typename TX>
+__device__ __forceinline__ ACC sell_row(int w, const CI *__restrict__ c, const TA *__restrict__ a,
+                                        const TX *__restrict__ x, int32_t cb)
+{
+    switch (w) {
+#define MDX_SELL_CASE(n) \
+    case n: return sell_row_w<n, NT, ACC>(c, a, x, cb);
+        MDX_SELL_CASE(1) MDX_SELL_CASE(2) MDX_SELL_CASE(3) MDX_SELL_CASE(4)
+        MDX_SELL_CASE(5) MDX_SELL_CASE(6) MDX_SELL_CASE(7) MDX_SELL_CASE(8)
+        MDX_SELL_CASE(9) MDX_SELL_CASE(10) MDX_SELL_CASE(11) MDX_SELL_CASE(12)
+        MDX_SELL_CASE(13) MDX_SELL_CASE(14) MDX_SELL_CASE(15) MDX_SELL_CASE(16)
+        MDX_SELL_CASE(17) MDX_SELL_CASE(18) MDX_SELL_CASE(19) MDX_SELL_CASE(20)
+        MDX_SELL_CASE(21) MDX_SELL_CASE(22) MDX_SELL_CASE(23) MDX_SELL_CASE(24)
+#undef MDX_SELL_CASE
+    default: {
+        ACC s = 0;
+        for (int j = 0; j < w; ++j)
+            s += (ACC)ld_stream<NT>(a + j * SLICE) * (ACC)x[cb + (int32_t)ld_stream<NT>(c + j * SLICE)];
+        return s;
+    }
+    }
+}
+
+// Slice handled by wavefront `wv` (0..3) of tile `tile`, as a scalar: its
+// header loads then go through the scalar cache.
+__device__ __forceinline__ int64_t wave_slice(int tile)
+{
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    return (int64_t)tile * (TILE / SLICE) + wv;
+}
+
 // Every workgroup reduces the `groups` partials of a producer kernel, laid
 // out partial[k * groups + g], in the same order.
 template <int NV>

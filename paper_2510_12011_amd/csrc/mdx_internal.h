@@ -53,11 +53,11 @@ struct alignas(256) Scalars {
     // mixed-precision form: residual replacement protocol
     int32_t replace;    // a replacement is pending (iteration kernels idle): 1 the
                         // recursive residual passed the test, 2 periodic or cap
-    int32_t restart_it; // iteration whose rho and beta were set by the
-                        // initialisation or a replacement (no test there)
+    int32_t pad_;       // keeps the record's layout in whole 8-byte words
     int32_t it_next;    // iterations completed (index of the next one)
     int32_t use_mlp;    // learned warm start: the MLP guess was chosen this step
-    double beta;        // beta of iteration restart_it
+    double beta;        // beta of the next iteration (0: restart with p = z)
+    double alpha;       // alpha of the current iteration
 };
 
 // Scalars as published to host memory (coherent pinned): the host spins on
@@ -164,18 +164,15 @@ void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const dou
                            const StepParams &sp, const double *V, const double *Vprev,
                            const double *src, double *x, double *r64, float *r32, float *z32,
                            float *delta, double *partial, const double *kdiag, float *kvp, bool nt);
-// iteration k: test (or restart point), q = A z + beta q, p = z + beta p, partial p.q
-void launch_cg_spmv32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter, SellView P,
-                      const float *A32, const float *z, float *p, float *q,
-                      const double *partial_rz, double *partial_pq, Scalars *sc,
-                      hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
-// iteration k: alpha, delta += alpha p, r -= alpha q, z = D^-1 r, partials r.z, z.z
-void launch_cg_update32(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
-                        const float *dinv32, const float *p, const float *q, float *delta,
-                        float *r, float *z, double *partial_rz, Scalars *sc);
-// the test of iteration k alone (end of a chunk)
-void launch_cg_test32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter,
-                      const double *partial_rz, Scalars *sc);
+// PCG iteration k of the FP32 form: SpMV on the tiling ts (q = A z + beta q,
+// p = z + beta p, partial p.q), alpha, update on t (delta, r, z, partials
+// r.z, z.z), stopping test of ||z_{k+1}|| and beta.  Events (optional) are
+// recorded around the SpMV dispatch.
+void launch_cg_iteration32(hipStream_t s, const Tiling &ts, const Tiling &t, int k, int rr,
+                           int max_iter, SellView P, const float *A32, const float *dinv32,
+                           float *z, float *p, float *q, float *delta, float *r,
+                           double *partial_pq, double *partial_rz, Scalars *sc,
+                           hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
 // true residual update (r64 -= A32 delta), flush, finalize (all no-ops
 // unless a replacement is pending)
 void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const float *A32,
@@ -347,22 +344,18 @@ void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial,
 void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *Av,
                      const double *p, double *q, double *partial, const int32_t *done,
                      hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
-// PCG iteration k, first half: test of ||z_k||, beta_k, q = A z_k + beta_k q,
-// p = z_k + beta_k p (in place), partial p_k.q
-void launch_cg_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
-                    const double *Av, const double *dinv, const double *r, const double *z,
-                    double *p, double *q, const double *partial_rz, double *partial_pq,
-                    Scalars *sc, hipEvent_t ev_start, hipEvent_t ev_stop, bool nt);
-// three-kernel scheme: direction update (test, beta, p = z + beta p) and p_0 = z_0
-void launch_cg_direction(hipStream_t s, const Tiling &t, int k, const double *partial_rz,
-                         const double *dinv, const double *r, double *p, Scalars *sc);
+// PCG iteration k of the FP64 form: scheme 1 (two streaming kernels:
+// q = A z + beta q and p = z + beta p on the tiling ts, then x, r, z) or 0
+// (three: q = A p on ts, then x and r, then p = D^-1 r + beta p), each with
+// the alpha and the stopping-test/beta finalize kernels.  Events (optional)
+// are recorded around the SpMV dispatch.
+void launch_cg_iteration(hipStream_t s, const Tiling &ts, const Tiling &t, int k, int max_iter,
+                         int scheme, SellView P, const double *Av, const double *dinv, double *r,
+                         double *z, double *p, double *q, double *x, double *partial_pq,
+                         double *partial_rz, Scalars *sc, hipEvent_t ev_start, hipEvent_t ev_stop,
+                         bool nt);
 void launch_set_direction(hipStream_t s, int64_t n, const double *dinv, const double *r, double *p,
                           const Scalars *sc);
-// PCG iteration k, second half (alpha_k, x and r update, z = D^-1 r stored
-// when z is non-null, partials r.z, z.z)
-void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
-                      const double *dinv, const double *p, const double *q, double *x, double *r,
-                      double *z, double *partial_rz, Scalars *sc);
 // activation / repolarisation times at t1 and the non-finite check; with a
 // guard, only once *guard is non-zero (idempotent: it may be queued after
 // every chunk of a solve)

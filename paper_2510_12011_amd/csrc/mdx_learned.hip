@@ -165,7 +165,6 @@ __global__ __launch_bounds__(256) void k_init_finalize_ws(int groups, const doub
     sc->done = (!ok || z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
     sc->iters = 0;
     sc->replace = 0;
-    sc->restart_it = 0;
     sc->beta = 0.0;
     sc->it_next = 0;
 }

@@ -22,21 +22,23 @@
 // triggered by the recursive residual passing the test with p = z (the
 // recursion had drifted from the true residual; restart).
 //
-// Two kernels per iteration k (Algorithm 1's recurrences, regrouped):
-//   cg_spmv32    test of ||z_k|| on the previous update's partials (or, at a
-//                restart point, beta from the scalars); beta_k; then
-//                q = A p_k = A z_k + beta_k q_{k-1} and p_k = z_k + beta_k
-//                p_{k-1} by linearity of A: the gathers read z, the own rows
-//                update p and q; partial p_k . q
-//   cg_update32  alpha = rho_k / p_k.q; delta += alpha p; r -= alpha q;
-//                z = D^-1 r (stored); partials r.z, z.z
-// A chunk of iterations ends with cg_test32 (one workgroup), the same test,
-// so that a pass starts the replacement before the host reads the scalars.
+// Per iteration k (Algorithm 1's recurrences, regrouped), two streaming
+// kernels and two single-workgroup finalize kernels:
+//   cg_spmv32    beta_k from the scalars; q = A p_k = A z_k + beta_k q_{k-1}
+//                and p_k = z_k + beta_k p_{k-1} by linearity of A: the gathers
+//                read z, the own rows update p and q; partial p_k . q
+//   cg_alpha32   alpha_k = rho_k / p_k.q (fixed-order sum of the partials)
+//   cg_update32  delta += alpha p; r -= alpha q; z = D^-1 r (stored);
+//                partials r.z, z.z
+//   cg_beta32    stopping test of ||z_{k+1}||; beta_{k+1}, rho_{k+1}
+// The SpMV kernel runs on its own tiling (one 256-row tile per workgroup by
+// default: many short-lived workgroups hide the latency of the gathers), the
+// vector kernels on the shared one.  Only the finalize kernels read the
+// partials, so the count of SpMV workgroups costs no re-reduction.
 //
 // Kernels queued after convergence or while a replacement is pending return
 // at their first instruction; the replacement kernels return unless one is
-// pending.  Reductions are the deterministic two-level scheme of
-// mdx_device.h.
+// pending.  Reductions are deterministic (fixed-order sums, mdx_device.h).
 #include "mdx_device.h"
 #include "mdx_internal.h"
 
@@ -136,50 +138,36 @@ __device__ __forceinline__ int test_z(Scalars *sc, double zn, int k, int rr, int
     return why;
 }
 
-// Iteration k, first half (see the file comment).  All workgroups reduce the
-// same partials in the same order and take the same decision.
+// Iteration k, SpMV half (see the file comment); beta_k = 0 (the start,
+// or a restart after a replacement) takes p = z, q = A z without reading the
+// earlier p, q.
 template <bool NT, typename CI>
-__global__ __launch_bounds__(256) void k_cg_spmv32(Tiling t, int k, int rr, int max_iter,
-                                                   const int64_t *__restrict__ slice_ptr,
+__global__ __launch_bounds__(256) void k_cg_spmv32(Tiling t, const int64_t *__restrict__ slice_ptr,
                                                    Cols<CI> col, const float *__restrict__ A32,
                                                    const float *__restrict__ z,
                                                    float *__restrict__ p, float *__restrict__ q,
-                                                   const double *__restrict__ partial_rz,
                                                    double *__restrict__ partial_pq,
-                                                   Scalars *__restrict__ sc)
+                                                   const Scalars *__restrict__ sc)
 {
     if (halted(sc)) return;
-    double beta;
-    if (sc->restart_it == k) {
-        beta = sc->beta;   // rho_k, beta_k set by the initialisation or the replacement
-    } else {
-        double v[2];
-        reduce_partials<2>(partial_rz, t.groups, v);
-        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-        const double zn = sqrt(v[1]);
-        if (test_z(sc, zn, k, rr, max_iter, lead)) return;
-        beta = v[0] / sc->rho[(k - 1) & 1];
-        if (lead) {
-            sc->rho[k & 1] = v[0];
-            sc->znorm = zn;
-        }
-    }
-    const bool fresh = beta == 0.0;   // p = z, q = A z: earlier p, q are not read
+    const double beta = sc->beta;
+    const bool fresh = beta == 0.0;
     const float bf = (float)beta;
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
     double acc[1] = {0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = slice_ptr[sl];
+        const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
         const int32_t cb = slice_base(col, sl);
-        float sum = 0.0f;
-#pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(A32 + e) * z[cb + (int32_t)ld_stream<NT>(col.idx + e)];
-        const float pi = fresh ? z[row] : z[row] + bf * p[row];
-        const float qi = fresh ? sum : sum + bf * q[row];
+        const float zi = z[row];
+        const float pold = fresh ? 0.0f : p[row], qold = fresh ? 0.0f : q[row];
+        const float sum = sell_row<NT, float>(w, col.idx + b0 + lane, A32 + b0 + lane, z, cb);
+        const float pi = fresh ? zi : zi + bf * pold;
+        const float qi = fresh ? sum : sum + bf * qold;
         p[row] = pi;
         q[row] = qi;
         acc[0] += (double)pi * (double)qi;
@@ -187,23 +175,32 @@ __global__ __launch_bounds__(256) void k_cg_spmv32(Tiling t, int k, int rr, int 
     write_partials<1>(acc, partial_pq, t.groups, g);
 }
 
-// Iteration k, second half: alpha_k = rho_k / (p_k . q); delta += alpha p;
-// r -= alpha q; z = D^-1 r; partials r.z and z.z for the next test.
-__global__ __launch_bounds__(256) void k_cg_update32(Tiling t, int k,
-                                                     const double *__restrict__ partial_pq,
-                                                     const float *__restrict__ dinv32,
+// Iteration k: alpha_k = rho_k / (p_k . q) from the SpMV's partials.
+__global__ __launch_bounds__(FIN) void k_cg_alpha32(int groups, int k,
+                                                    const double *__restrict__ partial_pq,
+                                                    Scalars *__restrict__ sc)
+{
+    if (halted(sc)) return;
+    double pq[1];
+    finalize_partials<1>(partial_pq, groups, pq);
+    if (threadIdx.x == 0) {
+        sc->alpha = sc->rho[k & 1] / pq[0];
+        sc->it_next = k + 1;
+    }
+}
+
+// Iteration k, update half: delta += alpha p; r -= alpha q; z = D^-1 r;
+// partials r.z and z.z for the next test.
+__global__ __launch_bounds__(256) void k_cg_update32(Tiling t, const float *__restrict__ dinv32,
                                                      const float *__restrict__ p,
                                                      const float *__restrict__ q,
                                                      float *__restrict__ delta,
                                                      float *__restrict__ r, float *__restrict__ z,
                                                      double *__restrict__ partial_rz,
-                                                     Scalars *__restrict__ sc)
+                                                     const Scalars *__restrict__ sc)
 {
     if (halted(sc)) return;
-    double pq[1];
-    reduce_partials<1>(partial_pq, t.groups, pq);
-    const float alpha = (float)(sc->rho[k & 1] / pq[0]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->it_next = k + 1;
+    const float alpha = (float)sc->alpha;
     const int g = logical_group(t.groups);
     double acc[2] = {0.0, 0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
@@ -220,16 +217,23 @@ __global__ __launch_bounds__(256) void k_cg_update32(Tiling t, int k,
     write_partials<2>(acc, partial_rz, t.groups, g);
 }
 
-// End of a chunk of iterations (one workgroup): the test k_cg_spmv32 would
-// apply at iteration k, so that a pass starts the replacement at once.
-__global__ __launch_bounds__(256) void k_cg_test32(int groups, int k, int rr, int max_iter,
+// After iteration k's update (k1 = k + 1): the stopping test of ||z_k1||; if
+// the iteration goes on, beta_k1 = rho_k1 / rho_k.
+__global__ __launch_bounds__(FIN) void k_cg_beta32(int groups, int k1, int rr, int max_iter,
                                                    const double *__restrict__ partial_rz,
                                                    Scalars *__restrict__ sc)
 {
-    if (halted(sc) || sc->restart_it == k) return;
+    if (halted(sc)) return;
     double v[2];
-    reduce_partials<2>(partial_rz, groups, v);
-    test_z(sc, sqrt(v[1]), k, rr, max_iter, threadIdx.x == 0);
+    finalize_partials<2>(partial_rz, groups, v);
+    const bool lead = threadIdx.x == 0;
+    const double zn = sqrt(v[1]);
+    if (test_z(sc, zn, k1, rr, max_iter, lead)) return;
+    if (lead) {
+        sc->beta = v[0] / sc->rho[(k1 - 1) & 1];
+        sc->rho[k1 & 1] = v[0];
+        sc->znorm = zn;
+    }
 }
 
 // replacement, part 2: x64 += delta, delta = 0
@@ -263,14 +267,12 @@ __global__ __launch_bounds__(256) void k_true_residual(
     double acc[2] = {0.0, 0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
-        const int32_t cb = slice_base(col, sl);
-        double ad = 0.0;
-#pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE)
-            ad += (double)ld_stream<NT>(A32 + e) * (double)delta[cb + (int32_t)ld_stream<NT>(col.idx + e)];
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = slice_ptr[sl];
+        const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
+        const double ad =
+            sell_row<NT, double>(w, col.idx + b0 + lane, A32 + b0 + lane, delta, slice_base(col, sl));
         const double ri = r64[row] - ad;
         r64[row] = ri;
         const float rf = (float)ri;
@@ -317,7 +319,6 @@ __global__ __launch_bounds__(256) void k_replace_finalize(int groups, int max_it
     // recurrence (beta = rho_new / rho_old).
     sc->beta = why == 1 ? 0.0 : v[0] / sc->rho[(it - 1) & 1];
     sc->rho[it & 1] = v[0];
-    sc->restart_it = it;
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -340,28 +341,19 @@ void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const dou
                     kvp);
 }
 
-void launch_cg_spmv32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter, SellView P,
-                      const float *A32, const float *z, float *p, float *q,
-                      const double *partial_rz, double *partial_pq, Scalars *sc,
-                      hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
+void launch_cg_iteration32(hipStream_t s, const Tiling &ts, const Tiling &t, int k, int rr,
+                           int max_iter, SellView P, const float *A32, const float *dinv32,
+                           float *z, float *p, float *q, float *delta, float *r,
+                           double *partial_pq, double *partial_rz, Scalars *sc,
+                           hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
 {
-    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_cg_spmv32, dim3(t.groups), dim3(TILE), 0, s, t, k,
-                       rr, max_iter, P.slice_ptr, cols, A32, z, p, q, partial_rz, partial_pq, sc);
-}
-
-void launch_cg_update32(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
-                        const float *dinv32, const float *p, const float *q, float *delta,
-                        float *r, float *z, double *partial_rz, Scalars *sc)
-{
-    hipLaunchKernelGGL(k_cg_update32, dim3(t.groups), dim3(TILE), 0, s, t, k, partial_pq, dinv32, p,
-                       q, delta, r, z, partial_rz, sc);
-}
-
-void launch_cg_test32(hipStream_t s, const Tiling &t, int k, int rr, int max_iter,
-                      const double *partial_rz, Scalars *sc)
-{
-    hipLaunchKernelGGL(k_cg_test32, dim3(1), dim3(TILE), 0, s, t.groups, k, rr, max_iter, partial_rz,
-                       sc);
+    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_cg_spmv32, dim3(ts.groups), dim3(TILE), 0, s, ts,
+                       P.slice_ptr, cols, A32, z, p, q, partial_pq, sc);
+    hipLaunchKernelGGL(k_cg_alpha32, dim3(1), dim3(FIN), 0, s, ts.groups, k, partial_pq, sc);
+    hipLaunchKernelGGL(k_cg_update32, dim3(t.groups), dim3(TILE), 0, s, t, dinv32, p, q, delta, r,
+                       z, partial_rz, sc);
+    hipLaunchKernelGGL(k_cg_beta32, dim3(1), dim3(FIN), 0, s, t.groups, k + 1, rr, max_iter,
+                       partial_rz, sc);
 }
 
 void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter, const float *A32,

@@ -8,29 +8,31 @@
 //                 per-workgroup partials of r.z, z.z, |D^-1 b|^2
 //   init_finalize rho_0, ||z_0||, the stopping reference, done if z_0 is at the
 //                 rounding floor
-//   per iteration k (two kernels, the default):
-//   cg_spmv       (k >= 1) ||z_k||; stop if ||z_k|| < atol, < rtol * ref
-//                 or at the floor; beta_k = rho_k / rho_{k-1};
-//                 q = A p_k = A z_k + beta_k q_{k-1} and p_k = z_k + beta_k
-//                 p_{k-1} (A is linear: the gathers read z only); partial
-//                 p_k . q
-//   cg_update     alpha = rho_k / p_k.q; x += alpha p_k; r -= alpha q;
-//                 z = D^-1 r (stored); partials r.z, z.z
-//   or three kernels: spmv_dot (q = A p, partial p.q), cg_update,
-//   cg_direction (test, beta, p = z + beta p)
-//   spmv_dot      plain q = A p with partial p.q (inspection entry point)
+//   per iteration k, two streaming kernels (the default: three) and two
+//   single-workgroup finalize kernels:
+//   cg_spmv       beta_k from the scalars; q = A p_k = A z_k + beta_k q_{k-1}
+//                 and p_k = z_k + beta_k p_{k-1} (A is linear: the gathers
+//                 read z only); partial p_k . q
+//   (or spmv_dot  q = A p_k with partial p_k . q)
+//   cg_alpha      alpha_k = rho_k / p_k.q
+//   cg_update     x += alpha p_k; r -= alpha q; z = D^-1 r (stored for
+//                 cg_spmv); partials r.z, z.z
+//   cg_beta       stopping test of ||z_{k+1}|| (< atol, < rtol * ref, or at
+//                 the floor); beta_{k+1} = rho_{k+1} / rho_k
+//   (cg_direction p_{k+1} = z_{k+1} + beta_{k+1} p_k, with spmv_dot)
 //   epilogue      activation / repolarisation times, non-finite check
 //
 // Matrix traversal: sliced ELL (see mdx_internal.h); one lane per row, so the
-// j-th column/value loads of a wavefront are contiguous.  Each workgroup owns
-// a contiguous run of 256-row tiles, and workgroups are remapped so that each
-// of the 8 XCDs owns a contiguous eighth of the rows: the x-gathers of
-// neighbouring rows (RCM keeps them within the bandwidth) then hit that XCD's
-// own L2.
+// j-th column/value loads of a wavefront are contiguous; a row's loads are
+// all issued before its gathers (sell_row).  The SpMV kernels run one 256-row
+// tile per workgroup by default: many short-lived workgroups hide the
+// gathers' latency.  Workgroups are remapped so that each of the 8 XCDs owns
+// a contiguous eighth of the rows: the x-gathers of neighbouring rows (RCM
+// keeps them within the bandwidth) then hit that XCD's own L2.
 //
-// Reductions: wavefront butterfly (shfl_xor) -> LDS across the 4 wavefronts
-// -> one partial per workgroup.  Consumers re-reduce all partials in a fixed
-// order in every workgroup, so scalars are bitwise identical everywhere and
+// Reductions: wavefront butterfly (shfl_xor) -> LDS across the wavefronts
+// -> one partial per workgroup; a single-workgroup finalize kernel sums the
+// partials in a fixed order and writes the scalar the next kernel reads, so
 // runs are deterministic; no atomics, no grid-wide synchronisation.
 #include "mdx_device.h"
 #include "mdx_internal.h"
@@ -172,7 +174,6 @@ __global__ __launch_bounds__(256) void k_init_finalize(int groups, const double 
         sc->done = (!finite || z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
         sc->iters = 0;
         sc->replace = 0;
-        sc->restart_it = 0;
         sc->beta = 0.0;
         sc->it_next = 0;
     }
@@ -193,90 +194,51 @@ __global__ __launch_bounds__(256) void k_spmv_dot(Tiling t, const int64_t *__res
     double acc[1] = {0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
-        const int32_t cb = slice_base(col, sl);
-        double sum = 0.0;
-#pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(Av + e) * p[cb + (int32_t)ld_stream<NT>(col.idx + e)];
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = slice_ptr[sl];
+        const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
+        const double pi = p[row];
+        const double sum =
+            sell_row<NT, double>(w, col.idx + b0 + lane, Av + b0 + lane, p, slice_base(col, sl));
         q[row] = sum;
-        acc[0] += p[row] * sum;
+        acc[0] += pi * sum;
     }
     write_partials<1>(acc, partial, t.groups, g);
 }
 
-// Iteration k, first half.  For k >= 1 every workgroup reduces the r.z and
-// z.z partials of the previous update, applies the stopping test to
-// ||z_k|| (Algorithm 1, with z formed before the test), and forms
-// beta_k = rho_k / rho_{k-1}.  Then, A being linear,
+// Iteration k, SpMV half of the two-kernel scheme: beta_k from the
+// scalars, then, A being linear,
 //   q = A p_k = A z_k + beta_k q_{k-1},   p_k = z_k + beta_k p_{k-1}:
-// the gathers read z_k only (for k = 0, z_0 = D^-1 r_0 formed per gathered
-// column), own rows update p and q in place; partial p_k . q.
-// k == max_iter only tests.
+// the gathers read z_k only (z_0 written by the pass that forms r_0), own
+// rows update p and q in place; beta_0 = 0 takes p = z, q = A z without
+// reading the earlier p, q; partial p_k . q.
 template <bool NT, typename CI>
-__global__ __launch_bounds__(256) void k_cg_spmv(
-    Tiling t, int k, int max_iter, const int64_t *__restrict__ slice_ptr,
-    Cols<CI> col, const double *__restrict__ Av,
-    const double *__restrict__ dinv, const double *__restrict__ r,
-    const double *__restrict__ z, double *__restrict__ p, double *__restrict__ q,
-    const double *__restrict__ partial_rz, double *__restrict__ partial_pq,
-    Scalars *__restrict__ sc)
+__global__ __launch_bounds__(256) void k_cg_spmv(Tiling t, const int64_t *__restrict__ slice_ptr,
+                                                 Cols<CI> col, const double *__restrict__ Av,
+                                                 const double *__restrict__ z,
+                                                 double *__restrict__ p, double *__restrict__ q,
+                                                 double *__restrict__ partial_pq,
+                                                 const Scalars *__restrict__ sc)
 {
     if (sc->done) return;
-    double beta = 0.0;
-    if (k > 0) {
-        double v[2];
-        reduce_partials<2>(partial_rz, t.groups, v);
-        const double zn = sqrt(v[1]);
-        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-        if (!isfinite(zn)) {   // NaN or overflow: stop the solve and flag it
-            if (lead) {
-                sc->nonfinite = 2;
-                sc->done = 1;
-                sc->iters = k;
-                sc->znorm = zn;
-            }
-            return;
-        }
-        if (zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_) {
-            if (lead) {
-                sc->done = 1;
-                sc->iters = k;
-                sc->znorm = zn;
-            }
-            return;
-        }
-        if (lead) sc->znorm = zn;
-        if (k >= max_iter) return;   // cap reached: the host reports no convergence
-        beta = v[0] / sc->rho[(k - 1) & 1];
-        if (lead) sc->rho[k & 1] = v[0];
-    }
+    const double beta = sc->beta;
+    const bool fresh = beta == 0.0;
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
     double acc[1] = {0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
-        const int32_t cb = slice_base(col, sl);
-        double sum = 0.0, pi, qi;
-        if (k == 0) {
-#pragma unroll 4
-            for (int64_t e = beg; e < end; e += SLICE) {
-                const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
-                sum += ld_stream<NT>(Av + e) * (dinv[c] * r[c]);
-            }
-            pi = dinv[row] * r[row];
-            qi = sum;
-        } else {
-#pragma unroll 4
-            for (int64_t e = beg; e < end; e += SLICE)
-                sum += ld_stream<NT>(Av + e) * z[cb + (int32_t)ld_stream<NT>(col.idx + e)];
-            pi = z[row] + beta * p[row];
-            qi = sum + beta * q[row];
-        }
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = slice_ptr[sl];
+        const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
+        const double zi = z[row];
+        const double pold = fresh ? 0.0 : p[row], qold = fresh ? 0.0 : q[row];
+        const double sum =
+            sell_row<NT, double>(w, col.idx + b0 + lane, Av + b0 + lane, z, slice_base(col, sl));
+        const double pi = fresh ? zi : zi + beta * pold;
+        const double qi = fresh ? sum : sum + beta * qold;
         p[row] = pi;
         q[row] = qi;
         acc[0] += pi * qi;
@@ -284,23 +246,29 @@ __global__ __launch_bounds__(256) void k_cg_spmv(
     write_partials<1>(acc, partial_pq, t.groups, g);
 }
 
-// Iteration k, second half: alpha_k = rho_k / (p_k . q); x += alpha p_k;
-// r -= alpha q; z = D^-1 r (stored when z is given); partials r.z and z.z
-// for the next test.
-__global__ __launch_bounds__(256) void k_cg_update(Tiling t, int k,
-                                                   const double *__restrict__ partial_pq,
-                                                   const double *__restrict__ dinv,
+// Iteration k: alpha_k = rho_k / (p_k . q) from the SpMV's partials.
+__global__ __launch_bounds__(FIN) void k_cg_alpha(int groups, int k,
+                                                  const double *__restrict__ partial_pq,
+                                                  Scalars *__restrict__ sc)
+{
+    if (sc->done) return;
+    double pq[1];
+    finalize_partials<1>(partial_pq, groups, pq);
+    if (threadIdx.x == 0) sc->alpha = sc->rho[k & 1] / pq[0];
+}
+
+// Iteration k, update half: x += alpha_k p_k; r -= alpha_k q; z = D^-1 r
+// (stored when z is given); partials r.z and z.z for the next test.
+__global__ __launch_bounds__(256) void k_cg_update(Tiling t, const double *__restrict__ dinv,
                                                    const double *__restrict__ p,
                                                    const double *__restrict__ q,
                                                    double *__restrict__ x, double *__restrict__ r,
                                                    double *__restrict__ z,
                                                    double *__restrict__ partial_rz,
-                                                   Scalars *__restrict__ sc)
+                                                   const Scalars *__restrict__ sc)
 {
     if (sc->done) return;
-    double pq[1];
-    reduce_partials<1>(partial_pq, t.groups, pq);
-    const double alpha = sc->rho[k & 1] / pq[0];
+    const double alpha = sc->alpha;
     const int g = logical_group(t.groups);
     double acc[2] = {0.0, 0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
@@ -317,43 +285,45 @@ __global__ __launch_bounds__(256) void k_cg_update(Tiling t, int k,
     write_partials<2>(acc, partial_rz, t.groups, g);
 }
 
-// Three-kernel scheme, last kernel of iteration k: stopping test on
-// ||z_{k+1}||, beta = rho_{k+1} / rho_k, p = z + beta p in place (p and the
-// SpMV input are the same buffer).  Used with k_spmv_dot + k_cg_update.
-__global__ __launch_bounds__(256) void k_cg_direction(Tiling t, int k,
-                                                      const double *__restrict__ partial_rz,
-                                                      const double *__restrict__ dinv,
-                                                      const double *__restrict__ r,
-                                                      double *__restrict__ p,
-                                                      Scalars *__restrict__ sc)
+// After iteration k's update (k1 = k + 1): Algorithm 1's stopping test on
+// ||z_k1|| (the solve ends after k1 iterations), else beta_k1 =
+// rho_k1 / rho_k.  At k1 == max_iter it only tests: the cap is reached and the
+// host reports no convergence.
+__global__ __launch_bounds__(FIN) void k_cg_beta(int groups, int k1, int max_iter,
+                                                 const double *__restrict__ partial_rz,
+                                                 Scalars *__restrict__ sc)
 {
     if (sc->done) return;
     double v[2];
-    reduce_partials<2>(partial_rz, t.groups, v);
+    finalize_partials<2>(partial_rz, groups, v);
+    if (threadIdx.x != 0) return;
     const double zn = sqrt(v[1]);
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (!isfinite(zn)) {
-        if (lead) {
-            sc->nonfinite = 2;
-            sc->done = 1;
-            sc->iters = k + 1;
-            sc->znorm = zn;
-        }
+    sc->znorm = zn;
+    if (!isfinite(zn)) {   // NaN or overflow: stop the solve and flag it
+        sc->nonfinite = 2;
+        sc->done = 1;
+        sc->iters = k1;
         return;
     }
     if (zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_) {
-        if (lead) {
-            sc->done = 1;
-            sc->iters = k + 1;
-            sc->znorm = zn;
-        }
+        sc->done = 1;
+        sc->iters = k1;
         return;
     }
-    const double beta = v[0] / sc->rho[k & 1];
-    if (lead) {
-        sc->rho[(k + 1) & 1] = v[0];
-        sc->znorm = zn;
-    }
+    if (k1 >= max_iter) return;
+    sc->beta = v[0] / sc->rho[(k1 - 1) & 1];
+    sc->rho[k1 & 1] = v[0];
+}
+
+// Three-kernel scheme, last kernel of iteration k: p = z + beta p in place
+// (p and the SpMV input are the same buffer), z = D^-1 r formed here.
+__global__ __launch_bounds__(256) void k_cg_direction(Tiling t, const double *__restrict__ dinv,
+                                                      const double *__restrict__ r,
+                                                      double *__restrict__ p,
+                                                      const Scalars *__restrict__ sc)
+{
+    if (sc->done) return;
+    const double beta = sc->beta;
     const int g = logical_group(t.groups);
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
@@ -454,29 +424,25 @@ void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *A
                        P.slice_ptr, cols, Av, p, q, partial, done);
 }
 
-void launch_cg_spmv(hipStream_t s, const Tiling &t, int k, int max_iter, SellView P,
-                    const double *Av, const double *dinv, const double *r, const double *z,
-                    double *p, double *q, const double *partial_rz, double *partial_pq,
-                    Scalars *sc, hipEvent_t ev_start, hipEvent_t ev_stop, bool nt)
+void launch_cg_iteration(hipStream_t s, const Tiling &ts, const Tiling &t, int k, int max_iter,
+                         int scheme, SellView P, const double *Av, const double *dinv, double *r,
+                         double *z, double *p, double *q, double *x, double *partial_pq,
+                         double *partial_rz, Scalars *sc, hipEvent_t ev_start, hipEvent_t ev_stop,
+                         bool nt)
 {
-    MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_cg_spmv, dim3(t.groups), dim3(TILE), 0, s, t, k,
-                       max_iter, P.slice_ptr, cols, Av, dinv, r, z, p, q, partial_rz, partial_pq,
+    if (scheme == 1)
+        MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_cg_spmv, dim3(ts.groups), dim3(TILE), 0, s,
+                           ts, P.slice_ptr, cols, Av, z, p, q, partial_pq, sc);
+    else
+        MDX_LAUNCH_SELL_EV(P, nt, ev_start, ev_stop, k_spmv_dot, dim3(ts.groups), dim3(TILE), 0, s,
+                           ts, P.slice_ptr, cols, Av, p, q, partial_pq, &sc->done);
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(FIN), 0, s, ts.groups, k, partial_pq, sc);
+    hipLaunchKernelGGL(k_cg_update, dim3(t.groups), dim3(TILE), 0, s, t, dinv, p, q, x, r,
+                       scheme == 1 ? z : nullptr, partial_rz, sc);
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(FIN), 0, s, t.groups, k + 1, max_iter, partial_rz,
                        sc);
-}
-
-void launch_cg_update(hipStream_t s, const Tiling &t, int k, const double *partial_pq,
-                      const double *dinv, const double *p, const double *q, double *x, double *r,
-                      double *z, double *partial_rz, Scalars *sc)
-{
-    hipLaunchKernelGGL(k_cg_update, dim3(t.groups), dim3(TILE), 0, s, t, k, partial_pq, dinv, p, q,
-                       x, r, z, partial_rz, sc);
-}
-
-void launch_cg_direction(hipStream_t s, const Tiling &t, int k, const double *partial_rz,
-                         const double *dinv, const double *r, double *p, Scalars *sc)
-{
-    hipLaunchKernelGGL(k_cg_direction, dim3(t.groups), dim3(TILE), 0, s, t, k, partial_rz, dinv, r,
-                       p, sc);
+    if (scheme != 1)
+        hipLaunchKernelGGL(k_cg_direction, dim3(t.groups), dim3(TILE), 0, s, t, dinv, r, p, sc);
 }
 
 void launch_set_direction(hipStream_t s, int64_t n, const double *dinv, const double *r, double *p,
