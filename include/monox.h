@@ -401,6 +401,23 @@ MDX_API size_t mdx_mlp_grad_scratch(int64_t n);
 MDX_API mdx_status mdx_mlp_grad(mdx_ctx *ctx, const float *params, int64_t n, const float *X,
                                 const float *T, float *grad, float *loss, void *scratch,
                                 size_t scratch_bytes);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc):
+ * the gradient and loss of mdx_mlp_grad with no scratch argument.  The
+ * per-workgroup partials live in a file-scope device array of the library,
+ * 256 workgroups x (MDX_MLP_NPARAM + 1) floats = 8.9 MB, held by every device
+ * the library runs on until the process ends; its address is resolved per
+ * device at mdx_create.  Any n in [1, 2^31 - 1] fits (each workgroup takes
+ * ceil(n / 8192) tiles of 32 samples); a larger n is rejected with
+ * MDX_ERR_INVALID_ARG.  For n <= 8192 the samples are partitioned as in
+ * mdx_mlp_grad and the results are bitwise the same; above, they differ by
+ * the FP32 summation order of the partials.  Allocates nothing and calls no
+ * allocating routine.  All calls on one device share its array (each call
+ * overwrites it): calls queued on one stream are safe, calls that overlap on
+ * one GPU (other streams or contexts) race. */
+MDX_API mdx_status mdx_mlp_grad_noalloc(mdx_ctx *ctx, const float *params, int64_t n,
+                                        const float *X, const float *T, float *grad,
+                                        float *loss);
 /* one Adam step (Kingma & Ba) on params with moments m, v; t >= 1 */
 MDX_API mdx_status mdx_mlp_adam(mdx_ctx *ctx, float *params, float *m, float *v, const float *grad,
                                 int32_t t, double lr, double beta1, double beta2, double eps);

@@ -116,6 +116,7 @@ _SIGS = {
     "mdx_mlp_forward": (C.c_int, [P, P, C.c_int64, P, P]),
     "mdx_mlp_grad_scratch": (C.c_size_t, [C.c_int64]),
     "mdx_mlp_grad": (C.c_int, [P, P, C.c_int64, P, P, P, P, P, C.c_size_t]),
+    "mdx_mlp_grad_noalloc": (C.c_int, [P, P, C.c_int64, P, P, P, P]),
     "mdx_mlp_adam": (C.c_int, [P, P, P, P, P, C.c_int32, C.c_double, C.c_double, C.c_double,
                                C.c_double]),
 }

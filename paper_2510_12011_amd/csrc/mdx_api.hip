@@ -100,6 +100,7 @@ struct mdx_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     Layout L{};
+    float *grad_scratch = nullptr;   // library-owned partials of mdx_mlp_grad_noalloc
     Tiling tiling{};        // vector and right-hand-side kernels
     Tiling tiling_spmv{};   // the PCG iteration's SpMV kernel
     bool prepared = false;
@@ -1271,6 +1272,9 @@ mdx_status mdx_create(mdx_ctx **out, int device, void *stream)
         return MDX_ERR_DEVICE;
     }
     ctx->pub->seq = 0;
+    // device address of the allocation-free gradient's partials (resolved
+    // once per device, with the device current)
+    ctx->grad_scratch = mlp_noalloc_scratch(device);
     *out = ctx;
     return MDX_OK;
 }
@@ -2352,7 +2356,25 @@ mdx_status mdx_mlp_grad(mdx_ctx *ctx, const float *params, int64_t n, const floa
         return fail(ctx, MDX_ERR_NO_WORKSPACE, "scratch of %zu bytes required",
                     mlp_grad_scratch_bytes(n));
     HIPCHK(hipSetDevice(ctx->device));
-    launch_mlp_grad(ctx->stream, params, n, X, T, grad, loss, (float *)scratch);
+    launch_mlp_grad(ctx->stream, params, n, X, T, grad, loss, (float *)scratch, kGradGroups);
+    HIPCHK(hipGetLastError());
+    return MDX_OK;
+}
+
+mdx_status mdx_mlp_grad_noalloc(mdx_ctx *ctx, const float *params, int64_t n, const float *X,
+                                const float *T, float *grad, float *loss)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
+    if (n <= 0 || !params || !X || !T || !grad || ((uintptr_t)X % 16) != 0)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "null or misaligned device array, or n <= 0");
+    if (n > (int64_t)INT32_MAX)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "n = %lld exceeds the maximum 2^31 - 1 samples",
+                    (long long)n);
+    if (!ctx->grad_scratch)
+        return fail(ctx, MDX_ERR_DEVICE, "the library's gradient partials were not resolved");
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_mlp_grad(ctx->stream, params, n, X, T, grad, loss, ctx->grad_scratch, kNoAllocGroups);
     HIPCHK(hipGetLastError());
     return MDX_OK;
 }

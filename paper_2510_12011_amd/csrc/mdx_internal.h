@@ -182,15 +182,22 @@ void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter
 
 // ---- learned warm start network (mdx_mlp.hip) ------------------------------
 int mlp_nparams();
-int mlp_grad_groups(int64_t n);
+// gradient partials: one row of NPARAM + 1 floats per workgroup, at most
+// kGradGroups (caller's scratch) or kNoAllocGroups (the library's array)
+constexpr int kGradGroups = 2048;
+constexpr int kNoAllocGroups = 256;
+int mlp_grad_groups(int64_t n, int max_groups);
 size_t mlp_grad_scratch_bytes(int64_t n);
+// device address of the library's partials array on `device`, which must be
+// current; resolved on the first call per device (null if that fails)
+float *mlp_noalloc_scratch(int device);
 void launch_mlp_forward(hipStream_t s, const float *P, int64_t n, const float *X, float *y);
 // the same with the features formed from the state (no feature pass)
 void launch_mlp_forward_state(hipStream_t s, const float *P, int64_t n, const double *V,
                               const double *Vprev, const double *src, const float *kvp, double cm,
                               const MlpNorm &nm, float *y);
 void launch_mlp_grad(hipStream_t s, const float *P, int64_t n, const float *X, const float *T,
-                     float *grad, float *loss, float *partials);
+                     float *grad, float *loss, float *partials, int max_groups);
 void launch_adam(hipStream_t s, float *P, float *m, float *v, const float *g, int t, double lr,
                  double b1, double b2, double eps);
 

@@ -23,6 +23,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 namespace mdx {
 
@@ -626,16 +628,40 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ P, float *__re
 
 int mlp_nparams() { return NPARAM; }
 
-int mlp_grad_groups(int64_t n)
+int mlp_grad_groups(int64_t n, int max_groups)
 {
     const int64_t tiles = (n + 31) / 32;
-    const int64_t tpg = std::max<int64_t>(1, (tiles + 2047) / 2048);
+    const int64_t tpg = std::max<int64_t>(1, (tiles + max_groups - 1) / max_groups);
     return (int)((tiles + tpg - 1) / tpg);
 }
 
 size_t mlp_grad_scratch_bytes(int64_t n)
 {
-    return sizeof(float) * (size_t)(NPARAM + 1) * (size_t)mlp_grad_groups(n);
+    return sizeof(float) * (size_t)(NPARAM + 1) * (size_t)mlp_grad_groups(n, kGradGroups);
+}
+
+// Partials of the allocation-free gradient entry point: at most
+// kNoAllocGroups workgroups of NPARAM + 1 floats (8.9 MB).  Every device the
+// library runs on holds its own copy until the process ends; host code never
+// names this array directly (its host-side symbol is not a device address)
+// but only the address that mlp_noalloc_scratch resolves per device.
+static __device__ __align__(256) float scratch[(size_t)kNoAllocGroups * (NPARAM + 1)];
+
+float *mlp_noalloc_scratch(int device)
+{
+    static std::mutex mu;
+    static std::vector<float *> table;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) return nullptr;
+    if ((size_t)device >= table.size()) table.resize((size_t)device + 1, nullptr);
+    if (!table[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != device) return nullptr;
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        table[device] = static_cast<float *>(ptr);
+    }
+    return table[device];
 }
 
 // inference grid: 144 registers per lane leave three wavefronts per SIMD,
@@ -664,10 +690,10 @@ void launch_mlp_forward_state(hipStream_t s, const float *P, int64_t n, const do
 }
 
 void launch_mlp_grad(hipStream_t s, const float *P, int64_t n, const float *X, const float *T,
-                     float *grad, float *loss, float *partials)
+                     float *grad, float *loss, float *partials, int max_groups)
 {
     const int64_t tiles = (n + 31) / 32;
-    const int groups = mlp_grad_groups(n);
+    const int groups = mlp_grad_groups(n, max_groups);
     const int tpg = (int)((tiles + groups - 1) / groups);
     hipLaunchKernelGGL(k_mlp_grad, dim3(groups), dim3(64), 0, s, P, n, X, T, tpg, partials);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, s, groups,
