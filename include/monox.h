@@ -65,8 +65,9 @@ typedef struct mdx_ctx mdx_ctx;
  * ten Tusscher-Panfilov 2006 (endocardial) */
 enum { MDX_IONIC_NONE = 0, MDX_IONIC_MS = 1, MDX_IONIC_TT = 2 };
 /* PCG warm start: previous step V^k, extrapolation 2V^k - V^{k-1} (paper),
- * or the learned per-node network (see mdx_set_mlp), which falls back to
- * V^k whenever its initial residual is not the smaller of the two */
+ * or the learned per-node network (see mdx_set_mlp), which corrects the
+ * extrapolation and falls back to it whenever its initial residual is not
+ * the smaller of the two */
 enum { MDX_WS_PREV = 0, MDX_WS_EXTRAP = 1, MDX_WS_MLP = 2 };
 /* relative stopping test: ||z|| / ||z_0|| (paper) or ||z|| / ||D^-1 b|| */
 enum { MDX_REL_INITIAL = 0, MDX_REL_RHS = 1 };
@@ -427,17 +428,22 @@ MDX_API mdx_status mdx_mlp_adam(mdx_ctx *ctx, float *params, float *m, float *v,
  * norm: HOST [9] = feature means (4), feature standard deviations (4),
  * output scale.  Features of node i at step n: V^n, V^n - V^{n-1},
  * (I_stim - I_ion)/Cm (mV/ms), (K V^{n-1})_i / K_ii (the neighbour aggregate
- * of the previous step's right-hand side); guess x0 = V^n + scale y,
- * used when its initial residual ||D^-1 r0|| is below that of x0 = V^n.
- * Requires a prepared context; the network lives in the workspace. */
+ * of the previous step's right-hand side).  The network predicts the
+ * departure from the paper's extrapolation: guess x0 = 2V^n - V^{n-1} +
+ * scale y, used when its initial residual ||D^-1 r0|| is below that of the
+ * extrapolation itself (the fallback; a network with zero output is the
+ * paper's warm start).  Requires a prepared context; the network lives in
+ * the workspace. */
 MDX_API mdx_status mdx_set_mlp(mdx_ctx *ctx, const float *params, const double *norm);
 /* Training-data recorder: when non-NULL, every step of mdx_run writes the
  * raw features of node i (internal node order, i < n_nodes) to X[i][0..3]
  * and, after the solve, V^{n+1}_i - V^n_i to dV[i] (DEVICE arrays of
- * n_nodes float4 / float, overwritten each step).  The permutation from
- * internal to original order is node_order[i] (mdx_get_node_order).  Pass
- * NULLs to stop recording. */
-MDX_API mdx_status mdx_set_recorder(mdx_ctx *ctx, float *X, float *dV);
+ * n_nodes float4 / float, overwritten each step); y (DEVICE, n_nodes floats,
+ * may be NULL; needs X and dV) receives the network's output of the step
+ * when the warm start is MDX_WS_MLP.  The permutation from internal to
+ * original order is node_order[i] (mdx_get_node_order).  Pass NULLs to stop
+ * recording. */
+MDX_API mdx_status mdx_set_recorder(mdx_ctx *ctx, float *X, float *dV, float *y);
 /* original node id of internal row i, i < n_nodes (host array) */
 MDX_API mdx_status mdx_get_node_order(mdx_ctx *ctx, int32_t *order);
 

@@ -2,9 +2,10 @@
 (tests, smoke check, benchmark CPU baseline).
 
 A per-node multilayer perceptron 4 -> 64 -> 64 -> 64 -> 1 with ReLU
-activations predicts the normalised increment V^{n+1} - V^n of the
-monodomain step from node-local features; it is trained by mean-squared
-error with Adam (Kingma & Ba, ICLR 2015).  Plain FP64 numpy: forward pass,
+activations maps node-local features of the monodomain step to one
+normalised output (the learned warm start uses it as the departure of
+V^{n+1} from the extrapolation 2V^n - V^{n-1}); it is trained by
+mean-squared error with Adam (Kingma & Ba, ICLR 2015).  Plain FP64 numpy: forward pass,
 hand-written backward pass (chain rule, no autograd), Adam.  Pinned in the
 CPU tests against central finite differences and hand-computed Adam steps.
 

@@ -111,7 +111,7 @@ _SIGS = {
     "mdx_ionic_step": (C.c_int, [P, C.c_double, C.c_int64, P, P, P]),
     "mdx_mlp_nparams": (C.c_int32, []),
     "mdx_set_mlp": (C.c_int, [P, P, P]),
-    "mdx_set_recorder": (C.c_int, [P, P, P]),
+    "mdx_set_recorder": (C.c_int, [P, P, P, P]),
     "mdx_get_node_order": (C.c_int, [P, P]),
     "mdx_mlp_forward": (C.c_int, [P, P, C.c_int64, P, P]),
     "mdx_mlp_grad_scratch": (C.c_size_t, [C.c_int64]),

@@ -120,6 +120,7 @@ struct mdx_ctx {
     bool mlp_set = false;
     MlpNorm mlp_norm{{0.f, 0.f, 0.f, 0.f}, {1.f, 1.f, 1.f, 1.f}, 0.f};
     float *rec_X = nullptr, *rec_dV = nullptr;   // training-data recorder
+    float *rec_y = nullptr;                      // and the network's in-step output
     bool kvp_valid = false;   // kvp holds (K V^{n-1})_i / K_ii of the current state
 
     // launch-shape tuning
@@ -1692,7 +1693,7 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
     ctx->stats = mdx_stats{};
     ctx->prepared = true;
     ctx->mlp_set = false;
-    ctx->rec_X = ctx->rec_dV = nullptr;
+    ctx->rec_X = ctx->rec_dV = ctx->rec_y = nullptr;
     return MDX_OK;
     GUARD_END
 }
@@ -1777,20 +1778,24 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         const bool want_kvp = learned || ctx->rec_X;
         if (want_kvp && !ctx->kvp_valid) launch_kv_feature(st, T, P, Kv, kdiag, Vprev, kvp);
         if (learned) {
-            // padding rows keep y = 0
-            if (ctx->rec_X) {   // the recorder also wants the raw features
-                launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm, feat,
-                                ctx->rec_X);
-                launch_mlp_forward(st, mlp_params, ctx->n, feat, mlp_y);
-            } else {
-                launch_mlp_forward_state(st, mlp_params, ctx->n, V, Vprev, s, kvp, ctx->cm,
-                                         ctx->mlp_norm, mlp_y);
-            }
-            launch_rhs_learned(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm.out_scale, V, s,
-                               mlp_y, b, X, r, q, kvp, mixed ? 1 : 0, part_pq, part0, nt_rhs);
+            // the network forms its features from the state (padding rows
+            // keep y = 0); the recorder also takes the raw features and y
+            if (ctx->rec_X)
+                launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm,
+                                nullptr, ctx->rec_X);
+            launch_mlp_forward_state(st, mlp_params, ctx->n, V, Vprev, s, kvp, ctx->cm,
+                                     ctx->mlp_norm, mlp_y);
+            if (ctx->rec_y)
+                HIPCHK(hipMemcpyAsync(ctx->rec_y, mlp_y, sizeof(float) * ctx->n,
+                                      hipMemcpyDeviceToDevice, st));
+            // r_ex (the extrapolation's residual) goes to the FP64 q buffer,
+            // free until the iteration starts
+            launch_rhs_learned(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm.out_scale, V,
+                               Vprev, s, mlp_y, b, X, r, q, kvp, mixed ? 1 : 0, part_pq, part0,
+                               nt_rhs);
             launch_init_finalize_ws(st, T, part_pq, part0, sp.rel_mode, sc);
-            launch_select(st, ctx->npad, V, q, X, r, dinv, p0_fp64, dinv32, mixed ? r32 : nullptr,
-                          z32, delta, sc);
+            launch_select(st, ctx->npad, V, Vprev, q, X, r, dinv, p0_fp64, dinv32,
+                          mixed ? r32 : nullptr, z32, delta, sc);
         } else {
             if (ctx->rec_X)   // training-data recorder: raw features
                 launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm,
@@ -2417,15 +2422,17 @@ mdx_status mdx_set_mlp(mdx_ctx *ctx, const float *params, const double *norm)
     return MDX_OK;
 }
 
-mdx_status mdx_set_recorder(mdx_ctx *ctx, float *X, float *dV)
+mdx_status mdx_set_recorder(mdx_ctx *ctx, float *X, float *dV, float *y)
 {
     if (!ctx) return MDX_ERR_INVALID_ARG;
     if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "not prepared");
     if ((X == nullptr) != (dV == nullptr))
         return fail(ctx, MDX_ERR_INVALID_ARG, "set both recorder arrays or neither");
+    if (y && !X) return fail(ctx, MDX_ERR_INVALID_ARG, "y is recorded only with X and dV");
     if (X && ((uintptr_t)X % 16) != 0) return fail(ctx, MDX_ERR_INVALID_ARG, "X must be 16-byte aligned");
     ctx->rec_X = X;
     ctx->rec_dV = dV;
+    ctx->rec_y = y;
     return MDX_OK;
 }
 

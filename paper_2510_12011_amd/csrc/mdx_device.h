@@ -178,6 +178,50 @@ __device__ __forceinline__ ACC sell_row(int w, const CI *__restrict__ c, const T
     }
 }
 
+// A row of two matrices sharing the pattern (M and K values at a0, a1):
+// f(column, m, k) is applied to its entries in column order, in chunks of
+// up to C entries whose column and value loads are all issued before the
+// chunk's first gather (f does the gathers).
+template <int W, bool NT, typename CI, typename F>
+__device__ __forceinline__ void sell_chunk2(const CI *__restrict__ c, const double *__restrict__ a0,
+                                            const double *__restrict__ a1, int32_t cb, F &f)
+{
+    CI cc[W];
+    double m[W], k[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        cc[j] = ld_stream<NT>(c + j * SLICE);
+        m[j] = ld_stream<NT>(a0 + j * SLICE);
+        k[j] = ld_stream<NT>(a1 + j * SLICE);
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) f(cb + (int32_t)cc[j], m[j], k[j]);
+}
+
+template <int C, bool NT, typename CI, typename F>
+__device__ __forceinline__ void sell_row2(int w, const CI *__restrict__ c,
+                                          const double *__restrict__ a0,
+                                          const double *__restrict__ a1, int32_t cb, F &&f)
+{
+    static_assert(C == 8, "remainder cases below cover chunks of 8");
+    int j = 0;
+    for (; j + C <= w; j += C)
+        sell_chunk2<C, NT>(c + j * SLICE, a0 + j * SLICE, a1 + j * SLICE, cb, f);
+    c += j * SLICE;
+    a0 += j * SLICE;
+    a1 += j * SLICE;
+    switch (w - j) {
+    case 1: sell_chunk2<1, NT>(c, a0, a1, cb, f); break;
+    case 2: sell_chunk2<2, NT>(c, a0, a1, cb, f); break;
+    case 3: sell_chunk2<3, NT>(c, a0, a1, cb, f); break;
+    case 4: sell_chunk2<4, NT>(c, a0, a1, cb, f); break;
+    case 5: sell_chunk2<5, NT>(c, a0, a1, cb, f); break;
+    case 6: sell_chunk2<6, NT>(c, a0, a1, cb, f); break;
+    case 7: sell_chunk2<7, NT>(c, a0, a1, cb, f); break;
+    default: break;
+    }
+}
+
 // Slice handled by wavefront `wv` (0..3) of tile `tile`, as a scalar: its
 // header loads then go through the scalar cache.
 __device__ __forceinline__ int64_t wave_slice(int tile)

@@ -212,21 +212,24 @@ void launch_kv_feature(hipStream_t s, const Tiling &t, SellView P, const double 
 void launch_features(hipStream_t s, int64_t n_real, int64_t n_rows, const double *V,
                      const double *Vprev, const double *src, const float *kvp, double cm,
                      const MlpNorm &nm, float *feat, float *raw);
-// one pass over M and K: b, x_mlp = V + scale y, r_mlp = b - A x_mlp (into
-// r_mlp), r_prev = b - A V (into r_prev), kvp = (K V)_i / K_ii for the next
-// step; partials r.z, z.z of both (FP32-rounded first if fp32_iter) into
-// part4 and |D^-1 b|^2 into part1
+// one pass over M and K: b, x_mlp = 2V - V_prev + scale y, r_mlp = b - A x_mlp
+// (into r_mlp), r_ex = b - A (2V - V_prev) (into r_ex), kvp = (K V)_i / K_ii
+// for the next step; partials r.z, z.z of both (FP32-rounded first if
+// fp32_iter) into part4 and |D^-1 b|^2 into part1
 void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                         const double *Kv, const double *kdiag, const double *dinv,
                         const StepParams &sp, float out_scale, const double *V,
-                        const double *src, const float *y, double *b, double *x, double *r_mlp,
-                        double *r_prev, float *kvp, int fp32_iter, double *part4, double *part1,
-                        bool nt);
+                        const double *Vprev, const double *src, const float *y, double *b,
+                        double *x, double *r_mlp, double *r_ex, float *kvp, int fp32_iter,
+                        double *part4, double *part1, bool nt);
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
                              int rel_mode, Scalars *sc);
-void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
-                   double *r, const double *dinv, double *p0, const float *dinv32, float *r32,
-                   float *z32, float *delta, const Scalars *sc);
+// the chosen guess: the extrapolation's x and r where the network's residual
+// was not the smaller; p0 = z0 (FP64 iteration) or the FP32 residual, z and
+// correction
+void launch_select(hipStream_t s, int64_t n, const double *V, const double *Vprev,
+                   const double *r_ex, double *x, double *r, const double *dinv, double *p0,
+                   const float *dinv32, float *r32, float *z32, float *delta, const Scalars *sc);
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv);
 
 // ---- batched form (mdx_batch.hip) -----------------------------------------

@@ -5,12 +5,14 @@
 //   f3 = (K V^{n-1})_i / K_ii  (one neighbour aggregate: the stiffness SpMV
 //        the previous step's right-hand side already formed)
 // are standardised and fed to the per-node MLP (mdx_mlp.hip), whose output
-// y predicts the increment: x_mlp = V^n + out_scale * y.  Because the
+// y predicts the departure of V^{n+1} from the paper's extrapolation:
+// x_mlp = x_ex + out_scale * y, x_ex = 2V^n - V^{n-1}.  Because the
 // aggregate is the previous step's, the network runs before the right-hand
 // side, and one pass over M and K then forms b, the initial residuals of
-// both x_mlp and the previous-step guess V^n, and the next step's
-// aggregate.  The MLP guess is used only if its ||D^-1 r0|| is smaller (and
-// finite), otherwise the previous step is (the fallback).
+// both x_mlp and x_ex, and the next step's aggregate.  The MLP guess is used
+// only if its ||D^-1 r0|| is smaller (and finite), otherwise the
+// extrapolation is (the fallback): the network can only lower the initial
+// residual of the method without it.
 //
 // k_features also serves as the recorder of training data: raw features of
 // every node, and after the solve the increment V^{n+1} - V^n.
@@ -34,12 +36,12 @@ __global__ __launch_bounds__(256) void k_kv_feature(Tiling t, const int64_t *__r
     const int lane = threadIdx.x & (SLICE - 1);
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int32_t cb = slice_base(col, sl);
-        double kv = 0.0;
-        for (int64_t e = slice_ptr[sl] + lane; e < slice_ptr[sl + 1]; e += SLICE)
-            kv += ld_stream<NT>(Kv + e) * v[cb + (int32_t)ld_stream<NT>(col.idx + e)];
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = slice_ptr[sl];
+        const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
+        const double kv =
+            sell_row<NT, double>(w, col.idx + b0 + lane, Kv + b0 + lane, v, slice_base(col, sl));
         const double kd = kdiag[row];
         kvp[row] = kd != 0.0 ? (float)(kv / kd) : 0.0f;
     }
@@ -72,17 +74,20 @@ __global__ __launch_bounds__(256) void k_features(int64_t n_real, int64_t n_rows
     }
 }
 
-// b = chi M (Cm V + dt s) - (1-theta) dt K V;  A V = chi Cm M V + theta dt K V;
-// r_prev = b - A V;  r_mlp = r_prev - scale A y;  x = V + scale y
+// b = chi M (Cm V + dt s) - (1-theta) dt K V;  with e = V - V_prev the
+// extrapolation x_ex = V + e has A x_ex = chi Cm M (V + e) + theta dt K (V + e);
+// r_ex = b - A x_ex;  r_mlp = r_ex - scale A y;  x = x_ex + scale y.
+// Partials: r_mlp.z_mlp, |z_mlp|^2, r_ex.z_ex, |z_ex|^2 (FP32-rounded
+// residuals when the iteration runs in FP32) and |D^-1 b|^2.
 template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_rhs_learned(
     Tiling t, const int64_t *__restrict__ slice_ptr, Cols<CI> col,
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ kdiag,
     const double *__restrict__ dinv, StepParams sp, float out_scale, const double *__restrict__ V,
-    const double *__restrict__ src, const float *__restrict__ y, double *__restrict__ b,
-    double *__restrict__ x, double *__restrict__ r_mlp, double *__restrict__ r_prev,
-    float *__restrict__ kvp, int fp32_iter, double *__restrict__ part4,
-    double *__restrict__ part1)
+    const double *__restrict__ Vprev, const double *__restrict__ src,
+    const float *__restrict__ y, double *__restrict__ b, double *__restrict__ x,
+    double *__restrict__ r_mlp, double *__restrict__ r_ex, float *__restrict__ kvp, int fp32_iter,
+    double *__restrict__ part4, double *__restrict__ part1)
 {
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
@@ -93,44 +98,46 @@ __global__ __launch_bounds__(256) void k_rhs_learned(
     double acc[4] = {0.0, 0.0, 0.0, 0.0}, accb[1] = {0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
-        const int32_t cb = slice_base(col, sl);
-        double mv = 0.0, ms = 0.0, kv = 0.0, my = 0.0, ky = 0.0;
-        for (int64_t e = beg; e < end; e += SLICE) {
-            const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
-            const double m = ld_stream<NT>(Mv + e), kk = ld_stream<NT>(Kv + e);
-            const double vj = V[c], yj = (double)y[c];
-            mv += m * vj;
-            ms += m * src[c];
-            kv += kk * vj;
-            my += m * yj;
-            ky += kk * yj;
-        }
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = slice_ptr[sl];
+        const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
+        double mv = 0.0, ms = 0.0, kv = 0.0, me = 0.0, ke = 0.0, my = 0.0, ky = 0.0;
+        sell_row2<8, NT>(w, col.idx + b0 + lane, Mv + b0 + lane, Kv + b0 + lane,
+                         slice_base(col, sl), [&](int32_t c, double m, double kk) {
+                             const double vj = V[c], ej = vj - Vprev[c], yj = (double)y[c];
+                             mv += m * vj;
+                             ms += m * src[c];
+                             kv += kk * vj;
+                             me += m * ej;
+                             ke += kk * ej;
+                             my += m * yj;
+                             ky += kk * yj;
+                         });
         const double bi = sp.chi * (sp.cm * mv + sp.dt * ms) - cK_old * kv;
-        const double rp = bi - (cM_new * mv + cK_new * kv);
-        const double rm = rp - scale * (cM_new * my + cK_new * ky);
+        const double rx = bi - (cM_new * (mv + me) + cK_new * (kv + ke));
+        const double rm = rx - scale * (cM_new * my + cK_new * ky);
+        const double vi = V[row];
         b[row] = bi;
-        x[row] = V[row] + scale * (double)y[row];
+        x[row] = (2.0 * vi - Vprev[row]) + scale * (double)y[row];
         r_mlp[row] = rm;
-        r_prev[row] = rp;
+        r_ex[row] = rx;
         const double kd = kdiag[row];
         kvp[row] = kd != 0.0 ? (float)(kv / kd) : 0.0f;
         const double di = dinv[row];
         if (fp32_iter) {
-            const float rmf = (float)rm, rpf = (float)rp, df = (float)di;
-            const float zmf = df * rmf, zpf = df * rpf;
+            const float rmf = (float)rm, rxf = (float)rx, df = (float)di;
+            const float zmf = df * rmf, zxf = df * rxf;
             acc[0] += (double)rmf * (double)zmf;
             acc[1] += (double)zmf * (double)zmf;
-            acc[2] += (double)rpf * (double)zpf;
-            acc[3] += (double)zpf * (double)zpf;
+            acc[2] += (double)rxf * (double)zxf;
+            acc[3] += (double)zxf * (double)zxf;
         } else {
-            const double zm = di * rm, zp = di * rp;
+            const double zm = di * rm, zx = di * rx;
             acc[0] += rm * zm;
             acc[1] += zm * zm;
-            acc[2] += rp * zp;
-            acc[3] += zp * zp;
+            acc[2] += rx * zx;
+            acc[3] += zx * zx;
         }
         accb[0] += (di * bi) * (di * bi);
     }
@@ -169,10 +176,11 @@ __global__ __launch_bounds__(256) void k_init_finalize_ws(int groups, const doub
     sc->it_next = 0;
 }
 
-// fallback: r = r_prev, x = V; then the FP32 residual, z = D^-1 r and the
-// correction if the iteration runs in FP32
+// fallback: x = 2V - V_prev, r = r_ex; then the FP32 residual, z = D^-1 r and
+// the correction if the iteration runs in FP32
 __global__ __launch_bounds__(256) void k_select(int64_t n, const double *__restrict__ V,
-                                                const double *__restrict__ r_prev,
+                                                const double *__restrict__ Vprev,
+                                                const double *__restrict__ r_ex,
                                                 double *__restrict__ x, double *__restrict__ r,
                                                 const double *__restrict__ dinv,
                                                 double *__restrict__ p0,
@@ -184,8 +192,8 @@ __global__ __launch_bounds__(256) void k_select(int64_t n, const double *__restr
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (!sc->use_mlp) {
-        x[i] = V[i];
-        r[i] = r_prev[i];
+        x[i] = 2.0 * V[i] - Vprev[i];
+        r[i] = r_ex[i];
     }
     if (p0) p0[i] = dinv[i] * r[i];   // FP64 iteration: the first direction p0 = z0
     if (r32) {
@@ -252,13 +260,13 @@ void launch_features(hipStream_t s, int64_t n_real, int64_t n_rows, const double
 void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                         const double *Kv, const double *kdiag, const double *dinv,
                         const StepParams &sp, float out_scale, const double *V,
-                        const double *src, const float *y, double *b, double *x, double *r_mlp,
-                        double *r_prev, float *kvp, int fp32_iter, double *part4, double *part1,
-                        bool nt)
+                        const double *Vprev, const double *src, const float *y, double *b,
+                        double *x, double *r_mlp, double *r_ex, float *kvp, int fp32_iter,
+                        double *part4, double *part1, bool nt)
 {
     MDX_LAUNCH_SELL(P, nt, k_rhs_learned, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols, Mv,
-                    Kv, kdiag, dinv, sp, out_scale, V, src, y, b, x, r_mlp, r_prev, kvp, fp32_iter,
-                    part4, part1);
+                    Kv, kdiag, dinv, sp, out_scale, V, Vprev, src, y, b, x, r_mlp, r_ex, kvp,
+                    fp32_iter, part4, part1);
 }
 
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
@@ -267,12 +275,12 @@ void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, c
     hipLaunchKernelGGL(k_init_finalize_ws, dim3(1), dim3(TILE), 0, s, t.groups, p4, p1, rel_mode, sc);
 }
 
-void launch_select(hipStream_t s, int64_t n, const double *V, const double *r_prev, double *x,
-                   double *r, const double *dinv, double *p0, const float *dinv32, float *r32,
-                   float *z32, float *delta, const Scalars *sc)
+void launch_select(hipStream_t s, int64_t n, const double *V, const double *Vprev,
+                   const double *r_ex, double *x, double *r, const double *dinv, double *p0,
+                   const float *dinv32, float *r32, float *z32, float *delta, const Scalars *sc)
 {
-    hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(256), 0, s, n, V, r_prev, x, r, dinv,
-                       p0, dinv32, r32, z32, delta, sc);
+    hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(256), 0, s, n, V, Vprev, r_ex, x, r,
+                       dinv, p0, dinv32, r32, z32, delta, sc);
 }
 
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv)

@@ -88,21 +88,20 @@ __global__ __launch_bounds__(256) void k_rhs_init(
     double acc[3] = {0.0, 0.0, 0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
-        const int32_t cb = slice_base(col, sl);
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = slice_ptr[sl];
+        const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
         double mv = 0.0, kv = 0.0, mx = 0.0, kx = 0.0;
-        for (int64_t e = beg; e < end; e += SLICE) {
-            const int32_t c = cb + (int32_t)ld_stream<NT>(col.idx + e);
-            const double m = ld_stream<NT>(Mv + e), kk = ld_stream<NT>(Kv + e);
-            const double vj = V[c];
-            const double x0j = extrap ? 2.0 * vj - Vprev[c] : vj;
-            mv += m * (sp.cm * vj + sp.dt * src[c]);
-            kv += kk * vj;
-            mx += m * x0j;
-            kx += kk * x0j;
-        }
+        sell_row2<8, NT>(w, col.idx + b0 + lane, Mv + b0 + lane, Kv + b0 + lane,
+                         slice_base(col, sl), [&](int32_t c, double m, double kk) {
+                             const double vj = V[c], vpj = Vprev[c];
+                             const double x0j = extrap ? 2.0 * vj - vpj : vj;
+                             mv += m * (sp.cm * vj + sp.dt * src[c]);
+                             kv += kk * vj;
+                             mx += m * x0j;
+                             kx += kk * x0j;
+                         });
         const double bi = sp.chi * mv - cK_old * kv;
         const double ax = cM_new * mx + cK_new * kx;
         const double vi = V[row];

@@ -520,11 +520,23 @@ def _gpu_may_be_live() -> bool:
         return True
 
 
+def cohort_targets(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
+                   n_min: int = 50_000, n_max: int = 400_000) -> np.ndarray:
+    """Node targets of batch_shells' instances (the same draws)."""
+    rng = np.random.default_rng(seed)
+    rng.uniform(0.0, 1.0, (n_inst, 3))
+    rng.uniform(0.0, 1.0, n_inst)
+    n = np.exp(rng.uniform(np.log(n_min), np.log(n_max), n_inst))
+    for _ in range(20):
+        n = np.clip(n * (total_nodes / n.sum()), n_min, n_max)
+    return n
+
+
 def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
                  n_min: int = 50_000, n_max: int = 400_000, n_steps: int = 5000,
                  dt: float = 0.01, ionic: str = "ms", workers: int = 1,
                  axes_mm: tuple = (25.0, 45.0), wall_mm: tuple = (6.0, 12.0),
-                 stim_radius: float = 1.5) -> BatchSpec:
+                 stim_radius: float = 1.5, only=None) -> BatchSpec:
     """A seeded cohort of unstructured ellipsoidal shells: semi-axes
     U(axes_mm) (default 25-45 mm, the longest along z), wall U(wall_mm)
     (default 6-12 mm), node targets log-uniform in [n_min, n_max] rescaled to
@@ -532,7 +544,9 @@ def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
     S/m times U(0.5, 1.5), stimulus 0.5 uA/mm^2 for 2 ms on the nodes within
     stim_radius mm of a random endocardial node; Mitchell-Schaeffer cells,
     chi 140/mm, Cm 0.01 uF/mm^2, theta 0.5, relative tolerance 1e-8 of
-    ||D^-1 b||, mixed precision."""
+    ||D^-1 b||, mixed precision.  only: indices of the instances to mesh and
+    keep (in that order; every draw of the full cohort is still made, so each
+    kept instance is the one the full cohort holds)."""
     rng = np.random.default_rng(seed)
     axes = np.sort(rng.uniform(axes_mm[0], axes_mm[1], (n_inst, 3)), axis=1)
     walls = rng.uniform(wall_mm[0], wall_mm[1], n_inst)
@@ -544,6 +558,8 @@ def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
     jobs = [dict(a=float(axes[i, 0]), b=float(axes[i, 1]), c=float(axes[i, 2]),
                  wall=float(walls[i]), n_nodes=int(n[i]), seed=int(seed * 1000 + i))
             for i in range(n_inst)]
+    keep = list(range(n_inst)) if only is None else [int(i) for i in only]
+    jobs = [jobs[i] for i in keep]
     if workers > 1 and not _gpu_may_be_live():
         import multiprocessing as mp
         with mp.get_context("fork").Pool(workers) as pool:
@@ -551,7 +567,7 @@ def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
     else:
         meshes = [shell_cap(**j) for j in jobs]
     inst = []
-    for i, m in enumerate(meshes):
+    for i, m in zip(keep, meshes):
         stim = Stimulus(endocardial_site(m, int(sites[i]), stim_radius), 0.0, 2.0,
                         50.0 * UA_PER_CM2_TO_PER_MM2)
         inst.append(Instance(mesh=m, sigma_l=0.17 * scale[i], sigma_t=0.019 * scale[i],

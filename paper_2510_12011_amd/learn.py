@@ -59,9 +59,9 @@ def record(sim, n_steps: int, every: int = 10, front: float = 0.02, frac: float 
         skip = min(every - 1, n_steps - done - 1)
         if skip > 0:
             sim.run(skip)
-        sim._check(L.lib().mdx_set_recorder(sim._h, _p(Xr), _p(dVr)))
+        sim._check(L.lib().mdx_set_recorder(sim._h, _p(Xr), _p(dVr), None))
         sim.run(1)
-        sim._check(L.lib().mdx_set_recorder(sim._h, None, None))
+        sim._check(L.lib().mdx_set_recorder(sim._h, None, None, None))
         keep = (dVr.abs() > front) | (torch.rand(n, generator=g, device=dev) < frac)
         idx = keep.nonzero().squeeze(1)
         xs.append(Xr[idx].clone())
@@ -72,16 +72,18 @@ def record(sim, n_steps: int, every: int = 10, front: float = 0.02, frac: float 
 
 def fit(sim, X, dV, epochs: int = 10, batch: int = 8192, lr: float = 2e-3, seed: int = 0,
         theta0: np.ndarray | None = None, log=None):
-    """Train on (X, dV): the network's target is the standardised increment
-    V^{n+1} - V^n.  Returns (params float32 [8705], norm float64 [9],
-    per-epoch mean loss)."""
+    """Train on (X, dV): the network's target is the standardised departure
+    of V^{n+1} from the extrapolation 2V^n - V^{n-1}, i.e. the increment
+    V^{n+1} - V^n less the previous one (feature 1).  Returns (params
+    float32 [8705], norm float64 [9], per-epoch mean loss)."""
     import torch
     dev = X.device
     mean = X.mean(0)
     std = X.std(0).clamp_min(1e-6)
-    out_scale = dV.std().clamp_min(1e-6)
+    D = dV - X[:, 1]
+    out_scale = D.std().clamp_min(1e-6)
     Xn = ((X - mean) / std).contiguous()
-    T = (dV / out_scale).contiguous()
+    T = (D / out_scale).contiguous()
     n = Xn.shape[0]
     P = torch.tensor(init_params(seed) if theta0 is None else theta0, dtype=torch.float32,
                      device=dev)
