@@ -62,8 +62,9 @@ typedef enum {
 typedef struct mdx_ctx mdx_ctx;
 
 /* ionic models: none (diffusion only), Mitchell-Schaeffer two-variable,
- * ten Tusscher-Panfilov 2006 (endocardial) */
-enum { MDX_IONIC_NONE = 0, MDX_IONIC_MS = 1, MDX_IONIC_TT = 2 };
+ * ten Tusscher-Panfilov 2006 (endocardial), Courtemanche-Ramirez-Nattel
+ * 1998 (human atrial) */
+enum { MDX_IONIC_NONE = 0, MDX_IONIC_MS = 1, MDX_IONIC_TT = 2, MDX_IONIC_CRN = 3 };
 /* PCG warm start: previous step V^k, extrapolation 2V^k - V^{k-1} (paper),
  * or the learned per-node network (see mdx_set_mlp), which corrects the
  * extrapolation and falls back to it whenever its initial residual is not
@@ -177,7 +178,13 @@ MDX_API mdx_status mdx_set_mass_lumping(mdx_ctx *ctx, int32_t lumped);
  * MDX_IONIC_MS, 7 params: tau_in, tau_out, tau_open, tau_close, u_gate,
  *   v_rest, v_amp (defaults 0.3, 6, 120, 150, 0.13, -80, 100).
  * MDX_IONIC_TT, 12 params: maximal conductances GNa, GK1, Gto, GKr, GKs,
- *   GCaL, GbNa, GbCa, GpCa, GpK and pump/exchanger scales PNaK, kNaCa. */
+ *   GCaL, GbNa, GbCa, GpCa, GpK and pump/exchanger scales PNaK, kNaCa.
+ * MDX_IONIC_CRN, 13 params: gNa, gK1, gto, gKr, gKs, gCaL, gbNa, gbCa
+ *   (nS/pF; defaults 7.8, 0.09, 0.1652, 0.029411765, 0.12941176, 0.12375,
+ *   6.744375e-4, 1.131e-3), INaK_max, INaCa_max, IpCa_max (pA/pF; 0.59933874,
+ *   1600, 0.275), Iup_max (mM/ms; 0.005) and a scale of gKur(V) (1).  Its
+ *   gating variables always advance in FP64 (MDX_PREC_MIXED_GATES32 is
+ *   MDX_ERR_UNSUPPORTED with this model). */
 MDX_API mdx_status mdx_set_ionic(mdx_ctx *ctx, int32_t kind, int32_t n_params, const double *params);
 /* number of ionic states per node (excluding V) and of parameters */
 MDX_API int32_t mdx_ionic_nstates(int32_t kind);

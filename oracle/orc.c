@@ -589,15 +589,233 @@ static void tt_point(const double *g, double dt, double V, double *y, double *ii
     *iion = tt_sum(&c);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Courtemanche-Ramirez-Nattel 1998 human atrial cell (the atrial model the  */
+/* paper's "Software implementation" section names), from the published     */
+/* equations.  States (index):                                               */
+/*  0 Nai 1 Ki 2 Cai 3 Caup 4 Carel 5 m 6 h 7 j 8 oa 9 oi 10 ua 11 ui        */
+/*  12 xr 13 xs 14 d 15 f 16 fCa 17 u 18 v 19 w.  V in mV, t in ms; currents */
+/*  per unit capacitance (pA/pF = mV/ms), concentrations mM, volumes um^3.   */
+/* params: 0 gNa 1 gK1 2 gto 3 gKr 4 gKs 5 gCaL 6 gbNa 7 gbCa (nS/pF)        */
+/*  8 INaK_max 9 INaCa_max 10 IpCa_max (pA/pF) 11 Iup_max (mM/ms)            */
+/*  12 scale of the ultrarapid K conductance gKur(V)                         */
+/* ------------------------------------------------------------------------ */
+#define CRN_NS 20
+#define CRN_NPAR 13
+static const double CRN_DEFAULT[CRN_NPAR] = {7.8, 0.09, 0.1652, 0.029411765, 0.12941176,
+                                             0.12375, 6.744375e-4, 1.131e-3, 0.59933874,
+                                             1600.0, 0.275, 0.005, 1.0};
+static const double CRN_INIT[CRN_NS] = {11.17, 139.0, 1.013e-4, 1.488, 1.488,
+                                        2.908e-3, 0.9649, 0.9775, 3.043e-2, 0.9992,
+                                        4.966e-3, 0.9986, 3.296e-5, 1.869e-2, 1.367e-4,
+                                        0.9996, 0.7755, 0.0, 1.0, 0.9992};
+static const double CRN_V0 = -81.18;
+#define CRN_R 8.3143
+#define CRN_T 310.0
+#define CRN_F 96.4867
+#define CRN_CM 100.0          /* pF */
+#define CRN_VI 13668.0
+#define CRN_VUP 1109.52
+#define CRN_VREL 96.48
+#define CRN_KO 5.4
+#define CRN_NAO 140.0
+#define CRN_CAO 1.8
+#define CRN_KMNAI 10.0        /* I_NaK half-saturation in Na_i */
+#define CRN_KMKO 1.5          /* I_NaK half-saturation in K_o */
+#define CRN_KMNA 87.5         /* I_NaCa */
+#define CRN_KMCA 1.38
+#define CRN_KSAT 0.1
+#define CRN_GAMMA 0.35
+#define CRN_KREL 30.0
+#define CRN_KUP 0.00092
+#define CRN_CAUPMAX 15.0
+#define CRN_TAUTR 180.0
+#define CRN_CMDN 0.05
+#define CRN_TRPN 0.07
+#define CRN_CSQN 10.0
+#define CRN_KMCMDN 0.00238
+#define CRN_KMTRPN 0.0005
+#define CRN_KMCSQN 0.8
+#define CRN_KQ10 3.0
+
+/* x / (1 - exp(-x/s)) and x / (exp(x/s) - 1), with their limits s at x = 0 */
+static double crn_x_over_1mexp(double x, double s)
+{
+    double t = x / s;
+    return t == 0.0 ? s : -x / expm1(-t);
+}
+static double crn_x_over_expm1(double x, double s)
+{
+    double t = x / s;
+    return t == 0.0 ? s : x / expm1(t);
+}
+
+typedef struct {
+    double INa, IK1, Ito, IKur, IKr, IKs, ICaL, INaK, INaCa, IbNa, IbCa, IpCa;
+} crn_currents;
+
+static void crn_currents_at(const double *g, double V, const double *y, crn_currents *c)
+{
+    const double RTF = CRN_R * CRN_T / CRN_F;
+    double Nai = y[0], Ki = y[1], Cai = y[2];
+    double ENa = RTF * log(CRN_NAO / Nai);
+    double EK = RTF * log(CRN_KO / Ki);
+    double ECa = 0.5 * RTF * log(CRN_CAO / Cai);
+    double vf = V / RTF;
+    c->INa = g[0] * y[5] * y[5] * y[5] * y[6] * y[7] * (V - ENa);
+    c->IK1 = g[1] * (V - EK) / (1.0 + exp(0.07 * (V + 80.0)));
+    c->Ito = g[2] * y[8] * y[8] * y[8] * y[9] * (V - EK);
+    double gKur = g[12] * (0.005 + 0.05 / (1.0 + exp(-(V - 15.0) / 13.0)));
+    c->IKur = gKur * y[10] * y[10] * y[10] * y[11] * (V - EK);
+    c->IKr = g[3] * y[12] * (V - EK) / (1.0 + exp((V + 15.0) / 22.4));
+    c->IKs = g[4] * y[13] * y[13] * (V - EK);
+    c->ICaL = g[5] * y[14] * y[15] * y[16] * (V - 65.0);
+    double sigma = (exp(CRN_NAO / 67.3) - 1.0) / 7.0;
+    double fNaK = 1.0 / (1.0 + 0.1245 * exp(-0.1 * vf) + 0.0365 * sigma * exp(-vf));
+    c->INaK = g[8] * fNaK / (1.0 + pow(CRN_KMNAI / Nai, 1.5)) * CRN_KO / (CRN_KO + CRN_KMKO);
+    c->INaCa = g[9] * (exp(CRN_GAMMA * vf) * Nai * Nai * Nai * CRN_CAO
+                       - exp((CRN_GAMMA - 1.0) * vf) * CRN_NAO * CRN_NAO * CRN_NAO * Cai)
+             / ((CRN_KMNA * CRN_KMNA * CRN_KMNA + CRN_NAO * CRN_NAO * CRN_NAO)
+                * (CRN_KMCA + CRN_CAO) * (1.0 + CRN_KSAT * exp((CRN_GAMMA - 1.0) * vf)));
+    c->IbNa = g[6] * (V - ENa);
+    c->IbCa = g[7] * (V - ECa);
+    c->IpCa = g[10] * Cai / (0.0005 + Cai);
+}
+
+static double crn_sum(const crn_currents *c)
+{
+    return c->INa + c->IK1 + c->Ito + c->IKur + c->IKr + c->IKs + c->ICaL + c->INaK
+         + c->INaCa + c->IbNa + c->IbCa + c->IpCa;
+}
+
+static void crn_point(const double *g, double dt, double V, double *y, double *iion)
+{
+    crn_currents c;
+    crn_currents_at(g, V, y, &c);
+    double Nai = y[0], Cai = y[2], Caup = y[3], Carel = y[4];
+    (void)Nai;
+    /* SR fluxes (mM/ms) and concentrations, derivatives at (V^k, u^k);
+     * currents in pA are the per-capacitance values times Cm */
+    double Irel = CRN_KREL * y[17] * y[17] * y[18] * y[19] * (Carel - Cai);
+    double Itr = (Caup - Carel) / CRN_TAUTR;
+    double Iup = g[11] / (1.0 + CRN_KUP / Cai);
+    double Iupleak = g[11] * Caup / CRN_CAUPMAX;
+    double FV = CRN_F * CRN_VI;
+    double dNai = -CRN_CM * (3.0 * c.INaK + 3.0 * c.INaCa + c.IbNa + c.INa) / FV;
+    double dKi = CRN_CM * (2.0 * c.INaK - (c.IK1 + c.Ito + c.IKur + c.IKr + c.IKs)) / FV;
+    double B1 = CRN_CM * (2.0 * c.INaCa - (c.IpCa + c.ICaL + c.IbCa)) / (2.0 * FV)
+              + (CRN_VUP * (Iupleak - Iup) + Irel * CRN_VREL) / CRN_VI;
+    double B2 = 1.0 + CRN_TRPN * CRN_KMTRPN / ((Cai + CRN_KMTRPN) * (Cai + CRN_KMTRPN))
+              + CRN_CMDN * CRN_KMCMDN / ((Cai + CRN_KMCMDN) * (Cai + CRN_KMCMDN));
+    double dCai = B1 / B2;
+    double dCaup = Iup - Iupleak - Itr * CRN_VREL / CRN_VUP;
+    double dCarel = (Itr - Irel)
+                  / (1.0 + CRN_CSQN * CRN_KMCSQN / ((Carel + CRN_KMCSQN) * (Carel + CRN_KMCSQN)));
+
+    /* gates at V^k (and at Fn, Ca_i of step k for u, v, fCa) */
+    double am = 0.32 * crn_x_over_1mexp(V + 47.13, 10.0);
+    double bm = 0.08 * exp(-V / 11.0);
+    double ah, bh, aj, bj;
+    if (V < -40.0) {
+        ah = 0.135 * exp((V + 80.0) / -6.8);
+        bh = 3.56 * exp(0.079 * V) + 3.1e5 * exp(0.35 * V);
+        aj = (-127140.0 * exp(0.2444 * V) - 3.474e-5 * exp(-0.04391 * V)) * (V + 37.78)
+           / (1.0 + exp(0.311 * (V + 79.23)));
+        bj = 0.1212 * exp(-0.01052 * V) / (1.0 + exp(-0.1378 * (V + 40.14)));
+    } else {
+        ah = 0.0;
+        bh = 1.0 / (0.13 * (1.0 + exp((V + 10.66) / -11.1)));
+        aj = 0.0;
+        bj = 0.3 * exp(-2.535e-7 * V) / (1.0 + exp(-0.1 * (V + 32.0)));
+    }
+    double a_oa = 0.65 / (exp((V + 10.0) / -8.5) + exp((V - 30.0) / -59.0));
+    double b_oa = 0.65 / (2.5 + exp((V + 82.0) / 17.0));
+    double t_oa = 1.0 / ((a_oa + b_oa) * CRN_KQ10);
+    double oainf = 1.0 / (1.0 + exp((V + 20.47) / -17.54));
+    double a_oi = 1.0 / (18.53 + exp((V + 113.7) / 10.95));
+    double b_oi = 1.0 / (35.56 + exp((V + 1.26) / -7.44));
+    double t_oi = 1.0 / ((a_oi + b_oi) * CRN_KQ10);
+    double oiinf = 1.0 / (1.0 + exp((V + 43.1) / 5.3));
+    /* the ultrarapid activation gate has the transient one's rates */
+    double t_ua = t_oa;
+    double uainf = 1.0 / (1.0 + exp((V + 30.3) / -9.6));
+    double a_ui = 1.0 / (21.0 + exp((V - 185.0) / -28.0));
+    double b_ui = exp((V - 158.0) / 16.0);
+    double t_ui = 1.0 / ((a_ui + b_ui) * CRN_KQ10);
+    double uiinf = 1.0 / (1.0 + exp((V - 99.45) / 27.48));
+    double a_xr = 0.0003 * crn_x_over_1mexp(V + 14.1, 5.0);
+    double b_xr = 7.3898e-5 * crn_x_over_expm1(V - 3.3328, 5.1237);
+    double t_xr = 1.0 / (a_xr + b_xr);
+    double xrinf = 1.0 / (1.0 + exp((V + 14.1) / -6.5));
+    double a_xs = 4e-5 * crn_x_over_1mexp(V - 19.9, 17.0);
+    double b_xs = 3.5e-5 * crn_x_over_expm1(V - 19.9, 9.0);
+    double t_xs = 0.5 / (a_xs + b_xs);
+    double xsinf = 1.0 / sqrt(1.0 + exp((V - 19.9) / -12.7));
+    /* tau_d = (1 - e^{-x/6.24}) / (0.035 x (1 + e^{-x/6.24})), x = V + 10 */
+    double xd = V + 10.0;
+    double t_d = 1.0 / (0.035 * crn_x_over_1mexp(xd, 6.24) * (1.0 + exp(-xd / 6.24)));
+    double dinf = 1.0 / (1.0 + exp(-xd / 8.0));
+    double t_f = 9.0 / (0.0197 * exp(-0.0337 * 0.0337 * xd * xd) + 0.02);
+    double finf = 1.0 / (1.0 + exp((V + 28.0) / 6.9));
+    double fcainf = 1.0 / (1.0 + Cai / 0.00035);
+    double t_fca = 2.0;
+    double Fn = 1e-12 * CRN_VREL * Irel
+              - 5e-13 / CRN_F * (0.5 * CRN_CM * c.ICaL - 0.2 * CRN_CM * c.INaCa);
+    double su = 1.0 / (1.0 + exp(-(Fn - 3.4175e-13) / 13.67e-16));
+    double uinf = su;
+    double t_u = 8.0;
+    double vinf = 1.0 - 1.0 / (1.0 + exp(-(Fn - 6.835e-14) / 13.67e-16));
+    double t_v = 1.91 + 2.09 * su;
+    double winf = 1.0 - 1.0 / (1.0 + exp(-(V - 40.0) / 17.0));
+    /* tau_w = 6 (1 - e^{-x/5}) / ((1 + 0.3 e^{-x/5}) x), x = V - 7.9 */
+    double xw = V - 7.9;
+    double t_w = 6.0 / (crn_x_over_1mexp(xw, 5.0) * (1.0 + 0.3 * exp(-xw / 5.0)));
+
+    /* forward Euler for the concentrations */
+    y[0] += dt * dNai;
+    y[1] += dt * dKi;
+    y[2] += dt * dCai;
+    y[3] += dt * dCaup;
+    y[4] += dt * dCarel;
+    /* Rush-Larsen for the gates */
+    y[5] = rl(y[5], am / (am + bm), 1.0 / (am + bm), dt);
+    y[6] = rl(y[6], ah / (ah + bh), 1.0 / (ah + bh), dt);
+    y[7] = rl(y[7], aj / (aj + bj), 1.0 / (aj + bj), dt);
+    y[8] = rl(y[8], oainf, t_oa, dt);
+    y[9] = rl(y[9], oiinf, t_oi, dt);
+    y[10] = rl(y[10], uainf, t_ua, dt);
+    y[11] = rl(y[11], uiinf, t_ui, dt);
+    y[12] = rl(y[12], xrinf, t_xr, dt);
+    y[13] = rl(y[13], xsinf, t_xs, dt);
+    y[14] = rl(y[14], dinf, t_d, dt);
+    y[15] = rl(y[15], finf, t_f, dt);
+    y[16] = rl(y[16], fcainf, t_fca, dt);
+    y[17] = rl(y[17], uinf, t_u, dt);
+    y[18] = rl(y[18], vinf, t_v, dt);
+    y[19] = rl(y[19], winf, t_w, dt);
+
+    /* I_ion(V^k, u^{k+1}) */
+    crn_currents_at(g, V, y, &c);
+    *iion = crn_sum(&c);
+}
+
 /* number of states (excluding V) and parameters per model kind
- * kind 0: no ionic current (diffusion only), 1: Mitchell-Schaeffer, 2: TTP06 */
-int orc_ionic_nstates(int kind) { return kind == 1 ? 1 : kind == 2 ? TT_NS : 0; }
-int orc_ionic_nparams(int kind) { return kind == 1 ? MS_NPAR : kind == 2 ? TT_NPAR : 0; }
+ * kind 0: no ionic current (diffusion only), 1: Mitchell-Schaeffer, 2: TTP06,
+ * 3: Courtemanche-Ramirez-Nattel */
+int orc_ionic_nstates(int kind)
+{
+    return kind == 1 ? 1 : kind == 2 ? TT_NS : kind == 3 ? CRN_NS : 0;
+}
+int orc_ionic_nparams(int kind)
+{
+    return kind == 1 ? MS_NPAR : kind == 2 ? TT_NPAR : kind == 3 ? CRN_NPAR : 0;
+}
 
 void orc_ionic_defaults(int kind, double *params)
 {
     if (kind == 1) memcpy(params, MS_DEFAULT, sizeof(MS_DEFAULT));
     if (kind == 2) memcpy(params, TT_DEFAULT, sizeof(TT_DEFAULT));
+    if (kind == 3) memcpy(params, CRN_DEFAULT, sizeof(CRN_DEFAULT));
 }
 
 /* rest state: V0 and u0 (SoA, u[s*n + i]) */
@@ -608,6 +826,9 @@ void orc_ionic_init(int kind, const double *params, int64_t n, double *V, double
         else if (kind == 2) {
             V[i] = TT_V0;
             for (int s = 0; s < TT_NS; ++s) u[(int64_t)s * n + i] = TT_INIT[s];
+        } else if (kind == 3) {
+            V[i] = CRN_V0;
+            for (int s = 0; s < CRN_NS; ++s) u[(int64_t)s * n + i] = CRN_INIT[s];
         } else V[i] = 0.0;
     }
 }
@@ -625,6 +846,11 @@ void orc_ionic_step(int kind, const double *params, int64_t n, double dt,
             for (int s = 0; s < TT_NS; ++s) y[s] = u[(int64_t)s * n + i];
             tt_point(params, dt, V[i], y, &iion[i]);
             for (int s = 0; s < TT_NS; ++s) u[(int64_t)s * n + i] = y[s];
+        } else if (kind == 3) {
+            double y[CRN_NS];
+            for (int s = 0; s < CRN_NS; ++s) y[s] = u[(int64_t)s * n + i];
+            crn_point(params, dt, V[i], y, &iion[i]);
+            for (int s = 0; s < CRN_NS; ++s) u[(int64_t)s * n + i] = y[s];
         } else {
             iion[i] = 0.0;
         }

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orc.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-IONIC_KIND = {"none": 0, "ms": 1, "tt": 2}
+IONIC_KIND = {"none": 0, "ms": 1, "tt": 2, "crn": 3}
 
 
 def build(force: bool = True) -> str:

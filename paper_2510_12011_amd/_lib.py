@@ -23,7 +23,7 @@ MDX_ERR_NONFINITE = -5
 MDX_ERR_STATE = -6
 MDX_ERR_UNSUPPORTED = -7
 
-MDX_IONIC_NONE, MDX_IONIC_MS, MDX_IONIC_TT = 0, 1, 2
+MDX_IONIC_NONE, MDX_IONIC_MS, MDX_IONIC_TT, MDX_IONIC_CRN = 0, 1, 2, 3
 MDX_WS_PREV, MDX_WS_EXTRAP, MDX_WS_MLP = 0, 1, 2
 MDX_REL_INITIAL, MDX_REL_RHS = 0, 1
 MDX_PREC_FP64, MDX_PREC_MIXED, MDX_PREC_MIXED_GATES32 = 0, 1, 2

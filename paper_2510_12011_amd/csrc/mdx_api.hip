@@ -101,6 +101,8 @@ struct mdx_ctx {
     size_t ws_bytes = 0;
     Layout L{};
     float *grad_scratch = nullptr;   // library-owned partials of mdx_mlp_grad_noalloc
+    // the model's gates have no FP32 form (MDX_PREC_MIXED_GATES32 unsupported)
+    bool ionic_gates64_only() const { return ionic_kind == MDX_IONIC_CRN; }
     Tiling tiling{};        // vector and right-hand-side kernels
     Tiling tiling_spmv{};   // the PCG iteration's SpMV kernel
     bool prepared = false;
@@ -1398,7 +1400,7 @@ mdx_status mdx_set_tissue(mdx_ctx *ctx, double chi, double cm, double theta)
 mdx_status mdx_set_ionic(mdx_ctx *ctx, int32_t kind, int32_t n_params, const double *params)
 {
     if (!ctx) return MDX_ERR_INVALID_ARG;
-    if (kind < MDX_IONIC_NONE || kind > MDX_IONIC_TT)
+    if (kind < MDX_IONIC_NONE || kind > MDX_IONIC_CRN)
         return fail(ctx, MDX_ERR_UNSUPPORTED, "unknown ionic model %d", kind);
     int np = ionic_nparams(kind);
     if (params && n_params != np)
@@ -1703,6 +1705,9 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     if (!ctx) return MDX_ERR_INVALID_ARG;
     if (!ctx->prepared) return fail(ctx, MDX_ERR_STATE, "mdx_prepare has not been called");
     if (n_steps < 0 || out_every < 0) return fail(ctx, MDX_ERR_INVALID_ARG, "negative count");
+    if (ctx->opts.precision == MDX_PREC_MIXED_GATES32 && ctx->ionic_gates64_only())
+        return fail(ctx, MDX_ERR_UNSUPPORTED,
+                    "this ionic model advances its gates in FP64 only (use MDX_PREC_MIXED)");
     GUARD_BEGIN
     HIPCHK(hipSetDevice(ctx->device));
     if (ctx->batched) return run_batched(ctx, n_steps, out_every, v_out);

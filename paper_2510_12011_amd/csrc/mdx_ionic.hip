@@ -13,14 +13,16 @@
 //  * Mitchell-Schaeffer two-variable model (Bull. Math. Biol. 2003), with the
 //    membrane variable u = (V - v_rest) / v_amp and gate h;
 //  * ten Tusscher-Panfilov 2006 human ventricular model, endocardial cell
-//    (Am. J. Physiol. Heart Circ. Physiol. 291:H1088), 18 states + V.
+//    (Am. J. Physiol. Heart Circ. Physiol. 291:H1088), 18 states + V;
+//  * Courtemanche-Ramirez-Nattel 1998 human atrial model (Am. J. Physiol.
+//    275:H301), 20 states + V.
 #include "mdx_internal.h"
 
 namespace mdx {
 
 namespace {
 
-enum { MDX_KIND_NONE = 0, MDX_KIND_MS = 1, MDX_KIND_TT = 2 };
+enum { MDX_KIND_NONE = 0, MDX_KIND_MS = 1, MDX_KIND_TT = 2, MDX_KIND_CRN = 3 };
 constexpr int MS_NP = 7;
 constexpr int TT_NS = 18;
 constexpr int TT_NP = 12;
@@ -354,6 +356,188 @@ __device__ double tt_point(const IonicParams &P, double dt, double V, double *c,
     return tt_currents(P, V, vo, c, pn).total();
 }
 
+// ---------------------------------------------------------------------------
+// Courtemanche-Ramirez-Nattel 1998 human atrial cell (Am. J. Physiol. 275:
+// H301), 20 states + V, held in registers for the step:
+//   y[0..4]  Na_i K_i Ca_i Ca_up Ca_rel (mM; forward Euler)
+//   y[5..19] m h j oa oi ua ui xr xs d f fCa u v w (Rush-Larsen)
+// params: gNa gK1 gto gKr gKs gCaL gbNa gbCa (nS/pF), INaK_max INaCa_max
+// IpCa_max (pA/pF), Iup_max (mM/ms), and a scale of gKur(V).
+// Currents are per unit capacitance; the membrane capacitance (100 pF) turns
+// them into the pA that the concentration balances and the release trigger
+// use.
+// ---------------------------------------------------------------------------
+namespace crn {
+constexpr double RT_F = 8.3143 * 310.0 / 96.4867;   // mV
+constexpr double FARADAY = 96.4867;                   // C/mmol
+constexpr double CAP = 100.0;                         // pF
+constexpr double VOL_I = 13668.0, VOL_UP = 1109.52, VOL_REL = 96.48;   // um^3
+constexpr double K_OUT = 5.4, NA_OUT = 140.0, CA_OUT = 1.8;
+constexpr double NAK_KM_NA = 10.0, NAK_KM_K = 1.5;
+constexpr double NACA_KM_NA = 87.5, NACA_KM_CA = 1.38, NACA_SAT = 0.1, NACA_GAMMA = 0.35;
+constexpr double REL_RATE = 30.0, UP_KM = 0.00092, UP_CA_MAX = 15.0, TR_TAU = 180.0;
+constexpr double CMDN_TOT = 0.05, CMDN_KM = 0.00238, TRPN_TOT = 0.07, TRPN_KM = 0.0005;
+constexpr double CSQN_TOT = 10.0, CSQN_KM = 0.8;
+constexpr double Q10 = 3.0;
+constexpr double V_REST = -81.18;
+// ratio of the sodium-potassium pump's [Na]_o dependence, (e^{Na_o/67.3} - 1) / 7
+__device__ __forceinline__ double nak_sigma() { return (exp(NA_OUT / 67.3) - 1.0) / 7.0; }
+}  // namespace crn
+constexpr int CRN_NS = 20;
+constexpr int CRN_NP = 13;
+__device__ const double CRN_U0[CRN_NS] = {11.17,  139.0,  1.013e-4, 1.488,    1.488,
+                                          2.908e-3, 0.9649, 0.9775, 3.043e-2, 0.9992,
+                                          4.966e-3, 0.9986, 3.296e-5, 1.869e-2, 1.367e-4,
+                                          0.9996, 0.7755, 0.0,      1.0,      0.9992};
+
+// x / (1 - e^{-x/s}), whose limit at x = 0 is s
+__device__ __forceinline__ double rise_ratio(double x, double s)
+{
+    const double t = x / s;
+    return t != 0.0 ? x / -expm1(-t) : s;
+}
+// x / (e^{x/s} - 1), whose limit at x = 0 is s
+__device__ __forceinline__ double fall_ratio(double x, double s)
+{
+    const double t = x / s;
+    return t != 0.0 ? x / expm1(t) : s;
+}
+__device__ __forceinline__ double logistic(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+struct CrnCurrents {
+    double iNa, iK1, ito, iKur, iKr, iKs, iCaL, iNaK, iNaCa, ibNa, ibCa, ipCa;
+    __device__ double total() const
+    {
+        return ((iNa + ibNa) + (iK1 + ito + iKur + iKr + iKs)) + ((iCaL + ibCa + ipCa) + (iNaK + iNaCa));
+    }
+};
+
+__device__ __forceinline__ CrnCurrents crn_currents(const IonicParams &P, double V, const double *y)
+{
+    using namespace crn;
+    const double na = y[0], k = y[1], ca = y[2];
+    const double e_na = RT_F * log(NA_OUT / na), e_k = RT_F * log(K_OUT / k);
+    const double e_ca = 0.5 * RT_F * log(CA_OUT / ca);
+    const double u = V * (1.0 / RT_F);
+    CrnCurrents c;
+    const double m = y[5];
+    c.iNa = P.v[0] * (m * m * m) * y[6] * y[7] * (V - e_na);
+    c.iK1 = P.v[1] * (V - e_k) * logistic(-0.07 * (V + 80.0));
+    const double oa = y[8];
+    c.ito = P.v[2] * (oa * oa * oa) * y[9] * (V - e_k);
+    const double ua = y[10];
+    const double g_kur = P.v[12] * (0.005 + 0.05 * logistic((V - 15.0) * (1.0 / 13.0)));
+    c.iKur = g_kur * (ua * ua * ua) * y[11] * (V - e_k);
+    c.iKr = P.v[3] * y[12] * (V - e_k) * logistic(-(V + 15.0) * (1.0 / 22.4));
+    c.iKs = P.v[4] * y[13] * y[13] * (V - e_k);
+    c.iCaL = P.v[5] * y[14] * y[15] * y[16] * (V - 65.0);
+    const double pump_v = 1.0 / (1.0 + 0.1245 * exp(-0.1 * u) + 0.0365 * nak_sigma() * exp(-u));
+    const double pump_na = 1.0 / (1.0 + (NAK_KM_NA / na) * sqrt(NAK_KM_NA / na));
+    c.iNaK = P.v[8] * pump_v * pump_na * (K_OUT / (K_OUT + NAK_KM_K));
+    const double e_in = exp(NACA_GAMMA * u), e_out = exp((NACA_GAMMA - 1.0) * u);
+    const double km3 = NACA_KM_NA * NACA_KM_NA * NACA_KM_NA, nao3 = NA_OUT * NA_OUT * NA_OUT;
+    c.iNaCa = P.v[9] * (e_in * (na * na * na) * CA_OUT - e_out * nao3 * ca)
+            / ((km3 + nao3) * (NACA_KM_CA + CA_OUT) * (1.0 + NACA_SAT * e_out));
+    c.ibNa = P.v[6] * (V - e_na);
+    c.ibCa = P.v[7] * (V - e_ca);
+    c.ipCa = P.v[10] * ca / (0.0005 + ca);
+    return c;
+}
+
+// One step at one node: fluxes and rates at (V^k, u^k), then u^{k+1};
+// returns I_ion(V^k, u^{k+1}) / Cm (mV/ms).
+__device__ double crn_point(const IonicParams &P, double dt, double V, double *y)
+{
+    using namespace crn;
+    const CrnCurrents c = crn_currents(P, V, y);
+    const double ca = y[2], ca_up = y[3], ca_rel = y[4];
+    const double uu = y[17];
+    const double j_rel = REL_RATE * (uu * uu) * y[18] * y[19] * (ca_rel - ca);
+    const double j_tr = (ca_up - ca_rel) * (1.0 / TR_TAU);
+    const double j_up = P.v[11] / (1.0 + UP_KM / ca);
+    const double j_leak = P.v[11] * ca_up * (1.0 / UP_CA_MAX);
+    // current (pA/pF) to concentration rate in the myoplasm (mM/ms)
+    constexpr double to_conc = CAP / (FARADAY * VOL_I);
+    const double d_na = -to_conc * (3.0 * (c.iNaK + c.iNaCa) + c.ibNa + c.iNa);
+    const double d_k = to_conc * (2.0 * c.iNaK - (c.iK1 + c.ito + c.iKur + c.iKr + c.iKs));
+    const double free_ca = 0.5 * to_conc * (2.0 * c.iNaCa - c.ipCa - c.iCaL - c.ibCa)
+                         + (VOL_UP * (j_leak - j_up) + VOL_REL * j_rel) * (1.0 / VOL_I);
+    const double b_cmdn = CMDN_TOT * CMDN_KM / ((ca + CMDN_KM) * (ca + CMDN_KM));
+    const double b_trpn = TRPN_TOT * TRPN_KM / ((ca + TRPN_KM) * (ca + TRPN_KM));
+    const double d_ca = free_ca / (1.0 + b_trpn + b_cmdn);
+    const double d_up = j_up - j_leak - j_tr * (VOL_REL / VOL_UP);
+    const double d_rel = (j_tr - j_rel) / (1.0 + CSQN_TOT * CSQN_KM / ((ca_rel + CSQN_KM) * (ca_rel + CSQN_KM)));
+
+    // release trigger: SR release plus the Ca entry of I_CaL and I_NaCa (pA)
+    const double fn = 1e-12 * VOL_REL * j_rel - (5e-13 / FARADAY) * CAP * (0.5 * c.iCaL - 0.2 * c.iNaCa);
+    const double on_u = logistic((fn - 3.4175e-13) * (1.0 / 13.67e-16));
+
+    // ---- gates: Rush-Larsen with the rate 1/tau at V^k ----
+    {   // fast sodium m, h, j from their opening and closing rates
+        const double am = 0.32 * rise_ratio(V + 47.13, 10.0), bm = 0.08 * exp(-V * (1.0 / 11.0));
+        y[5] = rush_larsen_rate(y[5], am / (am + bm), am + bm, dt);
+        double ah = 0.0, bh, aj = 0.0, bj;
+        if (V < -40.0) {
+            ah = 0.135 * exp(-(V + 80.0) * (1.0 / 6.8));
+            bh = 3.56 * exp(0.079 * V) + 3.1e5 * exp(0.35 * V);
+            aj = (-127140.0 * exp(0.2444 * V) - 3.474e-5 * exp(-0.04391 * V)) * (V + 37.78)
+               * logistic(-0.311 * (V + 79.23));
+            bj = 0.1212 * exp(-0.01052 * V) * logistic(0.1378 * (V + 40.14));
+        } else {
+            bh = (1.0 / 0.13) * logistic((V + 10.66) * (1.0 / 11.1));
+            bj = 0.3 * exp(-2.535e-7 * V) * logistic(0.1 * (V + 32.0));
+        }
+        y[6] = rush_larsen_rate(y[6], ah / (ah + bh), ah + bh, dt);
+        y[7] = rush_larsen_rate(y[7], aj / (aj + bj), aj + bj, dt);
+    }
+    {   // transient (oa, oi) and ultrarapid (ua, ui) potassium, Q10 = 3
+        const double a_a = 0.65 / (exp(-(V + 10.0) * (1.0 / 8.5)) + exp(-(V - 30.0) * (1.0 / 59.0)));
+        const double b_a = 0.65 / (2.5 + exp((V + 82.0) * (1.0 / 17.0)));
+        const double r_a = (a_a + b_a) * Q10;
+        y[8] = rush_larsen_rate(y[8], logistic((V + 20.47) * (1.0 / 17.54)), r_a, dt);
+        y[10] = rush_larsen_rate(y[10], logistic((V + 30.3) * (1.0 / 9.6)), r_a, dt);
+        const double a_oi = 1.0 / (18.53 + exp((V + 113.7) * (1.0 / 10.95)));
+        const double b_oi = 1.0 / (35.56 + exp(-(V + 1.26) * (1.0 / 7.44)));
+        y[9] = rush_larsen_rate(y[9], logistic(-(V + 43.1) * (1.0 / 5.3)), (a_oi + b_oi) * Q10, dt);
+        const double a_ui = 1.0 / (21.0 + exp(-(V - 185.0) * (1.0 / 28.0)));
+        const double b_ui = exp((V - 158.0) * (1.0 / 16.0));
+        y[11] = rush_larsen_rate(y[11], logistic(-(V - 99.45) * (1.0 / 27.48)), (a_ui + b_ui) * Q10, dt);
+    }
+    {   // rapid and slow delayed rectifiers
+        const double a_r = 0.0003 * rise_ratio(V + 14.1, 5.0);
+        const double b_r = 7.3898e-5 * fall_ratio(V - 3.3328, 5.1237);
+        y[12] = rush_larsen_rate(y[12], logistic((V + 14.1) * (1.0 / 6.5)), a_r + b_r, dt);
+        const double a_s = 4e-5 * rise_ratio(V - 19.9, 17.0);
+        const double b_s = 3.5e-5 * fall_ratio(V - 19.9, 9.0);
+        y[13] = rush_larsen_rate(y[13], sqrt(logistic((V - 19.9) * (1.0 / 12.7))), 2.0 * (a_s + b_s), dt);
+    }
+    {   // L-type calcium d, f, fCa
+        const double x = V + 10.0;
+        // 1/tau_d = 0.035 x (1 + e^{-x/6.24}) / (1 - e^{-x/6.24})
+        const double r_d = 0.035 * rise_ratio(x, 6.24) * (1.0 + exp(-x * (1.0 / 6.24)));
+        y[14] = rush_larsen_rate(y[14], logistic(x * (1.0 / 8.0)), r_d, dt);
+        const double r_f = (0.0197 * exp(-(0.0337 * 0.0337) * x * x) + 0.02) * (1.0 / 9.0);
+        y[15] = rush_larsen_rate(y[15], logistic(-(V + 28.0) * (1.0 / 6.9)), r_f, dt);
+        y[16] = rush_larsen_rate(y[16], 1.0 / (1.0 + ca * (1.0 / 0.00035)), 0.5, dt);
+    }
+    {   // SR release gates u, v (trigger fn) and w (voltage)
+        y[17] = rush_larsen_rate(y[17], on_u, 1.0 / 8.0, dt);
+        const double v_inf = 1.0 - logistic((fn - 6.835e-14) * (1.0 / 13.67e-16));
+        y[18] = rush_larsen_rate(y[18], v_inf, 1.0 / (1.91 + 2.09 * on_u), dt);
+        const double xw = V - 7.9;
+        // 1/tau_w = x (1 + 0.3 e^{-x/5}) / (6 (1 - e^{-x/5}))
+        const double r_w = rise_ratio(xw, 5.0) * (1.0 + 0.3 * exp(-xw * (1.0 / 5.0))) * (1.0 / 6.0);
+        y[19] = rush_larsen_rate(y[19], 1.0 - logistic((V - 40.0) * (1.0 / 17.0)), r_w, dt);
+    }
+    // ---- forward Euler for the concentrations ----
+    y[0] += dt * d_na;
+    y[1] += dt * d_k;
+    y[2] = ca + dt * d_ca;
+    y[3] = ca_up + dt * d_up;
+    y[4] = ca_rel + dt * d_rel;
+    return crn_currents(P, V, y).total();
+}
+
 // Row i holds a cell: i < n, or, with the per-tile count of real rows of the
 // batched layout (padding rows at the end of each instance's last tile),
 // (i mod TILE) < tile_real[i / TILE].
@@ -396,6 +580,13 @@ __global__ __launch_bounds__(256) void k_ionic_step(IonicParams P, int64_t n, in
         iion = tt_point<double>(P, dt, v, c, u + 6 * ld + i, ld);
 #pragma unroll
         for (int s = 0; s < 6; ++s) u[s * ld + i] = c[s];
+    } else if constexpr (KIND == MDX_KIND_CRN) {
+        double y[CRN_NS];
+#pragma unroll
+        for (int s = 0; s < CRN_NS; ++s) y[s] = u[s * ld + i];
+        iion = crn_point(P, dt, v, y);
+#pragma unroll
+        for (int s = 0; s < CRN_NS; ++s) u[s * ld + i] = y[s];
     }
     if (raw)
         out[i] = iion;
@@ -421,6 +612,11 @@ __global__ __launch_bounds__(256) void k_ionic_init(IonicParams P, int64_t n, in
         v0 = TT_V_REST;
         if (u)
             for (int s = 0; s < TT_NS; ++s) u[s * ld + i] = real ? TT_U0[s] : 0.0;
+    } else if constexpr (KIND == MDX_KIND_CRN) {
+        v0 = crn::V_REST;
+        // padding rows hold the rest state too (finite logarithms if read)
+        if (u)
+            for (int s = 0; s < CRN_NS; ++s) u[s * ld + i] = CRN_U0[s];
     }
     V[i] = real ? v0 : 0.0;
     Vprev[i] = real ? v0 : 0.0;
@@ -492,8 +688,8 @@ IonicParams pack(int kind, const double *params)
 
 }  // namespace
 
-int ionic_nstates(int kind) { return kind == 1 ? 1 : kind == 2 ? TT_NS : 0; }
-int ionic_nparams(int kind) { return kind == 1 ? MS_NP : kind == 2 ? TT_NP : 0; }
+int ionic_nstates(int kind) { return kind == 1 ? 1 : kind == 2 ? TT_NS : kind == 3 ? CRN_NS : 0; }
+int ionic_nparams(int kind) { return kind == 1 ? MS_NP : kind == 2 ? TT_NP : kind == 3 ? CRN_NP : 0; }
 
 void ionic_defaults(int kind, double *params)
 {
@@ -504,6 +700,11 @@ void ionic_defaults(int kind, double *params)
         for (int i = 0; i < MS_NP; ++i) params[i] = ms[i];
     if (kind == 2)
         for (int i = 0; i < TT_NP; ++i) params[i] = tt[i];
+    static const double crn_p[CRN_NP] = {7.8,     0.09,     0.1652,     0.029411765, 0.12941176,
+                                         0.12375, 6.744375e-4, 1.131e-3, 0.59933874,  1600.0,
+                                         0.275,   0.005,    1.0};
+    if (kind == 3)
+        for (int i = 0; i < CRN_NP; ++i) params[i] = crn_p[i];
 }
 
 void launch_ionic_init(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
@@ -515,6 +716,8 @@ void launch_ionic_init(hipStream_t s, int kind, const double *params, int64_t n,
         hipLaunchKernelGGL(k_ionic_init<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, V, Vprev, u, tile_real);
     else if (kind == 2)
         hipLaunchKernelGGL(k_ionic_init<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, V, Vprev, u, tile_real);
+    else if (kind == 3)
+        hipLaunchKernelGGL(k_ionic_init<MDX_KIND_CRN>, grid, block, 0, s, P, n, ld, V, Vprev, u, tile_real);
     else
         hipLaunchKernelGGL(k_ionic_init<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, V, Vprev, u, tile_real);
 }
@@ -531,6 +734,9 @@ void launch_ionic_step(hipStream_t s, int kind, const double *params, int64_t n,
                            istim, out, raw, tile_real, guard);
     else if (kind == 2)
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
+                           istim, out, raw, tile_real, guard);
+    else if (kind == 3)
+        hipLaunchKernelGGL(k_ionic_step<MDX_KIND_CRN>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
                            istim, out, raw, tile_real, guard);
     else
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, dt, cm, V, u,

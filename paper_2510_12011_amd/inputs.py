@@ -629,36 +629,43 @@ def ellipsoid_surface(level: int, axes=(40.0, 33.0, 30.0), fibres: bool = True) 
                 region=np.zeros(tris.shape[0], np.int32), shape=(level,))
 
 
-# modified two-variable Mitchell-Schaeffer of the paper's left-atrium example
-# ("Best Practices" section):
+# parameters of the paper's left-atrium example ("Best Practices" section),
+# applied to the classic two-variable Mitchell-Schaeffer model (the paper
+# calls its cell model a modified one without giving the modification):
 # tau_in, tau_out, tau_open, tau_close, u_gate (its u_crit, 0.1 there too, is
 # the same threshold here), v_rest, v_amp
 ATRIUM_MS_PARAMS = (0.15, 1.5, 105.0, 185.0, 0.1, -80.0, 100.0)
 
 
 def atrium_surface(level: int = 8, n_steps: int = 5000, axes=(40.0, 33.0, 30.0),
-                   radius: float = 2.0) -> RunSpec:
+                   radius: float = 2.0, ionic: str = "ms") -> RunSpec:
     """Left-atrium-like surface workload, after the paper's atrium example
     ("Best Practices" section; its surface timings are in "Performance
     measurements"): a closed ellipsoidal triangle surface (level 8: 655,362
-    nodes, close to the 660,557-node atrial mesh it reports), isotropic 0.4 S/m, the modified
-    Mitchell-Schaeffer parameters above, dt 0.01 ms, a 50 uA/cm^2 stimulus for
-    2 ms on the nodes within ``radius`` mm of the +x apex, absolute and
-    relative tolerance 1e-5 (relative to ||D^-1 b||)."""
+    nodes, close to the 660,557-node atrial mesh it reports), isotropic
+    0.4 S/m, dt 0.01 ms, a 50 uA/cm^2 stimulus for 2 ms on the nodes within
+    ``radius`` mm of the +x apex, absolute and relative tolerance 1e-5
+    (relative to ||D^-1 b||).  Cell model: the classic two-variable
+    Mitchell-Schaeffer with the atrial parameters above (``ionic="ms"``) or
+    the Courtemanche-Ramirez-Nattel atrial model (``"crn"``), the other
+    atrial model the paper names."""
     mesh = ellipsoid_surface(level, axes, fibres=False)
     apex = np.array([axes[0], 0.0, 0.0])
     nodes = np.flatnonzero(np.linalg.norm(mesh.xyz - apex, axis=1) <= radius).astype(np.int32)
     stim = Stimulus(nodes, 0.0, 2.0, 50.0 * UA_PER_CM2_TO_PER_MM2)
     return RunSpec(name=f"atrium_surface_{mesh.n_nodes}", mesh=mesh, sigma_l=0.4, sigma_t=0.4,
                    chi=1400 * PER_CM_TO_PER_MM, cm=1.0 * UF_PER_CM2_TO_PER_MM2, theta=0.5,
-                   ionic="ms", dt=0.01, n_steps=n_steps, stimuli=[stim], rtol=1e-5, atol=1e-5,
-                   rel_mode=1, max_iter=100, ionic_params=ATRIUM_MS_PARAMS)
+                   ionic=ionic, dt=0.01, n_steps=n_steps, stimuli=[stim], rtol=1e-5, atol=1e-5,
+                   rel_mode=1, max_iter=100,
+                   ionic_params=ATRIUM_MS_PARAMS if ionic == "ms" else None)
 
 
-def small_surface(level: int = 4, n_steps: int = 400, anisotropic: bool = True) -> RunSpec:
+def small_surface(level: int = 4, n_steps: int = 400, anisotropic: bool = True,
+                  ionic: str = "ms") -> RunSpec:
     """A small ellipsoidal surface for parity runs (level 4: 2,562 nodes,
     semi-axes 8 x 6.6 x 6 mm), tangent-projected azimuthal fibres with 0.4 /
-    0.1 S/m if ``anisotropic``, the atrial cell parameters, dt 0.01 ms."""
+    0.1 S/m if ``anisotropic``, dt 0.01 ms; Mitchell-Schaeffer with the atrial
+    parameters or (``ionic="crn"``) the Courtemanche-Ramirez-Nattel model."""
     axes = (8.0, 6.6, 6.0)
     mesh = ellipsoid_surface(level, axes, fibres=anisotropic)
     apex = np.array([axes[0], 0.0, 0.0])
@@ -666,8 +673,9 @@ def small_surface(level: int = 4, n_steps: int = 400, anisotropic: bool = True) 
     stim = Stimulus(nodes, 0.0, 2.0, 50.0 * UA_PER_CM2_TO_PER_MM2)
     return RunSpec(name=f"small_surface_{mesh.n_nodes}", mesh=mesh, sigma_l=0.4,
                    sigma_t=0.1 if anisotropic else 0.4, chi=1400 * PER_CM_TO_PER_MM,
-                   cm=1.0 * UF_PER_CM2_TO_PER_MM2, theta=0.5, ionic="ms", dt=0.01,
-                   n_steps=n_steps, stimuli=[stim], rtol=1e-10, ionic_params=ATRIUM_MS_PARAMS)
+                   cm=1.0 * UF_PER_CM2_TO_PER_MM2, theta=0.5, ionic=ionic, dt=0.01,
+                   n_steps=n_steps, stimuli=[stim], rtol=1e-10,
+                   ionic_params=ATRIUM_MS_PARAMS if ionic == "ms" else None)
 
 
 def batch_surfaces(n_inst: int = 4, levels=(3, 4), seed: int = 0, n_steps: int = 400,

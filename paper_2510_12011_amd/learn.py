@@ -41,11 +41,11 @@ def _p(t):
 
 
 def record(sim, n_steps: int, every: int = 10, front: float = 0.02, frac: float = 0.05,
-           seed: int = 0):
+           seed: int = 0, cap: int | None = None):
     """Advance `sim` by n_steps; on every `every`-th step record (raw
     features, V^{n+1} - V^n) of all nodes whose increment exceeds `front` mV
-    plus a random `frac` of the others.  Returns device tensors X [N, 4],
-    dV [N]."""
+    plus a random `frac` of the others (at most `cap` of them per recorded
+    step, drawn at random).  Returns device tensors X [N, 4], dV [N]."""
     import torch
     dev = f"cuda:{sim.device}"
     n = sim.n
@@ -64,6 +64,8 @@ def record(sim, n_steps: int, every: int = 10, front: float = 0.02, frac: float 
         sim._check(L.lib().mdx_set_recorder(sim._h, None, None, None))
         keep = (dVr.abs() > front) | (torch.rand(n, generator=g, device=dev) < frac)
         idx = keep.nonzero().squeeze(1)
+        if cap is not None and idx.numel() > cap:
+            idx = idx[torch.randperm(idx.numel(), generator=g, device=dev)[:cap]]
         xs.append(Xr[idx].clone())
         ds.append(dVr[idx].clone())
         done += skip + 1
@@ -138,3 +140,17 @@ def timed_run(sim, n_steps: int):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     return el, sim.iterations(n_steps), sim.stats()["fallbacks"] - f0
+
+
+def save(path: str, params: np.ndarray, norm: np.ndarray, **meta):
+    """Network and standardisation to an .npz (meta: scalars describing the
+    training run and the mesh it belongs to)."""
+    np.savez(path, params=np.asarray(params, np.float32), norm=np.asarray(norm, np.float64),
+             **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load(path: str):
+    """(params, norm, meta dict) from save()'s file."""
+    z = np.load(path, allow_pickle=False)
+    meta = {k: z[k].item() for k in z.files if k not in ("params", "norm")}
+    return z["params"].astype(np.float32), z["norm"].astype(np.float64), meta

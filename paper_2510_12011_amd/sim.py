@@ -27,7 +27,8 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-IONIC = {"none": L.MDX_IONIC_NONE, "ms": L.MDX_IONIC_MS, "tt": L.MDX_IONIC_TT}
+IONIC = {"none": L.MDX_IONIC_NONE, "ms": L.MDX_IONIC_MS, "tt": L.MDX_IONIC_TT,
+         "crn": L.MDX_IONIC_CRN}
 # theta of the integration schemes the paper tabulates
 THETA = {"forward_euler": 0.0, "crank_nicolson": 0.5, "galerkin": 2.0 / 3.0, "backward_euler": 1.0}
 

@@ -78,7 +78,21 @@ def _tt_states(n_samples=256):
     return np.array(Vs), np.stack(us, axis=1)
 
 
-@pytest.mark.parametrize("kind", ["ms", "tt"])
+def _crn_states(n_samples=256):
+    """Physiological CRN states along a single-cell action potential (oracle)."""
+    V, u = orc.ionic_init("crn", 1)
+    Vs, us = [], []
+    dt = 0.01
+    for k in range(40000):
+        iion = orc.ionic_step("crn", V, u, dt)
+        V = V + dt * ((20.0 if k < 200 else 0.0) - iion)
+        if k % (40000 // n_samples) == 0 or (k < 600 and k % 10 == 0):
+            Vs.append(V[0])
+            us.append(u[:, 0].copy())
+    return np.array(Vs), np.stack(us, axis=1)
+
+
+@pytest.mark.parametrize("kind", ["ms", "tt", "crn"])
 def test_ionic_step_parity(kind):
     import torch
     from paper_2510_12011_amd import sim
@@ -90,9 +104,11 @@ def test_ionic_step_parity(kind):
         V = rng.uniform(-95.0, 30.0, n)
         u = rng.uniform(0.0, 1.0, (1, n))
     else:
-        V, u = _tt_states()
-        V = np.concatenate([V, V + rng.normal(0, 2.0, V.shape[0]), [15.0, -40.0]])
-        u = np.concatenate([u, u, u[:, :2]], axis=1)
+        V, u = _tt_states() if kind == "tt" else _crn_states()
+        # also the removable singularities of the rate expressions
+        extra = [15.0, -40.0] if kind == "tt" else [-47.13, -14.1, 3.3328, 19.9, -10.0, 7.9]
+        V = np.concatenate([V, V + rng.normal(0, 2.0, V.shape[0]), extra])
+        u = np.concatenate([u, u, u[:, :len(extra)]], axis=1)
         u = np.ascontiguousarray(u)
     n = V.shape[0]
     for dt in (0.01, 0.02):

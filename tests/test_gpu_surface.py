@@ -69,6 +69,30 @@ def test_surface_trajectory_parity(precision, bar):
     _lat_check(s, o, spec.dt)
 
 
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-9), ("mixed", 1e-5)])
+def test_surface_trajectory_parity_crn(precision, bar):
+    """The same surface with the Courtemanche-Ramirez-Nattel atrial cell
+    (the atrial workload's second cell model), 1,500 steps of 0.01 ms (the
+    wave's spread from the apex), against the oracle; the gates-in-FP32
+    precision variant is refused for this model."""
+    from paper_2510_12011_amd import _lib as L
+    spec = inputs.small_surface(4, n_steps=1500, ionic="crn")
+    s = _sim(spec, precision=precision)
+    o = orc.Oracle(spec)
+    v_or, _ = o.steps(1500, out_every=500)
+    v_gpu, status = s.run(1500, out_every=500)
+    assert status == 0
+    errs = [_rel_l2(a, b) for a, b in zip(v_gpu, v_or)]
+    print(f"  CRN {precision}: V rel L2 max {max(errs):.2e}, activated "
+          f"{int(np.isfinite(o.state.lat).sum())} of {spec.mesh.n_nodes}", flush=True)
+    assert max(errs) <= bar, errs
+    assert np.isfinite(o.state.lat).sum() > 100
+    _lat_check(s, o, spec.dt)
+    s.set_solver(spec.atol, spec.rtol, spec.rel_mode, spec.max_iter, 1, L.MDX_PREC_MIXED_GATES32,
+                 50)
+    assert L.lib().mdx_run(s._h, 1, 0, None) == L.MDX_ERR_UNSUPPORTED
+
+
 def test_atrial_surface_full_size_prefix():
     """The 655,362-node atrial surface: the first 100 steps (stimulus on) at
     rtol 1e-10 against the oracle, iteration counts within one."""

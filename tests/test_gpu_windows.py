@@ -1,0 +1,151 @@
+"""Long windows that contain the wavefront, against stored oracle results
+(tests/golden/*.npz, written by tests/golden/make_golden.py from the CPU
+oracle alone): activation times and V on a seeded sample of nodes.
+
+  slab_h0.1          442,401-node slab, ten Tusscher-Panfilov, its full
+                     10,000 steps, plain FP64 (bar 1e-9, LAT within one dt)
+  cohort4            the four smallest instances of the 64-shell batched
+                     cohort, their full 5,000 steps, batched mixed precision
+                     in the storage layouts the autotuner chooses among (bar
+                     1e-5, LAT within one dt)
+  slab_h0.05_prefix  the 3.45M-node precision workload, first 50 ms, mixed
+  shell_prefix       the learned workload's shell, held-out site 101, first
+                     50 ms: plain FP64 and learned + mixed with the committed
+                     network
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2510_12011_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    z = np.load(os.path.join(GOLDEN, f"{name}.npz"), allow_pickle=False)
+    out = {}
+    for k in z.files:
+        grp, key = k.split("/")
+        out.setdefault(grp, {})[key] = z[k]
+    return out
+
+
+def _sim(spec, precision):
+    from paper_2510_12011_amd import sim
+    print(f"[case] {spec.name} n={spec.mesh.n_nodes} {precision}", flush=True)
+    return sim.from_spec(spec, precision=precision)
+
+
+def _compare(tag, V, lat, g, v_bar, dt, max_flips=2):
+    nodes = g["nodes"]
+    v, l = V[nodes], lat[nodes]
+    err = np.linalg.norm(v - g["V"]) / np.linalg.norm(g["V"])
+    fa, fb = np.isfinite(l), np.isfinite(g["lat"])
+    both = fa & fb
+    dl = float(np.abs(l[both] - g["lat"][both]).max()) if both.any() else 0.0
+    print(f"  {tag}: V rel L2 {err:.2e} on {nodes.size} nodes, LAT max diff {dl:g} ms, "
+          f"{int(both.sum())} activated, {int((fa != fb).sum())} activation flips", flush=True)
+    assert err <= v_bar, err
+    assert (fa != fb).sum() <= max_flips
+    assert dl <= dt * (1 + 1e-9)
+    assert both.sum() > 0
+
+
+def test_slab_full_length_matches_oracle():
+    g = _golden("slab_h0.1")["slab"]
+    spec = inputs.slab(h=0.1)
+    steps = int(g["steps"])
+    s = _sim(spec, "fp64")
+    _, st = s.run(steps)
+    assert st == 0
+    lat, _ = s.times()
+    V = s.get_state()["V"]
+    it = s.iterations(steps)
+    print(f"  iterations: GPU mean {it.mean():.3f}, oracle {g['iters'].mean():.3f}; steps "
+          f"differing {int((it != g['iters']).sum())}", flush=True)
+    assert abs(it.mean() - g["iters"].mean()) <= 0.01
+    assert np.abs(it - g["iters"]).max() <= 1
+    _compare("slab h0.1 fp64 10,000 steps", V, lat, g, 1e-9, spec.dt, max_flips=0)
+    assert int(np.isfinite(lat).sum()) == int(g["n_activated"])
+
+
+@pytest.mark.parametrize("layout", ["sell", "sell4nt", "csr", "graph"])
+def test_cohort_smallest_instances_match_oracle(layout):
+    from paper_2510_12011_amd import sim
+    g = _golden("cohort4")
+    t = inputs.cohort_targets()
+    small = [int(i) for i in np.argsort(t)[:4]]
+    b = inputs.batch_shells(only=small)
+    steps = int(g[f"inst{small[0]}"]["steps"])
+    print(f"[case] cohort4 {layout}: instances {small}, {b.n_nodes} nodes", flush=True)
+    s = sim.batch_from_spec(b)
+    if layout == "sell4nt":
+        s.set_tuning(fmt="sell4nt")
+    elif layout == "csr":
+        s.set_tuning(fmt="csr")
+        s.set_tuning(lanes_per_row=8)
+    elif layout == "graph":
+        s.set_tuning(graph=True)
+    _, st = s.run(steps)
+    assert st == 0
+    state = s.get_state()
+    lat, _ = s.times()
+    ptr = b.node_ptr()
+    for k, i in enumerate(small):
+        gi = g[f"inst{i}"]
+        assert int(gi["n_nodes"]) == ptr[k + 1] - ptr[k]
+        sl = slice(ptr[k], ptr[k + 1])
+        _compare(f"instance {i} ({layout})", state["V"][sl], lat[sl], gi, 1e-5, b.dt)
+
+
+def _needs(name):
+    if not os.path.exists(os.path.join(GOLDEN, f"{name}.npz")):
+        pytest.skip(f"tests/golden/{name}.npz not written (make_golden.py {name})")
+
+
+def test_precision_slab_prefix_matches_oracle():
+    _needs("slab_h0.05_prefix")
+    g = _golden("slab_h0.05_prefix")["slab"]
+    spec = inputs.slab_precision(h=0.05, precision="mixed")
+    steps = int(g["steps"])
+    s = _sim(spec, "mixed")
+    _, st = s.run(steps)
+    assert st == 0
+    lat, _ = s.times()
+    V = s.get_state()["V"]
+    _compare("slab h0.05 mixed, 50 ms", V, lat, g, 1e-5, spec.dt,
+             max_flips=max(2, int(1e-4 * g["nodes"].size)))
+
+
+@pytest.mark.parametrize("form", ["fp64", "learned_mixed"])
+def test_shell_prefix_matches_oracle(form):
+    _needs("shell_prefix")
+    from paper_2510_12011_amd import _lib as L, learn
+    g = _golden("shell_prefix")["shell"]
+    steps = int(g["steps"])
+    spec = inputs.shell_run(ionic="tt", dt=0.02, n_steps=steps, site_seed=101, rtol=1e-10)
+    if form == "fp64":
+        s = _sim(spec, "fp64")
+    else:
+        weights = os.path.join(os.path.dirname(GOLDEN), "..", "paper_2510_12011_amd", "weights",
+                               "shell_tt_dt0.02.npz")
+        params, norm, meta = learn.load(weights)
+        assert int(meta["n_nodes"]) == spec.mesh.n_nodes
+        s = _sim(spec, "mixed")
+        learn.install(s, params, norm)
+        s.set_solver(0.0, spec.rtol, 1, 1000, L.MDX_WS_MLP, 1, 50)
+    _, st = s.run(steps)
+    assert st == 0
+    lat, _ = s.times()
+    V = s.get_state()["V"]
+    if form == "fp64":
+        _compare("shell fp64, 50 ms", V, lat, g, 1e-9, spec.dt, max_flips=0)
+    else:
+        fb = s.stats()["fallbacks"]
+        print(f"  learned: fallbacks {fb} of {steps}", flush=True)
+        _compare("shell learned + mixed, 50 ms", V, lat, g, 1e-5, spec.dt)
+        assert fb < steps // 2

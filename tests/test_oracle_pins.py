@@ -290,10 +290,15 @@ def test_ms_current_closed_form():
 def _single_cell(kind, t_end, dt=0.01, stim=50.0, dur=2.0):
     V, u = orc.ionic_init(kind, 1)
     Vs = np.empty(int(round(t_end / dt)))
-    for k in range(Vs.shape[0]):
-        iion = orc.ionic_step(kind, V, u, dt)
-        V = V + dt * ((stim if k * dt < dur else 0.0) - iion)
-        Vs[k] = V[0]
+    threads = orc.threads()
+    orc.lib().orc_set_threads(1)      # one cell: no thread team per step
+    try:
+        for k in range(Vs.shape[0]):
+            iion = orc.ionic_step(kind, V, u, dt)
+            V = V + dt * ((stim if k * dt < dur else 0.0) - iion)
+            Vs[k] = V[0]
+    finally:
+        orc.lib().orc_set_threads(threads)
     return Vs, u
 
 
@@ -322,6 +327,33 @@ def test_tt_qualitative_action_potential():
     rep = up + np.argmax(Vs[up + 500:] < lo + 0.1 * (Vs.max() - lo)) + 500
     assert 200.0 < t[rep] - t[up] < 400.0
     assert np.isfinite(u).all()
+
+
+def test_crn_qualitative_action_potential():
+    """Courtemanche-Ramirez-Nattel (parity unpinned against the literature:
+    qualitative pins of the published human atrial cell): the published
+    initial state is at rest (-81.2 mV held for 1 s unstimulated); a 2 ms
+    20 pA/pF pulse gives an upstroke overshooting 0 mV, a spike-and-dome
+    shape (a notch after the spike, then a plateau dome), APD90 of about
+    300 ms at 1 Hz and a return towards rest; gates stay in [0, 1] and the
+    concentrations positive."""
+    Vr, ur = _single_cell("crn", 1000.0, stim=0.0)
+    assert np.abs(Vr + 81.18).max() < 0.05
+    Vs, u = _single_cell("crn", 1000.0, stim=20.0, dur=2.0)
+    t = np.arange(Vs.shape[0]) * 0.01
+    assert 15.0 < Vs.max() < 35.0
+    assert t[Vs.argmax()] < 5.0
+    notch = Vs[(t > 5) & (t < 40)].min()
+    dome = Vs[(t > 40) & (t < 200)].max()
+    assert notch < -5.0 and dome > notch + 1.0
+    up = np.argmax(Vs > -40.0)
+    lo = Vs[-1]
+    rep = up + 500 + np.argmax(Vs[up + 500:] < Vs.max() - 0.9 * (Vs.max() - lo))
+    assert 250.0 < t[rep] - t[up] < 350.0
+    assert -82.0 < Vs[-1] < -79.0
+    assert np.isfinite(u).all() and np.isfinite(ur).all()
+    assert ((u[5:] >= 0.0) & (u[5:] <= 1.0)).all()
+    assert (u[:5] > 0.0).all()
 
 
 def test_symmetry_under_axis_permutations():
