@@ -31,9 +31,15 @@ FLAGS = [
 ]
 
 
+# per-source code generation options: the network's kernels keep the matrix
+# cores' accumulators in ordinary vector registers (the ReLU and BF16
+# conversion then read them without a copy out of the accumulation registers)
+FILE_FLAGS = {"mdx_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

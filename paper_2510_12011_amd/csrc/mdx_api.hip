@@ -1720,7 +1720,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     double *dinv = ctx->dev<double>(L.dinv);
     double *r = ctx->dev<double>(L.r), *q = ctx->dev<double>(L.q);
     double *pbuf[2] = {ctx->dev<double>(L.p), ctx->dev<double>(L.p2)};
-    double *b = ctx->dev<double>(L.b), *s = ctx->dev<double>(L.s);
+    double *s = ctx->dev<double>(L.s);
     double *u = ionic_nstates(ctx->ionic_kind) ? ctx->dev<double>(L.u) : nullptr;
     double *part0 = ctx->dev<double>(L.partial);
     double *part_pq = part0 + 3 * kPartialCap, *part_rz = part0 + 6 * kPartialCap;
@@ -1793,14 +1793,25 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             if (ctx->rec_y)
                 HIPCHK(hipMemcpyAsync(ctx->rec_y, mlp_y, sizeof(float) * ctx->n,
                                       hipMemcpyDeviceToDevice, st));
-            // r_ex (the extrapolation's residual) goes to the FP64 q buffer,
-            // free until the iteration starts
-            launch_rhs_learned(st, T, P, Mv, Kv, kdiag, dinv, sp, ctx->mlp_norm.out_scale, V,
-                               Vprev, s, mlp_y, b, X, r, q, kvp, mixed ? 1 : 0, part_pq, part0,
-                               nt_rhs);
+            launch_rhs_learned(st, T, P, Mv, Kv, kdiag, dinv, dinv32, sp,
+                               ctx->mlp_norm.out_scale, V, Vprev, s, mlp_y, X, r, p0_fp64,
+                               mixed ? r32 : nullptr, z32, delta, kvp, part_pq, part0, nt_rhs);
             launch_init_finalize_ws(st, T, part_pq, part0, sp.rel_mode, sc);
-            launch_select(st, ctx->npad, V, Vprev, q, X, r, dinv, p0_fp64, dinv32,
-                          mixed ? r32 : nullptr, z32, delta, sc);
+            // where the extrapolation's residual was the smaller, its start
+            // vectors (the scalars are already its own, from the same pass):
+            // one pass on a small grid, which returns at once, and cheaply,
+            // when the network's guess is taken
+            StepParams ex = sp;
+            ex.warm_start = MDX_WS_EXTRAP;
+            const Tiling TF = make_tiling(ctx->npad, 256);
+            const int32_t *lost = &sc->use_mlp;
+            double *part_unused = part0 + 3 * kPartialCap;   // no reader
+            if (mixed)
+                launch_rhs_init_mixed(st, TF, P, Mv, Kv, dinv, dinv32, ex, V, Vprev, s, X, r, r32,
+                                      z32, delta, part_unused, kdiag, nullptr, nt_rhs, lost);
+            else
+                launch_rhs_init(st, TF, P, Mv, Kv, dinv, ex, V, Vprev, s, X, r, part_unused,
+                                kdiag, nullptr, p0_fp64, nt_rhs, lost);
         } else {
             if (ctx->rec_X)   // training-data recorder: raw features
                 launch_features(st, ctx->n, ctx->n, V, Vprev, s, kvp, ctx->cm, ctx->mlp_norm,
@@ -1810,7 +1821,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                 launch_rhs_init_mixed(st, T, P, Mv, Kv, dinv, dinv32, sp, V, Vprev, s, X, r, r32,
                                       z32, delta, part0, kdiag, kvp_out, nt_rhs);
             else
-                launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, b, part0, kdiag,
+                launch_rhs_init(st, T, P, Mv, Kv, dinv, sp, V, Vprev, s, X, r, part0, kdiag,
                                 kvp_out, p0_fp64, nt_rhs);
             launch_init_finalize(st, T, part0, sp.rel_mode, sc);
         }

@@ -163,7 +163,8 @@ void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const dou
                            const double *Kv, const double *dinv, const float *dinv32,
                            const StepParams &sp, const double *V, const double *Vprev,
                            const double *src, double *x, double *r64, float *r32, float *z32,
-                           float *delta, double *partial, const double *kdiag, float *kvp, bool nt);
+                           float *delta, double *partial, const double *kdiag, float *kvp, bool nt,
+                           const int32_t *skip = nullptr);
 // PCG iteration k of the FP32 form: SpMV on the tiling ts (q = A z + beta q,
 // p = z + beta p, partial p.q), alpha, update on t (delta, r, z, partials
 // r.z, z.z), stopping test of ||z_{k+1}|| and beta.  Events (optional) are
@@ -212,24 +213,20 @@ void launch_kv_feature(hipStream_t s, const Tiling &t, SellView P, const double 
 void launch_features(hipStream_t s, int64_t n_real, int64_t n_rows, const double *V,
                      const double *Vprev, const double *src, const float *kvp, double cm,
                      const MlpNorm &nm, float *feat, float *raw);
-// one pass over M and K: b, x_mlp = 2V - V_prev + scale y, r_mlp = b - A x_mlp
-// (into r_mlp), r_ex = b - A (2V - V_prev) (into r_ex), kvp = (K V)_i / K_ii
-// for the next step; partials r.z, z.z of both (FP32-rounded first if
-// fp32_iter) into part4 and |D^-1 b|^2 into part1
+// one pass over M and K: x = 2V - V_prev + scale y and its residual r = b - A x,
+// the FP32 residual, z and zero correction (r32 non-null: FP32 iteration) or
+// p0 = D^-1 r (FP64, p0 may be null), kvp = (K V)_i / K_ii for the next step;
+// partials r.z, z.z of x and of 2V - V_prev (FP32-rounded in the FP32
+// iteration) into part4 and |D^-1 b|^2 into part1
 void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                         const double *Kv, const double *kdiag, const double *dinv,
-                        const StepParams &sp, float out_scale, const double *V,
-                        const double *Vprev, const double *src, const float *y, double *b,
-                        double *x, double *r_mlp, double *r_ex, float *kvp, int fp32_iter,
-                        double *part4, double *part1, bool nt);
+                        const float *dinv32, const StepParams &sp, float out_scale,
+                        const double *V, const double *Vprev, const double *src, const float *y,
+                        double *x, double *r, double *p0, float *r32, float *z32, float *delta,
+                        float *kvp, double *part4, double *part1, bool nt);
+// chooses the guess (sc->use_mlp) and sets the scalars of its PCG start
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
                              int rel_mode, Scalars *sc);
-// the chosen guess: the extrapolation's x and r where the network's residual
-// was not the smaller; p0 = z0 (FP64 iteration) or the FP32 residual, z and
-// correction
-void launch_select(hipStream_t s, int64_t n, const double *V, const double *Vprev,
-                   const double *r_ex, double *x, double *r, const double *dinv, double *p0,
-                   const float *dinv32, float *r32, float *z32, float *delta, const Scalars *sc);
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv);
 
 // ---- batched form (mdx_batch.hip) -----------------------------------------
@@ -338,17 +335,19 @@ void launch_b_spmv(hipStream_t s, const SegTiling &t, const IterMatrix &A,
 void launch_fill(hipStream_t s, int64_t n, double v, double *x);
 void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double amp, double *istim);
 // b, x0, r0 = b - A x0 and the partials (r.z, z.z, |D^-1 b|^2), z = D^-1 r
+// skip (optional): the kernels return at once while *skip is non-zero (the
+// learned warm start's fallback pass, run only where the network lost)
 void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                      const double *Kv, const double *dinv, const StepParams &sp,
                      const double *V, const double *Vprev, const double *src, double *x,
-                     double *r, double *b, double *partial, const double *kdiag, float *kvp,
-                     double *p0, bool nt);
+                     double *r, double *partial, const double *kdiag, float *kvp, double *p0,
+                     bool nt, const int32_t *skip = nullptr);
 // standalone solve: r = b - A x, p0 = z = D^-1 r, partials as the RHS pass
 void launch_residual_init(hipStream_t s, const Tiling &t, SellView P, const double *Av,
                           const double *dinv, const double *b, const double *x, double *r,
                           double *p0, double *partial);
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
-                          Scalars *sc);
+                          Scalars *sc, const int32_t *skip = nullptr);
 // q = A p with partial p.q (no convergence logic; `done` non-zero skips it).
 // ev_start/ev_stop: optional events recorded around the dispatch
 void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *Av,

@@ -8,11 +8,12 @@
 // y predicts the departure of V^{n+1} from the paper's extrapolation:
 // x_mlp = x_ex + out_scale * y, x_ex = 2V^n - V^{n-1}.  Because the
 // aggregate is the previous step's, the network runs before the right-hand
-// side, and one pass over M and K then forms b, the initial residuals of
-// both x_mlp and x_ex, and the next step's aggregate.  The MLP guess is used
+// side, and one pass over M and K then forms the initial residual of x_mlp
+// (with the vectors the iteration starts from), the norms of both x_mlp's and
+// x_ex's residuals, and the next step's aggregate.  The MLP guess is used
 // only if its ||D^-1 r0|| is smaller (and finite), otherwise the
-// extrapolation is (the fallback): the network can only lower the initial
-// residual of the method without it.
+// extrapolation is (the fallback, whose vectors a guarded pass then forms):
+// the network can only lower the initial residual of the method without it.
 //
 // k_features also serves as the recorder of training data: raw features of
 // every node, and after the solve the increment V^{n+1} - V^n.
@@ -74,19 +75,24 @@ __global__ __launch_bounds__(256) void k_features(int64_t n_real, int64_t n_rows
     }
 }
 
-// b = chi M (Cm V + dt s) - (1-theta) dt K V;  with e = V - V_prev the
-// extrapolation x_ex = V + e has A x_ex = chi Cm M (V + e) + theta dt K (V + e);
-// r_ex = b - A x_ex;  r_mlp = r_ex - scale A y;  x = x_ex + scale y.
-// Partials: r_mlp.z_mlp, |z_mlp|^2, r_ex.z_ex, |z_ex|^2 (FP32-rounded
-// residuals when the iteration runs in FP32) and |D^-1 b|^2.
+// b = chi M (Cm V + dt s) - (1-theta) dt K V;  the extrapolation
+// x_ex = 2V - V_prev has A x_ex = chi Cm M x_ex + theta dt K x_ex and
+// r_ex = b - A x_ex;  the network's guess x = x_ex + scale y has
+// r = r_ex - scale A y, which is what the pass stores, with what the
+// iteration starts from: the FP32 residual, z and correction (FP32
+// iteration) or z0 = D^-1 r (FP64 iteration; p0 may be null).  Partials:
+// r.z, |z|^2 of the guess and of the extrapolation (FP32-rounded residuals
+// when the iteration runs in FP32), |D^-1 b|^2.  Where the extrapolation
+// wins, a guarded pass recomputes its x and r (k_rhs_init*).
 template <bool NT, typename CI>
 __global__ __launch_bounds__(256) void k_rhs_learned(
     Tiling t, const int64_t *__restrict__ slice_ptr, Cols<CI> col,
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ kdiag,
-    const double *__restrict__ dinv, StepParams sp, float out_scale, const double *__restrict__ V,
-    const double *__restrict__ Vprev, const double *__restrict__ src,
-    const float *__restrict__ y, double *__restrict__ b, double *__restrict__ x,
-    double *__restrict__ r_mlp, double *__restrict__ r_ex, float *__restrict__ kvp, int fp32_iter,
+    const double *__restrict__ dinv, const float *__restrict__ dinv32, StepParams sp,
+    float out_scale, const double *__restrict__ V, const double *__restrict__ Vprev,
+    const double *__restrict__ src, const float *__restrict__ y, double *__restrict__ x,
+    double *__restrict__ r, double *__restrict__ p0, float *__restrict__ r32,
+    float *__restrict__ z32, float *__restrict__ delta, float *__restrict__ kvp,
     double *__restrict__ part4, double *__restrict__ part1)
 {
     const int g = logical_group(t.groups);
@@ -95,6 +101,7 @@ __global__ __launch_bounds__(256) void k_rhs_learned(
     const double cM_new = sp.chi * sp.cm;
     const double cK_new = sp.theta * sp.dt;
     const double scale = (double)out_scale;
+    const bool fp32_iter = r32 != nullptr;
     double acc[4] = {0.0, 0.0, 0.0, 0.0}, accb[1] = {0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
@@ -102,38 +109,41 @@ __global__ __launch_bounds__(256) void k_rhs_learned(
         const int64_t row = sl * SLICE + lane;
         const int64_t b0 = slice_ptr[sl];
         const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
-        double mv = 0.0, ms = 0.0, kv = 0.0, me = 0.0, ke = 0.0, my = 0.0, ky = 0.0;
+        // M (Cm V + dt s), K V, M x_ex, K x_ex, M y, K y
+        double mb = 0.0, kv = 0.0, mx = 0.0, kx = 0.0, my = 0.0, ky = 0.0;
         sell_row2<8, NT>(w, col.idx + b0 + lane, Mv + b0 + lane, Kv + b0 + lane,
                          slice_base(col, sl), [&](int32_t c, double m, double kk) {
-                             const double vj = V[c], ej = vj - Vprev[c], yj = (double)y[c];
-                             mv += m * vj;
-                             ms += m * src[c];
+                             const double vj = V[c], xj = 2.0 * vj - Vprev[c];
+                             const double yj = (double)y[c];
+                             mb += m * (sp.cm * vj + sp.dt * src[c]);
                              kv += kk * vj;
-                             me += m * ej;
-                             ke += kk * ej;
+                             mx += m * xj;
+                             kx += kk * xj;
                              my += m * yj;
                              ky += kk * yj;
                          });
-        const double bi = sp.chi * (sp.cm * mv + sp.dt * ms) - cK_old * kv;
-        const double rx = bi - (cM_new * (mv + me) + cK_new * (kv + ke));
+        const double bi = sp.chi * mb - cK_old * kv;
+        const double rx = bi - (cM_new * mx + cK_new * kx);
         const double rm = rx - scale * (cM_new * my + cK_new * ky);
         const double vi = V[row];
-        b[row] = bi;
         x[row] = (2.0 * vi - Vprev[row]) + scale * (double)y[row];
-        r_mlp[row] = rm;
-        r_ex[row] = rx;
+        r[row] = rm;
         const double kd = kdiag[row];
         kvp[row] = kd != 0.0 ? (float)(kv / kd) : 0.0f;
         const double di = dinv[row];
         if (fp32_iter) {
-            const float rmf = (float)rm, rxf = (float)rx, df = (float)di;
+            const float rmf = (float)rm, rxf = (float)rx, df = dinv32[row];
             const float zmf = df * rmf, zxf = df * rxf;
+            r32[row] = rmf;
+            z32[row] = zmf;
+            delta[row] = 0.0f;
             acc[0] += (double)rmf * (double)zmf;
             acc[1] += (double)zmf * (double)zmf;
             acc[2] += (double)rxf * (double)zxf;
             acc[3] += (double)zxf * (double)zxf;
         } else {
             const double zm = di * rm, zx = di * rx;
+            if (p0) p0[row] = zm;
             acc[0] += rm * zm;
             acc[1] += zm * zm;
             acc[2] += rx * zx;
@@ -174,34 +184,6 @@ __global__ __launch_bounds__(256) void k_init_finalize_ws(int groups, const doub
     sc->replace = 0;
     sc->beta = 0.0;
     sc->it_next = 0;
-}
-
-// fallback: x = 2V - V_prev, r = r_ex; then the FP32 residual, z = D^-1 r and
-// the correction if the iteration runs in FP32
-__global__ __launch_bounds__(256) void k_select(int64_t n, const double *__restrict__ V,
-                                                const double *__restrict__ Vprev,
-                                                const double *__restrict__ r_ex,
-                                                double *__restrict__ x, double *__restrict__ r,
-                                                const double *__restrict__ dinv,
-                                                double *__restrict__ p0,
-                                                const float *__restrict__ dinv32,
-                                                float *__restrict__ r32, float *__restrict__ z32,
-                                                float *__restrict__ delta,
-                                                const Scalars *__restrict__ sc)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (!sc->use_mlp) {
-        x[i] = 2.0 * V[i] - Vprev[i];
-        r[i] = r_ex[i];
-    }
-    if (p0) p0[i] = dinv[i] * r[i];   // FP64 iteration: the first direction p0 = z0
-    if (r32) {
-        const float rf = (float)r[i];
-        r32[i] = rf;
-        z32[i] = dinv32[i] * rf;
-        delta[i] = 0.0f;
-    }
 }
 
 __global__ __launch_bounds__(256) void k_record_dv(int64_t n, const double *__restrict__ Vold,
@@ -259,28 +241,20 @@ void launch_features(hipStream_t s, int64_t n_real, int64_t n_rows, const double
 
 void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                         const double *Kv, const double *kdiag, const double *dinv,
-                        const StepParams &sp, float out_scale, const double *V,
-                        const double *Vprev, const double *src, const float *y, double *b,
-                        double *x, double *r_mlp, double *r_ex, float *kvp, int fp32_iter,
-                        double *part4, double *part1, bool nt)
+                        const float *dinv32, const StepParams &sp, float out_scale,
+                        const double *V, const double *Vprev, const double *src, const float *y,
+                        double *x, double *r, double *p0, float *r32, float *z32, float *delta,
+                        float *kvp, double *part4, double *part1, bool nt)
 {
     MDX_LAUNCH_SELL(P, nt, k_rhs_learned, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols, Mv,
-                    Kv, kdiag, dinv, sp, out_scale, V, Vprev, src, y, b, x, r_mlp, r_ex, kvp,
-                    fp32_iter, part4, part1);
+                    Kv, kdiag, dinv, dinv32, sp, out_scale, V, Vprev, src, y, x, r, p0, r32, z32,
+                    delta, kvp, part4, part1);
 }
 
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
                              int rel_mode, Scalars *sc)
 {
     hipLaunchKernelGGL(k_init_finalize_ws, dim3(1), dim3(TILE), 0, s, t.groups, p4, p1, rel_mode, sc);
-}
-
-void launch_select(hipStream_t s, int64_t n, const double *V, const double *Vprev,
-                   const double *r_ex, double *x, double *r, const double *dinv, double *p0,
-                   const float *dinv32, float *r32, float *z32, float *delta, const Scalars *sc)
-{
-    hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(256), 0, s, n, V, Vprev, r_ex, x, r,
-                       dinv, p0, dinv32, r32, z32, delta, sc);
 }
 
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv)

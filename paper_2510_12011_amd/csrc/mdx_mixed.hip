@@ -67,8 +67,9 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
     const double *__restrict__ Vprev, const double *__restrict__ src, double *__restrict__ x,
     double *__restrict__ r64, float *__restrict__ r32, float *__restrict__ z32,
     float *__restrict__ delta, double *__restrict__ partial, const double *__restrict__ kdiag,
-    float *__restrict__ kvp)
+    float *__restrict__ kvp, const int32_t *__restrict__ skip)
 {
+    if (skip && *skip) return;   // the learned guess was taken: nothing to redo
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
     const double cK_old = (1.0 - sp.theta) * sp.dt;
@@ -333,11 +334,12 @@ void launch_rhs_init_mixed(hipStream_t s, const Tiling &t, SellView P, const dou
                            const double *Kv, const double *dinv, const float *dinv32,
                            const StepParams &sp, const double *V, const double *Vprev,
                            const double *src, double *x, double *r64, float *r32, float *z32,
-                           float *delta, double *partial, const double *kdiag, float *kvp, bool nt)
+                           float *delta, double *partial, const double *kdiag, float *kvp, bool nt,
+                           const int32_t *skip)
 {
     MDX_LAUNCH_SELL(P, nt, k_rhs_init_mixed, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
                     Mv, Kv, dinv, dinv32, sp, V, Vprev, src, x, r64, r32, z32, delta, partial, kdiag,
-                    kvp);
+                    kvp, skip);
 }
 
 void launch_cg_iteration32(hipStream_t s, const Tiling &ts, const Tiling &t, int k, int rr,

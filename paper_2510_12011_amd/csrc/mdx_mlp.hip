@@ -211,6 +211,22 @@ __device__ __forceinline__ bf16x4 pack_bf16x4(float a, float b, float c, float d
     u32x2 u = {pack_bf16(a, b), pack_bf16(c, d)};
     return __builtin_bit_cast(bf16x4, u);
 }
+// bf16(relu(a)), ... for four values: ReLU after the rounding, on the packed
+// pairs as signed 16-bit integers (a BF16 value is negative exactly when its
+// bit pattern is, and rounding to nearest keeps the sign, so max(bits, 0)
+// maps negatives, -0 included, to +0 and keeps the rest)
+typedef short s16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned relu_bf16x2(float a, float b)
+{
+    const s16x2v zero = {0, 0};
+    const s16x2v v = __builtin_bit_cast(s16x2v, pack_bf16(a, b));
+    return __builtin_bit_cast(unsigned, __builtin_elementwise_max(v, zero));
+}
+__device__ __forceinline__ bf16x4 relu_pack_bf16x4(float a, float b, float c, float d)
+{
+    u32x2 u = {relu_bf16x2(a, b), relu_bf16x2(c, d)};
+    return __builtin_bit_cast(bf16x4, u);
+}
 
 struct alignas(16) InferLds {
     float b1[NH], b2[NH], b3[NH], w4[NH];   // FP32 biases, BF16-rounded w4
@@ -291,7 +307,7 @@ struct FeatIn {
 };
 
 template <bool STATE>
-__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P, int64_t n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_mlp_forward(const float *__restrict__ P, int64_t n,
                                                      FeatIn in, float *__restrict__ y)
 {
     __shared__ InferLds w;
@@ -363,9 +379,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P
                 const f32x16 acc = mfma16(a, xb[b], bias);
 #pragma unroll
                 for (int g = 0; g < 4; ++g)
-                    h1[b][4 * ot + g] =
-                        pack_bf16x4(fmaxf(acc[4 * g], 0.f), fmaxf(acc[4 * g + 1], 0.f),
-                                    fmaxf(acc[4 * g + 2], 0.f), fmaxf(acc[4 * g + 3], 0.f));
+                    h1[b][4 * ot + g] = relu_pack_bf16x4(acc[4 * g], acc[4 * g + 1],
+                                                         acc[4 * g + 2], acc[4 * g + 3]);
             }
         }
         // layer 2
@@ -385,9 +400,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ P
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int g = 0; g < 4; ++g)
-                    h2[b][4 * ot + g] =
-                        pack_bf16x4(fmaxf(acc[b][4 * g], 0.f), fmaxf(acc[b][4 * g + 1], 0.f),
-                                    fmaxf(acc[b][4 * g + 2], 0.f), fmaxf(acc[b][4 * g + 3], 0.f));
+                    h2[b][4 * ot + g] = relu_pack_bf16x4(acc[b][4 * g], acc[b][4 * g + 1],
+                                                         acc[b][4 * g + 2], acc[b][4 * g + 3]);
         }
         // layer 3 and the output unit
         float sum[2] = {0.0f, 0.0f};

@@ -2,7 +2,8 @@
 //
 // One time step (the paper's Eq. 2 and the definitions of A and b after
 // Eq. 3, Jacobi-PCG of Algorithm 1):
-//   rhs_init      b = chi M (Cm V^k + dt s) - (1-theta) dt K V^k,  s = I_stim - I_ion,
+//   rhs_init      b = chi M (Cm V^k + dt s) - (1-theta) dt K V^k,  s = I_stim - I_ion
+//                 (formed per row, not stored),
 //                 x0 = 2V^k - V^{k-1} (or V^k), r0 = b - A x0 with
 //                 A x0 = chi Cm (M x0) + theta dt (K x0), p0 = z0 = D^-1 r0,
 //                 per-workgroup partials of r.z, z.z, |D^-1 b|^2
@@ -76,9 +77,10 @@ __global__ __launch_bounds__(256) void k_rhs_init(
     const double *__restrict__ Mv, const double *__restrict__ Kv, const double *__restrict__ dinv,
     StepParams sp, const double *__restrict__ V, const double *__restrict__ Vprev,
     const double *__restrict__ src, double *__restrict__ x, double *__restrict__ r,
-    double *__restrict__ b, double *__restrict__ partial, const double *__restrict__ kdiag,
-    float *__restrict__ kvp, double *__restrict__ p0)
+    double *__restrict__ partial, const double *__restrict__ kdiag, float *__restrict__ kvp,
+    double *__restrict__ p0, const int32_t *__restrict__ skip)
 {
+    if (skip && *skip) return;   // the learned guess was taken: nothing to redo
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
     const double cK_old = (1.0 - sp.theta) * sp.dt;   // weight of K V^k in b
@@ -111,7 +113,6 @@ __global__ __launch_bounds__(256) void k_rhs_init(
         const double zi = di * ri;
         x[row] = x0i;
         r[row] = ri;
-        b[row] = bi;
         if (p0) p0[row] = zi;   // the first direction p0 = z0
         if (kvp) kvp[row] = kdiag[row] != 0.0 ? (float)(kv / kdiag[row]) : 0.0f;
         acc[0] += ri * zi;
@@ -154,8 +155,10 @@ __global__ __launch_bounds__(256) void k_residual_init(
 }
 
 __global__ __launch_bounds__(256) void k_init_finalize(int groups, const double *__restrict__ partial,
-                                                       int rel_mode, Scalars *__restrict__ sc)
+                                                       int rel_mode, Scalars *__restrict__ sc,
+                                                       const int32_t *__restrict__ skip)
 {
+    if (skip && *skip) return;
     double v[3];
     reduce_partials<3>(partial, groups, v);
     if (threadIdx.x == 0) {
@@ -394,11 +397,12 @@ void launch_stim_add(hipStream_t s, int64_t n_idx, const int32_t *idx, double am
 
 void launch_rhs_init(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                      const double *Kv, const double *dinv, const StepParams &sp, const double *V,
-                     const double *Vprev, const double *src, double *x, double *r, double *b,
-                     double *partial, const double *kdiag, float *kvp, double *p0, bool nt)
+                     const double *Vprev, const double *src, double *x, double *r,
+                     double *partial, const double *kdiag, float *kvp, double *p0, bool nt,
+                     const int32_t *skip)
 {
     MDX_LAUNCH_SELL(P, nt, k_rhs_init, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols, Mv,
-                    Kv, dinv, sp, V, Vprev, src, x, r, b, partial, kdiag, kvp, p0);
+                    Kv, dinv, sp, V, Vprev, src, x, r, partial, kdiag, kvp, p0, skip);
 }
 
 void launch_residual_init(hipStream_t s, const Tiling &t, SellView P, const double *Av,
@@ -410,9 +414,10 @@ void launch_residual_init(hipStream_t s, const Tiling &t, SellView P, const doub
 }
 
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
-                          Scalars *sc)
+                          Scalars *sc, const int32_t *skip)
 {
-    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(TILE), 0, s, t.groups, partial, rel_mode, sc);
+    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(TILE), 0, s, t.groups, partial, rel_mode, sc,
+                       skip);
 }
 
 void launch_spmv_dot(hipStream_t s, const Tiling &t, SellView P, const double *Av, const double *p,
