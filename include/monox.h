@@ -261,6 +261,15 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
  *                        up to the convergence check as a captured HIP graph
  *                        (one per iteration count and buffer rotation), 0 to
  *                        launch it kernel by kernel (default 0).
+ *   MDX_TUNE_PERSISTENT  batched context: 1 to run each step's CG iterations
+ *                        of all instances in one persistent launch (every
+ *                        workgroup resident, the workgroups of an instance
+ *                        meeting at barriers of their own, each instance
+ *                        iterating until its next residual replacement),
+ *                        0 (default) as five launches per iteration.  A
+ *                        barrier that waits longer than about 60 ms (its
+ *                        workgroups could not all be resident) ends the
+ *                        launch and mdx_run returns MDX_ERR_DEVICE;
  *   MDX_TUNE_NONTEMPORAL matrix streams (values, column indices) read with the
  *                        non-temporal cache hint: -1 (default) for each
  *                        kernel whose streams exceed 256 MiB (larger than
@@ -285,7 +294,8 @@ enum {
     MDX_TUNE_FORMAT = 6,
     MDX_TUNE_NONTEMPORAL = 7,
     MDX_TUNE_COMPACT_COLUMNS = 8,
-    MDX_TUNE_SPMV_MAX_GROUPS = 9
+    MDX_TUNE_SPMV_MAX_GROUPS = 9,
+    MDX_TUNE_PERSISTENT = 10
 };
 MDX_API mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value);
 

@@ -33,6 +33,7 @@ MDX_TUNE_LANES_PER_ROW, MDX_TUNE_TILES_PER_GROUP, MDX_TUNE_GRAPH, MDX_TUNE_FORMA
 MDX_TUNE_NONTEMPORAL = 7
 MDX_TUNE_COMPACT_COLUMNS = 8
 MDX_TUNE_SPMV_MAX_GROUPS = 9
+MDX_TUNE_PERSISTENT = 10
 MDX_TUNE_MAX_CANDIDATES = 32
 
 

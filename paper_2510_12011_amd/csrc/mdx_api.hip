@@ -59,6 +59,7 @@ struct Layout {
     size_t A32, dinv32, r32, z32, p32, q32, delta, g32;   // mixed-precision form
     size_t kdiag, kvp, feat, mlp_y, mlp_params;       // learned warm start
     size_t tile_real, grp, inst_grp, bsc, sptr_t, col_t, A32_t;   // batched form
+    size_t pgrp, pinst_grp, pbar;   // batched form, persistent iteration
     size_t csr_ptr, csr_col, csr_val, gv;
     size_t total;
     size_t x_xyz, x_tets, x_fibre, x_sig, x_vol, x_ek, x_cptr, x_contrib, x_total;
@@ -147,6 +148,8 @@ struct mdx_ctx {
     int lpr_built = 0;                    // layout in sptr_t / col_t / A32_t: 2, 4 (lanes
                                           // per row), 5 (4-entry chunks), 0 none
     int tpb_b = 1;                        // tiles per workgroup
+    bool persistent = false;              // CG iterations in one persistent launch
+    SegTiling pseg{};                     // its group table (all groups resident)
     SegTiling seg{};
     BScalars *bsc_host = nullptr;         // pinned, n_inst
     std::vector<int32_t> inst_iters_hist; // per step, n_inst each
@@ -478,6 +481,9 @@ void compute_layout(mdx_ctx *c)
         L.tile_real = take(sizeof(int32_t) * n_tiles);
         L.grp = take(sizeof(int4) * (n_tiles + ni));
         L.inst_grp = take(sizeof(int32_t) * (ni + 1));
+        L.pgrp = take(sizeof(int4) * (n_tiles + ni));
+        L.pinst_grp = take(sizeof(int32_t) * (ni + 1));
+        L.pbar = take(sizeof(uint32_t) * (ni + 1));
         L.bsc = take(sizeof(BScalars) * ni);
         const size_t alt =
             c->batched ? (size_t)std::max({c->nslots_lpr[1], c->nslots_lpr[2], c->nslots_lpr[3]}) : 1;
@@ -627,6 +633,32 @@ mdx_status build_groups(mdx_ctx *c, int tpb, std::vector<int4> &grp, std::vector
     if ((int64_t)grp.size() > kPartialCap)
         return fail(c, MDX_ERR_INVALID_ARG, "%zu workgroups exceed %d: use more tiles per group",
                     grp.size(), kPartialCap);
+    return MDX_OK;
+}
+
+// Group table of the persistent iteration: the fewest tiles per group for
+// which every group can be resident at once.
+mdx_status install_persistent_groups(mdx_ctx *c)
+{
+    mdx_ctx *ctx = c;   // for HIPCHK
+    const int cap = persistent_capacity(c->device);
+    if (cap <= 0) return fail(c, MDX_ERR_DEVICE, "occupancy query of the persistent kernel failed");
+    std::vector<int4> grp;
+    std::vector<int32_t> ig;
+    int tpb = 1;
+    for (;; ++tpb) {
+        if (mdx_status e = build_groups(c, tpb, grp, ig)) return e;
+        if ((int)grp.size() <= cap) break;
+    }
+    HIPCHK(hipMemcpyAsync(c->dev<int4>(c->L.pgrp), grp.data(), sizeof(int4) * grp.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->dev<int32_t>(c->L.pinst_grp), ig.data(), sizeof(int32_t) * ig.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->pseg.groups = (int)grp.size();
+    c->pseg.n_inst = c->n_inst;
+    c->pseg.grp = c->dev<int4>(c->L.pgrp);
+    c->pseg.inst_grp = c->dev<int32_t>(c->L.pinst_grp);
     return MDX_OK;
 }
 
@@ -1048,6 +1080,31 @@ BParams batch_params(const mdx_ctx *c)
                    c->opts.rel_mode};
 }
 
+constexpr int kPersistentSpinCap = 1000000;   // polls (about 60 ms) before a barrier gives up
+
+void launch_persistent(mdx_ctx *c, hipStream_t st, const BatchPtrs &q, const BParams &bp)
+{
+    unsigned *bar = c->dev<unsigned>(c->L.pbar);
+    launch_b_persistent(st, c->pseg, q.P, c->dev<float>(c->L.A32), q.dinv32, bp, q.p32, q.q32,
+                        q.delta, q.r32, q.part_pq, q.part_rz, q.bsc, bar,
+                        reinterpret_cast<int *>(bar + c->n_inst), kPersistentSpinCap);
+}
+
+// the persistent iteration's barrier timed out (its groups were not all resident)
+mdx_status persistent_fault(mdx_ctx *c, hipStream_t st)
+{
+    mdx_ctx *ctx = c;   // for HIPCHK
+    int fault = 0;
+    HIPCHK(hipMemcpyAsync(&fault, c->dev<unsigned>(c->L.pbar) + c->n_inst, sizeof(int),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (fault)
+        return fail(c, MDX_ERR_DEVICE,
+                    "a barrier of the persistent batched iteration timed out (%d workgroups; "
+                    "not all were resident)", c->pseg.groups);
+    return MDX_OK;
+}
+
 // ionic update, right-hand side and initial residual, `iters` PCG iterations
 // of every running instance, one residual-replacement pass.  With `timed`,
 // event pairs bracket the SpMV launches.
@@ -1068,6 +1125,10 @@ void enqueue_batched_step(mdx_ctx *c, hipStream_t st, int iters, const double *i
                       use_nt(c, 20.0 * slots(c)));
     launch_b_init_finalize(st, c->seg, q.part0, bp, q.bsc);
     launch_b_set_direction(st, c->seg, q.dinv32, q.r32, q.p32, q.bsc);
+    if (c->persistent) {
+        launch_persistent(c, st, q, bp);
+        iters = 0;
+    }
     for (int i = 0; i < iters; ++i) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timed && 2 * i + 1 < (int)c->ev.size()) {
@@ -1134,7 +1195,7 @@ mdx_status run_batched(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double 
         const bool profiling = ctx->profile_every > 0 && k % ctx->profile_every == 0;
         const int C = std::max(1, std::min(ctx->last_iters, max_iter));
         if (ctx->use_graph && !profiling) {
-            const std::pair<int, int> key{C, ctx->vb[0]};
+            const std::pair<int, int> key{ctx->persistent ? -1 : C, ctx->vb[0]};
             auto it = ctx->graphs.find(key);
             if (it == ctx->graphs.end()) {
                 hipGraph_t g = nullptr;
@@ -1154,19 +1215,26 @@ mdx_status run_batched(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double 
         HIPCHK(hipGetLastError());
         int units = C;
         if (mdx_status e = fetch_bscalars(ctx, st)) return e;
+        if (ctx->persistent)
+            if (mdx_status e = persistent_fault(ctx, st)) return e;
         while (!all_done(ctx) && units < max_iter + 1) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (profiling && 2 * units + 1 < (int)ctx->ev.size()) {
                 e0 = ctx->ev[2 * units];
                 e1 = ctx->ev[2 * units + 1];
             }
-            launch_b_iteration(st, ctx->seg, q.IM, bp, q.dinv32, q.p32, q.q32, q.delta, q.r32,
-                               q.part_pq, q.part_rz, q.bsc, e0, e1);
+            if (ctx->persistent)
+                launch_persistent(ctx, st, q, bp);
+            else
+                launch_b_iteration(st, ctx->seg, q.IM, bp, q.dinv32, q.p32, q.q32, q.delta, q.r32,
+                                   q.part_pq, q.part_rz, q.bsc, e0, e1);
             launch_b_replacement(st, ctx->seg, q.P, bp, q.Av, X, q.delta, q.b, q.dinv, q.dinv32, q.r32,
                                  q.p32, q.part0, q.bsc, use_nt(ctx, 12.0 * slots(ctx)));
             HIPCHK(hipGetLastError());
             ++units;
             if (mdx_status e = fetch_bscalars(ctx, st)) return e;
+            if (ctx->persistent)
+                if (mdx_status e = persistent_fault(ctx, st)) return e;
         }
         if (!all_done(ctx))
             return fail(ctx, MDX_ERR_STATE, "batched solve of step %lld did not finish",
@@ -1686,6 +1754,10 @@ mdx_status mdx_prepare(mdx_ctx *ctx, double dt, void *scratch, size_t scratch_by
         const int64_t slots = ctx->npad / TILE + ctx->n_inst;
         const int tpb = (int)std::max<int64_t>(1, (slots + kPartialCap - 1) / kPartialCap + 1);
         if (mdx_status e = install_groups(ctx, slots <= kPartialCap ? 1 : tpb)) return e;
+        // back to the default iteration (as the layout choice); the persistent
+        // group table is rebuilt when it is next selected
+        ctx->persistent = false;
+        ctx->pseg = SegTiling{};
     }
     ctx->dt = dt;
     ctx->step = 0;
@@ -2160,6 +2232,19 @@ mdx_status mdx_set_tuning(mdx_ctx *ctx, int32_t key, int64_t value)
     case MDX_TUNE_COMPACT_COLUMNS:
         if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "use 0 or 1");
         ctx->compact_cols = value != 0;
+        return MDX_OK;
+    case MDX_TUNE_PERSISTENT:
+        if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "persistent is 0 or 1");
+        if (!ctx->batched || !ctx->prepared)
+            return fail(ctx, MDX_ERR_STATE, "needs a prepared batched context");
+        if (value == 1 && ctx->pseg.groups == 0) {
+            GUARD_BEGIN
+            HIPCHK(hipSetDevice(ctx->device));
+            if (mdx_status e = install_persistent_groups(ctx)) return e;
+            GUARD_END
+        }
+        ctx->persistent = value == 1;
+        release_graphs(ctx);
         return MDX_OK;
     case MDX_TUNE_GRAPH:
         if (value != 0 && value != 1) return fail(ctx, MDX_ERR_INVALID_ARG, "graph is 0 or 1");

@@ -550,6 +550,152 @@ __global__ __launch_bounds__(256) void k_b_redirect(SegTiling t, const float *__
     }
 }
 
+// ---- persistent iteration --------------------------------------------------
+// All CG iterations of every running instance in one launch: each workgroup
+// owns a fixed range of one instance's tiles (its own group table, sized so
+// that every workgroup is resident at once) and the workgroups of an
+// instance meet at a barrier of their own after the product, after the
+// update and after the direction.  Every workgroup of an instance sums that
+// instance's partials in the same fixed order and so takes the same
+// decisions; the instance's first workgroup records them in its scalars.
+// An instance leaves the loop when its recursive residual passes the test,
+// every rr iterations and at the cap (the residual replacement kernels then
+// run), or when a value is not finite.
+//
+// Barrier: a counter per instance, raised once per workgroup and barrier;
+// the n-th barrier of an instance with G workgroups ends when the counter
+// reaches n G.  Device-scope fences order the partials around it.  The wait
+// is bounded: after `spin_cap` polls the workgroup records a timeout in
+// *fault and leaves (the host reports an error), so a launch whose
+// workgroups could not all be resident ends instead of hanging.
+__device__ __forceinline__ bool inst_barrier(unsigned *__restrict__ counter, unsigned target,
+                                             int *__restrict__ fault, int spin_cap)
+{
+    __shared__ int flag;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(counter, 1u);
+        int spins = 0, f = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > spin_cap ||
+                __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                atomicOr(fault, 1);
+                f = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        flag = f;
+    }
+    __syncthreads();
+    return flag == 0;
+}
+
+__global__ __launch_bounds__(256) void k_b_zero_u32(int n, unsigned *__restrict__ a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_b_persistent(
+    SegTiling t, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+    const float *__restrict__ A32, const float *__restrict__ dinv32, BParams bp,
+    float *__restrict__ p, float *__restrict__ q, float *__restrict__ delta,
+    float *__restrict__ r, double *__restrict__ part_pq, double *__restrict__ part_rz,
+    BScalars *__restrict__ sc, unsigned *__restrict__ bar, int *__restrict__ fault, int spin_cap)
+{
+    const int g = blockIdx.x;   // instance-major order: an instance's groups are adjacent
+    const int4 gr = t.grp[g];
+    const int inst = gr.x;
+    const int g0 = t.inst_grp[inst], g1 = t.inst_grp[inst + 1];
+    const unsigned G = (unsigned)(g1 - g0);
+    const bool lead = g == g0 && threadIdx.x == 0;
+    BScalars &s = sc[inst];
+    if (idle(s)) return;   // every group of the instance reads the same state
+    const int lane = threadIdx.x & (SLICE - 1);
+    double rho = s.rho, beta = s.beta;
+    int it = s.it;
+    if (lead) s.redirect = 0;   // p holds the direction (set before the launch)
+    unsigned n_bar = 0;
+    for (;;) {
+        // ---- q = A p, partial p.q ----
+        double acc1[1] = {0.0};
+        for (int tile = gr.y; tile < gr.z; ++tile) {
+            const int64_t sl = wave_slice(tile);
+            const int64_t row = sl * SLICE + lane;
+            const int64_t b0 = slice_ptr[sl];
+            const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
+            const float sum = sell_row<false, float>(w, col + b0 + lane, A32 + b0 + lane, p, 0);
+            q[row] = sum;
+            acc1[0] += (double)p[row] * (double)sum;
+        }
+        write_partials<1>(acc1, part_pq, t.groups, g);
+        if (!inst_barrier(bar + inst, ++n_bar * G, fault, spin_cap)) return;
+        // ---- alpha; delta += alpha p, r -= alpha q; partials r.z, z.z ----
+        double pq[1];
+        reduce_range<1>(part_pq, t.groups, g0, g1, pq);
+        const double alpha = rho / pq[0];
+        const float af = (float)alpha;
+        double acc2[2] = {0.0, 0.0};
+        for (int tile = gr.y; tile < gr.z; ++tile) {
+            const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+            delta[i] += af * p[i];
+            const float ri = r[i] - af * q[i];
+            r[i] = ri;
+            const float zi = dinv32[i] * ri;
+            acc2[0] += (double)ri * (double)zi;
+            acc2[1] += (double)zi * (double)zi;
+        }
+        write_partials<2>(acc2, part_rz, t.groups, g);
+        if (!inst_barrier(bar + inst, ++n_bar * G, fault, spin_cap)) return;
+        // ---- stopping test, beta ----
+        double v[2];
+        reduce_range<2>(part_rz, t.groups, g0, g1, v);
+        const double zn = sqrt(v[1]);
+        ++it;
+        int why = 0;
+        if (!isfinite(zn) || !isfinite(v[0])) {
+            why = -1;
+        } else {
+            const bool pass = zn < bp.atol || zn < bp.rtol * s.ref || zn <= s.floor_;
+            why = pass ? 1 : ((bp.rr > 0 && it % bp.rr == 0) || it >= bp.max_iter) ? 2 : 0;
+        }
+        if (why != 0) {
+            if (lead) {
+                s.it = it;
+                s.znorm = zn;
+                s.alpha = alpha;
+                if (why < 0) {
+                    s.nonfinite = 1;
+                    s.done = 1;
+                    s.iters = it;
+                } else {
+                    s.replace = why;
+                }
+            }
+            return;
+        }
+        beta = v[0] / rho;
+        rho = v[0];
+        // ---- p = D^-1 r + beta p ----
+        const float bf = (float)beta;
+        for (int tile = gr.y; tile < gr.z; ++tile) {
+            const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+            p[i] = dinv32[i] * r[i] + bf * p[i];
+        }
+        if (lead) {
+            s.it = it;
+            s.znorm = zn;
+            s.rho = rho;
+            s.beta = beta;
+            s.alpha = alpha;
+        }
+        if (!inst_barrier(bar + inst, ++n_bar * G, fault, spin_cap)) return;
+    }
+}
+
 template <class Ptr, class Kernel>
 void spmv_launch(Kernel k, hipStream_t s, const SegTiling &t, const Ptr *ptr, const IterMatrix &A,
                  const float *p32, float *q32, double *part_pq, const BScalars *sc, hipEvent_t e0,
@@ -659,6 +805,26 @@ void launch_b_iteration(hipStream_t s, const SegTiling &t, const IterMatrix &A, 
     hipLaunchKernelGGL(k_b_beta, dim3(t.n_inst), dim3(TILE), 0, s, t.groups, t.inst_grp, part_rz, bp,
                        sc);
     hipLaunchKernelGGL(k_b_direction, dim3(t.groups), dim3(TILE), 0, s, t, dinv32, r32, p32, sc);
+}
+
+int persistent_capacity(int device)
+{
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_persistent, TILE, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+void launch_b_persistent(hipStream_t s, const SegTiling &t, SellView P, const float *A32,
+                         const float *dinv32, const BParams &bp, float *p32, float *q32,
+                         float *delta, float *r32, double *part_pq, double *part_rz,
+                         BScalars *sc, unsigned *bar, int *fault, int spin_cap)
+{
+    const int n = t.n_inst + 1;   // the counters and the fault flag
+    hipLaunchKernelGGL(k_b_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, bar);
+    hipLaunchKernelGGL(k_b_persistent, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, P.col, A32,
+                       dinv32, bp, p32, q32, delta, r32, part_pq, part_rz, sc, bar, fault, spin_cap);
 }
 
 void launch_b_replacement(hipStream_t s, const SegTiling &t, SellView P, const BParams &bp,

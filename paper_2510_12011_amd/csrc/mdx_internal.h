@@ -322,6 +322,16 @@ void launch_b_iteration(hipStream_t s, const SegTiling &t, const IterMatrix &A,
                         float *delta, float *r32, double *part_pq, double *part_rz, BScalars *sc,
                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // flush, true residual, finalize, redirect for instances with a pending replacement
+// Persistent iteration: every running instance iterates in one launch until
+// its next replacement point (see mdx_batch.hip); t must be a group table
+// whose workgroups can all be resident (persistent_capacity: the most that
+// can, 0 if the query fails).  bar: t.n_inst + 1 words (counters, then the
+// fault flag at bar[t.n_inst], viewed as fault), cleared by the launch.
+int persistent_capacity(int device);
+void launch_b_persistent(hipStream_t s, const SegTiling &t, SellView P, const float *A32,
+                         const float *dinv32, const BParams &bp, float *p32, float *q32,
+                         float *delta, float *r32, double *part_pq, double *part_rz,
+                         BScalars *sc, unsigned *bar, int *fault, int spin_cap);
 void launch_b_replacement(hipStream_t s, const SegTiling &t, SellView P, const BParams &bp,
                           const double *Av, double *x, float *delta, const double *b,
                           const double *dinv, const float *dinv32, float *r32, float *p32,

@@ -195,13 +195,14 @@ class Simulation:
 
     def set_tuning(self, max_groups=None, iter_scheme=None, lanes_per_row=None,
                    tiles_per_group=None, graph=None, fmt=None, nontemporal=None,
-                   compact_columns=None, spmv_max_groups=None):
+                   compact_columns=None, spmv_max_groups=None, persistent=None):
         """fmt: 'sell', 'csr', 'sell4' or 'sell4nt' (batched iteration SpMV
         storage), set before lanes_per_row; compact_columns: 16-bit column
         offsets in the single-mesh per-step kernels (default on)."""
         f = None if fmt is None else {"sell": 0, "csr": 1, "sell4": 2, "sell4nt": 3}[fmt]
         for key, v in ((L.MDX_TUNE_MAX_GROUPS, max_groups), (L.MDX_TUNE_ITER_SCHEME, iter_scheme),
                        (L.MDX_TUNE_SPMV_MAX_GROUPS, spmv_max_groups),
+                       (L.MDX_TUNE_PERSISTENT, None if persistent is None else int(bool(persistent))),
                        (L.MDX_TUNE_FORMAT, f), (L.MDX_TUNE_NONTEMPORAL, nontemporal),
                        (L.MDX_TUNE_COMPACT_COLUMNS,
                         None if compact_columns is None else int(bool(compact_columns))),

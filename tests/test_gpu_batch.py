@@ -10,7 +10,10 @@ with per-instance CG scalars.
 * graph-replayed steps against kernel-by-kernel steps (bitwise, every
   snapshot, with eager work between the replays);
 * the autotuner's choices and forced lanes-per-row layouts against the
-  default (FP32 summation order only).
+  default (FP32 summation order only);
+* the persistent iteration (one launch runs every instance's iterations,
+  instance-local barriers) against the oracle and the default path, also
+  replayed as graphs.
 """
 import numpy as np
 import pytest
@@ -160,3 +163,33 @@ def test_batch_converges_relative_to_initial_residual(bspec):
         v_or, _ = o.steps(200, out_every=100)
         errs = [_rel_l2(a, c) for a, c in zip(_split(v, ptr)[k], v_or)]
         assert max(errs) <= V_REL_L2, errs
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_persistent_iteration(bspec, batch_run, graph):
+    """The persistent launch against the oracle (the mixed-precision bar) and
+    against the five-launch iteration (same scalars and stopping decisions,
+    so the same iteration counts; V within FP32 summation-order effects)."""
+    from paper_2510_12011_amd import sim
+    print(f"[case] batched run, persistent iteration, graph={graph}", flush=True)
+    s = sim.batch_from_spec(bspec)
+    s.set_tuning(persistent=True, graph=graph)
+    v, st = s.run(STEPS, EVERY)
+    assert st == 0
+    lat, _ = s.times()
+    its = s.instance_iterations(STEPS)
+    ptr = bspec.node_ptr()
+    vs, lats = _split(v, ptr), _split(lat, ptr)
+    ref = _split(batch_run["v"], ptr)
+    diff = max(_rel_l2(a, b) for k in range(len(ptr) - 1) for a, b in zip(vs[k], ref[k]))
+    print(f"  persistent vs five-launch: V rel L2 max {diff:.2e}, iteration counts equal on "
+          f"{(its == batch_run['its']).mean():.3f} of the solves", flush=True)
+    assert diff <= 1e-9
+    assert abs(its.astype(int) - batch_run["its"]).max() <= 1
+    for k in (0, len(bspec.instances) - 1):
+        spec = bspec.instance_spec(k)
+        o = orc.Oracle(spec)
+        v_or, _ = o.steps(STEPS, out_every=EVERY)
+        assert max(_rel_l2(a, b) for a, b in zip(vs[k], v_or)) <= V_REL_L2
+        fin = np.isfinite(o.state.lat) & np.isfinite(lats[k])
+        assert abs(lats[k][fin] - o.state.lat[fin]).max() <= spec.dt * (1 + 1e-9)

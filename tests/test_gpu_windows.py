@@ -73,7 +73,7 @@ def test_slab_full_length_matches_oracle():
     assert int(np.isfinite(lat).sum()) == int(g["n_activated"])
 
 
-@pytest.mark.parametrize("layout", ["sell", "sell4nt", "csr", "graph"])
+@pytest.mark.parametrize("layout", ["sell", "sell4nt", "csr", "graph", "persistent"])
 def test_cohort_smallest_instances_match_oracle(layout):
     from paper_2510_12011_amd import sim
     g = _golden("cohort4")
@@ -90,6 +90,8 @@ def test_cohort_smallest_instances_match_oracle(layout):
         s.set_tuning(lanes_per_row=8)
     elif layout == "graph":
         s.set_tuning(graph=True)
+    elif layout == "persistent":
+        s.set_tuning(persistent=True, graph=True)
     _, st = s.run(steps)
     assert st == 0
     state = s.get_state()
