@@ -88,6 +88,12 @@ def workload(name):
                 "paper's atrial parameters, isotropic 0.4 S/m, dt 0.01 ms, apex stimulus, "
                 f"{'mixed FP32/FP64' if prec == 'mixed' else 'plain FP64'}, atol 1e-5 and "
                 "rtol 1e-5 of ||D^-1 b||", prec)
+    if name == "surface_crn":
+        return (inputs.atrium_surface(ionic="crn"),
+                "atrial surface stand-in: closed ellipsoidal triangle surface 40x33x30 mm "
+                "(655,362 nodes, 1,310,720 P1 triangles), Courtemanche-Ramirez-Nattel atrial "
+                "cell, isotropic 0.4 S/m, dt 0.01 ms, apex stimulus, plain FP64, atol 1e-5 and "
+                "rtol 1e-5 of ||D^-1 b||", "fp64")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -219,8 +225,9 @@ def learned_workload(args):
 
     params, norm, net = shell_network(args, mesh, spec)
     k0 = int(round(CHECKPOINT_MS / 0.02))
+    held = HELD_OUT[:max(1, min(args.sites, len(HELD_OUT)))]
     ckpt = {}
-    for site in HELD_OUT:
+    for site in held:
         s = sim.from_spec(spec(site, k0), precision="fp64")
         s.set_solver(0.0, 1e-10, 1, 1000, L.MDX_WS_EXTRAP, 0, 50)
         s.run(k0)
@@ -236,7 +243,7 @@ def learned_workload(args):
     def context(precision, ws):
         key = (precision, ws)
         if key not in ctxs:
-            s = sim.from_spec(spec(HELD_OUT[0], k0 + args.steps), precision=precision)
+            s = sim.from_spec(spec(held[0], k0 + args.steps), precision=precision)
             if ws == L.MDX_WS_MLP:
                 learn.install(s, params, norm)
             ctxs[key] = s
@@ -245,7 +252,7 @@ def learned_workload(args):
     def restore(s, c):
         s.set_state(c["V"], c["Vprev"], c["u"], c["lat"], c["lrt"], c["step"])
 
-    def timed(precision, ws, rtol, site=HELD_OUT[0], profile=False):
+    def timed(precision, ws, rtol, site=held[0], profile=False):
         s = context(precision, ws)
         s.set_solver(0.0, rtol, 1, 1000, ws, sim.PRECISION[precision], 50)
         c = ckpt[site]
@@ -286,7 +293,7 @@ def learned_workload(args):
         "plain_fp64_3e-9": timed("fp64", L.MDX_WS_EXTRAP, eq),
         "extrap_mixed_3e-9": timed("mixed", L.MDX_WS_EXTRAP, eq),
     }
-    tight = {HELD_OUT[0]: timed("fp64", L.MDX_WS_EXTRAP, 1e-12)}
+    tight = {held[0]: timed("fp64", L.MDX_WS_EXTRAP, 1e-12)}
 
     def accuracy(r, ref):
         e = float(np.linalg.norm(r["V"] - ref["V"]) / np.linalg.norm(ref["V"]))
@@ -297,7 +304,7 @@ def learned_workload(args):
 
     summary = {}
     for key, r in runs.items():
-        e, lat, mism = accuracy(r, tight[HELD_OUT[0]])
+        e, lat, mism = accuracy(r, tight[held[0]])
         r.update(V_rel_l2=e, lat_max_diff_ms=lat, lat_mismatch=mism)
         summary[key] = {"dof_steps_per_s": r["rate"], "mean_cg_iters": r["iters"],
                         "p95_cg_iters": r["iters_p95"], "V_rel_l2": e, "lat_max_diff_ms": lat,
@@ -305,9 +312,9 @@ def learned_workload(args):
         print(f"[bench] {key}: {r['rate']:.3e} DOF*steps/s, V rel L2 {e:.2e}, LAT max diff "
               f"{lat:g} ms", flush=True)
     # the other held-out sites: the three runs at equal accuracy
-    sites = {HELD_OUT[0]: {k: runs[k] for k in ("learned_mixed_3e-9", "plain_fp64_3e-9",
+    sites = {held[0]: {k: runs[k] for k in ("learned_mixed_3e-9", "plain_fp64_3e-9",
                                                 "extrap_mixed_3e-9")}}
-    for site in HELD_OUT[1:]:
+    for site in held[1:]:
         sites[site] = {"learned_mixed_3e-9": timed("mixed", L.MDX_WS_MLP, eq, site),
                        "plain_fp64_3e-9": timed("fp64", L.MDX_WS_EXTRAP, eq, site),
                        "extrap_mixed_3e-9": timed("mixed", L.MDX_WS_EXTRAP, eq, site)}
@@ -317,19 +324,19 @@ def learned_workload(args):
             r.update(V_rel_l2=e, lat_max_diff_ms=lat, lat_mismatch=mism)
 
     def agg(key):
-        rs = [sites[st][key] for st in HELD_OUT]
+        rs = [sites[st][key] for st in held]
         return (n * args.steps * len(rs) / sum(r["seconds"] for r in rs),
                 float(np.mean([r["iters"] for r in rs])), max(r["V_rel_l2"] for r in rs),
                 max(r["lat_max_diff_ms"] for r in rs), sum(r["lat_mismatch"] for r in rs))
 
     five = {k: agg(k) for k in ("learned_mixed_3e-9", "plain_fp64_3e-9", "extrap_mixed_3e-9")}
     for k, v in five.items():
-        print(f"[bench] 5 held-out sites, {k}: {v[0]:.3e} DOF*steps/s, mean CG iterations "
+        print(f"[bench] {len(held)} held-out sites, {k}: {v[0]:.3e} DOF*steps/s, mean CG iterations "
               f"{v[1]:.2f}, worst V rel L2 {v[2]:.2e}, worst LAT diff {v[3]:g} ms", flush=True)
     lrn = runs["learned_mixed_3e-9"]
     plain = runs["plain_fp64_3e-9"]
     ok = all(r["V_rel_l2"] <= ACCURACY_BAR and r["lat_max_diff_ms"] <= 0.02 + 1e-12
-             and r["lat_mismatch"] == 0 for st in HELD_OUT for r in sites[st].values())
+             and r["lat_mismatch"] == 0 for st in held for r in sites[st].values())
     if not ok:
         print("[bench] WARNING: a run at 3e-9 missed the accuracy bar (1e-5, one dt): "
               "the speed-ups below are not at equal accuracy", flush=True)
@@ -359,6 +366,7 @@ def learned_workload(args):
                    "V_rel_l2_learned": lrn["V_rel_l2"], "V_rel_l2_plain": plain["V_rel_l2"],
                    "lat_max_diff_ms_learned": lrn["lat_max_diff_ms"],
                    "equal_accuracy": bool(ok),
+                   "held_out_sites": len(held),
                    "five_sites_speedup_vs_plain_fp64":
                        five["learned_mixed_3e-9"][0] / five["plain_fp64_3e-9"][0],
                    "five_sites_speedup_vs_extrapolated_mixed":
@@ -391,9 +399,9 @@ def learned_workload(args):
     if not args.no_cpu:
         print(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps of the same window",
               flush=True)
-        sp = spec(HELD_OUT[0], k0 + args.cpu_steps)
+        sp = spec(held[0], k0 + args.cpu_steps)
         sp.rtol = eq
-        out["cpu_baseline"] = cpu_baseline_window(sp, ckpt[HELD_OUT[0]], args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline_window(sp, ckpt[held[0]], args.cpu_steps)
         out["config"]["cpu_single_core_dof_steps_per_s"] = out["cpu_baseline"]["single_core"]["value"]
         out["config"]["cpu_model"] = out["cpu_baseline"]["cpu_model"]
     print(json.dumps(out), flush=True)
@@ -549,13 +557,17 @@ def batched_workload(args):
     for c in rep["candidates"]:
         print(f"[bench]   candidate {c[0]:4s} lanes/row {c[1]:2d} tiles/group {c[2]}: "
               f"{c[3] * 1e6:8.1f} us, {rep['bytes'] / c[3] / 1e9:7.1f} GB/s", flush=True)
+    def install():
+        s.set_tuning(fmt=rep["fmt"])
+        s.set_tuning(lanes_per_row=rep["lanes_per_row"], tiles_per_group=rep["tiles_per_group"],
+                     graph=not args.no_graph)
+        if args.persistent:
+            s.set_tuning(persistent=True)
     if args.warmup:
-        s.set_tuning(graph=True)
+        install()
         s.run(args.warmup)
         s.prepare(b.dt)           # back to rest (also resets the layout choice)
-    s.set_tuning(fmt=rep["fmt"])
-    s.set_tuning(lanes_per_row=rep["lanes_per_row"], tiles_per_group=rep["tiles_per_group"],
-                 graph=not args.no_graph)
+    install()
     s.set_profiling(args.profile_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -566,14 +578,16 @@ def batched_workload(args):
     its = s.instance_iterations(args.steps)
     print(f"[bench] {args.steps} steps in {elapsed:.3f} s, mean CG iterations per instance "
           f"{its.mean():.2f} (max {its.max()}), status {status}", flush=True)
-    launches = max(1, st["spmv_timed"])
-    spmv_avg = st["spmv_seconds"] / launches
-    bytes_avg = st["spmv_bytes"] / launches
-    achieved = bytes_avg / spmv_avg / 1e9
+    launches = st["spmv_timed"]
+    # the persistent iteration has no separate SpMV launches to time
+    spmv_avg = st["spmv_seconds"] / launches if launches else None
+    bytes_avg = st["spmv_bytes"] / launches if launches else None
+    achieved = bytes_avg / spmv_avg / 1e9 if launches else None
     desc = (f"batched form: {len(sizes)} unstructured ellipsoidal shells (Delaunay, "
             f"{min(sizes)}..{max(sizes)} nodes, {n} total), Mitchell-Schaeffer, sigma scaled "
             f"U(0.5,1.5), random endocardial sites, mixed FP32/FP64, rtol 1e-8 of ||D^-1 b||, "
-            f"per-instance CG, HIP-graph steps")
+            f"per-instance CG, HIP-graph steps"
+            f"{', persistent iteration kernel' if args.persistent else ''}")
     if surf:
         desc = (f"batched form: {len(sizes)} closed ellipsoidal triangle surfaces (atrial "
                 f"stand-ins, {min(sizes)}..{max(sizes)} nodes, {n} total), Mitchell-Schaeffer "
@@ -588,13 +602,15 @@ def batched_workload(args):
                    "nnz": st["nnz"], "dt_ms": b.dt, "rtol": b.rtol,
                    "spmv_format": rep["fmt"], "lanes_per_row": rep["lanes_per_row"],
                    "tiles_per_group": rep["tiles_per_group"], "graph": not args.no_graph,
+                   "persistent": bool(args.persistent),
                    "mean_cg_iters": float(its.mean()), "max_cg_iters": int(its.max())},
         "roofline": {"bound": "hbm",
                      "kernel": {"sell": "k_b_spmv", "csr": "k_b_spmv_csr", "sell4": "k_b_spmv_v4",
                                 "sell4nt": "k_b_spmv_v4"}[rep["fmt"]],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_avg, "avg_launch_us": 1e6 * spmv_avg,
+                     "frac": achieved / HBM_PEAK_GBS if launches else None, "traffic": None,
+                     "bytes_per_launch": bytes_avg,
+                     "avg_launch_us": 1e6 * spmv_avg if launches else None,
                      "launches_timed": st["spmv_timed"],
                      "sampled_every_n_steps": args.profile_every, "cache_resident": False},
     }
@@ -627,16 +643,21 @@ def main():
                          "100 otherwise)")
     ap.add_argument("--workload", default="learned",
                     choices=["learned", "slab", "precision", "precision_fp64", "batched", "tiny",
-                             "nversion", "surface", "surface_mixed", "batched_surface"])
+                             "nversion", "surface", "surface_mixed", "surface_crn",
+                             "batched_surface"])
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-every", type=int, default=10)
     ap.add_argument("--instances", type=int, default=64, help="batched workload")
     ap.add_argument("--total-nodes", type=int, default=12_000_000, help="batched workload")
     ap.add_argument("--no-graph", action="store_true", help="batched workload")
+    ap.add_argument("--persistent", action="store_true",
+                    help="batched workload: CG iterations in one persistent launch")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB device buffer 3 times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
+    ap.add_argument("--sites", type=int, default=5,
+                    help="learned workload: held-out stimulus sites timed (1-5)")
     ap.add_argument("--train-sites", type=int, default=8, help="learned workload")
     ap.add_argument("--train-steps", type=int, default=2000, help="learned workload")
     ap.add_argument("--train-epochs", type=int, default=10, help="learned workload")
@@ -648,7 +669,7 @@ def main():
     if args.steps is None:
         args.steps = {"learned": 3000, "slab": 10000, "batched": 1000, "precision": 2000,
                       "precision_fp64": 2000, "tiny": 500, "nversion": 0, "surface": 5000,
-                      "surface_mixed": 5000, "batched_surface": 2000}[args.workload]
+                      "surface_mixed": 5000, "surface_crn": 5000, "batched_surface": 2000}[args.workload]
     if args.warmup is None:
         args.warmup = {"learned": 0, "batched": 10, "batched_surface": 10}.get(args.workload, 100)
     if args.workload in ("batched", "batched_surface"):

@@ -172,19 +172,19 @@ __global__ __launch_bounds__(256) void k_b_rhs_init(
     const double cK_new = sp.theta * sp.dt;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int tile = gr.y; tile < gr.z; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = slice_ptr[sl];
+        const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
         double mv = 0.0, kv = 0.0, mx = 0.0, kx = 0.0;
-        for (int64_t e = beg; e < end; e += SLICE) {
-            const int32_t c = ld_stream<NT>(col + e);
-            const double m = ld_stream<NT>(Mv + e), kk = ld_stream<NT>(Kv + e);
-            const double4 gj = gv[c];
-            mv += m * gj.x;
-            kv += kk * gj.y;
-            mx += m * gj.z;
-            kx += kk * gj.z;
-        }
+        sell_row2<8, NT>(w, col + b0 + lane, Mv + b0 + lane, Kv + b0 + lane, 0,
+                         [&](int32_t c, double m, double kk) {
+                             const double4 gj = gv[c];
+                             mv += m * gj.x;
+                             kv += kk * gj.y;
+                             mx += m * gj.z;
+                             kx += kk * gj.z;
+                         });
         const double bi = sp.chi * mv - cK_old * kv;
         const double ri = bi - (cM_new * mx + cK_new * kx);
         x[row] = gv[row].z;
@@ -265,10 +265,9 @@ __global__ __launch_bounds__(256) void k_b_spmv(SegTiling t, const int64_t *__re
         for (int pass = 0; pass < LPR; ++pass) {
             const int64_t row = (int64_t)tile * TILE + pass * (TILE / LPR) + w * H + lane / LPR;
             const int64_t sl = row / H;
-            const int64_t beg = sptr[sl] + lane, end = sptr[sl + 1];
-            float sum = 0.0f;
-#pragma unroll 4
-            for (int64_t e = beg; e < end; e += SLICE) sum += ld_stream<NT>(A + e) * p[ld_stream<NT>(col + e)];
+            const int64_t b0 = sptr[sl];
+            const int wl = (int)((sptr[sl + 1] - b0) / SLICE);   // entries per lane
+            float sum = sell_row<NT, float>(wl, col + b0 + lane, A + b0 + lane, p, 0);
             if constexpr (LPR >= 4) sum += __shfl_xor(sum, 2, 64);
             if constexpr (LPR >= 2) sum += __shfl_xor(sum, 1, 64);
             if ((lane & (LPR - 1)) == 0) {
@@ -278,6 +277,70 @@ __global__ __launch_bounds__(256) void k_b_spmv(SegTiling t, const int64_t *__re
         }
     }
     write_partials<1>(acc, partial, t.groups, g);
+}
+
+// Row of the vector-load sliced layout (chunk k of a lane at 4k * SLICE):
+// for a fixed chunk count all chunk loads are issued before the gathers;
+// entries are summed in column order as a loop would.
+template <int NC, bool NT>
+__device__ __forceinline__ float v4_row_n(const int32_t *__restrict__ col, const float *__restrict__ A,
+                                          const float *__restrict__ p)
+{
+    i32x4 c[NC];
+    f32x4 a[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        if constexpr (NT) {
+            c[k] = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(col + 4 * k * SLICE));
+            a[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(A + 4 * k * SLICE));
+        } else {
+            c[k] = *reinterpret_cast<const i32x4 *>(col + 4 * k * SLICE);
+            a[k] = *reinterpret_cast<const f32x4 *>(A + 4 * k * SLICE);
+        }
+    }
+    float x[NC][4];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[k][j] = p[c[k][j]];
+    float sum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sum += a[k][j] * x[k][j];
+    return sum;
+}
+
+template <bool NT>
+__device__ __forceinline__ float v4_row(int nc, const int32_t *__restrict__ col,
+                                        const float *__restrict__ A, const float *__restrict__ p)
+{
+    switch (nc) {
+    case 0: return 0.0f;
+    case 1: return v4_row_n<1, NT>(col, A, p);
+    case 2: return v4_row_n<2, NT>(col, A, p);
+    case 3: return v4_row_n<3, NT>(col, A, p);
+    case 4: return v4_row_n<4, NT>(col, A, p);
+    case 5: return v4_row_n<5, NT>(col, A, p);
+    case 6: return v4_row_n<6, NT>(col, A, p);
+    default: {
+        float sum = 0.0f;
+        for (int k = 0; k < nc; ++k) {
+            i32x4 c;
+            f32x4 a;
+            if constexpr (NT) {
+                c = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(col + 4 * k * SLICE));
+                a = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(A + 4 * k * SLICE));
+            } else {
+                c = *reinterpret_cast<const i32x4 *>(col + 4 * k * SLICE);
+                a = *reinterpret_cast<const f32x4 *>(A + 4 * k * SLICE);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sum += a[j] * p[c[j]];
+        }
+        return sum;
+    }
+    }
 }
 
 // q = A p, vector-load sliced layout: one lane per row, 4 entries per load.
@@ -298,26 +361,11 @@ __global__ __launch_bounds__(256) void k_b_spmv_v4(SegTiling t, const int64_t *_
     const int lane = threadIdx.x & (SLICE - 1);
     double acc[1] = {0.0};
     for (int tile = gr.y; tile < gr.z; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = sptr[sl] + 4 * lane, end = sptr[sl + 1];
-        float sum = 0.0f;
-#pragma unroll 2
-        for (int64_t e = beg; e < end; e += 4 * SLICE) {
-            i32x4 c;
-            f32x4 a;
-            if constexpr (NT) {
-                c = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(col + e));
-                a = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(A + e));
-            } else {
-                c = *reinterpret_cast<const i32x4 *>(col + e);
-                a = *reinterpret_cast<const f32x4 *>(A + e);
-            }
-            sum += a[0] * p[c[0]];
-            sum += a[1] * p[c[1]];
-            sum += a[2] * p[c[2]];
-            sum += a[3] * p[c[3]];
-        }
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = sptr[sl];
+        const int nc = (int)((sptr[sl + 1] - b0) / (4 * SLICE));   // 4-entry chunks per lane
+        const float sum = v4_row<NT>(nc, col + b0 + 4 * lane, A + b0 + 4 * lane, p);
         q[row] = sum;
         acc[0] += (double)p[row] * (double)sum;
     }
@@ -478,12 +526,11 @@ __global__ __launch_bounds__(256) void k_b_true_residual(
     const int lane = threadIdx.x & (SLICE - 1);
     double acc[2] = {0.0, 0.0};
     for (int tile = gr.y; tile < gr.z; ++tile) {
-        const int64_t row = (int64_t)tile * TILE + threadIdx.x;
-        const int64_t sl = row / SLICE;
-        const int64_t beg = slice_ptr[sl] + lane, end = slice_ptr[sl + 1];
-        double ax = 0.0;
-#pragma unroll 4
-        for (int64_t e = beg; e < end; e += SLICE) ax += ld_stream<NT>(Av + e) * x[ld_stream<NT>(col + e)];
+        const int64_t sl = wave_slice(tile);
+        const int64_t row = sl * SLICE + lane;
+        const int64_t b0 = slice_ptr[sl];
+        const int w = (int)((slice_ptr[sl + 1] - b0) / SLICE);
+        const double ax = sell_row<NT, double>(w, col + b0 + lane, Av + b0 + lane, x, 0);
         const double ri = b[row] - ax;
         const float rf = (float)ri;
         r32[row] = rf;
