@@ -1,5 +1,6 @@
-// Internal interface between the host library (mdx_api.hip) and the gfx950
-// kernels (mdx_assembly.hip, mdx_ionic.hip, mdx_solver.hip).
+// Internal interface between the host library (mdx_host.h and the sources
+// that include it) and the gfx950 kernels (mdx_assembly.hip, mdx_ionic.hip,
+// mdx_solver.hip and the forms' files).
 //
 // Matrix layout on the device: sliced ELL with slices of 64 consecutive rows
 // (one wavefront, one lane per row), column-major inside a slice:

@@ -10,7 +10,7 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "paper_2510_12011_amd", "csrc", "mdx_api.hip")
+SRC = os.path.join(ROOT, "paper_2510_12011_amd", "csrc", "mdx_order.hip")
 
 PROG = r"""
 #include <cstdint>
