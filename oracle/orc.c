@@ -286,7 +286,7 @@ int64_t orc_assemble_tri(int64_t n, const double *xyz, int64_t m, const int32_t 
 void orc_spmv(int64_t n, const int64_t *row_ptr, const int32_t *col,
               const double *val, const double *x, double *y)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n > 20000)
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) s += val[q] * x[col[q]];
@@ -837,7 +837,7 @@ void orc_ionic_init(int kind, const double *params, int64_t n, double *V, double
 void orc_ionic_step(int kind, const double *params, int64_t n, double dt,
                     const double *V, double *u, double *iion)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n > 20000)
     for (int64_t i = 0; i < n; ++i) {
         if (kind == 1) {
             ms_point(params, dt, V[i], &u[i], &iion[i]);
