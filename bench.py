@@ -540,7 +540,9 @@ def batched_workload(args):
                                   axes_mm=(20.0, 40.0), stim_radius=2.0)
     else:
         b = inputs.batch_shells(n_inst=args.instances, total_nodes=args.total_nodes, seed=0,
-                                workers=min(16, os.cpu_count() or 1))
+                                workers=min(16, os.cpu_count() or 1),
+                                progress=lambda k, m: print(f"[bench] meshed {k} of {m}",
+                                                            flush=True))
     n = b.n_nodes
     sizes = [i.mesh.n_nodes for i in b.instances]
     print(f"[bench] {len(sizes)} {'surfaces' if surf else 'shells'}, {n} nodes "

@@ -536,7 +536,7 @@ def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
                  n_min: int = 50_000, n_max: int = 400_000, n_steps: int = 5000,
                  dt: float = 0.01, ionic: str = "ms", workers: int = 1,
                  axes_mm: tuple = (25.0, 45.0), wall_mm: tuple = (6.0, 12.0),
-                 stim_radius: float = 1.5, only=None) -> BatchSpec:
+                 stim_radius: float = 1.5, only=None, progress=None) -> BatchSpec:
     """A seeded cohort of unstructured ellipsoidal shells: semi-axes
     U(axes_mm) (default 25-45 mm, the longest along z), wall U(wall_mm)
     (default 6-12 mm), node targets log-uniform in [n_min, n_max] rescaled to
@@ -546,7 +546,8 @@ def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
     chi 140/mm, Cm 0.01 uF/mm^2, theta 0.5, relative tolerance 1e-8 of
     ||D^-1 b||, mixed precision.  only: indices of the instances to mesh and
     keep (in that order; every draw of the full cohort is still made, so each
-    kept instance is the one the full cohort holds)."""
+    kept instance is the one the full cohort holds).  progress(done, total),
+    if given, is called after each mesh built in this process."""
     rng = np.random.default_rng(seed)
     axes = np.sort(rng.uniform(axes_mm[0], axes_mm[1], (n_inst, 3)), axis=1)
     walls = rng.uniform(wall_mm[0], wall_mm[1], n_inst)
@@ -565,7 +566,11 @@ def batch_shells(n_inst: int = 64, total_nodes: int = 12_000_000, seed: int = 0,
         with mp.get_context("fork").Pool(workers) as pool:
             meshes = pool.map(_cap_job, jobs, chunksize=1)
     else:
-        meshes = [shell_cap(**j) for j in jobs]
+        meshes = []
+        for j in jobs:
+            meshes.append(shell_cap(**j))
+            if progress:
+                progress(len(meshes), len(jobs))
     inst = []
     for i, m in zip(keep, meshes):
         stim = Stimulus(endocardial_site(m, int(sites[i]), stim_radius), 0.0, 2.0,
