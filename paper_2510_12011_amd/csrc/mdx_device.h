@@ -203,21 +203,23 @@ __device__ __forceinline__ void sell_row2(int w, const CI *__restrict__ c,
                                           const double *__restrict__ a0,
                                           const double *__restrict__ a1, int32_t cb, F &&f)
 {
-    static_assert(C == 8, "remainder cases below cover chunks of 8");
+    static_assert(C >= 2 && C <= 8, "remainder cases below cover chunks of up to 8");
     int j = 0;
     for (; j + C <= w; j += C)
         sell_chunk2<C, NT>(c + j * SLICE, a0 + j * SLICE, a1 + j * SLICE, cb, f);
     c += j * SLICE;
     a0 += j * SLICE;
     a1 += j * SLICE;
+    // the remainder (fewer than C entries); cases of C entries or more are
+    // not instantiated, so they cost no registers
     switch (w - j) {
     case 1: sell_chunk2<1, NT>(c, a0, a1, cb, f); break;
-    case 2: sell_chunk2<2, NT>(c, a0, a1, cb, f); break;
-    case 3: sell_chunk2<3, NT>(c, a0, a1, cb, f); break;
-    case 4: sell_chunk2<4, NT>(c, a0, a1, cb, f); break;
-    case 5: sell_chunk2<5, NT>(c, a0, a1, cb, f); break;
-    case 6: sell_chunk2<6, NT>(c, a0, a1, cb, f); break;
-    case 7: sell_chunk2<7, NT>(c, a0, a1, cb, f); break;
+    case 2: if constexpr (C > 2) sell_chunk2<2, NT>(c, a0, a1, cb, f); break;
+    case 3: if constexpr (C > 3) sell_chunk2<3, NT>(c, a0, a1, cb, f); break;
+    case 4: if constexpr (C > 4) sell_chunk2<4, NT>(c, a0, a1, cb, f); break;
+    case 5: if constexpr (C > 5) sell_chunk2<5, NT>(c, a0, a1, cb, f); break;
+    case 6: if constexpr (C > 6) sell_chunk2<6, NT>(c, a0, a1, cb, f); break;
+    case 7: if constexpr (C > 7) sell_chunk2<7, NT>(c, a0, a1, cb, f); break;
     default: break;
     }
 }
