@@ -182,7 +182,7 @@ def shell_network(args, mesh, spec):
         Xs.append(X)
         Ds.append(dV)
         trainer = s
-    X, dV = torch.cat(Xs), torch.cat(Ds)
+    X, dV = learn.concat(Xs), learn.concat(Ds)
     params, norm, hist = learn.fit(trainer, X, dV, epochs=args.train_epochs, batch=8192, lr=2e-3)
     print(f"[bench] network: no weights file for this mesh, trained here on {args.train_sites} "
           f"sites x {args.train_steps} steps in {time.perf_counter() - t0:.1f} s", flush=True)

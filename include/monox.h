@@ -399,8 +399,9 @@ MDX_API mdx_status mdx_ionic_step(mdx_ctx *ctx, double dt, int64_t n, const doub
 
 /* ---- learned warm start: the network ---------------------------------- */
 /* A per-node MLP 4 -> 64 -> 64 -> 64 -> 1 (ReLU) predicts the normalised
- * increment V^{n+1} - V^n from node-local features; not part of the paper,
- * whose warm start is the extrapolation 2V^k - V^{k-1} (after Algorithm 1).
+ * departure of V^{n+1} from the extrapolation 2V^n - V^{n-1} (the paper's
+ * warm start, after Algorithm 1) from node-local features; the network is
+ * not part of the paper.
  * Parameters: FP32, MDX_MLP_NPARAM values laid out
  *   W1[64][4] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[64] b4
  * (W[out][in]).  Kernels use BF16 weights and activations with FP32
@@ -452,6 +453,20 @@ MDX_API mdx_status mdx_mlp_adam(mdx_ctx *ctx, float *params, float *m, float *v,
  * paper's warm start).  Requires a prepared context; the network lives in
  * the workspace. */
 MDX_API mdx_status mdx_set_mlp(mdx_ctx *ctx, const float *params, const double *norm);
+/* Training samples for mdx_mlp_grad (the network's training data plumbing,
+ * on the device): for i < n_idx, row j = idx[i] of the recorder's output
+ * (X: [n_rows][4] raw features, dV: [n_rows] increments V^{n+1} - V^n) is
+ * written to Xo[i][0..3] and To[i], either raw (norm NULL) or as the network
+ * trains on it (norm: HOST double[9] as mdx_set_mlp takes it): Xo = (X -
+ * mean) / std, To = (dV - X[1]) / out_scale, i.e. the departure of V^{n+1}
+ * from the extrapolation 2V^n - V^{n-1} in units of out_scale.  idx, X, dV,
+ * Xo, To are DEVICE arrays (idx int64; X and Xo 16-byte aligned); an index
+ * outside [0, n_rows) gives a zero feature row and a NaN target.  Queued on
+ * ctx's stream.  Errors: MDX_ERR_INVALID_ARG for a negative count, a null
+ * or misaligned array, a non-finite norm or a std or out_scale <= 0. */
+MDX_API mdx_status mdx_mlp_samples(mdx_ctx *ctx, int64_t n_idx, const int64_t *idx, int64_t n_rows,
+                                   const float *X, const float *dV, const double *norm, float *Xo,
+                                   float *To);
 /* Training-data recorder: when non-NULL, every step of mdx_run writes the
  * raw features of node i (internal node order, i < n_nodes) to X[i][0..3]
  * and, after the solve, V^{n+1}_i - V^n_i to dV[i] (DEVICE arrays of

@@ -120,6 +120,7 @@ _SIGS = {
     "mdx_mlp_grad_noalloc": (C.c_int, [P, P, C.c_int64, P, P, P, P]),
     "mdx_mlp_adam": (C.c_int, [P, P, P, P, P, C.c_int32, C.c_double, C.c_double, C.c_double,
                                C.c_double]),
+    "mdx_mlp_samples": (C.c_int, [P, C.c_int64, P, C.c_int64, P, P, P, P, P]),
 }
 
 _lib = None

@@ -958,6 +958,35 @@ mdx_status mdx_mlp_adam(mdx_ctx *ctx, float *params, float *m, float *v, const f
     return MDX_OK;
 }
 
+mdx_status mdx_mlp_samples(mdx_ctx *ctx, int64_t n_idx, const int64_t *idx, int64_t n_rows,
+                           const float *X, const float *dV, const double *norm, float *Xo,
+                           float *To)
+{
+    if (!ctx) return MDX_ERR_INVALID_ARG;
+    if (ctx->device < 0) return fail(ctx, MDX_ERR_DEVICE, "host-only context (device -1)");
+    if (n_idx < 0 || n_rows < 0) return fail(ctx, MDX_ERR_INVALID_ARG, "negative count");
+    if (n_idx == 0) return MDX_OK;
+    if (!idx || !X || !dV || !Xo || !To) return fail(ctx, MDX_ERR_INVALID_ARG, "null array");
+    if (reinterpret_cast<uintptr_t>(X) % 16 || reinterpret_cast<uintptr_t>(Xo) % 16)
+        return fail(ctx, MDX_ERR_INVALID_ARG, "X and Xo must be 16-byte aligned");
+    MlpNorm nm{{0.f, 0.f, 0.f, 0.f}, {1.f, 1.f, 1.f, 1.f}, 1.f};
+    if (norm) {
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(norm[i])) return fail(ctx, MDX_ERR_INVALID_ARG, "non-finite norm %d", i);
+        for (int c = 0; c < 4; ++c) {
+            if (!(norm[4 + c] > 0.0)) return fail(ctx, MDX_ERR_INVALID_ARG, "std must be > 0");
+            nm.mean[c] = (float)norm[c];
+            nm.inv_std[c] = (float)(1.0 / norm[4 + c]);
+        }
+        if (!(norm[8] > 0.0)) return fail(ctx, MDX_ERR_INVALID_ARG, "out_scale must be > 0");
+        nm.out_scale = (float)norm[8];
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_mlp_samples(ctx->stream, n_idx, idx, n_rows, X, dV, norm != nullptr, nm, Xo, To);
+    HIPCHK(hipGetLastError());
+    return MDX_OK;
+}
+
 mdx_status mdx_set_mlp(mdx_ctx *ctx, const float *params, const double *norm)
 {
     if (!ctx || !params || !norm) return MDX_ERR_INVALID_ARG;

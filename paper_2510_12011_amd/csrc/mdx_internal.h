@@ -229,6 +229,9 @@ void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
                              int rel_mode, Scalars *sc);
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv);
+void launch_mlp_samples(hipStream_t s, int64_t n_idx, const int64_t *idx, int64_t n_rows,
+                        const float *X, const float *dV, bool stdz, const MlpNorm &nm, float *Xo,
+                        float *To);
 
 // ---- batched form (mdx_batch.hip) -----------------------------------------
 // Several independent systems ("instances") share one block-diagonal matrix.

@@ -236,11 +236,14 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
             // per nonzero: value + column.  Per row: the three-kernel FP64
             // scheme reads p once and writes q once; the two-kernel schemes
             // read z once and read and write p and q (q = A z + beta q,
-            // p = z + beta p)
+            // p = z + beta p), except the solve's first iteration (beta = 0),
+            // which reads neither the old p nor the old q
             const double per_nnz = (mixed ? 4.0 : 8.0) + cbytes;
             const double per_row = mixed ? 20.0 : ctx->iter_scheme == 1 ? 40.0 : 16.0;
+            const double fresh_saving = mixed ? 8.0 : ctx->iter_scheme == 1 ? 16.0 : 0.0;
             ctx->stats.spmv_bytes +=
-                (double)work * (per_nnz * (double)ctx->nnz + per_row * (double)ctx->n);
+                (double)work * (per_nnz * (double)ctx->nnz + per_row * (double)ctx->n) -
+                (work > 0 ? fresh_saving * (double)ctx->n : 0.0);
         }
         ionic_queued = next_queued && done;
         if (!done)   // iteration cap: the guarded epilogue did not act

@@ -2,9 +2,11 @@
 per-node network on the GPU with the library's own kernels (mdx_mlp_grad,
 mdx_mlp_adam), install it (mdx_set_mlp) and measure what it saves.
 
-Torch is used here only as device memory and for data plumbing (selecting,
-standardising and batching recorded samples); the network's forward pass,
-gradient and optimiser step are the library's BF16-MFMA kernels.
+Torch is used here only for device memory and copies; the selection of
+recorded samples, their standardisation statistics and the epochs'
+permutations are host (numpy) work, and the batches' gather and
+standardisation (mdx_mlp_samples), the network's forward pass, gradient and
+optimiser step are the library's kernels (BF16 MFMA for the network).
 """
 from __future__ import annotations
 
@@ -40,20 +42,40 @@ def _p(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _device_copy(a, dev, dtype=None):
+    """Host numpy array -> new device tensor (a copy, no device arithmetic)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to(dev)
+
+
+def concat(parts):
+    """Device tensors joined along their first axis, by copies."""
+    import torch
+    total = sum(int(t.shape[0]) for t in parts)
+    out = torch.empty((total,) + tuple(parts[0].shape[1:]), dtype=parts[0].dtype,
+                      device=parts[0].device)
+    o = 0
+    for t in parts:
+        out[o:o + t.shape[0]].copy_(t)
+        o += int(t.shape[0])
+    return out
+
+
 def record(sim, n_steps: int, every: int = 10, front: float = 0.02, frac: float = 0.05,
            seed: int = 0, cap: int | None = None):
     """Advance `sim` by n_steps; on every `every`-th step record (raw
     features, V^{n+1} - V^n) of all nodes whose increment exceeds `front` mV
     plus a random `frac` of the others (at most `cap` of them per recorded
-    step, drawn at random).  Returns device tensors X [N, 4], dV [N]."""
+    step, drawn at random).  The selection is made on the host from the
+    step's increments; the library's mdx_mlp_samples gathers the chosen rows
+    on the device.  Returns device tensors X [N, 4], dV [N]."""
     import torch
     dev = f"cuda:{sim.device}"
     n = sim.n
     Xr = torch.empty((n, 4), dtype=torch.float32, device=dev)
     dVr = torch.empty(n, dtype=torch.float32, device=dev)
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
-    xs, ds = [], []
+    rng = np.random.default_rng(seed)
+    chunks = []
     done = 0
     while done < n_steps:
         skip = min(every - 1, n_steps - done - 1)
@@ -62,64 +84,75 @@ def record(sim, n_steps: int, every: int = 10, front: float = 0.02, frac: float 
         sim._check(L.lib().mdx_set_recorder(sim._h, _p(Xr), _p(dVr), None))
         sim.run(1)
         sim._check(L.lib().mdx_set_recorder(sim._h, None, None, None))
-        keep = (dVr.abs() > front) | (torch.rand(n, generator=g, device=dev) < frac)
-        idx = keep.nonzero().squeeze(1)
-        if cap is not None and idx.numel() > cap:
-            idx = idx[torch.randperm(idx.numel(), generator=g, device=dev)[:cap]]
-        xs.append(Xr[idx].clone())
-        ds.append(dVr[idx].clone())
+        d = dVr.cpu().numpy()                     # waits for the step
+        keep = np.flatnonzero((np.abs(d) > front) | (rng.random(n) < frac))
+        if cap is not None and keep.size > cap:
+            keep = np.sort(rng.choice(keep, size=cap, replace=False))
+        if keep.size:
+            idx = _device_copy(keep, dev, np.int64)
+            Xc = torch.empty((keep.size, 4), dtype=torch.float32, device=dev)
+            dc = torch.empty(keep.size, dtype=torch.float32, device=dev)
+            sim._check(L.lib().mdx_mlp_samples(sim._h, keep.size, _p(idx), n, _p(Xr), _p(dVr),
+                                               None, _p(Xc), _p(dc)))
+            chunks.append((Xc, dc))
         done += skip + 1
-    return torch.cat(xs), torch.cat(ds)
+    if not chunks:
+        return (torch.empty((0, 4), dtype=torch.float32, device=dev),
+                torch.empty(0, dtype=torch.float32, device=dev))
+    return concat([c[0] for c in chunks]), concat([c[1] for c in chunks])
 
 
 def fit(sim, X, dV, epochs: int = 10, batch: int = 8192, lr: float = 2e-3, seed: int = 0,
         theta0: np.ndarray | None = None, log=None):
     """Train on (X, dV): the network's target is the standardised departure
     of V^{n+1} from the extrapolation 2V^n - V^{n-1}, i.e. the increment
-    V^{n+1} - V^n less the previous one (feature 1).  Returns (params
-    float32 [8705], norm float64 [9], per-epoch mean loss)."""
+    V^{n+1} - V^n less the previous one (feature 1).  The standardisation
+    (FP64 mean and standard deviation of the samples, computed on the host)
+    and the per-epoch permutation are host work; every batch is gathered and
+    standardised by mdx_mlp_samples, and the gradient and Adam step are the
+    library's kernels.  Returns (params float32 [8705], norm float64 [9],
+    per-epoch mean loss)."""
     import torch
     dev = X.device
-    mean = X.mean(0)
-    std = X.std(0).clamp_min(1e-6)
-    D = dV - X[:, 1]
-    out_scale = D.std().clamp_min(1e-6)
-    Xn = ((X - mean) / std).contiguous()
-    T = (D / out_scale).contiguous()
-    n = Xn.shape[0]
-    P = torch.tensor(init_params(seed) if theta0 is None else theta0, dtype=torch.float32,
-                     device=dev)
-    M = torch.zeros_like(P)
-    Vm = torch.zeros_like(P)
+    Xh = X.cpu().numpy().astype(np.float64)
+    dh = dV.cpu().numpy().astype(np.float64)
+    n = Xh.shape[0]
+    mean = Xh.mean(0)
+    std = np.maximum(Xh.std(0, ddof=1), 1e-6)
+    out_scale = max(float((dh - Xh[:, 1]).std(ddof=1)), 1e-6)
+    norm = np.concatenate([mean, std, [out_scale]])
+    del Xh, dh
+    P = _device_copy(init_params(seed) if theta0 is None else theta0, dev, np.float32)
+    M = _device_copy(np.zeros(N_PARAM), dev, np.float32)
+    Vm = _device_copy(np.zeros(N_PARAM), dev, np.float32)
     G = torch.empty_like(P)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     nb = L.lib().mdx_mlp_grad_scratch(batch)
     scratch = torch.empty(nb // 4 + 64, dtype=torch.float32, device=dev)
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
+    Xb = torch.empty((batch, 4), dtype=torch.float32, device=dev)
+    Tb = torch.empty(batch, dtype=torch.float32, device=dev)
+    nm = np.ascontiguousarray(norm, np.float64)
+    nm_p = nm.ctypes.data_as(C.c_void_p)
+    rng = np.random.default_rng(seed)
     t = 0
     history = []
     for ep in range(epochs):
-        perm = torch.randperm(n, generator=g, device=dev)
+        perm = _device_copy(rng.permutation(n), dev, np.int64)
         tot, cnt = 0.0, 0
         for s in range(0, n - batch + 1, batch):
-            idx = perm[s:s + batch]
-            xb, tb = Xn[idx].contiguous(), T[idx].contiguous()
             t += 1
-            sim._check(L.lib().mdx_mlp_grad(sim._h, _p(P), batch, _p(xb), _p(tb), _p(G),
+            sim._check(L.lib().mdx_mlp_samples(sim._h, batch, C.c_void_p(perm.data_ptr() + 8 * s),
+                                               n, _p(X), _p(dV), nm_p, _p(Xb), _p(Tb)))
+            sim._check(L.lib().mdx_mlp_grad(sim._h, _p(P), batch, _p(Xb), _p(Tb), _p(G),
                                             _p(loss), _p(scratch), nb))
             sim._check(L.lib().mdx_mlp_adam(sim._h, _p(P), _p(M), _p(Vm), _p(G), t, lr, 0.9,
                                             0.999, 1e-8))
             if cnt % 16 == 0:
                 tot += float(loss.item())
-                cnt += 1
-            else:
-                cnt += 1
+            cnt += 1
         history.append(tot / max(1, (cnt + 15) // 16))
         if log:
             log(f"epoch {ep}: loss {history[-1]:.4f}")
-    norm = np.concatenate([mean.double().cpu().numpy(), std.double().cpu().numpy(),
-                           [float(out_scale)]])
     return P.cpu().numpy(), norm, history
 
 

@@ -32,7 +32,6 @@ def main():
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--out", default=DEFAULT_OUT)
     a = ap.parse_args()
-    import torch
     from . import inputs, learn, sim
     t0 = time.perf_counter()
     mesh = inputs.ellipsoid_shell(n_nodes=1_200_000, seed=1000)
@@ -53,7 +52,7 @@ def main():
         trainer = s
         print(f"[train] site {site}: {X.shape[0]} samples, {a.steps} steps "
               f"({it:.2f} CG iterations/step) in {time.perf_counter() - t1:.1f} s", flush=True)
-    X, dV = torch.cat(Xs), torch.cat(Ds)
+    X, dV = learn.concat(Xs), learn.concat(Ds)
     del Xs, Ds
     t1 = time.perf_counter()
     params, norm, hist = learn.fit(trainer, X, dV, epochs=a.epochs, batch=8192, lr=2e-3,

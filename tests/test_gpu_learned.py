@@ -164,7 +164,6 @@ def trained():
     trajectories of a ~100k-node shell (ten Tusscher-Panfilov, dt 0.02 ms,
     40 ms each, random endocardial sites)."""
     from paper_2510_12011_amd import learn
-    import torch
     mesh = inputs.ellipsoid_shell(n_nodes=100_000, seed=1000)
     steps = 2000
     Xs, Ds = [], []
@@ -174,7 +173,7 @@ def trained():
         Xs.append(X)
         Ds.append(dV)
         trainer = s
-    X, dV = torch.cat(Xs), torch.cat(Ds)
+    X, dV = learn.concat(Xs), learn.concat(Ds)
     print(f"  {X.shape[0]} samples", flush=True)
     params, norm, hist = learn.fit(trainer, X, dV, epochs=8, batch=4096, lr=2e-3,
                                    log=lambda m: print("  " + m, flush=True))

@@ -154,3 +154,48 @@ def test_training_on_gpu_reduces_loss(ctx):
     L1 = np.mean((mlp.forward(theta, X) - T) ** 2)
     print(f"  loss {L0:.4f} -> {L1:.4f}", flush=True)
     assert L1 < 0.1 * L0
+
+
+def test_samples_gather_raw_and_standardised(ctx):
+    """mdx_mlp_samples, the training batches' gather: the rows an index list
+    picks, raw (bitwise) and standardised as the network trains on them (the
+    same FP32 operations written out in numpy: (x - mean) * (1/std), target
+    (dV - x1) / out_scale), and a zero row with a NaN target for an index
+    outside the rows."""
+    import torch
+    from paper_2510_12011_amd import _lib as L
+    rng = np.random.default_rng(5)
+    n, k = 5000, 777
+    X = rng.normal(size=(n, 4)).astype(np.float32)
+    dV = rng.normal(size=n).astype(np.float32)
+    idx = rng.integers(0, n, k).astype(np.int64)
+    idx[5] = n + 3
+    norm = np.array([0.1, -0.2, 0.3, 0.0, 1.5, 0.7, 2.0, 1.1, 0.25])
+    Xd, dVd = _t(X), _t(dV)
+    idxd = torch.from_numpy(idx).to("cuda:0")
+    Xo = torch.empty((k, 4), dtype=torch.float32, device="cuda:0")
+    To = torch.empty(k, dtype=torch.float32, device="cuda:0")
+    ok = np.arange(k) != 5
+    ctx._check(L.lib().mdx_mlp_samples(ctx._h, k, _p(idxd), n, _p(Xd), _p(dVd), None, _p(Xo),
+                                       _p(To)))
+    torch.cuda.synchronize()
+    xo, to = Xo.cpu().numpy(), To.cpu().numpy()
+    assert np.array_equal(xo[ok], X[idx[ok]]) and np.array_equal(to[ok], dV[idx[ok]])
+    assert not xo[5].any() and np.isnan(to[5])
+    nm = norm.ctypes.data_as(C.c_void_p)
+    ctx._check(L.lib().mdx_mlp_samples(ctx._h, k, _p(idxd), n, _p(Xd), _p(dVd), nm, _p(Xo),
+                                       _p(To)))
+    torch.cuda.synchronize()
+    xo, to = Xo.cpu().numpy(), To.cpu().numpy()
+    mean = norm[:4].astype(np.float32)
+    inv = (1.0 / norm[4:8]).astype(np.float32)
+    want_x = (X[idx[ok]] - mean) * inv
+    want_t = (dV[idx[ok]] - X[idx[ok], 1]) / np.float32(norm[8])
+    np.testing.assert_allclose(xo[ok], want_x, rtol=2e-7, atol=1e-7)
+    np.testing.assert_allclose(to[ok], want_t, rtol=2e-7, atol=1e-7)
+    assert not xo[5].any() and np.isnan(to[5])
+    bad = norm.copy()
+    bad[5] = 0.0
+    assert L.lib().mdx_mlp_samples(ctx._h, k, _p(idxd), n, _p(Xd), _p(dVd),
+                                   bad.ctypes.data_as(C.c_void_p), _p(Xo),
+                                   _p(To)) == L.MDX_ERR_INVALID_ARG
