@@ -96,3 +96,23 @@ def adam_step(theta, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     vhat = v / (1.0 - beta2 ** t)
     theta -= lr * mhat / (np.sqrt(vhat) + eps)
     return theta
+
+
+BF16_U = 2.0 ** -8   # unit roundoff of bfloat16 (8 significand bits)
+
+
+def bf16_error_bound(theta, X, k=6.0):
+    """Per-sample bound on |y_bf16 - y| for an evaluation of the network with
+    BF16 inputs, weights and activations and FP32 accumulation: each rounding
+    is an independent relative error of at most BF16_U, propagated through
+    the layers in root-sum-square with this network's own activations
+    (var_0 = (u x)^2, var_l = (var_{l-1} + 2 (u h_{l-1})^2) W_l^2 elementwise
+    squared, ReLU 1-Lipschitz); k standard deviations per sample."""
+    p = unpack(np.asarray(theta, np.float64))
+    _, (X, z1, h1, z2, h2, z3, h3) = forward(theta, X, keep=True)
+    u = BF16_U
+    var = (u * X) ** 2
+    for W, h in ((p["W1"], X), (p["W2"], h1), (p["W3"], h2)):
+        var = (var + 2 * (u * h) ** 2) @ (W ** 2).T
+    var = (var + 2 * (u * h3) ** 2) @ (p["W4"] ** 2)
+    return k * np.sqrt(var) + 1e-6

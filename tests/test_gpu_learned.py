@@ -80,25 +80,11 @@ def test_untrained_network_leaves_solution_unchanged(precision):
     assert err <= 1e-5
 
 
-BF16_U = 2.0 ** -8   # unit roundoff of bfloat16 (8 significand bits)
-
-
 def bf16_bound(theta, xhat, k=6.0):
-    """Per-node bound on |y_bf16 - y| for the network's forward pass with
-    BF16 inputs, weights and activations and FP32 accumulation: each rounding
-    is an independent error of at most u times its value, propagated through
-    the layers in root-sum-square (var_0 = (u x)^2, var_l = W_l^2 (var_{l-1} +
-    2 (u h_{l-1})^2), ReLU 1-Lipschitz) with the oracle's own activations h;
-    k standard deviations per node."""
+    """Per-node BF16 error bound of the network's evaluation (the oracle's
+    root-sum-square propagation, oracle/mlp.py)."""
     from oracle import mlp
-    p = mlp.unpack(np.asarray(theta, np.float64))
-    _, (X, z1, h1, z2, h2, z3, h3) = mlp.forward(theta, xhat, keep=True)
-    u = BF16_U
-    var = (u * X) ** 2
-    for W, h in ((p["W1"], X), (p["W2"], h1), (p["W3"], h2)):
-        var = (var + 2 * (u * h) ** 2) @ (W ** 2).T
-    var = (var + 2 * (u * h3) ** 2) @ (p["W4"] ** 2)
-    return k * np.sqrt(var) + 1e-6
+    return mlp.bf16_error_bound(theta, xhat, k)
 
 
 @pytest.mark.parametrize("nontemporal", [0, 1])

@@ -74,3 +74,31 @@ def test_training_reduces_loss_on_a_smooth_target():
         L, g = mlp.loss_and_grad(theta, X, T)
         mlp.adam_step(theta, m, v, g, t, lr=3e-3)
     assert L < 0.1 * L0
+
+
+def _bf16(a):
+    """Round to bfloat16 (nearest, ties to even), returned as float32."""
+    b = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def test_bf16_error_bound_holds_for_an_emulated_bf16_evaluation():
+    """The per-sample bound the GPU tests use: a numpy evaluation with BF16
+    inputs, weights and activations and FP32 sums and biases stays within
+    it at every sample, and the bound is not vacuous (its median ratio to
+    the actual error is within two orders of magnitude)."""
+    rng = np.random.default_rng(9)
+    theta = mlp.init_params(7)
+    theta[mlp.N_PARAM - 1] = 0.3
+    X = rng.normal(size=(20000, 4))
+    p = mlp.unpack(theta)
+    h = _bf16(X)
+    for W, b in (("W1", "b1"), ("W2", "b2"), ("W3", "b3")):
+        z = h @ _bf16(p[W]).T + p[b].astype(np.float32)
+        h = _bf16(np.maximum(z, 0.0))
+    y = h @ _bf16(p["W4"]) + np.float32(p["b4"][0])
+    err = np.abs(y.astype(np.float64) - mlp.forward(theta, X))
+    bound = mlp.bf16_error_bound(theta, X)
+    assert np.all(err <= bound)
+    assert np.median(err / bound) > 1e-2
