@@ -269,7 +269,9 @@ MDX_API mdx_status mdx_set_profiling(mdx_ctx *ctx, int32_t every_n);
  *                        0 (default) as five launches per iteration.  A
  *                        barrier that waits longer than about 60 ms (its
  *                        workgroups could not all be resident) ends the
- *                        launch and mdx_run returns MDX_ERR_DEVICE;
+ *                        launch and mdx_run returns MDX_ERR_DEVICE; a
+ *                        batch with more instances than workgroups that can
+ *                        be resident at once is refused (MDX_ERR_UNSUPPORTED);
  *   MDX_TUNE_NONTEMPORAL matrix streams (values, column indices) read with the
  *                        non-temporal cache hint: -1 (default) for each
  *                        kernel whose streams exceed 256 MiB (larger than

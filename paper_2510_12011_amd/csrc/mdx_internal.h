@@ -309,7 +309,7 @@ void launch_relayout_v4(hipStream_t s, int64_t n_slices, const int64_t *sptr_new
 void launch_build_csr(hipStream_t s, int64_t n_rows, SellView base, const float *A32,
                       const int32_t *rptr, int32_t *col_csr, float *val_csr);
 
-// gv: scratch of 4 doubles per row (the gathered per-node values)
+// gv: scratch of 3 doubles per row (the gathered per-node values)
 void launch_b_rhs_init(hipStream_t s, const SegTiling &t, SellView P, const double *Mv,
                        const double *Kv, const double *dinv, const float *dinv32,
                        const StepParams &sp, int64_t n_rows, const double *V, const double *Vprev,

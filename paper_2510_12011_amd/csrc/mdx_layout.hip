@@ -117,7 +117,7 @@ void compute_layout(mdx_ctx *c)
         L.csr_ptr = take(sizeof(int32_t) * (c->batched ? np + 1 : 1));
         L.csr_col = take(sizeof(int32_t) * cnz);
         L.csr_val = take(sizeof(float) * cnz);
-        L.gv = take(sizeof(double) * 4 * (c->batched ? np : 1));
+        L.gv = take(sizeof(double) * 3 * (c->batched ? np : 1));
     }
     L.total = o;
 
@@ -266,9 +266,16 @@ mdx_status install_persistent_groups(mdx_ctx *c)
     mdx_ctx *ctx = c;   // for HIPCHK
     const int cap = persistent_capacity(c->device);
     if (cap <= 0) return fail(c, MDX_ERR_DEVICE, "occupancy query of the persistent kernel failed");
+    // every instance needs a group of its own; from there on, more tiles per
+    // group always end with one group per instance
+    if (c->n_inst > cap)
+        return fail(c, MDX_ERR_UNSUPPORTED,
+                    "%d instances exceed the %d workgroups the persistent iteration can keep "
+                    "resident", c->n_inst, cap);
     std::vector<int4> grp;
     std::vector<int32_t> ig;
-    int tpb = 1;
+    const int64_t tiles = c->npad / TILE;
+    int tpb = (int)std::max<int64_t>(1, (tiles + cap - 1) / cap);
     for (;; ++tpb) {
         if (mdx_status e = build_groups(c, tpb, grp, ig)) return e;
         if ((int)grp.size() <= cap) break;
