@@ -244,6 +244,8 @@ def learned_workload(args):
         key = (precision, ws)
         if key not in ctxs:
             s = sim.from_spec(spec(held[0], k0 + args.steps), precision=precision)
+            if precision == "fp64" and args.iter_scheme is not None:
+                s.set_tuning(iter_scheme=args.iter_scheme)
             if ws == L.MDX_WS_MLP:
                 learn.install(s, params, norm)
             ctxs[key] = s
@@ -653,6 +655,9 @@ def main():
     ap.add_argument("--instances", type=int, default=64, help="batched workload")
     ap.add_argument("--total-nodes", type=int, default=12_000_000, help="batched workload")
     ap.add_argument("--no-graph", action="store_true", help="batched workload")
+    ap.add_argument("--iter-scheme", type=int, choices=[0, 1], default=None,
+                    help="FP64 PCG iteration in three kernels (0, the library's default) or "
+                         "two (1): single-mesh workloads and the learned workload's FP64 runs")
     ap.add_argument("--persistent", action="store_true",
                     help="batched workload: CG iterations in one persistent launch")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
@@ -708,6 +713,8 @@ def single_workload(args):
     print(f"[bench] workload {args.workload}: {n} nodes, {spec.mesh.n_tets} elements, {prec}",
           flush=True)
     s = sim.from_spec(spec, precision=prec)
+    if args.iter_scheme is not None:
+        s.set_tuning(iter_scheme=args.iter_scheme)
     st = s.stats()
     if args.warmup:
         s.run(args.warmup)
@@ -752,8 +759,11 @@ def single_workload(args):
                    "dt_ms": spec.dt, "rtol": spec.rtol,
                    "stopping": "relative to ||z0||" if spec.rel_mode == 0 else "relative to ||D^-1 b||",
                    "warm_start": "2V^k - V^(k-1)", "mean_cg_iters": float(iters.mean()),
-                   "max_cg_iters": int(iters.max())},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv_dot" if prec == "fp64" else "k_cg_spmv32",
+                   "max_cg_iters": int(iters.max()),
+                   "iteration_kernels": 2 if prec != "fp64" or args.iter_scheme == 1 else 3},
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_cg_spmv" if args.iter_scheme == 1 else "k_spmv_dot")
+                     if prec == "fp64" else "k_cg_spmv32",
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_launch": bytes_avg,

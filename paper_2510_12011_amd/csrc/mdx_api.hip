@@ -771,6 +771,11 @@ mdx_status mdx_set_state(mdx_ctx *ctx, const double *V, const double *Vprev, con
         if (mdx_status e = copy_vec_in(ctx, lrt, ctx->dev<double>(ctx->L.lrt))) return e;
     }
     // padding rows of lat/lrt were zeroed by copy_vec_in; they are never read
+    const int32_t zero = 0;   // a non-finite V of the replaced state no longer stands
+    HIPCHK(hipMemcpyAsync(reinterpret_cast<char *>(ctx->dev<Scalars>(ctx->L.scalars)) +
+                              offsetof(Scalars, nonfinite_v),
+                          &zero, sizeof zero, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->step = step;
     ctx->kvp_valid = false;
     return MDX_OK;

@@ -112,6 +112,23 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
     __syncthreads();
 }
 
+// Activation and repolarisation times of row i after a step to time t1 with
+// V^k = vo, V^{k+1} = vn: LAT = the first t^{k+1} with V > 0; LRT = the first
+// later t^{k+1} with V < -70 mV while V falls.  Returns false for a
+// non-finite vn.
+__device__ __forceinline__ bool update_times(int64_t i, double t1, double vo, double vn,
+                                             double *__restrict__ lat, double *__restrict__ lrt)
+{
+    if (!isfinite(vn)) return false;
+    double l = lat[i];
+    if (isinf(l) && vn > 0.0) {
+        l = t1;
+        lat[i] = t1;
+    }
+    if (!isinf(l) && l < t1 && isinf(lrt[i]) && vn < -70.0 && vn < vo) lrt[i] = t1;
+    return true;
+}
+
 // One workgroup (the finalize kernels: FIN threads) sums the `groups`
 // partials of a producer kernel, laid out partial[k * groups + g], in a fixed
 // order.

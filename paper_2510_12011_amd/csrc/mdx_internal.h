@@ -54,7 +54,8 @@ struct alignas(256) Scalars {
     // mixed-precision form: residual replacement protocol
     int32_t replace;    // a replacement is pending (iteration kernels idle): 1 the
                         // recursive residual passed the test, 2 periodic or cap
-    int32_t pad_;       // keeps the record's layout in whole 8-byte words
+    int32_t nonfinite_v;  // a non-finite V found by the activation-time update
+                          // (kept across solves; cleared with the state)
     int32_t it_next;    // iterations completed (index of the next one)
     int32_t use_mlp;    // learned warm start: the MLP guess was chosen this step
     double beta;        // beta of the next iteration (0: restart with p = z)
@@ -133,10 +134,19 @@ void launch_ionic_init(hipStream_t s, int kind, const double *params, int64_t n,
 // With a guard, the kernel does nothing unless *guard is non-zero when it
 // runs (a step's update queued before its predecessor's solve is known to be
 // done).
+// The previous step's activation and repolarisation times, carried by the
+// kernel that reads the state they are taken from: t1 is the time of V (the
+// kernel's input, V^{k+1}), Vold is V^k; lat == nullptr carries nothing.
+struct StepTimes {
+    double t1 = 0.0;
+    const double *Vold = nullptr;
+    double *lat = nullptr, *lrt = nullptr;
+    Scalars *sc = nullptr;   // its nonfinite_v flag
+};
 void launch_ionic_step(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                        double dt, double cm, const double *V, double *u, const double *istim,
                        double *out, int raw, const int32_t *tile_real = nullptr,
-                       const int32_t *guard = nullptr);
+                       const int32_t *guard = nullptr, const StepTimes &times = StepTimes{});
 
 // Mixed-precision form: gates in FP32 (g32, ionic_gate_rows(kind) rows of ld
 // floats), concentrations and the current in FP64 (u).  The FP64 array u
@@ -148,7 +158,8 @@ void launch_ionic_step_mixed(hipStream_t s, int kind, const double *params, int6
                              double dt, double cm, const double *V, double *u, float *g32,
                              const double *istim, double *out,
                              const int32_t *tile_real = nullptr,
-                             const int32_t *guard = nullptr);
+                             const int32_t *guard = nullptr,
+                             const StepTimes &times = StepTimes{});
 void launch_gates_to_f32(hipStream_t s, int kind, int64_t ld, const double *u, float *g32);
 void launch_gates_to_f64(hipStream_t s, int kind, int64_t ld, const float *g32, double *u);
 

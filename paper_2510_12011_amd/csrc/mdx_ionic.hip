@@ -16,6 +16,7 @@
 //    (Am. J. Physiol. Heart Circ. Physiol. 291:H1088), 18 states + V;
 //  * Courtemanche-Ramirez-Nattel 1998 human atrial model (Am. J. Physiol.
 //    275:H301), 20 states + V.
+#include "mdx_device.h"
 #include "mdx_internal.h"
 
 namespace mdx {
@@ -558,7 +559,8 @@ __global__ __launch_bounds__(256) void k_ionic_step(IonicParams P, int64_t n, in
                                                     const double *__restrict__ istim,
                                                     double *__restrict__ out, int raw,
                                                     const int32_t *__restrict__ tile_real,
-                                                    const int32_t *__restrict__ guard)
+                                                    const int32_t *__restrict__ guard,
+                                                    StepTimes times)
 {
     if (guard && !*guard) return;   // enqueued ahead of a solve that is not done
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -568,6 +570,8 @@ __global__ __launch_bounds__(256) void k_ionic_step(IonicParams P, int64_t n, in
         return;
     }
     double v = V[i];
+    if (times.lat && !update_times(i, times.t1, times.Vold[i], v, times.lat, times.lrt))
+        times.sc->nonfinite_v = 1;
     double iion = 0.0;
     if constexpr (KIND == MDX_KIND_MS) {
         double h = u[i];
@@ -635,7 +639,8 @@ __global__ __launch_bounds__(256) void k_ionic_step_mixed(IonicParams P, int64_t
                                                           const double *__restrict__ istim,
                                                           double *__restrict__ out,
                                                           const int32_t *__restrict__ tile_real,
-                                                          const int32_t *__restrict__ guard)
+                                                          const int32_t *__restrict__ guard,
+                                                          StepTimes times)
 {
     if (guard && !*guard) return;   // enqueued ahead of a solve that is not done
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -645,6 +650,8 @@ __global__ __launch_bounds__(256) void k_ionic_step_mixed(IonicParams P, int64_t
         return;
     }
     const double v = V[i];
+    if (times.lat && !update_times(i, times.t1, times.Vold[i], v, times.lat, times.lrt))
+        times.sc->nonfinite_v = 1;
     double iion = 0.0;
     if constexpr (KIND == MDX_KIND_MS) {
         float h = g32[i];
@@ -724,23 +731,24 @@ void launch_ionic_init(hipStream_t s, int kind, const double *params, int64_t n,
 
 void launch_ionic_step(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                        double dt, double cm, const double *V, double *u, const double *istim,
-                       double *out, int raw, const int32_t *tile_real, const int32_t *guard)
+                       double *out, int raw, const int32_t *tile_real, const int32_t *guard,
+                       const StepTimes &times)
 {
     if (n <= 0) return;
     IonicParams P = pack(kind, params);
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (kind == 1)
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw, tile_real, guard);
+                           istim, out, raw, tile_real, guard, times);
     else if (kind == 2)
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw, tile_real, guard);
+                           istim, out, raw, tile_real, guard, times);
     else if (kind == 3)
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_CRN>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw, tile_real, guard);
+                           istim, out, raw, tile_real, guard, times);
     else
         hipLaunchKernelGGL(k_ionic_step<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, dt, cm, V, u,
-                           istim, out, raw, tile_real, guard);
+                           istim, out, raw, tile_real, guard, times);
 }
 
 int ionic_gate_rows(int kind) { return kind == 1 ? 1 : kind == 2 ? 12 : 0; }
@@ -749,20 +757,20 @@ int ionic_gate_row0(int kind) { return kind == 1 ? 0 : kind == 2 ? 6 : 0; }
 void launch_ionic_step_mixed(hipStream_t s, int kind, const double *params, int64_t n, int64_t ld,
                              double dt, double cm, const double *V, double *u, float *g32,
                              const double *istim, double *out, const int32_t *tile_real,
-                             const int32_t *guard)
+                             const int32_t *guard, const StepTimes &times)
 {
     if (n <= 0) return;
     IonicParams P = pack(kind, params);
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (kind == 1)
         hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_MS>, grid, block, 0, s, P, n, ld, dt, cm, V,
-                           u, g32, istim, out, tile_real, guard);
+                           u, g32, istim, out, tile_real, guard, times);
     else if (kind == 2)
         hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_TT>, grid, block, 0, s, P, n, ld, dt, cm, V,
-                           u, g32, istim, out, tile_real, guard);
+                           u, g32, istim, out, tile_real, guard, times);
     else
         hipLaunchKernelGGL(k_ionic_step_mixed<MDX_KIND_NONE>, grid, block, 0, s, P, n, ld, dt, cm,
-                           V, u, g32, istim, out, tile_real, guard);
+                           V, u, g32, istim, out, tile_real, guard, times);
 }
 
 void launch_gates_to_f32(hipStream_t s, int kind, int64_t ld, const double *u, float *g32)

@@ -63,13 +63,17 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     auto t_start = std::chrono::steady_clock::now();
     double *lat = ctx->dev<double>(L.lat), *lrt = ctx->dev<double>(L.lrt);
     // ionic update from Vk: s = I_stim - I_ion (with a guard: only if *guard)
-    auto queue_ionic = [&](const double *Vk, const double *istim_k, const int32_t *guard) {
+    // (and, with times, the previous step's activation and repolarisation
+    // times from the same read of Vk)
+    auto queue_ionic = [&](const double *Vk, const double *istim_k, const int32_t *guard,
+                           const StepTimes &times) {
         if (gates32)
             launch_ionic_step_mixed(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
-                                    ctx->dt, ctx->cm, Vk, u, g32, istim_k, s, nullptr, guard);
+                                    ctx->dt, ctx->cm, Vk, u, g32, istim_k, s, nullptr, guard,
+                                    times);
         else
             launch_ionic_step(st, ctx->ionic_kind, ctx->ionic_params.data(), ctx->n, ctx->npad,
-                              ctx->dt, ctx->cm, Vk, u, istim_k, s, 0, nullptr, guard);
+                              ctx->dt, ctx->cm, Vk, u, istim_k, s, 0, nullptr, guard, times);
     };
     bool ionic_queued = false;   // this step's ionic update was queued by the previous step
 
@@ -82,7 +86,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         const double *istim = any_stim ? ctx->dev<double>(L.istim) : nullptr;
 
         // ---- ionic update: s = I_stim - I_ion ----
-        if (!ionic_queued) queue_ionic(V, istim, nullptr);
+        if (!ionic_queued) queue_ionic(V, istim, nullptr, StepTimes{});
         ionic_queued = false;
 
         // ---- right-hand side, warm start, initial residual ----
@@ -148,13 +152,18 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         // host reads the scalars and queues the rest of that step.
         const double t1 = (double)(k + 1) * ctx->dt;
         bool next_queued = false;
+        // The times of this step ride in the next step's ionic update (it
+        // reads V^{k+1} anyway); the last step of the run has its own
+        // epilogue.
         auto end_chunk = [&]() -> mdx_status {
-            launch_epilogue(st, ctx->n, t1, V, X, lat, lrt, sc, &sc->done);
+            const bool carry = j + 1 < n_steps;
+            if (!carry) launch_epilogue(st, ctx->n, t1, V, X, lat, lrt, sc, &sc->done);
             launch_publish(st, sc, ctx->pub_dev, ++ctx->pub_seq);
-            if (j + 1 < n_steps) {
+            if (carry) {
                 bool any_next = false;
                 if (mdx_status e = update_stimulus(ctx, st, k + 1, any_next)) return e;
-                queue_ionic(X, any_next ? ctx->dev<double>(L.istim) : nullptr, &sc->done);
+                queue_ionic(X, any_next ? ctx->dev<double>(L.istim) : nullptr, &sc->done,
+                            StepTimes{t1, V, lat, lrt, sc});
                 next_queued = true;
             }
             HIPCHK(hipGetLastError());
@@ -219,6 +228,8 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         if (ctx->sc_host->nonfinite)
             return fail(ctx, MDX_ERR_NONFINITE, "non-finite value in the solve of step %lld",
                         (long long)k);
+        if (ctx->sc_host->nonfinite_v)   // found while reading V^k in this step's ionic update
+            return fail(ctx, MDX_ERR_NONFINITE, "non-finite V after step %lld", (long long)k - 1);
         const int iters = done ? ctx->sc_host->iters : -1;
         ctx->last_iters = done ? iters : max_iter;
         if (ctx->profiling) {
@@ -273,7 +284,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     HIPCHK(hipStreamSynchronize(st));
     ctx->stats.step_loop_seconds +=
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    if (ctx->sc_host->nonfinite)
+    if (ctx->sc_host->nonfinite || ctx->sc_host->nonfinite_v)
         return fail(ctx, MDX_ERR_NONFINITE, "non-finite V after step %lld", (long long)ctx->step);
     return result;
     GUARD_END

@@ -354,14 +354,7 @@ __global__ __launch_bounds__(256) void k_epilogue(int64_t n, double t1, const do
     if (guard && !*guard) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double vn = Vnew[i];
-    if (!isfinite(vn)) sc->nonfinite = 1;
-    double l = lat[i];
-    if (isinf(l) && vn > 0.0) {
-        l = t1;
-        lat[i] = t1;
-    }
-    if (!isinf(l) && l < t1 && isinf(lrt[i]) && vn < -70.0 && vn < Vold[i]) lrt[i] = t1;
+    if (!update_times(i, t1, Vold[i], Vnew[i], lat, lrt)) sc->nonfinite = 1;
 }
 
 // One wavefront: the scalars (whole 4-byte words) into host-visible memory,
