@@ -2,11 +2,12 @@
 // forms).  Per step the kernels of mdx_ionic.hip / mdx_solver.hip
 // (mdx_mixed.hip, mdx_learned.hip for the forms) are queued on the
 // context's stream; PCG iterations are queued in chunks (first chunk = last
-// step's count).  A chunk ends with the guarded epilogue, a one-wave kernel
-// that publishes the solver scalars to coherent pinned host memory with a
-// sequence number, and the next step's ionic update guarded by the done
-// flag; the host spins on the sequence number.  Kernels queued after
-// convergence return at their first instruction.
+// step's count).  A chunk ends with a one-wave kernel that publishes the
+// solver scalars to coherent pinned host memory with a sequence number and
+// the next step's ionic update guarded by the done flag (it also records
+// this step's activation and repolarisation times); the host spins on the
+// sequence number.  Kernels queued after convergence return at their first
+// instruction.
 #include "mdx_host.h"
 
 extern "C" {
@@ -145,16 +146,15 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
         // ---- PCG ----
         int units = 0;   // kernels carrying the SpMV launched so far
         bool done = false;
-        // End of a chunk of iterations: the epilogue (activation times; it
-        // acts once the solve is done and is idempotent), the scalars
-        // published to host memory, and the next step's ionic update (it acts
-        // only if this solve is done), which keeps the device busy while the
-        // host reads the scalars and queues the rest of that step.
+        // End of a chunk of iterations: the scalars published to host
+        // memory and the next step's ionic update (it acts only if this solve
+        // is done), which keeps the device busy while the host reads the
+        // scalars and queues the rest of that step.  This step's activation
+        // and repolarisation times ride in that update (it reads V^{k+1}
+        // anyway; idempotent, so the chunk's copy that finds the solve done
+        // acts once); the last step of the run has an epilogue kernel instead.
         const double t1 = (double)(k + 1) * ctx->dt;
         bool next_queued = false;
-        // The times of this step ride in the next step's ionic update (it
-        // reads V^{k+1} anyway); the last step of the run has its own
-        // epilogue.
         auto end_chunk = [&]() -> mdx_status {
             const bool carry = j + 1 < n_steps;
             if (!carry) launch_epilogue(st, ctx->n, t1, V, X, lat, lrt, sc, &sc->done);
@@ -257,7 +257,7 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                 (work > 0 ? fresh_saving * (double)ctx->n : 0.0);
         }
         ionic_queued = next_queued && done;
-        if (!done)   // iteration cap: the guarded epilogue did not act
+        if (!done)   // iteration cap: the guarded update carrying the times did not act
             launch_epilogue(st, ctx->n, t1, V, X, lat, lrt, sc);
         // rotate: V^{k+1} <- x, V^k -> V^{k-1}
         int old_prev = ctx->vb[1];
