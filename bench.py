@@ -649,7 +649,7 @@ def main():
                     choices=["learned", "slab", "precision", "precision_fp64", "batched", "tiny",
                              "nversion", "surface", "surface_mixed", "surface_crn",
                              "batched_surface"])
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-every", type=int, default=10)
     ap.add_argument("--instances", type=int, default=64, help="batched workload")
