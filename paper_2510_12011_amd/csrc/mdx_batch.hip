@@ -24,6 +24,13 @@
 // the lanes of a row summed by a butterfly over adjacent lanes), sliced ELL
 // read with 16-byte vector loads (4 entries per lane and load), or CSR with
 // 4-16 lanes per row.
+//
+// Optionally (k_b_persistent) a chunk of iterations runs as one launch whose
+// workgroups are all resident: the workgroups of an instance meet at
+// barriers of their own (a generation counter per instance, a bounded wait
+// that raises a fault flag instead of hanging) between the SpMV, the update
+// and the direction, and each instance iterates until its next residual
+// replacement.
 #include "mdx_device.h"
 #include "mdx_internal.h"
 
