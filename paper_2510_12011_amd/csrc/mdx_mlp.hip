@@ -228,6 +228,11 @@ __device__ __forceinline__ bf16x4 relu_pack_bf16x4(float a, float b, float c, fl
     return __builtin_bit_cast(bf16x4, u);
 }
 
+// ReLU in FP32 as a signed-integer max on the bit pattern: values with the
+// sign bit set (negatives, -0) become +0, the rest are kept.  fmaxf would
+// add a canonicalising max per value.
+__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 struct alignas(16) InferLds {
     float b1[NH], b2[NH], b3[NH], w4[NH];   // FP32 biases, BF16-rounded w4
     unsigned short w1[NH * 16];             // BF16 [W1 W1 0]: columns 0..3, 4..7, 8..15
@@ -311,22 +316,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
                                                      FeatIn in, float *__restrict__ y)
 {
     __shared__ InferLds w;
-    for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {
-        const int o = i / NH, k = i % NH;
-        w.w2[o * WSTRIDE + k] = f2bf(P[OFF_W2 + i]);
-        w.w3[o * WSTRIDE + k] = f2bf(P[OFF_W3 + i]);
+    {
+        // the weights into LDS, every load issued before the first
+        // conversion: a fixed stride of 256 threads (the launch's size),
+        // fully unrolled (a loop over blockDim.x waited on each load in turn)
+        constexpr int NT = 256, R = NH * NH / NT;
+        const int t = threadIdx.x;
+        float a2[R], a3[R], a1[4];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            a2[j] = P[OFF_W2 + t + NT * j];
+            a3[j] = P[OFF_W3 + t + NT * j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = t + NT * j, o = i / 16, k = i % 16;
+            a1[j] = k < 8 ? P[OFF_W1 + 4 * o + (k & 3)] : 0.0f;
+        }
+        float bb[4] = {0.0f, 0.0f, 0.0f, 0.0f}, b4 = 0.0f;
+        if (t < NH) {
+            bb[0] = P[OFF_B1 + t];
+            bb[1] = P[OFF_B2 + t];
+            bb[2] = P[OFF_B3 + t];
+            bb[3] = P[OFF_W4 + t];
+        }
+        if (t == 0) b4 = P[OFF_B4];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + NT * j, o = i / NH, k = i % NH;
+            w.w2[o * WSTRIDE + k] = f2bf(a2[j]);
+            w.w3[o * WSTRIDE + k] = f2bf(a3[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w.w1[t + NT * j] = f2bf(a1[j]);
+        if (t < NH) {
+            w.b1[t] = bb[0];
+            w.b2[t] = bb[1];
+            w.b3[t] = bb[2];
+            w.w4[t] = round_bf(bb[3]);
+        }
+        if (t == 0) w.b4 = b4;
     }
-    for (int i = threadIdx.x; i < NH * 16; i += blockDim.x) {
-        const int o = i / 16, k = i % 16;
-        w.w1[i] = k < 8 ? f2bf(P[OFF_W1 + 4 * o + (k & 3)]) : (unsigned short)0;
-    }
-    for (int i = threadIdx.x; i < NH; i += blockDim.x) {
-        w.b1[i] = P[OFF_B1 + i];
-        w.b2[i] = P[OFF_B2 + i];
-        w.b3[i] = P[OFF_B3 + i];
-        w.w4[i] = round_bf(P[OFF_W4 + i]);
-    }
-    if (threadIdx.x == 0) w.b4 = P[OFF_B4];
     __syncthreads();
 
     const int lane = threadIdx.x & 63, half = lane >> 5;
@@ -420,7 +450,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) sum[b] += w4[v] * fmaxf(acc[b][v], 0.0f);
+                for (int v = 0; v < 16; ++v) sum[b] += w4[v] * relu_bits(acc[b][v]);
         }
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -678,7 +708,7 @@ float *mlp_noalloc_scratch(int device)
     return table[device];
 }
 
-// inference grid: 144 registers per lane leave three wavefronts per SIMD,
+// inference grid: 160 registers per lane leave three wavefronts per SIMD,
 // i.e. three 256-thread workgroups per CU on 256 CUs, all resident at once
 constexpr int64_t kInferGroups = 768;
 
