@@ -131,17 +131,32 @@ __device__ __forceinline__ bool update_times(int64_t i, double t1, double vo, do
 
 // One workgroup (the finalize kernels: FIN threads) sums the `groups`
 // partials of a producer kernel, laid out partial[k * groups + g], in a fixed
-// order.
+// order: thread t adds g = t, t + FIN, t + 2 FIN, ... in turn, then the
+// workgroup sum.  The loads of up to FIN_U of a thread's partials are all
+// issued before its first add, so the partials cost one memory round trip
+// (a loop that added as it loaded waited on each load in turn).  Launched
+// with FIN threads.
 constexpr int FIN = 1024;
+constexpr int FIN_U = 8;
 template <int NV>
 __device__ __forceinline__ void finalize_partials(const double *__restrict__ partial, int groups,
                                                   double (&v)[NV])
 {
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = threadIdx.x; g < groups; g += blockDim.x)
+    for (int g0 = threadIdx.x; g0 < groups; g0 += FIN_U * FIN) {
+        double t[FIN_U][NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += partial[k * groups + g];
+        for (int j = 0; j < FIN_U; ++j)
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                t[j][k] = g0 + j * FIN < groups ? partial[k * groups + g0 + j * FIN] : 0.0;
+#pragma unroll
+        for (int j = 0; j < FIN_U; ++j)
+            if (g0 + j * FIN < groups)
+#pragma unroll
+                for (int k = 0; k < NV; ++k) v[k] += t[j][k];
+    }
     block_sum<NV>(v);
 }
 
@@ -249,20 +264,22 @@ __device__ __forceinline__ int64_t wave_slice(int tile)
     return (int64_t)tile * (TILE / SLICE) + wv;
 }
 
-// Every workgroup reduces the `groups` partials of a producer kernel, laid
-// out partial[k * groups + g], in the same order.
-template <int NV>
-__device__ __forceinline__ void reduce_partials(const double *__restrict__ partial, int groups,
-                                                double (&v)[NV])
+// The stopping test's constants, read by a finalize kernel together with its
+// verdict, so that they arrive with the first round trip rather than after
+// the partials' sum.
+struct StopTest {
+    double atol, rtol, ref, floor_;
+};
+__device__ __forceinline__ StopTest stop_test(const Scalars *sc)
 {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = threadIdx.x; g < groups; g += TILE)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += partial[k * groups + g];
-    group_sum<NV>(v);
+    return {sc->atol, sc->rtol, sc->ref, sc->floor_};
+}
+__device__ __forceinline__ bool passes(const StopTest &t, double zn)
+{
+    return zn < t.atol || zn < t.rtol * t.ref || zn <= t.floor_;
 }
 
+// A producer kernel's workgroup g stores its NV sums at partial[k * groups + g].
 template <int NV>
 __device__ __forceinline__ void write_partials(double (&v)[NV], double *__restrict__ partial,
                                                int groups, int g)

@@ -228,17 +228,17 @@ void launch_features(hipStream_t s, int64_t n_real, int64_t n_rows, const double
 // one pass over M and K: x = 2V - V_prev + scale y and its residual r = b - A x,
 // the FP32 residual, z and zero correction (r32 non-null: FP32 iteration) or
 // p0 = D^-1 r (FP64, p0 may be null), kvp = (K V)_i / K_ii for the next step;
-// partials r.z, z.z of x and of 2V - V_prev (FP32-rounded in the FP32
-// iteration) into part4 and |D^-1 b|^2 into part1
+// partials (five rows of t.groups) r.z, z.z of x and of 2V - V_prev
+// (FP32-rounded in the FP32 iteration) and |D^-1 b|^2 into part5
 void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
                         const double *Kv, const double *kdiag, const double *dinv,
                         const float *dinv32, const StepParams &sp, float out_scale,
                         const double *V, const double *Vprev, const double *src, const float *y,
                         double *x, double *r, double *p0, float *r32, float *z32, float *delta,
-                        float *kvp, double *part4, double *part1, bool nt);
+                        float *kvp, double *part5, bool nt);
 // chooses the guess (sc->use_mlp) and sets the scalars of its PCG start
-void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
-                             int rel_mode, Scalars *sc);
+void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p5, int rel_mode,
+                             Scalars *sc);
 void launch_record_dv(hipStream_t s, int64_t n, const double *Vold, const double *Vnew, float *dv);
 void launch_mlp_samples(hipStream_t s, int64_t n_idx, const int64_t *idx, int64_t n_rows,
                         const float *X, const float *dV, bool stdz, const MlpNorm &nm, float *Xo,

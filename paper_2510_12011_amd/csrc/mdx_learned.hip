@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_features(int64_t n_real, int64_t n_rows
                                                   const double *__restrict__ V,
                                                   const double *__restrict__ Vprev,
                                                   const double *__restrict__ src,
-                                                  const float *__restrict__ kvp, double cm,
+                                                  const float *__restrict__ kvp, double inv_cm,
                                                   MlpNorm nm, float4 *__restrict__ feat,
                                                   float4 *__restrict__ raw)
 {
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_features(int64_t n_real, int64_t n_rows
     float4 f;
     f.x = (float)vi;
     f.y = (float)(vi - Vprev[row]);
-    f.z = (float)(src[row] / cm);
+    f.z = (float)(src[row] * inv_cm);
     f.w = kvp[row];
     if (raw && row < n_real) raw[row] = f;
     if (feat) {
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void k_rhs_learned(
     const double *__restrict__ src, const float *__restrict__ y, double *__restrict__ x,
     double *__restrict__ r, double *__restrict__ p0, float *__restrict__ r32,
     float *__restrict__ z32, float *__restrict__ delta, float *__restrict__ kvp,
-    double *__restrict__ part4, double *__restrict__ part1)
+    double *__restrict__ part5)
 {
     const int g = logical_group(t.groups);
     const int lane = threadIdx.x & (SLICE - 1);
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_rhs_learned(
     const double cK_new = sp.theta * sp.dt;
     const double scale = (double)out_scale;
     const bool fp32_iter = r32 != nullptr;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0}, accb[1] = {0.0};
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int t_end = min((g + 1) * t.tpb, t.n_tiles);
     for (int tile = g * t.tpb; tile < t_end; ++tile) {
         const int64_t sl = wave_slice(tile);
@@ -152,37 +152,37 @@ __global__ __launch_bounds__(256) void k_rhs_learned(
             acc[2] += rx * zx;
             acc[3] += zx * zx;
         }
-        accb[0] += (di * bi) * (di * bi);
+        acc[4] += (di * bi) * (di * bi);
     }
-    write_partials<4>(acc, part4, t.groups, g);
-    write_partials<1>(accb, part1, t.groups, g);
+    write_partials<5>(acc, part5, t.groups, g);
 }
 
-// choose the guess; scalars of the PCG initialisation
-__global__ __launch_bounds__(256) void k_init_finalize_ws(int groups, const double *__restrict__ p4,
-                                                          const double *__restrict__ p1,
+// choose the guess; scalars of the PCG initialisation.  The pass's partials
+// are five rows: r.z and |z|^2 of the guess, of the extrapolation, |D^-1 b|^2.
+__global__ __launch_bounds__(FIN) void k_init_finalize_ws(int groups, const double *__restrict__ p5,
                                                           int rel_mode, Scalars *__restrict__ sc)
 {
-    double v[4], w[1];
-    reduce_partials<4>(p4, groups, v);
-    reduce_partials<1>(p1, groups, w);
+    const double atol = sc->atol;
+    double v[5];
+    finalize_partials<5>(p5, groups, v);
     if (threadIdx.x != 0) return;
     const bool finite = v[1] == v[1] && v[1] < 1e300;
     const bool use = finite && v[1] < v[3];
     const double rz = use ? v[0] : v[2];
     const double z0 = sqrt(use ? v[1] : v[3]);
-    const double db = sqrt(w[0]);
+    const double db = sqrt(v[4]);
+    const double floor_ = 1e-15 * db;
     sc->use_mlp = use ? 1 : 0;
     sc->rho[0] = rz;
     sc->z0 = z0;
     sc->znorm = z0;
     sc->ref = rel_mode == 1 ? db : z0;
-    sc->floor_ = 1e-15 * db;
+    sc->floor_ = floor_;
     // a non-finite start ends the solve and is reported; a finite one clears
     // the flag of an earlier solve
     const bool ok = isfinite(z0) && isfinite(db) && isfinite(rz);
     sc->nonfinite = ok ? 0 : 2;
-    sc->done = (!ok || z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
+    sc->done = (!ok || z0 <= floor_ || z0 < atol) ? 1 : 0;
     sc->iters = 0;
     sc->replace = 0;
     sc->beta = 0.0;
@@ -269,7 +269,7 @@ void launch_features(hipStream_t s, int64_t n_real, int64_t n_rows, const double
 {
     if (n_rows > 0)
         hipLaunchKernelGGL(k_features, dim3(blocks_for(n_rows)), dim3(256), 0, s, n_real, n_rows, V,
-                           Vprev, src, kvp, cm, nm, (float4 *)feat, (float4 *)raw);
+                           Vprev, src, kvp, 1.0 / cm, nm, (float4 *)feat, (float4 *)raw);
 }
 
 void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double *Mv,
@@ -277,17 +277,17 @@ void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double
                         const float *dinv32, const StepParams &sp, float out_scale,
                         const double *V, const double *Vprev, const double *src, const float *y,
                         double *x, double *r, double *p0, float *r32, float *z32, float *delta,
-                        float *kvp, double *part4, double *part1, bool nt)
+                        float *kvp, double *part5, bool nt)
 {
     MDX_LAUNCH_SELL(P, nt, k_rhs_learned, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols, Mv,
                     Kv, kdiag, dinv, dinv32, sp, out_scale, V, Vprev, src, y, x, r, p0, r32, z32,
-                    delta, kvp, part4, part1);
+                    delta, kvp, part5);
 }
 
-void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p4, const double *p1,
+void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p5,
                              int rel_mode, Scalars *sc)
 {
-    hipLaunchKernelGGL(k_init_finalize_ws, dim3(1), dim3(TILE), 0, s, t.groups, p4, p1, rel_mode, sc);
+    hipLaunchKernelGGL(k_init_finalize_ws, dim3(1), dim3(FIN), 0, s, t.groups, p5, rel_mode, sc);
 }
 
 void launch_mlp_samples(hipStream_t s, int64_t n_idx, const int64_t *idx, int64_t n_rows,

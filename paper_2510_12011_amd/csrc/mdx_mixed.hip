@@ -48,7 +48,8 @@ namespace mdx {
 
 namespace {
 
-__device__ __forceinline__ bool halted(const Scalars *sc) { return sc->done || sc->replace; }
+// both flags read in one round trip
+__device__ __forceinline__ bool halted(const Scalars *sc) { return (sc->done | sc->replace) != 0; }
 
 __global__ __launch_bounds__(256) void k_to_f32(int64_t n, const double *__restrict__ a,
                                                 float *__restrict__ b)
@@ -115,8 +116,8 @@ __global__ __launch_bounds__(256) void k_rhs_init_mixed(
 // Stopping test of the mixed iteration on ||z_k|| (zn): 0 continue; 1 the
 // recursive residual passes; 2 periodic replacement (every rr iterations)
 // or the iteration cap.  A NaN stops the solve and flags it.
-__device__ __forceinline__ int test_z(Scalars *sc, double zn, int k, int rr, int max_iter,
-                                      bool lead)
+__device__ __forceinline__ int test_z(Scalars *sc, const StopTest &st, double zn, int k, int rr,
+                                      int max_iter, bool lead)
 {
     if (!isfinite(zn)) {
         if (lead) {
@@ -128,7 +129,7 @@ __device__ __forceinline__ int test_z(Scalars *sc, double zn, int k, int rr, int
         }
         return -1;
     }
-    const bool pass = zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_;
+    const bool pass = passes(st, zn);
     const int why = pass ? 1 : (rr > 0 && k % rr == 0) || k >= max_iter ? 2 : 0;
     if (why && lead) {
         sc->replace = why;
@@ -180,11 +181,12 @@ __global__ __launch_bounds__(FIN) void k_cg_alpha32(int groups, int k,
                                                     const double *__restrict__ partial_pq,
                                                     Scalars *__restrict__ sc)
 {
+    const double rho = sc->rho[k & 1];   // read with the verdict
     if (halted(sc)) return;
     double pq[1];
     finalize_partials<1>(partial_pq, groups, pq);
     if (threadIdx.x == 0) {
-        sc->alpha = sc->rho[k & 1] / pq[0];
+        sc->alpha = rho / pq[0];
         sc->it_next = k + 1;
     }
 }
@@ -223,14 +225,16 @@ __global__ __launch_bounds__(FIN) void k_cg_beta32(int groups, int k1, int rr, i
                                                    const double *__restrict__ partial_rz,
                                                    Scalars *__restrict__ sc)
 {
+    const StopTest st = stop_test(sc);   // read with the verdict
+    const double rho_prev = sc->rho[(k1 - 1) & 1];
     if (halted(sc)) return;
     double v[2];
     finalize_partials<2>(partial_rz, groups, v);
     const bool lead = threadIdx.x == 0;
     const double zn = sqrt(v[1]);
-    if (test_z(sc, zn, k1, rr, max_iter, lead)) return;
+    if (test_z(sc, st, zn, k1, rr, max_iter, lead)) return;
     if (lead) {
-        sc->beta = v[0] / sc->rho[(k1 - 1) & 1];
+        sc->beta = v[0] / rho_prev;
         sc->rho[k1 & 1] = v[0];
         sc->znorm = zn;
     }
@@ -288,17 +292,20 @@ __global__ __launch_bounds__(256) void k_true_residual(
 
 // replacement, part 3 (one workgroup): stopping test on the true residual;
 // if it fails, iteration it restarts from it with rho and beta set here
-__global__ __launch_bounds__(256) void k_replace_finalize(int groups, int max_iter,
+__global__ __launch_bounds__(FIN) void k_replace_finalize(int groups, int max_iter,
                                                           const double *__restrict__ partial,
                                                           Scalars *__restrict__ sc)
 {
-    if (!sc->replace || sc->done) return;
-    double v[2];
-    reduce_partials<2>(partial, groups, v);
-    if (threadIdx.x != 0) return;
-    const double zn = sqrt(v[1]);
+    // everything read from the scalars is read with the verdict
+    const StopTest st = stop_test(sc);
     const int it = sc->it_next;
     const int why = sc->replace;
+    const double rho01[2] = {sc->rho[0], sc->rho[1]};
+    if (!why || sc->done) return;
+    double v[2];
+    finalize_partials<2>(partial, groups, v);
+    if (threadIdx.x != 0) return;
+    const double zn = sqrt(v[1]);
     sc->znorm = zn;
     sc->replace = 0;
     if (!isfinite(zn)) {
@@ -307,7 +314,7 @@ __global__ __launch_bounds__(256) void k_replace_finalize(int groups, int max_it
         sc->iters = it;
         return;
     }
-    if (zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_) {
+    if (passes(st, zn)) {
         sc->done = 1;
         sc->iters = it;
         return;
@@ -317,7 +324,7 @@ __global__ __launch_bounds__(256) void k_replace_finalize(int groups, int max_it
     // drifted apart, rho of the recursion is no measure of the true residual,
     // and CG restarts from it (p = z).  A periodic replacement keeps the
     // recurrence (beta = rho_new / rho_old).
-    sc->beta = why == 1 ? 0.0 : v[0] / sc->rho[(it - 1) & 1];
+    sc->beta = why == 1 ? 0.0 : v[0] / rho01[(it - 1) & 1];
     sc->rho[it & 1] = v[0];
 }
 
@@ -366,7 +373,7 @@ void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter
     MDX_LAUNCH_SELL(P, nt, k_true_residual, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
                     A32, delta, r64, dinv, dinv32, r32, z32, partial, sc);
     hipLaunchKernelGGL(k_flush, dim3(blocks_for(n)), dim3(256), 0, s, n, x, delta, sc);
-    hipLaunchKernelGGL(k_replace_finalize, dim3(1), dim3(TILE), 0, s, t.groups, max_iter, partial,
+    hipLaunchKernelGGL(k_replace_finalize, dim3(1), dim3(FIN), 0, s, t.groups, max_iter, partial,
                        sc);
 }
 

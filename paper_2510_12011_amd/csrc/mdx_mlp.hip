@@ -280,7 +280,7 @@ struct FeatIn {
     const float4 *X;
     const double *V, *Vprev, *src;
     const float *kvp;
-    double cm;
+    double inv_cm;   // 1 / Cm
     MlpNorm nm;
     template <bool STATE>
     __device__ __forceinline__ FeatRaw<STATE> fetch(int64_t i, bool ok) const
@@ -300,7 +300,7 @@ struct FeatIn {
     {
         if (!ok) return make_float4(0.f, 0.f, 0.f, 0.f);
         if constexpr (STATE) {
-            const float fx = (float)r.v, fy = (float)(r.v - r.vp), fz = (float)(r.s / cm);
+            const float fx = (float)r.v, fy = (float)(r.v - r.vp), fz = (float)(r.s * inv_cm);
             return make_float4((fx - nm.mean[0]) * nm.inv_std[0],
                                (fy - nm.mean[1]) * nm.inv_std[1],
                                (fz - nm.mean[2]) * nm.inv_std[2],
@@ -729,7 +729,7 @@ void launch_mlp_forward_state(hipStream_t s, const float *P, int64_t n, const do
     if (n <= 0) return;
     const int64_t pairs = ((n + 31) / 32 + 1) / 2;
     const int blocks = (int)std::min<int64_t>((pairs + 3) / 4, kInferGroups);
-    const FeatIn in{nullptr, V, Vprev, src, kvp, cm, nm};
+    const FeatIn in{nullptr, V, Vprev, src, kvp, 1.0 / cm, nm};
     hipLaunchKernelGGL(k_mlp_forward<true>, dim3(blocks), dim3(256), 0, s, P, n, in, y);
 }
 

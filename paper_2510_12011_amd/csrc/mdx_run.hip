@@ -35,6 +35,8 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
     double *s = ctx->dev<double>(L.s);
     double *u = ionic_nstates(ctx->ionic_kind) ? ctx->dev<double>(L.u) : nullptr;
     double *part0 = ctx->dev<double>(L.partial);
+    // (the learned right-hand-side pass writes five rows from part_pq on, into
+    // part_rz's space, which is unused until the iteration)
     double *part_pq = part0 + 3 * kPartialCap, *part_rz = part0 + 6 * kPartialCap;
     Scalars *sc = ctx->dev<Scalars>(L.scalars);
     const StepParams sp = step_params(ctx);
@@ -111,8 +113,8 @@ mdx_status mdx_run(mdx_ctx *ctx, int64_t n_steps, int64_t out_every, double *v_o
                                       hipMemcpyDeviceToDevice, st));
             launch_rhs_learned(st, T, P, Mv, Kv, kdiag, dinv, dinv32, sp,
                                ctx->mlp_norm.out_scale, V, Vprev, s, mlp_y, X, r, p0_fp64,
-                               mixed ? r32 : nullptr, z32, delta, kvp, part_pq, part0, nt_rhs);
-            launch_init_finalize_ws(st, T, part_pq, part0, sp.rel_mode, sc);
+                               mixed ? r32 : nullptr, z32, delta, kvp, part_pq, nt_rhs);
+            launch_init_finalize_ws(st, T, part_pq, sp.rel_mode, sc);
             // where the extrapolation's residual was the smaller, its start
             // vectors (the scalars are already its own, from the same pass):
             // one pass on a small grid, which returns at once, and cheaply,

@@ -154,13 +154,14 @@ __global__ __launch_bounds__(256) void k_residual_init(
     write_partials<3>(acc, partial, t.groups, g);
 }
 
-__global__ __launch_bounds__(256) void k_init_finalize(int groups, const double *__restrict__ partial,
+__global__ __launch_bounds__(FIN) void k_init_finalize(int groups, const double *__restrict__ partial,
                                                        int rel_mode, Scalars *__restrict__ sc,
                                                        const int32_t *__restrict__ skip)
 {
     if (skip && *skip) return;
+    const double atol = sc->atol;
     double v[3];
-    reduce_partials<3>(partial, groups, v);
+    finalize_partials<3>(partial, groups, v);
     if (threadIdx.x == 0) {
         const double z0 = sqrt(v[1]);
         const double db = sqrt(v[2]);
@@ -168,12 +169,13 @@ __global__ __launch_bounds__(256) void k_init_finalize(int groups, const double 
         sc->z0 = z0;
         sc->znorm = z0;
         sc->ref = rel_mode == 1 ? db : z0;
-        sc->floor_ = 1e-15 * db;
+        const double floor_ = 1e-15 * db;
+        sc->floor_ = floor_;
         // a non-finite start (NaN, or a norm that overflowed) ends the solve
         // and is reported; a finite one clears the flag of an earlier solve
         const bool finite = isfinite(z0) && isfinite(db) && isfinite(v[0]);
         sc->nonfinite = finite ? 0 : 2;
-        sc->done = (!finite || z0 <= sc->floor_ || z0 < sc->atol) ? 1 : 0;
+        sc->done = (!finite || z0 <= floor_ || z0 < atol) ? 1 : 0;
         sc->iters = 0;
         sc->replace = 0;
         sc->beta = 0.0;
@@ -253,10 +255,11 @@ __global__ __launch_bounds__(FIN) void k_cg_alpha(int groups, int k,
                                                   const double *__restrict__ partial_pq,
                                                   Scalars *__restrict__ sc)
 {
+    const double rho = sc->rho[k & 1];   // read with the verdict
     if (sc->done) return;
     double pq[1];
     finalize_partials<1>(partial_pq, groups, pq);
-    if (threadIdx.x == 0) sc->alpha = sc->rho[k & 1] / pq[0];
+    if (threadIdx.x == 0) sc->alpha = rho / pq[0];
 }
 
 // Iteration k, update half: x += alpha_k p_k; r -= alpha_k q; z = D^-1 r
@@ -295,6 +298,8 @@ __global__ __launch_bounds__(FIN) void k_cg_beta(int groups, int k1, int max_ite
                                                  const double *__restrict__ partial_rz,
                                                  Scalars *__restrict__ sc)
 {
+    const StopTest st = stop_test(sc);   // read with the verdict
+    const double rho_prev = sc->rho[(k1 - 1) & 1];
     if (sc->done) return;
     double v[2];
     finalize_partials<2>(partial_rz, groups, v);
@@ -307,13 +312,13 @@ __global__ __launch_bounds__(FIN) void k_cg_beta(int groups, int k1, int max_ite
         sc->iters = k1;
         return;
     }
-    if (zn < sc->atol || zn < sc->rtol * sc->ref || zn <= sc->floor_) {
+    if (passes(st, zn)) {
         sc->done = 1;
         sc->iters = k1;
         return;
     }
     if (k1 >= max_iter) return;
-    sc->beta = v[0] / sc->rho[(k1 - 1) & 1];
+    sc->beta = v[0] / rho_prev;
     sc->rho[k1 & 1] = v[0];
 }
 
@@ -409,7 +414,7 @@ void launch_residual_init(hipStream_t s, const Tiling &t, SellView P, const doub
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
                           Scalars *sc, const int32_t *skip)
 {
-    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(TILE), 0, s, t.groups, partial, rel_mode, sc,
+    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(FIN), 0, s, t.groups, partial, rel_mode, sc,
                        skip);
 }
 
