@@ -44,18 +44,31 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bool stopped(const BScalars &s) { return s.done != 0; }
-__device__ __forceinline__ bool idle(const BScalars &s) { return s.done != 0 || s.replace != 0; }
+__device__ __forceinline__ bool idle(const BScalars &s) { return (s.done | s.replace) != 0; }
 
-// Sum NV per-group partials of groups [g0, g1) (layout partial[k * groups + g]).
+// Sum NV per-group partials of groups [g0, g1) (layout partial[k * groups + g]):
+// thread t adds g0 + t, g0 + t + TILE, ... in turn, then the workgroup sum.
+// Up to U of a thread's loads are issued before its first add.
 template <int NV>
 __device__ __forceinline__ void reduce_range(const double *__restrict__ partial, int groups, int g0,
                                              int g1, double (&v)[NV])
 {
+    constexpr int U = 8;
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = g0 + (int)threadIdx.x; g < g1; g += TILE)
+    for (int gb = g0 + (int)threadIdx.x; gb < g1; gb += U * TILE) {
+        double t[U][NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += partial[k * groups + g];
+        for (int j = 0; j < U; ++j)
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                t[j][k] = gb + j * TILE < g1 ? partial[k * groups + gb + j * TILE] : 0.0;
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (gb + j * TILE < g1)
+#pragma unroll
+                for (int k = 0; k < NV; ++k) v[k] += t[j][k];
+    }
     group_sum<NV>(v);
 }
 
@@ -427,11 +440,14 @@ __global__ __launch_bounds__(256) void k_b_alpha(int groups, const int32_t *__re
 {
     const int i = blockIdx.x;
     BScalars &s = sc[i];
+    // what is read besides the partials is read with the verdict
+    const int g0 = inst_grp[i], g1 = inst_grp[i + 1];
+    const double rho = s.rho;
     if (idle(s)) return;
     double v[1];
-    reduce_range<1>(partial, groups, inst_grp[i], inst_grp[i + 1], v);
+    reduce_range<1>(partial, groups, g0, g1, v);
     if (threadIdx.x != 0) return;
-    s.alpha = s.rho / v[0];
+    s.alpha = rho / v[0];
     s.redirect = 0;
 }
 
@@ -469,12 +485,14 @@ __global__ __launch_bounds__(256) void k_b_beta(int groups, const int32_t *__res
 {
     const int i = blockIdx.x;
     BScalars &s = sc[i];
+    const int g0 = inst_grp[i], g1 = inst_grp[i + 1];
+    const int it = s.it + 1;
+    const double ref = s.ref, floor_ = s.floor_, rho = s.rho;
     if (idle(s)) return;
     double v[2];
-    reduce_range<2>(partial, groups, inst_grp[i], inst_grp[i + 1], v);
+    reduce_range<2>(partial, groups, g0, g1, v);
     if (threadIdx.x != 0) return;
     const double zn = sqrt(v[1]);
-    const int it = s.it + 1;
     s.it = it;
     s.znorm = zn;
     if (!isfinite(zn) || !isfinite(v[0])) {
@@ -483,12 +501,12 @@ __global__ __launch_bounds__(256) void k_b_beta(int groups, const int32_t *__res
         s.iters = it;
         return;
     }
-    const bool pass = zn < bp.atol || zn < bp.rtol * s.ref || zn <= s.floor_;
+    const bool pass = zn < bp.atol || zn < bp.rtol * ref || zn <= floor_;
     if (pass || (bp.rr > 0 && it % bp.rr == 0) || it >= bp.max_iter) {
         s.replace = pass ? 1 : 2;   // 1: the recursive residual passed the test
         return;
     }
-    s.beta = v[0] / s.rho;
+    s.beta = v[0] / rho;
     s.rho = v[0];
 }
 
@@ -565,13 +583,15 @@ __global__ __launch_bounds__(256) void k_b_replace_finalize(int groups,
 {
     const int i = blockIdx.x;
     BScalars &s = sc[i];
-    if (!replacing(s)) return;
-    double v[2];
-    reduce_range<2>(partial, groups, inst_grp[i], inst_grp[i + 1], v);
-    if (threadIdx.x != 0) return;
-    const double zn = sqrt(v[1]);
+    const int g0 = inst_grp[i], g1 = inst_grp[i + 1];
     const int it = s.it;
     const int why = s.replace;
+    const double ref = s.ref, floor_ = s.floor_, rho = s.rho;
+    if (!replacing(s)) return;
+    double v[2];
+    reduce_range<2>(partial, groups, g0, g1, v);
+    if (threadIdx.x != 0) return;
+    const double zn = sqrt(v[1]);
     s.znorm = zn;
     s.replace = 0;
     if (!isfinite(zn) || !isfinite(v[0])) {
@@ -580,7 +600,7 @@ __global__ __launch_bounds__(256) void k_b_replace_finalize(int groups,
         s.iters = it;
         return;
     }
-    if (zn < bp.atol || zn < bp.rtol * s.ref || zn <= s.floor_) {
+    if (zn < bp.atol || zn < bp.rtol * ref || zn <= floor_) {
         s.done = 1;
         s.iters = it;
         return;
@@ -593,7 +613,7 @@ __global__ __launch_bounds__(256) void k_b_replace_finalize(int groups,
     }
     // restart (p = z) after the recursive residual passed but the true one did
     // not; keep the recurrence after a periodic replacement
-    s.beta = why == 1 ? 0.0 : v[0] / s.rho;
+    s.beta = why == 1 ? 0.0 : v[0] / rho;
     s.rho = v[0];
     s.redirect = 1;
 }

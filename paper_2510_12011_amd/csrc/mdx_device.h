@@ -129,31 +129,33 @@ __device__ __forceinline__ bool update_times(int64_t i, double t1, double vo, do
     return true;
 }
 
-// One workgroup (the finalize kernels: FIN threads) sums the `groups`
+// One workgroup of NT threads (the finalize kernels) sums the `groups`
 // partials of a producer kernel, laid out partial[k * groups + g], in a fixed
-// order: thread t adds g = t, t + FIN, t + 2 FIN, ... in turn, then the
+// order: thread t adds g = t, t + NT, t + 2 NT, ... in turn, then the
 // workgroup sum.  The loads of up to FIN_U of a thread's partials are all
 // issued before its first add, so the partials cost one memory round trip
-// (a loop that added as it loaded waited on each load in turn).  Launched
-// with FIN threads.
+// (a loop that added as it loaded waited on each load in turn).  The
+// iteration's finalize kernels reduce one partial per SpMV workgroup (4,905
+// on the 1.26M-node shell) with FIN threads; those that reduce one per
+// vector-kernel workgroup (at most 2,048) are faster with 256.
 constexpr int FIN = 1024;
 constexpr int FIN_U = 8;
-template <int NV>
+template <int NV, int NT = FIN>
 __device__ __forceinline__ void finalize_partials(const double *__restrict__ partial, int groups,
                                                   double (&v)[NV])
 {
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g0 = threadIdx.x; g0 < groups; g0 += FIN_U * FIN) {
+    for (int g0 = threadIdx.x; g0 < groups; g0 += FIN_U * NT) {
         double t[FIN_U][NV];
 #pragma unroll
         for (int j = 0; j < FIN_U; ++j)
 #pragma unroll
             for (int k = 0; k < NV; ++k)
-                t[j][k] = g0 + j * FIN < groups ? partial[k * groups + g0 + j * FIN] : 0.0;
+                t[j][k] = g0 + j * NT < groups ? partial[k * groups + g0 + j * NT] : 0.0;
 #pragma unroll
         for (int j = 0; j < FIN_U; ++j)
-            if (g0 + j * FIN < groups)
+            if (g0 + j * NT < groups)
 #pragma unroll
                 for (int k = 0; k < NV; ++k) v[k] += t[j][k];
     }

@@ -159,12 +159,12 @@ __global__ __launch_bounds__(256) void k_rhs_learned(
 
 // choose the guess; scalars of the PCG initialisation.  The pass's partials
 // are five rows: r.z and |z|^2 of the guess, of the extrapolation, |D^-1 b|^2.
-__global__ __launch_bounds__(FIN) void k_init_finalize_ws(int groups, const double *__restrict__ p5,
+__global__ __launch_bounds__(TILE) void k_init_finalize_ws(int groups, const double *__restrict__ p5,
                                                           int rel_mode, Scalars *__restrict__ sc)
 {
     const double atol = sc->atol;
     double v[5];
-    finalize_partials<5>(p5, groups, v);
+    finalize_partials<5, TILE>(p5, groups, v);
     if (threadIdx.x != 0) return;
     const bool finite = v[1] == v[1] && v[1] < 1e300;
     const bool use = finite && v[1] < v[3];
@@ -287,7 +287,7 @@ void launch_rhs_learned(hipStream_t s, const Tiling &t, SellView P, const double
 void launch_init_finalize_ws(hipStream_t s, const Tiling &t, const double *p5,
                              int rel_mode, Scalars *sc)
 {
-    hipLaunchKernelGGL(k_init_finalize_ws, dim3(1), dim3(FIN), 0, s, t.groups, p5, rel_mode, sc);
+    hipLaunchKernelGGL(k_init_finalize_ws, dim3(1), dim3(TILE), 0, s, t.groups, p5, rel_mode, sc);
 }
 
 void launch_mlp_samples(hipStream_t s, int64_t n_idx, const int64_t *idx, int64_t n_rows,

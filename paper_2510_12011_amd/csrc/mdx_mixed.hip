@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256) void k_true_residual(
 
 // replacement, part 3 (one workgroup): stopping test on the true residual;
 // if it fails, iteration it restarts from it with rho and beta set here
-__global__ __launch_bounds__(FIN) void k_replace_finalize(int groups, int max_iter,
+__global__ __launch_bounds__(TILE) void k_replace_finalize(int groups, int max_iter,
                                                           const double *__restrict__ partial,
                                                           Scalars *__restrict__ sc)
 {
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(FIN) void k_replace_finalize(int groups, int max_it
     const double rho01[2] = {sc->rho[0], sc->rho[1]};
     if (!why || sc->done) return;
     double v[2];
-    finalize_partials<2>(partial, groups, v);
+    finalize_partials<2, TILE>(partial, groups, v);
     if (threadIdx.x != 0) return;
     const double zn = sqrt(v[1]);
     sc->znorm = zn;
@@ -373,7 +373,7 @@ void launch_replacement(hipStream_t s, const Tiling &t, SellView P, int max_iter
     MDX_LAUNCH_SELL(P, nt, k_true_residual, dim3(t.groups), dim3(TILE), 0, s, t, P.slice_ptr, cols,
                     A32, delta, r64, dinv, dinv32, r32, z32, partial, sc);
     hipLaunchKernelGGL(k_flush, dim3(blocks_for(n)), dim3(256), 0, s, n, x, delta, sc);
-    hipLaunchKernelGGL(k_replace_finalize, dim3(1), dim3(FIN), 0, s, t.groups, max_iter, partial,
+    hipLaunchKernelGGL(k_replace_finalize, dim3(1), dim3(TILE), 0, s, t.groups, max_iter, partial,
                        sc);
 }
 

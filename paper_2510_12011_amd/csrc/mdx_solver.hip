@@ -154,14 +154,14 @@ __global__ __launch_bounds__(256) void k_residual_init(
     write_partials<3>(acc, partial, t.groups, g);
 }
 
-__global__ __launch_bounds__(FIN) void k_init_finalize(int groups, const double *__restrict__ partial,
+__global__ __launch_bounds__(TILE) void k_init_finalize(int groups, const double *__restrict__ partial,
                                                        int rel_mode, Scalars *__restrict__ sc,
                                                        const int32_t *__restrict__ skip)
 {
     if (skip && *skip) return;
     const double atol = sc->atol;
     double v[3];
-    finalize_partials<3>(partial, groups, v);
+    finalize_partials<3, TILE>(partial, groups, v);
     if (threadIdx.x == 0) {
         const double z0 = sqrt(v[1]);
         const double db = sqrt(v[2]);
@@ -414,7 +414,7 @@ void launch_residual_init(hipStream_t s, const Tiling &t, SellView P, const doub
 void launch_init_finalize(hipStream_t s, const Tiling &t, const double *partial, int rel_mode,
                           Scalars *sc, const int32_t *skip)
 {
-    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(FIN), 0, s, t.groups, partial, rel_mode, sc,
+    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(TILE), 0, s, t.groups, partial, rel_mode, sc,
                        skip);
 }
 
