@@ -171,3 +171,22 @@ def test_mixed_iteration_cap_follows_oracle():
     err = max(_rel_l2(a, b) for a, b in zip(v_gpu, v_or))
     print(f"  capped mixed vs oracle: {err:.2e}", flush=True)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("precision,rtol,bar", [("fp64", 1e-12, 1e-9), ("mixed", 1e-8, V_REL_L2)])
+def test_vector_kernels_on_more_than_2048_workgroups(precision, rtol, bar):
+    """The 598,978-node slab (2,340 tiles) with the vector kernels' grid
+    raised past 2,048 workgroups: the 256-thread finalize kernels (initial
+    scalars, replacement) then sum their partials in two rounds of
+    up-front loads, and the run still matches the oracle at the form's bar."""
+    spec = _rhs_relative(inputs.slab(h=0.09, n_steps=20), rtol)
+    assert (spec.mesh.n_nodes + 255) // 256 > 2048
+    s = _sim(spec, precision)
+    s.set_tuning(max_groups=4096)
+    o = orc.Oracle(spec)
+    v_or, _ = o.steps(20, out_every=10)
+    v_gpu, status = s.run(20, 10)
+    assert status == 0
+    errs = [_rel_l2(a, b) for a, b in zip(v_gpu, v_or)]
+    print(f"  {precision}, 2,340 vector workgroups: V rel L2 max {max(errs):.2e}", flush=True)
+    assert max(errs) <= bar, errs
